@@ -1,0 +1,218 @@
+"""Projection method II time step (Sec. 4.6: eq:pm_prediction, eq:pm_poisson,
+eq:pm_projection, eq:pm_update) on the operators of oracle.operators.
+
+Readings (the paper states the scheme with unit mass matrices and density):
+  * Poisson:   (tau/rho) cont(M^-1 pres(Phi), 0) = cont(U*, D^{n+1})
+  * corrector: U^{n+1} = U* - (tau/rho) M^-1 pres(Phi)
+  * pressure:  P^{n+1/2} = P^{n-1/2} + Phi - (tau mu / 2 rho) V^-1 cont(M^-1 pres(Phi), 0)
+    With M = V = 1 and rho = 1 these are the printed equations.
+  * AB2 start: conv^{-1} := conv^0; P^{-1/2} = 0; Phi^0 = 0.
+  * The Poisson right-hand side has its mean over the pressure unknowns
+    removed (the problem is singular: pure Neumann in Phi).
+  * Predictor: Jacobi-PCG on H = (rho/tau) M - mu K, K U = visc(strain(U, 0)),
+    started from U^n, relative tolerance 1e-12; Poisson: Jacobi-PCG with the
+    zero-mean projection, started from Phi^n.
+"""
+
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import operators as ops
+from .derived import Prepared, inactive_dirichlet, laplacian
+from .solvers import OK, coloured_diagonal, pcg
+
+
+@dataclass
+class Params:
+    rho: float
+    mu: float
+    tau: float
+    u_inf: float = 1.0
+    gx: float = 0.0
+    gy: float = 0.0
+    pcg_tol: float = 1e-10
+    pcg_maxit: int = 100000
+    pred_tol: float = 1e-12
+    pred_maxit: int = 500
+    visc_form: str = "geometric"
+
+
+@dataclass
+class State:
+    Ux: np.ndarray
+    Uy: np.ndarray
+    P: np.ndarray
+    Phi: np.ndarray
+    conv_prev: tuple = None
+    n: int = 0
+
+
+@dataclass
+class StepInfo:
+    pred_iters: int = 0
+    pred_status: int = OK
+    cg_iters: int = 0
+    cg_relres: float = 0.0
+    cg_status: int = OK
+    div_max: float = 0.0
+    div_rel: float = 0.0
+    ke: float = 0.0
+    extra: dict = field(default_factory=dict)
+
+
+class Stepper:
+    def __init__(self, pr: Prepared, prm: Params, Dx, Dy, h):
+        self.pr = pr
+        self.prm = prm
+        self.Dx = Dx
+        self.Dy = Dy
+        self.h = h
+        c = pr.caps
+        self.Vu = np.where(pr.act_u, c["Vu"], 0.0)
+        self.Vv = np.where(pr.act_v, c["Vv"], 0.0)
+        self.mask2 = np.stack([pr.act_u, pr.act_v])
+        # Dirichlet contribution of the viscous term: visc(strain(U~, D)) with
+        # U~ = D on the non-unknown faces and 0 on unknowns
+        ix, iy = inactive_dirichlet(pr, Dx, Dy)
+        vdx, vdy = ops.viscous(c, ix, iy, Dx, Dy, prm.visc_form)
+        self.vD = np.stack([np.where(pr.act_u, vdx, 0.0), np.where(pr.act_v, vdy, 0.0)])
+        # Jacobi diagonal of H, probed on unit combs
+        self.Hdiag = coloured_diagonal(self.apply_H, self.mask2.shape, self.mask2)
+        self.Hdinv = np.where(self.mask2 & (self.Hdiag > 0), 1.0 / np.where(self.Hdiag > 0, self.Hdiag, 1.0), 0.0)
+        self.Pdinv = np.where(pr.act_p & (pr.diag > 0), 1.0 / np.where(pr.diag > 0, pr.diag, 1.0), 0.0)
+
+    # --- linear operators -------------------------------------------------
+    def apply_K(self, U2):
+        z = np.zeros_like(U2[0])
+        vx, vy = ops.viscous(self.pr.caps, np.where(self.pr.act_u, U2[0], 0.0),
+                             np.where(self.pr.act_v, U2[1], 0.0), z, z, self.prm.visc_form)
+        return np.stack([np.where(self.pr.act_u, vx, 0.0), np.where(self.pr.act_v, vy, 0.0)])
+
+    def apply_H(self, U2):
+        prm = self.prm
+        V2 = np.stack([self.Vu, self.Vv])
+        return (prm.rho / prm.tau) * V2 * U2 - prm.mu * self.apply_K(U2)
+
+    def apply_A(self, phi):
+        """A = -L (symmetric positive semi-definite)."""
+        return -laplacian(self.pr, phi)
+
+    # --- phases -------------------------------------------------------------
+    def full_velocity(self, U2):
+        return (np.where(self.pr.act_u, U2[0], self.Dx), np.where(self.pr.act_v, U2[1], self.Dy))
+
+    def convection(self, Ux, Uy):
+        cx, cy = ops.conv(self.pr.caps, Ux, Uy, Ux, Uy, self.Dx, self.Dy, self.Dx, self.Dy)
+        return np.stack([np.where(self.pr.act_u, cx, 0.0), np.where(self.pr.act_v, cy, 0.0)])
+
+    def predictor_rhs(self, st: State, conv_n, conv_prev):
+        prm, pr = self.prm, self.pr
+        px, py = ops.pres(pr.caps, np.where(pr.act_p, st.P, 0.0))
+        vx, vy = ops.viscous(pr.caps, st.Ux, st.Uy, self.Dx, self.Dy, prm.visc_form)
+        V2 = np.stack([self.Vu, self.Vv])
+        U2 = np.stack([st.Ux, st.Uy])
+        g2 = np.stack([np.full_like(self.Vu, prm.gx), np.full_like(self.Vv, prm.gy)])
+        rhs = ((prm.rho / prm.tau) * V2 * U2 - 1.5 * prm.rho * conv_n + 0.5 * prm.rho * conv_prev
+               - np.stack([px, py]) + prm.mu * np.stack([vx, vy]) + prm.mu * self.vD
+               + prm.rho * V2 * g2)
+        return np.where(self.mask2, rhs, 0.0)
+
+    def predict(self, st: State, info: StepInfo):
+        conv_n = self.convection(st.Ux, st.Uy)
+        conv_prev = conv_n if st.conv_prev is None else st.conv_prev
+        rhs = self.predictor_rhs(st, conv_n, conv_prev)
+        U0 = np.stack([st.Ux, st.Uy])
+        Us, it, rr, status = pcg(self.apply_H, rhs, U0, self.Hdinv, self.mask2,
+                                 self.prm.pred_tol, self.prm.pred_maxit)
+        info.pred_iters, info.pred_status = it, status
+        return self.full_velocity(Us), conv_n
+
+    def poisson_rhs(self, Ux, Uy):
+        prm, pr = self.prm, self.pr
+        b = (prm.rho / prm.tau) * ops.cont(pr.caps, Ux, Uy, self.Dx, self.Dy)
+        b = np.where(pr.act_p, b, 0.0)
+        if pr.n_active:
+            b = np.where(pr.act_p, b - b[pr.act_p].sum() / pr.n_active, 0.0)
+        return b
+
+    def solve_poisson(self, b, phi0, info: StepInfo, tol=None, solver="pcg"):
+        pr = self.pr
+        tol = self.prm.pcg_tol if tol is None else tol
+        if solver == "direct":
+            from .solvers import assemble, direct_zero_mean
+            A, idx = assemble(self.apply_A, pr.act_p)
+            x = np.zeros(pr.act_p.size)
+            x[idx] = direct_zero_mean(A, -b.ravel()[idx])
+            phi = x.reshape(b.shape)
+            info.cg_iters, info.cg_status = 0, OK
+        else:
+            phi, it, rr, status = pcg(self.apply_A, -b, phi0, self.Pdinv, pr.act_p, tol,
+                                      self.prm.pcg_maxit, zero_mean=True)
+            info.cg_iters, info.cg_relres, info.cg_status = it, rr, status
+        if pr.n_active:
+            phi = np.where(pr.act_p, phi - phi[pr.act_p].sum() / pr.n_active, 0.0)
+        return phi
+
+    def correct(self, Ux, Uy, phi):
+        prm, pr = self.prm, self.pr
+        s = prm.tau / prm.rho
+        Ux = Ux.copy()
+        Uy = Uy.copy()
+        dpx = np.zeros_like(phi)
+        dpy = np.zeros_like(phi)
+        dpx[:, :-1] = phi[:, 1:] - phi[:, :-1]
+        dpy[:-1, :] = phi[1:, :] - phi[:-1, :]
+        Ux = np.where(pr.act_u, Ux - s * pr.gx * dpx, Ux)
+        Uy = np.where(pr.act_v, Uy - s * pr.gy * dpy, Uy)
+        return Ux, Uy
+
+    def pressure_update(self, P, phi):
+        prm, pr = self.prm, self.pr
+        Lphi = laplacian(pr, phi)
+        Vinv = np.where(pr.act_p & (pr.caps["V"] > 0), 1.0 / np.where(pr.caps["V"] > 0, pr.caps["V"], 1.0), 0.0)
+        return np.where(pr.act_p, P + phi - (prm.tau * prm.mu / (2.0 * prm.rho)) * Vinv * Lphi, 0.0)
+
+    def diagnostics(self, Ux, Uy, info: StepInfo):
+        pr = self.pr
+        d = ops.cont(pr.caps, Ux, Uy, self.Dx, self.Dy)
+        dm = float(np.max(np.abs(d[pr.act_p]))) if pr.n_active else 0.0
+        info.div_max = dm
+        info.div_rel = dm / (self.prm.u_inf * self.h)
+        info.ke = float(ops.kinetic(pr.caps, Ux, Uy)[1:-1, 1:-1].sum())
+        return info
+
+    def project(self, st: State, solver="pcg"):
+        """Make st.U discretely divergence-free (initial condition)."""
+        info = StepInfo()
+        b = self.poisson_rhs(st.Ux, st.Uy)
+        phi = self.solve_poisson(b, np.zeros_like(b), info, solver=solver)
+        st.Ux, st.Uy = self.correct(st.Ux, st.Uy, phi)
+        return self.diagnostics(st.Ux, st.Uy, info)
+
+    def step(self, st: State, solver="pcg") -> StepInfo:
+        info = StepInfo()
+        (Usx, Usy), conv_n = self.predict(st, info)
+        b = self.poisson_rhs(Usx, Usy)
+        phi = self.solve_poisson(b, st.Phi, info, solver=solver)
+        Ux, Uy = self.correct(Usx, Usy, phi)
+        st.P = self.pressure_update(st.P, phi)
+        st.Ux, st.Uy, st.Phi = Ux, Uy, phi
+        st.conv_prev = conv_n
+        st.n += 1
+        info.extra["b_norm"] = float(np.sqrt(np.sum(b ** 2)))
+        return self.diagnostics(Ux, Uy, info)
+
+
+def initial_state(pr: Prepared, Dx, Dy, u_inf, pert=None):
+    """Free stream (u_inf, 0) on velocity unknowns plus an optional
+    perturbation, D elsewhere; P = Phi = 0."""
+    Ux = np.where(pr.act_u, u_inf, Dx)
+    Uy = np.where(pr.act_v, 0.0, Dy)
+    if pert is not None:
+        Ux = np.where(pr.act_u, Ux + pert[0], Ux)
+        Uy = np.where(pr.act_v, Uy + pert[1], Uy)
+    z = np.zeros_like(Ux)
+    return State(Ux, Uy, z.copy(), z.copy())

@@ -1,0 +1,111 @@
+"""Pins of the oracle's linear solves and projection step (Sec. 4.6): the
+iterative solve against the direct solution, the Poisson null space
+(constants, end of Sec. 4.6), definiteness of the predictor and Poisson
+matrices, the linear identity cont(U^{n+1}, D) = (tau/rho) * residual,
+free-stream preservation and the mass budget."""
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import derived, geometry, pmii
+from oracle.solvers import assemble, direct_zero_mean
+
+
+def _setup(n=24, r=0.17, seed=3, body=True):
+    g = W.GridSpec(n, n, 0.0, 0.0, 1.0, 1.0)
+    bodies = [W.Body(W.CIRCLE, 0.51, 0.48, a=r)] if body else []
+    case = W.Case("t", g, bodies, re=100.0, steps=3, noise=1e-2, seed=seed)
+    caps = geometry.capacities(g, bodies)
+    pr = derived.prepare(caps, n, n)
+    Dx, Dy = W.dirichlet(case)
+    prm = pmii.Params(rho=1.0, mu=case.mu, tau=case.tau, pcg_tol=1e-12)
+    st = pmii.Stepper(pr, prm, Dx, Dy, g.hx)
+    return case, pr, st, Dx, Dy
+
+
+def test_poisson_null_space_and_definiteness():
+    case, pr, st, Dx, Dy = _setup(n=10)
+    ones = np.where(pr.act_p, 1.0, 0.0)
+    assert np.max(np.abs(derived.laplacian(pr, ones))) < 1e-13
+    A, _ = assemble(st.apply_A, pr.act_p)
+    ev = np.linalg.eigvalsh(A.toarray())
+    assert abs(ev[0]) < 1e-12 * ev[-1] and ev[1] > 1e-8 * ev[-1]
+    assert np.max(np.abs((A - A.T).toarray())) == 0.0
+
+
+def test_predictor_matrix_spd():
+    case, pr, st, Dx, Dy = _setup(n=10)
+    H, _ = assemble(st.apply_H, st.mask2)
+    Hd = H.toarray()
+    assert np.max(np.abs(Hd - Hd.T)) < 1e-12 * np.max(np.abs(Hd))
+    assert np.linalg.eigvalsh(0.5 * (Hd + Hd.T)).min() > 0.0
+    assert np.allclose(np.diag(Hd), st.Hdiag[st.mask2], rtol=1e-14)
+
+
+def test_pcg_matches_direct_solution():
+    case, pr, st, Dx, Dy = _setup(n=24)
+    rng = np.random.default_rng(5)
+    b = np.where(pr.act_p, rng.uniform(-1, 1, pr.act_p.shape), 0.0)
+    b = np.where(pr.act_p, b - b[pr.act_p].mean(), 0.0)
+    info = pmii.StepInfo()
+    x_it = st.solve_poisson(b, np.zeros_like(b), info, tol=1e-13)
+    x_d = st.solve_poisson(b, np.zeros_like(b), pmii.StepInfo(), solver="direct")
+    err = np.linalg.norm((x_it - x_d)[pr.act_p]) / np.linalg.norm(x_d[pr.act_p])
+    assert err < 1e-9
+    assert info.cg_status == 0 and info.cg_iters > 10
+
+
+def test_step_divergence_identity_and_mass():
+    case, pr, st, Dx, Dy = _setup(n=24)
+    s0 = pmii.initial_state(pr, Dx, Dy, case.u_inf, W.perturbation(case))
+    info = st.project(s0)
+    assert info.div_rel < 1e-8
+    for _ in range(3):
+        (usx, usy), _c = st.predict(s0, pmii.StepInfo())
+        b = st.poisson_rhs(usx, usy)
+        phi = st.solve_poisson(b, s0.Phi, pmii.StepInfo())
+        ux, uy = st.correct(usx, usy, phi)
+        from oracle import operators as ops
+        d = ops.cont(pr.caps, ux, uy, Dx, Dy)
+        resid = b - derived.laplacian(pr, phi)
+        assert np.max(np.abs(d - (st.prm.tau / st.prm.rho) * resid)[pr.act_p]) < 1e-14
+        info = st.step(s0)
+        assert info.div_rel < 1e-8
+        assert info.pred_status == 0 and info.cg_status == 0
+        # net volume flux through the box is zero for the free-stream walls
+        mass = ops.cont(pr.caps, s0.Ux, s0.Uy, Dx, Dy)[1:-1, 1:-1].sum()
+        assert abs(mass) < 1e-12
+
+
+def test_free_stream_is_preserved_without_body():
+    case, pr, st, Dx, Dy = _setup(n=16, body=False)
+    s0 = pmii.initial_state(pr, Dx, Dy, case.u_inf)
+    for _ in range(4):
+        info = st.step(s0)
+    assert np.max(np.abs(s0.Ux[pr.act_u] - case.u_inf)) < 1e-13
+    assert np.max(np.abs(s0.Uy[pr.act_v])) < 1e-13
+    assert np.max(np.abs(s0.P)) < 1e-10
+    assert info.div_rel < 1e-12
+
+
+@pytest.mark.slow
+def test_kinetic_energy_decays_in_closed_box():
+    """No-slip box (D = 0), divergence-free initial field: viscosity and the
+    M-orthogonal projection make the discrete kinetic energy decrease."""
+    n = 20
+    g = W.GridSpec(n, n, 0.0, 0.0, 1.0, 1.0)
+    body = W.Body(W.CIRCLE, 0.5, 0.5, a=0.2)
+    caps = geometry.capacities(g, [body])
+    pr = derived.prepare(caps, n, n)
+    z = np.zeros_like(caps["V"])
+    prm = pmii.Params(rho=1.0, mu=0.01, tau=0.2 / n, pcg_tol=1e-12)
+    st = pmii.Stepper(pr, prm, z, z, g.hx)
+    case = W.Case("box", g, [body], re=100.0, noise=1.0, seed=7)
+    px, py = W.perturbation(case)
+    s0 = pmii.State(np.where(pr.act_u, px, 0.0), np.where(pr.act_v, py, 0.0), z.copy(), z.copy())
+    st.project(s0)
+    ke = [st.diagnostics(s0.Ux, s0.Uy, pmii.StepInfo()).ke]
+    for _ in range(5):
+        ke.append(st.step(s0).ke)
+    assert all(b < a for a, b in zip(ke[:-1], ke[1:]))
