@@ -1,0 +1,235 @@
+/*
+ * ccns -- conservative cut-cell Navier-Stokes hot path on MI355X (gfx950).
+ *
+ * C interface of the device library libccns.so.  The calls follow the
+ * statement of the discrete problem in Quiros Rodriguez, Fullana,
+ * Le Chenadec, Sayadi, "A Conservative Cartesian Cut Cell Method for the
+ * Solution of the Incompressible Navier-Stokes Equations on Staggered
+ * Meshes": geometry in (Sec. 3.1), capacities (Sec. 3.2-3.4), the staggered
+ * operators (Sec. 4.1-4.4), and the projection method II time step
+ * (Sec. 4.6).
+ *
+ * Conventions shared by every call
+ *  - Host field arrays ("dense layout") are row-major (ny+2) x (nx+2) doubles
+ *    with one ghost ring: cell (i,j) at [j][i]; x-face (i+1/2, j) at [j][i];
+ *    y-face (i, j+1/2) at [j][i]; node (i+1/2, j+1/2) at [j][i].  Real cells
+ *    are 1..nx x 1..ny; real x-faces i = 0..nx (0 and nx on the walls).
+ *  - Device memory is owned by the caller: one workspace buffer of
+ *    ccns_workspace_bytes() bytes, passed to ccns_ctx_create and kept alive
+ *    until ccns_ctx_destroy.  The library never allocates device memory
+ *    itself.  All device work is enqueued on the caller's HIP stream.
+ *  - Functions return a ccns_status.  No C++ exception crosses the
+ *    interface.  On error, ccns_last_error() describes the failure.
+ *  - A context is not thread-safe; use one context per host thread.
+ */
+#ifndef CCNS_H
+#define CCNS_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    CCNS_OK = 0,
+    CCNS_EINVAL = -1,      /* bad argument (sizes, NaN/negative capacity, rho<=0 ...) */
+    CCNS_ENOMEM = -2,      /* workspace smaller than ccns_workspace_bytes() */
+    CCNS_ENOTCONV = -3,    /* an iterative solve hit its iteration limit; outputs hold the last iterate */
+    CCNS_EBREAKDOWN = -4,  /* CG breakdown (p^T A p <= 0); outputs hold the last iterate */
+    CCNS_EDEVICE = -5,     /* a HIP runtime call failed */
+    CCNS_ESTATE = -6       /* call not valid in the context's current state */
+} ccns_status;
+
+/* Uniform Cartesian grid: nx*ny cells of size hx*hy, lower-left corner
+ * (x0, y0).  The cell edges are the abscissas of Sec. 3.1. */
+typedef struct {
+    int nx, ny;
+    double x0, y0, hx, hy;
+} ccns_grid;
+
+/* Synthetic bodies.  Fluid is where the body's level set is positive.
+ *  CCNS_CIRCLE : centre (cx, cy), radius a
+ *  CCNS_ELLIPSE: centre (cx, cy), semi-axes a, b, rotation `angle` (rad)
+ *  CCNS_NACA4  : symmetric NACA 4-digit section, leading edge (cx, cy),
+ *                chord `chord`, thickness ratio t, angle of attack `angle`
+ *                (nose up: trailing edge below the leading edge). */
+enum { CCNS_CIRCLE = 0, CCNS_ELLIPSE = 1, CCNS_NACA4 = 2 };
+typedef struct {
+    int kind;
+    double cx, cy, a, b, angle, chord, t;
+} ccns_body;
+
+/* A user level set: returns > 0 in the fluid. */
+typedef double (*ccns_levelset_fn)(double x, double y, void *user);
+
+/* Capacity arrays, each in the dense host layout, stored one after the other
+ * in this order (the symbols of Sec. 3.2-3.4; staggered-grid names
+ * A^{xx} etc. as in Sec. 3.4):
+ *   V Ax Ay Bx By Wx Wy | Vu Axx Axy Bxx Bxy Wxx Wxy | Vv Ayy Ayx Byy Byx Wyy Wyx */
+enum {
+    CCNS_CAP_V = 0, CCNS_CAP_AX, CCNS_CAP_AY, CCNS_CAP_BX, CCNS_CAP_BY, CCNS_CAP_WX, CCNS_CAP_WY,
+    CCNS_CAP_VU, CCNS_CAP_AXX, CCNS_CAP_AXY, CCNS_CAP_BXX, CCNS_CAP_BXY, CCNS_CAP_WXX, CCNS_CAP_WXY,
+    CCNS_CAP_VV, CCNS_CAP_AYY, CCNS_CAP_AYX, CCNS_CAP_BYY, CCNS_CAP_BYX, CCNS_CAP_WYY, CCNS_CAP_WYX,
+    CCNS_NCAPS
+};
+
+/* Number of doubles ccns_capacities writes: CCNS_NCAPS*(ny+2)*(nx+2). */
+size_t ccns_caps_count(const ccns_grid *grid);
+
+/* Capacities of the first and second kind (eq:volumefirstkind, eq:centroid,
+ * eq:surfacefirstkindx/y, eq:volumesecondkindx/y, eq:surfacesecondkindx/y)
+ * on the pressure grid and the two half-cell shifted velocity grids
+ * (Sec. 3.4), computed on the host from the fluid level set.
+ * The fluid is outside every body in `bodies` (nbody >= 0) and, if `fn` is
+ * not NULL, also where fn(x, y, user) > 0.  Box reading: each grid's fluid
+ * lies inside its own box (the pressure box; the velocity grids' boxes
+ * extend half a cell across their own normal walls); node lines on the
+ * tangential walls are dry; pressure-grid wall faces are wetted.
+ * caps_host: caller-owned host buffer of ccns_caps_count() doubles.
+ * Capacities below 1e-12 h (lengths) or 1e-12 hx hy (volumes) are 0.
+ * Errors: CCNS_EINVAL for a bad grid or body. */
+ccns_status ccns_capacities(const ccns_grid *grid, const ccns_body *bodies, int nbody,
+                            ccns_levelset_fn fn, void *user, double *caps_host);
+
+/* Solver parameters.
+ *  rho, mu, tau   density, dynamic viscosity, time step (> 0)
+ *  u_ref          reference velocity of the divergence diagnostic
+ *  gx, gy         gravity (body force rho*M*g of eq:semidiscrete)
+ *  pcg_tol        Poisson: stop when ||r||_2 <= pcg_tol ||b||_2
+ *  pred_tol       predictor: same criterion
+ *  div_tol        precision 1: outer refinement stops at div_rel <= div_tol
+ *  pcg_maxit, pred_maxit   iteration limits
+ *  precision      0 = FP64 throughout; 1 = FP32 stencils and inner CG with
+ *                 FP64 reductions and an FP64 iterative-refinement loop
+ *  visc_form      node strain weights: 0 symmetric (geometric mean of the two
+ *                 node volumes for the cross coupling), 1 as printed in
+ *                 eq:offdiag (not symmetric; apply only), 2 arithmetic mean
+ *  poisson_weight 0: Poisson face weight A^2/V_f (mass matrix explicit);
+ *                 1: A^2 (the printed equations with unit mass matrix) */
+typedef struct {
+    double rho, mu, tau, u_ref, gx, gy;
+    double pcg_tol, pred_tol, div_tol;
+    int pcg_maxit, pred_maxit;
+    int precision;
+    int visc_form;
+    int poisson_weight;
+    int reserved;
+} ccns_params;
+
+typedef struct ccns_ctx ccns_ctx;
+
+/* Device workspace needed for a context on this grid (bytes). */
+size_t ccns_workspace_bytes(const ccns_grid *grid, const ccns_params *params);
+
+/* Create a context: validates the capacities (no NaN, no negative value),
+ * derives the activity masks and coefficient fields (Poisson face weights,
+ * corrector factors, viscous node/cell weights, Jacobi diagonals, the
+ * Dirichlet contributions cont(0,D) and visc(strain(U~,D))), and uploads
+ * everything into the workspace on `hip_stream`.
+ *  caps_host   ccns_caps_count() doubles (ccns_capacities layout)
+ *  dirichlet_host  2*(ny+2)*(nx+2) doubles: D^x then D^y (dense layout);
+ *              the staggered Dirichlet data of Sec. 4, constant in time.
+ *  dev_workspace   device buffer of ws_bytes >= ccns_workspace_bytes()
+ *  hip_stream  hipStream_t (NULL = default stream)
+ * Errors: CCNS_EINVAL, CCNS_ENOMEM, CCNS_EDEVICE. */
+ccns_status ccns_ctx_create(const ccns_grid *grid, const ccns_params *params,
+                            const double *caps_host, const double *dirichlet_host,
+                            void *dev_workspace, size_t ws_bytes, void *hip_stream,
+                            ccns_ctx **out);
+void ccns_ctx_destroy(ccns_ctx *ctx);
+const char *ccns_last_error(const ccns_ctx *ctx);
+
+/* Fields held in the workspace (FP64). */
+enum {
+    CCNS_F_UX = 0,   /* U^x, x-faces */
+    CCNS_F_UY,       /* U^y, y-faces */
+    CCNS_F_P,        /* pressure P^{n-1/2}, cells */
+    CCNS_F_PHI,      /* last Poisson solution Phi^n (warm start), cells */
+    CCNS_F_CONVX,    /* conv^{n-1}, x-faces */
+    CCNS_F_CONVY,
+    CCNS_F_USX,      /* predicted U* of the last step, x-faces */
+    CCNS_F_USY,
+    CCNS_F_B,        /* Poisson right-hand side of the last solve, cells */
+    CCNS_NFIELDS
+};
+
+/* Copy a field between the workspace and a dense (ny+2)x(nx+2) array.
+ * `is_device` != 0: the array is device memory, else host memory.
+ * Setting CCNS_F_CONVX/Y marks conv^{n-1} as valid (otherwise the first
+ * step takes conv^{-1} := conv^0).  Errors: CCNS_EINVAL (bad field). */
+ccns_status ccns_field_set(ccns_ctx *ctx, int field, const double *src, int is_device);
+ccns_status ccns_field_get(ccns_ctx *ctx, int field, double *dst, int is_device);
+
+/* Operator applies on dense device arrays (FP64), for parity checks.
+ *  CCNS_OP_CONT : in = {Ux, Uy}  out = {c}     c = cont(U, D) (eq:divergence), cells
+ *  CCNS_OP_PRES : in = {P}       out = {gx, gy} pres(P) = A dP/dxi (eq:compatibility), real faces
+ *  CCNS_OP_VISC : in = {Ux, Uy}  out = {vx, vy} visc(strain(U, D)) (eq:diag, eq:offdiag, Sec. 4.3), interior faces
+ *  CCNS_OP_CONV : in = {Ux, Uy}  out = {cx, cy} conv(U, U, D, D) (eq:convective), interior faces
+ *  CCNS_OP_LAP  : in = {phi}     out = {q}     q = L phi = cont(M^-1 pres(phi), 0), active cells
+ *  CCNS_OP_H    : in = {px, py}  out = {hx, hy} H p = (rho/tau) V p - mu visc(strain(p, 0)), unknown faces
+ *  CCNS_OP_KINETIC: in = {Ux, Uy} out = {k}    kinetic(U) (Sec. 4.5), cells
+ * D is the context's Dirichlet data.  Outputs are written on the index range
+ * stated and set to 0 elsewhere.  in/out: arrays of device pointers to dense
+ * (ny+2)x(nx+2) doubles.  Errors: CCNS_EINVAL (unknown op). */
+enum { CCNS_OP_CONT = 0, CCNS_OP_PRES, CCNS_OP_VISC, CCNS_OP_CONV, CCNS_OP_LAP, CCNS_OP_H, CCNS_OP_KINETIC };
+ccns_status ccns_apply(ccns_ctx *ctx, int op, const double *const *in, double *const *out);
+
+typedef struct {
+    int iterations;        /* CG iterations (inner iterations in precision 1) */
+    int outer;             /* refinement sweeps (precision 1), else 1 */
+    double rel_residual;   /* final ||r||_2 / ||b||_2 (FP64) */
+    int status;            /* ccns_status of this solve */
+} ccns_solve_info;
+
+typedef struct {
+    ccns_solve_info pred;  /* predictor solve (eq:pm_prediction) */
+    ccns_solve_info poisson; /* pressure solve (eq:pm_poisson) */
+    double div_max;        /* max |cont(U^{n+1}, D)| over pressure unknowns */
+    double div_rel;        /* div_max / (u_ref * min(hx, hy)) */
+    double ke;             /* sum of kinetic(U^{n+1}) over cells (Sec. 4.5) */
+    double mass;           /* sum of cont(U^{n+1}, D) over cells (net boundary flux) */
+    double mom_x, mom_y;   /* sum of rho V_alpha U_alpha over unknown faces */
+} ccns_step_info;
+
+/* Pressure solve (eq:pm_poisson, Sec. 4.6 with the zero-mean projection):
+ * solves L phi = b on the pressure unknowns by Jacobi-preconditioned CG,
+ * starting from the current CCNS_F_PHI, after removing the mean of b.
+ * b, phi: dense device arrays (phi may be NULL: the result stays in
+ * CCNS_F_PHI).  Errors: CCNS_ENOTCONV, CCNS_EBREAKDOWN (outputs written). */
+ccns_status ccns_pressure_solve(ccns_ctx *ctx, const double *b, double *phi, ccns_solve_info *info);
+
+/* Make the current velocity discretely divergence-free (the initial
+ * projection): Poisson from cont(U, D), then the corrector.  P is unchanged. */
+ccns_status ccns_project(ccns_ctx *ctx, ccns_step_info *info);
+
+/* Advance nsteps projection-method-II time steps (eq:pm_prediction,
+ * eq:pm_poisson, eq:pm_projection, eq:pm_update).  info (may be NULL)
+ * receives the last step's figures.  The state stays on the device; the host
+ * reads a few scalars per step.  Errors: CCNS_ENOTCONV, CCNS_EBREAKDOWN. */
+ccns_status ccns_step(ccns_ctx *ctx, int nsteps, ccns_step_info *info);
+
+/* The phases of one step, for inspection:
+ *  ccns_predict  conv^n and the predictor solve (writes CCNS_F_USX/USY)
+ *  ccns_correct  Poisson right-hand side from U*, pressure solve, corrector
+ *                and pressure update (writes U, P, PHI, B) */
+ccns_status ccns_predict(ccns_ctx *ctx, ccns_solve_info *info);
+ccns_status ccns_correct(ccns_ctx *ctx, ccns_step_info *info);
+
+/* Kernel timing for measurement.  While enabled, every 4th iteration of
+ * each CG solve is bracketed with HIP events on the context's stream (the
+ * direction+operator kernel and the update kernel separately).  ms[4] and
+ * count[4] (may be NULL) receive the accumulated milliseconds and launch
+ * counts since the last reset, in the order: Poisson operator kernel,
+ * Poisson update kernel, predictor operator kernel, predictor update
+ * kernel.  enable: 1 on, 0 off, -1 leave unchanged; 0 and 1 also reset the
+ * accumulators (after they are returned). */
+ccns_status ccns_timing(ccns_ctx *ctx, int enable, double *ms, long *count);
+
+/* Diagnostics of the current state (FP64 reductions on the device). */
+ccns_status ccns_diagnostics(ccns_ctx *ctx, ccns_step_info *info);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CCNS_H */

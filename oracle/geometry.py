@@ -138,15 +138,19 @@ class CircleGeometry:
     def rect(self, xa, xb, ya, yb):
         if xb <= xa or yb <= ya:
             return 0.0, 0.0, 0.0
+        # moments about the rectangle's centre keep the cancellation between
+        # the rectangle and the disc parts at the scale of the rectangle
+        xc, yc = 0.5 * (xa + xb), 0.5 * (ya + yb)
+        hx, hy = 0.5 * (xb - xa), 0.5 * (yb - ya)
         a = (xb - xa) * (yb - ya)
-        mx = 0.5 * (xb * xb - xa * xa) * (yb - ya)
-        my = 0.5 * (yb * yb - ya * ya) * (xb - xa)
+        mx = my = 0.0
         for cx, cy, r in self.discs:
-            da, dmx, dmy = disc_rect_moments(cx, cy, r, xa, xb, ya, yb)
+            da, dmx, dmy = disc_rect_moments(cx - xc, cy - yc, r, -hx, hx, -hy, hy)
             a -= da
             mx -= dmx
             my -= dmy
-        return max(a, 0.0), mx, my
+        a = max(a, 0.0)
+        return a, mx + xc * a, my + yc * a
 
     def vseg(self, x, ya, yb):
         if yb <= ya:
@@ -291,18 +295,31 @@ class LevelSetGeometry:
         for yy in (ya, yb):
             for r in sign_change_roots(lambda x: phi(x, yy), xa, xb):
                 bps.add(r)
-        xs = np.linspace(xa, xb, 9)
-        cnt = [self._count(float(x), ya, yb) for x in xs]
-        for k in range(8):
-            if cnt[k] != cnt[k + 1]:
-                lo, hi, clo = float(xs[k]), float(xs[k + 1]), cnt[k]
-                while hi - lo > 1e-14 * max(1.0, abs(hi)):
-                    mid = 0.5 * (lo + hi)
-                    if self._count(mid, ya, yb) == clo:
-                        lo = mid
-                    else:
-                        hi = mid
-                bps.add(0.5 * (lo + hi))
+        # Vertical tangents change the number of roots on a vertical line:
+        # probe that count on a uniform grid and just beside every edge
+        # crossing (a tangent can sit closer to a crossing than any
+        # quadrature node), and bisect wherever it changes.
+        eps = 1e-12 * (xb - xa)
+        probe = list(np.linspace(xa, xb, 17))
+        for b0 in sorted(bps):
+            if b0 - eps > xa:
+                probe.append(b0 - eps)
+            if b0 + eps < xb:
+                probe.append(b0 + eps)
+        probe = sorted(probe)
+        cnt = [self._count(float(x), ya, yb) for x in probe]
+        for k in range(len(probe) - 1):
+            lo, hi = float(probe[k]), float(probe[k + 1])
+            if cnt[k] == cnt[k + 1] or hi - lo <= 2.5 * eps:
+                continue
+            clo = cnt[k]
+            while hi - lo > 1e-15 * max(1.0, abs(hi)):
+                mid = 0.5 * (lo + hi)
+                if self._count(mid, ya, yb) == clo:
+                    lo = mid
+                else:
+                    hi = mid
+            bps.add(0.5 * (lo + hi))
         pts = sorted(bps)
 
         def moments(x):
@@ -391,27 +408,68 @@ def _grid_caps(geo, ex, ey, box, wall_faces_wet, eps_v):
             return xb - xa
         return geo.hseg(y, xa, xb)
 
+    # Control volumes and segments away from every body are evaluated in
+    # closed form for the whole grid at once (the rectangle clipped to the
+    # box); the per-entry integration below then revisits only entries that
+    # may meet an interface.
+    exa, eya = np.asarray(ex), np.asarray(ey)
+    XA, YA = np.meshgrid(np.maximum(exa[:-1], bx0), np.maximum(eya[:-1], by0))
+    XB, YB = np.meshgrid(np.minimum(exa[1:], bx1), np.minimum(eya[1:], by1))
+    wx_, wy_ = np.clip(XB - XA, 0, None), np.clip(YB - YA, 0, None)
+    V[:] = wx_ * wy_
+    full = V > eps_v
+    Xc, Yc = np.meshgrid(0.5 * (exa[:-1] + exa[1:]), 0.5 * (eya[:-1] + eya[1:]))
+    X[:] = np.where(full, 0.5 * (XA + XB), Xc)
+    Y[:] = np.where(full, 0.5 * (YA + YB), Yc)
+    V[~full] = 0.0
+
+    def seg_len_v(xv, y0v, y1v, wet):
+        inside = ((xv > bx0) & (xv < bx1)) | (wet & (xv >= bx0) & (xv <= bx1))
+        return np.where(inside, np.clip(np.minimum(y1v, by1) - np.maximum(y0v, by0), 0, None), 0.0)
+
+    def seg_len_h(yv, x0v, x1v, wet):
+        inside = ((yv > by0) & (yv < by1)) | (wet & (yv >= by0) & (yv <= by1))
+        return np.where(inside, np.clip(np.minimum(x1v, bx1) - np.maximum(x0v, bx0), 0, None), 0.0)
+
+    EX0, EY0 = np.meshgrid(exa[:-1], eya[:-1])
+    EX1, EY1 = np.meshgrid(exa[1:], eya[1:])
+    E[:] = seg_len_v(EX1, EY0, EY1, wall_faces_wet)
+    N[:] = seg_len_h(EY1, EX0, EX1, wall_faces_wet)
+
+    def touched(xa, xb, ya, yb):
+        return geo.needs_work(max(xa, bx0), min(xb, bx1), max(ya, by0), min(yb, by1))
+
+    work = np.zeros(shape, dtype=bool)
     for j in range(nj):
         for i in range(ni):
-            a, mx, my = rect(ex[i], ex[i + 1], ey[j], ey[j + 1])
-            if a > eps_v:
-                V[j, i] = a
-                X[j, i] = min(max(mx / a, ex[i]), ex[i + 1])
-                Y[j, i] = min(max(my / a, ey[j]), ey[j + 1])
-            else:
-                X[j, i] = 0.5 * (ex[i] + ex[i + 1])
-                Y[j, i] = 0.5 * (ey[j] + ey[j + 1])
-    for j in range(nj):
-        for i in range(ni):
-            E[j, i] = vseg(ex[i + 1], ey[j], ey[j + 1], wall_faces_wet)
-            N[j, i] = hseg(ey[j + 1], ex[i], ex[i + 1], wall_faces_wet)
-            Bv[j, i] = vseg(X[j, i], ey[j], ey[j + 1])
-            Bh[j, i] = hseg(Y[j, i], ex[i], ex[i + 1])
-            if i + 1 < ni:
-                # fluid between the centroids of CV i and CV i+1 in this strip
-                We[j, i] = rect(X[j, i], X[j, i + 1], ey[j], ey[j + 1])[0]
-            if j + 1 < nj:
-                Wn[j, i] = rect(ex[i], ex[i + 1], Y[j, i], Y[j + 1, i])[0]
+            work[j, i] = touched(ex[i] - 1e-12, ex[i + 1] + 1e-12, ey[j] - 1e-12, ey[j + 1] + 1e-12)
+    for j, i in zip(*np.nonzero(work)):
+        a, mx, my = rect(ex[i], ex[i + 1], ey[j], ey[j + 1])
+        if a > eps_v:
+            V[j, i] = a
+            X[j, i] = min(max(mx / a, ex[i]), ex[i + 1])
+            Y[j, i] = min(max(my / a, ey[j]), ey[j + 1])
+        else:
+            V[j, i] = 0.0
+            X[j, i] = 0.5 * (ex[i] + ex[i + 1])
+            Y[j, i] = 0.5 * (ey[j] + ey[j + 1])
+        E[j, i] = vseg(ex[i + 1], ey[j], ey[j + 1], wall_faces_wet)
+        N[j, i] = hseg(ey[j + 1], ex[i], ex[i + 1], wall_faces_wet)
+    Bv[:] = seg_len_v(X, EY0, EY1, False)
+    Bh[:] = seg_len_h(Y, EX0, EX1, False)
+    We[:, :-1] = np.clip(np.minimum(X[:, 1:], bx1) - np.maximum(X[:, :-1], bx0), 0, None) * wy_[:, :-1]
+    Wn[:-1, :] = np.clip(np.minimum(Y[1:, :], by1) - np.maximum(Y[:-1, :], by0), 0, None) * wx_[:-1, :]
+    # entries next to a worked control volume can be cut as well
+    near = work.copy()
+    near[:, :-1] |= work[:, 1:]
+    near[:-1, :] |= work[1:, :]
+    for j, i in zip(*np.nonzero(near)):
+        Bv[j, i] = vseg(X[j, i], ey[j], ey[j + 1])
+        Bh[j, i] = hseg(Y[j, i], ex[i], ex[i + 1])
+        if i + 1 < ni:
+            We[j, i] = rect(X[j, i], X[j, i + 1], ey[j], ey[j + 1])[0]
+        if j + 1 < nj:
+            Wn[j, i] = rect(ex[i], ex[i + 1], Y[j, i], Y[j + 1, i])[0]
     return GridCaps(V, X, Y, E, N, Bv, Bh, We, Wn)
 
 

@@ -1,0 +1,456 @@
+// Host computation of the capacities of the first and second kind
+// (Sec. 3.2 eq:volumefirstkind, eq:centroid, eq:surfacefirstkindx/y;
+// Sec. 3.3 eq:volumesecondkindx/y, eq:surfacesecondkindx/y; Sec. 3.4 for the
+// two half-cell shifted velocity grids) from a level set.
+//
+// Every capacity is an integral of the fluid characteristic function over an
+// axis-aligned rectangle or segment.  Segments: the fluid intervals of a line
+// are found from sign changes of the level set on 16 samples, pairs of roots
+// hidden between samples are searched for around each local minimum of |phi|,
+// and roots are refined by bisection.  Rectangles: the wet length of the
+// vertical line through x (and its first moment in y) is integrated over x by
+// adaptive Gauss-Kronrod (7/15 points) after splitting at the points where
+// the interface meets the rectangle's top and bottom edges; vertical tangents
+// of the interface inside are resolved by the adaptive error control.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "ccns.h"
+#include "ccns_internal.h"
+
+namespace ccns {
+namespace {
+
+struct Fluid {
+    const ccns_body *bodies;
+    int nbody;
+    ccns_levelset_fn fn;
+    void *user;
+
+    static double naca_yt(double xi, double t) {
+        xi = std::min(std::max(xi, 0.0), 1.0);
+        return 5.0 * t * (0.2969 * std::sqrt(xi) - 0.1260 * xi - 0.3516 * xi * xi +
+                          0.2843 * xi * xi * xi - 0.1015 * xi * xi * xi * xi);
+    }
+    static double body(const ccns_body &b, double x, double y) {
+        switch (b.kind) {
+        case CCNS_CIRCLE:
+            return std::hypot(x - b.cx, y - b.cy) - b.a;
+        case CCNS_ELLIPSE: {
+            double c = std::cos(b.angle), s = std::sin(b.angle);
+            double xr = c * (x - b.cx) + s * (y - b.cy);
+            double yr = -s * (x - b.cx) + c * (y - b.cy);
+            return std::sqrt((xr / b.a) * (xr / b.a) + (yr / b.b) * (yr / b.b)) - 1.0;
+        }
+        default: {  // NACA 4-digit symmetric
+            double c = std::cos(b.angle), s = std::sin(b.angle);
+            double dx = x - b.cx, dy = y - b.cy;
+            double xi = (dx * c - dy * s) / b.chord;
+            double eta = (dx * s + dy * c) / b.chord;
+            double f;
+            if (xi < 0.0)
+                f = std::hypot(xi, eta);
+            else if (xi > 1.0)
+                f = std::hypot(xi - 1.0, std::max(std::fabs(eta) - naca_yt(1.0, b.t), 0.0)) + 1e-300;
+            else
+                f = std::fabs(eta) - naca_yt(xi, b.t);
+            return f * b.chord;
+        }
+        }
+    }
+    double operator()(double x, double y) const {
+        double v = 1.0;
+        bool any = false;
+        for (int k = 0; k < nbody; ++k) {
+            double f = body(bodies[k], x, y);
+            v = any ? std::min(v, f) : f;
+            any = true;
+        }
+        if (fn) {
+            double f = fn(x, y, user);
+            v = any ? std::min(v, f) : f;
+            any = true;
+        }
+        return v;
+    }
+    // Axis-aligned box that contains every interface point of the bodies.
+    void body_box(int k, double &x0, double &x1, double &y0, double &y1) const {
+        const ccns_body &b = bodies[k];
+        if (b.kind == CCNS_CIRCLE) {
+            x0 = b.cx - b.a; x1 = b.cx + b.a; y0 = b.cy - b.a; y1 = b.cy + b.a;
+        } else if (b.kind == CCNS_ELLIPSE) {
+            double r = std::max(b.a, b.b);
+            x0 = b.cx - r; x1 = b.cx + r; y0 = b.cy - r; y1 = b.cy + r;
+        } else {
+            double c = std::cos(b.angle), s = std::sin(b.angle), ht = 0.6 * b.t * b.chord;
+            double xa = b.cx, xb = b.cx + b.chord * c, ya = b.cy, yb = b.cy - b.chord * s;
+            x0 = std::min(xa, xb) - ht; x1 = std::max(xa, xb) + ht;
+            y0 = std::min(ya, yb) - ht; y1 = std::max(ya, yb) + ht;
+        }
+    }
+    // True when the rectangle may contain interface points.
+    bool maybe_cut(double xa, double xb, double ya, double yb, double margin) const {
+        if (fn) return true;
+        for (int k = 0; k < nbody; ++k) {
+            double x0, x1, y0, y1;
+            body_box(k, x0, x1, y0, y1);
+            if (xa < x1 + margin && xb > x0 - margin && ya < y1 + margin && yb > y0 - margin)
+                return true;
+        }
+        return false;
+    }
+};
+
+// Fluid sub-intervals of [a, b] for g(s) > 0; returns the count (<= cap).
+template <class G>
+int fluid_intervals(const G &g, double a, double b, double *lo, double *hi, int cap) {
+    if (!(b > a)) return 0;
+    const int n = 16;
+    double s[n + 1], v[n + 1];
+    for (int k = 0; k <= n; ++k) {
+        s[k] = (k == n) ? b : a + (b - a) * (double)k / n;
+        v[k] = g(s[k]);
+    }
+    double roots[64];
+    int nr = 0;
+    auto bisect = [&](double l, double r) {
+        bool pl = g(l) > 0.0;
+        for (int it = 0; it < 200 && r - l > 1e-16 * std::max(1.0, std::fabs(r)); ++it) {
+            double m = 0.5 * (l + r);
+            if ((g(m) > 0.0) == pl) l = m; else r = m;
+        }
+        return 0.5 * (l + r);
+    };
+    for (int k = 0; k < n; ++k)
+        if ((v[k] > 0.0) != (v[k + 1] > 0.0) && nr < 62) roots[nr++] = bisect(s[k], s[k + 1]);
+    // root pairs hidden between samples: look for a sign flip at local minima of |g|
+    for (int k = 0; k <= n; ++k) {
+        int l = std::max(k - 1, 0), r = std::min(k + 1, n);
+        bool p = v[k] > 0.0;
+        if ((v[l] > 0.0) != p || (v[r] > 0.0) != p) continue;
+        if (std::fabs(v[k]) > std::fabs(v[l]) || std::fabs(v[k]) > std::fabs(v[r])) continue;
+        double sg = p ? 1.0 : -1.0;
+        double xl = s[l], xr = s[r];
+        const double gr = 0.5 * (std::sqrt(5.0) - 1.0);
+        double c = xr - gr * (xr - xl), d = xl + gr * (xr - xl);
+        double fc = sg * g(c), fd = sg * g(d);
+        bool found = false;
+        double xm = 0.5 * (xl + xr);
+        for (int it = 0; it < 90; ++it) {
+            if (fc <= 0.0) { xm = c; found = true; break; }
+            if (fd <= 0.0) { xm = d; found = true; break; }
+            if (fc < fd) { xr = d; d = c; fd = fc; c = xr - gr * (xr - xl); fc = sg * g(c); }
+            else { xl = c; c = d; fc = fd; d = xl + gr * (xr - xl); fd = sg * g(d); }
+            if (xr - xl < 1e-15 * std::max(1.0, std::fabs(xr))) break;
+        }
+        if (!found) {
+            xm = 0.5 * (xl + xr);
+            found = (g(xm) > 0.0) != p;
+        }
+        if (found && nr < 62) {
+            roots[nr++] = bisect(s[l], xm);
+            roots[nr++] = bisect(xm, s[r]);
+        }
+    }
+    std::sort(roots, roots + nr);
+    double pts[66];
+    int np = 0;
+    pts[np++] = a;
+    for (int k = 0; k < nr; ++k)
+        if (roots[k] > a && roots[k] < b && roots[k] - pts[np - 1] > 1e-13 * (b - a)) pts[np++] = roots[k];
+    pts[np++] = b;
+    int m = 0;
+    for (int k = 0; k + 1 < np; ++k) {
+        if (pts[k + 1] > pts[k] && g(0.5 * (pts[k] + pts[k + 1])) > 0.0 && m < cap) {
+            lo[m] = pts[k];
+            hi[m] = pts[k + 1];
+            ++m;
+        }
+    }
+    return m;
+}
+
+// Gauss-Kronrod 7/15 nodes and weights on [-1, 1].
+const double kXK[8] = {0.991455371120812639206854697526329, 0.949107912342758524526189684047851,
+                       0.864864423359769072789712788640926, 0.741531185599394439863864773280788,
+                       0.586087235467691130294144845693013, 0.405845151377397166906606412076961,
+                       0.207784955007898467600689403773245, 0.000000000000000000000000000000000};
+const double kWK[8] = {0.022935322010529224963732008058970, 0.063092092629978553290700663189204,
+                       0.104790010322250183839876322541518, 0.140653259715525918745189590510238,
+                       0.169004726639267902826583426598550, 0.190350578064785409913256402421014,
+                       0.204432940075298892414161999234649, 0.209482141084727828012999174891714};
+const double kWG[4] = {0.129484966168869693270611432679082, 0.279705391489276667901467771423780,
+                       0.381830050505118944950369775488975, 0.417959183673469387755102040816327};
+
+struct Moments {
+    double a, mx, my;
+};
+
+class Integrator {
+  public:
+    Integrator(const Fluid &f) : f_(f) {}
+
+    double vseg(double x, double ya, double yb) const {
+        double lo[32], hi[32];
+        int m = fluid_intervals([&](double y) { return f_(x, y); }, ya, yb, lo, hi, 32);
+        double L = 0.0;
+        for (int k = 0; k < m; ++k) L += hi[k] - lo[k];
+        return L;
+    }
+    double hseg(double y, double xa, double xb) const {
+        double lo[32], hi[32];
+        int m = fluid_intervals([&](double x) { return f_(x, y); }, xa, xb, lo, hi, 32);
+        double L = 0.0;
+        for (int k = 0; k < m; ++k) L += hi[k] - lo[k];
+        return L;
+    }
+    Moments rect(double xa, double xb, double ya, double yb) const {
+        Moments out{0, 0, 0};
+        if (!(xb > xa) || !(yb > ya)) return out;
+        std::vector<double> pts{xa, xb};
+        for (double yy : {ya, yb}) {
+            double lo[32], hi[32];
+            int m = fluid_intervals([&](double x) { return f_(x, yy); }, xa, xb, lo, hi, 32);
+            for (int k = 0; k < m; ++k) {
+                if (lo[k] > xa) pts.push_back(lo[k]);
+                if (hi[k] < xb) pts.push_back(hi[k]);
+            }
+        }
+        std::sort(pts.begin(), pts.end());
+        // Vertical tangents of the interface change the number of roots on a
+        // vertical line.  Probe that count on a uniform grid and just beside
+        // every edge crossing (a tangent next to a crossing can be closer to
+        // it than any quadrature node), and bisect wherever it changes.
+        {
+            const double eps = 1e-12 * (xb - xa);
+            std::vector<double> probe;
+            for (int k = 0; k <= 16; ++k) probe.push_back(xa + (xb - xa) * k / 16.0);
+            for (double b : pts) {
+                if (b - eps > xa) probe.push_back(b - eps);
+                if (b + eps < xb) probe.push_back(b + eps);
+            }
+            std::sort(probe.begin(), probe.end());
+            auto count = [&](double x) {
+                double lo[32], hi[32];
+                int m = fluid_intervals([&](double y) { return f_(x, y); }, ya, yb, lo, hi, 32);
+                int c = 0;
+                for (int k = 0; k < m; ++k) c += (lo[k] > ya) + (hi[k] < yb);
+                return c;
+            };
+            std::vector<int> cnt(probe.size());
+            for (size_t k = 0; k < probe.size(); ++k) cnt[k] = count(probe[k]);
+            std::vector<double> extra;
+            for (size_t k = 0; k + 1 < probe.size(); ++k) {
+                double l = probe[k], r = probe[k + 1];
+                if (cnt[k] == cnt[k + 1] || r - l <= 2.5 * eps) continue;
+                int cl = cnt[k];
+                while (r - l > 1e-15 * std::max(1.0, std::fabs(r))) {
+                    double m = 0.5 * (l + r);
+                    if (count(m) == cl) l = m; else r = m;
+                }
+                extra.push_back(0.5 * (l + r));
+            }
+            pts.insert(pts.end(), extra.begin(), extra.end());
+            std::sort(pts.begin(), pts.end());
+        }
+        double tol = 1e-14 * (xb - xa) * (yb - ya);
+        for (size_t k = 0; k + 1 < pts.size(); ++k) {
+            if (pts[k + 1] <= pts[k]) continue;
+            Moments m = adapt(pts[k], pts[k + 1], ya, yb, tol * (pts[k + 1] - pts[k]) / (xb - xa), 0);
+            out.a += m.a; out.mx += m.mx; out.my += m.my;
+        }
+        return out;
+    }
+
+  private:
+    void column(double x, double ya, double yb, double &L, double &M) const {
+        double lo[32], hi[32];
+        int m = fluid_intervals([&](double y) { return f_(x, y); }, ya, yb, lo, hi, 32);
+        L = 0.0;
+        M = 0.0;
+        for (int k = 0; k < m; ++k) {
+            L += hi[k] - lo[k];
+            M += 0.5 * (hi[k] * hi[k] - lo[k] * lo[k]);
+        }
+    }
+    // one G7K15 panel; returns Kronrod estimates and the max error estimate
+    double panel(double p, double q, double ya, double yb, Moments &k) const {
+        double c = 0.5 * (p + q), h = 0.5 * (q - p);
+        double ka = 0, kx = 0, ky = 0, ga = 0, gx = 0, gy = 0;
+        for (int i = 0; i < 8; ++i) {
+            int nside = (i == 7) ? 1 : 2;
+            for (int sgn = 0; sgn < nside; ++sgn) {
+                double x = c + (sgn ? -1.0 : 1.0) * h * kXK[i];
+                double L, M;
+                column(x, ya, yb, L, M);
+                ka += kWK[i] * L; kx += kWK[i] * x * L; ky += kWK[i] * M;
+                if (i % 2 == 1) {
+                    double w = kWG[i / 2];
+                    ga += w * L; gx += w * x * L; gy += w * M;
+                }
+            }
+        }
+        k.a = ka * h; k.mx = kx * h; k.my = ky * h;
+        double e = std::max(std::fabs(ka - ga), std::max(std::fabs(kx - gx) / std::max(1.0, std::fabs(c)),
+                                                         std::fabs(ky - gy) / std::max(1.0, std::fabs(yb))));
+        return e * h;
+    }
+    Moments adapt(double p, double q, double ya, double yb, double tol, int depth) const {
+        Moments k;
+        double e = panel(p, q, ya, yb, k);
+        // the estimate itself carries rounding of about 1e-16 of the panel
+        // integral: never ask for less than a few hundred ulps of it
+        const double floor_ = 256.0 * 2.2e-16 * (q - p) * (yb - ya);
+        if (e <= std::max(tol, floor_) || depth >= 40 || q - p < 1e-15 * std::max(1.0, std::fabs(q))) return k;
+        double m = 0.5 * (p + q);
+        Moments l = adapt(p, m, ya, yb, 0.5 * tol, depth + 1);
+        Moments r = adapt(m, q, ya, yb, 0.5 * tol, depth + 1);
+        return Moments{l.a + r.a, l.mx + r.mx, l.my + r.my};
+    }
+    const Fluid &f_;
+};
+
+// Capacities of one grid of control volumes [ex[i], ex[i+1]] x [ey[j], ey[j+1]]
+// (i = 0..ni-1, j = 0..nj-1) for fluid = {phi > 0} inside the open box.
+struct GridOut {
+    std::vector<double> V, X, Y, E, N, Bv, Bh, We, Wn;
+};
+
+GridOut grid_caps(const Fluid &fl, const Integrator &in, const std::vector<double> &ex,
+                  const std::vector<double> &ey, double bx0, double bx1, double by0, double by1,
+                  bool wall_faces_wet, double epsV, double margin) {
+    const int ni = (int)ex.size() - 1, nj = (int)ey.size() - 1;
+    GridOut g;
+    size_t n = (size_t)ni * nj;
+    for (auto *v : {&g.V, &g.X, &g.Y, &g.E, &g.N, &g.Bv, &g.Bh, &g.We, &g.Wn}) v->assign(n, 0.0);
+    auto rect = [&](double xa, double xb, double ya, double yb) -> Moments {
+        xa = std::max(xa, bx0); xb = std::min(xb, bx1);
+        ya = std::max(ya, by0); yb = std::min(yb, by1);
+        if (!(xb > xa) || !(yb > ya)) return Moments{0, 0, 0};
+        if (!fl.maybe_cut(xa, xb, ya, yb, margin))
+            return Moments{(xb - xa) * (yb - ya), 0.5 * (xb * xb - xa * xa) * (yb - ya),
+                           0.5 * (yb * yb - ya * ya) * (xb - xa)};
+        return in.rect(xa, xb, ya, yb);
+    };
+    auto vseg = [&](double x, double ya, double yb, bool wet) -> double {
+        bool inside = (x > bx0 && x < bx1) || (wet && x >= bx0 && x <= bx1);
+        if (!inside) return 0.0;
+        ya = std::max(ya, by0); yb = std::min(yb, by1);
+        if (!(yb > ya)) return 0.0;
+        if (!fl.maybe_cut(x, x, ya, yb, margin)) return yb - ya;
+        return in.vseg(x, ya, yb);
+    };
+    auto hseg = [&](double y, double xa, double xb, bool wet) -> double {
+        bool inside = (y > by0 && y < by1) || (wet && y >= by0 && y <= by1);
+        if (!inside) return 0.0;
+        xa = std::max(xa, bx0); xb = std::min(xb, bx1);
+        if (!(xb > xa)) return 0.0;
+        if (!fl.maybe_cut(xa, xb, y, y, margin)) return xb - xa;
+        return in.hseg(y, xa, xb);
+    };
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int j = 0; j < nj; ++j)
+        for (int i = 0; i < ni; ++i) {
+            size_t k = (size_t)j * ni + i;
+            Moments m = rect(ex[i], ex[i + 1], ey[j], ey[j + 1]);
+            if (m.a > epsV) {
+                g.V[k] = m.a;
+                g.X[k] = std::min(std::max(m.mx / m.a, ex[i]), ex[i + 1]);
+                g.Y[k] = std::min(std::max(m.my / m.a, ey[j]), ey[j + 1]);
+            } else {
+                g.V[k] = 0.0;
+                g.X[k] = 0.5 * (ex[i] + ex[i + 1]);
+                g.Y[k] = 0.5 * (ey[j] + ey[j + 1]);
+            }
+        }
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int j = 0; j < nj; ++j)
+        for (int i = 0; i < ni; ++i) {
+            size_t k = (size_t)j * ni + i;
+            g.E[k] = vseg(ex[i + 1], ey[j], ey[j + 1], wall_faces_wet);
+            g.N[k] = hseg(ey[j + 1], ex[i], ex[i + 1], wall_faces_wet);
+            g.Bv[k] = vseg(g.X[k], ey[j], ey[j + 1], false);
+            g.Bh[k] = hseg(g.Y[k], ex[i], ex[i + 1], false);
+            if (i + 1 < ni) g.We[k] = rect(g.X[k], g.X[k + 1], ey[j], ey[j + 1]).a;
+            if (j + 1 < nj) g.Wn[k] = rect(ex[i], ex[i + 1], g.Y[k], g.Y[k + ni]).a;
+        }
+    return g;
+}
+
+}  // namespace
+}  // namespace ccns
+
+using namespace ccns;
+
+extern "C" size_t ccns_caps_count(const ccns_grid *grid) {
+    if (!grid || grid->nx < 1 || grid->ny < 1) return 0;
+    return (size_t)CCNS_NCAPS * (size_t)(grid->nx + 2) * (size_t)(grid->ny + 2);
+}
+
+extern "C" ccns_status ccns_capacities(const ccns_grid *grid, const ccns_body *bodies, int nbody,
+                                       ccns_levelset_fn fn, void *user, double *caps) {
+    if (!grid || !caps || grid->nx < 2 || grid->ny < 2 || !(grid->hx > 0) || !(grid->hy > 0) ||
+        nbody < 0 || (nbody > 0 && !bodies))
+        return CCNS_EINVAL;
+    for (int k = 0; k < nbody; ++k) {
+        const ccns_body &b = bodies[k];
+        if (b.kind < 0 || b.kind > 2) return CCNS_EINVAL;
+        if (b.kind == CCNS_CIRCLE && !(b.a > 0)) return CCNS_EINVAL;
+        if (b.kind == CCNS_ELLIPSE && !(b.a > 0 && b.b > 0)) return CCNS_EINVAL;
+        if (b.kind == CCNS_NACA4 && !(b.chord > 0 && b.t > 0)) return CCNS_EINVAL;
+    }
+    const int nx = grid->nx, ny = grid->ny;
+    const double hx = grid->hx, hy = grid->hy, x0 = grid->x0, y0 = grid->y0;
+    const double x1 = x0 + nx * hx, y1 = y0 + ny * hy;
+    Fluid fl{bodies, nbody, fn, user};
+    Integrator in(fl);
+    std::vector<double> xe(nx + 3), ye(ny + 3), xc(nx + 3), yc(ny + 3);
+    for (int i = 0; i < nx + 3; ++i) { xe[i] = x0 + (i - 1.0) * hx; xc[i] = x0 + (i - 0.5) * hx; }
+    for (int j = 0; j < ny + 3; ++j) { ye[j] = y0 + (j - 1.0) * hy; yc[j] = y0 + (j - 0.5) * hy; }
+    const double epsV = 1e-12 * hx * hy, margin = 2.0 * std::max(hx, hy);
+    GridOut p = grid_caps(fl, in, xe, ye, x0, x1, y0, y1, true, epsV, margin);
+    GridOut u = grid_caps(fl, in, xc, ye, x0 - 0.5 * hx, x1 + 0.5 * hx, y0, y1, false, epsV, margin);
+    GridOut v = grid_caps(fl, in, xe, yc, x0, x1, y0 - 0.5 * hy, y1 + 0.5 * hy, false, epsV, margin);
+    const size_t W = nx + 2, H = ny + 2, n = W * H;
+    std::memset(caps, 0, sizeof(double) * n * CCNS_NCAPS);
+    auto at = [&](int cap) { return caps + (size_t)cap * n; };
+    for (size_t j = 0; j < H; ++j)
+        for (size_t i = 0; i < W; ++i) {
+            size_t k = j * W + i;
+            size_t kw = (i > 0) ? k - 1 : SIZE_MAX;   // west neighbour in the CV grid
+            size_t ks = (j > 0) ? k - W : SIZE_MAX;   // south neighbour
+            at(CCNS_CAP_V)[k] = p.V[k];
+            at(CCNS_CAP_AX)[k] = p.E[k];
+            at(CCNS_CAP_AY)[k] = p.N[k];
+            at(CCNS_CAP_BX)[k] = p.Bv[k];
+            at(CCNS_CAP_BY)[k] = p.Bh[k];
+            at(CCNS_CAP_WX)[k] = p.We[k];
+            at(CCNS_CAP_WY)[k] = p.Wn[k];
+            at(CCNS_CAP_VU)[k] = u.V[k];
+            at(CCNS_CAP_AXX)[k] = (kw != SIZE_MAX) ? u.E[kw] : 0.0;
+            at(CCNS_CAP_AXY)[k] = u.N[k];
+            at(CCNS_CAP_BXX)[k] = u.Bv[k];
+            at(CCNS_CAP_BXY)[k] = u.Bh[k];
+            at(CCNS_CAP_WXX)[k] = (kw != SIZE_MAX) ? u.We[kw] : 0.0;
+            at(CCNS_CAP_WXY)[k] = u.Wn[k];
+            at(CCNS_CAP_VV)[k] = v.V[k];
+            at(CCNS_CAP_AYY)[k] = (ks != SIZE_MAX) ? v.N[ks] : 0.0;
+            at(CCNS_CAP_AYX)[k] = v.E[k];
+            at(CCNS_CAP_BYY)[k] = v.Bh[k];
+            at(CCNS_CAP_BYX)[k] = v.Bv[k];
+            at(CCNS_CAP_WYY)[k] = (ks != SIZE_MAX) ? v.Wn[ks] : 0.0;
+            at(CCNS_CAP_WYX)[k] = v.We[k];
+        }
+    // capacities below the thresholds are zero
+    const double epsX = 1e-12 * hy, epsY = 1e-12 * hx;
+    const int vol[] = {CCNS_CAP_V, CCNS_CAP_WX, CCNS_CAP_WY, CCNS_CAP_VU, CCNS_CAP_WXX, CCNS_CAP_WXY,
+                       CCNS_CAP_VV, CCNS_CAP_WYY, CCNS_CAP_WYX};
+    const int lx[] = {CCNS_CAP_AX, CCNS_CAP_BX, CCNS_CAP_AXX, CCNS_CAP_BXX, CCNS_CAP_AYX, CCNS_CAP_BYX};
+    const int ly[] = {CCNS_CAP_AY, CCNS_CAP_BY, CCNS_CAP_AYY, CCNS_CAP_BYY, CCNS_CAP_AXY, CCNS_CAP_BXY};
+    for (int c : vol) for (size_t k = 0; k < n; ++k) if (!(at(c)[k] > epsV)) at(c)[k] = 0.0;
+    for (int c : lx) for (size_t k = 0; k < n; ++k) if (!(at(c)[k] > epsX)) at(c)[k] = 0.0;
+    for (int c : ly) for (size_t k = 0; k < n; ++k) if (!(at(c)[k] > epsY)) at(c)[k] = 0.0;
+    return CCNS_OK;
+}

@@ -1,0 +1,56 @@
+// Internal declarations of libccns (not part of the C interface).
+#ifndef CCNS_INTERNAL_H
+#define CCNS_INTERNAL_H
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "ccns.h"
+
+namespace ccns {
+
+// Device layout of every field: `rows` = ny+2 rows of `pitch` elements
+// (pitch a multiple of 64), element (j, i) at j*pitch + i, with the same
+// index meaning as the dense host layout.
+struct Layout {
+    int nx = 0, ny = 0, rows = 0, pitch = 0;
+    size_t n = 0;  // rows * pitch
+};
+
+Layout make_layout(int nx, int ny);
+
+// Coefficient fields derived from the capacities on the host, in the dense
+// (ny+2) x (nx+2) layout.  Every name is a field of the device workspace.
+struct HostCoef {
+    std::vector<double> cx, cy, dinv;         // Poisson face weights and inverse diagonal
+    std::vector<double> gx, gy;               // corrector factors A/V on coupled faces
+    std::vector<double> ax, ay;               // A^x, A^y (mass fluxes, divergence)
+    std::vector<double> het;                  // cont(0, D) at cells
+    std::vector<double> hbx, hby;             // (het_L + het_R)/4 at faces (convective bracket)
+    std::vector<double> dx, dy;               // Dirichlet data
+    std::vector<double> vu, vv;               // V^x, V^y on velocity unknowns, 0 elsewhere
+    std::vector<double> bxx, bxy, byy, byx;   // viscous face weights
+    std::vector<double> wxx, wyy;             // 1/W^xx, 1/W^yy (cells)
+    std::vector<double> nxx, nxy, nyx, nyy;   // node strain weights
+    std::vector<double> hdx, hdy;             // inverse Jacobi diagonal of H (faces)
+    std::vector<double> vinv;                 // 1/V on pressure unknowns
+    std::vector<double> utx, uty;             // D on non-unknown faces, 0 on unknowns
+    std::vector<double> vur, vvr;             // V^x, V^y on every face (kinetic energy)
+    std::vector<double> vdx, vdy;             // visc(strain(U~, D)) on unknown faces
+    int n_active = 0;                         // pressure unknowns
+    int n_uact = 0, n_vact = 0;               // velocity unknowns
+};
+
+// Validates the inputs and derives every coefficient field (host, FP64).
+ccns_status prepare_coefficients(const ccns_grid &g, const ccns_params &prm, const double *caps,
+                                 const double *dir, HostCoef &out, std::string &err);
+
+// visc(strain(U, D)) with the Dirichlet terms, on the host (interior faces).
+void host_viscous(const ccns_grid &g, const double *caps, const HostCoef &o, const double *Ux,
+                  const double *Uy, std::vector<double> &vx, std::vector<double> &vy);
+
+}  // namespace ccns
+
+#endif

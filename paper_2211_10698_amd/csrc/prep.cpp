@@ -1,0 +1,241 @@
+// Host preparation of the coefficient fields of one context (setup, once per
+// geometry).  Readings of the paper used here:
+//  - velocity unknowns: faces interior to the box whose staggered control
+//    volume holds fluid; every other face keeps its Dirichlet value (Sec. 4)
+//  - Poisson operator cont(M^-1 pres(Phi), 0) (eq:pm_poisson with the mass
+//    matrix of Sec. 4.5 explicit): face weight c = A^2/V_f
+//  - pressure unknowns: fluid cells of the largest set connected through
+//    faces with c > 0 (Phi is known up to a constant on it, end of Sec. 4.6)
+//  - node strain weights (eq:offdiag): the printed form uses two node volumes
+//    W^xy and W^yx; the symmetric default keeps 1/W^xy for the x rows,
+//    1/W^yx for the y rows and 1/sqrt(W^xy W^yx) for the cross coupling.
+#include <algorithm>
+#include <cmath>
+#include <queue>
+
+#include "ccns_internal.h"
+
+namespace ccns {
+
+Layout make_layout(int nx, int ny) {
+    Layout L;
+    L.nx = nx;
+    L.ny = ny;
+    L.rows = ny + 2;
+    L.pitch = ((nx + 2 + 63) / 64) * 64;
+    L.n = (size_t)L.rows * L.pitch;
+    return L;
+}
+
+static inline double inv0(double a) { return a != 0.0 ? 1.0 / a : 0.0; }
+
+ccns_status prepare_coefficients(const ccns_grid &g, const ccns_params &prm, const double *caps,
+                                 const double *dir, HostCoef &o, std::string &err) {
+    const int nx = g.nx, ny = g.ny, W = nx + 2, H = ny + 2;
+    const size_t n = (size_t)W * H;
+    if (nx < 2 || ny < 2 || !(g.hx > 0) || !(g.hy > 0)) { err = "bad grid"; return CCNS_EINVAL; }
+    if (!(prm.rho > 0) || !(prm.mu >= 0) || !(prm.tau > 0)) { err = "rho, tau must be > 0 and mu >= 0"; return CCNS_EINVAL; }
+    if (prm.visc_form < 0 || prm.visc_form > 2 || prm.poisson_weight < 0 || prm.poisson_weight > 1) {
+        err = "bad visc_form or poisson_weight"; return CCNS_EINVAL;
+    }
+    for (size_t k = 0; k < n * CCNS_NCAPS; ++k)
+        if (!(caps[k] >= 0.0) || !std::isfinite(caps[k])) { err = "capacity negative or not finite"; return CCNS_EINVAL; }
+    for (size_t k = 0; k < 2 * n; ++k)
+        if (!std::isfinite(dir[k])) { err = "Dirichlet data not finite"; return CCNS_EINVAL; }
+    auto C = [&](int c) { return caps + (size_t)c * n; };
+    const double *V = C(CCNS_CAP_V), *Ax = C(CCNS_CAP_AX), *Ay = C(CCNS_CAP_AY);
+    const double *Bx = C(CCNS_CAP_BX), *By = C(CCNS_CAP_BY);
+    const double *Vu = C(CCNS_CAP_VU), *Vv = C(CCNS_CAP_VV);
+    const double *Axx = C(CCNS_CAP_AXX), *Axy = C(CCNS_CAP_AXY), *Bxx = C(CCNS_CAP_BXX), *Bxy = C(CCNS_CAP_BXY);
+    const double *Wxx = C(CCNS_CAP_WXX), *Wxy = C(CCNS_CAP_WXY);
+    const double *Ayy = C(CCNS_CAP_AYY), *Ayx = C(CCNS_CAP_AYX), *Byy = C(CCNS_CAP_BYY), *Byx = C(CCNS_CAP_BYX);
+    const double *Wyy = C(CCNS_CAP_WYY), *Wyx = C(CCNS_CAP_WYX);
+    const double *Dx = dir, *Dy = dir + n;
+    auto id = [&](int j, int i) { return (size_t)j * W + i; };
+
+    for (auto *v : {&o.cx, &o.cy, &o.dinv, &o.gx, &o.gy, &o.ax, &o.ay, &o.het, &o.hbx, &o.hby, &o.dx, &o.dy,
+                    &o.vu, &o.vv, &o.bxx, &o.bxy, &o.byy, &o.byx, &o.wxx, &o.wyy, &o.nxx, &o.nxy, &o.nyx,
+                    &o.nyy, &o.hdx, &o.hdy, &o.vinv, &o.utx, &o.uty, &o.vur, &o.vvr})
+        v->assign(n, 0.0);
+
+    std::vector<char> au(n, 0), av(n, 0), fluid(n, 0), act(n, 0);
+    for (int j = 0; j < H; ++j)
+        for (int i = 0; i < W; ++i) {
+            size_t k = id(j, i);
+            au[k] = (i >= 1 && i <= nx - 1 && j >= 1 && j <= ny && Vu[k] > 0.0);
+            av[k] = (i >= 1 && i <= nx && j >= 1 && j <= ny - 1 && Vv[k] > 0.0);
+            fluid[k] = (i >= 1 && i <= nx && j >= 1 && j <= ny && V[k] > 0.0);
+        }
+    const bool volw = prm.poisson_weight == 0;
+    for (size_t k = 0; k < n; ++k) {
+        double wu = volw ? inv0(Vu[k]) : 1.0, wv = volw ? inv0(Vv[k]) : 1.0;
+        o.cx[k] = au[k] ? Ax[k] * Ax[k] * wu : 0.0;
+        o.cy[k] = av[k] ? Ay[k] * Ay[k] * wv : 0.0;
+    }
+    // largest set of fluid cells connected through faces with c > 0
+    std::vector<int> lab(n, -1);
+    int best = -1, bestsz = 0, nl = 0;
+    for (int j = 1; j <= ny; ++j)
+        for (int i = 1; i <= nx; ++i) {
+            size_t s = id(j, i);
+            if (!fluid[s] || lab[s] >= 0) continue;
+            int sz = 0;
+            std::queue<size_t> q;
+            q.push(s);
+            lab[s] = nl;
+            while (!q.empty()) {
+                size_t k = q.front();
+                q.pop();
+                ++sz;
+                size_t nb[4] = {k + 1, k - 1, k + W, k - W};
+                double cc[4] = {o.cx[k], o.cx[k - 1], o.cy[k], o.cy[k - W]};
+                for (int e = 0; e < 4; ++e)
+                    if (cc[e] > 0.0 && fluid[nb[e]] && lab[nb[e]] < 0) {
+                        lab[nb[e]] = nl;
+                        q.push(nb[e]);
+                    }
+            }
+            if (sz > bestsz) { bestsz = sz; best = nl; }
+            ++nl;
+        }
+    o.n_active = 0;
+    for (size_t k = 0; k < n; ++k) {
+        act[k] = (lab[k] == best && best >= 0);
+        o.n_active += act[k];
+    }
+    for (size_t k = 0; k < n; ++k) {
+        bool ex = (k + 1 < n) && act[k] && act[k + 1];
+        bool ey = (k + W < n) && act[k] && act[k + W];
+        if (!ex) o.cx[k] = 0.0;
+        if (!ey) o.cy[k] = 0.0;
+        double wu = volw ? inv0(Vu[k]) : 1.0, wv = volw ? inv0(Vv[k]) : 1.0;
+        o.gx[k] = o.cx[k] > 0.0 ? Ax[k] * wu : 0.0;
+        o.gy[k] = o.cy[k] > 0.0 ? Ay[k] * wv : 0.0;
+    }
+    for (int j = 1; j <= ny; ++j)
+        for (int i = 1; i <= nx; ++i) {
+            size_t k = id(j, i);
+            if (!act[k]) continue;
+            double d = o.cx[k] + o.cx[k - 1] + o.cy[k] + o.cy[k - W];
+            o.dinv[k] = inv0(d);
+            o.vinv[k] = inv0(V[k]);
+        }
+    // divergence and convection data
+    o.n_uact = o.n_vact = 0;
+    for (size_t k = 0; k < n; ++k) {
+        o.ax[k] = Ax[k];
+        o.ay[k] = Ay[k];
+        o.dx[k] = Dx[k];
+        o.dy[k] = Dy[k];
+        o.vu[k] = au[k] ? Vu[k] : 0.0;
+        o.vv[k] = av[k] ? Vv[k] : 0.0;
+        o.vur[k] = Vu[k];
+        o.vvr[k] = Vv[k];
+        o.utx[k] = au[k] ? 0.0 : Dx[k];
+        o.uty[k] = av[k] ? 0.0 : Dy[k];
+        o.n_uact += au[k];
+        o.n_vact += av[k];
+    }
+    for (int j = 1; j <= ny; ++j)
+        for (int i = 1; i <= nx; ++i) {
+            size_t k = id(j, i);
+            o.het[k] = -Ax[k] * Dx[k] + Ax[k - 1] * Dx[k - 1] + Bx[k] * (Dx[k] - Dx[k - 1]) - Ay[k] * Dy[k] +
+                       Ay[k - W] * Dy[k - W] + By[k] * (Dy[k] - Dy[k - W]);
+        }
+    for (int j = 0; j < H; ++j)
+        for (int i = 0; i < W; ++i) {
+            size_t k = id(j, i);
+            if (i + 1 < W) o.hbx[k] = 0.25 * (o.het[k] + o.het[k + 1]);
+            if (j + 1 < H) o.hby[k] = 0.25 * (o.het[k] + o.het[k + W]);
+        }
+    // viscous weights
+    for (size_t k = 0; k < n; ++k) {
+        o.bxx[k] = Bxx[k];
+        o.bxy[k] = Bxy[k];
+        o.byy[k] = Byy[k];
+        o.byx[k] = Byx[k];
+        o.wxx[k] = inv0(Wxx[k]);
+        o.wyy[k] = inv0(Wyy[k]);
+        double ixy = inv0(Wxy[k]), iyx = inv0(Wyx[k]);
+        switch (prm.visc_form) {
+        case 0: {
+            double gm = inv0(std::sqrt(Wxy[k] * Wyx[k]));
+            o.nxx[k] = ixy; o.nxy[k] = gm; o.nyx[k] = gm; o.nyy[k] = iyx;
+            break;
+        }
+        case 1:
+            o.nxx[k] = ixy; o.nxy[k] = iyx; o.nyx[k] = ixy; o.nyy[k] = iyx;
+            break;
+        default: {
+            double m = inv0(0.5 * (Wxy[k] + Wyx[k]));
+            o.nxx[k] = o.nxy[k] = o.nyx[k] = o.nyy[k] = m;
+        }
+        }
+    }
+    // Jacobi diagonal of H = (rho/tau) V - mu visc(strain(., 0))
+    const double rt = prm.rho / prm.tau;
+    for (int j = 1; j < H - 1; ++j)
+        for (int i = 1; i < W - 1; ++i) {
+            size_t k = id(j, i);
+            if (au[k]) {
+                double kd = Bxx[k] * Bxx[k] * (o.wxx[k] + o.wxx[k + 1]) +
+                            0.5 * Bxy[k] * Bxy[k] * (o.nxx[k] + o.nxx[k - W]);
+                o.hdx[k] = inv0(rt * Vu[k] + prm.mu * kd);
+            }
+            if (av[k]) {
+                double kd = Byy[k] * Byy[k] * (o.wyy[k] + o.wyy[k + W]) +
+                            0.5 * Byx[k] * Byx[k] * (o.nyy[k] + o.nyy[k - 1]);
+                o.hdy[k] = inv0(rt * Vv[k] + prm.mu * kd);
+            }
+        }
+    (void)Axx; (void)Axy; (void)Ayy; (void)Ayx;
+    // constant Dirichlet contribution of the viscous term on the unknowns
+    host_viscous(g, caps, o, o.utx.data(), o.uty.data(), o.vdx, o.vdy);
+    for (size_t k = 0; k < n; ++k) {
+        if (!au[k]) o.vdx[k] = 0.0;
+        if (!av[k]) o.vdy[k] = 0.0;
+    }
+    return CCNS_OK;
+}
+
+// visc(strain(U, D)) with full Dirichlet terms (eq:diag, eq:offdiag, Sec. 4.3)
+// on the host, for the constant boundary contribution of the viscous term.
+void host_viscous(const ccns_grid &g, const double *caps, const HostCoef &o, const double *Ux,
+                  const double *Uy, std::vector<double> &vx, std::vector<double> &vy) {
+    const int nx = g.nx, ny = g.ny, W = nx + 2, H = ny + 2;
+    const size_t n = (size_t)W * H;
+    auto C = [&](int c) { return caps + (size_t)c * n; };
+    const double *Axx = C(CCNS_CAP_AXX), *Axy = C(CCNS_CAP_AXY), *Ayy = C(CCNS_CAP_AYY), *Ayx = C(CCNS_CAP_AYX);
+    const double *Dx = o.dx.data(), *Dy = o.dy.data();
+    std::vector<double> sxx(n, 0.0), syy(n, 0.0), sx(n, 0.0), sy(n, 0.0);
+    for (int j = 1; j <= ny; ++j)
+        for (int i = 1; i <= nx; ++i) {
+            size_t k = (size_t)j * W + i;
+            sxx[k] = o.wxx[k] * (o.bxx[k] * (Ux[k] - Dx[k]) - o.bxx[k - 1] * (Ux[k - 1] - Dx[k - 1]) +
+                                 Axx[k] * (Dx[k] - Dx[k - 1]));
+            syy[k] = o.wyy[k] * (o.byy[k] * (Uy[k] - Dy[k]) - o.byy[k - W] * (Uy[k - W] - Dy[k - W]) +
+                                 Ayy[k] * (Dy[k] - Dy[k - W]));
+        }
+    for (int j = 0; j <= ny; ++j)
+        for (int i = 0; i <= nx; ++i) {
+            size_t k = (size_t)j * W + i;
+            double gx = o.bxy[k + W] * (Ux[k + W] - Dx[k + W]) - o.bxy[k] * (Ux[k] - Dx[k]) +
+                        Axy[k] * (Dx[k + W] - Dx[k]);
+            double gy = o.byx[k + 1] * (Uy[k + 1] - Dy[k + 1]) - o.byx[k] * (Uy[k] - Dy[k]) +
+                        Ayx[k] * (Dy[k + 1] - Dy[k]);
+            sx[k] = 0.5 * (o.nxx[k] * gx + o.nxy[k] * gy);
+            sy[k] = 0.5 * (o.nyx[k] * gx + o.nyy[k] * gy);
+        }
+    vx.assign(n, 0.0);
+    vy.assign(n, 0.0);
+    for (int j = 1; j <= ny; ++j)
+        for (int i = 1; i <= nx; ++i) {
+            size_t k = (size_t)j * W + i;
+            if (i <= nx - 1)
+                vx[k] = o.bxx[k] * (sxx[k + 1] - sxx[k]) + o.bxy[k] * (sx[k] - sx[k - W]);
+            if (j <= ny - 1)
+                vy[k] = o.byy[k] * (syy[k + W] - syy[k]) + o.byx[k] * (sy[k] - sy[k - 1]);
+        }
+}
+
+}  // namespace ccns

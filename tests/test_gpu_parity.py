@@ -1,0 +1,174 @@
+"""Parity of the HIP path (through the C interface) with the oracle, on the
+same capacities and seeded inputs: operator applies element by element,
+the pressure solve, the phases of one step, and multi-step trajectories."""
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import derived, operators as ops, pmii
+from tests.gpu_common import case_setup, rel
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def _host(t):
+    return t.cpu().numpy()
+
+
+CASES = {
+    "cylinder_64": lambda: W.cylinder_64(),
+    # several tiles and a ragged tail in both directions (pitch 192, rows 75)
+    "channel_130x73": lambda: W.scaled_cylinder(130, 73, 2.6, 1.46, seed=5),
+}
+
+
+@pytest.fixture(scope="module", params=list(CASES))
+def setup(request):
+    case = CASES[request.param]()
+    return case, case_setup(case)
+
+
+def _fields(case, pr, Dx, Dy, seed):
+    sh = (case.grid.ny + 2, case.grid.nx + 2)
+    rng = np.random.default_rng(seed)
+    Ux = np.where(pr.act_u, rng.uniform(-1, 1, sh), Dx)
+    Uy = np.where(pr.act_v, rng.uniform(-1, 1, sh), Dy)
+    return Ux, Uy
+
+
+def test_operator_applies(setup):
+    from paper_2211_10698_amd import ccns
+    case, (caps, pr, st, ctx, Dx, Dy) = setup
+    Ux, Uy = _fields(case, pr, Dx, Dy, 1)
+    # cont (eq:divergence) on real cells
+    (c,) = ctx.apply(ccns.OP_CONT, [_dev(Ux), _dev(Uy)])
+    ref = ops.cont(caps, Ux, Uy, Dx, Dy)
+    assert rel(_host(c), ref) < 1e-13
+    # pres (eq:compatibility) on real faces
+    P = np.where(pr.act_p, np.random.default_rng(2).uniform(-1, 1, Ux.shape), 0.0)
+    gx, gy = ctx.apply(ccns.OP_PRES, [_dev(P)])
+    rx, ry = ops.pres(caps, P)
+    assert rel(_host(gx), rx) < 1e-14 and rel(_host(gy), ry) < 1e-14
+    # visc(strain(U, D)) on unknown faces (U = D elsewhere)
+    vx, vy = ctx.apply(ccns.OP_VISC, [_dev(Ux), _dev(Uy)])
+    wx, wy = ops.viscous(caps, Ux, Uy, Dx, Dy, "geometric")
+    assert rel(_host(vx), wx, pr.act_u) < 1e-12 and rel(_host(vy), wy, pr.act_v) < 1e-12
+    # conv (eq:convective) on interior faces
+    cx, cy = ctx.apply(ccns.OP_CONV, [_dev(Ux), _dev(Uy)])
+    kx, ky = ops.conv(caps, Ux, Uy, Ux, Uy, Dx, Dy, Dx, Dy)
+    assert rel(_host(cx), kx) < 1e-13 and rel(_host(cy), ky) < 1e-13
+    # Poisson operator L
+    (q,) = ctx.apply(ccns.OP_LAP, [_dev(P)])
+    assert rel(_host(q), derived.laplacian(pr, P)) < 1e-13
+    # predictor matrix H
+    hx, hy = ctx.apply(ccns.OP_H, [_dev(np.where(pr.act_u, Ux, 0)), _dev(np.where(pr.act_v, Uy, 0))])
+    H = st.apply_H(np.stack([np.where(pr.act_u, Ux, 0), np.where(pr.act_v, Uy, 0)]))
+    assert rel(_host(hx), H[0]) < 1e-12 and rel(_host(hy), H[1]) < 1e-12
+    # kinetic energy density
+    (k,) = ctx.apply(ccns.OP_KINETIC, [_dev(Ux), _dev(Uy)])
+    assert rel(_host(k), ops.kinetic(caps, Ux, Uy)) < 1e-14
+
+
+def test_pressure_solve(setup):
+    case, (caps, pr, st, ctx, Dx, Dy) = setup
+    rng = np.random.default_rng(3)
+    b = np.where(pr.act_p, rng.uniform(-1, 1, pr.act_p.shape), 0.0)
+    phi_d, info, status = ctx.pressure_solve(_dev(b))
+    assert status == 0
+    oinfo = pmii.StepInfo()
+    phi_o = st.solve_poisson(b - np.where(pr.act_p, b[pr.act_p].mean(), 0.0), np.zeros_like(b), oinfo)
+    # same algorithm: iteration counts agree closely
+    assert abs(info.iterations - oinfo.cg_iters) <= 2
+    # both meet the tolerance: compare with the oracle's direct solution
+    phi_x = st.solve_poisson(b - np.where(pr.act_p, b[pr.act_p].mean(), 0.0), np.zeros_like(b),
+                             pmii.StepInfo(), solver="direct") if pr.n_active < 6000 else phi_o
+    pd = _host(phi_d)
+    pd = np.where(pr.act_p, pd - pd[pr.act_p].mean(), 0.0)
+    assert rel(pd, phi_x, pr.act_p) < 1e-6
+    # the device solution satisfies the oracle's residual test
+    bm = b - np.where(pr.act_p, b[pr.act_p].mean(), 0.0)
+    res = bm - derived.laplacian(pr, pd)
+    assert np.linalg.norm(res[pr.act_p]) <= 1.01 * case.pcg_tol * np.linalg.norm(bm[pr.act_p])
+
+
+def test_step_phases_match(setup):
+    """One projection step phase by phase from the same state."""
+    from paper_2211_10698_amd import ccns
+    case, (caps, pr, st, ctx, Dx, Dy) = setup
+    s0 = pmii.initial_state(pr, Dx, Dy, case.u_inf, W.perturbation(case))
+    st.project(s0)
+    ctx.set_field(ccns.F_UX, s0.Ux)
+    ctx.set_field(ccns.F_UY, s0.Uy)
+    ctx.set_field(ccns.F_P, s0.P)
+    ctx.set_field(ccns.F_PHI, s0.Phi)
+    # predictor
+    info_p = ctx.predict()
+    (usx, usy), conv_n = st.predict(s0, pmii.StepInfo())
+    assert rel(_host(ctx.get_field(ccns.F_USX)), usx) < 1e-10
+    assert rel(_host(ctx.get_field(ccns.F_USY)), usy) < 1e-10
+    assert rel(_host(ctx.get_field(ccns.F_CONVX)), conv_n[0], pr.act_u) < 1e-13
+    # correction from the oracle's U* on both sides
+    ctx.set_field(ccns.F_USX, usx)
+    ctx.set_field(ccns.F_USY, usy)
+    info = ctx.correct()
+    b = st.poisson_rhs(usx, usy)
+    assert rel(_host(ctx.get_field(ccns.F_B)), b, pr.act_p) < 1e-12
+    oinfo = pmii.StepInfo()
+    phi = st.solve_poisson(b, s0.Phi, oinfo)
+    assert abs(info.poisson.iterations - oinfo.cg_iters) <= 2
+    ux, uy = st.correct(usx, usy, phi)
+    assert rel(_host(ctx.get_field(ccns.F_UX)), ux) < 1e-8
+    P = st.pressure_update(s0.P, phi)
+    pd = _host(ctx.get_field(ccns.F_P))
+    assert rel(pd - pd[pr.act_p].mean() * pr.act_p, P - P[pr.act_p].mean() * pr.act_p, pr.act_p) < 1e-6
+    od = st.diagnostics(ux, uy, pmii.StepInfo())
+    assert info.div_rel < 1e-8 and od.div_rel < 1e-8
+    assert abs(info.ke - od.ke) < 1e-10 * od.ke
+
+
+def test_trajectory_tight_tolerance():
+    """Ten steps on the 64x64 cylinder with tight solver tolerances: the
+    trajectories agree to 1e-11 relative (both solves converge far below
+    the differences that rounding order can cause)."""
+    from paper_2211_10698_amd import ccns
+    case = W.cylinder_64()
+    caps, pr, st, ctx, Dx, Dy = case_setup(case, pcg_tol=1e-13, pred_tol=1e-14)
+    s0 = pmii.initial_state(pr, Dx, Dy, case.u_inf, W.perturbation(case))
+    ctx.set_field(ccns.F_UX, s0.Ux)
+    ctx.set_field(ccns.F_UY, s0.Uy)
+    st.project(s0)
+    ctx.project()
+    assert rel(_host(ctx.get_field(ccns.F_UX)), s0.Ux) < 1e-11
+    for n in range(case.steps):
+        oi = st.step(s0)
+        di = ctx.step(1)
+        assert abs(di.poisson.iterations - oi.cg_iters) <= 3, n
+        assert abs(di.pred.iterations - oi.pred_iters) <= 2, n
+        assert di.div_rel < 1e-8
+    assert rel(_host(ctx.get_field(ccns.F_UX)), s0.Ux) < 1e-11
+    assert rel(_host(ctx.get_field(ccns.F_UY)), s0.Uy) < 1e-11
+    pd = _host(ctx.get_field(ccns.F_P))
+    po = s0.P
+    assert rel(pd - pd[pr.act_p].mean() * pr.act_p, po - po[pr.act_p].mean() * pr.act_p, pr.act_p) < 1e-9
+
+
+def test_breakdown_and_maxit_are_reported():
+    from paper_2211_10698_amd import ccns
+    case = W.cylinder_64()
+    g = case.grid
+    from oracle import geometry
+    caps = geometry.capacities(g, case.bodies)
+    Dx, Dy = W.dirichlet(case)
+    cp = ccns.make_params(1.0, case.mu, case.tau, pcg_maxit=3)
+    ctx = ccns.Context(g, cp, np.stack([caps[k] for k in ccns.CAP_NAMES]), Dx, Dy)
+    b = np.random.default_rng(0).uniform(-1, 1, (g.ny + 2, g.nx + 2))
+    phi, info, status = ctx.pressure_solve(_dev(b), check=False)
+    assert status == ccns.ENOTCONV and info.iterations == 3
+    assert np.all(np.isfinite(_host(phi)))
