@@ -8,12 +8,14 @@
 //  - a work-group is 256 threads (4 wavefronts) and owns a 64 x TY tile;
 //    tiles are numbered so that each of the 8 XCDs works on a contiguous
 //    band of rows (the L2 of that XCD then serves the halo rows);
-//  - stencil neighbours are read straight from global memory (L1/L2 hits);
-//  - reductions: wavefront shuffles, one block-level pass, per-block
-//    partials, and the last block to finish (atomic counter) reduces the
-//    partials in a fixed order and updates the solver scalars on the device.
-//    Results are therefore deterministic and the host never computes alpha
-//    or beta: it only reads a done flag every few iterations.
+//  - stencil halos are staged in LDS where a value is reused by several
+//    neighbours; all global loads of a thread are issued before the
+//    arithmetic that depends on the activity masks;
+//  - reductions never use atomics or fences: each work-group writes its
+//    partial sums, and the next kernel (or a one-group kernel) reduces them
+//    in a fixed order, so results are reproducible bit for bit.  Solver
+//    scalars (alpha, beta, convergence) are formed on the device; the host
+//    only reads a done flag every few iterations.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -26,238 +28,118 @@
 
 #include "ccns.h"
 #include "ccns_internal.h"
+#include "ccns_kern.h"
 
 namespace ccns {
 
-constexpr int NT = 256;  // threads per work-group
-constexpr int TX = 64;   // tile width (one wavefront)
-constexpr int TR = 2;    // rows per thread
-constexpr int TY = 4 * TR;
-constexpr int NRED = 8;  // reduction slots per block
+// ---------------------------------------------------------------------------
+// solver state on the device
+// ---------------------------------------------------------------------------
 
-struct Dims {
-    int nx, ny, rows, pitch;
-    int gx, gy, ntile, ncomp;  // tiles per component; components (1 cells, 2 faces)
-    int nlaunch;               // launched blocks (multiple of 8)
-    size_t n;                  // elements per component array
-};
-
-struct CgState {
-    double alpha, beta, rz, mean, fnorm2, rnorm2, tol2, pq, mean_b;
-    int it, maxit, done, status, zero_mean, n_active;
-    unsigned counter;
+// Conjugate-gradient bookkeeping.  Scalars that change every iteration live
+// in two slots used alternately, so that the work-group that records
+// iteration i never overwrites what the other groups of the same kernel are
+// still reading (iteration i-1).
+struct CgSlot {
+    double rz;
+    int it;
     int pad;
+};
+struct CgState {
+    double tol2, fnorm2, rnorm2_final;
+    int maxit, zero_mean, n_active;
+    int done, status, it_final;
+    CgSlot slot[2];
 };
 
 struct DiagState {
     double mass, ke, momx, momy, divmax;
-    unsigned counter;
-    int pad;
 };
-
-// ---------------------------------------------------------------------------
-// tile mapping and reductions
-// ---------------------------------------------------------------------------
-
-// Physical block b runs on XCD b % 8; give each XCD a contiguous range of
-// logical tiles so that vertically adjacent tiles share an L2.
-__device__ inline int logical_block(int nlaunch) {
-    const int b = blockIdx.x;
-    const int per = nlaunch >> 3;
-    return (b & 7) * per + (b >> 3);
-}
-
-__device__ inline double wave_sum(double v) {
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
-    return v;
-}
-__device__ inline double wave_max(double v) {
-    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_down(v, o, 64));
-    return v;
-}
-
-// Block-level sums (NS slots) and maxima (NM slots); result valid in sh[] for
-// every thread after the call.
-template <int NS, int NM>
-__device__ inline void block_reduce(double (&v)[NS + NM], double *sh) {
-    __shared__ double part[NRED][4];
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-#pragma unroll
-    for (int k = 0; k < NS + NM; ++k) {
-        double s = (k < NS) ? wave_sum(v[k]) : wave_max(v[k]);
-        if (lane == 0) part[k][w] = s;
-    }
-    __syncthreads();
-    if (threadIdx.x < NS + NM) {
-        const int k = threadIdx.x;
-        sh[k] = (k < NS) ? ((part[k][0] + part[k][1]) + (part[k][2] + part[k][3]))
-                         : fmax(fmax(part[k][0], part[k][1]), fmax(part[k][2], part[k][3]));
-    }
-    __syncthreads();
-}
-
-// Writes this block's partials; returns true in every thread of the last
-// block to arrive, with the grid totals (fixed reduction order) in tot[].
-template <int NS, int NM>
-__device__ inline bool grid_reduce(double (&v)[NS + NM], double *partials, unsigned *counter, int nlaunch,
-                                   double (&tot)[NS + NM]) {
-    __shared__ double sh[NRED];
-    __shared__ int amlast;
-    block_reduce<NS, NM>(v, sh);
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int k = 0; k < NS + NM; ++k) partials[(size_t)blockIdx.x * NRED + k] = sh[k];
-        __threadfence();
-        unsigned t = atomicAdd(counter, 1u);
-        amlast = (t == (unsigned)nlaunch - 1u);
-    }
-    __syncthreads();
-    if (!amlast) return false;
-    __threadfence();
-    double acc[NS + NM];
-#pragma unroll
-    for (int k = 0; k < NS + NM; ++k) acc[k] = (k < NS) ? 0.0 : -INFINITY;
-    const volatile double *vp = partials;
-    for (int b = threadIdx.x; b < nlaunch; b += NT) {
-#pragma unroll
-        for (int k = 0; k < NS + NM; ++k) {
-            double x = vp[(size_t)b * NRED + k];
-            acc[k] = (k < NS) ? acc[k] + x : fmax(acc[k], x);
-        }
-    }
-    block_reduce<NS, NM>(acc, sh);
-#pragma unroll
-    for (int k = 0; k < NS + NM; ++k) tot[k] = sh[k];
-    if (threadIdx.x == 0) *counter = 0u;
-    return true;
-}
-
-// Iterates over the cells (or faces) of this block's tile: f(comp, j, i, k).
-template <class F>
-__device__ inline void for_tile(const Dims &d, F f) {
-    const int L = logical_block(d.nlaunch);
-    if (L >= d.ntile * d.ncomp) return;
-    const int comp = L / d.ntile, t = L % d.ntile;
-    const int c0 = (t % d.gx) * TX, r0 = (t / d.gx) * TY;
-    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-    const int i = c0 + tx;
-#pragma unroll
-    for (int rr = 0; rr < TR; ++rr) {
-        const int j = r0 + ty + 4 * rr;
-        if (j < d.rows) f(comp, j, i, (size_t)j * d.pitch + i);
-    }
-}
-
-// ---------------------------------------------------------------------------
-// operator building blocks (index form of Sec. 4; k = j*pitch + i)
-// ---------------------------------------------------------------------------
-
-struct ViscCoef {
-    const double *bxx, *bxy, *byy, *byx, *wxx, *wyy, *nxx, *nxy, *nyx, *nyy;
-};
-
-// visc(strain(p, 0)) at x-face k (eq:diag, eq:offdiag, Sec. 4.3) for a
-// face vector given by loaders px(k), py(k).
-template <class PX, class PY>
-__device__ inline double visc_x(const ViscCoef &c, size_t k, size_t P, PX px, PY py) {
-    const double sxx_e = c.wxx[k + 1] * (c.bxx[k + 1] * px(k + 1) - c.bxx[k] * px(k));
-    const double sxx_w = c.wxx[k] * (c.bxx[k] * px(k) - c.bxx[k - 1] * px(k - 1));
-    const size_t s = k - P;
-    const double gxn = c.bxy[k + P] * px(k + P) - c.bxy[k] * px(k);
-    const double gyn = c.byx[k + 1] * py(k + 1) - c.byx[k] * py(k);
-    const double gxs = c.bxy[k] * px(k) - c.bxy[s] * px(s);
-    const double gys = c.byx[s + 1] * py(s + 1) - c.byx[s] * py(s);
-    const double sn = 0.5 * (c.nxx[k] * gxn + c.nxy[k] * gyn);
-    const double ss = 0.5 * (c.nxx[s] * gxs + c.nxy[s] * gys);
-    return c.bxx[k] * (sxx_e - sxx_w) + c.bxy[k] * (sn - ss);
-}
-
-template <class PX, class PY>
-__device__ inline double visc_y(const ViscCoef &c, size_t k, size_t P, PX px, PY py) {
-    const double syy_n = c.wyy[k + P] * (c.byy[k + P] * py(k + P) - c.byy[k] * py(k));
-    const double syy_s = c.wyy[k] * (c.byy[k] * py(k) - c.byy[k - P] * py(k - P));
-    const size_t w = k - 1;
-    const double gxe = c.bxy[k + P] * px(k + P) - c.bxy[k] * px(k);
-    const double gye = c.byx[k + 1] * py(k + 1) - c.byx[k] * py(k);
-    const double gxw = c.bxy[w + P] * px(w + P) - c.bxy[w] * px(w);
-    const double gyw = c.byx[k] * py(k) - c.byx[w] * py(w);
-    const double se = 0.5 * (c.nyx[k] * gxe + c.nyy[k] * gye);
-    const double sw = 0.5 * (c.nyx[w] * gxw + c.nyy[w] * gyw);
-    return c.byy[k] * (syy_n - syy_s) + c.byx[k] * (se - sw);
-}
-
-// conv(U, U, D, D) at x-face k and y-face k (eq:convective in index form).
-__device__ inline double conv_x(const double *ax, const double *ay, const double *ux, const double *uy,
-                                const double *hbx, const double *dx, size_t k, size_t P) {
-    auto Fxx = [&](size_t c) { return 0.25 * (ax[c - 1] * ux[c - 1] + ax[c] * ux[c]) * (ux[c - 1] + ux[c]); };
-    auto Fxy = [&](size_t nd) { return 0.25 * (ay[nd] * uy[nd] + ay[nd + 1] * uy[nd + 1]) * (ux[nd] + ux[nd + P]); };
-    return Fxx(k + 1) - Fxx(k) + Fxy(k) - Fxy(k - P) + hbx[k] * (ux[k] + dx[k]);
-}
-__device__ inline double conv_y(const double *ax, const double *ay, const double *ux, const double *uy,
-                                const double *hby, const double *dy, size_t k, size_t P) {
-    auto Fyy = [&](size_t c) { return 0.25 * (ay[c - P] * uy[c - P] + ay[c] * uy[c]) * (uy[c - P] + uy[c]); };
-    auto Fyx = [&](size_t nd) { return 0.25 * (ax[nd] * ux[nd] + ax[nd + P] * ux[nd + P]) * (uy[nd] + uy[nd + 1]); };
-    return Fyy(k + P) - Fyy(k) + Fyx(k) - Fyx(k - 1) + hby[k] * (uy[k] + dy[k]);
-}
-
-// ---------------------------------------------------------------------------
-// Poisson PCG kernels (A = -L, SPD on the zero-mean space)
-// ---------------------------------------------------------------------------
 
 struct PoisCoef {
     const double *cx, *cy, *dinv;
 };
 
-// b = (rho/tau) cont(U*, D) on pressure unknowns; mean of b; resets the solver.
+struct PredCoef {
+    ViscCoef vc;
+    const double *vu, *vv, *hdx, *hdy;
+    double rt, mu;
+};
+
+// Shared decision of every work-group of a direction kernel: given the
+// statistics of the current residual (r.z, sum z, sum r, r.r), is the solve
+// finished, and if not, what are rz, mean(z) and beta.  Group 0 records.
+struct DirStep {
+    bool stop;
+    double rz, mean, beta;
+};
+__device__ inline DirStep cg_decide(CgState *st, int first, int par, double fnorm2, double rs, double s, double r,
+                                    double rr) {
+    DirStep o;
+    const double m = st->zero_mean ? s / (double)st->n_active : 0.0;
+    o.mean = m;
+    o.rz = rs - m * r;
+    const int it = first ? 0 : st->slot[par ^ 1].it + 1;
+    const bool conv = !(rr > st->tol2 * fnorm2);
+    const bool lim = it >= st->maxit;
+    o.stop = conv || lim;
+    o.beta = first ? 0.0 : o.rz / st->slot[par ^ 1].rz;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        if (first) st->fnorm2 = fnorm2;
+        if (o.stop) {
+            st->done = 1;
+            st->status = conv ? 0 : CCNS_ENOTCONV;
+            st->it_final = it;
+            st->rnorm2_final = rr;
+        } else {
+            st->slot[par].rz = o.rz;
+            st->slot[par].it = it;
+        }
+    }
+    return o;
+}
+
+// ---------------------------------------------------------------------------
+// Poisson PCG kernels (A = -L, symmetric positive semi-definite; the
+// preconditioned residual is projected to zero mean, end of Sec. 4.6)
+// ---------------------------------------------------------------------------
+
+// b = (rho/tau) cont(U*, D) on the pressure unknowns (eq:pm_poisson); sum b.
 __global__ __launch_bounds__(NT) void k_pois_rhs(Dims d, PoisCoef pc, const double *__restrict__ ax,
                                                  const double *__restrict__ ay, const double *__restrict__ het,
                                                  const double *__restrict__ usx, const double *__restrict__ usy,
-                                                 double *__restrict__ b, double scale, CgState *st,
-                                                 double *partials) {
+                                                 double *__restrict__ b, double scale, double *pout) {
     const size_t P = d.pitch;
     double v[1] = {0.0};
-    for_tile(d, [&](int, int j, int i, size_t k) {
+    for_cells(d, [&](int, int j, int i, size_t k) {
         if (i < 1 || i > d.nx || j < 1 || j > d.ny) return;
-        if (pc.dinv[k] > 0.0) {
-            double c = ax[k] * usx[k] - ax[k - 1] * usx[k - 1] + ay[k] * usy[k] - ay[k - P] * usy[k - P] + het[k];
-            double bv = scale * c;
-            b[k] = bv;
-            v[0] += bv;
-        }
+        const double c = ax[k] * usx[k] - ax[k - 1] * usx[k - 1] + ay[k] * usy[k] - ay[k - P] * usy[k - P] + het[k];
+        const double bv = pc.dinv[k] > 0.0 ? scale * c : 0.0;
+        b[k] = bv;
+        v[0] += bv;
     });
-    double tot[1];
-    if (grid_reduce<1, 0>(v, partials, &st->counter, d.nlaunch, tot) && threadIdx.x == 0) {
-        st->mean_b = tot[0] / (double)st->n_active;
-        st->done = 0;
-        st->status = 0;
-        st->it = 0;
-    }
+    put_partials<1>(v, pout, d.nblk);
 }
 
-// Sum of b over the unknowns (caller-provided b); resets the solver.
-__global__ __launch_bounds__(NT) void k_pois_mean(Dims d, PoisCoef pc, const double *__restrict__ b, CgState *st,
-                                                  double *partials) {
+// Sum of a caller-provided b over the unknowns.
+__global__ __launch_bounds__(NT) void k_pois_sum(Dims d, PoisCoef pc, const double *__restrict__ b, double *pout) {
     double v[1] = {0.0};
-    for_tile(d, [&](int, int j, int i, size_t k) {
+    for_cells(d, [&](int, int, int, size_t k) {
         if (pc.dinv[k] > 0.0) v[0] += b[k];
     });
-    double tot[1];
-    if (grid_reduce<1, 0>(v, partials, &st->counter, d.nlaunch, tot) && threadIdx.x == 0) {
-        st->mean_b = tot[0] / (double)st->n_active;
-        st->done = 0;
-        st->status = 0;
-        st->it = 0;
-    }
+    put_partials<1>(v, pout, d.nblk);
 }
 
-// b <- b - mean(b); f = -b; r = f - A x; first preconditioned residual.
+// b <- b - mean(b); f = -b; r = f - A x; statistics of r.
 __global__ __launch_bounds__(NT) void k_pois_init(Dims d, PoisCoef pc, double *__restrict__ b,
                                                   const double *__restrict__ x, double *__restrict__ r, CgState *st,
-                                                  double *partials) {
+                                                  const double *pin, int nin, double *pout) {
+    double t[1];
+    get_totals<1>(pin, nin, t);
+    const double mb = t[0] / (double)st->n_active;
     const size_t P = d.pitch;
-    const double mb = st->mean_b;
     double v[5] = {0, 0, 0, 0, 0};
-    for_tile(d, [&](int, int j, int i, size_t k) {
+    for_cells(d, [&](int, int j, int i, size_t k) {
         const double dv = pc.dinv[k];
         if (!(dv > 0.0)) return;
         const double bp = b[k] - mb;
@@ -273,104 +155,131 @@ __global__ __launch_bounds__(NT) void k_pois_init(Dims d, PoisCoef pc, double *_
         v[3] += rv;
         v[4] += rv * rv;
     });
-    double tot[5];
-    if (grid_reduce<5, 0>(v, partials, &st->counter, d.nlaunch, tot) && threadIdx.x == 0) {
-        st->fnorm2 = tot[0];
-        const double m = st->zero_mean ? tot[2] / (double)st->n_active : 0.0;
-        st->mean = m;
-        st->rz = tot[1] - m * tot[3];
-        st->rnorm2 = tot[4];
-        st->beta = 0.0;
-        st->it = 0;
-        st->done = (tot[4] <= st->tol2 * tot[0]) ? 1 : 0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        st->done = 0;
         st->status = 0;
+        st->it_final = 0;
     }
+    put_partials<5>(v, pout, d.nblk);
 }
 
-// p = (M r) + beta p_old on the stencil; q = A p; partial p.q -> alpha.
-__global__ __launch_bounds__(NT) void k_pois_dir_apply(Dims d, PoisCoef pc, const double *__restrict__ r,
-                                                       const double *__restrict__ pold, double *__restrict__ pnew,
-                                                       double *__restrict__ q, CgState *st, double *partials) {
+// Tile of the Poisson stencil kernels: 64 columns x 16 rows (4 per thread).
+constexpr int PTY = 16;
+
+// Direction and operator: p = (M r) + beta p_old on the tile and a one-cell
+// halo staged in LDS; q = A p; partial p.q.  Consumes the residual statistics
+// of the previous kernel (init if `first`, else the update).
+__global__ __launch_bounds__(NT) void k_pois_dir(Dims d, PoisCoef pc, const double *__restrict__ r,
+                                                 const double *__restrict__ pold, double *__restrict__ pnew,
+                                                 double *__restrict__ q, CgState *st, int first, int par,
+                                                 const double *pin, int nin, double *pout) {
     if (st->done) return;
-    const size_t P = d.pitch;
-    const double beta = st->beta, m = st->mean;
-    double v[1] = {0.0};
-    for_tile(d, [&](int, int j, int i, size_t k) {
-        const double dv = pc.dinv[k];
-        if (!(dv > 0.0)) return;
-        auto pn = [&](size_t kk) {
-            const double di = pc.dinv[kk];
-            return di > 0.0 ? (di * r[kk] - m) + beta * pold[kk] : 0.0;
-        };
-        const double pcv = (dv * r[k] - m) + beta * pold[k];
-        const double ce = pc.cx[k], cw = pc.cx[k - 1], cn = pc.cy[k], cs = pc.cy[k - P];
-        const double qv = (ce + cw + cn + cs) * pcv - ce * pn(k + 1) - cw * pn(k - 1) - cn * pn(k + P) - cs * pn(k - P);
-        pnew[k] = pcv;
-        q[k] = qv;
-        v[0] += pcv * qv;
-    });
-    double tot[1];
-    if (grid_reduce<1, 0>(v, partials, &st->counter, d.nlaunch, tot) && threadIdx.x == 0) {
-        st->pq = tot[0];
-        if (!(tot[0] > 0.0)) {
-            st->done = 1;
-            st->status = CCNS_EBREAKDOWN;
-        } else {
-            st->alpha = st->rz / tot[0];
-        }
+    double fn2, rs, sm, rsum, rr;
+    if (first) {
+        double t[5];
+        get_totals<5>(pin, nin, t);
+        fn2 = t[0]; rs = t[1]; sm = t[2]; rsum = t[3]; rr = t[4];
+    } else {
+        double t[4];
+        get_totals<4>(pin, nin, t);
+        fn2 = st->fnorm2; rs = t[0]; sm = t[1]; rsum = t[2]; rr = t[3];
     }
+    const DirStep ds = cg_decide(st, first, par, fn2, rs, sm, rsum, rr);
+    if (ds.stop) return;
+    const double beta = ds.beta, m = ds.mean;
+    __shared__ double sp[PTY + 2][TX + 2];
+    const int P = d.pitch;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    double v[1] = {0.0};
+    for_tiles(d, [&](int, int c0, int r0) {
+        for (int e = threadIdx.x; e < (PTY + 2) * (TX + 2); e += NT) {
+            const int ly = e / (TX + 2), lx = e - ly * (TX + 2);
+            const int j = r0 - 1 + ly, i = c0 - 1 + lx;
+            const bool in = (j >= 0) && (j < d.rows) && (i >= 0) && (i < P);
+            const size_t k = in ? (size_t)j * P + i : 0;
+            const double di = pc.dinv[k], rv = r[k], po = pold[k];
+            sp[ly][lx] = (in && di > 0.0) ? (di * rv - m) + beta * po : 0.0;
+        }
+        __syncthreads();
+        const int i = c0 + tx;
+#pragma unroll
+        for (int rr2 = 0; rr2 < PTY / 4; ++rr2) {
+            const int lj = ty + 4 * rr2;
+            const int j = r0 + lj;
+            if (j < d.rows) {
+                const size_t k = (size_t)j * P + i;
+                const size_t kw = i > 0 ? k - 1 : k, ks = j > 0 ? k - P : k;
+                const double dv = pc.dinv[k], ce = pc.cx[k], cw = pc.cx[kw], cn = pc.cy[k], cs = pc.cy[ks];
+                const double pcv = sp[lj + 1][tx + 1];
+                double qv = (ce + cw + cn + cs) * pcv - ce * sp[lj + 1][tx + 2] - cw * sp[lj + 1][tx] -
+                            cn * sp[lj + 2][tx + 1] - cs * sp[lj][tx + 1];
+                qv = dv > 0.0 ? qv : 0.0;
+                pnew[k] = pcv;
+                q[k] = qv;
+                v[0] += pcv * qv;
+            }
+        }
+        __syncthreads();
+    });
+    put_partials<1>(v, pout, d.nblk);
 }
 
-// x += alpha p; r -= alpha q; z = M r statistics -> beta, convergence.
-// Flat over ncomp*n elements (inactive entries hold zeros).
-__global__ __launch_bounds__(NT) void k_cg_update(size_t ntot, int nlaunch, const double *__restrict__ dinv,
+// x += alpha p; r -= alpha q; statistics of the new residual.  Flat over
+// ntot entries (inactive entries hold zeros); each group works on contiguous
+// chunks of UPT*NT entries with every load issued before any arithmetic.
+constexpr int UPT = 4;
+__global__ __launch_bounds__(NT) void k_cg_update(size_t ntot, int nblk, const double *__restrict__ dinv,
                                                   double *__restrict__ x, double *__restrict__ r,
                                                   const double *__restrict__ p, const double *__restrict__ q,
-                                                  CgState *st, double *partials) {
+                                                  CgState *st, int par, const double *pin, int nin, double *pout) {
     if (st->done) return;
-    const double a = st->alpha;
-    double v[4] = {0, 0, 0, 0};
-    const size_t stride = (size_t)nlaunch * NT;
-    for (size_t k = (size_t)blockIdx.x * NT + threadIdx.x; k < ntot; k += stride) {
-        const double dv = dinv[k];
-        if (!(dv > 0.0)) continue;
-        x[k] += a * p[k];
-        const double rv = r[k] - a * q[k];
-        r[k] = rv;
-        const double s = dv * rv;
-        v[0] += rv * s;
-        v[1] += s;
-        v[2] += rv;
-        v[3] += rv * rv;
+    double t[1];
+    get_totals<1>(pin, nin, t);
+    if (!(t[0] > 0.0)) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            st->done = 1;
+            st->status = CCNS_EBREAKDOWN;
+            st->it_final = st->slot[par].it;
+        }
+        return;
     }
-    double tot[4];
-    if (grid_reduce<4, 0>(v, partials, &st->counter, nlaunch, tot) && threadIdx.x == 0) {
-        const double m = st->zero_mean ? tot[1] / (double)st->n_active : 0.0;
-        const double rz = tot[0] - m * tot[2];
-        st->beta = rz / st->rz;
-        st->rz = rz;
-        st->mean = m;
-        st->rnorm2 = tot[3];
-        st->it += 1;
-        if (tot[3] <= st->tol2 * st->fnorm2) {
-            st->done = 1;
-            st->status = CCNS_OK;
-        } else if (st->it >= st->maxit) {
-            st->done = 1;
-            st->status = CCNS_ENOTCONV;
+    const double a = st->slot[par].rz / t[0];
+    double v[4] = {0, 0, 0, 0};
+    const size_t chunk = (size_t)UPT * NT;
+    const int L = logical_group(nblk);
+    for (size_t base = (size_t)L * chunk; base < ntot; base += (size_t)nblk * chunk) {
+        double dv[UPT], xv[UPT], pv[UPT], rv[UPT], qv[UPT];
+#pragma unroll
+        for (int u = 0; u < UPT; ++u) {
+            const size_t k0 = base + (size_t)u * NT + threadIdx.x;
+            const size_t k = k0 < ntot ? k0 : ntot - 1;
+            dv[u] = dinv[k];
+            xv[u] = x[k];
+            pv[u] = p[k];
+            rv[u] = r[k];
+            qv[u] = q[k];
+        }
+#pragma unroll
+        for (int u = 0; u < UPT; ++u) {
+            const size_t k = base + (size_t)u * NT + threadIdx.x;
+            if (k < ntot && dv[u] > 0.0) {
+                x[k] = xv[u] + a * pv[u];
+                const double rn = rv[u] - a * qv[u];
+                r[k] = rn;
+                const double s = dv[u] * rn;
+                v[0] += rn * s;
+                v[1] += s;
+                v[2] += rn;
+                v[3] += rn * rn;
+            }
         }
     }
+    put_partials<4>(v, pout, nblk);
 }
 
 // ---------------------------------------------------------------------------
 // predictor (eq:pm_prediction): H = (rho/tau) V - mu visc(strain(., 0))
 // ---------------------------------------------------------------------------
-
-struct PredCoef {
-    ViscCoef vc;
-    const double *vu, *vv, *hdx, *hdy;
-    double rt, mu;
-};
 
 // conv^n, the predictor right-hand side, and U* := U^n as the start value.
 __global__ __launch_bounds__(NT) void k_pred_rhs(Dims d, PredCoef pc, const double *__restrict__ ax,
@@ -383,7 +292,7 @@ __global__ __launch_bounds__(NT) void k_pred_rhs(Dims d, PredCoef pc, const doub
                                                  double *__restrict__ rhs, double *__restrict__ xs, double rho,
                                                  double gxv, double gyv, int conv_valid) {
     const size_t P = d.pitch, n = d.n;
-    for_tile(d, [&](int comp, int j, int i, size_t k) {
+    for_cells(d, [&](int comp, int j, int i, size_t k) {
         auto pxm = [&](size_t kk) { return pc.vu[kk] > 0.0 ? ux[kk] : 0.0; };
         auto pym = [&](size_t kk) { return pc.vv[kk] > 0.0 ? uy[kk] : 0.0; };
         if (comp == 0) {
@@ -410,17 +319,17 @@ __global__ __launch_bounds__(NT) void k_pred_rhs(Dims d, PredCoef pc, const doub
     });
 }
 
-// r = rhs - H x0 (x0 masked to the unknowns); solver statistics.
+// r = rhs - H x0 (x0 masked to the unknowns); statistics of r.
 __global__ __launch_bounds__(NT) void k_pred_init(Dims d, PredCoef pc, const double *__restrict__ rhs,
                                                   const double *__restrict__ xs, double *__restrict__ r, CgState *st,
-                                                  double *partials) {
+                                                  double *pout) {
     const size_t P = d.pitch, n = d.n;
     const double *xu = xs, *xv = xs + n;
     auto pxm = [&](size_t kk) { return pc.vu[kk] > 0.0 ? xu[kk] : 0.0; };
     auto pym = [&](size_t kk) { return pc.vv[kk] > 0.0 ? xv[kk] : 0.0; };
     double v[5] = {0, 0, 0, 0, 0};
-    for_tile(d, [&](int comp, int j, int i, size_t k) {
-        double hv, f, dv;
+    for_cells(d, [&](int comp, int j, int i, size_t k) {
+        double hv, dv;
         size_t o;
         if (comp == 0) {
             if (!(pc.vu[k] > 0.0)) return;
@@ -433,7 +342,7 @@ __global__ __launch_bounds__(NT) void k_pred_init(Dims d, PredCoef pc, const dou
             o = n + k;
             dv = pc.hdy[k];
         }
-        f = rhs[o];
+        const double f = rhs[o];
         const double rv = f - hv;
         r[o] = rv;
         const double s = dv * rv;
@@ -443,29 +352,37 @@ __global__ __launch_bounds__(NT) void k_pred_init(Dims d, PredCoef pc, const dou
         v[3] += rv;
         v[4] += rv * rv;
     });
-    double tot[5];
-    if (grid_reduce<5, 0>(v, partials, &st->counter, d.nlaunch, tot) && threadIdx.x == 0) {
-        st->fnorm2 = tot[0];
-        st->mean = 0.0;
-        st->rz = tot[1];
-        st->rnorm2 = tot[4];
-        st->beta = 0.0;
-        st->it = 0;
-        st->done = (tot[4] <= st->tol2 * tot[0]) ? 1 : 0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        st->done = 0;
         st->status = 0;
+        st->it_final = 0;
     }
+    put_partials<5>(v, pout, d.nblk);
 }
 
-__global__ __launch_bounds__(NT) void k_pred_dir_apply(Dims d, PredCoef pc, const double *__restrict__ r,
-                                                       const double *__restrict__ pold, double *__restrict__ pnew,
-                                                       double *__restrict__ q, CgState *st, double *partials) {
+__global__ __launch_bounds__(NT) void k_pred_dir(Dims d, PredCoef pc, const double *__restrict__ r,
+                                                 const double *__restrict__ pold, double *__restrict__ pnew,
+                                                 double *__restrict__ q, CgState *st, int first, int par,
+                                                 const double *pin, int nin, double *pout) {
     if (st->done) return;
+    double fn2, rs, sm, rsum, rr;
+    if (first) {
+        double t[5];
+        get_totals<5>(pin, nin, t);
+        fn2 = t[0]; rs = t[1]; sm = t[2]; rsum = t[3]; rr = t[4];
+    } else {
+        double t[4];
+        get_totals<4>(pin, nin, t);
+        fn2 = st->fnorm2; rs = t[0]; sm = t[1]; rsum = t[2]; rr = t[3];
+    }
+    const DirStep ds = cg_decide(st, first, par, fn2, rs, sm, rsum, rr);
+    if (ds.stop) return;
+    const double beta = ds.beta;
     const size_t P = d.pitch, n = d.n;
-    const double beta = st->beta;
     auto pnx = [&](size_t kk) { return pc.hdx[kk] * r[kk] + beta * pold[kk]; };
     auto pny = [&](size_t kk) { return pc.hdy[kk] * r[n + kk] + beta * pold[n + kk]; };
     double v[1] = {0.0};
-    for_tile(d, [&](int comp, int j, int i, size_t k) {
+    for_cells(d, [&](int comp, int j, int i, size_t k) {
         if (comp == 0) {
             if (!(pc.vu[k] > 0.0)) return;
             const double pv = pnx(k);
@@ -482,16 +399,7 @@ __global__ __launch_bounds__(NT) void k_pred_dir_apply(Dims d, PredCoef pc, cons
             v[0] += pv * qv;
         }
     });
-    double tot[1];
-    if (grid_reduce<1, 0>(v, partials, &st->counter, d.nlaunch, tot) && threadIdx.x == 0) {
-        st->pq = tot[0];
-        if (!(tot[0] > 0.0)) {
-            st->done = 1;
-            st->status = CCNS_EBREAKDOWN;
-        } else {
-            st->alpha = st->rz / tot[0];
-        }
-    }
+    put_partials<1>(v, pout, d.nblk);
 }
 
 // ---------------------------------------------------------------------------
@@ -504,7 +412,7 @@ __global__ __launch_bounds__(NT) void k_correct(Dims d, const double *__restrict
                                                 const double *__restrict__ phi, double *__restrict__ ux,
                                                 double *__restrict__ uy, double s) {
     const size_t P = d.pitch;
-    for_tile(d, [&](int, int j, int i, size_t k) {
+    for_cells(d, [&](int, int j, int i, size_t k) {
         const double g1 = gx[k], g2 = gy[k];
         ux[k] = (g1 != 0.0) ? usx[k] - s * g1 * (phi[k + 1] - phi[k]) : usx[k];
         uy[k] = (g2 != 0.0) ? usy[k] - s * g2 * (phi[k + P] - phi[k]) : usy[k];
@@ -520,10 +428,10 @@ struct DiagCoef {
 __global__ __launch_bounds__(NT) void k_diag(Dims d, DiagCoef c, const double *__restrict__ ux,
                                              const double *__restrict__ uy, const double *__restrict__ phi,
                                              double *__restrict__ pr, double pcoef, int update_p, double rho,
-                                             DiagState *ds, double *partials) {
+                                             double *pout) {
     const size_t P = d.pitch;
     double v[5] = {0, 0, 0, 0, 0};
-    for_tile(d, [&](int, int j, int i, size_t k) {
+    for_cells(d, [&](int, int j, int i, size_t k) {
         v[2] += rho * c.vu[k] * ux[k];
         v[3] += rho * c.vv[k] * uy[k];
         if (i < 1 || i > d.nx || j < 1 || j > d.ny) return;
@@ -541,13 +449,18 @@ __global__ __launch_bounds__(NT) void k_diag(Dims d, DiagCoef c, const double *_
             }
         }
     });
-    double tot[5];
-    if (grid_reduce<4, 1>(v, partials, &ds->counter, d.nlaunch, tot) && threadIdx.x == 0) {
-        ds->mass = tot[0];
-        ds->ke = tot[1];
-        ds->momx = tot[2];
-        ds->momy = tot[3];
-        ds->divmax = tot[4];
+    put_partials<4, 1>(v, pout, d.nblk);
+}
+
+__global__ __launch_bounds__(NT) void k_diag_final(const double *pin, int nin, DiagState *ds) {
+    double t[5];
+    get_totals<4, 1>(pin, nin, t);
+    if (threadIdx.x == 0) {
+        ds->mass = t[0];
+        ds->ke = t[1];
+        ds->momx = t[2];
+        ds->momy = t[3];
+        ds->divmax = t[4];
     }
 }
 
@@ -558,8 +471,8 @@ __global__ __launch_bounds__(NT) void k_diag(Dims d, DiagCoef c, const double *_
 __global__ __launch_bounds__(NT) void k_op_cont(Dims d, const double *ax, const double *ay, const double *het,
                                                 const double *ux, const double *uy, double *out) {
     const size_t P = d.pitch;
-    for_tile(d, [&](int, int j, int i, size_t k) {
-        if (i < 1 || i > d.nx || j < 1 || j > d.ny || i >= d.nx + 2) { out[k] = 0.0; return; }
+    for_cells(d, [&](int, int j, int i, size_t k) {
+        if (i < 1 || i > d.nx || j < 1 || j > d.ny) { out[k] = 0.0; return; }
         out[k] = ax[k] * ux[k] - ax[k - 1] * ux[k - 1] + ay[k] * uy[k] - ay[k - P] * uy[k - P] + het[k];
     });
 }
@@ -567,7 +480,7 @@ __global__ __launch_bounds__(NT) void k_op_cont(Dims d, const double *ax, const 
 __global__ __launch_bounds__(NT) void k_op_pres(Dims d, const double *ax, const double *ay, const double *p,
                                                 double *gx, double *gy) {
     const size_t P = d.pitch;
-    for_tile(d, [&](int, int j, int i, size_t k) {
+    for_cells(d, [&](int, int j, int i, size_t k) {
         auto pv = [&](int jj, int ii) {
             return (ii >= 1 && ii <= d.nx && jj >= 1 && jj <= d.ny) ? p[(size_t)jj * P + ii] : 0.0;
         };
@@ -583,7 +496,7 @@ __global__ __launch_bounds__(NT) void k_op_visc(Dims d, PredCoef pc, const doubl
     const size_t P = d.pitch;
     auto pxm = [&](size_t kk) { return pc.vu[kk] > 0.0 ? ux[kk] : 0.0; };
     auto pym = [&](size_t kk) { return pc.vv[kk] > 0.0 ? uy[kk] : 0.0; };
-    for_tile(d, [&](int, int j, int i, size_t k) {
+    for_cells(d, [&](int, int j, int i, size_t k) {
         double a = 0.0, b = 0.0;
         if (pc.vu[k] > 0.0) {
             const double kv = visc_x(pc.vc, k, P, pxm, pym);
@@ -602,7 +515,7 @@ __global__ __launch_bounds__(NT) void k_op_conv(Dims d, const double *ax, const 
                                                 const double *hby, const double *dx, const double *dy,
                                                 const double *ux, const double *uy, double *ox, double *oy) {
     const size_t P = d.pitch;
-    for_tile(d, [&](int, int j, int i, size_t k) {
+    for_cells(d, [&](int, int j, int i, size_t k) {
         ox[k] = (i >= 1 && i <= d.nx - 1 && j >= 1 && j <= d.ny) ? conv_x(ax, ay, ux, uy, hbx, dx, k, P) : 0.0;
         oy[k] = (i >= 1 && i <= d.nx && j >= 1 && j <= d.ny - 1) ? conv_y(ax, ay, ux, uy, hby, dy, k, P) : 0.0;
     });
@@ -610,7 +523,7 @@ __global__ __launch_bounds__(NT) void k_op_conv(Dims d, const double *ax, const 
 
 __global__ __launch_bounds__(NT) void k_op_lap(Dims d, PoisCoef pc, const double *phi, double *out) {
     const size_t P = d.pitch;
-    for_tile(d, [&](int, int j, int i, size_t k) {
+    for_cells(d, [&](int, int j, int i, size_t k) {
         if (!(pc.dinv[k] > 0.0)) { out[k] = 0.0; return; }
         const double ph = phi[k];
         out[k] = pc.cx[k] * (phi[k + 1] - ph) - pc.cx[k - 1] * (ph - phi[k - 1]) + pc.cy[k] * (phi[k + P] - ph) -
@@ -621,7 +534,7 @@ __global__ __launch_bounds__(NT) void k_op_lap(Dims d, PoisCoef pc, const double
 __global__ __launch_bounds__(NT) void k_op_kin(Dims d, const double *vur, const double *vvr, const double *ux,
                                                const double *uy, double *out) {
     const size_t P = d.pitch;
-    for_tile(d, [&](int, int j, int i, size_t k) {
+    for_cells(d, [&](int, int j, int i, size_t k) {
         if (i < 1 || i > d.nx || j < 1 || j > d.ny) { out[k] = 0.0; return; }
         out[k] = 0.25 * (vur[k - 1] * ux[k - 1] * ux[k - 1] + vur[k] * ux[k] * ux[k] +
                          vvr[k - P] * uy[k - P] * uy[k - P] + vvr[k] * uy[k] * uy[k]);
@@ -658,23 +571,23 @@ enum Arr {
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
+// Partial-sum buffers: each holds up to 8 slots of NBMAX groups.
+enum Part { PB_RHS, PB_INIT, PB_DIR, PB_UPD, PB_DIAG, PB_COUNT };
+constexpr int TY = 8;   // tile rows of the face kernels and simple cell kernels
+
 struct WsPlan {
     Layout L;
     size_t arr_bytes;   // bytes per array
     size_t part_off, part_bytes, state_off, total;
-    int nlaunch_max;
 };
 
 WsPlan plan(int nx, int ny) {
     WsPlan w;
     w.L = make_layout(nx, ny);
     w.arr_bytes = align_up(w.L.n * sizeof(double), 256);
-    int gx = w.L.pitch / TX, gy = (w.L.rows + TY - 1) / TY;
-    int ntile2 = 2 * gx * gy;
-    w.nlaunch_max = std::max(((ntile2 + 7) / 8) * 8, 2048);
     w.part_off = w.arr_bytes * A_COUNT;
-    w.part_bytes = align_up((size_t)w.nlaunch_max * NRED * sizeof(double), 256);
-    w.state_off = w.part_off + w.part_bytes;
+    w.part_bytes = align_up((size_t)NBMAX * 8 * sizeof(double), 256);
+    w.state_off = w.part_off + w.part_bytes * PB_COUNT;
     w.total = w.state_off + 4096;
     return w;
 }
@@ -688,21 +601,23 @@ struct ccns_ctx {
     hipStream_t stream;
     char *base;
     double *a[A_COUNT];
-    double *partials;
+    double *part[PB_COUNT];
     CgState *st_pred, *st_pois;
     DiagState *diag;
     CgState *h_st;      // pinned host copies
     DiagState *h_diag;
     Dims dc, df;        // cell tiles (1 component) and face tiles (2 components)
+    Dims dp;            // tiles of the Poisson stencil kernels (PTY rows)
     int conv_valid;
     int n_active;
     int last_pois_it, last_pred_it;
     int pbuf_pred, pbuf_pois;
+    int init_nblk;      // groups of the last init kernel (its partials feed the first direction)
     // optional kernel timing: events around every 4th CG iteration
     int timing;
     std::vector<hipEvent_t> evpool;
     size_t evused;
-    double t_ms[4];    // Poisson dir-apply, Poisson update, predictor dir-apply, predictor update
+    double t_ms[4];    // Poisson direction, Poisson update, predictor direction, predictor update
     long t_count[4];
     std::string err;
 };
@@ -721,17 +636,21 @@ ccns_status fail(ccns_ctx *c, ccns_status s, const std::string &msg) {
             return fail(ctx, CCNS_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
     } while (0)
 
-Dims make_dims(const Layout &L, int ncomp) {
+Dims make_dims(const Layout &L, int ncomp, int ty) {
     Dims d;
     d.nx = L.nx;
     d.ny = L.ny;
     d.rows = L.rows;
     d.pitch = L.pitch;
     d.gx = L.pitch / TX;
-    d.gy = (L.rows + TY - 1) / TY;
+    d.ty = ty;
+    d.gy = (L.rows + ty - 1) / ty;
     d.ntile = d.gx * d.gy;
     d.ncomp = ncomp;
-    d.nlaunch = ((d.ntile * ncomp + 7) / 8) * 8;
+    const int total = d.ntile * ncomp;
+    d.tpb = (total + NBMAX - 1) / NBMAX;
+    const int groups = (total + d.tpb - 1) / d.tpb;
+    d.nblk = ((groups + 7) / 8) * 8;
     d.n = L.n;
     return d;
 }
@@ -765,14 +684,13 @@ ccns_status from_dev(ccns_ctx *c, double *dst, const double *src, hipMemcpyKind 
     return CCNS_OK;
 }
 
-// Blocks of an element-wise kernel over ntot entries (about 8 per thread).
+// Groups of an element-wise kernel over ntot entries.
 int flat_blocks(size_t ntot) {
-    size_t b = (ntot + (size_t)NT * 8 - 1) / ((size_t)NT * 8);
-    b = std::min<size_t>(std::max<size_t>(b, 8), 2048);
+    size_t b = (ntot + (size_t)NT * UPT - 1) / ((size_t)NT * UPT);
+    b = std::min<size_t>(std::max<size_t>(b, 8), NBMAX);
     return (int)((b + 7) / 8 * 8);
 }
 
-// Runs CG iterations until the device flags convergence; reads the state.
 hipEvent_t next_event(ccns_ctx *c) {
     if (c->evused == c->evpool.size()) {
         hipEvent_t e;
@@ -797,38 +715,45 @@ void harvest_events(ccns_ctx *c, int kid) {
     c->evused = 0;
 }
 
-template <class DirApply>
-ccns_status cg_loop(ccns_ctx *c, CgState *st, double *x, double *r, double *const pbuf[2], int &par, double *q,
-                    const double *dinv, size_t ntot, int &last_it, DirApply dir_apply, ccns_solve_info *info,
-                    int kid) {
-    int chunk = std::max(8, (int)(0.9 * last_it));
+// Runs CG iterations (after the caller launched the init kernel, whose
+// partials are in PB_INIT) until the device flags the end of the solve.
+// dir(first, par, pin, nin, pout) launches the direction+operator kernel and
+// returns its group count.
+template <class Dir>
+ccns_status cg_loop(ccns_ctx *c, CgState *st, double *x, double *r, double *const pbuf[2], int &par_buf, double *q,
+                    const double *dinv, size_t ntot, int &last_it, Dir dir, ccns_solve_info *info, int kid) {
     const int nl = flat_blocks(ntot);
-    HIPCHK(c, hipMemcpyAsync(c->h_st, st, sizeof(CgState), hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(c, hipStreamSynchronize(c->stream));
-    int issued = 0;
-    while (!c->h_st->done) {
-        for (int it = 0; it < chunk; ++it, ++issued) {
-            // timed launches stop at the predicted count so that no early-exit
-            // launch after convergence is sampled
-            const bool tm = c->timing && (issued % 4 == 0) && issued < last_it;
+    int chunk = std::max(8, (int)(0.9 * last_it));
+    int it = 0;
+    bool first = true;
+    for (;;) {
+        for (int u = 0; u < chunk; ++u, ++it) {
+            const int par = it & 1;
+            const bool tm = c->timing && (it % 4 == 0) && it < last_it;
             if (tm) (void)hipEventRecord(next_event(c), c->stream);
-            dir_apply(pbuf[par], pbuf[par ^ 1]);
+            const int nd = dir(first ? 1 : 0, par, pbuf[par_buf], pbuf[par_buf ^ 1],
+                               first ? c->part[PB_INIT] : c->part[PB_UPD], first ? c->init_nblk : nl,
+                               c->part[PB_DIR]);
             if (tm) (void)hipEventRecord(next_event(c), c->stream);
-            k_cg_update<<<nl, NT, 0, c->stream>>>(ntot, nl, dinv, x, r, pbuf[par ^ 1], q, st, c->partials);
+            k_cg_update<<<nl, NT, 0, c->stream>>>(ntot, nl, dinv, x, r, pbuf[par_buf ^ 1], q, st, par,
+                                                  c->part[PB_DIR], nd, c->part[PB_UPD]);
             if (tm) (void)hipEventRecord(next_event(c), c->stream);
-            par ^= 1;
+            par_buf ^= 1;
+            first = false;
         }
         HIPCHK(c, hipGetLastError());
         HIPCHK(c, hipMemcpyAsync(c->h_st, st, sizeof(CgState), hipMemcpyDeviceToHost, c->stream));
         HIPCHK(c, hipStreamSynchronize(c->stream));
         if (c->timing) harvest_events(c, kid);
+        if (c->h_st->done) break;
         chunk = 32;
     }
-    last_it = c->h_st->it;
+    last_it = c->h_st->it_final;
     if (info) {
-        info->iterations = c->h_st->it;
+        info->iterations = c->h_st->it_final;
         info->outer = 1;
-        info->rel_residual = c->h_st->fnorm2 > 0 ? std::sqrt(c->h_st->rnorm2 / c->h_st->fnorm2) : 0.0;
+        info->rel_residual =
+            c->h_st->fnorm2 > 0 ? std::sqrt(c->h_st->rnorm2_final / c->h_st->fnorm2) : 0.0;
         info->status = c->h_st->status;
     }
     return (ccns_status)c->h_st->status;
@@ -844,15 +769,17 @@ void set_cg(ccns_ctx *c, CgState *st, double tol, int maxit, int zero_mean, int 
     (void)hipMemcpyAsync(st, &h, sizeof(CgState), hipMemcpyHostToDevice, c->stream);
 }
 
-ccns_status pressure_solve_dev(ccns_ctx *c, ccns_solve_info *info) {
-    // b is in A_B with its mean computed; phi (A_PHI) is the start value
+// Pressure solve; b is in A_B with its sum's partials in PB_RHS (nin groups).
+ccns_status pressure_solve_dev(ccns_ctx *c, int nin, ccns_solve_info *info) {
     PoisCoef pc = pois_coef(c);
-    k_pois_init<<<c->dc.nlaunch, NT, 0, c->stream>>>(c->dc, pc, c->a[A_B], c->a[A_PHI], c->a[A_R], c->st_pois,
-                                                     c->partials);
+    k_pois_init<<<c->dc.nblk, NT, 0, c->stream>>>(c->dc, pc, c->a[A_B], c->a[A_PHI], c->a[A_R], c->st_pois,
+                                                  c->part[PB_RHS], nin, c->part[PB_INIT]);
+    c->init_nblk = c->dc.nblk;
     double *pb[2] = {c->a[A_P0], c->a[A_P1]};
-    auto dir = [&](double *pold, double *pnew) {
-        k_pois_dir_apply<<<c->dc.nlaunch, NT, 0, c->stream>>>(c->dc, pc, c->a[A_R], pold, pnew, c->a[A_Q], c->st_pois,
-                                                              c->partials);
+    auto dir = [&](int first, int par, double *pold, double *pnew, const double *pin, int nin2, double *pout) {
+        k_pois_dir<<<c->dp.nblk, NT, 0, c->stream>>>(c->dp, pc, c->a[A_R], pold, pnew, c->a[A_Q], c->st_pois,
+                                                     first, par, pin, nin2, pout);
+        return c->dp.nblk;
     };
     return cg_loop(c, c->st_pois, c->a[A_PHI], c->a[A_R], pb, c->pbuf_pois, c->a[A_Q], c->a[A_DINV], c->w.L.n,
                    c->last_pois_it, dir, info, 0);
@@ -860,18 +787,20 @@ ccns_status pressure_solve_dev(ccns_ctx *c, ccns_solve_info *info) {
 
 ccns_status predict_dev(ccns_ctx *c, ccns_solve_info *info) {
     PredCoef pc = pred_coef(c);
-    k_pred_rhs<<<c->df.nlaunch, NT, 0, c->stream>>>(c->df, pc, c->a[A_AX], c->a[A_AY], c->a[A_HBX], c->a[A_HBY],
-                                                    c->a[A_DX], c->a[A_DY], c->a[A_UX], c->a[A_UY], c->a[A_P],
-                                                    c->a[A_VDX], c->a[A_VDY], c->a[A_CONVX], c->a[A_CONVY],
-                                                    c->a[A_RHSX], c->a[A_USX], c->prm.rho, c->prm.gx, c->prm.gy,
-                                                    c->conv_valid);
+    k_pred_rhs<<<c->df.nblk, NT, 0, c->stream>>>(c->df, pc, c->a[A_AX], c->a[A_AY], c->a[A_HBX], c->a[A_HBY],
+                                                 c->a[A_DX], c->a[A_DY], c->a[A_UX], c->a[A_UY], c->a[A_P],
+                                                 c->a[A_VDX], c->a[A_VDY], c->a[A_CONVX], c->a[A_CONVY],
+                                                 c->a[A_RHSX], c->a[A_USX], c->prm.rho, c->prm.gx, c->prm.gy,
+                                                 c->conv_valid);
     c->conv_valid = 1;
-    k_pred_init<<<c->df.nlaunch, NT, 0, c->stream>>>(c->df, pc, c->a[A_RHSX], c->a[A_USX], c->a[A_PRX], c->st_pred,
-                                                     c->partials);
+    k_pred_init<<<c->df.nblk, NT, 0, c->stream>>>(c->df, pc, c->a[A_RHSX], c->a[A_USX], c->a[A_PRX], c->st_pred,
+                                                  c->part[PB_INIT]);
+    c->init_nblk = c->df.nblk;
     double *pb[2] = {c->a[A_PP0X], c->a[A_PP1X]};
-    auto dir = [&](double *pold, double *pnew) {
-        k_pred_dir_apply<<<c->df.nlaunch, NT, 0, c->stream>>>(c->df, pc, c->a[A_PRX], pold, pnew, c->a[A_PQX],
-                                                              c->st_pred, c->partials);
+    auto dir = [&](int first, int par, double *pold, double *pnew, const double *pin, int nin, double *pout) {
+        k_pred_dir<<<c->df.nblk, NT, 0, c->stream>>>(c->df, pc, c->a[A_PRX], pold, pnew, c->a[A_PQX], c->st_pred,
+                                                     first, par, pin, nin, pout);
+        return c->df.nblk;
     };
     return cg_loop(c, c->st_pred, c->a[A_USX], c->a[A_PRX], pb, c->pbuf_pred, c->a[A_PQX], c->a[A_HDX],
                    2 * c->w.L.n, c->last_pred_it, dir, info, 2);
@@ -881,8 +810,9 @@ ccns_status diag_dev(ccns_ctx *c, int update_p, ccns_step_info *info) {
     DiagCoef dc{c->a[A_AX], c->a[A_AY], c->a[A_HET], c->a[A_DINV], c->a[A_VUR], c->a[A_VVR],
                 c->a[A_VU], c->a[A_VV], c->a[A_CX], c->a[A_CY], c->a[A_VINV]};
     const double pcoef = c->prm.tau * c->prm.mu / (2.0 * c->prm.rho);
-    k_diag<<<c->dc.nlaunch, NT, 0, c->stream>>>(c->dc, dc, c->a[A_UX], c->a[A_UY], c->a[A_PHI], c->a[A_P], pcoef,
-                                                update_p, c->prm.rho, c->diag, c->partials);
+    k_diag<<<c->dc.nblk, NT, 0, c->stream>>>(c->dc, dc, c->a[A_UX], c->a[A_UY], c->a[A_PHI], c->a[A_P], pcoef,
+                                             update_p, c->prm.rho, c->part[PB_DIAG]);
+    k_diag_final<<<1, NT, 0, c->stream>>>(c->part[PB_DIAG], c->dc.nblk, c->diag);
     HIPCHK(c, hipGetLastError());
     HIPCHK(c, hipMemcpyAsync(c->h_diag, c->diag, sizeof(DiagState), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -899,14 +829,14 @@ ccns_status diag_dev(ccns_ctx *c, int update_p, ccns_step_info *info) {
 
 ccns_status correct_dev(ccns_ctx *c, int update_p, ccns_step_info *info) {
     PoisCoef pc = pois_coef(c);
-    k_pois_rhs<<<c->dc.nlaunch, NT, 0, c->stream>>>(c->dc, pc, c->a[A_AX], c->a[A_AY], c->a[A_HET], c->a[A_USX],
-                                                    c->a[A_USY], c->a[A_B], c->prm.rho / c->prm.tau, c->st_pois,
-                                                    c->partials);
+    k_pois_rhs<<<c->dc.nblk, NT, 0, c->stream>>>(c->dc, pc, c->a[A_AX], c->a[A_AY], c->a[A_HET], c->a[A_USX],
+                                                 c->a[A_USY], c->a[A_B], c->prm.rho / c->prm.tau,
+                                                 c->part[PB_RHS]);
     ccns_solve_info si{};
-    ccns_status s = pressure_solve_dev(c, &si);
+    ccns_status s = pressure_solve_dev(c, c->dc.nblk, &si);
     if (info) info->poisson = si;
-    k_correct<<<c->dc.nlaunch, NT, 0, c->stream>>>(c->dc, c->a[A_GX], c->a[A_GY], c->a[A_USX], c->a[A_USY],
-                                                   c->a[A_PHI], c->a[A_UX], c->a[A_UY], c->prm.tau / c->prm.rho);
+    k_correct<<<c->dc.nblk, NT, 0, c->stream>>>(c->dc, c->a[A_GX], c->a[A_GY], c->a[A_USX], c->a[A_USY],
+                                                c->a[A_PHI], c->a[A_UX], c->a[A_UY], c->prm.tau / c->prm.rho);
     ccns_status s2 = diag_dev(c, update_p, info);
     if (s2 != CCNS_OK) return s2;
     return s;
@@ -947,12 +877,14 @@ ccns_status ccns_ctx_create(const ccns_grid *grid, const ccns_params *params, co
     c->stream = (hipStream_t)hip_stream;
     c->base = (char *)dev_workspace;
     for (int k = 0; k < A_COUNT; ++k) c->a[k] = (double *)(c->base + (size_t)k * c->w.arr_bytes);
-    c->partials = (double *)(c->base + c->w.part_off);
+    for (int k = 0; k < PB_COUNT; ++k) c->part[k] = (double *)(c->base + c->w.part_off + (size_t)k * c->w.part_bytes);
     c->st_pred = (CgState *)(c->base + c->w.state_off);
     c->st_pois = c->st_pred + 1;
     c->diag = (DiagState *)(c->st_pois + 1);
-    c->dc = make_dims(c->w.L, 1);
-    c->df = make_dims(c->w.L, 2);
+    c->dc = make_dims(c->w.L, 1, TY);
+    c->df = make_dims(c->w.L, 2, TY);
+    c->dp = make_dims(c->w.L, 1, PTY);
+    c->init_nblk = c->dc.nblk;
     c->conv_valid = 0;
     c->last_pois_it = c->last_pred_it = 16;
     c->pbuf_pred = c->pbuf_pois = 0;
@@ -1037,35 +969,35 @@ ccns_status ccns_apply(ccns_ctx *c, int op, const double *const *in, double *con
     switch (op) {
     case CCNS_OP_CONT:
         if ((s = to_dev(c, t0, in[0], D2D)) || (s = to_dev(c, t1, in[1], D2D))) return s;
-        k_op_cont<<<c->dc.nlaunch, NT, 0, c->stream>>>(c->dc, c->a[A_AX], c->a[A_AY], c->a[A_HET], t0, t1, t2);
+        k_op_cont<<<c->dc.nblk, NT, 0, c->stream>>>(c->dc, c->a[A_AX], c->a[A_AY], c->a[A_HET], t0, t1, t2);
         if ((s = from_dev(c, out[0], t2, D2D))) return s;
         break;
     case CCNS_OP_PRES:
         if ((s = to_dev(c, t0, in[0], D2D))) return s;
-        k_op_pres<<<c->dc.nlaunch, NT, 0, c->stream>>>(c->dc, c->a[A_AX], c->a[A_AY], t0, t1, t2);
+        k_op_pres<<<c->dc.nblk, NT, 0, c->stream>>>(c->dc, c->a[A_AX], c->a[A_AY], t0, t1, t2);
         if ((s = from_dev(c, out[0], t1, D2D)) || (s = from_dev(c, out[1], t2, D2D))) return s;
         break;
     case CCNS_OP_VISC:
     case CCNS_OP_H:
         if ((s = to_dev(c, t0, in[0], D2D)) || (s = to_dev(c, t1, in[1], D2D))) return s;
-        k_op_visc<<<c->dc.nlaunch, NT, 0, c->stream>>>(c->dc, pred_coef(c), c->a[A_VDX], c->a[A_VDY], t0, t1, t2, t3,
+        k_op_visc<<<c->dc.nblk, NT, 0, c->stream>>>(c->dc, pred_coef(c), c->a[A_VDX], c->a[A_VDY], t0, t1, t2, t3,
                                                        op == CCNS_OP_VISC ? 0 : 1);
         if ((s = from_dev(c, out[0], t2, D2D)) || (s = from_dev(c, out[1], t3, D2D))) return s;
         break;
     case CCNS_OP_CONV:
         if ((s = to_dev(c, t0, in[0], D2D)) || (s = to_dev(c, t1, in[1], D2D))) return s;
-        k_op_conv<<<c->dc.nlaunch, NT, 0, c->stream>>>(c->dc, c->a[A_AX], c->a[A_AY], c->a[A_HBX], c->a[A_HBY],
+        k_op_conv<<<c->dc.nblk, NT, 0, c->stream>>>(c->dc, c->a[A_AX], c->a[A_AY], c->a[A_HBX], c->a[A_HBY],
                                                        c->a[A_DX], c->a[A_DY], t0, t1, t2, t3);
         if ((s = from_dev(c, out[0], t2, D2D)) || (s = from_dev(c, out[1], t3, D2D))) return s;
         break;
     case CCNS_OP_LAP:
         if ((s = to_dev(c, t0, in[0], D2D))) return s;
-        k_op_lap<<<c->dc.nlaunch, NT, 0, c->stream>>>(c->dc, pois_coef(c), t0, t1);
+        k_op_lap<<<c->dc.nblk, NT, 0, c->stream>>>(c->dc, pois_coef(c), t0, t1);
         if ((s = from_dev(c, out[0], t1, D2D))) return s;
         break;
     case CCNS_OP_KINETIC:
         if ((s = to_dev(c, t0, in[0], D2D)) || (s = to_dev(c, t1, in[1], D2D))) return s;
-        k_op_kin<<<c->dc.nlaunch, NT, 0, c->stream>>>(c->dc, c->a[A_VUR], c->a[A_VVR], t0, t1, t2);
+        k_op_kin<<<c->dc.nblk, NT, 0, c->stream>>>(c->dc, c->a[A_VUR], c->a[A_VVR], t0, t1, t2);
         if ((s = from_dev(c, out[0], t2, D2D))) return s;
         break;
     default:
@@ -1080,8 +1012,8 @@ ccns_status ccns_pressure_solve(ccns_ctx *c, const double *b, double *phi, ccns_
     if (!c || !b) return fail(c, CCNS_EINVAL, "null argument");
     ccns_status s = to_dev(c, c->a[A_B], b, hipMemcpyDeviceToDevice);
     if (s != CCNS_OK) return s;
-    k_pois_mean<<<c->dc.nlaunch, NT, 0, c->stream>>>(c->dc, pois_coef(c), c->a[A_B], c->st_pois, c->partials);
-    s = pressure_solve_dev(c, info);
+    k_pois_sum<<<c->dc.nblk, NT, 0, c->stream>>>(c->dc, pois_coef(c), c->a[A_B], c->part[PB_RHS]);
+    s = pressure_solve_dev(c, c->dc.nblk, info);
     if (phi) {
         ccns_status s2 = from_dev(c, phi, c->a[A_PHI], hipMemcpyDeviceToDevice);
         if (s2 != CCNS_OK) return s2;
