@@ -171,7 +171,7 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": case.name, "nx": g.nx, "ny": g.ny, "re": case.re, "cfl": case.cfl,
-                   "pcg_tol": case.pcg_tol, "precond": "jacobi", "precision": "fp64"},
+                   "pcg_tol": case.pcg_tol, "precond": "multigrid", "precision": "fp64"},
         "div_rel_max": div_max,
         "cg_iters_per_step": n_cg,
         "pred_iters_per_step": float(np.mean([i["pred_iters"] for i in infos])),

@@ -106,7 +106,12 @@ ccns_status ccns_capacities(const ccns_grid *grid, const ccns_body *bodies, int 
  *                 node volumes for the cross coupling), 1 as printed in
  *                 eq:offdiag (not symmetric; apply only), 2 arithmetic mean
  *  poisson_weight 0: Poisson face weight A^2/V_f (mass matrix explicit);
- *                 1: A^2 (the printed equations with unit mass matrix) */
+ *                 1: A^2 (the printed equations with unit mass matrix)
+ *  precond        Poisson preconditioner: 0 Jacobi (diagonal); 1 geometric
+ *                 multigrid V-cycle (2x2 cell agglomeration, weighted-Jacobi
+ *                 smoothing, pseudo-inverse on the coarsest grid).  The
+ *                 paper does not fix the solver; both converge to the same
+ *                 solution of eq:pm_poisson. */
 typedef struct {
     double rho, mu, tau, u_ref, gx, gy;
     double pcg_tol, pred_tol, div_tol;
@@ -114,7 +119,7 @@ typedef struct {
     int precision;
     int visc_form;
     int poisson_weight;
-    int reserved;
+    int precond;
 } ccns_params;
 
 typedef struct ccns_ctx ccns_ctx;

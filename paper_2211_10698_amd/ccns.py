@@ -42,7 +42,7 @@ class Params(C.Structure):
                 ("gx", C.c_double), ("gy", C.c_double), ("pcg_tol", C.c_double), ("pred_tol", C.c_double),
                 ("div_tol", C.c_double), ("pcg_maxit", C.c_int), ("pred_maxit", C.c_int),
                 ("precision", C.c_int), ("visc_form", C.c_int), ("poisson_weight", C.c_int),
-                ("reserved", C.c_int)]
+                ("precond", C.c_int)]
 
 
 class SolveInfo(C.Structure):
@@ -146,10 +146,14 @@ def ccns_capacities(spec, bodies, fn=None) -> np.ndarray:
     return out.reshape(NCAPS, spec.ny + 2, spec.nx + 2)
 
 
+PRECOND_JACOBI, PRECOND_MG = 0, 1
+
+
 def make_params(rho, mu, tau, u_ref=1.0, pcg_tol=1e-10, pred_tol=1e-12, div_tol=1e-8, pcg_maxit=200000,
-                pred_maxit=500, precision=0, visc_form=0, poisson_weight=0, gx=0.0, gy=0.0) -> Params:
+                pred_maxit=500, precision=0, visc_form=0, poisson_weight=0, gx=0.0, gy=0.0,
+                precond=PRECOND_MG) -> Params:
     return Params(rho, mu, tau, u_ref, gx, gy, pcg_tol, pred_tol, div_tol, pcg_maxit, pred_maxit, precision,
-                  visc_form, poisson_weight, 0)
+                  visc_form, poisson_weight, precond)
 
 
 class Context:

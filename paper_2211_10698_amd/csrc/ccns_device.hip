@@ -278,6 +278,173 @@ __global__ __launch_bounds__(NT) void k_cg_update(size_t ntot, int nblk, const d
 }
 
 // ---------------------------------------------------------------------------
+// multigrid V-cycle preconditioner for the Poisson solve.  Each coarse cell
+// agglomerates 2x2 cells; the coarse face weight is half the sum of the two
+// fine face weights it covers (for uncut cells this is the Laplacian
+// rediscretised on the coarse grid); weighted-Jacobi smoothing; interpolation
+// copies a coarse value to its active children and restriction is its
+// transpose.  With equal numbers of pre- and post-smoothing sweeps the cycle
+// is a symmetric positive definite operator, as the conjugate-gradient
+// iteration requires.
+// ---------------------------------------------------------------------------
+
+// x = omega D^-1 b: the first sweep from a zero initial guess.
+__global__ __launch_bounds__(NT) void k_mg_first(Dims d, const double *__restrict__ dinv,
+                                                 const double *__restrict__ b, double *__restrict__ x, double omega) {
+    for_cells(d, [&](int, int, int, size_t k) { x[k] = omega * dinv[k] * b[k]; });
+}
+
+// x_new = x' + omega D^-1 (b - A x') with x' = x (+ the interpolated coarse
+// correction when PROLONG).  With STATS, partials of (b.z, z, b, b.b) for
+// z = x_new (b is the residual the cycle preconditions).
+template <bool PROLONG, bool STATS>
+__global__ __launch_bounds__(NT) void k_mg_smooth(Dims d, PoisCoef c, const double *__restrict__ b,
+                                                  const double *__restrict__ x, const double *__restrict__ xc,
+                                                  int cpitch, double *__restrict__ xn, double omega, double *pout) {
+    __shared__ double sx[PTY + 2][TX + 2];
+    const int P = d.pitch;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    double v[4] = {0, 0, 0, 0};
+    for_tiles(d, [&](int, int c0, int r0) {
+        for (int e = threadIdx.x; e < (PTY + 2) * (TX + 2); e += NT) {
+            const int ly = e / (TX + 2), lx = e - ly * (TX + 2);
+            const int j = r0 - 1 + ly, i = c0 - 1 + lx;
+            const bool in = (j >= 0) && (j < d.rows) && (i >= 0) && (i < P);
+            const size_t k = in ? (size_t)j * P + i : 0;
+            double xv = x[k];
+            const double di = c.dinv[k];
+            if (PROLONG) {
+                const size_t kc = (size_t)((j + 1) >> 1) * cpitch + ((i + 1) >> 1);
+                const double e2 = xc[in ? kc : 0];
+                xv += (di > 0.0) ? e2 : 0.0;
+            }
+            sx[ly][lx] = (in && di > 0.0) ? xv : 0.0;
+        }
+        __syncthreads();
+        const int i = c0 + tx;
+        for (int lj = ty; lj < PTY; lj += 4) {
+            const int j = r0 + lj;
+            if (j < d.rows) {
+                const size_t k = (size_t)j * P + i;
+                const size_t kw = i > 0 ? k - 1 : k, ks = j > 0 ? k - P : k;
+                const double dv = c.dinv[k], bv = b[k];
+                const double ce = c.cx[k], cw = c.cx[kw], cn = c.cy[k], cs = c.cy[ks];
+                const double xcv = sx[lj + 1][tx + 1];
+                const double Ax = (ce + cw + cn + cs) * xcv - ce * sx[lj + 1][tx + 2] - cw * sx[lj + 1][tx] -
+                                  cn * sx[lj + 2][tx + 1] - cs * sx[lj][tx + 1];
+                const double z = dv > 0.0 ? xcv + omega * dv * (bv - Ax) : 0.0;
+                xn[k] = z;
+                if (STATS) {
+                    v[0] += bv * z;
+                    v[1] += z;
+                    v[2] += bv;
+                    v[3] += bv * bv;
+                }
+            }
+        }
+        __syncthreads();
+    });
+    if (STATS) put_partials<4>(v, pout, d.nblk);
+}
+
+// b_coarse = R (b - A x): the residual summed over the active children.
+__global__ __launch_bounds__(NT) void k_mg_restrict(Dims dcrs, int fpitch, int fnx, int fny, PoisCoef f,
+                                                   const double *__restrict__ bf, const double *__restrict__ xf,
+                                                   const double *__restrict__ dinvc, double *__restrict__ bc) {
+    const size_t P = fpitch;
+    for_cells(dcrs, [&](int, int J, int I, size_t kc) {
+        double sum = 0.0;
+        if (I >= 1 && I <= dcrs.nx && J >= 1 && J <= dcrs.ny) {
+#pragma unroll
+            for (int dj = 0; dj < 2; ++dj)
+#pragma unroll
+                for (int di2 = 0; di2 < 2; ++di2) {
+                    const int j = 2 * J - 1 + dj, i = 2 * I - 1 + di2;
+                    if (j > fny || i > fnx) continue;
+                    const size_t k = (size_t)j * P + i;
+                    if (!(f.dinv[k] > 0.0)) continue;
+                    const double ce = f.cx[k], cw = f.cx[k - 1], cn = f.cy[k], cs = f.cy[k - P];
+                    const double Ax = (ce + cw + cn + cs) * xf[k] - ce * xf[k + 1] - cw * xf[k - 1] -
+                                      cn * xf[k + P] - cs * xf[k - P];
+                    sum += bf[k] - Ax;
+                }
+        }
+        bc[kc] = dinvc[kc] > 0.0 ? sum : 0.0;
+    });
+}
+
+// Coarsest grid: x = A^+ b with the dense pseudo-inverse on the n unknowns.
+__global__ __launch_bounds__(NT) void k_mg_coarsest(int n, const int *__restrict__ idx,
+                                                    const double *__restrict__ pinv, const double *__restrict__ b,
+                                                    double *__restrict__ x) {
+    __shared__ double sb[1024];
+    for (int i = threadIdx.x; i < n; i += NT) sb[i] = b[idx[i]];
+    __syncthreads();
+    for (int i = threadIdx.x; i < n; i += NT) {
+        double acc = 0.0;
+        for (int j2 = 0; j2 < n; ++j2) acc += pinv[(size_t)i * n + j2] * sb[j2];
+        x[idx[i]] = acc;
+    }
+}
+
+// Direction and operator for the multigrid-preconditioned solve:
+// p = (z - mean z) + beta p_old; q = A p.  Consumes the statistics written by
+// the last smoothing sweep (and, on the first iteration, |f|^2 from init).
+__global__ __launch_bounds__(NT) void k_pois_dir_z(Dims d, PoisCoef pc, const double *__restrict__ z,
+                                                   const double *__restrict__ pold, double *__restrict__ pnew,
+                                                   double *__restrict__ q, CgState *st, int first, int par,
+                                                   const double *pin, int nin, const double *pinit, int ninit,
+                                                   double *pout) {
+    if (st->done) return;
+    double t[4];
+    get_totals<4>(pin, nin, t);
+    double fn2;
+    if (first) {
+        double f[1];
+        get_totals<1>(pinit, ninit, f);
+        fn2 = f[0];
+    } else {
+        fn2 = st->fnorm2;
+    }
+    const DirStep ds = cg_decide(st, first, par, fn2, t[0], t[1], t[2], t[3]);
+    if (ds.stop) return;
+    const double beta = ds.beta, m = ds.mean;
+    __shared__ double sp[PTY + 2][TX + 2];
+    const int P = d.pitch;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    double v[1] = {0.0};
+    for_tiles(d, [&](int, int c0, int r0) {
+        for (int e = threadIdx.x; e < (PTY + 2) * (TX + 2); e += NT) {
+            const int ly = e / (TX + 2), lx = e - ly * (TX + 2);
+            const int j = r0 - 1 + ly, i = c0 - 1 + lx;
+            const bool in = (j >= 0) && (j < d.rows) && (i >= 0) && (i < P);
+            const size_t k = in ? (size_t)j * P + i : 0;
+            const double di = pc.dinv[k], zv = z[k], po = pold[k];
+            sp[ly][lx] = (in && di > 0.0) ? (zv - m) + beta * po : 0.0;
+        }
+        __syncthreads();
+        const int i = c0 + tx;
+        for (int lj = ty; lj < PTY; lj += 4) {
+            const int j = r0 + lj;
+            if (j < d.rows) {
+                const size_t k = (size_t)j * P + i;
+                const size_t kw = i > 0 ? k - 1 : k, ks = j > 0 ? k - P : k;
+                const double dv = pc.dinv[k], ce = pc.cx[k], cw = pc.cx[kw], cn = pc.cy[k], cs = pc.cy[ks];
+                const double pcv = sp[lj + 1][tx + 1];
+                double qv = (ce + cw + cn + cs) * pcv - ce * sp[lj + 1][tx + 2] - cw * sp[lj + 1][tx] -
+                            cn * sp[lj + 2][tx + 1] - cs * sp[lj][tx + 1];
+                qv = dv > 0.0 ? qv : 0.0;
+                pnew[k] = pcv;
+                q[k] = qv;
+                v[0] += pcv * qv;
+            }
+        }
+        __syncthreads();
+    });
+    put_partials<1>(v, pout, d.nblk);
+}
+
+// ---------------------------------------------------------------------------
 // predictor (eq:pm_prediction): H = (rho/tau) V - mu visc(strain(., 0))
 // ---------------------------------------------------------------------------
 
@@ -565,6 +732,7 @@ enum Arr {
     A_PQX, A_PQY,    // predictor q
     A_RHSX, A_RHSY,  // predictor right-hand side
     A_B, A_R, A_P0, A_P1, A_Q,  // Poisson
+    A_Z, A_ZT,                  // multigrid output and its ping-pong partner
     A_T0, A_T1, A_T2, A_T3,     // scratch for operator applies
     A_COUNT
 };
@@ -572,13 +740,28 @@ enum Arr {
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 // Partial-sum buffers: each holds up to 8 slots of NBMAX groups.
-enum Part { PB_RHS, PB_INIT, PB_DIR, PB_UPD, PB_DIAG, PB_COUNT };
+enum Part { PB_RHS, PB_INIT, PB_DIR, PB_UPD, PB_DIAG, PB_MG, PB_COUNT };
 constexpr int TY = 8;   // tile rows of the face kernels and simple cell kernels
+
+// Multigrid levels: grid sizes from the fine one by halving (rounding up)
+// until both sides are at most 16 cells.
+std::vector<std::pair<int, int>> mg_sizes(int nx, int ny) {
+    std::vector<std::pair<int, int>> v{{nx, ny}};
+    while (v.back().first > 16 || v.back().second > 16)
+        v.push_back({(v.back().first + 1) / 2, (v.back().second + 1) / 2});
+    return v;
+}
+constexpr int MG_ARRS = 6;  // cx, cy, dinv, b, x, xt per coarse level
 
 struct WsPlan {
     Layout L;
     size_t arr_bytes;   // bytes per array
-    size_t part_off, part_bytes, state_off, total;
+    size_t part_off, part_bytes, state_off;
+    std::vector<Layout> mgL;       // coarse levels (index 1..)
+    std::vector<size_t> mg_off;    // byte offset of each coarse level's arrays
+    size_t pinv_off, idx_off;      // coarsest-grid pseudo-inverse and unknown list
+    int ncoarse;                   // cells of the coarsest grid
+    size_t total;
 };
 
 WsPlan plan(int nx, int ny) {
@@ -588,7 +771,22 @@ WsPlan plan(int nx, int ny) {
     w.part_off = w.arr_bytes * A_COUNT;
     w.part_bytes = align_up((size_t)NBMAX * 8 * sizeof(double), 256);
     w.state_off = w.part_off + w.part_bytes * PB_COUNT;
-    w.total = w.state_off + 4096;
+    size_t off = w.state_off + 4096;
+    auto sizes = mg_sizes(nx, ny);
+    w.mgL.push_back(w.L);
+    w.mg_off.push_back(0);
+    for (size_t l = 1; l < sizes.size(); ++l) {
+        Layout Lc = make_layout(sizes[l].first, sizes[l].second);
+        w.mgL.push_back(Lc);
+        w.mg_off.push_back(off);
+        off += MG_ARRS * align_up(Lc.n * sizeof(double), 256);
+    }
+    w.ncoarse = sizes.back().first * sizes.back().second;
+    w.pinv_off = off;
+    off += align_up((size_t)w.ncoarse * w.ncoarse * sizeof(double), 256);
+    w.idx_off = off;
+    off += align_up((size_t)w.ncoarse * sizeof(int), 256);
+    w.total = off;
     return w;
 }
 
@@ -613,6 +811,16 @@ struct ccns_ctx {
     int last_pois_it, last_pred_it;
     int pbuf_pred, pbuf_pois;
     int init_nblk;      // groups of the last init kernel (its partials feed the first direction)
+    // multigrid hierarchy (level 0 shares the Poisson arrays)
+    struct Level {
+        Layout L;
+        Dims d;      // PTY-row tiles
+        double *cx, *cy, *dinv, *b, *x, *xt;
+    };
+    std::vector<Level> mg;
+    double *pinv;
+    int *pidx;
+    int ncoarse_act;
     // optional kernel timing: events around every 4th CG iteration
     int timing;
     std::vector<hipEvent_t> evpool;
@@ -785,6 +993,172 @@ ccns_status pressure_solve_dev(ccns_ctx *c, int nin, ccns_solve_info *info) {
                    c->last_pois_it, dir, info, 0);
 }
 
+constexpr int MG_NU = 2;          // pre- and post-smoothing sweeps
+constexpr double MG_OMEGA = 0.8;  // weighted-Jacobi damping
+
+// Builds the coarse levels on the host from the fine Poisson weights and
+// uploads them; the coarsest grid gets a dense pseudo-inverse.
+ccns_status mg_setup(ccns_ctx *c, const HostCoef &hc) {
+    const WsPlan &w = c->w;
+    c->mg.clear();
+    ccns_ctx::Level l0;
+    l0.L = w.L;
+    l0.d = make_dims(w.L, 1, PTY);
+    l0.cx = c->a[A_CX];
+    l0.cy = c->a[A_CY];
+    l0.dinv = c->a[A_DINV];
+    l0.b = c->a[A_R];
+    l0.x = c->a[A_Z];
+    l0.xt = c->a[A_ZT];
+    c->mg.push_back(l0);
+    std::vector<double> cx = hc.cx, cy = hc.cy, dinv = hc.dinv;
+    int nx = c->g.nx, ny = c->g.ny;
+    for (size_t l = 1; l < w.mgL.size(); ++l) {
+        const Layout &Lc = w.mgL[l];
+        std::vector<double> cxc, cyc, dic;
+        coarsen_poisson(nx, ny, cx, cy, dinv, Lc.nx, Lc.ny, cxc, cyc, dic);
+        ccns_ctx::Level lv;
+        lv.L = Lc;
+        lv.d = make_dims(Lc, 1, PTY);
+        const size_t ab = align_up(Lc.n * sizeof(double), 256);
+        char *base = c->base + w.mg_off[l];
+        double **dst[MG_ARRS] = {&lv.cx, &lv.cy, &lv.dinv, &lv.b, &lv.x, &lv.xt};
+        for (int k = 0; k < MG_ARRS; ++k) *dst[k] = (double *)(base + k * ab);
+        const size_t Wc = Lc.nx + 2;
+        const std::vector<double> *src[3] = {&cxc, &cyc, &dic};
+        double *dd[3] = {lv.cx, lv.cy, lv.dinv};
+        for (int k = 0; k < 3; ++k)
+            HIPCHK(c, hipMemcpy2DAsync(dd[k], Lc.pitch * sizeof(double), src[k]->data(), Wc * sizeof(double),
+                                       Wc * sizeof(double), Lc.ny + 2, hipMemcpyHostToDevice, c->stream));
+        c->mg.push_back(lv);
+        cx.swap(cxc);
+        cy.swap(cyc);
+        dinv.swap(dic);
+        nx = Lc.nx;
+        ny = Lc.ny;
+    }
+    // coarsest grid: dense operator on its unknowns and its pseudo-inverse
+    const Layout &Lc = c->mg.back().L;
+    const size_t Wc = nx + 2;
+    std::vector<int> idx, pos((size_t)(ny + 2) * Wc, -1);
+    for (int j = 1; j <= ny; ++j)
+        for (int i = 1; i <= nx; ++i)
+            if (dinv[(size_t)j * Wc + i] > 0.0) {
+                pos[(size_t)j * Wc + i] = (int)idx.size();
+                idx.push_back(j * Lc.pitch + i);
+            }
+    const int n = (int)idx.size();
+    if (n > 1024) return fail(c, CCNS_EINVAL, "coarsest multigrid grid too large");
+    std::vector<double> A((size_t)n * n, 0.0);
+    for (int j = 1; j <= ny; ++j)
+        for (int i = 1; i <= nx; ++i) {
+            const size_t k = (size_t)j * Wc + i;
+            const int r = pos[k];
+            if (r < 0) continue;
+            const double ce = cx[k], cw = cx[k - 1], cn = cy[k], cs = cy[k - Wc];
+            A[(size_t)r * n + r] = ce + cw + cn + cs;
+            if (ce > 0 && pos[k + 1] >= 0) A[(size_t)r * n + pos[k + 1]] = -ce;
+            if (cw > 0 && pos[k - 1] >= 0) A[(size_t)r * n + pos[k - 1]] = -cw;
+            if (cn > 0 && pos[k + Wc] >= 0) A[(size_t)r * n + pos[k + Wc]] = -cn;
+            if (cs > 0 && pos[k - Wc] >= 0) A[(size_t)r * n + pos[k - Wc]] = -cs;
+        }
+    std::vector<double> Pinv = pseudo_inverse_spsd(A, n);
+    c->pinv = (double *)(c->base + w.pinv_off);
+    c->pidx = (int *)(c->base + w.idx_off);
+    c->ncoarse_act = n;
+    if (n > 0) {
+        HIPCHK(c, hipMemcpyAsync(c->pinv, Pinv.data(), Pinv.size() * sizeof(double), hipMemcpyHostToDevice,
+                                 c->stream));
+        HIPCHK(c, hipMemcpyAsync(c->pidx, idx.data(), idx.size() * sizeof(int), hipMemcpyHostToDevice, c->stream));
+    }
+    // the host vectors above are released when this returns: wait for the copies
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return CCNS_OK;
+}
+
+// z = V(b) on level l; returns the array holding the result.  On level 0 the
+// last sweep also writes the residual statistics into PB_MG.
+double *vcycle(ccns_ctx *c, size_t l, const double *b) {
+    ccns_ctx::Level &L = c->mg[l];
+    hipStream_t s = c->stream;
+    if (l + 1 == c->mg.size()) {
+        k_mg_coarsest<<<1, NT, 0, s>>>(c->ncoarse_act, c->pidx, c->pinv, b, L.x);
+        return L.x;
+    }
+    PoisCoef pc{L.cx, L.cy, L.dinv};
+    double *cur = L.x, *oth = L.xt;
+    k_mg_first<<<L.d.nblk, NT, 0, s>>>(L.d, L.dinv, b, cur, MG_OMEGA);
+    for (int k = 1; k < MG_NU; ++k) {
+        k_mg_smooth<false, false><<<L.d.nblk, NT, 0, s>>>(L.d, pc, b, cur, nullptr, 0, oth, MG_OMEGA, nullptr);
+        std::swap(cur, oth);
+    }
+    ccns_ctx::Level &C = c->mg[l + 1];
+    k_mg_restrict<<<C.d.nblk, NT, 0, s>>>(C.d, L.L.pitch, L.L.nx, L.L.ny, pc, b, cur, C.dinv, C.b);
+    const double *xc = vcycle(c, l + 1, C.b);
+    for (int k = 0; k < MG_NU; ++k) {
+        const bool last = (k == MG_NU - 1) && l == 0;
+        double *po = c->part[PB_MG];
+        if (k == 0 && last)
+            k_mg_smooth<true, true><<<L.d.nblk, NT, 0, s>>>(L.d, pc, b, cur, xc, C.L.pitch, oth, MG_OMEGA, po);
+        else if (k == 0)
+            k_mg_smooth<true, false><<<L.d.nblk, NT, 0, s>>>(L.d, pc, b, cur, xc, C.L.pitch, oth, MG_OMEGA, po);
+        else if (last)
+            k_mg_smooth<false, true><<<L.d.nblk, NT, 0, s>>>(L.d, pc, b, cur, nullptr, 0, oth, MG_OMEGA, po);
+        else
+            k_mg_smooth<false, false><<<L.d.nblk, NT, 0, s>>>(L.d, pc, b, cur, nullptr, 0, oth, MG_OMEGA, po);
+        std::swap(cur, oth);
+    }
+    return cur;
+}
+
+// Multigrid-preconditioned CG for the pressure; b is in A_B with its sum's
+// partials in PB_RHS (nin groups); the start value is A_PHI.
+ccns_status pressure_solve_mg(ccns_ctx *c, int nin, ccns_solve_info *info) {
+    PoisCoef pc = pois_coef(c);
+    const Dims &dp = c->dp;
+    k_pois_init<<<c->dc.nblk, NT, 0, c->stream>>>(c->dc, pc, c->a[A_B], c->a[A_PHI], c->a[A_R], c->st_pois,
+                                                  c->part[PB_RHS], nin, c->part[PB_INIT]);
+    const int ninit = c->dc.nblk;
+    const size_t ntot = c->w.L.n;
+    const int nl = flat_blocks(ntot);
+    double *pb[2] = {c->a[A_P0], c->a[A_P1]};
+    int &pbuf = c->pbuf_pois;
+    double *z = vcycle(c, 0, c->a[A_R]);
+    int chunk = std::max(4, (int)(0.9 * c->last_pois_it));
+    int it = 0;
+    for (;;) {
+        for (int u = 0; u < chunk; ++u, ++it) {
+            const int par = it & 1;
+            const bool tm = c->timing && (it % 2 == 0) && it < c->last_pois_it;
+            if (tm) (void)hipEventRecord(next_event(c), c->stream);
+            k_pois_dir_z<<<dp.nblk, NT, 0, c->stream>>>(dp, pc, z, pb[pbuf], pb[pbuf ^ 1], c->a[A_Q], c->st_pois,
+                                                        it == 0 ? 1 : 0, par, c->part[PB_MG], dp.nblk,
+                                                        c->part[PB_INIT], ninit, c->part[PB_DIR]);
+            if (tm) (void)hipEventRecord(next_event(c), c->stream);
+            k_cg_update<<<nl, NT, 0, c->stream>>>(ntot, nl, c->a[A_DINV], c->a[A_PHI], c->a[A_R], pb[pbuf ^ 1],
+                                                  c->a[A_Q], c->st_pois, par, c->part[PB_DIR], dp.nblk,
+                                                  c->part[PB_UPD]);
+            if (tm) (void)hipEventRecord(next_event(c), c->stream);
+            pbuf ^= 1;
+            z = vcycle(c, 0, c->a[A_R]);
+        }
+        HIPCHK(c, hipGetLastError());
+        HIPCHK(c, hipMemcpyAsync(c->h_st, c->st_pois, sizeof(CgState), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        if (c->timing) harvest_events(c, 0);
+        if (c->h_st->done) break;
+        chunk = 4;
+    }
+    c->last_pois_it = c->h_st->it_final;
+    if (info) {
+        info->iterations = c->h_st->it_final;
+        info->outer = 1;
+        info->rel_residual = c->h_st->fnorm2 > 0 ? std::sqrt(c->h_st->rnorm2_final / c->h_st->fnorm2) : 0.0;
+        info->status = c->h_st->status;
+    }
+    return (ccns_status)c->h_st->status;
+}
+
 ccns_status predict_dev(ccns_ctx *c, ccns_solve_info *info) {
     PredCoef pc = pred_coef(c);
     k_pred_rhs<<<c->df.nblk, NT, 0, c->stream>>>(c->df, pc, c->a[A_AX], c->a[A_AY], c->a[A_HBX], c->a[A_HBY],
@@ -833,7 +1207,8 @@ ccns_status correct_dev(ccns_ctx *c, int update_p, ccns_step_info *info) {
                                                  c->a[A_USY], c->a[A_B], c->prm.rho / c->prm.tau,
                                                  c->part[PB_RHS]);
     ccns_solve_info si{};
-    ccns_status s = pressure_solve_dev(c, c->dc.nblk, &si);
+    ccns_status s = c->prm.precond == 1 ? pressure_solve_mg(c, c->dc.nblk, &si)
+                                        : pressure_solve_dev(c, c->dc.nblk, &si);
     if (info) info->poisson = si;
     k_correct<<<c->dc.nblk, NT, 0, c->stream>>>(c->dc, c->a[A_GX], c->a[A_GY], c->a[A_USX], c->a[A_USY],
                                                 c->a[A_PHI], c->a[A_UX], c->a[A_UY], c->prm.tau / c->prm.rho);
@@ -860,7 +1235,7 @@ ccns_status ccns_ctx_create(const ccns_grid *grid, const ccns_params *params, co
     if (!out) return CCNS_EINVAL;
     *out = nullptr;
     if (!grid || !params || !caps_host || !dirichlet_host || !dev_workspace) return CCNS_EINVAL;
-    if (params->precision != 0) return CCNS_EINVAL;
+    if (params->precision != 0 || params->precond < 0 || params->precond > 1) return CCNS_EINVAL;
     ccns_ctx *c = new (std::nothrow) ccns_ctx();
     if (!c) return CCNS_ENOMEM;
     c->g = *grid;
@@ -923,6 +1298,10 @@ ccns_status ccns_ctx_create(const ccns_grid *grid, const ccns_params *params, co
     // state: U = D everywhere (the caller sets the initial field), P = Phi = 0
     to_dev(c, c->a[A_UX], hc.dx.data(), hipMemcpyHostToDevice);
     to_dev(c, c->a[A_UY], hc.dy.data(), hipMemcpyHostToDevice);
+    if (params->precond == 1 && (s = mg_setup(c, hc)) != CCNS_OK) {
+        ccns_ctx_destroy(c);
+        return s;
+    }
     set_cg(c, c->st_pred, params->pred_tol, params->pred_maxit, 0, hc.n_uact + hc.n_vact);
     set_cg(c, c->st_pois, params->pcg_tol, params->pcg_maxit, 1, hc.n_active);
     if (hipStreamSynchronize(c->stream) != hipSuccess) {
@@ -1013,7 +1392,7 @@ ccns_status ccns_pressure_solve(ccns_ctx *c, const double *b, double *phi, ccns_
     ccns_status s = to_dev(c, c->a[A_B], b, hipMemcpyDeviceToDevice);
     if (s != CCNS_OK) return s;
     k_pois_sum<<<c->dc.nblk, NT, 0, c->stream>>>(c->dc, pois_coef(c), c->a[A_B], c->part[PB_RHS]);
-    s = pressure_solve_dev(c, c->dc.nblk, info);
+    s = c->prm.precond == 1 ? pressure_solve_mg(c, c->dc.nblk, info) : pressure_solve_dev(c, c->dc.nblk, info);
     if (phi) {
         ccns_status s2 = from_dev(c, phi, c->a[A_PHI], hipMemcpyDeviceToDevice);
         if (s2 != CCNS_OK) return s2;

@@ -51,6 +51,14 @@ ccns_status prepare_coefficients(const ccns_grid &g, const ccns_params &prm, con
 void host_viscous(const ccns_grid &g, const double *caps, const HostCoef &o, const double *Ux,
                   const double *Uy, std::vector<double> &vx, std::vector<double> &vy);
 
+// One 2x2 agglomeration step of the Poisson weights (multigrid hierarchy).
+void coarsen_poisson(int nx, int ny, const std::vector<double> &cx, const std::vector<double> &cy,
+                     const std::vector<double> &dinv, int nxc, int nyc, std::vector<double> &cxc,
+                     std::vector<double> &cyc, std::vector<double> &dinvc);
+
+// Pseudo-inverse of a small symmetric positive semi-definite matrix.
+std::vector<double> pseudo_inverse_spsd(std::vector<double> A, int n);
+
 }  // namespace ccns
 
 #endif

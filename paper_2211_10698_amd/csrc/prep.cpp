@@ -198,6 +198,110 @@ ccns_status prepare_coefficients(const ccns_grid &g, const ccns_params &prm, con
     return CCNS_OK;
 }
 
+// One multigrid coarsening step (2x2 cell agglomeration) of the Poisson
+// weights: the coarse face weight is half the sum of the fine weights of the
+// two fine faces it covers; a coarse cell is an unknown when one of its
+// children is; faces touching a non-unknown are dropped.
+void coarsen_poisson(int nx, int ny, const std::vector<double> &cx, const std::vector<double> &cy,
+                     const std::vector<double> &dinv, int nxc, int nyc, std::vector<double> &cxc,
+                     std::vector<double> &cyc, std::vector<double> &dinvc) {
+    const size_t W = nx + 2, Wc = nxc + 2, nc = (size_t)(nyc + 2) * Wc;
+    cxc.assign(nc, 0.0);
+    cyc.assign(nc, 0.0);
+    dinvc.assign(nc, 0.0);
+    std::vector<char> act(nc, 0);
+    for (int J = 1; J <= nyc; ++J)
+        for (int I = 1; I <= nxc; ++I) {
+            bool a = false;
+            for (int dj = 0; dj < 2; ++dj)
+                for (int di = 0; di < 2; ++di) {
+                    int j = 2 * J - 1 + dj, i = 2 * I - 1 + di;
+                    if (j <= ny && i <= nx && dinv[(size_t)j * W + i] > 0.0) a = true;
+                }
+            act[(size_t)J * Wc + I] = a;
+        }
+    for (int J = 1; J <= nyc; ++J)
+        for (int I = 0; I <= nxc; ++I) {
+            double sum = 0.0;
+            for (int dj = 0; dj < 2; ++dj) {
+                int j = 2 * J - 1 + dj;
+                if (j <= ny) sum += cx[(size_t)j * W + 2 * I];
+            }
+            size_t k = (size_t)J * Wc + I;
+            cxc[k] = (I + 1 <= nxc + 1 && act[k] && act[k + 1]) ? 0.5 * sum : 0.0;
+        }
+    for (int J = 0; J <= nyc; ++J)
+        for (int I = 1; I <= nxc; ++I) {
+            double sum = 0.0;
+            for (int di = 0; di < 2; ++di) {
+                int i = 2 * I - 1 + di;
+                if (i <= nx) sum += cy[(size_t)(2 * J) * W + i];
+            }
+            size_t k = (size_t)J * Wc + I;
+            cyc[k] = (act[k] && act[k + Wc]) ? 0.5 * sum : 0.0;
+        }
+    for (int J = 1; J <= nyc; ++J)
+        for (int I = 1; I <= nxc; ++I) {
+            size_t k = (size_t)J * Wc + I;
+            double d = cxc[k] + cxc[k - 1] + cyc[k] + cyc[k - Wc];
+            dinvc[k] = (act[k] && d > 0.0) ? 1.0 / d : 0.0;
+        }
+}
+
+// Moore-Penrose pseudo-inverse of a small symmetric positive semi-definite
+// matrix (row-major n x n) by cyclic Jacobi eigenvalue rotations;
+// eigenvalues below 1e-12 of the largest are treated as zero (the constants
+// on each connected set of unknowns span the null space).
+std::vector<double> pseudo_inverse_spsd(std::vector<double> A, int n) {
+    std::vector<double> V((size_t)n * n, 0.0);
+    for (int i = 0; i < n; ++i) V[(size_t)i * n + i] = 1.0;
+    auto a = [&](int i, int j) -> double & { return A[(size_t)i * n + j]; };
+    for (int sweep = 0; sweep < 100; ++sweep) {
+        double off = 0.0, tot = 0.0;
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) {
+                tot += a(i, j) * a(i, j);
+                if (i != j) off += a(i, j) * a(i, j);
+            }
+        if (off <= 1e-30 * tot) break;
+        for (int p = 0; p < n - 1; ++p)
+            for (int q = p + 1; q < n; ++q) {
+                double apq = a(p, q);
+                if (std::fabs(apq) < 1e-300) continue;
+                double theta = (a(q, q) - a(p, p)) / (2.0 * apq);
+                double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
+                double cs = 1.0 / std::sqrt(t * t + 1.0), sn = t * cs;
+                for (int k = 0; k < n; ++k) {
+                    double akp = a(k, p), akq = a(k, q);
+                    a(k, p) = cs * akp - sn * akq;
+                    a(k, q) = sn * akp + cs * akq;
+                }
+                for (int k = 0; k < n; ++k) {
+                    double apk = a(p, k), aqk = a(q, k);
+                    a(p, k) = cs * apk - sn * aqk;
+                    a(q, k) = sn * apk + cs * aqk;
+                }
+                for (int k = 0; k < n; ++k) {
+                    double vkp = V[(size_t)k * n + p], vkq = V[(size_t)k * n + q];
+                    V[(size_t)k * n + p] = cs * vkp - sn * vkq;
+                    V[(size_t)k * n + q] = sn * vkp + cs * vkq;
+                }
+            }
+    }
+    double lmax = 0.0;
+    for (int i = 0; i < n; ++i) lmax = std::max(lmax, std::fabs(a(i, i)));
+    std::vector<double> P((size_t)n * n, 0.0);
+    for (int e = 0; e < n; ++e) {
+        double l = a(e, e);
+        if (!(l > 1e-12 * lmax)) continue;
+        for (int i = 0; i < n; ++i) {
+            double vi = V[(size_t)i * n + e] / l;
+            for (int j = 0; j < n; ++j) P[(size_t)i * n + j] += vi * V[(size_t)j * n + e];
+        }
+    }
+    return P;
+}
+
 // visc(strain(U, D)) with full Dirichlet terms (eq:diag, eq:offdiag, Sec. 4.3)
 // on the host, for the constant boundary contribution of the viscous term.
 void host_viscous(const ccns_grid &g, const double *caps, const HostCoef &o, const double *Ux,
