@@ -373,6 +373,169 @@ __global__ __launch_bounds__(NT) void k_mg_restrict(Dims dcrs, int fpitch, int f
     });
 }
 
+// Fused cycle kernels.  Tiles cover the real cells, starting at cell (1, 1)
+// so that every 2x2 group of children that forms a coarse cell lies inside
+// one tile (64 = 32 coarse columns, 16 = 8 coarse rows).  One tile per
+// work-group.  Values needed beyond the tile are recomputed on a halo in LDS
+// instead of being exchanged through a second kernel.
+constexpr int MTY = 16;
+constexpr int MH = 2;  // halo width
+constexpr int MW = TX + 2 * MH, MHt = MTY + 2 * MH;
+
+struct MgTile {
+    int c0, r0;  // first real cell of the tile
+};
+__device__ inline MgTile mg_tile(int gx) {
+    const int L = logical_group(((gridDim.x + 7) / 8) * 8);
+    MgTile t;
+    t.c0 = 1 + (L % gx) * TX;
+    t.r0 = 1 + (L / gx) * MTY;
+    return t;
+}
+
+// Local Poisson operator on an LDS tile: (A v)(j, i) for tile-local indices.
+struct LdsStencil {
+    const double *cx, *cy, *dinv;
+    int P;
+};
+
+// Two weighted-Jacobi sweeps from a zero guess, the residual, and its
+// restriction: x2 (written to x2out) and b_coarse.
+__global__ __launch_bounds__(NT) void k_mg_down(int nx, int ny, int P, int gx, PoisCoef c,
+                                                const double *__restrict__ b, double *__restrict__ x2out,
+                                                int Pc, int nxc, int nyc, const double *__restrict__ dinvc,
+                                                double *__restrict__ bc, double omega) {
+    __shared__ double s1[MHt][MW];            // first sweep on the 2-ring region
+    __shared__ double s2[MTY + 2][TX + 2];    // second sweep on the 1-ring region
+    __shared__ double sr[MTY][TX];            // residual on the tile
+    const MgTile t = mg_tile(gx);
+    if (t.r0 > ny || t.c0 > nx) return;
+    for (int e = threadIdx.x; e < MHt * MW; e += NT) {
+        const int ly = e / MW, lx = e - ly * MW;
+        const int j = t.r0 - MH + ly, i = t.c0 - MH + lx;
+        const bool in = (j >= 0) && (j <= ny + 1) && (i >= 0) && (i <= nx + 1);
+        const size_t k = in ? (size_t)j * P + i : 0;
+        const double dv = c.dinv[k], bv = b[k];
+        s1[ly][lx] = (in && dv > 0.0) ? omega * dv * bv : 0.0;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < (MTY + 2) * (TX + 2); e += NT) {
+        const int ly = e / (TX + 2), lx = e - ly * (TX + 2);
+        const int j = t.r0 - 1 + ly, i = t.c0 - 1 + lx;
+        const bool in = (j >= 1) && (j <= ny) && (i >= 1) && (i <= nx);
+        const size_t k = in ? (size_t)j * P + i : 0;
+        const double dv = c.dinv[k], bv = b[k];
+        const double ce = c.cx[k], cw = c.cx[in ? k - 1 : 0], cn = c.cy[k], cs = c.cy[in ? k - P : 0];
+        const int y = ly + 1, x = lx + 1;  // position in s1
+        const double xv = s1[y][x];
+        const double Ax = (ce + cw + cn + cs) * xv - ce * s1[y][x + 1] - cw * s1[y][x - 1] - cn * s1[y + 1][x] -
+                          cs * s1[y - 1][x];
+        s2[ly][lx] = (in && dv > 0.0) ? xv + omega * dv * (bv - Ax) : 0.0;
+    }
+    __syncthreads();
+    {
+        const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+        for (int ly = ty; ly < MTY; ly += 4) {
+            const int j = t.r0 + ly, i = t.c0 + tx;
+            const bool in = (j <= ny) && (i <= nx);
+            const size_t k = in ? (size_t)j * P + i : 0;
+            const double dv = c.dinv[k], bv = b[k];
+            const double ce = c.cx[k], cw = c.cx[in ? k - 1 : 0], cn = c.cy[k], cs = c.cy[in ? k - P : 0];
+            const int y = ly + 1, x = tx + 1;
+            const double xv = s2[y][x];
+            const double Ax = (ce + cw + cn + cs) * xv - ce * s2[y][x + 1] - cw * s2[y][x - 1] - cn * s2[y + 1][x] -
+                              cs * s2[y - 1][x];
+            sr[ly][tx] = (in && dv > 0.0) ? bv - Ax : 0.0;
+            if (in) x2out[k] = xv;
+        }
+    }
+    __syncthreads();
+    {
+        // one coarse cell per thread: 32 x 8 coarse cells per tile
+        const int cxl = threadIdx.x & 31, cyl = threadIdx.x >> 5;
+        const int I = (t.c0 + 1) / 2 + cxl, J = (t.r0 + 1) / 2 + cyl;
+        if (I <= nxc && J <= nyc) {
+            const double sum = (sr[2 * cyl][2 * cxl] + sr[2 * cyl][2 * cxl + 1]) +
+                               (sr[2 * cyl + 1][2 * cxl] + sr[2 * cyl + 1][2 * cxl + 1]);
+            const size_t kc = (size_t)J * Pc + I;
+            bc[kc] = dinvc[kc] > 0.0 ? sum : 0.0;
+        }
+    }
+}
+
+// The coarse correction interpolated onto x2, then two weighted-Jacobi
+// sweeps: z.  With STATS, partials of (b.z, z, b, b.b).
+template <bool STATS>
+__global__ __launch_bounds__(NT) void k_mg_up(int nx, int ny, int P, int gx, PoisCoef c, const double *__restrict__ b,
+                                              const double *__restrict__ x2, const double *__restrict__ xc, int Pc,
+                                              double *__restrict__ z, double omega, double *pout, int nblk) {
+    __shared__ double s1[MHt][MW];
+    __shared__ double s2[MTY + 2][TX + 2];
+    const MgTile t = mg_tile(gx);
+    double v[4] = {0, 0, 0, 0};
+    const bool live = !(t.r0 > ny || t.c0 > nx);
+    if (live) {
+        for (int e = threadIdx.x; e < MHt * MW; e += NT) {
+            const int ly = e / MW, lx = e - ly * MW;
+            const int j = t.r0 - MH + ly, i = t.c0 - MH + lx;
+            const bool in = (j >= 1) && (j <= ny) && (i >= 1) && (i <= nx);
+            const size_t k = in ? (size_t)j * P + i : 0;
+            const size_t kc = in ? (size_t)((j + 1) >> 1) * Pc + ((i + 1) >> 1) : 0;
+            const double dv = c.dinv[k], xv = x2[k], ec = xc[kc];
+            s1[ly][lx] = (in && dv > 0.0) ? xv + ec : 0.0;
+        }
+    }
+    __syncthreads();
+    if (live) {
+        for (int e = threadIdx.x; e < (MTY + 2) * (TX + 2); e += NT) {
+            const int ly = e / (TX + 2), lx = e - ly * (TX + 2);
+            const int j = t.r0 - 1 + ly, i = t.c0 - 1 + lx;
+            const bool in = (j >= 1) && (j <= ny) && (i >= 1) && (i <= nx);
+            const size_t k = in ? (size_t)j * P + i : 0;
+            const double dv = c.dinv[k], bv = b[k];
+            const double ce = c.cx[k], cw = c.cx[in ? k - 1 : 0], cn = c.cy[k], cs = c.cy[in ? k - P : 0];
+            const int y = ly + 1, x = lx + 1;
+            const double xv = s1[y][x];
+            const double Ax = (ce + cw + cn + cs) * xv - ce * s1[y][x + 1] - cw * s1[y][x - 1] - cn * s1[y + 1][x] -
+                              cs * s1[y - 1][x];
+            s2[ly][lx] = (in && dv > 0.0) ? xv + omega * dv * (bv - Ax) : 0.0;
+        }
+    }
+    __syncthreads();
+    if (live) {
+        const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+        for (int ly = ty; ly < MTY; ly += 4) {
+            const int j = t.r0 + ly, i = t.c0 + tx;
+            const bool in = (j <= ny) && (i <= nx);
+            const size_t k = in ? (size_t)j * P + i : 0;
+            const double dv = c.dinv[k], bv = b[k];
+            const double ce = c.cx[k], cw = c.cx[in ? k - 1 : 0], cn = c.cy[k], cs = c.cy[in ? k - P : 0];
+            const int y = ly + 1, x = tx + 1;
+            const double xv = s2[y][x];
+            const double Ax = (ce + cw + cn + cs) * xv - ce * s2[y][x + 1] - cw * s2[y][x - 1] - cn * s2[y + 1][x] -
+                              cs * s2[y - 1][x];
+            const double zv = (in && dv > 0.0) ? xv + omega * dv * (bv - Ax) : 0.0;
+            if (in) z[k] = zv;
+            if (STATS && in) {
+                v[0] += bv * zv;
+                v[1] += zv;
+                v[2] += bv;
+                v[3] += bv * bv;
+            }
+        }
+    }
+    if (STATS) put_partials<4>(v, pout, nblk);
+}
+
+// One work-group sums the partials of a producer into a single group's worth
+// (so that consumers read N values instead of N per producer group).
+template <int N>
+__global__ __launch_bounds__(NT) void k_reduce_partials(const double *pin, int nin, double *pout) {
+    double t[N];
+    get_totals<N>(pin, nin, t);
+    if (threadIdx.x < N) pout[threadIdx.x] = t[threadIdx.x];
+}
+
 // Coarsest grid: x = A^+ b with the dense pseudo-inverse on the n unknowns.
 __global__ __launch_bounds__(NT) void k_mg_coarsest(int n, const int *__restrict__ idx,
                                                     const double *__restrict__ pinv, const double *__restrict__ b,
@@ -567,6 +730,110 @@ __global__ __launch_bounds__(NT) void k_pred_dir(Dims d, PredCoef pc, const doub
         }
     });
     put_partials<1>(v, pout, d.nblk);
+}
+
+// Predictor direction and operator, both velocity components of a 64 x 8
+// tile per work-group.  p = M r + beta p_old is staged in LDS on the tile and
+// a one-face halo; the strains of eq:diag / eq:offdiag are formed once per
+// cell and node in LDS; then H p = (rho/tau) V p - mu visc(S) (Sec. 4.3) on
+// the tile.  Partial p.H p per group.
+constexpr int HTY = 8;
+__global__ __launch_bounds__(NT) void k_pred_dir_lds(int nx, int ny, int P, int rows, int gx, int gy, size_t n,
+                                                     PredCoef pc, const double *__restrict__ r,
+                                                     const double *__restrict__ pold, double *__restrict__ pnew,
+                                                     double *__restrict__ q, CgState *st, int first, int par,
+                                                     const double *pin, int nin, double *pout) {
+    if (st->done) return;
+    double fn2, rs, sm, rsum, rr;
+    if (first) {
+        double t[5];
+        get_totals<5>(pin, nin, t);
+        fn2 = t[0]; rs = t[1]; sm = t[2]; rsum = t[3]; rr = t[4];
+    } else {
+        double t[4];
+        get_totals<4>(pin, nin, t);
+        fn2 = st->fnorm2; rs = t[0]; sm = t[1]; rsum = t[2]; rr = t[3];
+    }
+    const DirStep ds = cg_decide(st, first, par, fn2, rs, sm, rsum, rr);
+    if (ds.stop) return;
+    const double beta = ds.beta;
+    __shared__ double spx[HTY + 2][TX + 2], spy[HTY + 2][TX + 2];
+    __shared__ double sxx[HTY][TX + 1], syy[HTY + 1][TX];
+    __shared__ double snx[HTY + 1][TX + 1], sny[HTY + 1][TX + 1];
+    const ViscCoef &c = pc.vc;
+    const int L = logical_group(((gridDim.x + 7) / 8) * 8);
+    const bool live = L < gx * gy;
+    const int c0 = (L % gx) * TX, r0 = (L / gx) * HTY;
+    double v[1] = {0.0};
+    if (live) {
+        // p on the tile and a one-face halo (rows r0-1 .. r0+HTY, cols c0-1 .. c0+TX)
+        for (int e = threadIdx.x; e < (HTY + 2) * (TX + 2); e += NT) {
+            const int ly = e / (TX + 2), lx = e - ly * (TX + 2);
+            const int j = r0 - 1 + ly, i = c0 - 1 + lx;
+            const bool in = (j >= 0) && (j < rows) && (i >= 0) && (i < P);
+            const size_t k = in ? (size_t)j * P + i : 0;
+            const double hx = pc.hdx[k], hy = pc.hdy[k], rx = r[k], ry = r[n + k], ox = pold[k], oy = pold[n + k];
+            spx[ly][lx] = in ? hx * rx + beta * ox : 0.0;
+            spy[ly][lx] = in ? hy * ry + beta * oy : 0.0;
+        }
+    }
+    __syncthreads();
+    if (live) {
+        // S_xx at cells (rows r0.., cols c0 .. c0+TX): x-faces i-1, i
+        for (int e = threadIdx.x; e < HTY * (TX + 1); e += NT) {
+            const int ly = e / (TX + 1), lx = e - ly * (TX + 1);
+            const int j = r0 + ly, i = c0 + lx;
+            const bool in = (j < rows) && (i >= 1) && (i < P);
+            const size_t k = in ? (size_t)j * P + i : 1;
+            const double w = c.wxx[k], be = c.bxx[k], bw = c.bxx[k - 1];
+            sxx[ly][lx] = in ? w * (be * spx[ly + 1][lx + 1] - bw * spx[ly + 1][lx]) : 0.0;
+        }
+        // S_yy at cells (rows r0 .. r0+HTY, cols c0..): y-faces j-1, j
+        for (int e = threadIdx.x; e < (HTY + 1) * TX; e += NT) {
+            const int ly = e / TX, lx = e - ly * TX;
+            const int j = r0 + ly, i = c0 + lx;
+            const bool in = (j >= 1) && (j < rows);
+            const size_t k = in ? (size_t)j * P + i : (size_t)P;
+            const double w = c.wyy[k], bn = c.byy[k], bs = c.byy[k - P];
+            syy[ly][lx] = in ? w * (bn * spy[ly + 1][lx + 1] - bs * spy[ly][lx + 1]) : 0.0;
+        }
+        // node strains (rows r0-1 .. r0+HTY-1, cols c0-1 .. c0+TX-1)
+        for (int e = threadIdx.x; e < (HTY + 1) * (TX + 1); e += NT) {
+            const int ly = e / (TX + 1), lx = e - ly * (TX + 1);
+            const int j = r0 - 1 + ly, i = c0 - 1 + lx;
+            const bool in = (j >= 0) && (j + 1 < rows) && (i >= 0) && (i + 1 < P);
+            const size_t k = in ? (size_t)j * P + i : 0;
+            const double bxn = c.bxy[k + P], bxs = c.bxy[k], bye = c.byx[k + 1], byw = c.byx[k];
+            const double gxv = bxn * spx[ly + 1][lx] - bxs * spx[ly][lx];
+            const double gyv = bye * spy[ly][lx + 1] - byw * spy[ly][lx];
+            const double a = c.nxx[k], b = c.nxy[k], cc = c.nyx[k], dd = c.nyy[k];
+            snx[ly][lx] = in ? 0.5 * (a * gxv + b * gyv) : 0.0;
+            sny[ly][lx] = in ? 0.5 * (cc * gxv + dd * gyv) : 0.0;
+        }
+    }
+    __syncthreads();
+    if (live) {
+        const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+        for (int ly = ty; ly < HTY; ly += 4) {
+            const int j = r0 + ly, i = c0 + tx;
+            if (j >= rows) break;
+            const size_t k = (size_t)j * P + i;
+            const double vu = pc.vu[k], vv = pc.vv[k];
+            const double bxx = c.bxx[k], bxy = c.bxy[k], byy = c.byy[k], byx = c.byx[k];
+            const double px = spx[ly + 1][tx + 1], py = spy[ly + 1][tx + 1];
+            const double kx = bxx * (sxx[ly][tx + 1] - sxx[ly][tx]) + bxy * (snx[ly + 1][tx + 1] - snx[ly][tx + 1]);
+            const double ky = byy * (syy[ly + 1][tx] - syy[ly][tx]) + byx * (sny[ly + 1][tx + 1] - sny[ly + 1][tx]);
+            const double qx = vu > 0.0 ? pc.rt * vu * px - pc.mu * kx : 0.0;
+            const double qy = vv > 0.0 ? pc.rt * vv * py - pc.mu * ky : 0.0;
+            const double pxo = vu > 0.0 ? px : 0.0, pyo = vv > 0.0 ? py : 0.0;
+            pnew[k] = pxo;
+            pnew[n + k] = pyo;
+            q[k] = qx;
+            q[n + k] = qy;
+            v[0] += pxo * qx + pyo * qy;
+        }
+    }
+    put_partials<1>(v, pout, gridDim.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -769,7 +1036,10 @@ WsPlan plan(int nx, int ny) {
     w.L = make_layout(nx, ny);
     w.arr_bytes = align_up(w.L.n * sizeof(double), 256);
     w.part_off = w.arr_bytes * A_COUNT;
-    w.part_bytes = align_up((size_t)NBMAX * 8 * sizeof(double), 256);
+    // partial sums: up to 8 slots for the largest number of work-groups any
+    // kernel launches (one 64 x 8 tile per group)
+    const size_t groups = ((size_t)(w.L.pitch / TX) * ((w.L.rows + 7) / 8) + 7) / 8 * 8;
+    w.part_bytes = align_up(std::max<size_t>(NBMAX, groups) * 8 * sizeof(double), 256);
     w.state_off = w.part_off + w.part_bytes * PB_COUNT;
     size_t off = w.state_off + 4096;
     auto sizes = mg_sizes(nx, ny);
@@ -931,7 +1201,7 @@ template <class Dir>
 ccns_status cg_loop(ccns_ctx *c, CgState *st, double *x, double *r, double *const pbuf[2], int &par_buf, double *q,
                     const double *dinv, size_t ntot, int &last_it, Dir dir, ccns_solve_info *info, int kid) {
     const int nl = flat_blocks(ntot);
-    int chunk = std::max(8, (int)(0.9 * last_it));
+    int chunk = std::max(4, last_it + 1);
     int it = 0;
     bool first = true;
     for (;;) {
@@ -954,7 +1224,7 @@ ccns_status cg_loop(ccns_ctx *c, CgState *st, double *x, double *r, double *cons
         HIPCHK(c, hipStreamSynchronize(c->stream));
         if (c->timing) harvest_events(c, kid);
         if (c->h_st->done) break;
-        chunk = 32;
+        chunk = 8;
     }
     last_it = c->h_st->it_final;
     if (info) {
@@ -1076,8 +1346,9 @@ ccns_status mg_setup(ccns_ctx *c, const HostCoef &hc) {
     return CCNS_OK;
 }
 
-// z = V(b) on level l; returns the array holding the result.  On level 0 the
-// last sweep also writes the residual statistics into PB_MG.
+// z = V(b) on level l; returns the array holding the result.  On level 0
+// the last kernel also writes the residual statistics, reduced to one group
+// in PB_MG.
 double *vcycle(ccns_ctx *c, size_t l, const double *b) {
     ccns_ctx::Level &L = c->mg[l];
     hipStream_t s = c->stream;
@@ -1086,29 +1357,21 @@ double *vcycle(ccns_ctx *c, size_t l, const double *b) {
         return L.x;
     }
     PoisCoef pc{L.cx, L.cy, L.dinv};
-    double *cur = L.x, *oth = L.xt;
-    k_mg_first<<<L.d.nblk, NT, 0, s>>>(L.d, L.dinv, b, cur, MG_OMEGA);
-    for (int k = 1; k < MG_NU; ++k) {
-        k_mg_smooth<false, false><<<L.d.nblk, NT, 0, s>>>(L.d, pc, b, cur, nullptr, 0, oth, MG_OMEGA, nullptr);
-        std::swap(cur, oth);
-    }
+    const int gx = (L.L.nx + TX - 1) / TX, gy = (L.L.ny + MTY - 1) / MTY;
+    const int nb = ((gx * gy + 7) / 8) * 8;
     ccns_ctx::Level &C = c->mg[l + 1];
-    k_mg_restrict<<<C.d.nblk, NT, 0, s>>>(C.d, L.L.pitch, L.L.nx, L.L.ny, pc, b, cur, C.dinv, C.b);
+    k_mg_down<<<nb, NT, 0, s>>>(L.L.nx, L.L.ny, L.L.pitch, gx, pc, b, L.x, C.L.pitch, C.L.nx, C.L.ny, C.dinv, C.b,
+                                MG_OMEGA);
     const double *xc = vcycle(c, l + 1, C.b);
-    for (int k = 0; k < MG_NU; ++k) {
-        const bool last = (k == MG_NU - 1) && l == 0;
-        double *po = c->part[PB_MG];
-        if (k == 0 && last)
-            k_mg_smooth<true, true><<<L.d.nblk, NT, 0, s>>>(L.d, pc, b, cur, xc, C.L.pitch, oth, MG_OMEGA, po);
-        else if (k == 0)
-            k_mg_smooth<true, false><<<L.d.nblk, NT, 0, s>>>(L.d, pc, b, cur, xc, C.L.pitch, oth, MG_OMEGA, po);
-        else if (last)
-            k_mg_smooth<false, true><<<L.d.nblk, NT, 0, s>>>(L.d, pc, b, cur, nullptr, 0, oth, MG_OMEGA, po);
-        else
-            k_mg_smooth<false, false><<<L.d.nblk, NT, 0, s>>>(L.d, pc, b, cur, nullptr, 0, oth, MG_OMEGA, po);
-        std::swap(cur, oth);
+    if (l == 0) {
+        k_mg_up<true><<<nb, NT, 0, s>>>(L.L.nx, L.L.ny, L.L.pitch, gx, pc, b, L.x, xc, C.L.pitch, L.xt, MG_OMEGA,
+                                        c->part[PB_UPD], nb);
+        k_reduce_partials<4><<<1, NT, 0, s>>>(c->part[PB_UPD], nb, c->part[PB_MG]);
+    } else {
+        k_mg_up<false><<<nb, NT, 0, s>>>(L.L.nx, L.L.ny, L.L.pitch, gx, pc, b, L.x, xc, C.L.pitch, L.xt, MG_OMEGA,
+                                         nullptr, nb);
     }
-    return cur;
+    return L.xt;
 }
 
 // Multigrid-preconditioned CG for the pressure; b is in A_B with its sum's
@@ -1124,7 +1387,7 @@ ccns_status pressure_solve_mg(ccns_ctx *c, int nin, ccns_solve_info *info) {
     double *pb[2] = {c->a[A_P0], c->a[A_P1]};
     int &pbuf = c->pbuf_pois;
     double *z = vcycle(c, 0, c->a[A_R]);
-    int chunk = std::max(4, (int)(0.9 * c->last_pois_it));
+    int chunk = std::max(2, c->last_pois_it + 1);
     int it = 0;
     for (;;) {
         for (int u = 0; u < chunk; ++u, ++it) {
@@ -1132,7 +1395,7 @@ ccns_status pressure_solve_mg(ccns_ctx *c, int nin, ccns_solve_info *info) {
             const bool tm = c->timing && (it % 2 == 0) && it < c->last_pois_it;
             if (tm) (void)hipEventRecord(next_event(c), c->stream);
             k_pois_dir_z<<<dp.nblk, NT, 0, c->stream>>>(dp, pc, z, pb[pbuf], pb[pbuf ^ 1], c->a[A_Q], c->st_pois,
-                                                        it == 0 ? 1 : 0, par, c->part[PB_MG], dp.nblk,
+                                                        it == 0 ? 1 : 0, par, c->part[PB_MG], 1,
                                                         c->part[PB_INIT], ninit, c->part[PB_DIR]);
             if (tm) (void)hipEventRecord(next_event(c), c->stream);
             k_cg_update<<<nl, NT, 0, c->stream>>>(ntot, nl, c->a[A_DINV], c->a[A_PHI], c->a[A_R], pb[pbuf ^ 1],
@@ -1147,7 +1410,7 @@ ccns_status pressure_solve_mg(ccns_ctx *c, int nin, ccns_solve_info *info) {
         HIPCHK(c, hipStreamSynchronize(c->stream));
         if (c->timing) harvest_events(c, 0);
         if (c->h_st->done) break;
-        chunk = 4;
+        chunk = 2;
     }
     c->last_pois_it = c->h_st->it_final;
     if (info) {
@@ -1171,10 +1434,15 @@ ccns_status predict_dev(ccns_ctx *c, ccns_solve_info *info) {
                                                   c->part[PB_INIT]);
     c->init_nblk = c->df.nblk;
     double *pb[2] = {c->a[A_PP0X], c->a[A_PP1X]};
+    const Layout &L = c->w.L;
+    const int gx = L.pitch / TX, gy = (L.rows + HTY - 1) / HTY;
+    const int nb = ((gx * gy + 7) / 8) * 8;
     auto dir = [&](int first, int par, double *pold, double *pnew, const double *pin, int nin, double *pout) {
-        k_pred_dir<<<c->df.nblk, NT, 0, c->stream>>>(c->df, pc, c->a[A_PRX], pold, pnew, c->a[A_PQX], c->st_pred,
-                                                     first, par, pin, nin, pout);
-        return c->df.nblk;
+        k_pred_dir_lds<<<nb, NT, 0, c->stream>>>(L.nx, L.ny, L.pitch, L.rows, gx, gy, L.n, pc, c->a[A_PRX], pold,
+                                                 pnew, c->a[A_PQX], c->st_pred, first, par, pin, nin,
+                                                 c->part[PB_RHS]);
+        k_reduce_partials<1><<<1, NT, 0, c->stream>>>(c->part[PB_RHS], nb, pout);
+        return 1;
     };
     return cg_loop(c, c->st_pred, c->a[A_USX], c->a[A_PRX], pb, c->pbuf_pred, c->a[A_PQX], c->a[A_HDX],
                    2 * c->w.L.n, c->last_pred_it, dir, info, 2);
