@@ -9,11 +9,12 @@ the viscous predictor solve, the Poisson right-hand side, the pressure
 solve, the corrector and the pressure update, with the diagnostics.
 
 Prints one JSON line.  `value` is whole-job cell-steps per second (in
-millions) with the state resident in HBM.  `roofline` reports the Poisson
-operator kernel (the dominant kernel): algorithmic bytes per launch over its
-mean duration, timed with HIP events on the library's stream inside the
-timed region.  `cpu_baseline` times the FP64 CPU oracle on a bounded sample
-of the same workload (see its `sample` field).
+millions) with the state resident in HBM.  `roofline` reports the dominant
+kernel, the predictor's direction+operator kernel (k_pred_dir_lds):
+algorithmic bytes per launch over its mean duration, timed with HIP events on
+the library's stream inside the timed region (every 4th launch).
+`cpu_baseline` times the FP64 CPU oracle on a bounded sample of the same
+workload (see its `sample` field).
 """
 
 from __future__ import annotations
@@ -32,16 +33,110 @@ sys.path.insert(0, ROOT)
 import workloads as W  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
-# Poisson operator kernel, FP64: reads r, dinv, p_old, c^x, c^y and writes
-# p, q -- 7 arrays of 8 bytes per cell
-POIS_APPLY_BYTES_PER_CELL = 56.0
-POIS_UPDATE_BYTES_PER_CELL = 56.0   # reads x, p, r, q, dinv; writes x, r
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+DEVICE_SRC = os.path.join(ROOT, "paper_2211_10698_amd", "csrc", "ccns_device.hip")
+KERNEL_HDR = os.path.join(ROOT, "paper_2211_10698_amd", "csrc", "ccns_kern.h")
+# Algorithmic bytes per cell of the timed kernels (FP64 = 8 bytes per value).
+# Predictor direction+operator, per cell = one x-face and one y-face: reads
+# r, p_old, M^-1 (2 components each), V^x, V^y, B^xx, B^xy, B^yy, B^yx,
+# 1/W^xx, 1/W^yy and the four node weights; writes p and H p (2 each).
+PRED_DIR_BYTES_PER_CELL = 22 * 8.0
+# CG update over the two face components: reads M^-1, x, p, r, H p; writes x, r.
+PRED_UPDATE_BYTES_PER_CELL = 2 * 7 * 8.0
+# Poisson direction+operator (multigrid path): reads z, p_old, 1/diag, c^x,
+# c^y; writes p, A p.
+POIS_DIR_BYTES_PER_CELL = 7 * 8.0
 
 WORKLOADS = {
     "channel_cylinder_2048x1024": W.channel_cylinder_2048,
     "cylinder_64": W.cylinder_64,
     "naca0012_4096x2048": W.naca_4096,
 }
+
+
+def kernel_digest(name):
+    """SHA-1 of a kernel's source text (its definition in the device source
+    plus the shared device header), so that stored counter readings are used
+    only while the kernel they were taken on is unchanged."""
+    import hashlib
+    import re
+
+    src = open(DEVICE_SRC).read()
+    m = re.search(r"__global__[^\n]*\b" + re.escape(name) + r"\(.*?\n}\n", src, re.S)
+    if m is None:
+        return None
+    h = hashlib.sha1(m.group(0).encode())
+    h.update(open(KERNEL_HDR, "rb").read())
+    return h.hexdigest()
+
+
+def stored_traffic(name, workload):
+    """HBM bytes per launch of `name` from the committed counter summary, or
+    None when there is none for this workload or the kernel has changed."""
+    try:
+        t = json.load(open(TRAFFIC_FILE)).get(name)
+    except (OSError, ValueError):
+        return None
+    if not t or t.get("workload") != workload or t.get("kernel_sha1") != kernel_digest(name):
+        return None
+    return t["bytes_per_launch"]
+
+
+def summarize_counters(root, kernel, workload):
+    """Turns four rocprofv3 --pmc runs into the stored traffic figure:
+    root/fetch and root/write hold FETCH_SIZE and WRITE_SIZE of the bench
+    run, root/cfetch and root/cwrite the same counters over the plain copies
+    of --calibrate-copy.  Each counter is scaled by (bytes the copy moved) /
+    (what the counter read for it); the result is the median over the
+    kernel's full launches."""
+    import csv
+    import glob
+    import statistics
+
+    def med(sub, pat, counter):
+        vals = []
+        for f in glob.glob(os.path.join(root, sub, "**", "*counter_collection.csv"), recursive=True):
+            for r in csv.DictReader(open(f)):
+                if pat in r["Kernel_Name"] and r["Counter_Name"] == counter:
+                    vals.append(float(r["Counter_Value"]))
+        big = max(vals)
+        vals = [v for v in vals if v > 0.5 * big]   # full launches, not early exits
+        return statistics.median(vals), len(vals)
+
+    copy_kib = CALIB_BYTES / 1024.0
+    cf, _ = med("cfetch", "copyBuffer", "FETCH_SIZE")
+    cw, _ = med("cwrite", "copyBuffer", "WRITE_SIZE")
+    fk, nf = med("fetch", kernel, "FETCH_SIZE")
+    wk, nw = med("write", kernel, "WRITE_SIZE")
+    sf, sw = copy_kib / cf, copy_kib / cw
+    rec = {"workload": workload, "kernel_sha1": kernel_digest(kernel), "fetch_kib": fk, "write_kib": wk,
+           "launches": [nf, nw], "copy_fetch_kib": cf, "copy_write_kib": cw, "fetch_scale": sf,
+           "write_scale": sw, "bytes_per_launch": (fk * sf + wk * sw) * 1024.0}
+    try:
+        data = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        data = {}
+    data[kernel] = rec
+    with open(TRAFFIC_FILE, "w") as f:
+        json.dump(data, f, indent=1)
+        f.write("\n")
+    print(json.dumps({kernel: rec}))
+
+
+CALIB_BYTES = 1 << 30
+
+
+def calibrate_copy(reps=3):
+    """Three device-to-device copies of 1 GiB: the reference reading for the
+    FETCH_SIZE / WRITE_SIZE counters (each copy reads and writes 1 GiB)."""
+    import torch
+
+    a = torch.empty(CALIB_BYTES // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(f"[bench] copied {reps} x {CALIB_BYTES} bytes", flush=True)
 
 
 def unknown_masks(caps, nx, ny):
@@ -55,10 +150,10 @@ def unknown_masks(caps, nx, ny):
 
 
 def cpu_baseline(case, n_cg_per_step, iters_sample=20):
-    """Times the oracle on the host: one full predictor phase plus a fixed
-    number of Poisson PCG iterations, plus the corrector/pressure update of
-    the same workload, then scales to one step with the Poisson iteration
-    count the device needed per step."""
+    """Times the oracle on the host: one full predictor phase, a fixed number
+    of its Poisson PCG (Jacobi) iterations, and the corrector/pressure update
+    of the same workload; the Poisson part is scaled to the number of Jacobi
+    iterations one step of this workload needs (n_cg_per_step)."""
     from oracle import derived, geometry, pmii, solvers
 
     g = case.grid
@@ -87,8 +182,10 @@ def cpu_baseline(case, n_cg_per_step, iters_sample=20):
         "kind": "oracle",
         "sample": (f"one step of the {case.name} workload on the full grid: predictor phase "
                    f"({t1 - t0:.2f} s) and corrector/pressure update ({t3 - t2:.2f} s) timed whole; "
-                   f"{it} Poisson PCG iterations timed ({per_it * 1e3:.1f} ms each) and scaled to the "
-                   f"{n_cg_per_step:.0f} iterations per step the device needed; numpy runs single-threaded"),
+                   f"{it} of the oracle's Jacobi-PCG Poisson iterations timed ({per_it * 1e3:.1f} ms each) "
+                   f"and scaled to {n_cg_per_step:.0f} iterations, the count one step's pressure solve needs "
+                   f"with that algorithm (taken from the library's Jacobi-PCG on the same right-hand side, "
+                   f"which matches the oracle's count within 2); numpy runs single-threaded"),
         "seconds_per_step": step_s,
     }
 
@@ -100,13 +197,24 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="channel_cylinder_2048x1024", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run the plain copies that calibrate the HBM byte counters")
+    ap.add_argument("--summarize-counters", metavar="DIR",
+                    help="store the HBM traffic of the predictor kernel from rocprofv3 counter runs under DIR")
     args = ap.parse_args()
+    if args.summarize_counters:
+        summarize_counters(args.summarize_counters, "k_pred_dir_lds", args.workload)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(independent simulations shard across GPUs without communication).", file=sys.stderr)
         sys.exit(2)
 
     import torch
+
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
     from paper_2211_10698_amd import ccns
 
     case = WORKLOADS[args.workload]()
@@ -154,9 +262,8 @@ def main():
     value = cells * args.steps / elapsed / 1e6
     div_max = max(i["div_rel"] for i in infos)
     n_cg = float(np.mean([i["cg_iters"] for i in infos]))
-    apply_ms = ms[0] / max(cnt[0], 1)
-    upd_ms = ms[1] / max(cnt[1], 1)
-    achieved = POIS_APPLY_BYTES_PER_CELL * cells / (apply_ms * 1e-3) / 1e9
+    mean_us = [ms[k] / max(cnt[k], 1) * 1e3 for k in range(4)]
+    achieved = PRED_DIR_BYTES_PER_CELL * cells / (mean_us[2] * 1e-6) / 1e9
     out = {
         "metric": "Mcell-steps/s at 1e-8 divergence",
         "value": value,
@@ -171,31 +278,49 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": case.name, "nx": g.nx, "ny": g.ny, "re": case.re, "cfl": case.cfl,
-                   "pcg_tol": case.pcg_tol, "precond": "multigrid", "precision": "fp64"},
+                   "pcg_tol": case.pcg_tol, "pred_tol": 1e-12, "precond": "multigrid", "precision": "fp64"},
         "div_rel_max": div_max,
         "cg_iters_per_step": n_cg,
         "pred_iters_per_step": float(np.mean([i["pred_iters"] for i in infos])),
         "roofline": {
-            "kernel": "k_pois_dir_apply",
+            "kernel": "k_pred_dir_lds",
             "bound": "hbm",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
-            "bytes_per_launch": POIS_APPLY_BYTES_PER_CELL * cells,
-            "mean_launch_us": apply_ms * 1e3,
-            "timed_launches": cnt[0],
-            "update_kernel_GBs": POIS_UPDATE_BYTES_PER_CELL * cells / (upd_ms * 1e-3) / 1e9,
-            "update_mean_launch_us": upd_ms * 1e3,
+            "traffic": stored_traffic("k_pred_dir_lds", case.name),
+            "bytes_per_launch": PRED_DIR_BYTES_PER_CELL * cells,
+            "mean_launch_us": mean_us[2],
+            "timed_launches": cnt[2],
+        },
+        "kernels": {
+            "k_pred_dir_lds": {"us": mean_us[2], "GBs": achieved},
+            "pred_reduce+k_cg_update": {"us": mean_us[3],
+                                        "GBs": PRED_UPDATE_BYTES_PER_CELL * cells / (mean_us[3] * 1e-6) / 1e9},
+            "k_pois_dir_z": {"us": mean_us[0],
+                             "GBs": POIS_DIR_BYTES_PER_CELL * cells / (mean_us[0] * 1e-6) / 1e9},
+            "pois_update+vcycle": {"us": mean_us[1]},
         },
         "cpu_baseline": None,
     }
     if div_max > 1e-8:
         out["warning"] = "divergence above 1e-8 in a timed step"
     if not args.no_cpu_baseline:
-        print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
-        cb = cpu_baseline(case, n_cg)
+        # the oracle solves the pressure with Jacobi-PCG: count the iterations
+        # that algorithm needs on this step's right-hand side (library, same
+        # algorithm as the oracle), to scale the oracle's timed sample
+        pj = ccns.make_params(case.rho, case.mu, case.tau, u_ref=case.u_inf, pcg_tol=case.pcg_tol,
+                              precond=ccns.PRECOND_JACOBI)
+        cj = ccns.Context(g, pj, caps, Dx, Dy, stream=stream)
+        phi_prev = ctx.get_field(ccns.F_PHI)
+        ctx.step(1)                      # one more (untimed) step: its warm start and right-hand side
+        cj.set_field(ccns.F_PHI, phi_prev)
+        _, jinfo, _ = cj.pressure_solve(ctx.get_field(ccns.F_B), check=False)
+        n_jac = jinfo.iterations
+        cj.close()
+        print(f"[bench] cpu baseline (oracle), Jacobi iterations per step {n_jac} ...", file=sys.stderr, flush=True)
+        cb = cpu_baseline(case, n_jac)
         out["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample")}
     print(json.dumps(out), flush=True)
 

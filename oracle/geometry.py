@@ -190,7 +190,8 @@ def sign_change_roots(f, a, b, n=16):
     """Sorted points in (a, b) where f changes between positive and
     non-positive.  f is vectorised.  Sign changes between samples are
     bracketed; a pair of roots hidden between samples is looked for near
-    every local minimum of |f| by a bounded golden-section search."""
+    every local minimum of |f| by repeated zooming (33 samples a level)
+    towards the extremum."""
     if b <= a:
         return []
     s = np.linspace(a, b, n + 1)
@@ -214,27 +215,25 @@ def sign_change_roots(f, a, b, n=16):
             continue
         if av[k] > av[lo] or av[k] > av[hi]:
             continue
-        # golden-section search for the extremum of f towards zero on [s_lo, s_hi]
+        if av[k] == av[lo] and av[k] == av[hi]:
+            continue            # flat: no dip between the samples to search
+        # zoom towards the extremum of f nearest zero on [s_lo, s_hi]: sample
+        # 33 points, keep the two sample intervals around the best one, repeat
         sg = 1.0 if pos[k] else -1.0
         xl, xh = float(s[lo]), float(s[hi])
-        gr = 0.5 * (math.sqrt(5.0) - 1.0)
-        c = xh - gr * (xh - xl)
-        d = xl + gr * (xh - xl)
-        fc, fd = sg * g(c), sg * g(d)
-        for _ in range(80):
-            if fc < fd:
-                xh, d, fd = d, c, fc
-                c = xh - gr * (xh - xl)
-                fc = sg * g(c)
-            else:
-                xl, c, fc = c, d, fd
-                d = xl + gr * (xh - xl)
-                fd = sg * g(d)
+        xm = None
+        for _ in range(16):
+            t = np.linspace(xl, xh, 33)
+            ft = f(t)
+            flip = (ft > 0.0) != pos[k]
+            if flip.any():
+                xm = float(t[int(np.argmax(flip))])
+                break
+            m = int(np.argmin(sg * ft))
+            xl, xh = float(t[max(m - 1, 0)]), float(t[min(m + 1, 32)])
             if xh - xl < 1e-15 * max(1.0, abs(xh)):
                 break
-        xm = 0.5 * (xl + xh)
-        fm = g(xm)
-        if (fm > 0.0) != pos[k]:
+        if xm is not None:
             roots.append(brentq(g, float(s[lo]), xm, xtol=1e-16, rtol=8.9e-16, maxiter=200))
             roots.append(brentq(g, xm, float(s[hi]), xtol=1e-16, rtol=8.9e-16, maxiter=200))
     roots = sorted(r for r in roots if a < r < b)

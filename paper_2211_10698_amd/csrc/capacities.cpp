@@ -6,12 +6,14 @@
 // Every capacity is an integral of the fluid characteristic function over an
 // axis-aligned rectangle or segment.  Segments: the fluid intervals of a line
 // are found from sign changes of the level set on 16 samples, pairs of roots
-// hidden between samples are searched for around each local minimum of |phi|,
-// and roots are refined by bisection.  Rectangles: the wet length of the
+// hidden between samples are searched for around each local minimum of |phi|
+// (by zooming towards the extremum), and roots are refined by bisection.  Rectangles: the wet length of the
 // vertical line through x (and its first moment in y) is integrated over x by
 // adaptive Gauss-Kronrod (7/15 points) after splitting at the points where
-// the interface meets the rectangle's top and bottom edges; vertical tangents
-// of the interface inside are resolved by the adaptive error control.
+// the interface meets the rectangle's top and bottom edges, below the
+// interface's corners (a NACA section's trailing edge) and at vertical
+// tangents (located where the number of crossings of a vertical line
+// changes).
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -90,6 +92,21 @@ struct Fluid {
             y0 = std::min(ya, yb) - ht; y1 = std::max(ya, yb) + ht;
         }
     }
+    // Abscissas of the interface's corners inside [xa, xb] x [ya, yb]: the
+    // two ends of a NACA section's blunt trailing edge.  Elsewhere the
+    // built-in interfaces are smooth.  (A user level set's corners are not
+    // known; adaptive quadrature then has to find them.)
+    void corners(double xa, double xb, double ya, double yb, std::vector<double> &xs) const {
+        for (int k = 0; k < nbody; ++k) {
+            const ccns_body &b = bodies[k];
+            if (b.kind != CCNS_NACA4) continue;
+            double c = std::cos(b.angle), s = std::sin(b.angle), ht = naca_yt(1.0, b.t);
+            for (double eta : {-ht, ht}) {
+                double x = b.cx + b.chord * (c + eta * s), y = b.cy + b.chord * (-s + eta * c);
+                if (x > xa && x < xb && y >= ya && y <= yb) xs.push_back(x);
+            }
+        }
+    }
     // True when the rectangle may contain interface points.
     bool maybe_cut(double xa, double xb, double ya, double yb, double margin) const {
         if (fn) return true;
@@ -131,23 +148,29 @@ int fluid_intervals(const G &g, double a, double b, double *lo, double *hi, int 
         bool p = v[k] > 0.0;
         if ((v[l] > 0.0) != p || (v[r] > 0.0) != p) continue;
         if (std::fabs(v[k]) > std::fabs(v[l]) || std::fabs(v[k]) > std::fabs(v[r])) continue;
-        double sg = p ? 1.0 : -1.0;
-        double xl = s[l], xr = s[r];
-        const double gr = 0.5 * (std::sqrt(5.0) - 1.0);
-        double c = xr - gr * (xr - xl), d = xl + gr * (xr - xl);
-        double fc = sg * g(c), fd = sg * g(d);
+        if (std::fabs(v[k]) == std::fabs(v[l]) && std::fabs(v[k]) == std::fabs(v[r])) continue;  // flat
+        // zoom towards the extremum of g nearest zero: 33 samples a level,
+        // keeping the two sample intervals around the best one (robust when
+        // g has several dips or a kink between the coarse samples)
+        const double sg = p ? 1.0 : -1.0;
+        double xl = s[l], xr = s[r], xm = 0.0;
         bool found = false;
-        double xm = 0.5 * (xl + xr);
-        for (int it = 0; it < 90; ++it) {
-            if (fc <= 0.0) { xm = c; found = true; break; }
-            if (fd <= 0.0) { xm = d; found = true; break; }
-            if (fc < fd) { xr = d; d = c; fd = fc; c = xr - gr * (xr - xl); fc = sg * g(c); }
-            else { xl = c; c = d; fc = fd; d = xl + gr * (xr - xl); fd = sg * g(d); }
+        for (int lev = 0; lev < 16 && !found; ++lev) {
+            const int m = 32;
+            double best = INFINITY;
+            int kb = 0;
+            for (int q = 0; q <= m; ++q) {
+                const double x = (q == m) ? xr : xl + (xr - xl) * q / m;
+                const double gv = g(x);
+                if ((gv > 0.0) != p) { xm = x; found = true; break; }
+                if (sg * gv < best) { best = sg * gv; kb = q; }
+            }
+            if (found) break;
+            const double nl = xl + (xr - xl) * std::max(kb - 1, 0) / m;
+            const double nr = (kb + 1 >= m) ? xr : xl + (xr - xl) * (kb + 1) / m;
+            xl = nl;
+            xr = nr;
             if (xr - xl < 1e-15 * std::max(1.0, std::fabs(xr))) break;
-        }
-        if (!found) {
-            xm = 0.5 * (xl + xr);
-            found = (g(xm) > 0.0) != p;
         }
         if (found && nr < 62) {
             roots[nr++] = bisect(s[l], xm);
@@ -218,6 +241,8 @@ class Integrator {
                 if (hi[k] < xb) pts.push_back(hi[k]);
             }
         }
+        // the wet length has a kink below each corner of the interface
+        f_.corners(xa, xb, ya, yb, pts);
         std::sort(pts.begin(), pts.end());
         // Vertical tangents of the interface change the number of roots on a
         // vertical line.  Probe that count on a uniform grid and just beside
@@ -301,9 +326,14 @@ class Integrator {
         Moments k;
         double e = panel(p, q, ya, yb, k);
         // the estimate itself carries rounding of about 1e-16 of the panel
-        // integral: never ask for less than a few hundred ulps of it
+        // integral: never ask for less than a few hundred ulps of it.  Next to
+        // a vertical tangent the wet length is only known to the rounding of
+        // the level set (the root pair there is ill-conditioned), so the
+        // estimate stays above any tolerance on a band about 1e-13 wide: stop
+        // halving at 2^-30 of the rectangle, where such a panel's whole
+        // integral is below 1e-9 of the rectangle's and its error far below.
         const double floor_ = 256.0 * 2.2e-16 * (q - p) * (yb - ya);
-        if (e <= std::max(tol, floor_) || depth >= 40 || q - p < 1e-15 * std::max(1.0, std::fabs(q))) return k;
+        if (e <= std::max(tol, floor_) || depth >= 30 || q - p < 1e-15 * std::max(1.0, std::fabs(q))) return k;
         double m = 0.5 * (p + q);
         Moments l = adapt(p, m, ya, yb, 0.5 * tol, depth + 1);
         Moments r = adapt(m, q, ya, yb, 0.5 * tol, depth + 1);

@@ -288,91 +288,6 @@ __global__ __launch_bounds__(NT) void k_cg_update(size_t ntot, int nblk, const d
 // iteration requires.
 // ---------------------------------------------------------------------------
 
-// x = omega D^-1 b: the first sweep from a zero initial guess.
-__global__ __launch_bounds__(NT) void k_mg_first(Dims d, const double *__restrict__ dinv,
-                                                 const double *__restrict__ b, double *__restrict__ x, double omega) {
-    for_cells(d, [&](int, int, int, size_t k) { x[k] = omega * dinv[k] * b[k]; });
-}
-
-// x_new = x' + omega D^-1 (b - A x') with x' = x (+ the interpolated coarse
-// correction when PROLONG).  With STATS, partials of (b.z, z, b, b.b) for
-// z = x_new (b is the residual the cycle preconditions).
-template <bool PROLONG, bool STATS>
-__global__ __launch_bounds__(NT) void k_mg_smooth(Dims d, PoisCoef c, const double *__restrict__ b,
-                                                  const double *__restrict__ x, const double *__restrict__ xc,
-                                                  int cpitch, double *__restrict__ xn, double omega, double *pout) {
-    __shared__ double sx[PTY + 2][TX + 2];
-    const int P = d.pitch;
-    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-    double v[4] = {0, 0, 0, 0};
-    for_tiles(d, [&](int, int c0, int r0) {
-        for (int e = threadIdx.x; e < (PTY + 2) * (TX + 2); e += NT) {
-            const int ly = e / (TX + 2), lx = e - ly * (TX + 2);
-            const int j = r0 - 1 + ly, i = c0 - 1 + lx;
-            const bool in = (j >= 0) && (j < d.rows) && (i >= 0) && (i < P);
-            const size_t k = in ? (size_t)j * P + i : 0;
-            double xv = x[k];
-            const double di = c.dinv[k];
-            if (PROLONG) {
-                const size_t kc = (size_t)((j + 1) >> 1) * cpitch + ((i + 1) >> 1);
-                const double e2 = xc[in ? kc : 0];
-                xv += (di > 0.0) ? e2 : 0.0;
-            }
-            sx[ly][lx] = (in && di > 0.0) ? xv : 0.0;
-        }
-        __syncthreads();
-        const int i = c0 + tx;
-        for (int lj = ty; lj < PTY; lj += 4) {
-            const int j = r0 + lj;
-            if (j < d.rows) {
-                const size_t k = (size_t)j * P + i;
-                const size_t kw = i > 0 ? k - 1 : k, ks = j > 0 ? k - P : k;
-                const double dv = c.dinv[k], bv = b[k];
-                const double ce = c.cx[k], cw = c.cx[kw], cn = c.cy[k], cs = c.cy[ks];
-                const double xcv = sx[lj + 1][tx + 1];
-                const double Ax = (ce + cw + cn + cs) * xcv - ce * sx[lj + 1][tx + 2] - cw * sx[lj + 1][tx] -
-                                  cn * sx[lj + 2][tx + 1] - cs * sx[lj][tx + 1];
-                const double z = dv > 0.0 ? xcv + omega * dv * (bv - Ax) : 0.0;
-                xn[k] = z;
-                if (STATS) {
-                    v[0] += bv * z;
-                    v[1] += z;
-                    v[2] += bv;
-                    v[3] += bv * bv;
-                }
-            }
-        }
-        __syncthreads();
-    });
-    if (STATS) put_partials<4>(v, pout, d.nblk);
-}
-
-// b_coarse = R (b - A x): the residual summed over the active children.
-__global__ __launch_bounds__(NT) void k_mg_restrict(Dims dcrs, int fpitch, int fnx, int fny, PoisCoef f,
-                                                   const double *__restrict__ bf, const double *__restrict__ xf,
-                                                   const double *__restrict__ dinvc, double *__restrict__ bc) {
-    const size_t P = fpitch;
-    for_cells(dcrs, [&](int, int J, int I, size_t kc) {
-        double sum = 0.0;
-        if (I >= 1 && I <= dcrs.nx && J >= 1 && J <= dcrs.ny) {
-#pragma unroll
-            for (int dj = 0; dj < 2; ++dj)
-#pragma unroll
-                for (int di2 = 0; di2 < 2; ++di2) {
-                    const int j = 2 * J - 1 + dj, i = 2 * I - 1 + di2;
-                    if (j > fny || i > fnx) continue;
-                    const size_t k = (size_t)j * P + i;
-                    if (!(f.dinv[k] > 0.0)) continue;
-                    const double ce = f.cx[k], cw = f.cx[k - 1], cn = f.cy[k], cs = f.cy[k - P];
-                    const double Ax = (ce + cw + cn + cs) * xf[k] - ce * xf[k + 1] - cw * xf[k - 1] -
-                                      cn * xf[k + P] - cs * xf[k - P];
-                    sum += bf[k] - Ax;
-                }
-        }
-        bc[kc] = dinvc[kc] > 0.0 ? sum : 0.0;
-    });
-}
-
 // Fused cycle kernels.  Tiles cover the real cells, starting at cell (1, 1)
 // so that every 2x2 group of children that forms a coarse cell lies inside
 // one tile (64 = 32 coarse columns, 16 = 8 coarse rows).  One tile per
@@ -688,48 +603,6 @@ __global__ __launch_bounds__(NT) void k_pred_init(Dims d, PredCoef pc, const dou
         st->it_final = 0;
     }
     put_partials<5>(v, pout, d.nblk);
-}
-
-__global__ __launch_bounds__(NT) void k_pred_dir(Dims d, PredCoef pc, const double *__restrict__ r,
-                                                 const double *__restrict__ pold, double *__restrict__ pnew,
-                                                 double *__restrict__ q, CgState *st, int first, int par,
-                                                 const double *pin, int nin, double *pout) {
-    if (st->done) return;
-    double fn2, rs, sm, rsum, rr;
-    if (first) {
-        double t[5];
-        get_totals<5>(pin, nin, t);
-        fn2 = t[0]; rs = t[1]; sm = t[2]; rsum = t[3]; rr = t[4];
-    } else {
-        double t[4];
-        get_totals<4>(pin, nin, t);
-        fn2 = st->fnorm2; rs = t[0]; sm = t[1]; rsum = t[2]; rr = t[3];
-    }
-    const DirStep ds = cg_decide(st, first, par, fn2, rs, sm, rsum, rr);
-    if (ds.stop) return;
-    const double beta = ds.beta;
-    const size_t P = d.pitch, n = d.n;
-    auto pnx = [&](size_t kk) { return pc.hdx[kk] * r[kk] + beta * pold[kk]; };
-    auto pny = [&](size_t kk) { return pc.hdy[kk] * r[n + kk] + beta * pold[n + kk]; };
-    double v[1] = {0.0};
-    for_cells(d, [&](int comp, int j, int i, size_t k) {
-        if (comp == 0) {
-            if (!(pc.vu[k] > 0.0)) return;
-            const double pv = pnx(k);
-            const double qv = pc.rt * pc.vu[k] * pv - pc.mu * visc_x(pc.vc, k, P, pnx, pny);
-            pnew[k] = pv;
-            q[k] = qv;
-            v[0] += pv * qv;
-        } else {
-            if (!(pc.vv[k] > 0.0)) return;
-            const double pv = pny(k);
-            const double qv = pc.rt * pc.vv[k] * pv - pc.mu * visc_y(pc.vc, k, P, pnx, pny);
-            pnew[n + k] = pv;
-            q[n + k] = qv;
-            v[0] += pv * qv;
-        }
-    });
-    put_partials<1>(v, pout, d.nblk);
 }
 
 // Predictor direction and operator, both velocity components of a 64 x 8
@@ -1197,9 +1070,10 @@ void harvest_events(ccns_ctx *c, int kid) {
 // partials are in PB_INIT) until the device flags the end of the solve.
 // dir(first, par, pin, nin, pout) launches the direction+operator kernel and
 // returns its group count.
-template <class Dir>
+template <class Dir, class Finish>
 ccns_status cg_loop(ccns_ctx *c, CgState *st, double *x, double *r, double *const pbuf[2], int &par_buf, double *q,
-                    const double *dinv, size_t ntot, int &last_it, Dir dir, ccns_solve_info *info, int kid) {
+                    const double *dinv, size_t ntot, int &last_it, Dir dir, Finish finish, ccns_solve_info *info,
+                    int kid) {
     const int nl = flat_blocks(ntot);
     int chunk = std::max(4, last_it + 1);
     int it = 0;
@@ -1213,6 +1087,7 @@ ccns_status cg_loop(ccns_ctx *c, CgState *st, double *x, double *r, double *cons
                                first ? c->part[PB_INIT] : c->part[PB_UPD], first ? c->init_nblk : nl,
                                c->part[PB_DIR]);
             if (tm) (void)hipEventRecord(next_event(c), c->stream);
+            finish();
             k_cg_update<<<nl, NT, 0, c->stream>>>(ntot, nl, dinv, x, r, pbuf[par_buf ^ 1], q, st, par,
                                                   c->part[PB_DIR], nd, c->part[PB_UPD]);
             if (tm) (void)hipEventRecord(next_event(c), c->stream);
@@ -1260,7 +1135,7 @@ ccns_status pressure_solve_dev(ccns_ctx *c, int nin, ccns_solve_info *info) {
         return c->dp.nblk;
     };
     return cg_loop(c, c->st_pois, c->a[A_PHI], c->a[A_R], pb, c->pbuf_pois, c->a[A_Q], c->a[A_DINV], c->w.L.n,
-                   c->last_pois_it, dir, info, 0);
+                   c->last_pois_it, dir, [] {}, info, 0);
 }
 
 constexpr int MG_NU = 2;          // pre- and post-smoothing sweeps
@@ -1441,11 +1316,12 @@ ccns_status predict_dev(ccns_ctx *c, ccns_solve_info *info) {
         k_pred_dir_lds<<<nb, NT, 0, c->stream>>>(L.nx, L.ny, L.pitch, L.rows, gx, gy, L.n, pc, c->a[A_PRX], pold,
                                                  pnew, c->a[A_PQX], c->st_pred, first, par, pin, nin,
                                                  c->part[PB_RHS]);
-        k_reduce_partials<1><<<1, NT, 0, c->stream>>>(c->part[PB_RHS], nb, pout);
+        (void)pout;
         return 1;
     };
+    auto finish = [&]() { k_reduce_partials<1><<<1, NT, 0, c->stream>>>(c->part[PB_RHS], nb, c->part[PB_DIR]); };
     return cg_loop(c, c->st_pred, c->a[A_USX], c->a[A_PRX], pb, c->pbuf_pred, c->a[A_PQX], c->a[A_HDX],
-                   2 * c->w.L.n, c->last_pred_it, dir, info, 2);
+                   2 * c->w.L.n, c->last_pred_it, dir, finish, info, 2);
 }
 
 ccns_status diag_dev(ccns_ctx *c, int update_p, ccns_step_info *info) {
