@@ -45,11 +45,14 @@ def test_argument_validation_without_gpu():
     assert L.ccns_ctx_create(C.byref(g), C.byref(p), None, None, None, 0, None, C.byref(h)) == ccns.EINVAL
 
 
-@pytest.mark.parametrize("name", ["cylinder_64", "offcentre_40"])
+@pytest.mark.parametrize("name", ["cylinder_64", "offcentre_40", "channel_cylinder_2048x1024"])
 def test_library_capacities_match_oracle(name):
     from paper_2211_10698_amd import ccns
     if name == "cylinder_64":
         case = W.cylinder_64()
+        g, bodies = case.grid, case.bodies
+    elif name == "channel_cylinder_2048x1024":
+        case = W.channel_cylinder_2048()     # the benchmark's full size
         g, bodies = case.grid, case.bodies
     else:
         g = W.GridSpec(40, 36, -0.1, 0.05, 1.2, 1.08)
