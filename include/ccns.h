@@ -98,10 +98,18 @@ ccns_status ccns_capacities(const ccns_grid *grid, const ccns_body *bodies, int 
  *  gx, gy         gravity (body force rho*M*g of eq:semidiscrete)
  *  pcg_tol        Poisson: stop when ||r||_2 <= pcg_tol ||b||_2
  *  pred_tol       predictor: same criterion
- *  div_tol        precision 1: outer refinement stops at div_rel <= div_tol
+ *  div_tol        precision 1: the pressure refinement stops once
+ *                 (tau/rho) max|r| / (u_ref min(hx,hy)) <= div_tol / 2, which
+ *                 bounds the step's div_rel by div_tol; 0 selects the 2-norm
+ *                 test with pcg_tol instead
  *  pcg_maxit, pred_maxit   iteration limits
- *  precision      0 = FP64 throughout; 1 = FP32 stencils and inner CG with
- *                 FP64 reductions and an FP64 iterative-refinement loop
+ *  precision      0 = FP64 throughout; 1 = iterative refinement: each sweep
+ *                 forms the residual in FP64 with FP64 coefficients, solves
+ *                 for the correction with float vectors, float coefficients
+ *                 and float stencils (dot products summed in FP64), and adds
+ *                 it in FP64.  Both solves; the predictor stops at the same
+ *                 2-norm test as in precision 0 (pred_tol).  The state and
+ *                 every explicit phase stay FP64.
  *  visc_form      node strain weights: 0 symmetric (geometric mean of the two
  *                 node volumes for the cross coupling), 1 as printed in
  *                 eq:offdiag (not symmetric; apply only), 2 arithmetic mean
@@ -181,7 +189,7 @@ enum { CCNS_OP_CONT = 0, CCNS_OP_PRES, CCNS_OP_VISC, CCNS_OP_CONV, CCNS_OP_LAP, 
 ccns_status ccns_apply(ccns_ctx *ctx, int op, const double *const *in, double *const *out);
 
 typedef struct {
-    int iterations;        /* CG iterations (inner iterations in precision 1) */
+    int iterations;        /* CG iterations (precision 1: inner iterations of all sweeps) */
     int outer;             /* refinement sweeps (precision 1), else 1 */
     double rel_residual;   /* final ||r||_2 / ||b||_2 (FP64) */
     int status;            /* ccns_status of this solve */

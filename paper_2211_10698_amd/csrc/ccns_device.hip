@@ -56,10 +56,26 @@ struct DiagState {
     double mass, ke, momx, momy, divmax;
 };
 
-struct PoisCoef {
-    const double *cx, *cy, *dinv;
+// Coefficient sets.  T is the storage and stencil type of a solve: double in
+// precision 0 and in the FP64 residuals of precision 1, float in the inner
+// iterations of precision 1 (whose dot products are still summed in double).
+template <class T>
+struct PoisCoefT {
+    const T *cx, *cy, *dinv;
+};
+using PoisCoef = PoisCoefT<double>;
+
+template <class T>
+struct ViscCoefT {
+    const T *bxx, *bxy, *byy, *byx, *wxx, *wyy, *nxx, *nxy, *nyx, *nyy;
 };
 
+template <class T>
+struct PredCoefT {
+    ViscCoefT<T> vc;
+    const T *vu, *vv, *hdx, *hdy;
+    double rt, mu;
+};
 struct PredCoef {
     ViscCoef vc;
     const double *vu, *vv, *hdx, *hdy;
@@ -130,37 +146,71 @@ __global__ __launch_bounds__(NT) void k_pois_sum(Dims d, PoisCoef pc, const doub
     put_partials<1>(v, pout, d.nblk);
 }
 
-// b <- b - mean(b); f = -b; r = f - A x; statistics of r.
+// b <- b - mean(b) (when pin is given: the partial sums of b); f = -b;
+// r = f - A x in FP64; statistics of r.
+//  MIX = false: r is stored; partials (f.f, r.z, z, r, r.r) with z = D^-1 r.
+//  MIX = true (precision 1): r is rounded to float into r32 (the right-hand
+//  side of the inner solve, whose start value x32 is cleared); partials
+//  (r32.r32, r32.z, z, r32, r32.r32 | f.f, r.r | max |r|) with z = D32^-1 r32.
+template <bool MIX>
 __global__ __launch_bounds__(NT) void k_pois_init(Dims d, PoisCoef pc, double *__restrict__ b,
                                                   const double *__restrict__ x, double *__restrict__ r, CgState *st,
-                                                  const double *pin, int nin, double *pout) {
-    double t[1];
-    get_totals<1>(pin, nin, t);
-    const double mb = t[0] / (double)st->n_active;
+                                                  const double *pin, int nin, double *pout, float *__restrict__ r32,
+                                                  float *__restrict__ x32, const float *__restrict__ dinv32) {
+    double mb = 0.0;
+    if (pin) {
+        double t[1];
+        get_totals<1>(pin, nin, t);
+        mb = t[0] / (double)st->n_active;
+    }
     const size_t P = d.pitch;
-    double v[5] = {0, 0, 0, 0, 0};
+    double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     for_cells(d, [&](int, int j, int i, size_t k) {
         const double dv = pc.dinv[k];
+        if (MIX) {
+            x32[k] = 0.0f;
+            r32[k] = 0.0f;
+        }
         if (!(dv > 0.0)) return;
         const double bp = b[k] - mb;
-        b[k] = bp;
+        if (pin) b[k] = bp;
         const double ce = pc.cx[k], cw = pc.cx[k - 1], cn = pc.cy[k], cs = pc.cy[k - P];
         const double Axv = (ce + cw + cn + cs) * x[k] - ce * x[k + 1] - cw * x[k - 1] - cn * x[k + P] - cs * x[k - P];
         const double rv = -bp - Axv;
-        r[k] = rv;
-        const double s = dv * rv;
-        v[0] += bp * bp;
-        v[1] += rv * s;
-        v[2] += s;
-        v[3] += rv;
-        v[4] += rv * rv;
+        if (MIX) {
+            const float rf = (float)rv;
+            r32[k] = rf;
+            const float sf = dinv32[k] * rf;
+            const double rd = rf, sd = sf;
+            v[0] += rd * rd;
+            v[1] += rd * sd;
+            v[2] += sd;
+            v[3] += rd;
+            v[4] += rd * rd;
+            v[5] += bp * bp;
+            v[6] += rv * rv;
+            v[7] = fmax(v[7], fabs(rv));
+        } else {
+            r[k] = rv;
+            const double sv = dv * rv;
+            v[0] += bp * bp;
+            v[1] += rv * sv;
+            v[2] += sv;
+            v[3] += rv;
+            v[4] += rv * rv;
+        }
     });
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         st->done = 0;
         st->status = 0;
         st->it_final = 0;
     }
-    put_partials<5>(v, pout, d.nblk);
+    if (MIX) {
+        put_partials<7, 1>(v, pout, d.nblk);
+    } else {
+        double w[5] = {v[0], v[1], v[2], v[3], v[4]};
+        put_partials<5>(w, pout, d.nblk);
+    }
 }
 
 // Tile of the Poisson stencil kernels: 64 columns x 16 rows (4 per thread).
@@ -169,9 +219,10 @@ constexpr int PTY = 16;
 // Direction and operator: p = (M r) + beta p_old on the tile and a one-cell
 // halo staged in LDS; q = A p; partial p.q.  Consumes the residual statistics
 // of the previous kernel (init if `first`, else the update).
-__global__ __launch_bounds__(NT) void k_pois_dir(Dims d, PoisCoef pc, const double *__restrict__ r,
-                                                 const double *__restrict__ pold, double *__restrict__ pnew,
-                                                 double *__restrict__ q, CgState *st, int first, int par,
+template <class T>
+__global__ __launch_bounds__(NT) void k_pois_dir(Dims d, PoisCoefT<T> pc, const T *__restrict__ r,
+                                                 const T *__restrict__ pold, T *__restrict__ pnew,
+                                                 T *__restrict__ q, CgState *st, int first, int par,
                                                  const double *pin, int nin, double *pout) {
     if (st->done) return;
     double fn2, rs, sm, rsum, rr;
@@ -186,8 +237,8 @@ __global__ __launch_bounds__(NT) void k_pois_dir(Dims d, PoisCoef pc, const doub
     }
     const DirStep ds = cg_decide(st, first, par, fn2, rs, sm, rsum, rr);
     if (ds.stop) return;
-    const double beta = ds.beta, m = ds.mean;
-    __shared__ double sp[PTY + 2][TX + 2];
+    const T beta = (T)ds.beta, m = (T)ds.mean;
+    __shared__ T sp[PTY + 2][TX + 2];
     const int P = d.pitch;
     const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
     double v[1] = {0.0};
@@ -197,8 +248,8 @@ __global__ __launch_bounds__(NT) void k_pois_dir(Dims d, PoisCoef pc, const doub
             const int j = r0 - 1 + ly, i = c0 - 1 + lx;
             const bool in = (j >= 0) && (j < d.rows) && (i >= 0) && (i < P);
             const size_t k = in ? (size_t)j * P + i : 0;
-            const double di = pc.dinv[k], rv = r[k], po = pold[k];
-            sp[ly][lx] = (in && di > 0.0) ? (di * rv - m) + beta * po : 0.0;
+            const T di = pc.dinv[k], rv = r[k], po = pold[k];
+            sp[ly][lx] = (in && di > (T)0) ? (di * rv - m) + beta * po : (T)0;
         }
         __syncthreads();
         const int i = c0 + tx;
@@ -209,14 +260,14 @@ __global__ __launch_bounds__(NT) void k_pois_dir(Dims d, PoisCoef pc, const doub
             if (j < d.rows) {
                 const size_t k = (size_t)j * P + i;
                 const size_t kw = i > 0 ? k - 1 : k, ks = j > 0 ? k - P : k;
-                const double dv = pc.dinv[k], ce = pc.cx[k], cw = pc.cx[kw], cn = pc.cy[k], cs = pc.cy[ks];
-                const double pcv = sp[lj + 1][tx + 1];
-                double qv = (ce + cw + cn + cs) * pcv - ce * sp[lj + 1][tx + 2] - cw * sp[lj + 1][tx] -
-                            cn * sp[lj + 2][tx + 1] - cs * sp[lj][tx + 1];
-                qv = dv > 0.0 ? qv : 0.0;
+                const T dv = pc.dinv[k], ce = pc.cx[k], cw = pc.cx[kw], cn = pc.cy[k], cs = pc.cy[ks];
+                const T pcv = sp[lj + 1][tx + 1];
+                T qv = (ce + cw + cn + cs) * pcv - ce * sp[lj + 1][tx + 2] - cw * sp[lj + 1][tx] -
+                       cn * sp[lj + 2][tx + 1] - cs * sp[lj][tx + 1];
+                qv = dv > (T)0 ? qv : (T)0;
                 pnew[k] = pcv;
                 q[k] = qv;
-                v[0] += pcv * qv;
+                v[0] += (double)pcv * (double)qv;
             }
         }
         __syncthreads();
@@ -228,9 +279,10 @@ __global__ __launch_bounds__(NT) void k_pois_dir(Dims d, PoisCoef pc, const doub
 // ntot entries (inactive entries hold zeros); each group works on contiguous
 // chunks of UPT*NT entries with every load issued before any arithmetic.
 constexpr int UPT = 4;
-__global__ __launch_bounds__(NT) void k_cg_update(size_t ntot, int nblk, const double *__restrict__ dinv,
-                                                  double *__restrict__ x, double *__restrict__ r,
-                                                  const double *__restrict__ p, const double *__restrict__ q,
+template <class T>
+__global__ __launch_bounds__(NT) void k_cg_update(size_t ntot, int nblk, const T *__restrict__ dinv,
+                                                  T *__restrict__ x, T *__restrict__ r,
+                                                  const T *__restrict__ p, const T *__restrict__ q,
                                                   CgState *st, int par, const double *pin, int nin, double *pout) {
     if (st->done) return;
     double t[1];
@@ -243,12 +295,12 @@ __global__ __launch_bounds__(NT) void k_cg_update(size_t ntot, int nblk, const d
         }
         return;
     }
-    const double a = st->slot[par].rz / t[0];
+    const T a = (T)(st->slot[par].rz / t[0]);
     double v[4] = {0, 0, 0, 0};
     const size_t chunk = (size_t)UPT * NT;
     const int L = logical_group(nblk);
     for (size_t base = (size_t)L * chunk; base < ntot; base += (size_t)nblk * chunk) {
-        double dv[UPT], xv[UPT], pv[UPT], rv[UPT], qv[UPT];
+        T dv[UPT], xv[UPT], pv[UPT], rv[UPT], qv[UPT];
 #pragma unroll
         for (int u = 0; u < UPT; ++u) {
             const size_t k0 = base + (size_t)u * NT + threadIdx.x;
@@ -262,19 +314,27 @@ __global__ __launch_bounds__(NT) void k_cg_update(size_t ntot, int nblk, const d
 #pragma unroll
         for (int u = 0; u < UPT; ++u) {
             const size_t k = base + (size_t)u * NT + threadIdx.x;
-            if (k < ntot && dv[u] > 0.0) {
+            if (k < ntot && dv[u] > (T)0) {
                 x[k] = xv[u] + a * pv[u];
-                const double rn = rv[u] - a * qv[u];
+                const T rn = rv[u] - a * qv[u];
                 r[k] = rn;
-                const double s = dv[u] * rn;
-                v[0] += rn * s;
-                v[1] += s;
-                v[2] += rn;
-                v[3] += rn * rn;
+                const T sv = dv[u] * rn;
+                const double rd = rn, sd = sv;
+                v[0] += rd * sd;
+                v[1] += sd;
+                v[2] += rd;
+                v[3] += rd * rd;
             }
         }
     }
     put_partials<4>(v, pout, nblk);
+}
+
+// x += dx (float correction of an inner solve) over ntot entries.
+__global__ __launch_bounds__(NT) void k_add_correction(size_t ntot, double *__restrict__ x,
+                                                       const float *__restrict__ dx) {
+    for (size_t k = (size_t)blockIdx.x * NT + threadIdx.x; k < ntot; k += (size_t)gridDim.x * NT)
+        x[k] += (double)dx[k];
 }
 
 // ---------------------------------------------------------------------------
@@ -316,13 +376,14 @@ struct LdsStencil {
 
 // Two weighted-Jacobi sweeps from a zero guess, the residual, and its
 // restriction: x2 (written to x2out) and b_coarse.
-__global__ __launch_bounds__(NT) void k_mg_down(int nx, int ny, int P, int gx, PoisCoef c,
-                                                const double *__restrict__ b, double *__restrict__ x2out,
-                                                int Pc, int nxc, int nyc, const double *__restrict__ dinvc,
-                                                double *__restrict__ bc, double omega) {
-    __shared__ double s1[MHt][MW];            // first sweep on the 2-ring region
-    __shared__ double s2[MTY + 2][TX + 2];    // second sweep on the 1-ring region
-    __shared__ double sr[MTY][TX];            // residual on the tile
+template <class T>
+__global__ __launch_bounds__(NT) void k_mg_down(int nx, int ny, int P, int gx, PoisCoefT<T> c,
+                                                const T *__restrict__ b, T *__restrict__ x2out,
+                                                int Pc, int nxc, int nyc, const T *__restrict__ dinvc,
+                                                T *__restrict__ bc, T omega) {
+    __shared__ T s1[MHt][MW];            // first sweep on the 2-ring region
+    __shared__ T s2[MTY + 2][TX + 2];    // second sweep on the 1-ring region
+    __shared__ T sr[MTY][TX];            // residual on the tile
     const MgTile t = mg_tile(gx);
     if (t.r0 > ny || t.c0 > nx) return;
     for (int e = threadIdx.x; e < MHt * MW; e += NT) {
@@ -330,8 +391,8 @@ __global__ __launch_bounds__(NT) void k_mg_down(int nx, int ny, int P, int gx, P
         const int j = t.r0 - MH + ly, i = t.c0 - MH + lx;
         const bool in = (j >= 0) && (j <= ny + 1) && (i >= 0) && (i <= nx + 1);
         const size_t k = in ? (size_t)j * P + i : 0;
-        const double dv = c.dinv[k], bv = b[k];
-        s1[ly][lx] = (in && dv > 0.0) ? omega * dv * bv : 0.0;
+        const T dv = c.dinv[k], bv = b[k];
+        s1[ly][lx] = (in && dv > (T)0) ? omega * dv * bv : (T)0;
     }
     __syncthreads();
     for (int e = threadIdx.x; e < (MTY + 2) * (TX + 2); e += NT) {
@@ -339,13 +400,13 @@ __global__ __launch_bounds__(NT) void k_mg_down(int nx, int ny, int P, int gx, P
         const int j = t.r0 - 1 + ly, i = t.c0 - 1 + lx;
         const bool in = (j >= 1) && (j <= ny) && (i >= 1) && (i <= nx);
         const size_t k = in ? (size_t)j * P + i : 0;
-        const double dv = c.dinv[k], bv = b[k];
-        const double ce = c.cx[k], cw = c.cx[in ? k - 1 : 0], cn = c.cy[k], cs = c.cy[in ? k - P : 0];
+        const T dv = c.dinv[k], bv = b[k];
+        const T ce = c.cx[k], cw = c.cx[in ? k - 1 : 0], cn = c.cy[k], cs = c.cy[in ? k - P : 0];
         const int y = ly + 1, x = lx + 1;  // position in s1
-        const double xv = s1[y][x];
-        const double Ax = (ce + cw + cn + cs) * xv - ce * s1[y][x + 1] - cw * s1[y][x - 1] - cn * s1[y + 1][x] -
+        const T xv = s1[y][x];
+        const T Ax = (ce + cw + cn + cs) * xv - ce * s1[y][x + 1] - cw * s1[y][x - 1] - cn * s1[y + 1][x] -
                           cs * s1[y - 1][x];
-        s2[ly][lx] = (in && dv > 0.0) ? xv + omega * dv * (bv - Ax) : 0.0;
+        s2[ly][lx] = (in && dv > (T)0) ? xv + omega * dv * (bv - Ax) : (T)0;
     }
     __syncthreads();
     {
@@ -354,13 +415,13 @@ __global__ __launch_bounds__(NT) void k_mg_down(int nx, int ny, int P, int gx, P
             const int j = t.r0 + ly, i = t.c0 + tx;
             const bool in = (j <= ny) && (i <= nx);
             const size_t k = in ? (size_t)j * P + i : 0;
-            const double dv = c.dinv[k], bv = b[k];
-            const double ce = c.cx[k], cw = c.cx[in ? k - 1 : 0], cn = c.cy[k], cs = c.cy[in ? k - P : 0];
+            const T dv = c.dinv[k], bv = b[k];
+            const T ce = c.cx[k], cw = c.cx[in ? k - 1 : 0], cn = c.cy[k], cs = c.cy[in ? k - P : 0];
             const int y = ly + 1, x = tx + 1;
-            const double xv = s2[y][x];
-            const double Ax = (ce + cw + cn + cs) * xv - ce * s2[y][x + 1] - cw * s2[y][x - 1] - cn * s2[y + 1][x] -
+            const T xv = s2[y][x];
+            const T Ax = (ce + cw + cn + cs) * xv - ce * s2[y][x + 1] - cw * s2[y][x - 1] - cn * s2[y + 1][x] -
                               cs * s2[y - 1][x];
-            sr[ly][tx] = (in && dv > 0.0) ? bv - Ax : 0.0;
+            sr[ly][tx] = (in && dv > (T)0) ? bv - Ax : (T)0;
             if (in) x2out[k] = xv;
         }
     }
@@ -370,22 +431,22 @@ __global__ __launch_bounds__(NT) void k_mg_down(int nx, int ny, int P, int gx, P
         const int cxl = threadIdx.x & 31, cyl = threadIdx.x >> 5;
         const int I = (t.c0 + 1) / 2 + cxl, J = (t.r0 + 1) / 2 + cyl;
         if (I <= nxc && J <= nyc) {
-            const double sum = (sr[2 * cyl][2 * cxl] + sr[2 * cyl][2 * cxl + 1]) +
+            const T sum = (sr[2 * cyl][2 * cxl] + sr[2 * cyl][2 * cxl + 1]) +
                                (sr[2 * cyl + 1][2 * cxl] + sr[2 * cyl + 1][2 * cxl + 1]);
             const size_t kc = (size_t)J * Pc + I;
-            bc[kc] = dinvc[kc] > 0.0 ? sum : 0.0;
+            bc[kc] = dinvc[kc] > (T)0 ? sum : (T)0;
         }
     }
 }
 
 // The coarse correction interpolated onto x2, then two weighted-Jacobi
 // sweeps: z.  With STATS, partials of (b.z, z, b, b.b).
-template <bool STATS>
-__global__ __launch_bounds__(NT) void k_mg_up(int nx, int ny, int P, int gx, PoisCoef c, const double *__restrict__ b,
-                                              const double *__restrict__ x2, const double *__restrict__ xc, int Pc,
-                                              double *__restrict__ z, double omega, double *pout, int nblk) {
-    __shared__ double s1[MHt][MW];
-    __shared__ double s2[MTY + 2][TX + 2];
+template <class T, bool STATS>
+__global__ __launch_bounds__(NT) void k_mg_up(int nx, int ny, int P, int gx, PoisCoefT<T> c, const T *__restrict__ b,
+                                              const T *__restrict__ x2, const T *__restrict__ xc, int Pc,
+                                              T *__restrict__ z, T omega, double *pout, int nblk) {
+    __shared__ T s1[MHt][MW];
+    __shared__ T s2[MTY + 2][TX + 2];
     const MgTile t = mg_tile(gx);
     double v[4] = {0, 0, 0, 0};
     const bool live = !(t.r0 > ny || t.c0 > nx);
@@ -396,8 +457,8 @@ __global__ __launch_bounds__(NT) void k_mg_up(int nx, int ny, int P, int gx, Poi
             const bool in = (j >= 1) && (j <= ny) && (i >= 1) && (i <= nx);
             const size_t k = in ? (size_t)j * P + i : 0;
             const size_t kc = in ? (size_t)((j + 1) >> 1) * Pc + ((i + 1) >> 1) : 0;
-            const double dv = c.dinv[k], xv = x2[k], ec = xc[kc];
-            s1[ly][lx] = (in && dv > 0.0) ? xv + ec : 0.0;
+            const T dv = c.dinv[k], xv = x2[k], ec = xc[kc];
+            s1[ly][lx] = (in && dv > (T)0) ? xv + ec : (T)0;
         }
     }
     __syncthreads();
@@ -407,13 +468,13 @@ __global__ __launch_bounds__(NT) void k_mg_up(int nx, int ny, int P, int gx, Poi
             const int j = t.r0 - 1 + ly, i = t.c0 - 1 + lx;
             const bool in = (j >= 1) && (j <= ny) && (i >= 1) && (i <= nx);
             const size_t k = in ? (size_t)j * P + i : 0;
-            const double dv = c.dinv[k], bv = b[k];
-            const double ce = c.cx[k], cw = c.cx[in ? k - 1 : 0], cn = c.cy[k], cs = c.cy[in ? k - P : 0];
+            const T dv = c.dinv[k], bv = b[k];
+            const T ce = c.cx[k], cw = c.cx[in ? k - 1 : 0], cn = c.cy[k], cs = c.cy[in ? k - P : 0];
             const int y = ly + 1, x = lx + 1;
-            const double xv = s1[y][x];
-            const double Ax = (ce + cw + cn + cs) * xv - ce * s1[y][x + 1] - cw * s1[y][x - 1] - cn * s1[y + 1][x] -
+            const T xv = s1[y][x];
+            const T Ax = (ce + cw + cn + cs) * xv - ce * s1[y][x + 1] - cw * s1[y][x - 1] - cn * s1[y + 1][x] -
                               cs * s1[y - 1][x];
-            s2[ly][lx] = (in && dv > 0.0) ? xv + omega * dv * (bv - Ax) : 0.0;
+            s2[ly][lx] = (in && dv > (T)0) ? xv + omega * dv * (bv - Ax) : (T)0;
         }
     }
     __syncthreads();
@@ -423,19 +484,20 @@ __global__ __launch_bounds__(NT) void k_mg_up(int nx, int ny, int P, int gx, Poi
             const int j = t.r0 + ly, i = t.c0 + tx;
             const bool in = (j <= ny) && (i <= nx);
             const size_t k = in ? (size_t)j * P + i : 0;
-            const double dv = c.dinv[k], bv = b[k];
-            const double ce = c.cx[k], cw = c.cx[in ? k - 1 : 0], cn = c.cy[k], cs = c.cy[in ? k - P : 0];
+            const T dv = c.dinv[k], bv = b[k];
+            const T ce = c.cx[k], cw = c.cx[in ? k - 1 : 0], cn = c.cy[k], cs = c.cy[in ? k - P : 0];
             const int y = ly + 1, x = tx + 1;
-            const double xv = s2[y][x];
-            const double Ax = (ce + cw + cn + cs) * xv - ce * s2[y][x + 1] - cw * s2[y][x - 1] - cn * s2[y + 1][x] -
+            const T xv = s2[y][x];
+            const T Ax = (ce + cw + cn + cs) * xv - ce * s2[y][x + 1] - cw * s2[y][x - 1] - cn * s2[y + 1][x] -
                               cs * s2[y - 1][x];
-            const double zv = (in && dv > 0.0) ? xv + omega * dv * (bv - Ax) : 0.0;
+            const T zv = (in && dv > (T)0) ? xv + omega * dv * (bv - Ax) : (T)0;
             if (in) z[k] = zv;
             if (STATS && in) {
-                v[0] += bv * zv;
-                v[1] += zv;
-                v[2] += bv;
-                v[3] += bv * bv;
+                const double bd = bv, zd = zv;
+                v[0] += bd * zd;
+                v[1] += zd;
+                v[2] += bd;
+                v[3] += bd * bd;
             }
         }
     }
@@ -444,33 +506,36 @@ __global__ __launch_bounds__(NT) void k_mg_up(int nx, int ny, int P, int gx, Poi
 
 // One work-group sums the partials of a producer into a single group's worth
 // (so that consumers read N values instead of N per producer group).
-template <int N>
+template <int NS, int NM = 0>
 __global__ __launch_bounds__(NT) void k_reduce_partials(const double *pin, int nin, double *pout) {
-    double t[N];
-    get_totals<N>(pin, nin, t);
-    if (threadIdx.x < N) pout[threadIdx.x] = t[threadIdx.x];
+    double t[NS + NM];
+    get_totals<NS, NM>(pin, nin, t);
+    if (threadIdx.x < NS + NM) pout[threadIdx.x] = t[threadIdx.x];
 }
 
 // Coarsest grid: x = A^+ b with the dense pseudo-inverse on the n unknowns.
+template <class T>
 __global__ __launch_bounds__(NT) void k_mg_coarsest(int n, const int *__restrict__ idx,
-                                                    const double *__restrict__ pinv, const double *__restrict__ b,
-                                                    double *__restrict__ x) {
+                                                    const double *__restrict__ pinv, const T *__restrict__ b,
+                                                    T *__restrict__ x) {
     __shared__ double sb[1024];
     for (int i = threadIdx.x; i < n; i += NT) sb[i] = b[idx[i]];
     __syncthreads();
     for (int i = threadIdx.x; i < n; i += NT) {
         double acc = 0.0;
         for (int j2 = 0; j2 < n; ++j2) acc += pinv[(size_t)i * n + j2] * sb[j2];
-        x[idx[i]] = acc;
+        x[idx[i]] = (T)acc;
     }
 }
 
 // Direction and operator for the multigrid-preconditioned solve:
 // p = (z - mean z) + beta p_old; q = A p.  Consumes the statistics written by
-// the last smoothing sweep (and, on the first iteration, |f|^2 from init).
-__global__ __launch_bounds__(NT) void k_pois_dir_z(Dims d, PoisCoef pc, const double *__restrict__ z,
-                                                   const double *__restrict__ pold, double *__restrict__ pnew,
-                                                   double *__restrict__ q, CgState *st, int first, int par,
+// the last smoothing sweep (b.z, z, b, b.b) and, on the first iteration, |f|^2
+// from init (pinit; without it, the norm of the cycle's input b is taken).
+template <class T>
+__global__ __launch_bounds__(NT) void k_pois_dir_z(Dims d, PoisCoefT<T> pc, const T *__restrict__ z,
+                                                   const T *__restrict__ pold, T *__restrict__ pnew,
+                                                   T *__restrict__ q, CgState *st, int first, int par,
                                                    const double *pin, int nin, const double *pinit, int ninit,
                                                    double *pout) {
     if (st->done) return;
@@ -478,16 +543,20 @@ __global__ __launch_bounds__(NT) void k_pois_dir_z(Dims d, PoisCoef pc, const do
     get_totals<4>(pin, nin, t);
     double fn2;
     if (first) {
-        double f[1];
-        get_totals<1>(pinit, ninit, f);
-        fn2 = f[0];
+        if (pinit) {
+            double f[1];
+            get_totals<1>(pinit, ninit, f);
+            fn2 = f[0];
+        } else {
+            fn2 = t[3];
+        }
     } else {
         fn2 = st->fnorm2;
     }
     const DirStep ds = cg_decide(st, first, par, fn2, t[0], t[1], t[2], t[3]);
     if (ds.stop) return;
-    const double beta = ds.beta, m = ds.mean;
-    __shared__ double sp[PTY + 2][TX + 2];
+    const T beta = (T)ds.beta, m = (T)ds.mean;
+    __shared__ T sp[PTY + 2][TX + 2];
     const int P = d.pitch;
     const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
     double v[1] = {0.0};
@@ -497,8 +566,8 @@ __global__ __launch_bounds__(NT) void k_pois_dir_z(Dims d, PoisCoef pc, const do
             const int j = r0 - 1 + ly, i = c0 - 1 + lx;
             const bool in = (j >= 0) && (j < d.rows) && (i >= 0) && (i < P);
             const size_t k = in ? (size_t)j * P + i : 0;
-            const double di = pc.dinv[k], zv = z[k], po = pold[k];
-            sp[ly][lx] = (in && di > 0.0) ? (zv - m) + beta * po : 0.0;
+            const T di = pc.dinv[k], zv = z[k], po = pold[k];
+            sp[ly][lx] = (in && di > (T)0) ? (zv - m) + beta * po : (T)0;
         }
         __syncthreads();
         const int i = c0 + tx;
@@ -507,14 +576,14 @@ __global__ __launch_bounds__(NT) void k_pois_dir_z(Dims d, PoisCoef pc, const do
             if (j < d.rows) {
                 const size_t k = (size_t)j * P + i;
                 const size_t kw = i > 0 ? k - 1 : k, ks = j > 0 ? k - P : k;
-                const double dv = pc.dinv[k], ce = pc.cx[k], cw = pc.cx[kw], cn = pc.cy[k], cs = pc.cy[ks];
-                const double pcv = sp[lj + 1][tx + 1];
-                double qv = (ce + cw + cn + cs) * pcv - ce * sp[lj + 1][tx + 2] - cw * sp[lj + 1][tx] -
-                            cn * sp[lj + 2][tx + 1] - cs * sp[lj][tx + 1];
-                qv = dv > 0.0 ? qv : 0.0;
+                const T dv = pc.dinv[k], ce = pc.cx[k], cw = pc.cx[kw], cn = pc.cy[k], cs = pc.cy[ks];
+                const T pcv = sp[lj + 1][tx + 1];
+                T qv = (ce + cw + cn + cs) * pcv - ce * sp[lj + 1][tx + 2] - cw * sp[lj + 1][tx] -
+                       cn * sp[lj + 2][tx + 1] - cs * sp[lj][tx + 1];
+                qv = dv > (T)0 ? qv : (T)0;
                 pnew[k] = pcv;
                 q[k] = qv;
-                v[0] += pcv * qv;
+                v[0] += (double)pcv * (double)qv;
             }
         }
         __syncthreads();
@@ -564,18 +633,29 @@ __global__ __launch_bounds__(NT) void k_pred_rhs(Dims d, PredCoef pc, const doub
     });
 }
 
-// r = rhs - H x0 (x0 masked to the unknowns); statistics of r.
+// r = rhs - H x0 (x0 masked to the unknowns) in FP64; statistics of r.
+//  MIX = false: r is stored; partials (f.f, r.z, z, r, r.r), z = M^-1 r.
+//  MIX = true (precision 1): r is rounded to float into r32 (right-hand side
+//  of the inner solve, whose start value x32 is cleared); partials
+//  (r32.r32, r32.z, z, r32, r32.r32, f.f, r.r) with z = M32^-1 r32.
+template <bool MIX>
 __global__ __launch_bounds__(NT) void k_pred_init(Dims d, PredCoef pc, const double *__restrict__ rhs,
                                                   const double *__restrict__ xs, double *__restrict__ r, CgState *st,
-                                                  double *pout) {
+                                                  double *pout, float *__restrict__ r32, float *__restrict__ x32,
+                                                  const float *__restrict__ hd32) {
     const size_t P = d.pitch, n = d.n;
     const double *xu = xs, *xv = xs + n;
     auto pxm = [&](size_t kk) { return pc.vu[kk] > 0.0 ? xu[kk] : 0.0; };
     auto pym = [&](size_t kk) { return pc.vv[kk] > 0.0 ? xv[kk] : 0.0; };
-    double v[5] = {0, 0, 0, 0, 0};
+    double v[7] = {0, 0, 0, 0, 0, 0, 0};
     for_cells(d, [&](int comp, int j, int i, size_t k) {
         double hv, dv;
         size_t o;
+        if (MIX) {
+            const size_t oo = comp == 0 ? k : n + k;
+            x32[oo] = 0.0f;
+            r32[oo] = 0.0f;
+        }
         if (comp == 0) {
             if (!(pc.vu[k] > 0.0)) return;
             hv = pc.rt * pc.vu[k] * xu[k] - pc.mu * visc_x(pc.vc, k, P, pxm, pym);
@@ -589,20 +669,39 @@ __global__ __launch_bounds__(NT) void k_pred_init(Dims d, PredCoef pc, const dou
         }
         const double f = rhs[o];
         const double rv = f - hv;
-        r[o] = rv;
-        const double s = dv * rv;
-        v[0] += f * f;
-        v[1] += rv * s;
-        v[2] += s;
-        v[3] += rv;
-        v[4] += rv * rv;
+        if (MIX) {
+            const float rf = (float)rv;
+            r32[o] = rf;
+            const float sf = hd32[o] * rf;
+            const double rd = rf, sd = sf;
+            v[0] += rd * rd;
+            v[1] += rd * sd;
+            v[2] += sd;
+            v[3] += rd;
+            v[4] += rd * rd;
+            v[5] += f * f;
+            v[6] += rv * rv;
+        } else {
+            r[o] = rv;
+            const double sv = dv * rv;
+            v[0] += f * f;
+            v[1] += rv * sv;
+            v[2] += sv;
+            v[3] += rv;
+            v[4] += rv * rv;
+        }
     });
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         st->done = 0;
         st->status = 0;
         st->it_final = 0;
     }
-    put_partials<5>(v, pout, d.nblk);
+    if (MIX) {
+        put_partials<7>(v, pout, d.nblk);
+    } else {
+        double w[5] = {v[0], v[1], v[2], v[3], v[4]};
+        put_partials<5>(w, pout, d.nblk);
+    }
 }
 
 // Predictor direction and operator, both velocity components of a 64 x 8
@@ -611,10 +710,11 @@ __global__ __launch_bounds__(NT) void k_pred_init(Dims d, PredCoef pc, const dou
 // cell and node in LDS; then H p = (rho/tau) V p - mu visc(S) (Sec. 4.3) on
 // the tile.  Partial p.H p per group.
 constexpr int HTY = 8;
+template <class T>
 __global__ __launch_bounds__(NT) void k_pred_dir_lds(int nx, int ny, int P, int rows, int gx, int gy, size_t n,
-                                                     PredCoef pc, const double *__restrict__ r,
-                                                     const double *__restrict__ pold, double *__restrict__ pnew,
-                                                     double *__restrict__ q, CgState *st, int first, int par,
+                                                     PredCoefT<T> pc, const T *__restrict__ r,
+                                                     const T *__restrict__ pold, T *__restrict__ pnew,
+                                                     T *__restrict__ q, CgState *st, int first, int par,
                                                      const double *pin, int nin, double *pout) {
     if (st->done) return;
     double fn2, rs, sm, rsum, rr;
@@ -629,11 +729,12 @@ __global__ __launch_bounds__(NT) void k_pred_dir_lds(int nx, int ny, int P, int 
     }
     const DirStep ds = cg_decide(st, first, par, fn2, rs, sm, rsum, rr);
     if (ds.stop) return;
-    const double beta = ds.beta;
-    __shared__ double spx[HTY + 2][TX + 2], spy[HTY + 2][TX + 2];
-    __shared__ double sxx[HTY][TX + 1], syy[HTY + 1][TX];
-    __shared__ double snx[HTY + 1][TX + 1], sny[HTY + 1][TX + 1];
-    const ViscCoef &c = pc.vc;
+    const T beta = (T)ds.beta;
+    const T rt = (T)pc.rt, mu = (T)pc.mu;
+    __shared__ T spx[HTY + 2][TX + 2], spy[HTY + 2][TX + 2];
+    __shared__ T sxx[HTY][TX + 1], syy[HTY + 1][TX];
+    __shared__ T snx[HTY + 1][TX + 1], sny[HTY + 1][TX + 1];
+    const ViscCoefT<T> &c = pc.vc;
     const int L = logical_group(((gridDim.x + 7) / 8) * 8);
     const bool live = L < gx * gy;
     const int c0 = (L % gx) * TX, r0 = (L / gx) * HTY;
@@ -645,9 +746,9 @@ __global__ __launch_bounds__(NT) void k_pred_dir_lds(int nx, int ny, int P, int 
             const int j = r0 - 1 + ly, i = c0 - 1 + lx;
             const bool in = (j >= 0) && (j < rows) && (i >= 0) && (i < P);
             const size_t k = in ? (size_t)j * P + i : 0;
-            const double hx = pc.hdx[k], hy = pc.hdy[k], rx = r[k], ry = r[n + k], ox = pold[k], oy = pold[n + k];
-            spx[ly][lx] = in ? hx * rx + beta * ox : 0.0;
-            spy[ly][lx] = in ? hy * ry + beta * oy : 0.0;
+            const T hx = pc.hdx[k], hy = pc.hdy[k], rx = r[k], ry = r[n + k], ox = pold[k], oy = pold[n + k];
+            spx[ly][lx] = in ? hx * rx + beta * ox : (T)0;
+            spy[ly][lx] = in ? hy * ry + beta * oy : (T)0;
         }
     }
     __syncthreads();
@@ -658,8 +759,8 @@ __global__ __launch_bounds__(NT) void k_pred_dir_lds(int nx, int ny, int P, int 
             const int j = r0 + ly, i = c0 + lx;
             const bool in = (j < rows) && (i >= 1) && (i < P);
             const size_t k = in ? (size_t)j * P + i : 1;
-            const double w = c.wxx[k], be = c.bxx[k], bw = c.bxx[k - 1];
-            sxx[ly][lx] = in ? w * (be * spx[ly + 1][lx + 1] - bw * spx[ly + 1][lx]) : 0.0;
+            const T w = c.wxx[k], be = c.bxx[k], bw = c.bxx[k - 1];
+            sxx[ly][lx] = in ? w * (be * spx[ly + 1][lx + 1] - bw * spx[ly + 1][lx]) : (T)0;
         }
         // S_yy at cells (rows r0 .. r0+HTY, cols c0..): y-faces j-1, j
         for (int e = threadIdx.x; e < (HTY + 1) * TX; e += NT) {
@@ -667,8 +768,8 @@ __global__ __launch_bounds__(NT) void k_pred_dir_lds(int nx, int ny, int P, int 
             const int j = r0 + ly, i = c0 + lx;
             const bool in = (j >= 1) && (j < rows);
             const size_t k = in ? (size_t)j * P + i : (size_t)P;
-            const double w = c.wyy[k], bn = c.byy[k], bs = c.byy[k - P];
-            syy[ly][lx] = in ? w * (bn * spy[ly + 1][lx + 1] - bs * spy[ly][lx + 1]) : 0.0;
+            const T w = c.wyy[k], bn = c.byy[k], bs = c.byy[k - P];
+            syy[ly][lx] = in ? w * (bn * spy[ly + 1][lx + 1] - bs * spy[ly][lx + 1]) : (T)0;
         }
         // node strains (rows r0-1 .. r0+HTY-1, cols c0-1 .. c0+TX-1)
         for (int e = threadIdx.x; e < (HTY + 1) * (TX + 1); e += NT) {
@@ -676,12 +777,12 @@ __global__ __launch_bounds__(NT) void k_pred_dir_lds(int nx, int ny, int P, int 
             const int j = r0 - 1 + ly, i = c0 - 1 + lx;
             const bool in = (j >= 0) && (j + 1 < rows) && (i >= 0) && (i + 1 < P);
             const size_t k = in ? (size_t)j * P + i : 0;
-            const double bxn = c.bxy[k + P], bxs = c.bxy[k], bye = c.byx[k + 1], byw = c.byx[k];
-            const double gxv = bxn * spx[ly + 1][lx] - bxs * spx[ly][lx];
-            const double gyv = bye * spy[ly][lx + 1] - byw * spy[ly][lx];
-            const double a = c.nxx[k], b = c.nxy[k], cc = c.nyx[k], dd = c.nyy[k];
-            snx[ly][lx] = in ? 0.5 * (a * gxv + b * gyv) : 0.0;
-            sny[ly][lx] = in ? 0.5 * (cc * gxv + dd * gyv) : 0.0;
+            const T bxn = c.bxy[k + P], bxs = c.bxy[k], bye = c.byx[k + 1], byw = c.byx[k];
+            const T gxv = bxn * spx[ly + 1][lx] - bxs * spx[ly][lx];
+            const T gyv = bye * spy[ly][lx + 1] - byw * spy[ly][lx];
+            const T a = c.nxx[k], b = c.nxy[k], cc = c.nyx[k], dd = c.nyy[k];
+            snx[ly][lx] = in ? (T)0.5 * (a * gxv + b * gyv) : (T)0;
+            sny[ly][lx] = in ? (T)0.5 * (cc * gxv + dd * gyv) : (T)0;
         }
     }
     __syncthreads();
@@ -691,19 +792,19 @@ __global__ __launch_bounds__(NT) void k_pred_dir_lds(int nx, int ny, int P, int 
             const int j = r0 + ly, i = c0 + tx;
             if (j >= rows) break;
             const size_t k = (size_t)j * P + i;
-            const double vu = pc.vu[k], vv = pc.vv[k];
-            const double bxx = c.bxx[k], bxy = c.bxy[k], byy = c.byy[k], byx = c.byx[k];
-            const double px = spx[ly + 1][tx + 1], py = spy[ly + 1][tx + 1];
-            const double kx = bxx * (sxx[ly][tx + 1] - sxx[ly][tx]) + bxy * (snx[ly + 1][tx + 1] - snx[ly][tx + 1]);
-            const double ky = byy * (syy[ly + 1][tx] - syy[ly][tx]) + byx * (sny[ly + 1][tx + 1] - sny[ly + 1][tx]);
-            const double qx = vu > 0.0 ? pc.rt * vu * px - pc.mu * kx : 0.0;
-            const double qy = vv > 0.0 ? pc.rt * vv * py - pc.mu * ky : 0.0;
-            const double pxo = vu > 0.0 ? px : 0.0, pyo = vv > 0.0 ? py : 0.0;
+            const T vu = pc.vu[k], vv = pc.vv[k];
+            const T bxx = c.bxx[k], bxy = c.bxy[k], byy = c.byy[k], byx = c.byx[k];
+            const T px = spx[ly + 1][tx + 1], py = spy[ly + 1][tx + 1];
+            const T kx = bxx * (sxx[ly][tx + 1] - sxx[ly][tx]) + bxy * (snx[ly + 1][tx + 1] - snx[ly][tx + 1]);
+            const T ky = byy * (syy[ly + 1][tx] - syy[ly][tx]) + byx * (sny[ly + 1][tx + 1] - sny[ly + 1][tx]);
+            const T qx = vu > (T)0 ? rt * vu * px - mu * kx : (T)0;
+            const T qy = vv > (T)0 ? rt * vv * py - mu * ky : (T)0;
+            const T pxo = vu > (T)0 ? px : (T)0, pyo = vv > (T)0 ? py : (T)0;
             pnew[k] = pxo;
             pnew[n + k] = pyo;
             q[k] = qx;
             q[n + k] = qy;
-            v[0] += pxo * qx + pyo * qy;
+            v[0] += (double)pxo * (double)qx + (double)pyo * (double)qy;
         }
     }
     put_partials<1>(v, pout, gridDim.x);
@@ -893,6 +994,20 @@ std::vector<std::pair<int, int>> mg_sizes(int nx, int ny) {
 }
 constexpr int MG_ARRS = 6;  // cx, cy, dinv, b, x, xt per coarse level
 
+// Float arrays of precision 1 (FP32 inner solves), in allocation order.
+// Pairs of face components are adjacent (the y array starts n floats after
+// the x array), as the face kernels index them.
+enum Arr32 {
+    G_CX, G_CY, G_DINV,                 // Poisson coefficients
+    G_R, G_X, G_P0, G_P1, G_Q, G_Z, G_ZT,  // Poisson inner vectors
+    G_VU, G_VV, G_BXX, G_BXY, G_BYY, G_BYX, G_WXX, G_WYY, G_NXX, G_NXY, G_NYX, G_NYY,
+    G_HDX, G_HDY,    // predictor Jacobi diagonal (pair)
+    G_PRX, G_PRY,    // predictor inner r (pair)
+    G_PXX, G_PXY,    // predictor inner x = correction (pair)
+    G_PP0X, G_PP0Y, G_PP1X, G_PP1Y, G_PQX, G_PQY,
+    G_COUNT
+};
+
 struct WsPlan {
     Layout L;
     size_t arr_bytes;   // bytes per array
@@ -901,10 +1016,13 @@ struct WsPlan {
     std::vector<size_t> mg_off;    // byte offset of each coarse level's arrays
     size_t pinv_off, idx_off;      // coarsest-grid pseudo-inverse and unknown list
     int ncoarse;                   // cells of the coarsest grid
+    // precision 1 only (else 0): float arrays and float coarse levels
+    size_t arr32_bytes, f32_off;
+    std::vector<size_t> mg32_off;
     size_t total;
 };
 
-WsPlan plan(int nx, int ny) {
+WsPlan plan(int nx, int ny, int precision) {
     WsPlan w;
     w.L = make_layout(nx, ny);
     w.arr_bytes = align_up(w.L.n * sizeof(double), 256);
@@ -929,6 +1047,19 @@ WsPlan plan(int nx, int ny) {
     off += align_up((size_t)w.ncoarse * w.ncoarse * sizeof(double), 256);
     w.idx_off = off;
     off += align_up((size_t)w.ncoarse * sizeof(int), 256);
+    w.arr32_bytes = 0;
+    w.f32_off = 0;
+    w.mg32_off.assign(w.mgL.size(), 0);
+    if (precision == 1) {
+        // n * 4 bytes is a multiple of 256 (the pitch is a multiple of 64)
+        w.arr32_bytes = w.L.n * sizeof(float);
+        w.f32_off = off;
+        off += w.arr32_bytes * G_COUNT;
+        for (size_t l = 1; l < w.mgL.size(); ++l) {
+            w.mg32_off[l] = off;
+            off += MG_ARRS * align_up(w.mgL[l].n * sizeof(float), 256);
+        }
+    }
     w.total = off;
     return w;
 }
@@ -944,9 +1075,14 @@ struct ccns_ctx {
     double *a[A_COUNT];
     double *part[PB_COUNT];
     CgState *st_pred, *st_pois;
+    CgState *st_pred_in, *st_pois_in;  // inner solves of precision 1
     DiagState *diag;
+    double *outer;      // totals of the FP64 residual statistics (precision 1)
     CgState *h_st;      // pinned host copies
     DiagState *h_diag;
+    double *h_outer;
+    float *f[G_COUNT];  // precision 1 arrays
+    int last_pois_in, last_pred_in;
     Dims dc, df;        // cell tiles (1 component) and face tiles (2 components)
     Dims dp;            // tiles of the Poisson stencil kernels (PTY rows)
     int conv_valid;
@@ -955,12 +1091,15 @@ struct ccns_ctx {
     int pbuf_pred, pbuf_pois;
     int init_nblk;      // groups of the last init kernel (its partials feed the first direction)
     // multigrid hierarchy (level 0 shares the Poisson arrays)
-    struct Level {
+    template <class T>
+    struct LevelT {
         Layout L;
         Dims d;      // PTY-row tiles
-        double *cx, *cy, *dinv, *b, *x, *xt;
+        T *cx, *cy, *dinv, *b, *x, *xt;
     };
+    using Level = LevelT<double>;
     std::vector<Level> mg;
+    std::vector<LevelT<float>> mg32;   // the same hierarchy in float (precision 1)
     double *pinv;
     int *pidx;
     int ncoarse_act;
@@ -1068,12 +1207,12 @@ void harvest_events(ccns_ctx *c, int kid) {
 
 // Runs CG iterations (after the caller launched the init kernel, whose
 // partials are in PB_INIT) until the device flags the end of the solve.
-// dir(first, par, pin, nin, pout) launches the direction+operator kernel and
-// returns its group count.
-template <class Dir, class Finish>
-ccns_status cg_loop(ccns_ctx *c, CgState *st, double *x, double *r, double *const pbuf[2], int &par_buf, double *q,
-                    const double *dinv, size_t ntot, int &last_it, Dir dir, Finish finish, ccns_solve_info *info,
-                    int kid) {
+// dir(first, par, pold, pnew, pin, nin, pout) launches the direction+operator
+// kernel and returns the number of partials it leaves in PB_DIR; finish()
+// runs after it.  T is the storage type of the vectors.
+template <class T, class Dir, class Finish>
+ccns_status cg_loop(ccns_ctx *c, CgState *st, T *x, T *r, T *const pbuf[2], int &par_buf, T *q, const T *dinv,
+                    size_t ntot, int &last_it, Dir dir, Finish finish, ccns_solve_info *info, int kid) {
     const int nl = flat_blocks(ntot);
     int chunk = std::max(4, last_it + 1);
     int it = 0;
@@ -1088,8 +1227,8 @@ ccns_status cg_loop(ccns_ctx *c, CgState *st, double *x, double *r, double *cons
                                c->part[PB_DIR]);
             if (tm) (void)hipEventRecord(next_event(c), c->stream);
             finish();
-            k_cg_update<<<nl, NT, 0, c->stream>>>(ntot, nl, dinv, x, r, pbuf[par_buf ^ 1], q, st, par,
-                                                  c->part[PB_DIR], nd, c->part[PB_UPD]);
+            k_cg_update<T><<<nl, NT, 0, c->stream>>>(ntot, nl, dinv, x, r, pbuf[par_buf ^ 1], q, st, par,
+                                                     c->part[PB_DIR], nd, c->part[PB_UPD]);
             if (tm) (void)hipEventRecord(next_event(c), c->stream);
             par_buf ^= 1;
             first = false;
@@ -1120,32 +1259,51 @@ void set_cg(ccns_ctx *c, CgState *st, double tol, int maxit, int zero_mean, int 
     h.n_active = std::max(n_active, 1);
     h.done = 1;
     (void)hipMemcpyAsync(st, &h, sizeof(CgState), hipMemcpyHostToDevice, c->stream);
+    (void)hipStreamSynchronize(c->stream);
 }
 
-// Pressure solve; b is in A_B with its sum's partials in PB_RHS (nin groups).
-ccns_status pressure_solve_dev(ccns_ctx *c, int nin, ccns_solve_info *info) {
-    PoisCoef pc = pois_coef(c);
-    k_pois_init<<<c->dc.nblk, NT, 0, c->stream>>>(c->dc, pc, c->a[A_B], c->a[A_PHI], c->a[A_R], c->st_pois,
-                                                  c->part[PB_RHS], nin, c->part[PB_INIT]);
-    c->init_nblk = c->dc.nblk;
-    double *pb[2] = {c->a[A_P0], c->a[A_P1]};
-    auto dir = [&](int first, int par, double *pold, double *pnew, const double *pin, int nin2, double *pout) {
-        k_pois_dir<<<c->dp.nblk, NT, 0, c->stream>>>(c->dp, pc, c->a[A_R], pold, pnew, c->a[A_Q], c->st_pois,
-                                                     first, par, pin, nin2, pout);
+// Relative tolerance of the next inner solve (precision 1).
+__global__ void k_set_tol(CgState *st, double tol2) {
+    if (threadIdx.x == 0) st->tol2 = tol2;
+}
+
+// Jacobi-preconditioned CG for the pressure; the init kernel's partials are
+// in PB_INIT (init_nblk groups).
+template <class T>
+ccns_status jacobi_cg(ccns_ctx *c, PoisCoefT<T> pc, CgState *st, T *x, T *r, T *p0, T *p1, T *q, int &last_it,
+                      ccns_solve_info *info) {
+    T *pb[2] = {p0, p1};
+    auto dir = [&](int first, int par, T *pold, T *pnew, const double *pin, int nin2, double *pout) {
+        k_pois_dir<T><<<c->dp.nblk, NT, 0, c->stream>>>(c->dp, pc, r, pold, pnew, q, st, first, par, pin, nin2,
+                                                        pout);
         return c->dp.nblk;
     };
-    return cg_loop(c, c->st_pois, c->a[A_PHI], c->a[A_R], pb, c->pbuf_pois, c->a[A_Q], c->a[A_DINV], c->w.L.n,
-                   c->last_pois_it, dir, [] {}, info, 0);
+    return cg_loop<T>(c, st, x, r, pb, c->pbuf_pois, q, pc.dinv, c->w.L.n, last_it, dir, [] {}, info, 0);
+}
+
+// Pressure solve (precision 0, Jacobi); b is in A_B with its sum's partials
+// in PB_RHS (nin groups).
+ccns_status pressure_solve_dev(ccns_ctx *c, int nin, ccns_solve_info *info) {
+    PoisCoef pc = pois_coef(c);
+    k_pois_init<false><<<c->dc.nblk, NT, 0, c->stream>>>(c->dc, pc, c->a[A_B], c->a[A_PHI], c->a[A_R], c->st_pois,
+                                                         c->part[PB_RHS], nin, c->part[PB_INIT], nullptr, nullptr,
+                                                         nullptr);
+    c->init_nblk = c->dc.nblk;
+    return jacobi_cg<double>(c, pc, c->st_pois, c->a[A_PHI], c->a[A_R], c->a[A_P0], c->a[A_P1], c->a[A_Q],
+                             c->last_pois_it, info);
 }
 
 constexpr int MG_NU = 2;          // pre- and post-smoothing sweeps
 constexpr double MG_OMEGA = 0.8;  // weighted-Jacobi damping
 
 // Builds the coarse levels on the host from the fine Poisson weights and
-// uploads them; the coarsest grid gets a dense pseudo-inverse.
+// uploads them (and their float copies in precision 1); the coarsest grid
+// gets a dense pseudo-inverse.
 ccns_status mg_setup(ccns_ctx *c, const HostCoef &hc) {
     const WsPlan &w = c->w;
+    const bool mix = c->prm.precision == 1;
     c->mg.clear();
+    c->mg32.clear();
     ccns_ctx::Level l0;
     l0.L = w.L;
     l0.d = make_dims(w.L, 1, PTY);
@@ -1156,7 +1314,20 @@ ccns_status mg_setup(ccns_ctx *c, const HostCoef &hc) {
     l0.x = c->a[A_Z];
     l0.xt = c->a[A_ZT];
     c->mg.push_back(l0);
+    if (mix) {
+        ccns_ctx::LevelT<float> f0;
+        f0.L = w.L;
+        f0.d = l0.d;
+        f0.cx = c->f[G_CX];
+        f0.cy = c->f[G_CY];
+        f0.dinv = c->f[G_DINV];
+        f0.b = c->f[G_R];
+        f0.x = c->f[G_Z];
+        f0.xt = c->f[G_ZT];
+        c->mg32.push_back(f0);
+    }
     std::vector<double> cx = hc.cx, cy = hc.cy, dinv = hc.dinv;
+    std::vector<std::vector<float>> keep;  // float copies in flight
     int nx = c->g.nx, ny = c->g.ny;
     for (size_t l = 1; l < w.mgL.size(); ++l) {
         const Layout &Lc = w.mgL[l];
@@ -1176,6 +1347,22 @@ ccns_status mg_setup(ccns_ctx *c, const HostCoef &hc) {
             HIPCHK(c, hipMemcpy2DAsync(dd[k], Lc.pitch * sizeof(double), src[k]->data(), Wc * sizeof(double),
                                        Wc * sizeof(double), Lc.ny + 2, hipMemcpyHostToDevice, c->stream));
         c->mg.push_back(lv);
+        if (mix) {
+            ccns_ctx::LevelT<float> fv;
+            fv.L = Lc;
+            fv.d = lv.d;
+            const size_t ab32 = align_up(Lc.n * sizeof(float), 256);
+            char *b32 = c->base + w.mg32_off[l];
+            float **d32[MG_ARRS] = {&fv.cx, &fv.cy, &fv.dinv, &fv.b, &fv.x, &fv.xt};
+            for (int k = 0; k < MG_ARRS; ++k) *d32[k] = (float *)(b32 + k * ab32);
+            float *df[3] = {fv.cx, fv.cy, fv.dinv};
+            for (int k = 0; k < 3; ++k) {
+                keep.emplace_back(src[k]->begin(), src[k]->end());
+                HIPCHK(c, hipMemcpy2DAsync(df[k], Lc.pitch * sizeof(float), keep.back().data(), Wc * sizeof(float),
+                                           Wc * sizeof(float), Lc.ny + 2, hipMemcpyHostToDevice, c->stream));
+            }
+            c->mg32.push_back(fv);
+        }
         cx.swap(cxc);
         cy.swap(cyc);
         dinv.swap(dic);
@@ -1221,73 +1408,72 @@ ccns_status mg_setup(ccns_ctx *c, const HostCoef &hc) {
     return CCNS_OK;
 }
 
-// z = V(b) on level l; returns the array holding the result.  On level 0
-// the last kernel also writes the residual statistics, reduced to one group
-// in PB_MG.
-double *vcycle(ccns_ctx *c, size_t l, const double *b) {
-    ccns_ctx::Level &L = c->mg[l];
+// z = V(b) on level l of a hierarchy; returns the array holding the result.
+// On level 0 the last kernel also writes the residual statistics, reduced to
+// one group in PB_MG.
+template <class T>
+T *vcycle(ccns_ctx *c, std::vector<ccns_ctx::LevelT<T>> &mg, size_t l, const T *b) {
+    ccns_ctx::LevelT<T> &L = mg[l];
     hipStream_t s = c->stream;
-    if (l + 1 == c->mg.size()) {
-        k_mg_coarsest<<<1, NT, 0, s>>>(c->ncoarse_act, c->pidx, c->pinv, b, L.x);
+    if (l + 1 == mg.size()) {
+        k_mg_coarsest<T><<<1, NT, 0, s>>>(c->ncoarse_act, c->pidx, c->pinv, b, L.x);
         return L.x;
     }
-    PoisCoef pc{L.cx, L.cy, L.dinv};
+    PoisCoefT<T> pc{L.cx, L.cy, L.dinv};
     const int gx = (L.L.nx + TX - 1) / TX, gy = (L.L.ny + MTY - 1) / MTY;
     const int nb = ((gx * gy + 7) / 8) * 8;
-    ccns_ctx::Level &C = c->mg[l + 1];
-    k_mg_down<<<nb, NT, 0, s>>>(L.L.nx, L.L.ny, L.L.pitch, gx, pc, b, L.x, C.L.pitch, C.L.nx, C.L.ny, C.dinv, C.b,
-                                MG_OMEGA);
-    const double *xc = vcycle(c, l + 1, C.b);
+    ccns_ctx::LevelT<T> &C = mg[l + 1];
+    const T om = (T)MG_OMEGA;
+    k_mg_down<T><<<nb, NT, 0, s>>>(L.L.nx, L.L.ny, L.L.pitch, gx, pc, b, L.x, C.L.pitch, C.L.nx, C.L.ny, C.dinv,
+                                   C.b, om);
+    const T *xc = vcycle<T>(c, mg, l + 1, C.b);
     if (l == 0) {
-        k_mg_up<true><<<nb, NT, 0, s>>>(L.L.nx, L.L.ny, L.L.pitch, gx, pc, b, L.x, xc, C.L.pitch, L.xt, MG_OMEGA,
-                                        c->part[PB_UPD], nb);
+        k_mg_up<T, true><<<nb, NT, 0, s>>>(L.L.nx, L.L.ny, L.L.pitch, gx, pc, b, L.x, xc, C.L.pitch, L.xt, om,
+                                           c->part[PB_UPD], nb);
         k_reduce_partials<4><<<1, NT, 0, s>>>(c->part[PB_UPD], nb, c->part[PB_MG]);
     } else {
-        k_mg_up<false><<<nb, NT, 0, s>>>(L.L.nx, L.L.ny, L.L.pitch, gx, pc, b, L.x, xc, C.L.pitch, L.xt, MG_OMEGA,
-                                         nullptr, nb);
+        k_mg_up<T, false><<<nb, NT, 0, s>>>(L.L.nx, L.L.ny, L.L.pitch, gx, pc, b, L.x, xc, C.L.pitch, L.xt, om,
+                                            nullptr, nb);
     }
     return L.xt;
 }
 
-// Multigrid-preconditioned CG for the pressure; b is in A_B with its sum's
-// partials in PB_RHS (nin groups); the start value is A_PHI.
-ccns_status pressure_solve_mg(ccns_ctx *c, int nin, ccns_solve_info *info) {
-    PoisCoef pc = pois_coef(c);
+// Multigrid-preconditioned CG on A x = f, the residual r of the start value
+// x being given.  pinit: partials whose slot 0 is |f|^2 (ninit groups), or
+// NULL when r is f itself (zero start value).
+template <class T>
+ccns_status mg_cg(ccns_ctx *c, std::vector<ccns_ctx::LevelT<T>> &mg, PoisCoefT<T> pc, CgState *st, T *x, T *r,
+                  T *p0, T *p1, T *q, const double *pinit, int ninit, int &last_it, ccns_solve_info *info) {
     const Dims &dp = c->dp;
-    k_pois_init<<<c->dc.nblk, NT, 0, c->stream>>>(c->dc, pc, c->a[A_B], c->a[A_PHI], c->a[A_R], c->st_pois,
-                                                  c->part[PB_RHS], nin, c->part[PB_INIT]);
-    const int ninit = c->dc.nblk;
     const size_t ntot = c->w.L.n;
     const int nl = flat_blocks(ntot);
-    double *pb[2] = {c->a[A_P0], c->a[A_P1]};
+    T *pb[2] = {p0, p1};
     int &pbuf = c->pbuf_pois;
-    double *z = vcycle(c, 0, c->a[A_R]);
-    int chunk = std::max(2, c->last_pois_it + 1);
+    T *z = vcycle<T>(c, mg, 0, r);
+    int chunk = std::max(2, last_it + 1);
     int it = 0;
     for (;;) {
         for (int u = 0; u < chunk; ++u, ++it) {
             const int par = it & 1;
-            const bool tm = c->timing && (it % 2 == 0) && it < c->last_pois_it;
+            const bool tm = c->timing && (it % 2 == 0) && it < last_it;
             if (tm) (void)hipEventRecord(next_event(c), c->stream);
-            k_pois_dir_z<<<dp.nblk, NT, 0, c->stream>>>(dp, pc, z, pb[pbuf], pb[pbuf ^ 1], c->a[A_Q], c->st_pois,
-                                                        it == 0 ? 1 : 0, par, c->part[PB_MG], 1,
-                                                        c->part[PB_INIT], ninit, c->part[PB_DIR]);
+            k_pois_dir_z<T><<<dp.nblk, NT, 0, c->stream>>>(dp, pc, z, pb[pbuf], pb[pbuf ^ 1], q, st, it == 0 ? 1 : 0,
+                                                           par, c->part[PB_MG], 1, pinit, ninit, c->part[PB_DIR]);
             if (tm) (void)hipEventRecord(next_event(c), c->stream);
-            k_cg_update<<<nl, NT, 0, c->stream>>>(ntot, nl, c->a[A_DINV], c->a[A_PHI], c->a[A_R], pb[pbuf ^ 1],
-                                                  c->a[A_Q], c->st_pois, par, c->part[PB_DIR], dp.nblk,
-                                                  c->part[PB_UPD]);
+            k_cg_update<T><<<nl, NT, 0, c->stream>>>(ntot, nl, pc.dinv, x, r, pb[pbuf ^ 1], q, st, par,
+                                                     c->part[PB_DIR], dp.nblk, c->part[PB_UPD]);
             if (tm) (void)hipEventRecord(next_event(c), c->stream);
             pbuf ^= 1;
-            z = vcycle(c, 0, c->a[A_R]);
+            z = vcycle<T>(c, mg, 0, r);
         }
         HIPCHK(c, hipGetLastError());
-        HIPCHK(c, hipMemcpyAsync(c->h_st, c->st_pois, sizeof(CgState), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipMemcpyAsync(c->h_st, st, sizeof(CgState), hipMemcpyDeviceToHost, c->stream));
         HIPCHK(c, hipStreamSynchronize(c->stream));
         if (c->timing) harvest_events(c, 0);
         if (c->h_st->done) break;
         chunk = 2;
     }
-    c->last_pois_it = c->h_st->it_final;
+    last_it = c->h_st->it_final;
     if (info) {
         info->iterations = c->h_st->it_final;
         info->outer = 1;
@@ -1297,7 +1483,105 @@ ccns_status pressure_solve_mg(ccns_ctx *c, int nin, ccns_solve_info *info) {
     return (ccns_status)c->h_st->status;
 }
 
-ccns_status predict_dev(ccns_ctx *c, ccns_solve_info *info) {
+// Pressure solve (precision 0, multigrid); b is in A_B with its sum's
+// partials in PB_RHS (nin groups); the start value is A_PHI.
+ccns_status pressure_solve_mg(ccns_ctx *c, int nin, ccns_solve_info *info) {
+    PoisCoef pc = pois_coef(c);
+    k_pois_init<false><<<c->dc.nblk, NT, 0, c->stream>>>(c->dc, pc, c->a[A_B], c->a[A_PHI], c->a[A_R], c->st_pois,
+                                                         c->part[PB_RHS], nin, c->part[PB_INIT], nullptr, nullptr,
+                                                         nullptr);
+    return mg_cg<double>(c, c->mg, pc, c->st_pois, c->a[A_PHI], c->a[A_R], c->a[A_P0], c->a[A_P1], c->a[A_Q],
+                         c->part[PB_INIT], c->dc.nblk, c->last_pois_it, info);
+}
+
+// Limits of the refinement loops of precision 1.
+constexpr int MAX_OUTER = 20;
+constexpr double INNER_TOL_MIN = 1e-5, INNER_TOL_MAX = 0.1;
+
+double inner_tol(double reduction) {
+    return std::min(INNER_TOL_MAX, std::max(INNER_TOL_MIN, 0.5 * reduction));
+}
+
+ccns_status read_outer(ccns_ctx *c, int n) {
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipMemcpyAsync(c->h_outer, c->outer, n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return CCNS_OK;
+}
+
+// Pressure solve in precision 1: iterative refinement.  Each sweep forms the
+// residual r = f - A phi in FP64 (FP64 coefficients), solves A d = r in float
+// (float coefficients and vectors, FP64 dot products) to a relative
+// tolerance, and adds d to phi in FP64.  Stops when max |cont(U^{n+1}, D)|
+// / (u_ref h) = (tau/rho) max |r| / (u_ref h) is at most div_tol / 2 (div_tol
+// > 0), else when |r|_2 <= pcg_tol |f|_2.
+ccns_status pressure_solve_mixed(ccns_ctx *c, int nin, ccns_solve_info *info) {
+    PoisCoef pc = pois_coef(c);
+    PoisCoefT<float> pf{c->f[G_CX], c->f[G_CY], c->f[G_DINV]};
+    const ccns_params &p = c->prm;
+    const double sdiv = (p.tau / p.rho) / (p.u_ref * std::min(c->g.hx, c->g.hy));
+    double bn2 = 0.0, rn2 = 0.0;
+    int inner_its = 0, sweeps = 0;
+    ccns_status st = CCNS_ENOTCONV;
+    for (int o = 0;; ++o) {
+        k_pois_init<true><<<c->dc.nblk, NT, 0, c->stream>>>(c->dc, pc, c->a[A_B], c->a[A_PHI], nullptr,
+                                                            c->st_pois_in, o == 0 ? c->part[PB_RHS] : nullptr, nin,
+                                                            c->part[PB_INIT], c->f[G_R], c->f[G_X], c->f[G_DINV]);
+        c->init_nblk = c->dc.nblk;
+        k_reduce_partials<7, 1><<<1, NT, 0, c->stream>>>(c->part[PB_INIT], c->dc.nblk, c->outer);
+        ccns_status s = read_outer(c, 8);
+        if (s != CCNS_OK) return s;
+        if (o == 0) bn2 = c->h_outer[5];
+        rn2 = c->h_outer[6];
+        const double rmax = c->h_outer[7];
+        double need;  // reduction of the residual still needed
+        bool conv;
+        if (p.div_tol > 0.0) {
+            conv = sdiv * rmax <= 0.5 * p.div_tol;
+            need = rmax > 0.0 ? 0.5 * p.div_tol / (sdiv * rmax) : 1.0;
+        } else {
+            conv = rn2 <= p.pcg_tol * p.pcg_tol * bn2;
+            need = rn2 > 0.0 ? p.pcg_tol * std::sqrt(bn2 / rn2) : 1.0;
+        }
+        if (!(bn2 > 0.0) || c->n_active == 0) conv = true;
+        if (conv) {
+            st = CCNS_OK;
+            break;
+        }
+        if (o >= MAX_OUTER) break;
+        const double it = inner_tol(need);
+        k_set_tol<<<1, 1, 0, c->stream>>>(c->st_pois_in, it * it);
+        ccns_solve_info si{};
+        if (p.precond == 1)
+            mg_cg<float>(c, c->mg32, pf, c->st_pois_in, c->f[G_X], c->f[G_R], c->f[G_P0], c->f[G_P1], c->f[G_Q],
+                         nullptr, 0, c->last_pois_in, &si);
+        else
+            jacobi_cg<float>(c, pf, c->st_pois_in, c->f[G_X], c->f[G_R], c->f[G_P0], c->f[G_P1], c->f[G_Q],
+                             c->last_pois_in, &si);
+        if (si.status == CCNS_EDEVICE) return CCNS_EDEVICE;
+        inner_its += si.iterations;
+        ++sweeps;
+        k_add_correction<<<flat_blocks(c->w.L.n), NT, 0, c->stream>>>(c->w.L.n, c->a[A_PHI], c->f[G_X]);
+    }
+    c->last_pois_it = inner_its;
+    if (info) {
+        info->iterations = inner_its;
+        info->outer = sweeps;
+        info->rel_residual = bn2 > 0.0 ? std::sqrt(rn2 / bn2) : 0.0;
+        info->status = st;
+    }
+    return st;
+}
+
+// Pressure solve on b in A_B (partials of its sum in PB_RHS), by precision
+// and preconditioner.
+ccns_status pressure_solve_any(ccns_ctx *c, int nin, ccns_solve_info *info) {
+    if (c->prm.precision == 1) return pressure_solve_mixed(c, nin, info);
+    return c->prm.precond == 1 ? pressure_solve_mg(c, nin, info) : pressure_solve_dev(c, nin, info);
+}
+
+// conv^n and the predictor right-hand side; U* := U^n.
+void predictor_rhs(ccns_ctx *c) {
     PredCoef pc = pred_coef(c);
     k_pred_rhs<<<c->df.nblk, NT, 0, c->stream>>>(c->df, pc, c->a[A_AX], c->a[A_AY], c->a[A_HBX], c->a[A_HBY],
                                                  c->a[A_DX], c->a[A_DY], c->a[A_UX], c->a[A_UY], c->a[A_P],
@@ -1305,23 +1589,89 @@ ccns_status predict_dev(ccns_ctx *c, ccns_solve_info *info) {
                                                  c->a[A_RHSX], c->a[A_USX], c->prm.rho, c->prm.gx, c->prm.gy,
                                                  c->conv_valid);
     c->conv_valid = 1;
-    k_pred_init<<<c->df.nblk, NT, 0, c->stream>>>(c->df, pc, c->a[A_RHSX], c->a[A_USX], c->a[A_PRX], c->st_pred,
-                                                  c->part[PB_INIT]);
+}
+
+// Jacobi-PCG on H x = f with storage type T; the init kernel's partials are
+// in PB_INIT.
+template <class T>
+ccns_status pred_cg(ccns_ctx *c, PredCoefT<T> pc, CgState *st, T *x, T *r, T *p0, T *p1, T *q, int &last_it,
+                    ccns_solve_info *info) {
     c->init_nblk = c->df.nblk;
-    double *pb[2] = {c->a[A_PP0X], c->a[A_PP1X]};
+    T *pb[2] = {p0, p1};
     const Layout &L = c->w.L;
     const int gx = L.pitch / TX, gy = (L.rows + HTY - 1) / HTY;
     const int nb = ((gx * gy + 7) / 8) * 8;
-    auto dir = [&](int first, int par, double *pold, double *pnew, const double *pin, int nin, double *pout) {
-        k_pred_dir_lds<<<nb, NT, 0, c->stream>>>(L.nx, L.ny, L.pitch, L.rows, gx, gy, L.n, pc, c->a[A_PRX], pold,
-                                                 pnew, c->a[A_PQX], c->st_pred, first, par, pin, nin,
-                                                 c->part[PB_RHS]);
+    auto dir = [&](int first, int par, T *pold, T *pnew, const double *pin, int nin, double *pout) {
+        k_pred_dir_lds<T><<<nb, NT, 0, c->stream>>>(L.nx, L.ny, L.pitch, L.rows, gx, gy, L.n, pc, r, pold, pnew, q,
+                                                    st, first, par, pin, nin, c->part[PB_RHS]);
         (void)pout;
         return 1;
     };
     auto finish = [&]() { k_reduce_partials<1><<<1, NT, 0, c->stream>>>(c->part[PB_RHS], nb, c->part[PB_DIR]); };
-    return cg_loop(c, c->st_pred, c->a[A_USX], c->a[A_PRX], pb, c->pbuf_pred, c->a[A_PQX], c->a[A_HDX],
-                   2 * c->w.L.n, c->last_pred_it, dir, finish, info, 2);
+    return cg_loop<T>(c, st, x, r, pb, c->pbuf_pred, q, pc.hdx, 2 * c->w.L.n, last_it, dir, finish, info, 2);
+}
+
+ccns_status predict_dev(ccns_ctx *c, ccns_solve_info *info) {
+    PredCoef pc = pred_coef(c);
+    predictor_rhs(c);
+    k_pred_init<false><<<c->df.nblk, NT, 0, c->stream>>>(c->df, pc, c->a[A_RHSX], c->a[A_USX], c->a[A_PRX],
+                                                         c->st_pred, c->part[PB_INIT], nullptr, nullptr, nullptr);
+    PredCoefT<double> pd{ViscCoefT<double>{pc.vc.bxx, pc.vc.bxy, pc.vc.byy, pc.vc.byx, pc.vc.wxx, pc.vc.wyy,
+                                           pc.vc.nxx, pc.vc.nxy, pc.vc.nyx, pc.vc.nyy},
+                         pc.vu, pc.vv, pc.hdx, pc.hdy, pc.rt, pc.mu};
+    return pred_cg<double>(c, pd, c->st_pred, c->a[A_USX], c->a[A_PRX], c->a[A_PP0X], c->a[A_PP1X], c->a[A_PQX],
+                           c->last_pred_it, info);
+}
+
+// Predictor in precision 1: iterative refinement as for the pressure, with
+// the FP64 residual rhs - H U* and float inner Jacobi-PCG; stops when
+// |r|_2 <= pred_tol |rhs|_2.
+ccns_status predict_mixed(ccns_ctx *c, ccns_solve_info *info) {
+    PredCoef pc = pred_coef(c);
+    PredCoefT<float> pf{ViscCoefT<float>{c->f[G_BXX], c->f[G_BXY], c->f[G_BYY], c->f[G_BYX], c->f[G_WXX],
+                                         c->f[G_WYY], c->f[G_NXX], c->f[G_NXY], c->f[G_NYX], c->f[G_NYY]},
+                        c->f[G_VU], c->f[G_VV], c->f[G_HDX], c->f[G_HDY], pc.rt, pc.mu};
+    const double tol = c->prm.pred_tol;
+    predictor_rhs(c);
+    double fn2 = 0.0, rn2 = 0.0;
+    int inner_its = 0, sweeps = 0;
+    ccns_status st = CCNS_ENOTCONV;
+    for (int o = 0;; ++o) {
+        k_pred_init<true><<<c->df.nblk, NT, 0, c->stream>>>(c->df, pc, c->a[A_RHSX], c->a[A_USX], nullptr,
+                                                            c->st_pred_in, c->part[PB_INIT], c->f[G_PRX],
+                                                            c->f[G_PXX], c->f[G_HDX]);
+        k_reduce_partials<7><<<1, NT, 0, c->stream>>>(c->part[PB_INIT], c->df.nblk, c->outer);
+        ccns_status s = read_outer(c, 7);
+        if (s != CCNS_OK) return s;
+        fn2 = c->h_outer[5];
+        rn2 = c->h_outer[6];
+        if (!(fn2 > 0.0) || rn2 <= tol * tol * fn2) {
+            st = CCNS_OK;
+            break;
+        }
+        if (o >= MAX_OUTER) break;
+        const double it = inner_tol(tol * std::sqrt(fn2 / rn2));
+        k_set_tol<<<1, 1, 0, c->stream>>>(c->st_pred_in, it * it);
+        ccns_solve_info si{};
+        pred_cg<float>(c, pf, c->st_pred_in, c->f[G_PXX], c->f[G_PRX], c->f[G_PP0X], c->f[G_PP1X], c->f[G_PQX],
+                       c->last_pred_in, &si);
+        if (si.status == CCNS_EDEVICE) return CCNS_EDEVICE;
+        inner_its += si.iterations;
+        ++sweeps;
+        k_add_correction<<<flat_blocks(2 * c->w.L.n), NT, 0, c->stream>>>(2 * c->w.L.n, c->a[A_USX], c->f[G_PXX]);
+    }
+    c->last_pred_it = inner_its;
+    if (info) {
+        info->iterations = inner_its;
+        info->outer = sweeps;
+        info->rel_residual = fn2 > 0.0 ? std::sqrt(rn2 / fn2) : 0.0;
+        info->status = st;
+    }
+    return st;
+}
+
+ccns_status predict_any(ccns_ctx *c, ccns_solve_info *info) {
+    return c->prm.precision == 1 ? predict_mixed(c, info) : predict_dev(c, info);
 }
 
 ccns_status diag_dev(ccns_ctx *c, int update_p, ccns_step_info *info) {
@@ -1351,8 +1701,7 @@ ccns_status correct_dev(ccns_ctx *c, int update_p, ccns_step_info *info) {
                                                  c->a[A_USY], c->a[A_B], c->prm.rho / c->prm.tau,
                                                  c->part[PB_RHS]);
     ccns_solve_info si{};
-    ccns_status s = c->prm.precond == 1 ? pressure_solve_mg(c, c->dc.nblk, &si)
-                                        : pressure_solve_dev(c, c->dc.nblk, &si);
+    ccns_status s = pressure_solve_any(c, c->dc.nblk, &si);
     if (info) info->poisson = si;
     k_correct<<<c->dc.nblk, NT, 0, c->stream>>>(c->dc, c->a[A_GX], c->a[A_GY], c->a[A_USX], c->a[A_USY],
                                                 c->a[A_PHI], c->a[A_UX], c->a[A_UY], c->prm.tau / c->prm.rho);
@@ -1366,9 +1715,8 @@ ccns_status correct_dev(ccns_ctx *c, int update_p, ccns_step_info *info) {
 extern "C" {
 
 size_t ccns_workspace_bytes(const ccns_grid *grid, const ccns_params *params) {
-    (void)params;
     if (!grid || grid->nx < 2 || grid->ny < 2) return 0;
-    return plan(grid->nx, grid->ny).total;
+    return plan(grid->nx, grid->ny, params ? params->precision : 0).total;
 }
 
 const char *ccns_last_error(const ccns_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
@@ -1379,12 +1727,13 @@ ccns_status ccns_ctx_create(const ccns_grid *grid, const ccns_params *params, co
     if (!out) return CCNS_EINVAL;
     *out = nullptr;
     if (!grid || !params || !caps_host || !dirichlet_host || !dev_workspace) return CCNS_EINVAL;
-    if (params->precision != 0 || params->precond < 0 || params->precond > 1) return CCNS_EINVAL;
+    if (params->precision < 0 || params->precision > 1 || params->precond < 0 || params->precond > 1)
+        return CCNS_EINVAL;
     ccns_ctx *c = new (std::nothrow) ccns_ctx();
     if (!c) return CCNS_ENOMEM;
     c->g = *grid;
     c->prm = *params;
-    c->w = plan(grid->nx, grid->ny);
+    c->w = plan(grid->nx, grid->ny, params->precision);
     if (ws_bytes < c->w.total) {
         delete c;
         return CCNS_ENOMEM;
@@ -1399,13 +1748,19 @@ ccns_status ccns_ctx_create(const ccns_grid *grid, const ccns_params *params, co
     for (int k = 0; k < PB_COUNT; ++k) c->part[k] = (double *)(c->base + c->w.part_off + (size_t)k * c->w.part_bytes);
     c->st_pred = (CgState *)(c->base + c->w.state_off);
     c->st_pois = c->st_pred + 1;
-    c->diag = (DiagState *)(c->st_pois + 1);
+    c->st_pred_in = c->st_pred + 2;
+    c->st_pois_in = c->st_pred + 3;
+    c->diag = (DiagState *)(c->st_pred + 4);
+    c->outer = (double *)(c->base + c->w.state_off + 2048);
+    for (int k = 0; k < G_COUNT; ++k)
+        c->f[k] = params->precision == 1 ? (float *)(c->base + c->w.f32_off + (size_t)k * c->w.arr32_bytes) : nullptr;
     c->dc = make_dims(c->w.L, 1, TY);
     c->df = make_dims(c->w.L, 2, TY);
     c->dp = make_dims(c->w.L, 1, PTY);
     c->init_nblk = c->dc.nblk;
     c->conv_valid = 0;
     c->last_pois_it = c->last_pred_it = 16;
+    c->last_pois_in = c->last_pred_in = 8;
     c->pbuf_pred = c->pbuf_pois = 0;
     c->timing = 0;
     c->evused = 0;
@@ -1420,8 +1775,9 @@ ccns_status ccns_ctx_create(const ccns_grid *grid, const ccns_params *params, co
     }
     c->n_active = hc.n_active;
     if (hipHostMalloc((void **)&c->h_st, sizeof(CgState)) != hipSuccess ||
-        hipHostMalloc((void **)&c->h_diag, sizeof(DiagState)) != hipSuccess) {
-        delete c;
+        hipHostMalloc((void **)&c->h_diag, sizeof(DiagState)) != hipSuccess ||
+        hipHostMalloc((void **)&c->h_outer, 8 * sizeof(double)) != hipSuccess) {
+        ccns_ctx_destroy(c);
         return CCNS_EDEVICE;
     }
     // zero the whole workspace, then upload the coefficient fields
@@ -1439,6 +1795,30 @@ ccns_status ccns_ctx_create(const ccns_grid *grid, const ccns_params *params, co
             return s;
         }
     }
+    if (params->precision == 1) {
+        // float copies of the coefficients of the inner solves
+        const std::vector<double> *s32[] = {&hc.cx, &hc.cy, &hc.dinv};
+        const int d32[] = {G_CX, G_CY, G_DINV};
+        const std::vector<double> *p32[] = {&hc.vu, &hc.vv, &hc.bxx, &hc.bxy, &hc.byy, &hc.byx, &hc.wxx, &hc.wyy,
+                                            &hc.nxx, &hc.nxy, &hc.nyx, &hc.nyy, &hc.hdx, &hc.hdy};
+        const int q32[] = {G_VU, G_VV, G_BXX, G_BXY, G_BYY, G_BYX, G_WXX, G_WYY, G_NXX, G_NXY, G_NYX, G_NYY,
+                           G_HDX, G_HDY};
+        std::vector<float> tmp;
+        const size_t W = grid->nx + 2;
+        auto up32 = [&](float *dst, const std::vector<double> &v) {
+            tmp.assign(v.begin(), v.end());
+            return hipMemcpy2DAsync(dst, c->w.L.pitch * sizeof(float), tmp.data(), W * sizeof(float),
+                                    W * sizeof(float), grid->ny + 2, hipMemcpyHostToDevice, c->stream) == hipSuccess &&
+                   hipStreamSynchronize(c->stream) == hipSuccess;
+        };
+        bool ok = true;
+        for (int k = 0; k < 3 && ok; ++k) ok = up32(c->f[d32[k]], *s32[k]);
+        for (int k = 0; k < 14 && ok; ++k) ok = up32(c->f[q32[k]], *p32[k]);
+        if (!ok) {
+            ccns_ctx_destroy(c);
+            return CCNS_EDEVICE;
+        }
+    }
     // state: U = D everywhere (the caller sets the initial field), P = Phi = 0
     to_dev(c, c->a[A_UX], hc.dx.data(), hipMemcpyHostToDevice);
     to_dev(c, c->a[A_UY], hc.dy.data(), hipMemcpyHostToDevice);
@@ -1448,6 +1828,8 @@ ccns_status ccns_ctx_create(const ccns_grid *grid, const ccns_params *params, co
     }
     set_cg(c, c->st_pred, params->pred_tol, params->pred_maxit, 0, hc.n_uact + hc.n_vact);
     set_cg(c, c->st_pois, params->pcg_tol, params->pcg_maxit, 1, hc.n_active);
+    set_cg(c, c->st_pred_in, INNER_TOL_MIN, params->pred_maxit, 0, hc.n_uact + hc.n_vact);
+    set_cg(c, c->st_pois_in, INNER_TOL_MIN, params->pcg_maxit, 1, hc.n_active);
     if (hipStreamSynchronize(c->stream) != hipSuccess) {
         ccns_ctx_destroy(c);
         return CCNS_EDEVICE;
@@ -1461,6 +1843,7 @@ void ccns_ctx_destroy(ccns_ctx *ctx) {
     (void)hipStreamSynchronize(ctx->stream);
     if (ctx->h_st) (void)hipHostFree(ctx->h_st);
     if (ctx->h_diag) (void)hipHostFree(ctx->h_diag);
+    if (ctx->h_outer) (void)hipHostFree(ctx->h_outer);
     for (hipEvent_t e : ctx->evpool) (void)hipEventDestroy(e);
     delete ctx;
 }
@@ -1536,7 +1919,7 @@ ccns_status ccns_pressure_solve(ccns_ctx *c, const double *b, double *phi, ccns_
     ccns_status s = to_dev(c, c->a[A_B], b, hipMemcpyDeviceToDevice);
     if (s != CCNS_OK) return s;
     k_pois_sum<<<c->dc.nblk, NT, 0, c->stream>>>(c->dc, pois_coef(c), c->a[A_B], c->part[PB_RHS]);
-    s = c->prm.precond == 1 ? pressure_solve_mg(c, c->dc.nblk, info) : pressure_solve_dev(c, c->dc.nblk, info);
+    s = pressure_solve_any(c, c->dc.nblk, info);
     if (phi) {
         ccns_status s2 = from_dev(c, phi, c->a[A_PHI], hipMemcpyDeviceToDevice);
         if (s2 != CCNS_OK) return s2;
@@ -1558,7 +1941,7 @@ ccns_status ccns_project(ccns_ctx *c, ccns_step_info *info) {
 
 ccns_status ccns_predict(ccns_ctx *c, ccns_solve_info *info) {
     if (!c) return CCNS_EINVAL;
-    return predict_dev(c, info);
+    return predict_any(c, info);
 }
 
 ccns_status ccns_correct(ccns_ctx *c, ccns_step_info *info) {
@@ -1571,7 +1954,7 @@ ccns_status ccns_step(ccns_ctx *c, int nsteps, ccns_step_info *info) {
     ccns_step_info si{};
     ccns_status worst = CCNS_OK;
     for (int n = 0; n < nsteps; ++n) {
-        ccns_status s1 = predict_dev(c, &si.pred);
+        ccns_status s1 = predict_any(c, &si.pred);
         if (s1 == CCNS_EDEVICE) return s1;
         ccns_status s2 = correct_dev(c, 1, &si);
         if (s2 == CCNS_EDEVICE) return s2;

@@ -8,7 +8,8 @@ import workloads as W
 from oracle import derived, geometry, pmii
 
 
-def case_setup(case, pcg_tol=None, pred_tol=1e-12, visc_form="geometric", caps=None, precond="mg"):
+def case_setup(case, pcg_tol=None, pred_tol=1e-12, visc_form="geometric", caps=None, precond="mg",
+               precision=0, div_tol=1e-8):
     from paper_2211_10698_amd import ccns
 
     g = case.grid
@@ -22,7 +23,7 @@ def case_setup(case, pcg_tol=None, pred_tol=1e-12, visc_form="geometric", caps=N
     st = pmii.Stepper(pr, prm, Dx, Dy, min(g.hx, g.hy))
     form = {"geometric": 0, "literal": 1, "mean": 2}[visc_form]
     cp = ccns.make_params(case.rho, case.mu, case.tau, u_ref=case.u_inf, pcg_tol=tol, pred_tol=pred_tol,
-                          visc_form=form,
+                          visc_form=form, precision=precision, div_tol=div_tol,
                           precond={"jacobi": ccns.PRECOND_JACOBI, "mg": ccns.PRECOND_MG}[precond])
     capsarr = np.stack([caps[k] for k in ccns.CAP_NAMES])
     ctx = ccns.Context(g, cp, capsarr, Dx, Dy)

@@ -43,6 +43,15 @@ def test_argument_validation_without_gpu():
     h = C.c_void_p()
     p = ccns.make_params(1.0, 0.01, 0.01)
     assert L.ccns_ctx_create(C.byref(g), C.byref(p), None, None, None, 0, None, C.byref(h)) == ccns.EINVAL
+    # precision 1 needs the float arrays on top of the FP64 workspace
+    p1 = ccns.make_params(1.0, 0.01, 0.01, precision=1)
+    assert L.ccns_workspace_bytes(C.byref(g), C.byref(p1)) > L.ccns_workspace_bytes(C.byref(g), C.byref(p))
+    # unknown precision or preconditioner: rejected before any device work
+    caps = np.zeros(L.ccns_caps_count(C.byref(g)))
+    dir2 = np.zeros(2 * 10 * 10)
+    for bad_p in (ccns.make_params(1.0, 0.01, 0.01, precision=2), ccns.make_params(1.0, 0.01, 0.01, precond=5)):
+        assert L.ccns_ctx_create(C.byref(g), C.byref(bad_p), caps.ctypes.data, dir2.ctypes.data,
+                                 C.c_void_p(256), 1 << 30, None, C.byref(h)) == ccns.EINVAL
 
 
 @pytest.mark.parametrize("name", ["cylinder_64", "offcentre_40", "channel_cylinder_2048x1024"])
