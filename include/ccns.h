@@ -242,6 +242,28 @@ ccns_status ccns_timing(ccns_ctx *ctx, int enable, double *ms, long *count);
 /* Diagnostics of the current state (FP64 reductions on the device). */
 ccns_status ccns_diagnostics(ccns_ctx *ctx, ccns_step_info *info);
 
+/* Batches of independent simulations of any sizes (the ragged batches of
+ * many uneven simulations that share one GPU).  A batch borrows contexts
+ * the caller created and still owns; each should have its own HIP stream,
+ * so that the kernels of different simulations run concurrently.
+ *
+ * ccns_batch_create: n >= 1 distinct contexts; nthreads host threads drive
+ *   them (each runs whole projection steps of one simulation at a time, the
+ *   largest simulations first; 0 = one per simulation up to 16).  Errors:
+ *   CCNS_EINVAL (n < 1, NULL or repeated context, nthreads < 0).
+ * ccns_batch_step: advances every simulation by nsteps projection steps,
+ *   exactly as ccns_step on each context alone would (the kernels' fixed
+ *   reduction order makes each result bit-identical to a solo run).
+ *   per_sim (may be NULL): n ccns_step_info, the last step of each;
+ *   per_status (may be NULL): n statuses.  Returns the worst status:
+ *   CCNS_EDEVICE if any simulation hit a device error, else a solver status
+ *   (CCNS_ENOTCONV, CCNS_EBREAKDOWN) if any, else CCNS_OK.
+ * ccns_batch_destroy: frees the batch (not the contexts). */
+typedef struct ccns_batch ccns_batch;
+ccns_status ccns_batch_create(int n, ccns_ctx *const *ctxs, int nthreads, ccns_batch **out);
+ccns_status ccns_batch_step(ccns_batch *batch, int nsteps, ccns_step_info *per_sim, int *per_status);
+void ccns_batch_destroy(ccns_batch *batch);
+
 #ifdef __cplusplus
 }
 #endif

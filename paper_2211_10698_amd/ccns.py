@@ -106,6 +106,12 @@ def lib():
         L.ccns_timing.argtypes = [C.c_void_p, C.c_int, P(C.c_double), P(C.c_long)]
         L.ccns_step.restype = C.c_int
         L.ccns_step.argtypes = [C.c_void_p, C.c_int, P(StepInfo)]
+        L.ccns_batch_create.restype = C.c_int
+        L.ccns_batch_create.argtypes = [C.c_int, P(C.c_void_p), C.c_int, P(C.c_void_p)]
+        L.ccns_batch_step.restype = C.c_int
+        L.ccns_batch_step.argtypes = [C.c_void_p, C.c_int, P(StepInfo), P(C.c_int)]
+        L.ccns_batch_destroy.restype = None
+        L.ccns_batch_destroy.argtypes = [C.c_void_p]
         _lib = L
     return _lib
 
@@ -113,7 +119,7 @@ def lib():
 EXPORTED = ("ccns_caps_count", "ccns_capacities", "ccns_workspace_bytes", "ccns_ctx_create",
             "ccns_ctx_destroy", "ccns_last_error", "ccns_field_set", "ccns_field_get", "ccns_apply",
             "ccns_pressure_solve", "ccns_project", "ccns_step", "ccns_predict", "ccns_correct",
-            "ccns_diagnostics", "ccns_timing")
+            "ccns_diagnostics", "ccns_timing", "ccns_batch_create", "ccns_batch_step", "ccns_batch_destroy")
 
 
 class CcnsError(RuntimeError):
@@ -274,3 +280,40 @@ class Context:
         info = StepInfo()
         self._chk(lib().ccns_diagnostics(self.h, C.byref(info)), "diagnostics")
         return info
+
+
+class Batch:
+    """A ragged batch of contexts stepped together (ccns_batch_*).  The
+    contexts stay owned by the caller and must outlive the batch."""
+
+    def __init__(self, contexts: Sequence["Context"], nthreads: int = 0):
+        self.contexts = list(contexts)
+        arr = (C.c_void_p * len(self.contexts))(*[c.h.value for c in self.contexts])
+        h = C.c_void_p()
+        st = lib().ccns_batch_create(len(self.contexts), arr, nthreads, C.byref(h))
+        if st != OK:
+            raise CcnsError(st, "ccns_batch_create")
+        self.h = h
+
+    def step(self, n=1, check=True):
+        """Advances every simulation by n steps; returns (worst status,
+        per-simulation StepInfo list, per-simulation statuses)."""
+        m = len(self.contexts)
+        infos = (StepInfo * m)()
+        sts = (C.c_int * m)()
+        st = lib().ccns_batch_step(self.h, n, infos, sts)
+        if check and st not in (OK,):
+            raise CcnsError(st, "ccns_batch_step")
+        return st, list(infos), list(sts)
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().ccns_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+

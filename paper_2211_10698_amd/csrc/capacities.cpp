@@ -17,6 +17,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <queue>
 #include <vector>
 
 #include "ccns.h"
@@ -30,6 +31,24 @@ struct Fluid {
     int nbody;
     ccns_levelset_fn fn;
     void *user;
+    double lip = INFINITY;  // Lipschitz bound of the level set (see lipschitz())
+
+    // A Lipschitz bound of the level set: 1 for circles (a distance), 1/min(a,b)
+    // for ellipses (|grad| of sqrt((x/a)^2 + (y/b)^2) - 1), none for NACA
+    // sections (the thickness slope is unbounded at the nose) or a user
+    // function.  The level set is a minimum over bodies, bounded by the
+    // largest of their bounds.
+    double lipschitz() const {
+        if (fn) return INFINITY;
+        double L = 0.0;
+        for (int k = 0; k < nbody; ++k) {
+            const ccns_body &b = bodies[k];
+            if (b.kind == CCNS_CIRCLE) L = std::max(L, 1.0);
+            else if (b.kind == CCNS_ELLIPSE) L = std::max(L, 1.0 / std::min(b.a, b.b));
+            else return INFINITY;
+        }
+        return L;
+    }
 
     static double naca_yt(double xi, double t) {
         xi = std::min(std::max(xi, 0.0), 1.0);
@@ -107,6 +126,20 @@ struct Fluid {
             }
         }
     }
+    // +1 when the rectangle is certainly all fluid, -1 certainly all solid,
+    // 0 when it may contain interface points: first the bodies' boxes, then,
+    // with a Lipschitz bound, the level set at the centre against the
+    // bound times the half diagonal.
+    int classify(double xa, double xb, double ya, double yb, double margin) const {
+        if (!maybe_cut(xa, xb, ya, yb, margin)) return 1;
+        if (std::isfinite(lip)) {
+            const double c = (*this)(0.5 * (xa + xb), 0.5 * (ya + yb));
+            const double r = lip * 0.5 * std::hypot(xb - xa, yb - ya);
+            if (c > r) return 1;
+            if (c < -r) return -1;
+        }
+        return 0;
+    }
     // True when the rectangle may contain interface points.
     bool maybe_cut(double xa, double xb, double ya, double yb, double margin) const {
         if (fn) return true;
@@ -121,8 +154,11 @@ struct Fluid {
 };
 
 // Fluid sub-intervals of [a, b] for g(s) > 0; returns the count (<= cap).
+// lip: a Lipschitz bound of g along the line (INFINITY if unknown); a local
+// minimum of |g| larger than lip times the sample spacing cannot hide a root
+// pair, and is not searched.
 template <class G>
-int fluid_intervals(const G &g, double a, double b, double *lo, double *hi, int cap) {
+int fluid_intervals(const G &g, double a, double b, double *lo, double *hi, int cap, double lip) {
     if (!(b > a)) return 0;
     const int n = 16;
     double s[n + 1], v[n + 1];
@@ -132,10 +168,12 @@ int fluid_intervals(const G &g, double a, double b, double *lo, double *hi, int 
     }
     double roots[64];
     int nr = 0;
+    // bisection down to 1e-16 relative width, or to adjacent doubles
     auto bisect = [&](double l, double r) {
         bool pl = g(l) > 0.0;
         for (int it = 0; it < 200 && r - l > 1e-16 * std::max(1.0, std::fabs(r)); ++it) {
             double m = 0.5 * (l + r);
+            if (!(m > l && m < r)) break;
             if ((g(m) > 0.0) == pl) l = m; else r = m;
         }
         return 0.5 * (l + r);
@@ -149,6 +187,7 @@ int fluid_intervals(const G &g, double a, double b, double *lo, double *hi, int 
         if ((v[l] > 0.0) != p || (v[r] > 0.0) != p) continue;
         if (std::fabs(v[k]) > std::fabs(v[l]) || std::fabs(v[k]) > std::fabs(v[r])) continue;
         if (std::fabs(v[k]) == std::fabs(v[l]) && std::fabs(v[k]) == std::fabs(v[r])) continue;  // flat
+        if (std::fabs(v[k]) > lip * (b - a) / n) continue;  // every point of [s_l, s_r] is too far
         // zoom towards the extremum of g nearest zero: 33 samples a level,
         // keeping the two sample intervals around the best one (robust when
         // g has several dips or a kink between the coarse samples)
@@ -217,14 +256,14 @@ class Integrator {
 
     double vseg(double x, double ya, double yb) const {
         double lo[32], hi[32];
-        int m = fluid_intervals([&](double y) { return f_(x, y); }, ya, yb, lo, hi, 32);
+        int m = fluid_intervals([&](double y) { return f_(x, y); }, ya, yb, lo, hi, 32, f_.lip);
         double L = 0.0;
         for (int k = 0; k < m; ++k) L += hi[k] - lo[k];
         return L;
     }
     double hseg(double y, double xa, double xb) const {
         double lo[32], hi[32];
-        int m = fluid_intervals([&](double x) { return f_(x, y); }, xa, xb, lo, hi, 32);
+        int m = fluid_intervals([&](double x) { return f_(x, y); }, xa, xb, lo, hi, 32, f_.lip);
         double L = 0.0;
         for (int k = 0; k < m; ++k) L += hi[k] - lo[k];
         return L;
@@ -232,10 +271,10 @@ class Integrator {
     Moments rect(double xa, double xb, double ya, double yb) const {
         Moments out{0, 0, 0};
         if (!(xb > xa) || !(yb > ya)) return out;
-        std::vector<double> pts{xa, xb};
+        std::vector<double> pts{xa, xb}, tangents;
         for (double yy : {ya, yb}) {
             double lo[32], hi[32];
-            int m = fluid_intervals([&](double x) { return f_(x, yy); }, xa, xb, lo, hi, 32);
+            int m = fluid_intervals([&](double x) { return f_(x, yy); }, xa, xb, lo, hi, 32, f_.lip);
             for (int k = 0; k < m; ++k) {
                 if (lo[k] > xa) pts.push_back(lo[k]);
                 if (hi[k] < xb) pts.push_back(hi[k]);
@@ -259,7 +298,7 @@ class Integrator {
             std::sort(probe.begin(), probe.end());
             auto count = [&](double x) {
                 double lo[32], hi[32];
-                int m = fluid_intervals([&](double y) { return f_(x, y); }, ya, yb, lo, hi, 32);
+                int m = fluid_intervals([&](double y) { return f_(x, y); }, ya, yb, lo, hi, 32, f_.lip);
                 int c = 0;
                 for (int k = 0; k < m; ++k) c += (lo[k] > ya) + (hi[k] < yb);
                 return c;
@@ -273,18 +312,39 @@ class Integrator {
                 int cl = cnt[k];
                 while (r - l > 1e-15 * std::max(1.0, std::fabs(r))) {
                     double m = 0.5 * (l + r);
+                    if (!(m > l && m < r)) break;
                     if (count(m) == cl) l = m; else r = m;
                 }
                 extra.push_back(0.5 * (l + r));
             }
             pts.insert(pts.end(), extra.begin(), extra.end());
             std::sort(pts.begin(), pts.end());
+            tangents.swap(extra);
         }
-        double tol = 1e-14 * (xb - xa) * (yb - ya);
+        // At a vertical tangent the wet length behaves like the square root of
+        // the distance to it: pieces that end there are integrated in
+        // u = sqrt(|x - x_t|), where the integrand is smooth.
+        auto singular = [&](double x) {
+            return std::find(tangents.begin(), tangents.end(), x) != tangents.end();
+        };
+        const double tol = 1e-14 * (xb - xa) * (yb - ya);
+        auto add = [&](const Moments &m) { out.a += m.a; out.mx += m.mx; out.my += m.my; };
         for (size_t k = 0; k + 1 < pts.size(); ++k) {
-            if (pts[k + 1] <= pts[k]) continue;
-            Moments m = adapt(pts[k], pts[k + 1], ya, yb, tol * (pts[k + 1] - pts[k]) / (xb - xa), 0);
-            out.a += m.a; out.mx += m.mx; out.my += m.my;
+            const double a = pts[k], b = pts[k + 1];
+            if (b <= a) continue;
+            const double t = tol * (b - a) / (xb - xa);
+            const bool sa = singular(a), sb = singular(b);
+            if (!sa && !sb) {
+                add(adapt(a, b, ya, yb, t, 0.0, 0));
+            } else if (sa && !sb) {
+                add(adapt(0.0, std::sqrt(b - a), ya, yb, t, a, 1));
+            } else if (!sa && sb) {
+                add(adapt(0.0, std::sqrt(b - a), ya, yb, t, b, -1));
+            } else {
+                const double m = 0.5 * (a + b);
+                add(adapt(0.0, std::sqrt(m - a), ya, yb, 0.5 * t, a, 1));
+                add(adapt(0.0, std::sqrt(b - m), ya, yb, 0.5 * t, b, -1));
+            }
         }
         return out;
     }
@@ -292,7 +352,7 @@ class Integrator {
   private:
     void column(double x, double ya, double yb, double &L, double &M) const {
         double lo[32], hi[32];
-        int m = fluid_intervals([&](double y) { return f_(x, y); }, ya, yb, lo, hi, 32);
+        int m = fluid_intervals([&](double y) { return f_(x, y); }, ya, yb, lo, hi, 32, f_.lip);
         L = 0.0;
         M = 0.0;
         for (int k = 0; k < m; ++k) {
@@ -300,16 +360,22 @@ class Integrator {
             M += 0.5 * (hi[k] * hi[k] - lo[k] * lo[k]);
         }
     }
-    // one G7K15 panel; returns Kronrod estimates and the max error estimate
-    double panel(double p, double q, double ya, double yb, Moments &k) const {
+    // One G7K15 panel over [p, q] in the integration variable u, with
+    // x = u (mode 0) or x = x0 + mode u^2 (mode +-1, Jacobian 2u); returns
+    // the Kronrod estimates and the largest error estimate.
+    double panel(double p, double q, double ya, double yb, Moments &k, double x0, int mode) const {
         double c = 0.5 * (p + q), h = 0.5 * (q - p);
         double ka = 0, kx = 0, ky = 0, ga = 0, gx = 0, gy = 0;
         for (int i = 0; i < 8; ++i) {
             int nside = (i == 7) ? 1 : 2;
             for (int sgn = 0; sgn < nside; ++sgn) {
-                double x = c + (sgn ? -1.0 : 1.0) * h * kXK[i];
+                const double u = c + (sgn ? -1.0 : 1.0) * h * kXK[i];
+                const double x = mode == 0 ? u : x0 + mode * u * u;
+                const double jac = mode == 0 ? 1.0 : 2.0 * u;
                 double L, M;
                 column(x, ya, yb, L, M);
+                L *= jac;
+                M *= jac;
                 ka += kWK[i] * L; kx += kWK[i] * x * L; ky += kWK[i] * M;
                 if (i % 2 == 1) {
                     double w = kWG[i / 2];
@@ -318,26 +384,58 @@ class Integrator {
             }
         }
         k.a = ka * h; k.mx = kx * h; k.my = ky * h;
-        double e = std::max(std::fabs(ka - ga), std::max(std::fabs(kx - gx) / std::max(1.0, std::fabs(c)),
+        const double xs = mode == 0 ? c : x0;
+        double e = std::max(std::fabs(ka - ga), std::max(std::fabs(kx - gx) / std::max(1.0, std::fabs(xs)),
                                                          std::fabs(ky - gy) / std::max(1.0, std::fabs(yb))));
         return e * h;
     }
-    Moments adapt(double p, double q, double ya, double yb, double tol, int depth) const {
-        Moments k;
-        double e = panel(p, q, ya, yb, k);
-        // the estimate itself carries rounding of about 1e-16 of the panel
-        // integral: never ask for less than a few hundred ulps of it.  Next to
-        // a vertical tangent the wet length is only known to the rounding of
-        // the level set (the root pair there is ill-conditioned), so the
-        // estimate stays above any tolerance on a band about 1e-13 wide: stop
-        // halving at 2^-30 of the rectangle, where such a panel's whole
-        // integral is below 1e-9 of the rectangle's and its error far below.
-        const double floor_ = 256.0 * 2.2e-16 * (q - p) * (yb - ya);
-        if (e <= std::max(tol, floor_) || depth >= 30 || q - p < 1e-15 * std::max(1.0, std::fabs(q))) return k;
-        double m = 0.5 * (p + q);
-        Moments l = adapt(p, m, ya, yb, 0.5 * tol, depth + 1);
-        Moments r = adapt(m, q, ya, yb, 0.5 * tol, depth + 1);
-        return Moments{l.a + r.a, l.mx + r.mx, l.my + r.my};
+    // Globally adaptive Gauss-Kronrod on [p, q] (in u): the panel with the
+    // largest error estimate is halved until the estimates add up to at most
+    // tol or the panel budget is spent.  A panel is final when its estimate is
+    // below the noise of its integrand (the roots that bound the wet length
+    // are known to about 1e-16 max(1, |y|), and the estimate itself carries
+    // rounding of about 1e-16 of the integral) or when its x-extent is at the
+    // resolution of x.  Next to a vertical tangent the root pair is
+    // ill-conditioned and the wet length noisier still; the budget bounds the
+    // work spent there, on contributions far below the tolerance.
+    static constexpr int MAX_PANELS = 400;
+    Moments adapt(double p, double q, double ya, double yb, double tol, double x0, int mode) const {
+        struct Pan {
+            double p, q, e;
+            Moments k;
+        };
+        auto cmp = [](const Pan &a, const Pan &b) { return a.e < b.e; };
+        std::priority_queue<Pan, std::vector<Pan>, decltype(cmp)> open(cmp);
+        Moments sum{0, 0, 0};
+        double esum = 0.0;
+        const double ynoise = 16.0 * 2.2e-16 * std::max(1.0, std::max(std::fabs(ya), std::fabs(yb)));
+        const double inoise = 256.0 * 2.2e-16 * (yb - ya);
+        auto push = [&](double a, double b) {
+            Pan pn{a, b, 0.0, Moments{0, 0, 0}};
+            const double e = panel(a, b, ya, yb, pn.k, x0, mode);
+            const double wx = mode == 0 ? b - a : b * b - a * a;  // x-extent
+            const double xr = mode == 0 ? b : x0;
+            if (e <= wx * std::max(ynoise, inoise) || wx < 1e-15 * std::max(1.0, std::fabs(xr))) {
+                sum.a += pn.k.a; sum.mx += pn.k.mx; sum.my += pn.k.my;
+                return;
+            }
+            pn.e = e;
+            esum += e;
+            open.push(pn);
+        };
+        push(p, q);
+        for (int npan = 1; !open.empty() && esum > tol && npan < MAX_PANELS; ++npan) {
+            const Pan w = open.top();
+            open.pop();
+            esum -= w.e;
+            const double m = 0.5 * (w.p + w.q);
+            push(w.p, m);
+            push(m, w.q);
+        }
+        for (; !open.empty(); open.pop()) {
+            sum.a += open.top().k.a; sum.mx += open.top().k.mx; sum.my += open.top().k.my;
+        }
+        return sum;
     }
     const Fluid &f_;
 };
@@ -359,9 +457,11 @@ GridOut grid_caps(const Fluid &fl, const Integrator &in, const std::vector<doubl
         xa = std::max(xa, bx0); xb = std::min(xb, bx1);
         ya = std::max(ya, by0); yb = std::min(yb, by1);
         if (!(xb > xa) || !(yb > ya)) return Moments{0, 0, 0};
-        if (!fl.maybe_cut(xa, xb, ya, yb, margin))
+        const int cl = fl.classify(xa, xb, ya, yb, margin);
+        if (cl > 0)
             return Moments{(xb - xa) * (yb - ya), 0.5 * (xb * xb - xa * xa) * (yb - ya),
                            0.5 * (yb * yb - ya * ya) * (xb - xa)};
+        if (cl < 0) return Moments{0, 0, 0};
         return in.rect(xa, xb, ya, yb);
     };
     auto vseg = [&](double x, double ya, double yb, bool wet) -> double {
@@ -369,7 +469,8 @@ GridOut grid_caps(const Fluid &fl, const Integrator &in, const std::vector<doubl
         if (!inside) return 0.0;
         ya = std::max(ya, by0); yb = std::min(yb, by1);
         if (!(yb > ya)) return 0.0;
-        if (!fl.maybe_cut(x, x, ya, yb, margin)) return yb - ya;
+        const int cl = fl.classify(x, x, ya, yb, margin);
+        if (cl != 0) return cl > 0 ? yb - ya : 0.0;
         return in.vseg(x, ya, yb);
     };
     auto hseg = [&](double y, double xa, double xb, bool wet) -> double {
@@ -377,7 +478,8 @@ GridOut grid_caps(const Fluid &fl, const Integrator &in, const std::vector<doubl
         if (!inside) return 0.0;
         xa = std::max(xa, bx0); xb = std::min(xb, bx1);
         if (!(xb > xa)) return 0.0;
-        if (!fl.maybe_cut(xa, xb, y, y, margin)) return xb - xa;
+        const int cl = fl.classify(xa, xb, y, y, margin);
+        if (cl != 0) return cl > 0 ? xb - xa : 0.0;
         return in.hseg(y, xa, xb);
     };
 #pragma omp parallel for schedule(dynamic, 4)
@@ -435,6 +537,7 @@ extern "C" ccns_status ccns_capacities(const ccns_grid *grid, const ccns_body *b
     const double hx = grid->hx, hy = grid->hy, x0 = grid->x0, y0 = grid->y0;
     const double x1 = x0 + nx * hx, y1 = y0 + ny * hy;
     Fluid fl{bodies, nbody, fn, user};
+    fl.lip = fl.lipschitz();
     Integrator in(fl);
     std::vector<double> xe(nx + 3), ye(ny + 3), xc(nx + 3), yc(ny + 3);
     for (int i = 0; i < nx + 3; ++i) { xe[i] = x0 + (i - 1.0) * hx; xc[i] = x0 + (i - 0.5) * hx; }

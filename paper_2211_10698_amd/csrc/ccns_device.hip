@@ -23,7 +23,9 @@
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <atomic>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "ccns.h"
@@ -1980,5 +1982,104 @@ ccns_status ccns_diagnostics(ccns_ctx *c, ccns_step_info *info) {
     if (!c) return CCNS_EINVAL;
     return diag_dev(c, 0, info);
 }
+
+}  // extern "C"
+
+struct ccns_batch {
+    std::vector<ccns_ctx *> sims;
+    std::vector<int> order;  // simulation indices, largest grid first
+    int nthreads;
+};
+
+namespace {
+// Severity order of statuses for the batch result.
+int severity(ccns_status s) {
+    switch (s) {
+    case CCNS_OK: return 0;
+    case CCNS_ENOTCONV: return 1;
+    case CCNS_EBREAKDOWN: return 2;
+    case CCNS_ESTATE: return 3;
+    case CCNS_EINVAL: return 4;
+    case CCNS_ENOMEM: return 5;
+    default: return 6;  // CCNS_EDEVICE
+    }
+}
+}  // namespace
+
+extern "C" {
+
+ccns_status ccns_batch_create(int n, ccns_ctx *const *ctxs, int nthreads, ccns_batch **out) {
+    if (!out) return CCNS_EINVAL;
+    *out = nullptr;
+    if (n < 1 || !ctxs || nthreads < 0) return CCNS_EINVAL;
+    std::vector<ccns_ctx *> v, sorted;
+    try {
+        v.assign(ctxs, ctxs + n);
+        sorted = v;
+    } catch (...) {
+        return CCNS_ENOMEM;
+    }
+    for (ccns_ctx *c : v)
+        if (!c) return CCNS_EINVAL;
+    std::sort(sorted.begin(), sorted.end());
+    if (std::adjacent_find(sorted.begin(), sorted.end()) != sorted.end()) return CCNS_EINVAL;
+    ccns_batch *b = new (std::nothrow) ccns_batch();
+    if (!b) return CCNS_ENOMEM;
+    try {
+        b->sims = v;
+        b->order.resize(n);
+    } catch (...) {
+        delete b;
+        return CCNS_ENOMEM;
+    }
+    for (int k = 0; k < n; ++k) b->order[k] = k;
+    std::stable_sort(b->order.begin(), b->order.end(), [&](int x, int y) {
+        return (long)v[x]->g.nx * v[x]->g.ny > (long)v[y]->g.nx * v[y]->g.ny;
+    });
+    b->nthreads = nthreads > 0 ? nthreads : std::min(n, 16);
+    *out = b;
+    return CCNS_OK;
+}
+
+ccns_status ccns_batch_step(ccns_batch *b, int nsteps, ccns_step_info *per_sim, int *per_status) {
+    if (!b || nsteps < 0) return CCNS_EINVAL;
+    const int n = (int)b->sims.size();
+    std::vector<ccns_status> st;
+    std::vector<ccns_step_info> info;
+    try {
+        st.assign(n, CCNS_OK);
+        info.resize(n);
+    } catch (...) {
+        return CCNS_ENOMEM;
+    }
+    std::atomic<int> next{0};
+    auto worker = [&]() {
+        for (;;) {
+            const int k = next.fetch_add(1);
+            if (k >= n) return;
+            const int s = b->order[k];
+            st[s] = ccns_step(b->sims[s], nsteps, &info[s]);
+        }
+    };
+    const int nt = std::min(b->nthreads, n);
+    std::vector<std::thread> pool;
+    try {
+        pool.reserve(nt > 1 ? nt - 1 : 0);
+        for (int t = 1; t < nt; ++t) pool.emplace_back(worker);
+    } catch (...) {
+        // fewer threads than asked for: the ones started and this one share the work
+    }
+    worker();
+    for (std::thread &t : pool) t.join();
+    ccns_status worst = CCNS_OK;
+    for (int s = 0; s < n; ++s) {
+        if (severity(st[s]) > severity(worst)) worst = st[s];
+        if (per_sim) per_sim[s] = info[s];
+        if (per_status) per_status[s] = st[s];
+    }
+    return worst;
+}
+
+void ccns_batch_destroy(ccns_batch *b) { delete b; }
 
 }  // extern "C"

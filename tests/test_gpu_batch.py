@@ -1,0 +1,120 @@
+"""Ragged batches: several uneven simulations stepped together through
+ccns_batch_step (one host thread and one HIP stream per simulation) give
+bit for bit the fields and solver figures of each simulation stepped alone,
+and each member matches the oracle as a solo run does."""
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import geometry, pmii
+from tests.gpu_common import rel
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _cases():
+    return [
+        ("cyl64", W.cylinder_64(), 0),
+        ("chan130", W.scaled_cylinder(130, 73, 2.6, 1.46, seed=5), 0),
+        ("cyl96_mixed", W.scaled_cylinder(96, 96, 1.0, 1.0, seed=7), 1),
+        ("ell200", W.Case("ell200", W.GridSpec(200, 120, 0.0, 0.0, 1.0, 0.6),
+                          [W.Body(W.ELLIPSE, 0.41, 0.3, a=0.12, b=0.06, angle=0.4)], re=200.0, steps=3,
+                          noise=1e-2, seed=8), 0),
+        ("cyl40", W.scaled_cylinder(40, 40, 1.0, 1.0, seed=9), 1),
+        ("cyl260", W.scaled_cylinder(260, 132, 2.0, 1.015, seed=10), 0),
+    ]
+
+
+_CAPS = {}
+
+
+def _context(case, precision, stream):
+    from paper_2211_10698_amd import ccns
+    g = case.grid
+    if case.name not in _CAPS:
+        _CAPS[case.name] = ccns.ccns_capacities(g, case.bodies)
+    caps = _CAPS[case.name]
+    Dx, Dy = W.dirichlet(case)
+    prm = ccns.make_params(case.rho, case.mu, case.tau, u_ref=case.u_inf, pcg_tol=1e-10, pred_tol=1e-12,
+                           precision=precision, div_tol=1e-8)
+    ctx = ccns.Context(g, prm, caps, Dx, Dy, stream=stream)
+    px, py = W.perturbation(case)
+    sh = (g.ny + 2, g.nx + 2)
+    J, I = np.indices(sh)
+    au = (I >= 1) & (I <= g.nx - 1) & (J >= 1) & (J <= g.ny) & (caps[7] > 0)
+    av = (I >= 1) & (I <= g.nx) & (J >= 1) & (J <= g.ny - 1) & (caps[14] > 0)
+    ctx.set_field(ccns.F_UX, np.where(au, case.u_inf + px, Dx))
+    ctx.set_field(ccns.F_UY, np.where(av, py, Dy))
+    ctx.project()
+    return ctx
+
+
+def _state(ctx):
+    from paper_2211_10698_amd import ccns
+    return [ctx.get_field(f).cpu().numpy() for f in (ccns.F_UX, ccns.F_UY, ccns.F_P, ccns.F_PHI)]
+
+
+def test_batch_matches_solo_runs_bit_for_bit():
+    from paper_2211_10698_amd import ccns
+    cases = _cases()
+    nsteps = 3
+    solo = []
+    for name, case, prec in cases:
+        print(f"[batch] solo {name}", flush=True)
+        ctx = _context(case, prec, torch.cuda.current_stream())
+        infos = [ctx.step(1) for _ in range(nsteps)]
+        solo.append((_state(ctx), infos[-1].as_dict()))
+        ctx.close()
+    streams = [torch.cuda.Stream() for _ in cases]
+    ctxs = [_context(case, prec, s) for (name, case, prec), s in zip(cases, streams)]
+    torch.cuda.synchronize()
+    batch = ccns.Batch(ctxs, nthreads=4)
+    print("[batch] batch step", flush=True)
+    st, infos, sts = batch.step(nsteps)
+    assert st == ccns.OK and all(s == ccns.OK for s in sts)
+    for (name, _, _), ctx, info, (ref, rinfo) in zip(cases, ctxs, infos, solo):
+        got = _state(ctx)
+        for a, b in zip(got, ref):
+            assert np.array_equal(a, b), name
+        assert info.as_dict() == rinfo, name
+    batch.close()
+    for c in ctxs:
+        c.close()
+
+
+def test_batch_member_matches_oracle():
+    """The 64x64 cylinder inside a batch against the oracle (10 steps at
+    tight tolerances, as the solo trajectory test)."""
+    from paper_2211_10698_amd import ccns
+    from oracle import derived
+    case = W.cylinder_64()
+    g = case.grid
+    caps = geometry.capacities(g, case.bodies)
+    pr = derived.prepare(caps, g.nx, g.ny)
+    Dx, Dy = W.dirichlet(case)
+    st = pmii.Stepper(pr, pmii.Params(rho=case.rho, mu=case.mu, tau=case.tau, pcg_tol=1e-13, pred_tol=1e-14),
+                      Dx, Dy, g.hx)
+    s0 = pmii.initial_state(pr, Dx, Dy, case.u_inf, W.perturbation(case))
+    capsarr = np.stack([caps[k] for k in ccns.CAP_NAMES])
+    prm = ccns.make_params(case.rho, case.mu, case.tau, pcg_tol=1e-13, pred_tol=1e-14)
+    streams = [torch.cuda.Stream() for _ in range(3)]
+    ctxs = [ccns.Context(g, prm, capsarr, Dx, Dy, stream=s) for s in streams]
+    for c in ctxs:
+        c.set_field(ccns.F_UX, s0.Ux)
+        c.set_field(ccns.F_UY, s0.Uy)
+        c.project()
+    st.project(s0)
+    batch = ccns.Batch(ctxs, nthreads=3)
+    for _ in range(case.steps):
+        st.step(s0)
+    status, infos, _ = batch.step(case.steps)
+    assert status == ccns.OK
+    for c in ctxs:
+        assert rel(c.get_field(ccns.F_UX).cpu().numpy(), s0.Ux) < 1e-11
+        assert rel(c.get_field(ccns.F_UY).cpu().numpy(), s0.Uy) < 1e-11
+    batch.close()
+    for c in ctxs:
+        c.close()

@@ -52,6 +52,14 @@ def test_argument_validation_without_gpu():
     for bad_p in (ccns.make_params(1.0, 0.01, 0.01, precision=2), ccns.make_params(1.0, 0.01, 0.01, precond=5)):
         assert L.ccns_ctx_create(C.byref(g), C.byref(bad_p), caps.ctypes.data, dir2.ctypes.data,
                                  C.c_void_p(256), 1 << 30, None, C.byref(h)) == ccns.EINVAL
+    # batches: empty, NULL member, repeated member (checked before any member is read)
+    bh = C.c_void_p()
+    fake = (C.c_void_p * 2)(4096, 4096)
+    assert L.ccns_batch_create(0, fake, 0, C.byref(bh)) == ccns.EINVAL
+    assert L.ccns_batch_create(2, (C.c_void_p * 2)(4096, None), 0, C.byref(bh)) == ccns.EINVAL
+    assert L.ccns_batch_create(2, fake, 0, C.byref(bh)) == ccns.EINVAL
+    assert L.ccns_batch_create(1, fake, -1, C.byref(bh)) == ccns.EINVAL
+    assert L.ccns_batch_step(None, 1, None, None) == ccns.EINVAL
 
 
 @pytest.mark.parametrize("name", ["cylinder_64", "offcentre_40", "channel_cylinder_2048x1024"])
