@@ -51,6 +51,8 @@ WORKLOADS = {
     "channel_cylinder_2048x1024": W.channel_cylinder_2048,
     "cylinder_64": W.cylinder_64,
     "naca0012_4096x2048": W.naca_4096,
+    "batched_cylinders_256": None,   # ragged batch, see run_batched
+    "serving_trace": None,           # served requests, see run_serving
 }
 
 
@@ -140,12 +142,12 @@ def calibrate_copy(reps=3):
 
 
 def unknown_masks(caps, nx, ny):
-    """Velocity unknowns: faces interior to the box with fluid in their
-    staggered control volume (the same rule the library applies)."""
+    """Velocity unknowns: open faces (A > 0) interior to the box with fluid
+    in their staggered control volume (the rule the library applies)."""
     sh = (ny + 2, nx + 2)
     J, I = np.indices(sh)
-    au = (I >= 1) & (I <= nx - 1) & (J >= 1) & (J <= ny) & (caps[7] > 0)
-    av = (I >= 1) & (I <= nx) & (J >= 1) & (J <= ny - 1) & (caps[14] > 0)
+    au = (I >= 1) & (I <= nx - 1) & (J >= 1) & (J <= ny) & (caps[7] > 0) & (caps[1] > 0)
+    av = (I >= 1) & (I <= nx) & (J >= 1) & (J <= ny - 1) & (caps[14] > 0) & (caps[2] > 0)
     return au, av
 
 
@@ -158,7 +160,7 @@ def cpu_baseline(case, n_cg_per_step, iters_sample=20):
 
     g = case.grid
     caps = geometry.capacities(g, case.bodies)
-    pr = derived.prepare(caps, g.nx, g.ny)
+    pr = derived.prepare(caps, g.nx, g.ny, vol_floor=case.mass_floor * g.hx * g.hy)
     Dx, Dy = W.dirichlet(case)
     prm = pmii.Params(rho=case.rho, mu=case.mu, tau=case.tau, pcg_tol=case.pcg_tol)
     st = pmii.Stepper(pr, prm, Dx, Dy, min(g.hx, g.hy))
@@ -190,6 +192,146 @@ def cpu_baseline(case, n_cg_per_step, iters_sample=20):
     }
 
 
+def host_inputs(ccns, case):
+    """Host part of a simulation's set-up (no GPU calls): capacities from the
+    library and the seeded inputs."""
+    g = case.grid
+    caps = ccns.ccns_capacities(g, case.bodies)
+    Dx, Dy = W.dirichlet(case)
+    au, av = unknown_masks(caps, g.nx, g.ny)
+    px, py = W.perturbation(case)
+    return caps, Dx, Dy, np.where(au, case.u_inf + px, Dx), np.where(av, py, Dy)
+
+
+def setup_context(ccns, case, precision, stream, host):
+    """Context, initial field and initial projection of one simulation (set-up,
+    outside any timed region)."""
+    caps, Dx, Dy, ux0, uy0 = host
+    params = ccns.make_params(case.rho, case.mu, case.tau, u_ref=case.u_inf, pcg_tol=case.pcg_tol,
+                              pred_tol=1e-12, precision=precision, div_tol=1e-8, mass_floor=case.mass_floor)
+    ctx = ccns.Context(case.grid, params, caps, Dx, Dy, stream=stream)
+    ctx.set_field(ccns.F_UX, ux0)
+    ctx.set_field(ccns.F_UY, uy0)
+    ctx.project()
+    return ctx
+
+
+def run_batched(args):
+    """The ragged batch: 256 cylinder simulations of 128^2 .. 1024^2 cells
+    (seeded sizes, radii, centres and Reynolds numbers), each on its own
+    stream, advanced together by ccns_batch_step.  A step advances every
+    simulation by one projection step; value = total cell-steps / time."""
+    import concurrent.futures as cf
+
+    import torch
+    from paper_2211_10698_amd import ccns
+
+    cases = W.batched_cylinders(256)
+    prec = 1 if args.precision == "mixed" else 0
+    torch.cuda.set_device(0)
+    t_setup = time.perf_counter()
+    streams = [torch.cuda.Stream() for _ in cases]
+    ctxs = []
+    with cf.ThreadPoolExecutor(max_workers=8) as ex:
+        for case, stream, host in zip(cases, streams, ex.map(lambda c: host_inputs(ccns, c), cases)):
+            ctxs.append(setup_context(ccns, case, prec, stream, host))
+    torch.cuda.synchronize()
+    cells = sum(c.grid.nx * c.grid.ny for c in cases)
+    print(f"[bench] setup {time.perf_counter() - t_setup:.1f}s: {len(cases)} simulations, {cells} cells",
+          file=sys.stderr, flush=True)
+    batch = ccns.Batch(ctxs, nthreads=16)
+    for k in range(args.warmup):
+        st, infos, _ = batch.step(1)
+        print(f"[bench] warmup {k}: worst div_rel {max(i.div_rel for i in infos):.2e}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    divs, cg, pred = [], [], []
+    for k in range(args.steps):
+        st, infos, _ = batch.step(1)
+        divs.append(max(i.div_rel for i in infos))
+        cg.append(float(np.mean([i.poisson.iterations for i in infos])))
+        pred.append(float(np.mean([i.pred.iterations for i in infos])))
+        print(f"[bench] step {k}: worst div_rel {divs[-1]:.2e}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    sizes = {}
+    for c in cases:
+        sizes[c.grid.nx] = sizes.get(c.grid.nx, 0) + 1
+    out = {
+        "metric": "Mcell-steps/s at 1e-8 divergence",
+        "value": cells * args.steps / wall / 1e6,
+        "unit": "Mcell-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64" if prec else "f64",
+        "data": "synthetic",
+        "config": {"workload": "batched_cylinders_256", "simulations": len(cases), "cells": cells,
+                   "sizes": {str(k): v for k, v in sorted(sizes.items())}, "precond": "multigrid",
+                   "precision": "fp32 inner + fp64 refinement, div_rel <= 1e-8" if prec else "fp64",
+                   "host_threads": 16},
+        "div_rel_max": max(divs),
+        "cg_iters_per_step_mean": float(np.mean(cg)),
+        "pred_iters_per_step_mean": float(np.mean(pred)),
+        "roofline": None,
+        "cpu_baseline": None,
+    }
+    if max(divs) > 1e-8:
+        out["warning"] = "divergence above 1e-8 in a timed step"
+    print(json.dumps(out), flush=True)
+    batch.close()
+    for c in ctxs:
+        c.close()
+
+
+def run_serving(args):
+    """The serving trace: Poisson arrivals (20 per second) of simulations of
+    256^2 .. 2048^2 cells with 1-3 ellipses, 100 steps each, served by the
+    continuous-batching server under an HBM budget of 85% of free device
+    memory.  The first --requests requests of the seeded trace are served in
+    real time; the line reports latency percentiles (queue and service
+    separately) and the served throughput."""
+    import torch
+    from paper_2211_10698_amd import serve
+
+    torch.cuda.set_device(0)
+    reqs = W.serving_trace()[: args.requests]
+    prec = 1 if args.precision == "mixed" else 0
+    srv = serve.Server(precision=prec, threads=16, prep_workers=8)
+    t0 = time.perf_counter()
+    recs = srv.run(reqs, log=lambda m: print(m, file=sys.stderr, flush=True))
+    wall = time.perf_counter() - t0
+    summ = serve.summarize(recs, wall)
+    busy = sum(r.completion - r.start for r in recs)
+    out = {
+        "metric": "served latency p50 (s)",
+        "value": summ["latency_p50_s"],
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": int(sum(r.steps for r in recs)),
+        "warmup": 0,
+        "ms_per_step": None,
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64" if prec else "f64",
+        "data": "synthetic",
+        "config": {"workload": "serving_trace", "requests": len(reqs), "arrival_rate_per_s": 20.0,
+                   "steps_per_request": 100, "hbm_budget_bytes": srv.budget,
+                   "precision": "fp32 inner + fp64 refinement, div_rel <= 1e-8" if prec else "fp64"},
+        "serving": summ,
+        "max_admitted_bytes": srv.max_used,
+        "mean_concurrency": busy / wall,
+        "roofline": None,
+        "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -200,6 +342,7 @@ def main():
                     help="fp64, or mixed: FP32 inner solves with FP64 residuals and refinement to "
                          "div_rel <= 1e-8")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--requests", type=int, default=40, help="serving_trace: requests served")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run the plain copies that calibrate the HBM byte counters")
     ap.add_argument("--summarize-counters", metavar="DIR",
@@ -218,6 +361,12 @@ def main():
     if args.calibrate_copy:
         calibrate_copy()
         return
+    if args.workload == "batched_cylinders_256":
+        run_batched(args)
+        return
+    if args.workload == "serving_trace":
+        run_serving(args)
+        return
     from paper_2211_10698_amd import ccns
 
     case = WORKLOADS[args.workload]()
@@ -227,7 +376,8 @@ def main():
     Dx, Dy = W.dirichlet(case)
     mixed = args.precision == "mixed"
     params = ccns.make_params(case.rho, case.mu, case.tau, u_ref=case.u_inf, pcg_tol=case.pcg_tol,
-                              pred_tol=1e-12, precision=1 if mixed else 0, div_tol=1e-8)
+                              pred_tol=1e-12, precision=1 if mixed else 0, div_tol=1e-8,
+                              mass_floor=case.mass_floor)
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
     ctx = ccns.Context(g, params, caps, Dx, Dy, stream=stream)
@@ -319,7 +469,7 @@ def main():
         # that algorithm needs on this step's right-hand side (library, same
         # algorithm as the oracle), to scale the oracle's timed sample
         pj = ccns.make_params(case.rho, case.mu, case.tau, u_ref=case.u_inf, pcg_tol=case.pcg_tol,
-                              precond=ccns.PRECOND_JACOBI)
+                              precond=ccns.PRECOND_JACOBI, mass_floor=case.mass_floor)
         cj = ccns.Context(g, pj, caps, Dx, Dy, stream=stream)
         phi_prev = ctx.get_field(ccns.F_PHI)
         ctx.step(1)                      # one more (untimed) step: its warm start and right-hand side

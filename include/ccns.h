@@ -21,6 +21,10 @@
  *  - Functions return a ccns_status.  No C++ exception crosses the
  *    interface.  On error, ccns_last_error() describes the failure.
  *  - A context is not thread-safe; use one context per host thread.
+ *  - Device arrays passed to a call must be ready when it is made: the
+ *    library orders its own work on the context's stream only, and
+ *    synchronizes that stream before any call that reads or writes caller
+ *    arrays returns.
  */
 #ifndef CCNS_H
 #define CCNS_H
@@ -115,6 +119,15 @@ ccns_status ccns_capacities(const ccns_grid *grid, const ccns_body *bodies, int 
  *                 eq:offdiag (not symmetric; apply only), 2 arithmetic mean
  *  poisson_weight 0: Poisson face weight A^2/V_f (mass matrix explicit);
  *                 1: A^2 (the printed equations with unit mass matrix)
+ *  mass_floor     theta in [0, 1]: every volume the step divides by is at
+ *                 least theta hx hy: the mass matrix of the time derivative
+ *                 and of the projection, M_f = max(V_f, theta hx hy) on
+ *                 velocity unknowns, and the cell volume of the pressure
+ *                 update, V^-1 -> 1/max(V, theta hx hy).  theta = 0 gives
+ *                 M = V exactly.  A sliver cell with open faces otherwise
+ *                 turns the pressure update's volume average into a spike
+ *                 that the next predictor feeds back (an instability that
+ *                 grows by orders of magnitude per step).
  *  precond        Poisson preconditioner: 0 Jacobi (diagonal); 1 geometric
  *                 multigrid V-cycle (2x2 cell agglomeration, weighted-Jacobi
  *                 smoothing, pseudo-inverse on the coarsest grid).  The
@@ -128,6 +141,7 @@ typedef struct {
     int visc_form;
     int poisson_weight;
     int precond;
+    double mass_floor;
 } ccns_params;
 
 typedef struct ccns_ctx ccns_ctx;
@@ -169,6 +183,9 @@ enum {
 
 /* Copy a field between the workspace and a dense (ny+2)x(nx+2) array.
  * `is_device` != 0: the array is device memory, else host memory.
+ * Setting CCNS_F_UX/UY: faces that are not velocity unknowns (on a wall
+ * normal to them, without fluid in their control volume, or closed, A = 0)
+ * take the Dirichlet value whatever the array holds there.
  * Setting CCNS_F_CONVX/Y marks conv^{n-1} as valid (otherwise the first
  * step takes conv^{-1} := conv^0).  Errors: CCNS_EINVAL (bad field). */
 ccns_status ccns_field_set(ccns_ctx *ctx, int field, const double *src, int is_device);

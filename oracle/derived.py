@@ -2,8 +2,20 @@
 
 Readings taken where the paper is silent:
   * A velocity face is an unknown when it is interior to the box (not on a
-    wall that is normal to it) and its staggered control volume has fluid.
-    Every other face holds its Dirichlet value, U = D.
+    wall that is normal to it), its staggered control volume has fluid and
+    the face itself is open (A > 0).  Every other face holds its Dirichlet
+    value, U = D.  A closed face carries no flux and takes no part in the
+    projection; left free, the velocity of such a face (the sliver between
+    the two sides of a thin trailing edge, say) is driven by the explicit
+    convective term divided by a tiny mass and grows without bound.
+  * Small control volumes: the paper does not treat them.  Every volume the
+    step divides by is at least vol_floor = theta hx hy (the mass matrix M
+    of the velocity unknowns, M_f = max(V_f, vol_floor), and the cell volume
+    of the pressure update).  Without it, a sliver cell with open faces
+    turns the pressure update's volume average V^-1 L Phi into a spike that
+    the next predictor feeds back; the NACA section's trailing edge at 4096
+    x 2048 then grows by orders of magnitude per step.  theta = 0.05 removes
+    that growth; theta = 0 is M = V exactly.
   * The Poisson operator is cont(M^-1 pres(Phi), 0): face coefficient
     c_f = A_f^2 / V_f (weight 'volume'), which is the paper's statement with
     the mass matrix of Sec. 4.5 made explicit; weight 'literal' drops the
@@ -38,15 +50,23 @@ class Prepared:
     gy: np.ndarray
     diag: np.ndarray    # diagonal of -L (cells)
     n_active: int
+    Mu: np.ndarray = None    # mass matrix of the x-face unknowns (0 elsewhere)
+    Mv: np.ndarray = None
+    Vp: np.ndarray = None    # cell volumes of the pressure update (floored)
 
 
-def prepare(caps: dict, nx: int, ny: int, weight: str = "volume") -> Prepared:
+def prepare(caps: dict, nx: int, ny: int, weight: str = "volume", vol_floor: float = 0.0) -> Prepared:
+    """vol_floor: the smallest volume the step divides by (theta hx hy): the
+    mass matrix of the velocity unknowns is max(V_f, vol_floor) and the
+    pressure update divides by max(V, vol_floor)."""
     shape = (ny + 2, nx + 2)
     J, I = np.indices(shape)
-    act_u = (I >= 1) & (I <= nx - 1) & (J >= 1) & (J <= ny) & (caps["Vu"] > 0.0)
-    act_v = (I >= 1) & (I <= nx) & (J >= 1) & (J <= ny - 1) & (caps["Vv"] > 0.0)
+    act_u = (I >= 1) & (I <= nx - 1) & (J >= 1) & (J <= ny) & (caps["Vu"] > 0.0) & (caps["Ax"] > 0.0)
+    act_v = (I >= 1) & (I <= nx) & (J >= 1) & (J <= ny - 1) & (caps["Vv"] > 0.0) & (caps["Ay"] > 0.0)
+    Mu = np.where(act_u, np.maximum(caps["Vu"], vol_floor), 0.0)
+    Mv = np.where(act_v, np.maximum(caps["Vv"], vol_floor), 0.0)
     if weight == "volume":
-        wu, wv = safe_inv(caps["Vu"]), safe_inv(caps["Vv"])
+        wu, wv = safe_inv(Mu), safe_inv(Mv)
     elif weight == "literal":
         wu, wv = np.ones(shape), np.ones(shape)
     else:
@@ -84,7 +104,8 @@ def prepare(caps: dict, nx: int, ny: int, weight: str = "volume") -> Prepared:
     diag = np.zeros(shape)
     diag[1:-1, 1:-1] = cx[1:-1, 1:-1] + cx[1:-1, :-2] + cy[1:-1, 1:-1] + cy[:-2, 1:-1]
     diag = np.where(act_p, diag, 0.0)
-    return Prepared(caps, nx, ny, act_u, act_v, act_p, cx, cy, gx, gy, diag, int(act_p.sum()))
+    Vp = np.where(caps["V"] > 0.0, np.maximum(caps["V"], vol_floor), 0.0)
+    return Prepared(caps, nx, ny, act_u, act_v, act_p, cx, cy, gx, gy, diag, int(act_p.sum()), Mu, Mv, Vp)
 
 
 def laplacian(pr: Prepared, phi):

@@ -71,8 +71,9 @@ class Stepper:
         self.Dy = Dy
         self.h = h
         c = pr.caps
-        self.Vu = np.where(pr.act_u, c["Vu"], 0.0)
-        self.Vv = np.where(pr.act_v, c["Vv"], 0.0)
+        # mass matrix of the unknowns (the cut-cell volumes, floored)
+        self.Vu = pr.Mu if pr.Mu is not None else np.where(pr.act_u, c["Vu"], 0.0)
+        self.Vv = pr.Mv if pr.Mv is not None else np.where(pr.act_v, c["Vv"], 0.0)
         self.mask2 = np.stack([pr.act_u, pr.act_v])
         # Dirichlet contribution of the viscous term: visc(strain(U~, D)) with
         # U~ = D on the non-unknown faces and 0 on unknowns
@@ -172,7 +173,8 @@ class Stepper:
     def pressure_update(self, P, phi):
         prm, pr = self.prm, self.pr
         Lphi = laplacian(pr, phi)
-        Vinv = np.where(pr.act_p & (pr.caps["V"] > 0), 1.0 / np.where(pr.caps["V"] > 0, pr.caps["V"], 1.0), 0.0)
+        V = pr.Vp if pr.Vp is not None else pr.caps["V"]
+        Vinv = np.where(pr.act_p & (V > 0), 1.0 / np.where(V > 0, V, 1.0), 0.0)
         return np.where(pr.act_p, P + phi - (prm.tau * prm.mu / (2.0 * prm.rho)) * Vinv * Lphi, 0.0)
 
     def diagnostics(self, Ux, Uy, info: StepInfo):

@@ -42,7 +42,7 @@ class Params(C.Structure):
                 ("gx", C.c_double), ("gy", C.c_double), ("pcg_tol", C.c_double), ("pred_tol", C.c_double),
                 ("div_tol", C.c_double), ("pcg_maxit", C.c_int), ("pred_maxit", C.c_int),
                 ("precision", C.c_int), ("visc_form", C.c_int), ("poisson_weight", C.c_int),
-                ("precond", C.c_int)]
+                ("precond", C.c_int), ("mass_floor", C.c_double)]
 
 
 class SolveInfo(C.Structure):
@@ -157,9 +157,9 @@ PRECOND_JACOBI, PRECOND_MG = 0, 1
 
 def make_params(rho, mu, tau, u_ref=1.0, pcg_tol=1e-10, pred_tol=1e-12, div_tol=1e-8, pcg_maxit=200000,
                 pred_maxit=500, precision=0, visc_form=0, poisson_weight=0, gx=0.0, gy=0.0,
-                precond=PRECOND_MG) -> Params:
+                precond=PRECOND_MG, mass_floor=0.05) -> Params:
     return Params(rho, mu, tau, u_ref, gx, gy, pcg_tol, pred_tol, div_tol, pcg_maxit, pred_maxit, precision,
-                  visc_form, poisson_weight, precond)
+                  visc_form, poisson_weight, precond, mass_floor)
 
 
 class Context:
@@ -212,16 +212,27 @@ class Context:
     def _dense(self):
         return self.torch.zeros(self.shape, dtype=self.torch.float64, device=self.ws.device)
 
+    def _ready(self):
+        """Tensors handed to the library were made (allocated, filled,
+        converted) on torch's current stream; the library works on the
+        context's stream.  Wait for the former before a call: the library
+        synchronizes its own stream before it returns."""
+        cur = self.torch.cuda.current_stream(self.ws.device)
+        if cur.cuda_stream != self.stream.cuda_stream:
+            cur.synchronize()
+
     def set_field(self, field: int, arr):
         t = self.torch
         if isinstance(arr, np.ndarray):
             a = np.ascontiguousarray(arr, dtype=np.float64)
             return self._chk(lib().ccns_field_set(self.h, field, a.ctypes.data, 0), "field_set")
         a = arr.to(dtype=t.float64).contiguous()
+        self._ready()
         return self._chk(lib().ccns_field_set(self.h, field, a.data_ptr(), 1), "field_set")
 
     def get_field(self, field: int):
         out = self._dense()
+        self._ready()
         self._chk(lib().ccns_field_get(self.h, field, out.data_ptr(), 1), "field_get")
         return out
 
@@ -232,6 +243,7 @@ class Context:
                for x in inputs]
         ins = [x.to(dtype=t.float64).contiguous() for x in ins]
         outs = [self._dense() for _ in range(nout)]
+        self._ready()
         pin = (C.c_void_p * nin)(*[x.data_ptr() for x in ins])
         pout = (C.c_void_p * nout)(*[x.data_ptr() for x in outs])
         self._chk(lib().ccns_apply(self.h, op, pin, pout), "apply")
@@ -241,6 +253,7 @@ class Context:
         t = self.torch
         b = b.to(dtype=t.float64).contiguous()
         phi = self._dense()
+        self._ready()
         info = SolveInfo()
         st = lib().ccns_pressure_solve(self.h, b.data_ptr(), phi.data_ptr(), C.byref(info))
         if check:

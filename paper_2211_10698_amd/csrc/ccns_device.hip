@@ -281,14 +281,15 @@ __global__ __launch_bounds__(NT) void k_pois_dir(Dims d, PoisCoefT<T> pc, const 
 // ntot entries (inactive entries hold zeros); each group works on contiguous
 // chunks of UPT*NT entries with every load issued before any arithmetic.
 constexpr int UPT = 4;
+constexpr int UT = 1024;  // threads per work-group of the update (16 wavefronts)
 template <class T>
-__global__ __launch_bounds__(NT) void k_cg_update(size_t ntot, int nblk, const T *__restrict__ dinv,
+__global__ __launch_bounds__(UT) void k_cg_update(size_t ntot, int nblk, const T *__restrict__ dinv,
                                                   T *__restrict__ x, T *__restrict__ r,
                                                   const T *__restrict__ p, const T *__restrict__ q,
                                                   CgState *st, int par, const double *pin, int nin, double *pout) {
     if (st->done) return;
     double t[1];
-    get_totals<1>(pin, nin, t);
+    get_totals<1, 0, UT>(pin, nin, t);
     if (!(t[0] > 0.0)) {
         if (blockIdx.x == 0 && threadIdx.x == 0) {
             st->done = 1;
@@ -299,13 +300,13 @@ __global__ __launch_bounds__(NT) void k_cg_update(size_t ntot, int nblk, const T
     }
     const T a = (T)(st->slot[par].rz / t[0]);
     double v[4] = {0, 0, 0, 0};
-    const size_t chunk = (size_t)UPT * NT;
+    const size_t chunk = (size_t)UPT * UT;
     const int L = logical_group(nblk);
     for (size_t base = (size_t)L * chunk; base < ntot; base += (size_t)nblk * chunk) {
         T dv[UPT], xv[UPT], pv[UPT], rv[UPT], qv[UPT];
 #pragma unroll
         for (int u = 0; u < UPT; ++u) {
-            const size_t k0 = base + (size_t)u * NT + threadIdx.x;
+            const size_t k0 = base + (size_t)u * UT + threadIdx.x;
             const size_t k = k0 < ntot ? k0 : ntot - 1;
             dv[u] = dinv[k];
             xv[u] = x[k];
@@ -315,7 +316,7 @@ __global__ __launch_bounds__(NT) void k_cg_update(size_t ntot, int nblk, const T
         }
 #pragma unroll
         for (int u = 0; u < UPT; ++u) {
-            const size_t k = base + (size_t)u * NT + threadIdx.x;
+            const size_t k = base + (size_t)u * UT + threadIdx.x;
             if (k < ntot && dv[u] > (T)0) {
                 x[k] = xv[u] + a * pv[u];
                 const T rn = rv[u] - a * qv[u];
@@ -329,7 +330,7 @@ __global__ __launch_bounds__(NT) void k_cg_update(size_t ntot, int nblk, const T
             }
         }
     }
-    put_partials<4>(v, pout, nblk);
+    put_partials<4, 0, UT>(v, pout, nblk);
 }
 
 // x += dx (float correction of an inner solve) over ntot entries.
@@ -874,6 +875,15 @@ __global__ __launch_bounds__(NT) void k_diag_final(const double *pin, int nin, D
     }
 }
 
+// U = D on every face that is not a velocity unknown (vm = 0 there).
+__global__ __launch_bounds__(NT) void k_keep_dirichlet(Dims d, double *__restrict__ u,
+                                                       const double *__restrict__ dd,
+                                                       const double *__restrict__ vm) {
+    for_cells(d, [&](int, int, int, size_t k) {
+        if (!(vm[k] > 0.0)) u[k] = dd[k];
+    });
+}
+
 // ---------------------------------------------------------------------------
 // operator applies (parity entry points)
 // ---------------------------------------------------------------------------
@@ -1128,6 +1138,25 @@ ccns_status fail(ccns_ctx *c, ccns_status s, const std::string &msg) {
             return fail(ctx, CCNS_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
     } while (0)
 
+// One tile per work-group (the stencil kernels of the CG iterations: enough
+// wavefronts in flight to cover the memory latency).
+Dims make_dims_1(const Layout &L, int ncomp, int ty) {
+    Dims d;
+    d.nx = L.nx;
+    d.ny = L.ny;
+    d.rows = L.rows;
+    d.pitch = L.pitch;
+    d.gx = L.pitch / TX;
+    d.ty = ty;
+    d.gy = (L.rows + ty - 1) / ty;
+    d.ntile = d.gx * d.gy;
+    d.ncomp = ncomp;
+    d.tpb = 1;
+    d.nblk = ((d.ntile * ncomp + 7) / 8) * 8;
+    d.n = L.n;
+    return d;
+}
+
 Dims make_dims(const Layout &L, int ncomp, int ty) {
     Dims d;
     d.nx = L.nx;
@@ -1182,6 +1211,12 @@ int flat_blocks(size_t ntot) {
     b = std::min<size_t>(std::max<size_t>(b, 8), NBMAX);
     return (int)((b + 7) / 8 * 8);
 }
+// Groups of the CG update kernel (UT threads, UPT entries per thread and pass).
+int update_blocks(size_t ntot) {
+    size_t b = (ntot + (size_t)UT * UPT - 1) / ((size_t)UT * UPT);
+    b = std::min<size_t>(std::max<size_t>(b, 8), NBMAX);
+    return (int)((b + 7) / 8 * 8);
+}
 
 hipEvent_t next_event(ccns_ctx *c) {
     if (c->evused == c->evpool.size()) {
@@ -1215,7 +1250,7 @@ void harvest_events(ccns_ctx *c, int kid) {
 template <class T, class Dir, class Finish>
 ccns_status cg_loop(ccns_ctx *c, CgState *st, T *x, T *r, T *const pbuf[2], int &par_buf, T *q, const T *dinv,
                     size_t ntot, int &last_it, Dir dir, Finish finish, ccns_solve_info *info, int kid) {
-    const int nl = flat_blocks(ntot);
+    const int nl = update_blocks(ntot);
     int chunk = std::max(4, last_it + 1);
     int it = 0;
     bool first = true;
@@ -1229,7 +1264,7 @@ ccns_status cg_loop(ccns_ctx *c, CgState *st, T *x, T *r, T *const pbuf[2], int 
                                c->part[PB_DIR]);
             if (tm) (void)hipEventRecord(next_event(c), c->stream);
             finish();
-            k_cg_update<T><<<nl, NT, 0, c->stream>>>(ntot, nl, dinv, x, r, pbuf[par_buf ^ 1], q, st, par,
+            k_cg_update<T><<<nl, UT, 0, c->stream>>>(ntot, nl, dinv, x, r, pbuf[par_buf ^ 1], q, st, par,
                                                      c->part[PB_DIR], nd, c->part[PB_UPD]);
             if (tm) (void)hipEventRecord(next_event(c), c->stream);
             par_buf ^= 1;
@@ -1448,7 +1483,7 @@ ccns_status mg_cg(ccns_ctx *c, std::vector<ccns_ctx::LevelT<T>> &mg, PoisCoefT<T
                   T *p0, T *p1, T *q, const double *pinit, int ninit, int &last_it, ccns_solve_info *info) {
     const Dims &dp = c->dp;
     const size_t ntot = c->w.L.n;
-    const int nl = flat_blocks(ntot);
+    const int nl = update_blocks(ntot);
     T *pb[2] = {p0, p1};
     int &pbuf = c->pbuf_pois;
     T *z = vcycle<T>(c, mg, 0, r);
@@ -1462,7 +1497,7 @@ ccns_status mg_cg(ccns_ctx *c, std::vector<ccns_ctx::LevelT<T>> &mg, PoisCoefT<T
             k_pois_dir_z<T><<<dp.nblk, NT, 0, c->stream>>>(dp, pc, z, pb[pbuf], pb[pbuf ^ 1], q, st, it == 0 ? 1 : 0,
                                                            par, c->part[PB_MG], 1, pinit, ninit, c->part[PB_DIR]);
             if (tm) (void)hipEventRecord(next_event(c), c->stream);
-            k_cg_update<T><<<nl, NT, 0, c->stream>>>(ntot, nl, pc.dinv, x, r, pb[pbuf ^ 1], q, st, par,
+            k_cg_update<T><<<nl, UT, 0, c->stream>>>(ntot, nl, pc.dinv, x, r, pb[pbuf ^ 1], q, st, par,
                                                      c->part[PB_DIR], dp.nblk, c->part[PB_UPD]);
             if (tm) (void)hipEventRecord(next_event(c), c->stream);
             pbuf ^= 1;
@@ -1605,12 +1640,10 @@ ccns_status pred_cg(ccns_ctx *c, PredCoefT<T> pc, CgState *st, T *x, T *r, T *p0
     const int nb = ((gx * gy + 7) / 8) * 8;
     auto dir = [&](int first, int par, T *pold, T *pnew, const double *pin, int nin, double *pout) {
         k_pred_dir_lds<T><<<nb, NT, 0, c->stream>>>(L.nx, L.ny, L.pitch, L.rows, gx, gy, L.n, pc, r, pold, pnew, q,
-                                                    st, first, par, pin, nin, c->part[PB_RHS]);
-        (void)pout;
-        return 1;
+                                                    st, first, par, pin, nin, pout);
+        return nb;
     };
-    auto finish = [&]() { k_reduce_partials<1><<<1, NT, 0, c->stream>>>(c->part[PB_RHS], nb, c->part[PB_DIR]); };
-    return cg_loop<T>(c, st, x, r, pb, c->pbuf_pred, q, pc.hdx, 2 * c->w.L.n, last_it, dir, finish, info, 2);
+    return cg_loop<T>(c, st, x, r, pb, c->pbuf_pred, q, pc.hdx, 2 * c->w.L.n, last_it, dir, [] {}, info, 2);
 }
 
 ccns_status predict_dev(ccns_ctx *c, ccns_solve_info *info) {
@@ -1758,7 +1791,7 @@ ccns_status ccns_ctx_create(const ccns_grid *grid, const ccns_params *params, co
         c->f[k] = params->precision == 1 ? (float *)(c->base + c->w.f32_off + (size_t)k * c->w.arr32_bytes) : nullptr;
     c->dc = make_dims(c->w.L, 1, TY);
     c->df = make_dims(c->w.L, 2, TY);
-    c->dp = make_dims(c->w.L, 1, PTY);
+    c->dp = make_dims_1(c->w.L, 1, PTY);
     c->init_nblk = c->dc.nblk;
     c->conv_valid = 0;
     c->last_pois_it = c->last_pred_it = 16;
@@ -1857,6 +1890,11 @@ ccns_status ccns_field_set(ccns_ctx *c, int field, const double *src, int is_dev
     ccns_status s = to_dev(c, c->a[kFieldArr[field]], src, is_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice);
     if (s != CCNS_OK) return s;
     if (field == CCNS_F_CONVX || field == CCNS_F_CONVY) c->conv_valid = 1;
+    if (field == CCNS_F_UX)
+        k_keep_dirichlet<<<c->dc.nblk, NT, 0, c->stream>>>(c->dc, c->a[A_UX], c->a[A_DX], c->a[A_VU]);
+    if (field == CCNS_F_UY)
+        k_keep_dirichlet<<<c->dc.nblk, NT, 0, c->stream>>>(c->dc, c->a[A_UY], c->a[A_DY], c->a[A_VV]);
+    HIPCHK(c, hipGetLastError());
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return CCNS_OK;
 }

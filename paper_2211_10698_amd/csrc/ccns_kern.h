@@ -74,11 +74,13 @@ __device__ inline double wave_max(double v) {
     return v;
 }
 
-// Block-level reduction of NS sums followed by NM maxima; the result is in
-// out[] for every thread.
-template <int NS, int NM>
+// Block-level reduction of NS sums followed by NM maxima over a work-group
+// of BT threads; the result is in out[] for every thread.  The wavefront
+// results are combined in a fixed order (adjacent pairs, level by level).
+template <int NS, int NM, int BT = NT>
 __device__ inline void block_reduce(const double (&v)[NS + NM], double (&out)[NS + NM]) {
-    __shared__ double part[NS + NM][4];
+    constexpr int NW = BT / 64;
+    __shared__ double part[NS + NM][NW];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
     for (int k = 0; k < NS + NM; ++k) {
@@ -87,35 +89,43 @@ __device__ inline void block_reduce(const double (&v)[NS + NM], double (&out)[NS
     }
     __syncthreads();
 #pragma unroll
-    for (int k = 0; k < NS + NM; ++k)
-        out[k] = (k < NS) ? ((part[k][0] + part[k][1]) + (part[k][2] + part[k][3]))
-                          : fmax(fmax(part[k][0], part[k][1]), fmax(part[k][2], part[k][3]));
+    for (int k = 0; k < NS + NM; ++k) {
+        double q[NW];
+#pragma unroll
+        for (int i = 0; i < NW; ++i) q[i] = part[k][i];
+#pragma unroll
+        for (int m = NW; m > 1; m /= 2)
+#pragma unroll
+            for (int i = 0; i < m / 2; ++i)
+                q[i] = (k < NS) ? q[2 * i] + q[2 * i + 1] : fmax(q[2 * i], q[2 * i + 1]);
+        out[k] = q[0];
+    }
     __syncthreads();
 }
 
-template <int NS, int NM = 0>
+template <int NS, int NM = 0, int BT = NT>
 __device__ inline void put_partials(const double (&v)[NS + NM], double *part, int nblk) {
     double t[NS + NM];
-    block_reduce<NS, NM>(v, t);
+    block_reduce<NS, NM, BT>(v, t);
     if (threadIdx.x == 0) {
 #pragma unroll
         for (int k = 0; k < NS + NM; ++k) part[(size_t)k * nblk + blockIdx.x] = t[k];
     }
 }
 
-template <int NS, int NM = 0>
+template <int NS, int NM = 0, int BT = NT>
 __device__ inline void get_totals(const double *part, int nblk, double (&tot)[NS + NM]) {
     double a[NS + NM];
 #pragma unroll
     for (int k = 0; k < NS + NM; ++k) a[k] = (k < NS) ? 0.0 : -INFINITY;
-    for (int b = threadIdx.x; b < nblk; b += NT) {
+    for (int b = threadIdx.x; b < nblk; b += BT) {
 #pragma unroll
         for (int k = 0; k < NS + NM; ++k) {
             const double x = part[(size_t)k * nblk + b];
             a[k] = (k < NS) ? a[k] + x : fmax(a[k], x);
         }
     }
-    block_reduce<NS, NM>(a, tot);
+    block_reduce<NS, NM, BT>(a, tot);
 }
 
 // ---------------------------------------------------------------------------

@@ -35,6 +35,7 @@ ccns_status prepare_coefficients(const ccns_grid &g, const ccns_params &prm, con
     const size_t n = (size_t)W * H;
     if (nx < 2 || ny < 2 || !(g.hx > 0) || !(g.hy > 0)) { err = "bad grid"; return CCNS_EINVAL; }
     if (!(prm.rho > 0) || !(prm.mu >= 0) || !(prm.tau > 0)) { err = "rho, tau must be > 0 and mu >= 0"; return CCNS_EINVAL; }
+    if (!(prm.mass_floor >= 0.0) || !(prm.mass_floor <= 1.0)) { err = "mass_floor must be in [0, 1]"; return CCNS_EINVAL; }
     if (prm.visc_form < 0 || prm.visc_form > 2 || prm.poisson_weight < 0 || prm.poisson_weight > 1) {
         err = "bad visc_form or poisson_weight"; return CCNS_EINVAL;
     }
@@ -62,13 +63,23 @@ ccns_status prepare_coefficients(const ccns_grid &g, const ccns_params &prm, con
     for (int j = 0; j < H; ++j)
         for (int i = 0; i < W; ++i) {
             size_t k = id(j, i);
-            au[k] = (i >= 1 && i <= nx - 1 && j >= 1 && j <= ny && Vu[k] > 0.0);
-            av[k] = (i >= 1 && i <= nx && j >= 1 && j <= ny - 1 && Vv[k] > 0.0);
+            // an unknown needs fluid in its control volume and an open face:
+            // a face of zero aperture carries no flux, and keeps the body's
+            // (Dirichlet) velocity
+            au[k] = (i >= 1 && i <= nx - 1 && j >= 1 && j <= ny && Vu[k] > 0.0 && Ax[k] > 0.0);
+            av[k] = (i >= 1 && i <= nx && j >= 1 && j <= ny - 1 && Vv[k] > 0.0 && Ay[k] > 0.0);
             fluid[k] = (i >= 1 && i <= nx && j >= 1 && j <= ny && V[k] > 0.0);
         }
+    // mass matrix of the velocity unknowns (with the optional floor)
+    const double mfloor = prm.mass_floor * g.hx * g.hy;
+    std::vector<double> Mu(n, 0.0), Mv(n, 0.0);
+    for (size_t k = 0; k < n; ++k) {
+        Mu[k] = au[k] ? std::max(Vu[k], mfloor) : Vu[k];
+        Mv[k] = av[k] ? std::max(Vv[k], mfloor) : Vv[k];
+    }
     const bool volw = prm.poisson_weight == 0;
     for (size_t k = 0; k < n; ++k) {
-        double wu = volw ? inv0(Vu[k]) : 1.0, wv = volw ? inv0(Vv[k]) : 1.0;
+        double wu = volw ? inv0(Mu[k]) : 1.0, wv = volw ? inv0(Mv[k]) : 1.0;
         o.cx[k] = au[k] ? Ax[k] * Ax[k] * wu : 0.0;
         o.cy[k] = av[k] ? Ay[k] * Ay[k] * wv : 0.0;
     }
@@ -108,7 +119,7 @@ ccns_status prepare_coefficients(const ccns_grid &g, const ccns_params &prm, con
         bool ey = (k + W < n) && act[k] && act[k + W];
         if (!ex) o.cx[k] = 0.0;
         if (!ey) o.cy[k] = 0.0;
-        double wu = volw ? inv0(Vu[k]) : 1.0, wv = volw ? inv0(Vv[k]) : 1.0;
+        double wu = volw ? inv0(Mu[k]) : 1.0, wv = volw ? inv0(Mv[k]) : 1.0;
         o.gx[k] = o.cx[k] > 0.0 ? Ax[k] * wu : 0.0;
         o.gy[k] = o.cy[k] > 0.0 ? Ay[k] * wv : 0.0;
     }
@@ -118,7 +129,7 @@ ccns_status prepare_coefficients(const ccns_grid &g, const ccns_params &prm, con
             if (!act[k]) continue;
             double d = o.cx[k] + o.cx[k - 1] + o.cy[k] + o.cy[k - W];
             o.dinv[k] = inv0(d);
-            o.vinv[k] = inv0(V[k]);
+            o.vinv[k] = inv0(std::max(V[k], mfloor));
         }
     // divergence and convection data
     o.n_uact = o.n_vact = 0;
@@ -127,8 +138,8 @@ ccns_status prepare_coefficients(const ccns_grid &g, const ccns_params &prm, con
         o.ay[k] = Ay[k];
         o.dx[k] = Dx[k];
         o.dy[k] = Dy[k];
-        o.vu[k] = au[k] ? Vu[k] : 0.0;
-        o.vv[k] = av[k] ? Vv[k] : 0.0;
+        o.vu[k] = au[k] ? Mu[k] : 0.0;
+        o.vv[k] = av[k] ? Mv[k] : 0.0;
         o.vur[k] = Vu[k];
         o.vvr[k] = Vv[k];
         o.utx[k] = au[k] ? 0.0 : Dx[k];
@@ -180,12 +191,12 @@ ccns_status prepare_coefficients(const ccns_grid &g, const ccns_params &prm, con
             if (au[k]) {
                 double kd = Bxx[k] * Bxx[k] * (o.wxx[k] + o.wxx[k + 1]) +
                             0.5 * Bxy[k] * Bxy[k] * (o.nxx[k] + o.nxx[k - W]);
-                o.hdx[k] = inv0(rt * Vu[k] + prm.mu * kd);
+                o.hdx[k] = inv0(rt * Mu[k] + prm.mu * kd);
             }
             if (av[k]) {
                 double kd = Byy[k] * Byy[k] * (o.wyy[k] + o.wyy[k + W]) +
                             0.5 * Byx[k] * Byx[k] * (o.nyy[k] + o.nyy[k - 1]);
-                o.hdy[k] = inv0(rt * Vv[k] + prm.mu * kd);
+                o.hdy[k] = inv0(rt * Mv[k] + prm.mu * kd);
             }
         }
     (void)Axx; (void)Axy; (void)Ayy; (void)Ayx;

@@ -1,0 +1,256 @@
+"""Serving loop: many independent simulation requests on one GPU.
+
+A request is a simulation case (grid, bodies, Reynolds number, step count)
+with an arrival time.  The server
+
+  * admits requests in arrival order (first come, first served) while their
+    device footprint (ccns_workspace_bytes plus field buffers) fits in an HBM
+    budget; a request that does not fit waits at the head of the queue;
+  * prepares each admitted request: capacities from the level set and the
+    seeded inputs on a host worker, overlapping the GPU work of the running
+    batch; then, on the driver thread, a context on a stream of its own and
+    the initial projection;
+  * runs every prepared simulation on a step worker of its own (continuous
+    batching without rounds: a simulation joins the GPU as soon as it is
+    prepared, shares it with the others, each on its own stream, and leaves
+    as soon as its last step is done, releasing its budget).
+
+Latency = completion - arrival, split into queue time (arrival to admission)
+and service time (admission to completion, which includes preparation).
+Every simulation's result is independent of the others that share the
+batch: the kernels reduce in a fixed order, so a request served in a mix
+returns the same fields, bit for bit, as served alone.
+
+This module is orchestration only; all numerical work runs in libccns.
+"""
+
+from __future__ import annotations
+
+import collections
+import concurrent.futures as cf
+import dataclasses
+import time
+from typing import Dict, List, Optional, Sequence
+
+import numpy as np
+
+from . import ccns
+
+
+@dataclasses.dataclass
+class Record:
+    """Timeline and figures of one served request (times in seconds from the
+    start of the run)."""
+
+    index: int
+    name: str
+    cells: int
+    steps: int
+    bytes: int
+    arrival: float
+    admit: float = float("nan")
+    start: float = float("nan")
+    completion: float = float("nan")
+    div_rel_max: float = 0.0
+    status: int = ccns.OK
+    note: str = ""
+    fields: Optional[Dict[str, np.ndarray]] = None
+
+    @property
+    def latency(self):
+        return self.completion - self.arrival
+
+    @property
+    def queue(self):
+        return self.admit - self.arrival
+
+    @property
+    def service(self):
+        return self.completion - self.admit
+
+
+def _seeded_inputs(case):
+    """The synthetic requests' inputs: free-stream Dirichlet data with
+    no-slip near the bodies, and the seeded divergence-free perturbation."""
+    import workloads as W
+
+    Dx, Dy = W.dirichlet(case)
+    px, py = W.perturbation(case)
+    return Dx, Dy, px, py
+
+
+def footprint(case, params) -> int:
+    """Device bytes one simulation holds while it is served: the workspace
+    plus the dense field buffers used while its inputs are uploaded."""
+    import ctypes as C
+
+    L = ccns.lib()
+    g = ccns.make_grid(case.grid)
+    ws = L.ccns_workspace_bytes(C.byref(g), C.byref(params))
+    return int(ws + 256 + 8 * (case.grid.nx + 2) * (case.grid.ny + 2) * 8)
+
+
+def default_budget(fraction=0.85) -> int:
+    """A fraction of the device memory that is free now."""
+    import torch
+
+    free, total = torch.cuda.mem_get_info()
+    return int(fraction * free)
+
+
+class Server:
+    """Continuous-batching server for simulation requests on one GPU."""
+
+    def __init__(self, hbm_budget: Optional[int] = None, precision: int = 1, threads: int = 16,
+                 prep_workers: int = 4, keep_fields: bool = False, inputs=None):
+        self.budget = hbm_budget if hbm_budget is not None else default_budget()
+        self.precision = precision
+        self.threads = threads
+        self.prep_workers = prep_workers
+        self.keep_fields = keep_fields
+        # inputs(case) -> (Dx, Dy, ux_perturbation, uy_perturbation)
+        self.inputs = inputs if inputs is not None else _seeded_inputs
+        self.max_used = 0      # largest admitted footprint total seen by the last run
+
+    def _params(self, case):
+        return ccns.make_params(case.rho, case.mu, case.tau, u_ref=case.u_inf, pcg_tol=case.pcg_tol,
+                                pred_tol=1e-12, precision=self.precision, div_tol=1e-8,
+                                mass_floor=case.mass_floor)
+
+    def _host_prepare(self, case):
+        """Host worker (no GPU calls): capacities from the level set and the
+        request's seeded inputs."""
+        g = case.grid
+        caps = ccns.ccns_capacities(g, case.bodies)
+        Dx, Dy, px, py = self.inputs(case)
+        sh = (g.ny + 2, g.nx + 2)
+        J, I = np.indices(sh)
+        au = (I >= 1) & (I <= g.nx - 1) & (J >= 1) & (J <= g.ny) & (caps[7] > 0) & (caps[1] > 0)
+        av = (I >= 1) & (I <= g.nx) & (J >= 1) & (J <= g.ny - 1) & (caps[14] > 0) & (caps[2] > 0)
+        return caps, Dx, Dy, np.where(au, case.u_inf + px, Dx), np.where(av, py, Dy)
+
+    def _device_prepare(self, case, host):
+        """Driver thread: context on a fresh stream, initial field, initial
+        projection.  Device memory is allocated and freed only on the driver
+        thread; the step workers only call ccns_step on their own context."""
+        import torch
+
+        caps, Dx, Dy, ux0, uy0 = host
+        stream = torch.cuda.Stream()
+        ctx = ccns.Context(case.grid, self._params(case), caps, Dx, Dy, stream=stream)
+        ctx.set_field(ccns.F_UX, ux0)
+        ctx.set_field(ccns.F_UY, uy0)
+        info = ctx.project()
+        return ctx, stream, info
+
+    @staticmethod
+    def _run_steps(ctx, steps, clock):
+        """Step worker: advances one simulation through all its steps (the GPU
+        is shared with the other running simulations, each on its own
+        stream).  Returns (start, completion, div_rel_max, status, note)."""
+        start = clock()
+        div, status, note = 0.0, ccns.OK, ""
+        for n in range(steps):
+            info = ctx.step(1, check=False)
+            div = max(div, info.div_rel)
+            for name, si in (("predictor", info.pred), ("pressure", info.poisson)):
+                if si.status != ccns.OK and status == ccns.OK:
+                    status = si.status
+                    note = (f"step {n}: {name} solve status {si.status} after {si.iterations} iterations, "
+                            f"{si.outer} sweeps, relative residual {si.rel_residual:.2e}")
+            if si.status == ccns.EDEVICE:
+                break
+        return start, clock(), div, status, note
+
+    def run(self, requests: Sequence, log=None) -> List[Record]:
+        """Serves the requests (objects with .case and .arrival, arrival in
+        seconds from the start) in real time; returns one Record each.
+
+        Every running simulation is driven by a step worker of its own (at
+        most `threads` at a time), so a simulation joins the GPU as soon as it
+        is prepared and leaves as soon as its last step is done: no
+        simulation waits for another's step."""
+        order = sorted(range(len(requests)), key=lambda k: requests[k].arrival)
+        recs = []
+        for k in order:
+            c = requests[k].case
+            recs.append(Record(k, c.name, c.grid.nx * c.grid.ny, c.steps, footprint(c, self._params(c)),
+                               requests[k].arrival))
+        for r in recs:
+            if r.bytes > self.budget:
+                raise ValueError(f"request {r.name} needs {r.bytes} bytes, more than the budget {self.budget}")
+        cases = {r.index: requests[r.index].case for r in recs}
+        self.max_used = 0
+        queue = collections.deque()
+        free = self.budget
+        nxt = 0
+        preparing = {}       # host-preparation future -> record
+        running = {}         # step future -> (record, context)
+        done = 0
+        t0 = time.perf_counter()
+        clock = lambda: time.perf_counter() - t0  # noqa: E731
+        prep_pool = cf.ThreadPoolExecutor(max_workers=self.prep_workers)
+        step_pool = cf.ThreadPoolExecutor(max_workers=self.threads)
+        try:
+            while done < len(recs):
+                now = clock()
+                while nxt < len(recs) and recs[nxt].arrival <= now:
+                    queue.append(recs[nxt])
+                    nxt += 1
+                while queue and queue[0].bytes <= free:
+                    r = queue.popleft()
+                    free -= r.bytes
+                    self.max_used = max(self.max_used, self.budget - free)
+                    r.admit = clock()
+                    preparing[prep_pool.submit(self._host_prepare, cases[r.index])] = r
+                for fut in [f for f in preparing if f.done()]:
+                    r = preparing.pop(fut)
+                    ctx, stream, info = self._device_prepare(cases[r.index], fut.result())
+                    r.div_rel_max = info.div_rel
+                    running[step_pool.submit(self._run_steps, ctx, r.steps, clock)] = (r, ctx)
+                for fut in [f for f in running if f.done()]:
+                    r, ctx = running.pop(fut)
+                    r.start, r.completion, div, r.status, r.note = fut.result()
+                    r.div_rel_max = max(r.div_rel_max, div)
+                    if self.keep_fields:
+                        r.fields = {n: ctx.get_field(f).cpu().numpy()
+                                    for n, f in (("ux", ccns.F_UX), ("uy", ccns.F_UY), ("p", ccns.F_P))}
+                    ctx.close()
+                    free += r.bytes
+                    done += 1
+                    if log:
+                        log(f"[serve] {r.name} done: latency {r.latency:.2f}s "
+                            f"(queue {r.queue:.2f}s, service {r.service:.2f}s){' ' + r.note if r.note else ''}")
+                waits = list(preparing) + list(running)
+                timeout = 0.005
+                if nxt < len(recs):
+                    timeout = max(0.0, min(timeout, recs[nxt].arrival - clock()))
+                if waits:
+                    cf.wait(waits, timeout=timeout, return_when=cf.FIRST_COMPLETED)
+                else:
+                    time.sleep(timeout)
+        finally:
+            step_pool.shutdown(wait=True)
+            prep_pool.shutdown(wait=True)
+        return sorted(recs, key=lambda r: r.index)
+
+
+def summarize(recs: Sequence[Record], wall: float) -> dict:
+    """p50/p99 latency, queue and service times, and throughput."""
+    lat = np.array([r.latency for r in recs])
+    que = np.array([r.queue for r in recs])
+    svc = np.array([r.service for r in recs])
+    cell_steps = sum(r.cells * r.steps for r in recs)
+    return {
+        "requests": len(recs),
+        "latency_p50_s": float(np.percentile(lat, 50)),
+        "latency_p99_s": float(np.percentile(lat, 99)),
+        "queue_p50_s": float(np.percentile(que, 50)),
+        "queue_p99_s": float(np.percentile(que, 99)),
+        "service_p50_s": float(np.percentile(svc, 50)),
+        "service_p99_s": float(np.percentile(svc, 99)),
+        "throughput_mcell_steps_s": cell_steps / wall / 1e6,
+        "wall_s": wall,
+        "div_rel_max": float(max(r.div_rel_max for r in recs)),
+        "statuses": sorted({int(r.status) for r in recs}),
+    }

@@ -9,13 +9,14 @@ from oracle import derived, geometry, pmii
 
 
 def case_setup(case, pcg_tol=None, pred_tol=1e-12, visc_form="geometric", caps=None, precond="mg",
-               precision=0, div_tol=1e-8):
+               precision=0, div_tol=1e-8, mass_floor=None):
     from paper_2211_10698_amd import ccns
 
     g = case.grid
     if caps is None:
         caps = geometry.capacities(g, case.bodies)
-    pr = derived.prepare(caps, g.nx, g.ny)
+    theta = case.mass_floor if mass_floor is None else mass_floor
+    pr = derived.prepare(caps, g.nx, g.ny, vol_floor=theta * g.hx * g.hy)
     Dx, Dy = W.dirichlet(case)
     tol = case.pcg_tol if pcg_tol is None else pcg_tol
     prm = pmii.Params(rho=case.rho, mu=case.mu, tau=case.tau, u_inf=case.u_inf, pcg_tol=tol,
@@ -23,7 +24,7 @@ def case_setup(case, pcg_tol=None, pred_tol=1e-12, visc_form="geometric", caps=N
     st = pmii.Stepper(pr, prm, Dx, Dy, min(g.hx, g.hy))
     form = {"geometric": 0, "literal": 1, "mean": 2}[visc_form]
     cp = ccns.make_params(case.rho, case.mu, case.tau, u_ref=case.u_inf, pcg_tol=tol, pred_tol=pred_tol,
-                          visc_form=form, precision=precision, div_tol=div_tol,
+                          visc_form=form, precision=precision, div_tol=div_tol, mass_floor=theta,
                           precond={"jacobi": ccns.PRECOND_JACOBI, "mg": ccns.PRECOND_MG}[precond])
     capsarr = np.stack([caps[k] for k in ccns.CAP_NAMES])
     ctx = ccns.Context(g, cp, capsarr, Dx, Dy)

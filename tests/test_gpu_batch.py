@@ -39,13 +39,14 @@ def _context(case, precision, stream):
     caps = _CAPS[case.name]
     Dx, Dy = W.dirichlet(case)
     prm = ccns.make_params(case.rho, case.mu, case.tau, u_ref=case.u_inf, pcg_tol=1e-10, pred_tol=1e-12,
+                           mass_floor=case.mass_floor,
                            precision=precision, div_tol=1e-8)
     ctx = ccns.Context(g, prm, caps, Dx, Dy, stream=stream)
     px, py = W.perturbation(case)
     sh = (g.ny + 2, g.nx + 2)
     J, I = np.indices(sh)
-    au = (I >= 1) & (I <= g.nx - 1) & (J >= 1) & (J <= g.ny) & (caps[7] > 0)
-    av = (I >= 1) & (I <= g.nx) & (J >= 1) & (J <= g.ny - 1) & (caps[14] > 0)
+    au = (I >= 1) & (I <= g.nx - 1) & (J >= 1) & (J <= g.ny) & (caps[7] > 0) & (caps[1] > 0)
+    av = (I >= 1) & (I <= g.nx) & (J >= 1) & (J <= g.ny - 1) & (caps[14] > 0) & (caps[2] > 0)
     ctx.set_field(ccns.F_UX, np.where(au, case.u_inf + px, Dx))
     ctx.set_field(ccns.F_UY, np.where(av, py, Dy))
     ctx.project()
@@ -93,13 +94,13 @@ def test_batch_member_matches_oracle():
     case = W.cylinder_64()
     g = case.grid
     caps = geometry.capacities(g, case.bodies)
-    pr = derived.prepare(caps, g.nx, g.ny)
+    pr = derived.prepare(caps, g.nx, g.ny, vol_floor=case.mass_floor * g.hx * g.hy)
     Dx, Dy = W.dirichlet(case)
     st = pmii.Stepper(pr, pmii.Params(rho=case.rho, mu=case.mu, tau=case.tau, pcg_tol=1e-13, pred_tol=1e-14),
                       Dx, Dy, g.hx)
     s0 = pmii.initial_state(pr, Dx, Dy, case.u_inf, W.perturbation(case))
     capsarr = np.stack([caps[k] for k in ccns.CAP_NAMES])
-    prm = ccns.make_params(case.rho, case.mu, case.tau, pcg_tol=1e-13, pred_tol=1e-14)
+    prm = ccns.make_params(case.rho, case.mu, case.tau, pcg_tol=1e-13, pred_tol=1e-14, mass_floor=case.mass_floor)
     streams = [torch.cuda.Stream() for _ in range(3)]
     ctxs = [ccns.Context(g, prm, capsarr, Dx, Dy, stream=s) for s in streams]
     for c in ctxs:

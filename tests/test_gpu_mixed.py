@@ -60,7 +60,7 @@ def test_mixed_trajectory_against_fp64_oracle(name):
     caps, pr, st, ctx, Dx, Dy = case_setup(case, pcg_tol=1e-13, pred_tol=1e-14, precision=1, div_tol=1e-8)
     ctx.close()
     cp = ccns.make_params(case.rho, case.mu, case.tau, u_ref=case.u_inf, pcg_tol=1e-10, pred_tol=1e-10,
-                          div_tol=1e-8, precision=1)
+                          div_tol=1e-8, precision=1, mass_floor=case.mass_floor)
     ctx = ccns.Context(case.grid, cp, np.stack([caps[k] for k in ccns.CAP_NAMES]), Dx, Dy)
     s0 = pmii.initial_state(pr, Dx, Dy, case.u_inf, W.perturbation(case))
     ctx.set_field(ccns.F_UX, s0.Ux)

@@ -102,6 +102,8 @@ class Case:
     pcg_tol: float = 1e-10
     noise: float = 1e-2
     seed: int = 0
+    # smallest volume the step divides by, as a fraction of a cell
+    mass_floor: float = 0.05
 
     @property
     def ref_length(self) -> float:
@@ -153,7 +155,10 @@ def scaled_cylinder(nx: int, ny: int, lx: float, ly: float, seed: int = 2,
 
 def batched_cylinders(n: int = 256, seed: int = 4, steps: int = 50,
                       sizes=(128, 256, 512, 1024)) -> List[Case]:
-    """Ragged batch: N in sizes, r~U[0.05,0.2], centre jittered, Re~U[50,200]."""
+    """Ragged batch: N in sizes, r~U[0.05,0.2], centre jittered, Re~U[50,200].
+    CFL 0.25 (the paper's airfoil value): the smallest grids at the largest
+    Reynolds numbers have cell Reynolds numbers above 10, where the explicit
+    convection is unstable at 0.5."""
     rng = np.random.default_rng(seed)
     out = []
     for k in range(n):
@@ -163,7 +168,7 @@ def batched_cylinders(n: int = 256, seed: int = 4, steps: int = 50,
         re = float(rng.uniform(50.0, 200.0))
         g = GridSpec(m, m, 0.0, 0.0, 1.0, 1.0)
         out.append(Case(f"batch{k}_{m}", g, [Body(CIRCLE, float(cx), float(cy), a=r)],
-                        re=re, steps=steps, pcg_tol=1e-10, noise=1e-2,
+                        re=re, steps=steps, pcg_tol=1e-10, noise=1e-2, cfl=0.25,
                         seed=seed * 100003 + k))
     return out
 
@@ -179,7 +184,8 @@ class Request:
 def serving_trace(n: int = 400, lam: float = 20.0, seed: int = 5, steps: int = 100,
                   nmin: int = 256, nmax: int = 2048) -> List[Request]:
     """Poisson arrivals; N log-uniform on [nmin, nmax] (multiple of 64);
-    1-3 ellipses with semi-axes U[0.03,0.15], Re~U[50,500]."""
+    1-3 ellipses with semi-axes U[0.03,0.15], Re~U[50,500]; CFL 0.25 (as for
+    the batch)."""
     rng = np.random.default_rng(seed)
     t = 0.0
     out = []
@@ -204,7 +210,7 @@ def serving_trace(n: int = 400, lam: float = 20.0, seed: int = 5, steps: int = 1
                 bodies.append(Body(ELLIPSE, float(cx), float(cy), a=float(a), b=float(b), angle=ang))
         re = float(rng.uniform(50.0, 500.0))
         g = GridSpec(m, m, 0.0, 0.0, 1.0, 1.0)
-        out.append(Request(Case(f"req{k}_{m}", g, bodies, re=re, steps=steps,
+        out.append(Request(Case(f"req{k}_{m}", g, bodies, re=re, steps=steps, cfl=0.25,
                                 pcg_tol=1e-10, noise=1e-2, seed=seed * 100003 + k), t))
     return out
 
