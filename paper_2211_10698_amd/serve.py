@@ -111,11 +111,14 @@ class Server:
         # inputs(case) -> (Dx, Dy, ux_perturbation, uy_perturbation)
         self.inputs = inputs if inputs is not None else _seeded_inputs
         self.max_used = 0      # largest admitted footprint total seen by the last run
+        # a multigrid-preconditioned pressure solve needs tens of iterations;
+        # a request whose solve fails is stopped (status and note recorded)
+        self.pcg_maxit = 2000
 
     def _params(self, case):
         return ccns.make_params(case.rho, case.mu, case.tau, u_ref=case.u_inf, pcg_tol=case.pcg_tol,
                                 pred_tol=1e-12, precision=self.precision, div_tol=1e-8,
-                                mass_floor=case.mass_floor)
+                                mass_floor=case.mass_floor, pcg_maxit=self.pcg_maxit, pred_maxit=500)
 
     def _host_prepare(self, case):
         """Host worker (no GPU calls): capacities from the level set and the
@@ -147,7 +150,8 @@ class Server:
     def _run_steps(ctx, steps, clock):
         """Step worker: advances one simulation through all its steps (the GPU
         is shared with the other running simulations, each on its own
-        stream).  Returns (start, completion, div_rel_max, status, note)."""
+        stream), stopping at the first failed solve.  Returns (start,
+        completion, div_rel_max, status, note)."""
         start = clock()
         div, status, note = 0.0, ccns.OK, ""
         for n in range(steps):
@@ -158,7 +162,7 @@ class Server:
                     status = si.status
                     note = (f"step {n}: {name} solve status {si.status} after {si.iterations} iterations, "
                             f"{si.outer} sweeps, relative residual {si.rel_residual:.2e}")
-            if si.status == ccns.EDEVICE:
+            if status != ccns.OK:
                 break
         return start, clock(), div, status, note
 
