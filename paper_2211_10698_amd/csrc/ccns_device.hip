@@ -636,83 +636,73 @@ __global__ __launch_bounds__(NT) void k_pred_rhs(Dims d, PredCoef pc, const doub
     });
 }
 
-// r = rhs - H x0 (x0 masked to the unknowns) in FP64; statistics of r.
-//  MIX = false: r is stored; partials (f.f, r.z, z, r, r.r), z = M^-1 r.
-//  MIX = true (precision 1): r is rounded to float into r32 (right-hand side
-//  of the inner solve, whose start value x32 is cleared); partials
-//  (r32.r32, r32.z, z, r32, r32.r32, f.f, r.r) with z = M32^-1 r32.
-template <bool MIX>
-__global__ __launch_bounds__(NT) void k_pred_init(Dims d, PredCoef pc, const double *__restrict__ rhs,
-                                                  const double *__restrict__ xs, double *__restrict__ r, CgState *st,
-                                                  double *pout, float *__restrict__ r32, float *__restrict__ x32,
-                                                  const float *__restrict__ hd32) {
-    const size_t P = d.pitch, n = d.n;
-    const double *xu = xs, *xv = xs + n;
-    auto pxm = [&](size_t kk) { return pc.vu[kk] > 0.0 ? xu[kk] : 0.0; };
-    auto pym = [&](size_t kk) { return pc.vv[kk] > 0.0 ? xv[kk] : 0.0; };
-    double v[7] = {0, 0, 0, 0, 0, 0, 0};
-    for_cells(d, [&](int comp, int j, int i, size_t k) {
-        double hv, dv;
-        size_t o;
-        if (MIX) {
-            const size_t oo = comp == 0 ? k : n + k;
-            x32[oo] = 0.0f;
-            r32[oo] = 0.0f;
-        }
-        if (comp == 0) {
-            if (!(pc.vu[k] > 0.0)) return;
-            hv = pc.rt * pc.vu[k] * xu[k] - pc.mu * visc_x(pc.vc, k, P, pxm, pym);
-            o = k;
-            dv = pc.hdx[k];
-        } else {
-            if (!(pc.vv[k] > 0.0)) return;
-            hv = pc.rt * pc.vv[k] * xv[k] - pc.mu * visc_y(pc.vc, k, P, pxm, pym);
-            o = n + k;
-            dv = pc.hdy[k];
-        }
-        const double f = rhs[o];
-        const double rv = f - hv;
-        if (MIX) {
-            const float rf = (float)rv;
-            r32[o] = rf;
-            const float sf = hd32[o] * rf;
-            const double rd = rf, sd = sf;
-            v[0] += rd * rd;
-            v[1] += rd * sd;
-            v[2] += sd;
-            v[3] += rd;
-            v[4] += rd * rd;
-            v[5] += f * f;
-            v[6] += rv * rv;
-        } else {
-            r[o] = rv;
-            const double sv = dv * rv;
-            v[0] += f * f;
-            v[1] += rv * sv;
-            v[2] += sv;
-            v[3] += rv;
-            v[4] += rv * rv;
-        }
-    });
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        st->done = 0;
-        st->status = 0;
-        st->it_final = 0;
-    }
-    if (MIX) {
-        put_partials<7>(v, pout, d.nblk);
-    } else {
-        double w[5] = {v[0], v[1], v[2], v[3], v[4]};
-        put_partials<5>(w, pout, d.nblk);
-    }
-}
-
 // Predictor direction and operator, both velocity components of a 64 x 8
 // tile per work-group.  p = M r + beta p_old is staged in LDS on the tile and
 // a one-face halo; the strains of eq:diag / eq:offdiag are formed once per
 // cell and node in LDS; then H p = (rho/tau) V p - mu visc(S) (Sec. 4.3) on
 // the tile.  Partial p.H p per group.
 constexpr int HTY = 8;
+
+// LDS of a predictor tile: the staged face field on the tile and a one-face
+// halo, and its strains (cells and nodes) of eq:diag / eq:offdiag.
+template <class T>
+struct PredTile {
+    T spx[HTY + 2][TX + 2], spy[HTY + 2][TX + 2];
+    T sxx[HTY][TX + 1], syy[HTY + 1][TX];
+    T snx[HTY + 1][TX + 1], sny[HTY + 1][TX + 1];
+};
+
+// The strains of the staged field (rows r0-1 .. r0+HTY, cols c0-1 .. c0+TX
+// staged in spx, spy), formed once per cell and node.
+template <class T>
+__device__ inline void pred_tile_strains(PredTile<T> &s, const ViscCoefT<T> &c, int P, int rows, int c0, int r0) {
+    // S_xx at cells (rows r0.., cols c0 .. c0+TX): x-faces i-1, i
+    for (int e = threadIdx.x; e < HTY * (TX + 1); e += NT) {
+        const int ly = e / (TX + 1), lx = e - ly * (TX + 1);
+        const int j = r0 + ly, i = c0 + lx;
+        const bool in = (j < rows) && (i >= 1) && (i < P);
+        const size_t k = in ? (size_t)j * P + i : 1;
+        const T w = c.wxx[k], be = c.bxx[k], bw = c.bxx[k - 1];
+        s.sxx[ly][lx] = in ? w * (be * s.spx[ly + 1][lx + 1] - bw * s.spx[ly + 1][lx]) : (T)0;
+    }
+    // S_yy at cells (rows r0 .. r0+HTY, cols c0..): y-faces j-1, j
+    for (int e = threadIdx.x; e < (HTY + 1) * TX; e += NT) {
+        const int ly = e / TX, lx = e - ly * TX;
+        const int j = r0 + ly, i = c0 + lx;
+        const bool in = (j >= 1) && (j < rows);
+        const size_t k = in ? (size_t)j * P + i : (size_t)P;
+        const T w = c.wyy[k], bn = c.byy[k], bs = c.byy[k - P];
+        s.syy[ly][lx] = in ? w * (bn * s.spy[ly + 1][lx + 1] - bs * s.spy[ly][lx + 1]) : (T)0;
+    }
+    // node strains (rows r0-1 .. r0+HTY-1, cols c0-1 .. c0+TX-1)
+    for (int e = threadIdx.x; e < (HTY + 1) * (TX + 1); e += NT) {
+        const int ly = e / (TX + 1), lx = e - ly * (TX + 1);
+        const int j = r0 - 1 + ly, i = c0 - 1 + lx;
+        const bool in = (j >= 0) && (j + 1 < rows) && (i >= 0) && (i + 1 < P);
+        const size_t k = in ? (size_t)j * P + i : 0;
+        const T bxn = c.bxy[k + P], bxs = c.bxy[k], bye = c.byx[k + 1], byw = c.byx[k];
+        const T gxv = bxn * s.spx[ly + 1][lx] - bxs * s.spx[ly][lx];
+        const T gyv = bye * s.spy[ly][lx + 1] - byw * s.spy[ly][lx];
+        const T a = c.nxx[k], b = c.nxy[k], cc = c.nyx[k], dd = c.nyy[k];
+        s.snx[ly][lx] = in ? (T)0.5 * (a * gxv + b * gyv) : (T)0;
+        s.sny[ly][lx] = in ? (T)0.5 * (cc * gxv + dd * gyv) : (T)0;
+    }
+}
+
+// K v = visc(strain(v, 0)) (Sec. 4.3) at tile entry (ly, tx), index k.
+template <class T>
+__device__ inline void pred_tile_K(const PredTile<T> &s, const ViscCoefT<T> &c, size_t k, int ly, int tx, T &kx,
+                                   T &ky) {
+    const T bxx = c.bxx[k], bxy = c.bxy[k], byy = c.byy[k], byx = c.byx[k];
+    kx = bxx * (s.sxx[ly][tx + 1] - s.sxx[ly][tx]) + bxy * (s.snx[ly + 1][tx + 1] - s.snx[ly][tx + 1]);
+    ky = byy * (s.syy[ly + 1][tx] - s.syy[ly][tx]) + byx * (s.sny[ly + 1][tx + 1] - s.sny[ly + 1][tx]);
+}
+
+// Predictor direction and operator, both velocity components of a 64 x 8
+// tile per work-group.  p = M r + beta p_old is staged in LDS on the tile and
+// a one-face halo; the strains are formed once per cell and node in LDS; then
+// H p = (rho/tau) M p - mu visc(S) (Sec. 4.3) on the tile.  Partial p.H p per
+// group.
 template <class T>
 __global__ __launch_bounds__(NT) void k_pred_dir_lds(int nx, int ny, int P, int rows, int gx, int gy, size_t n,
                                                      PredCoefT<T> pc, const T *__restrict__ r,
@@ -734,10 +724,7 @@ __global__ __launch_bounds__(NT) void k_pred_dir_lds(int nx, int ny, int P, int 
     if (ds.stop) return;
     const T beta = (T)ds.beta;
     const T rt = (T)pc.rt, mu = (T)pc.mu;
-    __shared__ T spx[HTY + 2][TX + 2], spy[HTY + 2][TX + 2];
-    __shared__ T sxx[HTY][TX + 1], syy[HTY + 1][TX];
-    __shared__ T snx[HTY + 1][TX + 1], sny[HTY + 1][TX + 1];
-    const ViscCoefT<T> &c = pc.vc;
+    __shared__ PredTile<T> s;
     const int L = logical_group(((gridDim.x + 7) / 8) * 8);
     const bool live = L < gx * gy;
     const int c0 = (L % gx) * TX, r0 = (L / gx) * HTY;
@@ -750,44 +737,12 @@ __global__ __launch_bounds__(NT) void k_pred_dir_lds(int nx, int ny, int P, int 
             const bool in = (j >= 0) && (j < rows) && (i >= 0) && (i < P);
             const size_t k = in ? (size_t)j * P + i : 0;
             const T hx = pc.hdx[k], hy = pc.hdy[k], rx = r[k], ry = r[n + k], ox = pold[k], oy = pold[n + k];
-            spx[ly][lx] = in ? hx * rx + beta * ox : (T)0;
-            spy[ly][lx] = in ? hy * ry + beta * oy : (T)0;
+            s.spx[ly][lx] = in ? hx * rx + beta * ox : (T)0;
+            s.spy[ly][lx] = in ? hy * ry + beta * oy : (T)0;
         }
     }
     __syncthreads();
-    if (live) {
-        // S_xx at cells (rows r0.., cols c0 .. c0+TX): x-faces i-1, i
-        for (int e = threadIdx.x; e < HTY * (TX + 1); e += NT) {
-            const int ly = e / (TX + 1), lx = e - ly * (TX + 1);
-            const int j = r0 + ly, i = c0 + lx;
-            const bool in = (j < rows) && (i >= 1) && (i < P);
-            const size_t k = in ? (size_t)j * P + i : 1;
-            const T w = c.wxx[k], be = c.bxx[k], bw = c.bxx[k - 1];
-            sxx[ly][lx] = in ? w * (be * spx[ly + 1][lx + 1] - bw * spx[ly + 1][lx]) : (T)0;
-        }
-        // S_yy at cells (rows r0 .. r0+HTY, cols c0..): y-faces j-1, j
-        for (int e = threadIdx.x; e < (HTY + 1) * TX; e += NT) {
-            const int ly = e / TX, lx = e - ly * TX;
-            const int j = r0 + ly, i = c0 + lx;
-            const bool in = (j >= 1) && (j < rows);
-            const size_t k = in ? (size_t)j * P + i : (size_t)P;
-            const T w = c.wyy[k], bn = c.byy[k], bs = c.byy[k - P];
-            syy[ly][lx] = in ? w * (bn * spy[ly + 1][lx + 1] - bs * spy[ly][lx + 1]) : (T)0;
-        }
-        // node strains (rows r0-1 .. r0+HTY-1, cols c0-1 .. c0+TX-1)
-        for (int e = threadIdx.x; e < (HTY + 1) * (TX + 1); e += NT) {
-            const int ly = e / (TX + 1), lx = e - ly * (TX + 1);
-            const int j = r0 - 1 + ly, i = c0 - 1 + lx;
-            const bool in = (j >= 0) && (j + 1 < rows) && (i >= 0) && (i + 1 < P);
-            const size_t k = in ? (size_t)j * P + i : 0;
-            const T bxn = c.bxy[k + P], bxs = c.bxy[k], bye = c.byx[k + 1], byw = c.byx[k];
-            const T gxv = bxn * spx[ly + 1][lx] - bxs * spx[ly][lx];
-            const T gyv = bye * spy[ly][lx + 1] - byw * spy[ly][lx];
-            const T a = c.nxx[k], b = c.nxy[k], cc = c.nyx[k], dd = c.nyy[k];
-            snx[ly][lx] = in ? (T)0.5 * (a * gxv + b * gyv) : (T)0;
-            sny[ly][lx] = in ? (T)0.5 * (cc * gxv + dd * gyv) : (T)0;
-        }
-    }
+    if (live) pred_tile_strains<T>(s, pc.vc, P, rows, c0, r0);
     __syncthreads();
     if (live) {
         const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
@@ -796,10 +751,9 @@ __global__ __launch_bounds__(NT) void k_pred_dir_lds(int nx, int ny, int P, int 
             if (j >= rows) break;
             const size_t k = (size_t)j * P + i;
             const T vu = pc.vu[k], vv = pc.vv[k];
-            const T bxx = c.bxx[k], bxy = c.bxy[k], byy = c.byy[k], byx = c.byx[k];
-            const T px = spx[ly + 1][tx + 1], py = spy[ly + 1][tx + 1];
-            const T kx = bxx * (sxx[ly][tx + 1] - sxx[ly][tx]) + bxy * (snx[ly + 1][tx + 1] - snx[ly][tx + 1]);
-            const T ky = byy * (syy[ly + 1][tx] - syy[ly][tx]) + byx * (sny[ly + 1][tx + 1] - sny[ly + 1][tx]);
+            const T px = s.spx[ly + 1][tx + 1], py = s.spy[ly + 1][tx + 1];
+            T kx, ky;
+            pred_tile_K<T>(s, pc.vc, k, ly, tx, kx, ky);
             const T qx = vu > (T)0 ? rt * vu * px - mu * kx : (T)0;
             const T qy = vv > (T)0 ? rt * vv * py - mu * ky : (T)0;
             const T pxo = vu > (T)0 ? px : (T)0, pyo = vv > (T)0 ? py : (T)0;
@@ -811,6 +765,95 @@ __global__ __launch_bounds__(NT) void k_pred_dir_lds(int nx, int ny, int P, int 
         }
     }
     put_partials<1>(v, pout, gridDim.x);
+}
+
+// Predictor residual r = rhs - H x in FP64 on the tiles of k_pred_dir_lds
+// (x staged in LDS, masked to the unknowns), with the statistics of r.
+//  MIX = false: r is stored; partials (f.f, r.z, z, r, r.r), z = M^-1 r.
+//  MIX = true (precision 1): r is rounded to float into r32 (right-hand side
+//  of the inner solve, whose start value x32 is cleared); partials
+//  (r32.r32, r32.z, z, r32, r32.r32, f.f, r.r) with z = M32^-1 r32.
+template <bool MIX>
+__global__ __launch_bounds__(NT) void k_pred_resid(int P, int rows, int gx, int gy, size_t n, PredCoefT<double> pc,
+                                                   const double *__restrict__ rhs, const double *__restrict__ xs,
+                                                   double *__restrict__ r, CgState *st, double *pout,
+                                                   float *__restrict__ r32, float *__restrict__ x32,
+                                                   const float *__restrict__ hd32) {
+    __shared__ PredTile<double> s;
+    const int L = logical_group(((gridDim.x + 7) / 8) * 8);
+    const bool live = L < gx * gy;
+    const int c0 = (L % gx) * TX, r0 = (L / gx) * HTY;
+    double v[7] = {0, 0, 0, 0, 0, 0, 0};
+    if (live) {
+        for (int e = threadIdx.x; e < (HTY + 2) * (TX + 2); e += NT) {
+            const int ly = e / (TX + 2), lx = e - ly * (TX + 2);
+            const int j = r0 - 1 + ly, i = c0 - 1 + lx;
+            const bool in = (j >= 0) && (j < rows) && (i >= 0) && (i < P);
+            const size_t k = in ? (size_t)j * P + i : 0;
+            const double mx = pc.vu[k], my = pc.vv[k], ux = xs[k], uy = xs[n + k];
+            s.spx[ly][lx] = (in && mx > 0.0) ? ux : 0.0;
+            s.spy[ly][lx] = (in && my > 0.0) ? uy : 0.0;
+        }
+    }
+    __syncthreads();
+    if (live) pred_tile_strains<double>(s, pc.vc, P, rows, c0, r0);
+    __syncthreads();
+    if (live) {
+        const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+        for (int ly = ty; ly < HTY; ly += 4) {
+            const int j = r0 + ly, i = c0 + tx;
+            if (j >= rows) break;
+            const size_t k = (size_t)j * P + i;
+            double kv[2];
+            pred_tile_K<double>(s, pc.vc, k, ly, tx, kv[0], kv[1]);
+            const double m[2] = {pc.vu[k], pc.vv[k]};
+            const double xv[2] = {s.spx[ly + 1][tx + 1], s.spy[ly + 1][tx + 1]};
+            const double hd[2] = {pc.hdx[k], pc.hdy[k]};
+#pragma unroll
+            for (int comp = 0; comp < 2; ++comp) {
+                const size_t o = comp == 0 ? k : n + k;
+                if (MIX) {
+                    x32[o] = 0.0f;
+                    r32[o] = 0.0f;
+                }
+                if (!(m[comp] > 0.0)) continue;
+                const double f = rhs[o];
+                const double rv = f - (pc.rt * m[comp] * xv[comp] - pc.mu * kv[comp]);
+                if (MIX) {
+                    const float rf = (float)rv;
+                    r32[o] = rf;
+                    const float sf = hd32[o] * rf;
+                    const double rd = rf, sd = sf;
+                    v[0] += rd * rd;
+                    v[1] += rd * sd;
+                    v[2] += sd;
+                    v[3] += rd;
+                    v[4] += rd * rd;
+                    v[5] += f * f;
+                    v[6] += rv * rv;
+                } else {
+                    r[o] = rv;
+                    const double sv = hd[comp] * rv;
+                    v[0] += f * f;
+                    v[1] += rv * sv;
+                    v[2] += sv;
+                    v[3] += rv;
+                    v[4] += rv * rv;
+                }
+            }
+        }
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        st->done = 0;
+        st->status = 0;
+        st->it_final = 0;
+    }
+    if (MIX) {
+        put_partials<7>(v, pout, gridDim.x);
+    } else {
+        double w[5] = {v[0], v[1], v[2], v[3], v[4]};
+        put_partials<5>(w, pout, gridDim.x);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1191,6 +1234,13 @@ PredCoef pred_coef(ccns_ctx *c) {
     return p;
 }
 
+PredCoefT<double> pred_coef_t(ccns_ctx *c) {
+    PredCoef pc = pred_coef(c);
+    return PredCoefT<double>{ViscCoefT<double>{pc.vc.bxx, pc.vc.bxy, pc.vc.byy, pc.vc.byx, pc.vc.wxx, pc.vc.wyy,
+                                               pc.vc.nxx, pc.vc.nxy, pc.vc.nyx, pc.vc.nyy},
+                             pc.vu, pc.vv, pc.hdx, pc.hdy, pc.rt, pc.mu};
+}
+
 // dense (ny+2)x(nx+2) <-> padded device array
 ccns_status to_dev(ccns_ctx *c, double *dst, const double *src, hipMemcpyKind kind) {
     const size_t W = c->g.nx + 2;
@@ -1539,9 +1589,9 @@ double inner_tol(double reduction) {
     return std::min(INNER_TOL_MAX, std::max(INNER_TOL_MIN, 0.5 * reduction));
 }
 
-ccns_status read_outer(ccns_ctx *c, int n) {
+ccns_status read_outer(ccns_ctx *c, const double *src, int n) {
     HIPCHK(c, hipGetLastError());
-    HIPCHK(c, hipMemcpyAsync(c->h_outer, c->outer, n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->h_outer, src, n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return CCNS_OK;
 }
@@ -1566,7 +1616,7 @@ ccns_status pressure_solve_mixed(ccns_ctx *c, int nin, ccns_solve_info *info) {
                                                             c->part[PB_INIT], c->f[G_R], c->f[G_X], c->f[G_DINV]);
         c->init_nblk = c->dc.nblk;
         k_reduce_partials<7, 1><<<1, NT, 0, c->stream>>>(c->part[PB_INIT], c->dc.nblk, c->outer);
-        ccns_status s = read_outer(c, 8);
+        ccns_status s = read_outer(c, c->outer, 8);
         if (s != CCNS_OK) return s;
         if (o == 0) bn2 = c->h_outer[5];
         rn2 = c->h_outer[6];
@@ -1633,7 +1683,7 @@ void predictor_rhs(ccns_ctx *c) {
 template <class T>
 ccns_status pred_cg(ccns_ctx *c, PredCoefT<T> pc, CgState *st, T *x, T *r, T *p0, T *p1, T *q, int &last_it,
                     ccns_solve_info *info) {
-    c->init_nblk = c->df.nblk;
+    c->init_nblk = 1;  // the residual kernel's statistics, reduced to one group
     T *pb[2] = {p0, p1};
     const Layout &L = c->w.L;
     const int gx = L.pitch / TX, gy = (L.rows + HTY - 1) / HTY;
@@ -1646,14 +1696,27 @@ ccns_status pred_cg(ccns_ctx *c, PredCoefT<T> pc, CgState *st, T *x, T *r, T *p0
     return cg_loop<T>(c, st, x, r, pb, c->pbuf_pred, q, pc.hdx, 2 * c->w.L.n, last_it, dir, [] {}, info, 2);
 }
 
+// r = rhs - H x in FP64 (tiled residual kernel), its statistics reduced to
+// one group in PB_INIT (NS = 5, or 7 with MIX).
+template <bool MIX>
+void pred_residual(ccns_ctx *c, CgState *st) {
+    PredCoefT<double> pd = pred_coef_t(c);
+    const Layout &L = c->w.L;
+    const int gx = L.pitch / TX, gy = (L.rows + HTY - 1) / HTY;
+    const int nb = ((gx * gy + 7) / 8) * 8;
+    k_pred_resid<MIX><<<nb, NT, 0, c->stream>>>(L.pitch, L.rows, gx, gy, L.n, pd, c->a[A_RHSX], c->a[A_USX],
+                                                c->a[A_PRX], st, c->part[PB_RHS], MIX ? c->f[G_PRX] : nullptr,
+                                                MIX ? c->f[G_PXX] : nullptr, MIX ? c->f[G_HDX] : nullptr);
+    if (MIX)
+        k_reduce_partials<7><<<1, NT, 0, c->stream>>>(c->part[PB_RHS], nb, c->part[PB_INIT]);
+    else
+        k_reduce_partials<5><<<1, NT, 0, c->stream>>>(c->part[PB_RHS], nb, c->part[PB_INIT]);
+}
+
 ccns_status predict_dev(ccns_ctx *c, ccns_solve_info *info) {
-    PredCoef pc = pred_coef(c);
     predictor_rhs(c);
-    k_pred_init<false><<<c->df.nblk, NT, 0, c->stream>>>(c->df, pc, c->a[A_RHSX], c->a[A_USX], c->a[A_PRX],
-                                                         c->st_pred, c->part[PB_INIT], nullptr, nullptr, nullptr);
-    PredCoefT<double> pd{ViscCoefT<double>{pc.vc.bxx, pc.vc.bxy, pc.vc.byy, pc.vc.byx, pc.vc.wxx, pc.vc.wyy,
-                                           pc.vc.nxx, pc.vc.nxy, pc.vc.nyx, pc.vc.nyy},
-                         pc.vu, pc.vv, pc.hdx, pc.hdy, pc.rt, pc.mu};
+    pred_residual<false>(c, c->st_pred);
+    PredCoefT<double> pd = pred_coef_t(c);
     return pred_cg<double>(c, pd, c->st_pred, c->a[A_USX], c->a[A_PRX], c->a[A_PP0X], c->a[A_PP1X], c->a[A_PQX],
                            c->last_pred_it, info);
 }
@@ -1672,11 +1735,8 @@ ccns_status predict_mixed(ccns_ctx *c, ccns_solve_info *info) {
     int inner_its = 0, sweeps = 0;
     ccns_status st = CCNS_ENOTCONV;
     for (int o = 0;; ++o) {
-        k_pred_init<true><<<c->df.nblk, NT, 0, c->stream>>>(c->df, pc, c->a[A_RHSX], c->a[A_USX], nullptr,
-                                                            c->st_pred_in, c->part[PB_INIT], c->f[G_PRX],
-                                                            c->f[G_PXX], c->f[G_HDX]);
-        k_reduce_partials<7><<<1, NT, 0, c->stream>>>(c->part[PB_INIT], c->df.nblk, c->outer);
-        ccns_status s = read_outer(c, 7);
+        pred_residual<true>(c, c->st_pred_in);
+        ccns_status s = read_outer(c, c->part[PB_INIT], 7);
         if (s != CCNS_OK) return s;
         fn2 = c->h_outer[5];
         rn2 = c->h_outer[6];
