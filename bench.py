@@ -38,9 +38,11 @@ DEVICE_SRC = os.path.join(ROOT, "paper_2211_10698_amd", "csrc", "ccns_device.hip
 KERNEL_HDR = os.path.join(ROOT, "paper_2211_10698_amd", "csrc", "ccns_kern.h")
 # Algorithmic bytes per cell of the timed kernels (FP64 = 8 bytes per value).
 # Predictor direction+operator, per cell = one x-face and one y-face: reads
-# r, p_old, M^-1 (2 components each), V^x, V^y, B^xx, B^xy, B^yy, B^yx,
-# 1/W^xx, 1/W^yy and the four node weights; writes p and H p (2 each).
-PRED_DIR_BYTES_PER_CELL = 22 * 8.0
+# r, p_old, M^-1 (2 components each), M^x, M^y, B^xx, B^xy, B^yy, B^yx,
+# 1/W^xx, 1/W^yy and the two diagonal node weights (the cross weight of the
+# symmetric form is their geometric mean, formed in the kernel); writes p and
+# H p (2 each).
+PRED_DIR_BYTES_PER_CELL = 20 * 8.0
 # CG update over the two face components: reads M^-1, x, p, r, H p; writes x, r.
 PRED_UPDATE_BYTES_PER_CELL = 2 * 7 * 8.0
 # Poisson direction+operator (multigrid path): reads z, p_old, 1/diag, c^x,

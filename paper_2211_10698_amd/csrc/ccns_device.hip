@@ -653,8 +653,10 @@ struct PredTile {
 };
 
 // The strains of the staged field (rows r0-1 .. r0+HTY, cols c0-1 .. c0+TX
-// staged in spx, spy), formed once per cell and node.
-template <class T>
+// staged in spx, spy), formed once per cell and node.  GEO: the node weights
+// are the symmetric geometric form (cross weight = sqrt of the product of the
+// two diagonal ones), so the cross weights are formed instead of read.
+template <class T, bool GEO>
 __device__ inline void pred_tile_strains(PredTile<T> &s, const ViscCoefT<T> &c, int P, int rows, int c0, int r0) {
     // S_xx at cells (rows r0.., cols c0 .. c0+TX): x-faces i-1, i
     for (int e = threadIdx.x; e < HTY * (TX + 1); e += NT) {
@@ -683,7 +685,14 @@ __device__ inline void pred_tile_strains(PredTile<T> &s, const ViscCoefT<T> &c, 
         const T bxn = c.bxy[k + P], bxs = c.bxy[k], bye = c.byx[k + 1], byw = c.byx[k];
         const T gxv = bxn * s.spx[ly + 1][lx] - bxs * s.spx[ly][lx];
         const T gyv = bye * s.spy[ly][lx + 1] - byw * s.spy[ly][lx];
-        const T a = c.nxx[k], b = c.nxy[k], cc = c.nyx[k], dd = c.nyy[k];
+        const T a = c.nxx[k], dd = c.nyy[k];
+        T b, cc;
+        if (GEO) {
+            b = cc = sqrt(a * dd);
+        } else {
+            b = c.nxy[k];
+            cc = c.nyx[k];
+        }
         s.snx[ly][lx] = in ? (T)0.5 * (a * gxv + b * gyv) : (T)0;
         s.sny[ly][lx] = in ? (T)0.5 * (cc * gxv + dd * gyv) : (T)0;
     }
@@ -703,7 +712,7 @@ __device__ inline void pred_tile_K(const PredTile<T> &s, const ViscCoefT<T> &c, 
 // a one-face halo; the strains are formed once per cell and node in LDS; then
 // H p = (rho/tau) M p - mu visc(S) (Sec. 4.3) on the tile.  Partial p.H p per
 // group.
-template <class T>
+template <class T, bool GEO>
 __global__ __launch_bounds__(NT) void k_pred_dir_lds(int nx, int ny, int P, int rows, int gx, int gy, size_t n,
                                                      PredCoefT<T> pc, const T *__restrict__ r,
                                                      const T *__restrict__ pold, T *__restrict__ pnew,
@@ -742,7 +751,7 @@ __global__ __launch_bounds__(NT) void k_pred_dir_lds(int nx, int ny, int P, int 
         }
     }
     __syncthreads();
-    if (live) pred_tile_strains<T>(s, pc.vc, P, rows, c0, r0);
+    if (live) pred_tile_strains<T, GEO>(s, pc.vc, P, rows, c0, r0);
     __syncthreads();
     if (live) {
         const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
@@ -773,7 +782,7 @@ __global__ __launch_bounds__(NT) void k_pred_dir_lds(int nx, int ny, int P, int 
 //  MIX = true (precision 1): r is rounded to float into r32 (right-hand side
 //  of the inner solve, whose start value x32 is cleared); partials
 //  (r32.r32, r32.z, z, r32, r32.r32, f.f, r.r) with z = M32^-1 r32.
-template <bool MIX>
+template <bool MIX, bool GEO>
 __global__ __launch_bounds__(NT) void k_pred_resid(int P, int rows, int gx, int gy, size_t n, PredCoefT<double> pc,
                                                    const double *__restrict__ rhs, const double *__restrict__ xs,
                                                    double *__restrict__ r, CgState *st, double *pout,
@@ -796,7 +805,7 @@ __global__ __launch_bounds__(NT) void k_pred_resid(int P, int rows, int gx, int 
         }
     }
     __syncthreads();
-    if (live) pred_tile_strains<double>(s, pc.vc, P, rows, c0, r0);
+    if (live) pred_tile_strains<double, GEO>(s, pc.vc, P, rows, c0, r0);
     __syncthreads();
     if (live) {
         const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
@@ -1689,8 +1698,12 @@ ccns_status pred_cg(ccns_ctx *c, PredCoefT<T> pc, CgState *st, T *x, T *r, T *p0
     const int gx = L.pitch / TX, gy = (L.rows + HTY - 1) / HTY;
     const int nb = ((gx * gy + 7) / 8) * 8;
     auto dir = [&](int first, int par, T *pold, T *pnew, const double *pin, int nin, double *pout) {
-        k_pred_dir_lds<T><<<nb, NT, 0, c->stream>>>(L.nx, L.ny, L.pitch, L.rows, gx, gy, L.n, pc, r, pold, pnew, q,
-                                                    st, first, par, pin, nin, pout);
+        if (c->prm.visc_form == 0)
+            k_pred_dir_lds<T, true><<<nb, NT, 0, c->stream>>>(L.nx, L.ny, L.pitch, L.rows, gx, gy, L.n, pc, r, pold,
+                                                              pnew, q, st, first, par, pin, nin, pout);
+        else
+            k_pred_dir_lds<T, false><<<nb, NT, 0, c->stream>>>(L.nx, L.ny, L.pitch, L.rows, gx, gy, L.n, pc, r, pold,
+                                                               pnew, q, st, first, par, pin, nin, pout);
         return nb;
     };
     return cg_loop<T>(c, st, x, r, pb, c->pbuf_pred, q, pc.hdx, 2 * c->w.L.n, last_it, dir, [] {}, info, 2);
@@ -1704,9 +1717,16 @@ void pred_residual(ccns_ctx *c, CgState *st) {
     const Layout &L = c->w.L;
     const int gx = L.pitch / TX, gy = (L.rows + HTY - 1) / HTY;
     const int nb = ((gx * gy + 7) / 8) * 8;
-    k_pred_resid<MIX><<<nb, NT, 0, c->stream>>>(L.pitch, L.rows, gx, gy, L.n, pd, c->a[A_RHSX], c->a[A_USX],
-                                                c->a[A_PRX], st, c->part[PB_RHS], MIX ? c->f[G_PRX] : nullptr,
-                                                MIX ? c->f[G_PXX] : nullptr, MIX ? c->f[G_HDX] : nullptr);
+    float *r32 = MIX ? c->f[G_PRX] : nullptr, *x32 = MIX ? c->f[G_PXX] : nullptr;
+    const float *hd32 = MIX ? c->f[G_HDX] : nullptr;
+    if (c->prm.visc_form == 0)
+        k_pred_resid<MIX, true><<<nb, NT, 0, c->stream>>>(L.pitch, L.rows, gx, gy, L.n, pd, c->a[A_RHSX],
+                                                          c->a[A_USX], c->a[A_PRX], st, c->part[PB_RHS], r32, x32,
+                                                          hd32);
+    else
+        k_pred_resid<MIX, false><<<nb, NT, 0, c->stream>>>(L.pitch, L.rows, gx, gy, L.n, pd, c->a[A_RHSX],
+                                                           c->a[A_USX], c->a[A_PRX], st, c->part[PB_RHS], r32, x32,
+                                                           hd32);
     if (MIX)
         k_reduce_partials<7><<<1, NT, 0, c->stream>>>(c->part[PB_RHS], nb, c->part[PB_INIT]);
     else
