@@ -507,6 +507,126 @@ __global__ __launch_bounds__(NT) void k_mg_up(int nx, int ny, int P, int gx, Poi
     if (STATS) put_partials<4>(v, pout, nblk);
 }
 
+// The coarse end of the cycle in one work-group of TT threads: every level
+// from the tail's first down to the coarsest and back, one phase after the
+// other with work-group barriers between them (the levels are a few thousand
+// cells: one launch instead of two per level, each of which would be a
+// latency-bound launch of a few work-groups).  The arithmetic and its order
+// per cell are those of k_mg_down, k_mg_coarsest and k_mg_up.  The level
+// arrays stay in global memory (L2); within one work-group a barrier makes
+// the global writes of one phase visible to the next.
+constexpr int TT = 1024;
+constexpr int MAX_TAIL = 10;
+template <class T>
+struct TailLevel {
+    const T *cx, *cy, *dinv;
+    T *b, *x, *xt;
+    int nx, ny, P;
+};
+template <class T>
+struct TailDesc {
+    TailLevel<T> lv[MAX_TAIL];
+    int nlev;            // levels of the tail, the last one the coarsest
+    int ncoarse;         // unknowns of the coarsest grid
+    const int *idx;
+    const double *pinv;
+    T omega;
+};
+
+template <class T>
+__device__ inline T tail_Ax(const TailLevel<T> &L, const T *v, size_t k) {
+    const T ce = L.cx[k], cw = L.cx[k - 1], cn = L.cy[k], cs = L.cy[k - L.P];
+    return (ce + cw + cn + cs) * v[k] - ce * v[k + 1] - cw * v[k - 1] - cn * v[k + L.P] - cs * v[k - L.P];
+}
+
+template <class T>
+__global__ __launch_bounds__(TT) void k_mg_tail(TailDesc<T> d) {
+    const T om = d.omega;
+    // down: two sweeps from zero, the residual restricted to the next level
+    for (int l = 0; l + 1 < d.nlev; ++l) {
+        const TailLevel<T> &L = d.lv[l];
+        const TailLevel<T> &C = d.lv[l + 1];
+        const int ncell = L.nx * L.ny;
+        for (int e = threadIdx.x; e < ncell; e += TT) {
+            const size_t k = (size_t)(e / L.nx + 1) * L.P + (e % L.nx + 1);
+            const T dv = L.dinv[k], bv = L.b[k];
+            L.xt[k] = dv > (T)0 ? om * dv * bv : (T)0;
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < ncell; e += TT) {
+            const size_t k = (size_t)(e / L.nx + 1) * L.P + (e % L.nx + 1);
+            const T dv = L.dinv[k], bv = L.b[k];
+            const T xv = L.xt[k];
+            L.x[k] = dv > (T)0 ? xv + om * dv * (bv - tail_Ax(L, L.xt, k)) : (T)0;
+        }
+        __syncthreads();
+        const int nc = C.nx * C.ny;
+        for (int e = threadIdx.x; e < nc; e += TT) {
+            const int I = e % C.nx + 1, J = e / C.nx + 1;
+            T r[2][2];
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int bb = 0; bb < 2; ++bb) {
+                    const int j = 2 * J - 1 + a, i = 2 * I - 1 + bb;
+                    T rv = (T)0;
+                    if (j <= L.ny && i <= L.nx) {
+                        const size_t k = (size_t)j * L.P + i;
+                        const T dv = L.dinv[k];
+                        if (dv > (T)0) rv = L.b[k] - tail_Ax(L, L.x, k);
+                    }
+                    r[a][bb] = rv;
+                }
+            const size_t kc = (size_t)J * C.P + I;
+            const T sum = (r[0][0] + r[0][1]) + (r[1][0] + r[1][1]);
+            C.b[kc] = C.dinv[kc] > (T)0 ? sum : (T)0;
+        }
+        __syncthreads();
+    }
+    // coarsest: x = A^+ b with the dense pseudo-inverse
+    {
+        const TailLevel<T> &L = d.lv[d.nlev - 1];
+        __shared__ double sb[1024];
+        for (int i = threadIdx.x; i < d.ncoarse; i += TT) sb[i] = L.b[d.idx[i]];
+        __syncthreads();
+        for (int i = threadIdx.x; i < d.ncoarse; i += TT) {
+            double acc = 0.0;
+            for (int j2 = 0; j2 < d.ncoarse; ++j2) acc += d.pinv[(size_t)i * d.ncoarse + j2] * sb[j2];
+            L.x[d.idx[i]] = (T)acc;
+        }
+        __syncthreads();
+    }
+    // up: the coarse correction interpolated onto x2, then two sweeps
+    for (int l = d.nlev - 2; l >= 0; --l) {
+        const TailLevel<T> &L = d.lv[l];
+        const TailLevel<T> &C = d.lv[l + 1];
+        const T *xc = (l + 2 == d.nlev) ? C.x : C.xt;
+        const int ncell = L.nx * L.ny;
+        for (int e = threadIdx.x; e < ncell; e += TT) {
+            const int i = e % L.nx + 1, j = e / L.nx + 1;
+            const size_t k = (size_t)j * L.P + i;
+            const size_t kc = (size_t)((j + 1) >> 1) * C.P + ((i + 1) >> 1);
+            const T dv = L.dinv[k], xv = L.x[k], ec = xc[kc];
+            L.xt[k] = dv > (T)0 ? xv + ec : (T)0;
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < ncell; e += TT) {
+            const size_t k = (size_t)(e / L.nx + 1) * L.P + (e % L.nx + 1);
+            const T dv = L.dinv[k], bv = L.b[k];
+            const T xv = L.xt[k];
+            L.x[k] = dv > (T)0 ? xv + om * dv * (bv - tail_Ax(L, L.xt, k)) : (T)0;
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < ncell; e += TT) {
+            const size_t k = (size_t)(e / L.nx + 1) * L.P + (e % L.nx + 1);
+            const T dv = L.dinv[k], bv = L.b[k];
+            const T xv = L.x[k];
+            L.xt[k] = dv > (T)0 ? xv + om * dv * (bv - tail_Ax(L, L.x, k)) : (T)0;
+        }
+        __syncthreads();
+    }
+}
+
 // One work-group sums the partials of a producer into a single group's worth
 // (so that consumers read N values instead of N per producer group).
 template <int NS, int NM = 0>
@@ -1507,6 +1627,16 @@ ccns_status mg_setup(ccns_ctx *c, const HostCoef &hc) {
 // z = V(b) on level l of a hierarchy; returns the array holding the result.
 // On level 0 the last kernel also writes the residual statistics, reduced to
 // one group in PB_MG.
+// First level of the fused coarse end of the cycle: the first level (after
+// the finest) of at most TAIL_CELLS cells.
+constexpr long TAIL_CELLS = 64 * 32;
+template <class T>
+size_t tail_start(const std::vector<ccns_ctx::LevelT<T>> &mg) {
+    for (size_t l = 1; l < mg.size(); ++l)
+        if ((long)mg[l].L.nx * mg[l].L.ny <= TAIL_CELLS && mg.size() - l <= (size_t)MAX_TAIL) return l;
+    return mg.size() - 1;
+}
+
 template <class T>
 T *vcycle(ccns_ctx *c, std::vector<ccns_ctx::LevelT<T>> &mg, size_t l, const T *b) {
     ccns_ctx::LevelT<T> &L = mg[l];
@@ -1514,6 +1644,21 @@ T *vcycle(ccns_ctx *c, std::vector<ccns_ctx::LevelT<T>> &mg, size_t l, const T *
     if (l + 1 == mg.size()) {
         k_mg_coarsest<T><<<1, NT, 0, s>>>(c->ncoarse_act, c->pidx, c->pinv, b, L.x);
         return L.x;
+    }
+    if (l >= 1 && l == tail_start(mg)) {
+        // b is this level's b array (written by the restriction above)
+        TailDesc<T> d{};
+        d.nlev = (int)(mg.size() - l);
+        for (int t = 0; t < d.nlev; ++t) {
+            ccns_ctx::LevelT<T> &M = mg[l + t];
+            d.lv[t] = TailLevel<T>{M.cx, M.cy, M.dinv, M.b, M.x, M.xt, M.L.nx, M.L.ny, M.L.pitch};
+        }
+        d.ncoarse = c->ncoarse_act;
+        d.idx = c->pidx;
+        d.pinv = c->pinv;
+        d.omega = (T)MG_OMEGA;
+        k_mg_tail<T><<<1, TT, 0, s>>>(d);
+        return d.nlev >= 2 ? L.xt : L.x;
     }
     PoisCoefT<T> pc{L.cx, L.cy, L.dinv};
     const int gx = (L.L.nx + TX - 1) / TX, gy = (L.L.ny + MTY - 1) / MTY;
