@@ -10,9 +10,9 @@ solve, the corrector and the pressure update, with the diagnostics.
 
 Prints one JSON line.  `value` is whole-job cell-steps per second (in
 millions) with the state resident in HBM.  `roofline` reports the dominant
-kernel, the predictor's direction+operator kernel (k_pred_dir_lds):
-algorithmic bytes per launch over its mean duration, timed with HIP events on
-the library's stream inside the timed region (every 4th launch).
+kernel, the predictor's CG iteration kernel (k_pred_cg): algorithmic bytes
+per launch over its mean duration, timed with HIP events on the library's
+stream inside the timed region (every 4th launch).
 `cpu_baseline` times the FP64 CPU oracle on a bounded sample of the same
 workload (see its `sample` field).
 """
@@ -37,14 +37,12 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 DEVICE_SRC = os.path.join(ROOT, "paper_2211_10698_amd", "csrc", "ccns_device.hip")
 KERNEL_HDR = os.path.join(ROOT, "paper_2211_10698_amd", "csrc", "ccns_kern.h")
 # Algorithmic bytes per cell of the timed kernels (FP64 = 8 bytes per value).
-# Predictor direction+operator, per cell = one x-face and one y-face: reads
-# r, p_old, M^-1 (2 components each), M^x, M^y, B^xx, B^xy, B^yy, B^yx,
-# 1/W^xx, 1/W^yy and the two diagonal node weights (the cross weight of the
-# symmetric form is their geometric mean, formed in the kernel); writes p and
-# H p (2 each).
-PRED_DIR_BYTES_PER_CELL = 20 * 8.0
-# CG update over the two face components: reads M^-1, x, p, r, H p; writes x, r.
-PRED_UPDATE_BYTES_PER_CELL = 2 * 7 * 8.0
+# Predictor CG iteration (k_pred_cg), per cell = one x-face and one y-face:
+# reads r, H p and p of the previous iteration, x and M^-1 (2 components
+# each), M^x, M^y, B^xx, B^xy, B^yy, B^yx, 1/W^xx, 1/W^yy and the two diagonal
+# node weights (the cross weight of the symmetric form is their geometric
+# mean, formed in the kernel); writes r, x, p and H p (2 each).
+PRED_CG_BYTES_PER_CELL = 28 * 8.0
 # Poisson direction+operator (multigrid path): reads z, p_old, 1/diag, c^x,
 # c^y; writes p, A p.
 POIS_DIR_BYTES_PER_CELL = 7 * 8.0
@@ -58,10 +56,17 @@ WORKLOADS = {
 }
 
 
+# Device helpers whose text a kernel's counter readings also depend on.
+KERNEL_DEPS = {
+    "k_pred_cg": ["ViscCoefT", "PredCoefT", "PredTile", "pred_tile_strains", "pred_tile_K"],
+}
+
+
 def kernel_digest(name):
-    """SHA-1 of a kernel's source text (its definition in the device source
-    plus the shared device header), so that stored counter readings are used
-    only while the kernel they were taken on is unchanged."""
+    """SHA-1 of a kernel's source text (its definition in the device source,
+    the device helpers it calls, and the shared device header), so that
+    stored counter readings are used only while the kernel they were taken
+    on is unchanged."""
     import hashlib
     import re
 
@@ -70,6 +75,12 @@ def kernel_digest(name):
     if m is None:
         return None
     h = hashlib.sha1(m.group(0).encode())
+    for dep in KERNEL_DEPS.get(name, []):
+        d = re.search(r"^(?:template <[^\n]*>\n)?(?:struct " + re.escape(dep) + r"\b|__device__[^\n]*\b"
+                      + re.escape(dep) + r"\().*?^};?$", src, re.S | re.M)
+        if d is None:
+            return None
+        h.update(d.group(0).encode())
     h.update(open(KERNEL_HDR, "rb").read())
     return h.hexdigest()
 
@@ -351,7 +362,7 @@ def main():
                     help="store the HBM traffic of the predictor kernel from rocprofv3 counter runs under DIR")
     args = ap.parse_args()
     if args.summarize_counters:
-        summarize_counters(args.summarize_counters, "k_pred_dir_lds", args.workload)
+        summarize_counters(args.summarize_counters, "k_pred_cg", args.workload)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -421,8 +432,8 @@ def main():
     mean_us = [ms[k] / max(cnt[k], 1) * 1e3 for k in range(4)]
     # the timed kernels run in float in the inner solves of the mixed mode
     esz = 0.5 if mixed else 1.0
-    kname = "k_pred_dir_lds<float>" if mixed else "k_pred_dir_lds"
-    achieved = esz * PRED_DIR_BYTES_PER_CELL * cells / (mean_us[2] * 1e-6) / 1e9
+    kname = "k_pred_cg<float>" if mixed else "k_pred_cg"
+    achieved = esz * PRED_CG_BYTES_PER_CELL * cells / (mean_us[2] * 1e-6) / 1e9
     out = {
         "metric": "Mcell-steps/s at 1e-8 divergence",
         "value": value,
@@ -449,15 +460,14 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None if mixed else stored_traffic("k_pred_dir_lds", case.name),
-            "bytes_per_launch": esz * PRED_DIR_BYTES_PER_CELL * cells,
+            "traffic": None if mixed else stored_traffic("k_pred_cg", case.name),
+            "bytes_per_launch": esz * PRED_CG_BYTES_PER_CELL * cells,
             "mean_launch_us": mean_us[2],
             "timed_launches": cnt[2],
         },
         "kernels": {
             kname: {"us": mean_us[2], "GBs": achieved},
-            "pred_reduce+k_cg_update": {"us": mean_us[3],
-                                        "GBs": esz * PRED_UPDATE_BYTES_PER_CELL * cells / (mean_us[3] * 1e-6) / 1e9},
+            "k_reduce_partials<7>": {"us": mean_us[3]},
             "k_pois_dir_z": {"us": mean_us[0],
                              "GBs": esz * POIS_DIR_BYTES_PER_CELL * cells / (mean_us[0] * 1e-6) / 1e9},
             "pois_update+vcycle": {"us": mean_us[1]},

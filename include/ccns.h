@@ -247,13 +247,13 @@ ccns_status ccns_predict(ccns_ctx *ctx, ccns_solve_info *info);
 ccns_status ccns_correct(ccns_ctx *ctx, ccns_step_info *info);
 
 /* Kernel timing for measurement.  While enabled, every 4th iteration of
- * each CG solve is bracketed with HIP events on the context's stream (the
- * direction+operator kernel and the update kernel separately).  ms[4] and
- * count[4] (may be NULL) receive the accumulated milliseconds and launch
- * counts since the last reset, in the order: Poisson operator kernel,
- * Poisson update kernel, predictor operator kernel, predictor update
- * kernel.  enable: 1 on, 0 off, -1 leave unchanged; 0 and 1 also reset the
- * accumulators (after they are returned). */
+ * each CG solve is bracketed with HIP events on the context's stream.
+ * ms[4] and count[4] (may be NULL) receive the accumulated milliseconds and
+ * launch counts since the last reset, in the order: Poisson
+ * direction+operator kernel, Poisson update with the preconditioner that
+ * follows it, predictor CG iteration kernel, reduction of its partial
+ * products.  enable: 1 on, 0 off, -1 leave unchanged; 0 and 1 also reset
+ * the accumulators (after they are returned). */
 ccns_status ccns_timing(ccns_ctx *ctx, int enable, double *ms, long *count);
 
 /* Diagnostics of the current state (FP64 reductions on the device). */

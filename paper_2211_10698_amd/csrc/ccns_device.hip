@@ -51,6 +51,7 @@ struct CgState {
     double tol2, fnorm2, rnorm2_final;
     int maxit, zero_mean, n_active;
     int done, status, it_final;
+    int stop_it;  // predictor CG: the launch that stopped the solve
     CgSlot slot[2];
 };
 
@@ -206,6 +207,7 @@ __global__ __launch_bounds__(NT) void k_pois_init(Dims d, PoisCoef pc, double *_
         st->done = 0;
         st->status = 0;
         st->it_final = 0;
+        st->stop_it = 0x7fffffff;
     }
     if (MIX) {
         put_partials<7, 1>(v, pout, d.nblk);
@@ -354,11 +356,9 @@ __global__ __launch_bounds__(NT) void k_add_correction(size_t ntot, double *__re
 // Fused cycle kernels.  Tiles cover the real cells, starting at cell (1, 1)
 // so that every 2x2 group of children that forms a coarse cell lies inside
 // one tile (64 = 32 coarse columns, 16 = 8 coarse rows).  One tile per
-// work-group.  Values needed beyond the tile are recomputed on a halo in LDS
-// instead of being exchanged through a second kernel.
+// work-group.  Values needed beyond the tile are recomputed on a one-cell
+// ring (in LDS) instead of being exchanged through a second kernel.
 constexpr int MTY = 16;
-constexpr int MH = 2;  // halo width
-constexpr int MW = TX + 2 * MH, MHt = MTY + 2 * MH;
 
 struct MgTile {
     int c0, r0;  // first real cell of the tile
@@ -371,16 +371,18 @@ __device__ inline MgTile mg_tile(int gx) {
     return t;
 }
 
-// Local Poisson operator on an LDS tile: (A v)(j, i) for tile-local indices.
-struct LdsStencil {
-    const double *cx, *cy, *dinv;
-    int P;
-};
+// Forms of k_mg_down and k_mg_up for a level large enough to be bound by
+// HBM bandwidth rather than by latency (the finest): the first sweep's input
+// is staged in LDS on a two-cell ring, so each value is loaded once per tile
+// instead of being formed at the five points of every stencil.  Same
+// arithmetic per cell as the forms below.
+constexpr int MH = 2;  // halo width of the staged first sweep
+constexpr int MW = TX + 2 * MH, MHt = MTY + 2 * MH;
 
 // Two weighted-Jacobi sweeps from a zero guess, the residual, and its
 // restriction: x2 (written to x2out) and b_coarse.
 template <class T>
-__global__ __launch_bounds__(NT) void k_mg_down(int nx, int ny, int P, int gx, PoisCoefT<T> c,
+__global__ __launch_bounds__(NT) void k_mg_down_staged(int nx, int ny, int P, int gx, PoisCoefT<T> c,
                                                 const T *__restrict__ b, T *__restrict__ x2out,
                                                 int Pc, int nxc, int nyc, const T *__restrict__ dinvc,
                                                 T *__restrict__ bc, T omega) {
@@ -445,7 +447,7 @@ __global__ __launch_bounds__(NT) void k_mg_down(int nx, int ny, int P, int gx, P
 // The coarse correction interpolated onto x2, then two weighted-Jacobi
 // sweeps: z.  With STATS, partials of (b.z, z, b, b.b).
 template <class T, bool STATS>
-__global__ __launch_bounds__(NT) void k_mg_up(int nx, int ny, int P, int gx, PoisCoefT<T> c, const T *__restrict__ b,
+__global__ __launch_bounds__(NT) void k_mg_up_staged(int nx, int ny, int P, int gx, PoisCoefT<T> c, const T *__restrict__ b,
                                               const T *__restrict__ x2, const T *__restrict__ xc, int Pc,
                                               T *__restrict__ z, T omega, double *pout, int nblk) {
     __shared__ T s1[MHt][MW];
@@ -497,6 +499,161 @@ __global__ __launch_bounds__(NT) void k_mg_up(int nx, int ny, int P, int gx, Poi
             if (in) z[k] = zv;
             if (STATS && in) {
                 const double bd = bv, zd = zv;
+                v[0] += bd * zd;
+                v[1] += zd;
+                v[2] += bd;
+                v[3] += bd * bd;
+            }
+        }
+    }
+    if (STATS) put_partials<4>(v, pout, nblk);
+}
+
+// Stencil operands of one cell of the tile phase (the residual of k_mg_down,
+// the last sweep of k_mg_up): 1/diag, right-hand side and the four face
+// weights.  They do not depend on the sweep before, so every thread loads
+// its cells' operands at the start of the kernel and the loads overlap the
+// first phase.
+constexpr int MROWS = MTY / 4;  // tile rows per thread (NT / 64 = 4 row groups)
+template <class T>
+struct MgCellOps {
+    T d[MROWS], b[MROWS], e[MROWS], w[MROWS], n[MROWS], s[MROWS];
+};
+template <class T>
+__device__ inline void mg_load_tile_ops(MgCellOps<T> &o, const PoisCoefT<T> &c, const T *b, int nx, int ny, int P,
+                                        const MgTile &t) {
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+#pragma unroll
+    for (int m = 0; m < MROWS; ++m) {
+        const int j = t.r0 + ty + 4 * m, i = t.c0 + tx;
+        const bool in = (j <= ny) && (i <= nx);
+        const size_t k = in ? (size_t)j * P + i : 0;
+        o.d[m] = c.dinv[k];
+        o.b[m] = b[k];
+        o.e[m] = c.cx[k];
+        o.w[m] = c.cx[in ? k - 1 : 0];
+        o.n[m] = c.cy[k];
+        o.s[m] = c.cy[in ? k - P : 0];
+    }
+}
+
+// Two weighted-Jacobi sweeps from a zero guess, the residual, and its
+// restriction: x2 (written to x2out) and b_coarse.  The first sweep from
+// zero is pointwise (x1 = omega D^-1 b), so it is formed at the five points
+// of the second sweep's stencil instead of being staged: two phases with one
+// barrier between the sweeps and the residual.
+template <class T>
+__global__ __launch_bounds__(NT) void k_mg_down(int nx, int ny, int P, int gx, PoisCoefT<T> c,
+                                                const T *__restrict__ b, T *__restrict__ x2out,
+                                                int Pc, int nxc, int nyc, const T *__restrict__ dinvc,
+                                                T *__restrict__ bc, T omega) {
+    __shared__ T s2[MTY + 2][TX + 2];    // x after two sweeps, on the tile and a one-cell ring
+    __shared__ T sr[MTY][TX];            // residual on the tile
+    const MgTile t = mg_tile(gx);
+    if (t.r0 > ny || t.c0 > nx) return;
+    MgCellOps<T> o;
+    mg_load_tile_ops<T>(o, c, b, nx, ny, P, t);
+    // one coarse cell per thread for the restriction: 32 x 8 coarse cells per tile
+    const int cxl = threadIdx.x & 31, cyl = threadIdx.x >> 5;
+    const int I = (t.c0 + 1) / 2 + cxl, J = (t.r0 + 1) / 2 + cyl;
+    const bool cin = (I <= nxc) && (J <= nyc);
+    const size_t kc = cin ? (size_t)J * Pc + I : 0;
+    const T dcv = dinvc[kc];
+    for (int e = threadIdx.x; e < (MTY + 2) * (TX + 2); e += NT) {
+        const int ly = e / (TX + 2), lx = e - ly * (TX + 2);
+        const int j = t.r0 - 1 + ly, i = t.c0 - 1 + lx;
+        const bool in = (j >= 1) && (j <= ny) && (i >= 1) && (i <= nx);
+        // outside the real cells a stand-in cell whose neighbours exist
+        const size_t k = in ? (size_t)j * P + i : (size_t)P + 1;
+        const T dv = c.dinv[k], bv = b[k];
+        const T de = c.dinv[k + 1], dw = c.dinv[k - 1], dn = c.dinv[k + P], ds = c.dinv[k - P];
+        const T be = b[k + 1], bw = b[k - 1], bn = b[k + P], bs = b[k - P];
+        const T ce = c.cx[k], cw = c.cx[k - 1], cn = c.cy[k], cs = c.cy[k - P];
+        const T xv = dv > (T)0 ? omega * dv * bv : (T)0;
+        const T xe = de > (T)0 ? omega * de * be : (T)0, xw = dw > (T)0 ? omega * dw * bw : (T)0;
+        const T xn = dn > (T)0 ? omega * dn * bn : (T)0, xs = ds > (T)0 ? omega * ds * bs : (T)0;
+        const T Ax = (ce + cw + cn + cs) * xv - ce * xe - cw * xw - cn * xn - cs * xs;
+        s2[ly][lx] = (in && dv > (T)0) ? xv + omega * dv * (bv - Ax) : (T)0;
+    }
+    __syncthreads();
+    {
+        const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+#pragma unroll
+        for (int m = 0; m < MROWS; ++m) {
+            const int ly = ty + 4 * m;
+            const int j = t.r0 + ly, i = t.c0 + tx;
+            const bool in = (j <= ny) && (i <= nx);
+            const int y = ly + 1, x = tx + 1;
+            const T xv = s2[y][x];
+            const T Ax = (o.e[m] + o.w[m] + o.n[m] + o.s[m]) * xv - o.e[m] * s2[y][x + 1] -
+                         o.w[m] * s2[y][x - 1] - o.n[m] * s2[y + 1][x] - o.s[m] * s2[y - 1][x];
+            sr[ly][tx] = (in && o.d[m] > (T)0) ? o.b[m] - Ax : (T)0;
+            if (in) x2out[(size_t)j * P + i] = xv;
+        }
+    }
+    __syncthreads();
+    if (cin) {
+        const T sum = (sr[2 * cyl][2 * cxl] + sr[2 * cyl][2 * cxl + 1]) +
+                      (sr[2 * cyl + 1][2 * cxl] + sr[2 * cyl + 1][2 * cxl + 1]);
+        bc[kc] = dcv > (T)0 ? sum : (T)0;
+    }
+}
+
+// The coarse correction interpolated onto x2, then two weighted-Jacobi
+// sweeps: z.  With STATS, partials of (b.z, z, b, b.b).  The interpolated
+// start value is pointwise, so it is formed at the five points of the first
+// sweep's stencil instead of being staged: one barrier, between the sweeps.
+template <class T, bool STATS>
+__global__ __launch_bounds__(NT) void k_mg_up(int nx, int ny, int P, int gx, PoisCoefT<T> c, const T *__restrict__ b,
+                                              const T *__restrict__ x2, const T *__restrict__ xc, int Pc,
+                                              T *__restrict__ z, T omega, double *pout, int nblk) {
+    __shared__ T s2[MTY + 2][TX + 2];    // x after the first sweep, on the tile and a one-cell ring
+    const MgTile t = mg_tile(gx);
+    double v[4] = {0, 0, 0, 0};
+    const bool live = !(t.r0 > ny || t.c0 > nx);
+    MgCellOps<T> o;
+    if (live) {
+        mg_load_tile_ops<T>(o, c, b, nx, ny, P, t);
+        // start value x2 + interpolated correction at cell (j, i): 0 outside
+        // the real cells and at inactive ones
+        auto start = [&](int j, int i, size_t k) -> T {
+            const bool in = (j >= 1) && (j <= ny) && (i >= 1) && (i <= nx);
+            const size_t kk = in ? k : 0;
+            const size_t kc = in ? (size_t)((j + 1) >> 1) * Pc + ((i + 1) >> 1) : 0;
+            const T dv = c.dinv[kk], xv = x2[kk], ec = xc[kc];
+            return (in && dv > (T)0) ? xv + ec : (T)0;
+        };
+        for (int e = threadIdx.x; e < (MTY + 2) * (TX + 2); e += NT) {
+            const int ly = e / (TX + 2), lx = e - ly * (TX + 2);
+            const int j = t.r0 - 1 + ly, i = t.c0 - 1 + lx;
+            const bool in = (j >= 1) && (j <= ny) && (i >= 1) && (i <= nx);
+            const size_t k = in ? (size_t)j * P + i : (size_t)P + 1;
+            const int jj = in ? j : 1, ii = in ? i : 1;
+            const T dv = c.dinv[k], bv = b[k];
+            const T ce = c.cx[k], cw = c.cx[k - 1], cn = c.cy[k], cs = c.cy[k - P];
+            const T xv = start(jj, ii, k);
+            const T xe = start(jj, ii + 1, k + 1), xw = start(jj, ii - 1, k - 1);
+            const T xn = start(jj + 1, ii, k + P), xs = start(jj - 1, ii, k - P);
+            const T Ax = (ce + cw + cn + cs) * xv - ce * xe - cw * xw - cn * xn - cs * xs;
+            s2[ly][lx] = (in && dv > (T)0) ? xv + omega * dv * (bv - Ax) : (T)0;
+        }
+    }
+    __syncthreads();
+    if (live) {
+        const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+#pragma unroll
+        for (int m = 0; m < MROWS; ++m) {
+            const int ly = ty + 4 * m;
+            const int j = t.r0 + ly, i = t.c0 + tx;
+            const bool in = (j <= ny) && (i <= nx);
+            const int y = ly + 1, x = tx + 1;
+            const T xv = s2[y][x];
+            const T Ax = (o.e[m] + o.w[m] + o.n[m] + o.s[m]) * xv - o.e[m] * s2[y][x + 1] -
+                         o.w[m] * s2[y][x - 1] - o.n[m] * s2[y + 1][x] - o.s[m] * s2[y - 1][x];
+            const T zv = (in && o.d[m] > (T)0) ? xv + omega * o.d[m] * (o.b[m] - Ax) : (T)0;
+            if (in) z[(size_t)j * P + i] = zv;
+            if (STATS && in) {
+                const double bd = o.b[m], zd = zv;
                 v[0] += bd * zd;
                 v[1] += zd;
                 v[2] += bd;
@@ -629,12 +786,33 @@ __global__ __launch_bounds__(TT) void k_mg_tail(TailDesc<T> d) {
 
 // One work-group sums the partials of a producer into a single group's worth
 // (so that consumers read N values instead of N per producer group).
-template <int NS, int NM = 0>
-__global__ __launch_bounds__(NT) void k_reduce_partials(const double *pin, int nin, double *pout) {
+template <int NS, int NM = 0, int BT = NT>
+__global__ __launch_bounds__(BT) void k_reduce_partials(const double *pin, int nin, double *pout) {
     double t[NS + NM];
-    get_totals<NS, NM>(pin, nin, t);
+    get_totals<NS, NM, BT>(pin, nin, t);
     if (threadIdx.x < NS + NM) pout[threadIdx.x] = t[threadIdx.x];
 }
+
+// G work-groups sum the partials of a producer into G sets (group g takes
+// the producers' groups [g nin / G, (g+1) nin / G)), stored slot-major for a
+// consumer that sums G values per slot.  Spreads a large reduction over
+// several compute units instead of one.
+template <int NS>
+__global__ __launch_bounds__(NT) void k_reduce_partials_split(const double *pin, int nin, double *pout) {
+    const int G = gridDim.x, g = blockIdx.x;
+    const int lo = (int)((long)g * nin / G), hi = (int)((long)(g + 1) * nin / G);
+    double a[NS];
+#pragma unroll
+    for (int k = 0; k < NS; ++k) a[k] = 0.0;
+    for (int b = lo + threadIdx.x; b < hi; b += NT) {
+#pragma unroll
+        for (int k = 0; k < NS; ++k) a[k] += pin[(size_t)k * nin + b];
+    }
+    double t[NS];
+    block_reduce<NS, 0>(a, t);
+    if (threadIdx.x < NS) pout[(size_t)threadIdx.x * G + g] = t[threadIdx.x];
+}
+constexpr int PRED_RED = 16;  // groups of the predictor CG's partial reduction
 
 // Coarsest grid: x = A^+ b with the dense pseudo-inverse on the n unknowns.
 template <class T>
@@ -756,11 +934,8 @@ __global__ __launch_bounds__(NT) void k_pred_rhs(Dims d, PredCoef pc, const doub
     });
 }
 
-// Predictor direction and operator, both velocity components of a 64 x 8
-// tile per work-group.  p = M r + beta p_old is staged in LDS on the tile and
-// a one-face halo; the strains of eq:diag / eq:offdiag are formed once per
-// cell and node in LDS; then H p = (rho/tau) V p - mu visc(S) (Sec. 4.3) on
-// the tile.  Partial p.H p per group.
+// Predictor kernels work on tiles of 64 x 8 faces of both velocity
+// components per work-group, staged in LDS with a one-face halo.
 constexpr int HTY = 8;
 
 // LDS of a predictor tile: the staged face field on the tile and a one-face
@@ -827,76 +1002,186 @@ __device__ inline void pred_tile_K(const PredTile<T> &s, const ViscCoefT<T> &c, 
     ky = byy * (s.syy[ly + 1][tx] - s.syy[ly][tx]) + byx * (s.sny[ly + 1][tx + 1] - s.sny[ly + 1][tx]);
 }
 
-// Predictor direction and operator, both velocity components of a 64 x 8
-// tile per work-group.  p = M r + beta p_old is staged in LDS on the tile and
-// a one-face halo; the strains are formed once per cell and node in LDS; then
-// H p = (rho/tau) M p - mu visc(S) (Sec. 4.3) on the tile.  Partial p.H p per
-// group.
+// Predictor CG with one launch per iteration (Jacobi-preconditioned CG on
+// H x = f, Sec. 4.3; M = inverse of H's diagonal).  Launch `it` receives the
+// partial sums of launch it-1, reduced to a few sets: p.q, q.Mr, q.Mq, q.r,
+// q.q, r.Mr and r.r of iteration it-1.  From them, identically in every
+// group:
+//   alpha = r.Mr / p.q,
+//   r'.Mr' = r.Mr - 2 alpha q.Mr + alpha^2 q.Mq   (r' = r - alpha q),
+//   r'.r'  = r.r  - 2 alpha q.r  + alpha^2 q.q,
+//   beta = r'.Mr' / r.Mr, and the stopping test on r'.r'.
+// Every product is summed afresh from the current vectors, so the expansion
+// carries no error from one iteration to the next.  On its tile the launch
+// then applies the update of iteration it-1 (x += alpha p_old, r' = r -
+// alpha q), stages p = M r' + beta p_old on the tile and a one-face halo,
+// forms the strains and H p, and writes r', p, H p with the seven partial
+// products of the next launch.  Launch 0 starts from the residual kernel's
+// statistics (f.f, r.Mr, -, -, r.r) with beta = 0 and no update.  r, p and
+// H p alternate between two buffers (the halo of the old value is read while
+// the new one is written); x is updated in place (tile only).  Launches
+// after the one that stopped return at once (stop_it).
 template <class T, bool GEO>
-__global__ __launch_bounds__(NT) void k_pred_dir_lds(int nx, int ny, int P, int rows, int gx, int gy, size_t n,
-                                                     PredCoefT<T> pc, const T *__restrict__ r,
-                                                     const T *__restrict__ pold, T *__restrict__ pnew,
-                                                     T *__restrict__ q, CgState *st, int first, int par,
-                                                     const double *pin, int nin, double *pout) {
-    if (st->done) return;
-    double fn2, rs, sm, rsum, rr;
-    if (first) {
+__global__ __launch_bounds__(NT) void k_pred_cg(int P, int rows, int gx, int gy, size_t n, PredCoefT<T> pc,
+                                                CgState *st, int it, T *__restrict__ x, const T *__restrict__ rin,
+                                                T *__restrict__ rout, const T *__restrict__ pold,
+                                                T *__restrict__ pnew, const T *__restrict__ qin,
+                                                T *__restrict__ qout, const double *tin, int nin, double *part) {
+    if (st->stop_it < it) return;
+    double fn2, rr, alpha = 0.0, beta = 0.0;
+    bool breakdown = false;
+    if (it == 0) {
         double t[5];
-        get_totals<5>(pin, nin, t);
-        fn2 = t[0]; rs = t[1]; sm = t[2]; rsum = t[3]; rr = t[4];
+        get_totals<5>(tin, nin, t);
+        fn2 = t[0];
+        rr = t[4];
     } else {
-        double t[4];
-        get_totals<4>(pin, nin, t);
-        fn2 = st->fnorm2; rs = t[0]; sm = t[1]; rsum = t[2]; rr = t[3];
+        double t[7];
+        get_totals<7>(tin, nin, t);
+        fn2 = st->fnorm2;
+        breakdown = !(t[0] > 0.0);
+        alpha = breakdown ? 0.0 : t[5] / t[0];
+        const double rz = t[5] - 2.0 * alpha * t[1] + alpha * alpha * t[2];
+        rr = t[6] - 2.0 * alpha * t[3] + alpha * alpha * t[4];
+        beta = breakdown ? 0.0 : rz / t[5];
     }
-    const DirStep ds = cg_decide(st, first, par, fn2, rs, sm, rsum, rr);
-    if (ds.stop) return;
-    const T beta = (T)ds.beta;
-    const T rt = (T)pc.rt, mu = (T)pc.mu;
-    __shared__ PredTile<T> s;
+    const bool conv = !breakdown && !(rr > st->tol2 * fn2);
+    const bool stop = breakdown || conv || it >= st->maxit;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        if (it == 0) st->fnorm2 = fn2;
+        if (stop) {
+            st->done = 1;
+            st->status = conv ? 0 : (breakdown ? CCNS_EBREAKDOWN : CCNS_ENOTCONV);
+            st->it_final = breakdown ? it - 1 : it;
+            st->rnorm2_final = rr;
+            st->stop_it = it;
+        }
+    }
     const int L = logical_group(((gridDim.x + 7) / 8) * 8);
     const bool live = L < gx * gy;
     const int c0 = (L % gx) * TX, r0 = (L / gx) * HTY;
-    double v[1] = {0.0};
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    const T a = (T)alpha, b = (T)beta;
+    if (stop) {
+        // the last update, x += alpha p_old, on the tile
+        if (live && it >= 1 && !breakdown) {
+            for (int ly = ty; ly < HTY; ly += 4) {
+                const int j = r0 + ly, i = c0 + tx;
+                if (j >= rows) break;
+                const size_t k = (size_t)j * P + i;
+                const T ox = pold[k], oy = pold[n + k];
+                x[k] = x[k] + a * ox;
+                x[n + k] = x[n + k] + a * oy;
+            }
+        }
+        return;
+    }
+    __shared__ PredTile<T> s;
+    double v[7] = {0, 0, 0, 0, 0, 0, 0};
+    // r' and M^-1 of this thread's tile faces stay in registers for the
+    // products of the last phase (rows ty and ty + 4 of the tile)
+    constexpr int RW = HTY / 4;
+    T rxs[RW], rys[RW], hxs[RW], hys[RW];
     if (live) {
-        // p on the tile and a one-face halo (rows r0-1 .. r0+HTY, cols c0-1 .. c0+TX)
-        for (int e = threadIdx.x; e < (HTY + 2) * (TX + 2); e += NT) {
-            const int ly = e / (TX + 2), lx = e - ly * (TX + 2);
+        // the tile: r', x += alpha p_old, p = M r' + beta p_old
+#pragma unroll
+        for (int m = 0; m < RW; ++m) {
+            const int ly = ty + 4 * m;
+            const int j = r0 + ly, i = c0 + tx;
+            const bool in = j < rows;
+            const size_t k = in ? (size_t)j * P + i : 0;
+            const T hx = pc.hdx[k], hy = pc.hdy[k];
+            T rx = rin[k], ry = rin[n + k];
+            T px = hx * rx, py = hy * ry;
+            if (it >= 1) {
+                const T qx = qin[k], qy = qin[n + k], ox = pold[k], oy = pold[n + k];
+                rx = rx - a * qx;
+                ry = ry - a * qy;
+                px = hx * rx + b * ox;
+                py = hy * ry + b * oy;
+                if (in) {
+                    x[k] = x[k] + a * ox;
+                    x[n + k] = x[n + k] + a * oy;
+                }
+            }
+            rxs[m] = rx;
+            rys[m] = ry;
+            hxs[m] = hx;
+            hys[m] = hy;
+            s.spx[ly + 1][tx + 1] = in ? px : (T)0;
+            s.spy[ly + 1][tx + 1] = in ? py : (T)0;
+        }
+        // the one-face halo: rows r0-1 and r0+HTY (TX+2 faces each), columns
+        // c0-1 and c0+TX (HTY faces each)
+        for (int e = threadIdx.x; e < 2 * (TX + 2) + 2 * HTY; e += NT) {
+            int ly, lx;
+            if (e < 2 * (TX + 2)) {
+                ly = e < TX + 2 ? 0 : HTY + 1;
+                lx = e < TX + 2 ? e : e - (TX + 2);
+            } else {
+                const int f = e - 2 * (TX + 2);
+                ly = 1 + (f >> 1);
+                lx = (f & 1) ? TX + 1 : 0;
+            }
             const int j = r0 - 1 + ly, i = c0 - 1 + lx;
             const bool in = (j >= 0) && (j < rows) && (i >= 0) && (i < P);
             const size_t k = in ? (size_t)j * P + i : 0;
-            const T hx = pc.hdx[k], hy = pc.hdy[k], rx = r[k], ry = r[n + k], ox = pold[k], oy = pold[n + k];
-            s.spx[ly][lx] = in ? hx * rx + beta * ox : (T)0;
-            s.spy[ly][lx] = in ? hy * ry + beta * oy : (T)0;
+            const T hx = pc.hdx[k], hy = pc.hdy[k];
+            T rx = rin[k], ry = rin[n + k];
+            T px = hx * rx, py = hy * ry;
+            if (it >= 1) {
+                const T qx = qin[k], qy = qin[n + k], ox = pold[k], oy = pold[n + k];
+                rx = rx - a * qx;
+                ry = ry - a * qy;
+                px = hx * rx + b * ox;
+                py = hy * ry + b * oy;
+            }
+            s.spx[ly][lx] = in ? px : (T)0;
+            s.spy[ly][lx] = in ? py : (T)0;
         }
     }
     __syncthreads();
     if (live) pred_tile_strains<T, GEO>(s, pc.vc, P, rows, c0, r0);
     __syncthreads();
     if (live) {
-        const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-        for (int ly = ty; ly < HTY; ly += 4) {
+        const T rt = (T)pc.rt, mu = (T)pc.mu;
+#pragma unroll
+        for (int m = 0; m < RW; ++m) {
+            const int ly = ty + 4 * m;
             const int j = r0 + ly, i = c0 + tx;
             if (j >= rows) break;
             const size_t k = (size_t)j * P + i;
             const T vu = pc.vu[k], vv = pc.vv[k];
+            const T rx = rxs[m], ry = rys[m], hx = hxs[m], hy = hys[m];
             const T px = s.spx[ly + 1][tx + 1], py = s.spy[ly + 1][tx + 1];
             T kx, ky;
             pred_tile_K<T>(s, pc.vc, k, ly, tx, kx, ky);
             const T qx = vu > (T)0 ? rt * vu * px - mu * kx : (T)0;
             const T qy = vv > (T)0 ? rt * vv * py - mu * ky : (T)0;
             const T pxo = vu > (T)0 ? px : (T)0, pyo = vv > (T)0 ? py : (T)0;
+            if (it >= 1) {
+                rout[k] = rx;
+                rout[n + k] = ry;
+            }
             pnew[k] = pxo;
             pnew[n + k] = pyo;
-            q[k] = qx;
-            q[n + k] = qy;
-            v[0] += (double)pxo * (double)qx + (double)pyo * (double)qy;
+            qout[k] = qx;
+            qout[n + k] = qy;
+            const T zrx = hx * rx, zry = hy * ry, zqx = hx * qx, zqy = hy * qy;
+            const double dqx = qx, dqy = qy, drx = rx, dry = ry;
+            v[0] += (double)pxo * dqx + (double)pyo * dqy;
+            v[1] += dqx * (double)zrx + dqy * (double)zry;
+            v[2] += dqx * (double)zqx + dqy * (double)zqy;
+            v[3] += dqx * drx + dqy * dry;
+            v[4] += dqx * dqx + dqy * dqy;
+            v[5] += drx * (double)zrx + dry * (double)zry;
+            v[6] += drx * drx + dry * dry;
         }
     }
-    put_partials<1>(v, pout, gridDim.x);
+    put_partials<7>(v, part, gridDim.x);
 }
 
-// Predictor residual r = rhs - H x in FP64 on the tiles of k_pred_dir_lds
+// Predictor residual r = rhs - H x in FP64 on the tiles of k_pred_cg
 // (x staged in LDS, masked to the unknowns), with the statistics of r.
 //  MIX = false: r is stored; partials (f.f, r.z, z, r, r.r), z = M^-1 r.
 //  MIX = true (precision 1): r is rounded to float into r32 (right-hand side
@@ -976,6 +1261,7 @@ __global__ __launch_bounds__(NT) void k_pred_resid(int P, int rows, int gx, int 
         st->done = 0;
         st->status = 0;
         st->it_final = 0;
+        st->stop_it = 0x7fffffff;
     }
     if (MIX) {
         put_partials<7>(v, pout, gridDim.x);
@@ -1155,6 +1441,8 @@ enum Arr {
     A_PP0X, A_PP0Y,  // predictor p (ping)
     A_PP1X, A_PP1Y,  // predictor p (pong)
     A_PQX, A_PQY,    // predictor q
+    A_PR1X, A_PR1Y,  // predictor r (pong)
+    A_PQ1X, A_PQ1Y,  // predictor q (pong)
     A_RHSX, A_RHSY,  // predictor right-hand side
     A_B, A_R, A_P0, A_P1, A_Q,  // Poisson
     A_Z, A_ZT,                  // multigrid output and its ping-pong partner
@@ -1189,6 +1477,7 @@ enum Arr32 {
     G_PRX, G_PRY,    // predictor inner r (pair)
     G_PXX, G_PXY,    // predictor inner x = correction (pair)
     G_PP0X, G_PP0Y, G_PP1X, G_PP1Y, G_PQX, G_PQY,
+    G_PR1X, G_PR1Y, G_PQ1X, G_PQ1Y,  // pong partners of r and q
     G_COUNT
 };
 
@@ -1272,7 +1561,7 @@ struct ccns_ctx {
     int conv_valid;
     int n_active;
     int last_pois_it, last_pred_it;
-    int pbuf_pred, pbuf_pois;
+    int pbuf_pois;
     int init_nblk;      // groups of the last init kernel (its partials feed the first direction)
     // multigrid hierarchy (level 0 shares the Poisson arrays)
     template <class T>
@@ -1291,7 +1580,7 @@ struct ccns_ctx {
     int timing;
     std::vector<hipEvent_t> evpool;
     size_t evused;
-    double t_ms[4];    // Poisson direction, Poisson update, predictor direction, predictor update
+    double t_ms[4];    // Poisson direction, Poisson update (+ cycle), predictor CG iteration, its reduction
     long t_count[4];
     std::string err;
 };
@@ -1665,12 +1954,19 @@ T *vcycle(ccns_ctx *c, std::vector<ccns_ctx::LevelT<T>> &mg, size_t l, const T *
     const int nb = ((gx * gy + 7) / 8) * 8;
     ccns_ctx::LevelT<T> &C = mg[l + 1];
     const T om = (T)MG_OMEGA;
-    k_mg_down<T><<<nb, NT, 0, s>>>(L.L.nx, L.L.ny, L.L.pitch, gx, pc, b, L.x, C.L.pitch, C.L.nx, C.L.ny, C.dinv,
-                                   C.b, om);
+    // the finest level in the staged forms (measured: faster on the way down
+    // in FP64 and on the way up in both precisions; the FP32 way down is
+    // faster in the latency form at every level)
+    if (l == 0 && sizeof(T) == 8)
+        k_mg_down_staged<T><<<nb, NT, 0, s>>>(L.L.nx, L.L.ny, L.L.pitch, gx, pc, b, L.x, C.L.pitch, C.L.nx, C.L.ny,
+                                              C.dinv, C.b, om);
+    else
+        k_mg_down<T><<<nb, NT, 0, s>>>(L.L.nx, L.L.ny, L.L.pitch, gx, pc, b, L.x, C.L.pitch, C.L.nx, C.L.ny,
+                                       C.dinv, C.b, om);
     const T *xc = vcycle<T>(c, mg, l + 1, C.b);
     if (l == 0) {
-        k_mg_up<T, true><<<nb, NT, 0, s>>>(L.L.nx, L.L.ny, L.L.pitch, gx, pc, b, L.x, xc, C.L.pitch, L.xt, om,
-                                           c->part[PB_UPD], nb);
+        k_mg_up_staged<T, true><<<nb, NT, 0, s>>>(L.L.nx, L.L.ny, L.L.pitch, gx, pc, b, L.x, xc, C.L.pitch, L.xt,
+                                                  om, c->part[PB_UPD], nb);
         k_reduce_partials<4><<<1, NT, 0, s>>>(c->part[PB_UPD], nb, c->part[PB_MG]);
     } else {
         k_mg_up<T, false><<<nb, NT, 0, s>>>(L.L.nx, L.L.ny, L.L.pitch, gx, pc, b, L.x, xc, C.L.pitch, L.xt, om,
@@ -1832,26 +2128,55 @@ void predictor_rhs(ccns_ctx *c) {
     c->conv_valid = 1;
 }
 
-// Jacobi-PCG on H x = f with storage type T; the init kernel's partials are
-// in PB_INIT.
+// Jacobi-PCG on H x = f with storage type T, one k_pred_cg launch and one
+// reduction of its partials (to PRED_RED sets) per iteration; the residual
+// kernel's statistics are in PB_INIT (one group), its residual in r[0].
+// Launches are issued in chunks between looks at the device's stopping flag.
 template <class T>
-ccns_status pred_cg(ccns_ctx *c, PredCoefT<T> pc, CgState *st, T *x, T *r, T *p0, T *p1, T *q, int &last_it,
-                    ccns_solve_info *info) {
-    c->init_nblk = 1;  // the residual kernel's statistics, reduced to one group
-    T *pb[2] = {p0, p1};
+ccns_status pred_cg(ccns_ctx *c, PredCoefT<T> pc, CgState *st, T *x, T *const r[2], T *const p[2],
+                    T *const q[2], int &last_it, ccns_solve_info *info) {
+    c->init_nblk = 1;
     const Layout &L = c->w.L;
     const int gx = L.pitch / TX, gy = (L.rows + HTY - 1) / HTY;
     const int nb = ((gx * gy + 7) / 8) * 8;
-    auto dir = [&](int first, int par, T *pold, T *pnew, const double *pin, int nin, double *pout) {
-        if (c->prm.visc_form == 0)
-            k_pred_dir_lds<T, true><<<nb, NT, 0, c->stream>>>(L.nx, L.ny, L.pitch, L.rows, gx, gy, L.n, pc, r, pold,
-                                                              pnew, q, st, first, par, pin, nin, pout);
-        else
-            k_pred_dir_lds<T, false><<<nb, NT, 0, c->stream>>>(L.nx, L.ny, L.pitch, L.rows, gx, gy, L.n, pc, r, pold,
-                                                               pnew, q, st, first, par, pin, nin, pout);
-        return nb;
-    };
-    return cg_loop<T>(c, st, x, r, pb, c->pbuf_pred, q, pc.hdx, 2 * c->w.L.n, last_it, dir, [] {}, info, 2);
+    const bool geo = c->prm.visc_form == 0;
+    int chunk = std::max(4, last_it + 1);
+    int it = 0;
+    for (;;) {
+        for (int u = 0; u < chunk; ++u, ++it) {
+            const int b = it & 1, a = b ^ 1;
+            const T *rin = it == 0 ? r[0] : r[a];
+            const double *tin = it == 0 ? c->part[PB_INIT] : c->part[PB_UPD];
+            const int nin = it == 0 ? c->init_nblk : PRED_RED;
+            const bool tm = c->timing && (it % 4 == 0) && it < last_it;
+            if (tm) (void)hipEventRecord(next_event(c), c->stream);
+            if (geo)
+                k_pred_cg<T, true><<<nb, NT, 0, c->stream>>>(L.pitch, L.rows, gx, gy, L.n, pc, st, it, x, rin, r[b],
+                                                             p[a], p[b], q[a], q[b], tin, nin, c->part[PB_DIR]);
+            else
+                k_pred_cg<T, false><<<nb, NT, 0, c->stream>>>(L.pitch, L.rows, gx, gy, L.n, pc, st, it, x, rin,
+                                                              r[b], p[a], p[b], q[a], q[b], tin, nin,
+                                                              c->part[PB_DIR]);
+            if (tm) (void)hipEventRecord(next_event(c), c->stream);
+            k_reduce_partials_split<7><<<PRED_RED, NT, 0, c->stream>>>(c->part[PB_DIR], nb, c->part[PB_UPD]);
+            if (tm) (void)hipEventRecord(next_event(c), c->stream);
+        }
+        HIPCHK(c, hipGetLastError());
+        HIPCHK(c, hipMemcpyAsync(c->h_st, st, sizeof(CgState), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        if (c->timing) harvest_events(c, 2);
+        if (c->h_st->done) break;
+        chunk = 8;
+    }
+    last_it = c->h_st->it_final;
+    if (info) {
+        info->iterations = c->h_st->it_final;
+        info->outer = 1;
+        info->rel_residual = c->h_st->fnorm2 > 0 ? std::sqrt(std::max(c->h_st->rnorm2_final, 0.0) / c->h_st->fnorm2)
+                                                 : 0.0;
+        info->status = c->h_st->status;
+    }
+    return (ccns_status)c->h_st->status;
 }
 
 // r = rhs - H x in FP64 (tiled residual kernel), its statistics reduced to
@@ -1882,8 +2207,9 @@ ccns_status predict_dev(ccns_ctx *c, ccns_solve_info *info) {
     predictor_rhs(c);
     pred_residual<false>(c, c->st_pred);
     PredCoefT<double> pd = pred_coef_t(c);
-    return pred_cg<double>(c, pd, c->st_pred, c->a[A_USX], c->a[A_PRX], c->a[A_PP0X], c->a[A_PP1X], c->a[A_PQX],
-                           c->last_pred_it, info);
+    double *r[2] = {c->a[A_PRX], c->a[A_PR1X]}, *p[2] = {c->a[A_PP0X], c->a[A_PP1X]},
+           *q[2] = {c->a[A_PQX], c->a[A_PQ1X]};
+    return pred_cg<double>(c, pd, c->st_pred, c->a[A_USX], r, p, q, c->last_pred_it, info);
 }
 
 // Predictor in precision 1: iterative refinement as for the pressure, with
@@ -1913,8 +2239,9 @@ ccns_status predict_mixed(ccns_ctx *c, ccns_solve_info *info) {
         const double it = inner_tol(tol * std::sqrt(fn2 / rn2));
         k_set_tol<<<1, 1, 0, c->stream>>>(c->st_pred_in, it * it);
         ccns_solve_info si{};
-        pred_cg<float>(c, pf, c->st_pred_in, c->f[G_PXX], c->f[G_PRX], c->f[G_PP0X], c->f[G_PP1X], c->f[G_PQX],
-                       c->last_pred_in, &si);
+        float *r[2] = {c->f[G_PRX], c->f[G_PR1X]}, *p[2] = {c->f[G_PP0X], c->f[G_PP1X]},
+              *q[2] = {c->f[G_PQX], c->f[G_PQ1X]};
+        pred_cg<float>(c, pf, c->st_pred_in, c->f[G_PXX], r, p, q, c->last_pred_in, &si);
         if (si.status == CCNS_EDEVICE) return CCNS_EDEVICE;
         inner_its += si.iterations;
         ++sweeps;
@@ -2021,7 +2348,7 @@ ccns_status ccns_ctx_create(const ccns_grid *grid, const ccns_params *params, co
     c->conv_valid = 0;
     c->last_pois_it = c->last_pred_it = 16;
     c->last_pois_in = c->last_pred_in = 8;
-    c->pbuf_pred = c->pbuf_pois = 0;
+    c->pbuf_pois = 0;
     c->timing = 0;
     c->evused = 0;
     for (int k = 0; k < 4; ++k) { c->t_ms[k] = 0.0; c->t_count[k] = 0; }

@@ -118,7 +118,23 @@ __device__ inline void get_totals(const double *part, int nblk, double (&tot)[NS
     double a[NS + NM];
 #pragma unroll
     for (int k = 0; k < NS + NM; ++k) a[k] = (k < NS) ? 0.0 : -INFINITY;
-    for (int b = threadIdx.x; b < nblk; b += BT) {
+    // U groups' values in flight per thread (groups of 1024 threads have no
+    // registers to spare), then a remainder; the order of the sums is fixed
+    // by (nblk, BT)
+    constexpr int U = BT >= 1024 ? 1 : 4;
+    int b = threadIdx.x;
+    for (; b + (U - 1) * BT < nblk; b += U * BT) {
+        double x[U][NS + NM];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int k = 0; k < NS + NM; ++k) x[u][k] = part[(size_t)k * nblk + b + u * BT];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int k = 0; k < NS + NM; ++k) a[k] = (k < NS) ? a[k] + x[u][k] : fmax(a[k], x[u][k]);
+    }
+    for (; b < nblk; b += BT) {
 #pragma unroll
         for (int k = 0; k < NS + NM; ++k) {
             const double x = part[(size_t)k * nblk + b];
