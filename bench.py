@@ -12,7 +12,7 @@ Prints one JSON line.  `value` is whole-job cell-steps per second (in
 millions) with the state resident in HBM.  `roofline` reports the dominant
 kernel, the predictor's CG iteration kernel (k_pred_cg): algorithmic bytes
 per launch over its mean duration, timed with HIP events on the library's
-stream inside the timed region (every 4th launch).
+stream inside the timed region (iterations 4, 12, 20, ... of each solve).
 `cpu_baseline` times the FP64 CPU oracle on a bounded sample of the same
 workload (see its `sample` field).
 """
@@ -46,6 +46,8 @@ PRED_CG_BYTES_PER_CELL = 28 * 8.0
 # Poisson direction+operator (multigrid path): reads z, p_old, 1/diag, c^x,
 # c^y; writes p, A p.
 POIS_DIR_BYTES_PER_CELL = 7 * 8.0
+# Poisson CG update: reads 1/diag, x, p, r, A p; writes x, r.
+POIS_UPDATE_BYTES_PER_CELL = 7 * 8.0
 
 WORKLOADS = {
     "channel_cylinder_2048x1024": W.channel_cylinder_2048,
@@ -470,7 +472,8 @@ def main():
             "k_reduce_partials<7>": {"us": mean_us[3]},
             "k_pois_dir_z": {"us": mean_us[0],
                              "GBs": esz * POIS_DIR_BYTES_PER_CELL * cells / (mean_us[0] * 1e-6) / 1e9},
-            "pois_update+vcycle": {"us": mean_us[1]},
+            "k_cg_update (Poisson)": {"us": mean_us[1],
+                                      "GBs": esz * POIS_UPDATE_BYTES_PER_CELL * cells / (mean_us[1] * 1e-6) / 1e9},
         },
         "cpu_baseline": None,
     }

@@ -246,8 +246,9 @@ ccns_status ccns_step(ccns_ctx *ctx, int nsteps, ccns_step_info *info);
 ccns_status ccns_predict(ccns_ctx *ctx, ccns_solve_info *info);
 ccns_status ccns_correct(ccns_ctx *ctx, ccns_step_info *info);
 
-/* Kernel timing for measurement.  While enabled, every 4th iteration of
- * each CG solve is bracketed with HIP events on the context's stream.
+/* Kernel timing for measurement.  While enabled, iterations 4, 12, 20, ...
+ * of each CG solve (never the first, whose kernels do less) are bracketed
+ * with HIP events on the context's stream.
  * ms[4] and count[4] (may be NULL) receive the accumulated milliseconds and
  * launch counts since the last reset, in the order: Poisson
  * direction+operator kernel, Poisson update with the preconditioner that

@@ -17,6 +17,7 @@
 //    scalars (alpha, beta, convergence) are formed on the device; the host
 //    only reads a done flag every few iterations.
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include <algorithm>
 #include <cmath>
@@ -99,15 +100,18 @@ __device__ inline DirStep cg_decide(CgState *st, int first, int par, double fnor
     o.mean = m;
     o.rz = rs - m * r;
     const int it = first ? 0 : st->slot[par ^ 1].it + 1;
-    const bool conv = !(rr > st->tol2 * fnorm2);
+    // a residual that is not finite never counts as converged; r.z of an
+    // unconverged residual must be positive (the preconditioner is SPD)
+    const bool conv = rr <= st->tol2 * fnorm2;
+    const bool brk = !conv && !(o.rz > 0.0 && o.rz < INFINITY);
     const bool lim = it >= st->maxit;
-    o.stop = conv || lim;
+    o.stop = conv || lim || brk;
     o.beta = first ? 0.0 : o.rz / st->slot[par ^ 1].rz;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         if (first) st->fnorm2 = fnorm2;
         if (o.stop) {
             st->done = 1;
-            st->status = conv ? 0 : CCNS_ENOTCONV;
+            st->status = conv ? 0 : (brk ? CCNS_EBREAKDOWN : CCNS_ENOTCONV);
             st->it_final = it;
             st->rnorm2_final = rr;
         } else {
@@ -252,7 +256,7 @@ __global__ __launch_bounds__(NT) void k_pois_dir(Dims d, PoisCoefT<T> pc, const 
             const int j = r0 - 1 + ly, i = c0 - 1 + lx;
             const bool in = (j >= 0) && (j < d.rows) && (i >= 0) && (i < P);
             const size_t k = in ? (size_t)j * P + i : 0;
-            const T di = pc.dinv[k], rv = r[k], po = pold[k];
+            const T di = pc.dinv[k], rv = r[k], po = first ? (T)0 : pold[k];
             sp[ly][lx] = (in && di > (T)0) ? (di * rv - m) + beta * po : (T)0;
         }
         __syncthreads();
@@ -385,7 +389,8 @@ template <class T>
 __global__ __launch_bounds__(NT) void k_mg_down_staged(int nx, int ny, int P, int gx, PoisCoefT<T> c,
                                                 const T *__restrict__ b, T *__restrict__ x2out,
                                                 int Pc, int nxc, int nyc, const T *__restrict__ dinvc,
-                                                T *__restrict__ bc, T omega) {
+                                                T *__restrict__ bc, T omega, const int *done) {
+    if (*done) return;
     __shared__ T s1[MHt][MW];            // first sweep on the 2-ring region
     __shared__ T s2[MTY + 2][TX + 2];    // second sweep on the 1-ring region
     __shared__ T sr[MTY][TX];            // residual on the tile
@@ -449,7 +454,8 @@ __global__ __launch_bounds__(NT) void k_mg_down_staged(int nx, int ny, int P, in
 template <class T, bool STATS>
 __global__ __launch_bounds__(NT) void k_mg_up_staged(int nx, int ny, int P, int gx, PoisCoefT<T> c, const T *__restrict__ b,
                                               const T *__restrict__ x2, const T *__restrict__ xc, int Pc,
-                                              T *__restrict__ z, T omega, double *pout, int nblk) {
+                                              T *__restrict__ z, T omega, double *pout, int nblk, const int *done) {
+    if (*done) return;
     __shared__ T s1[MHt][MW];
     __shared__ T s2[MTY + 2][TX + 2];
     const MgTile t = mg_tile(gx);
@@ -546,7 +552,8 @@ template <class T>
 __global__ __launch_bounds__(NT) void k_mg_down(int nx, int ny, int P, int gx, PoisCoefT<T> c,
                                                 const T *__restrict__ b, T *__restrict__ x2out,
                                                 int Pc, int nxc, int nyc, const T *__restrict__ dinvc,
-                                                T *__restrict__ bc, T omega) {
+                                                T *__restrict__ bc, T omega, const int *done) {
+    if (*done) return;
     __shared__ T s2[MTY + 2][TX + 2];    // x after two sweeps, on the tile and a one-cell ring
     __shared__ T sr[MTY][TX];            // residual on the tile
     const MgTile t = mg_tile(gx);
@@ -606,7 +613,8 @@ __global__ __launch_bounds__(NT) void k_mg_down(int nx, int ny, int P, int gx, P
 template <class T, bool STATS>
 __global__ __launch_bounds__(NT) void k_mg_up(int nx, int ny, int P, int gx, PoisCoefT<T> c, const T *__restrict__ b,
                                               const T *__restrict__ x2, const T *__restrict__ xc, int Pc,
-                                              T *__restrict__ z, T omega, double *pout, int nblk) {
+                                              T *__restrict__ z, T omega, double *pout, int nblk, const int *done) {
+    if (*done) return;
     __shared__ T s2[MTY + 2][TX + 2];    // x after the first sweep, on the tile and a one-cell ring
     const MgTile t = mg_tile(gx);
     double v[4] = {0, 0, 0, 0};
@@ -688,6 +696,7 @@ struct TailDesc {
     const int *idx;
     const double *pinv;
     T omega;
+    const int *done;     // the solve's done flag: nothing to do once set
 };
 
 template <class T>
@@ -698,6 +707,7 @@ __device__ inline T tail_Ax(const TailLevel<T> &L, const T *v, size_t k) {
 
 template <class T>
 __global__ __launch_bounds__(TT) void k_mg_tail(TailDesc<T> d) {
+    if (*d.done) return;
     const T om = d.omega;
     // down: two sweeps from zero, the residual restricted to the next level
     for (int l = 0; l + 1 < d.nlev; ++l) {
@@ -818,7 +828,8 @@ constexpr int PRED_RED = 16;  // groups of the predictor CG's partial reduction
 template <class T>
 __global__ __launch_bounds__(NT) void k_mg_coarsest(int n, const int *__restrict__ idx,
                                                     const double *__restrict__ pinv, const T *__restrict__ b,
-                                                    T *__restrict__ x) {
+                                                    T *__restrict__ x, const int *done) {
+    if (*done) return;
     __shared__ double sb[1024];
     for (int i = threadIdx.x; i < n; i += NT) sb[i] = b[idx[i]];
     __syncthreads();
@@ -867,7 +878,7 @@ __global__ __launch_bounds__(NT) void k_pois_dir_z(Dims d, PoisCoefT<T> pc, cons
             const int j = r0 - 1 + ly, i = c0 - 1 + lx;
             const bool in = (j >= 0) && (j < d.rows) && (i >= 0) && (i < P);
             const size_t k = in ? (size_t)j * P + i : 0;
-            const T di = pc.dinv[k], zv = z[k], po = pold[k];
+            const T di = pc.dinv[k], zv = z[k], po = first ? (T)0 : pold[k];
             sp[ly][lx] = (in && di > (T)0) ? (zv - m) + beta * po : (T)0;
         }
         __syncthreads();
@@ -1039,20 +1050,23 @@ __global__ __launch_bounds__(NT) void k_pred_cg(int P, int rows, int gx, int gy,
         double t[7];
         get_totals<7>(tin, nin, t);
         fn2 = st->fnorm2;
-        breakdown = !(t[0] > 0.0);
+        breakdown = !(t[0] > 0.0 && t[0] < INFINITY && t[5] > 0.0 && t[5] < INFINITY);
         alpha = breakdown ? 0.0 : t[5] / t[0];
         const double rz = t[5] - 2.0 * alpha * t[1] + alpha * alpha * t[2];
         rr = t[6] - 2.0 * alpha * t[3] + alpha * alpha * t[4];
         beta = breakdown ? 0.0 : rz / t[5];
     }
-    const bool conv = !breakdown && !(rr > st->tol2 * fn2);
+    // an unconverged residual or a beta that is not finite (or a negative
+    // beta) ends the solve as a breakdown; a NaN never counts as converged
+    const bool conv = !breakdown && rr <= st->tol2 * fn2;
+    if (!conv && !(rr < INFINITY && beta >= 0.0 && beta < INFINITY)) breakdown = true;
     const bool stop = breakdown || conv || it >= st->maxit;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         if (it == 0) st->fnorm2 = fn2;
         if (stop) {
             st->done = 1;
             st->status = conv ? 0 : (breakdown ? CCNS_EBREAKDOWN : CCNS_ENOTCONV);
-            st->it_final = breakdown ? it - 1 : it;
+            st->it_final = breakdown ? max(it - 1, 0) : it;
             st->rnorm2_final = rr;
             st->stop_it = it;
         }
@@ -1576,11 +1590,12 @@ struct ccns_ctx {
     double *pinv;
     int *pidx;
     int ncoarse_act;
-    // optional kernel timing: events around every 4th CG iteration
+    // optional kernel timing: start/stop events attached to sampled launches
     int timing;
     std::vector<hipEvent_t> evpool;
     size_t evused;
-    double t_ms[4];    // Poisson direction, Poisson update (+ cycle), predictor CG iteration, its reduction
+    std::vector<std::pair<size_t, int>> evlog;  // (first event of the pair, timing slot)
+    double t_ms[4];    // Poisson direction, Poisson update, predictor CG iteration, its reduction
     long t_count[4];
     std::string err;
 };
@@ -1695,26 +1710,44 @@ hipEvent_t next_event(ccns_ctx *c) {
     return c->evpool[c->evused++];
 }
 
-// Adds the durations of the sampled launches recorded since the last call.
-void harvest_events(ccns_ctx *c, int kid) {
-    for (size_t k = 0; k + 3 <= c->evused; k += 3) {
-        float a = 0.f, b = 0.f;
-        if (hipEventElapsedTime(&a, c->evpool[k], c->evpool[k + 1]) == hipSuccess &&
-            hipEventElapsedTime(&b, c->evpool[k + 1], c->evpool[k + 2]) == hipSuccess) {
-            c->t_ms[kid] += a;
-            c->t_ms[kid + 1] += b;
-            c->t_count[kid] += 1;
-            c->t_count[kid + 1] += 1;
+// Launches a kernel on the context's stream.  When tm, HIP start and stop
+// events are attached to the dispatch itself (hipExtLaunchKernelGGL), so the
+// sampled time is the kernel's own duration without the gap of a separate
+// event packet, and the pair is logged for timing slot kid.
+template <typename... KArgs, typename... Args>
+void launch(ccns_ctx *c, bool tm, int kid, void (*kernel)(KArgs...), dim3 grid, dim3 block, Args... args) {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    const size_t i0 = c->evused;
+    if (tm) {
+        e0 = next_event(c);
+        e1 = e0 ? next_event(c) : nullptr;
+    }
+    if (e0 && e1) {
+        c->evlog.push_back({i0, kid});
+        hipExtLaunchKernelGGL(kernel, grid, block, 0, c->stream, e0, e1, 0, args...);
+    } else {
+        kernel<<<grid, block, 0, c->stream>>>(args...);
+    }
+}
+
+// Adds the durations of the sampled launches logged since the last call.
+void harvest_events(ccns_ctx *c) {
+    for (const auto &e : c->evlog) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, c->evpool[e.first], c->evpool[e.first + 1]) == hipSuccess) {
+            c->t_ms[e.second] += ms;
+            c->t_count[e.second] += 1;
         }
     }
+    c->evlog.clear();
     c->evused = 0;
 }
 
 // Runs CG iterations (after the caller launched the init kernel, whose
 // partials are in PB_INIT) until the device flags the end of the solve.
-// dir(first, par, pold, pnew, pin, nin, pout) launches the direction+operator
-// kernel and returns the number of partials it leaves in PB_DIR; finish()
-// runs after it.  T is the storage type of the vectors.
+// dir(first, par, pold, pnew, pin, nin, pout, tm) launches the
+// direction+operator kernel (timed when tm) and returns the number of
+// partials it leaves in PB_DIR; finish() runs after it.  T is the storage type of the vectors.
 template <class T, class Dir, class Finish>
 ccns_status cg_loop(ccns_ctx *c, CgState *st, T *x, T *r, T *const pbuf[2], int &par_buf, T *q, const T *dinv,
                     size_t ntot, int &last_it, Dir dir, Finish finish, ccns_solve_info *info, int kid) {
@@ -1725,23 +1758,21 @@ ccns_status cg_loop(ccns_ctx *c, CgState *st, T *x, T *r, T *const pbuf[2], int 
     for (;;) {
         for (int u = 0; u < chunk; ++u, ++it) {
             const int par = it & 1;
-            const bool tm = c->timing && (it % 4 == 0) && it < last_it;
-            if (tm) (void)hipEventRecord(next_event(c), c->stream);
+            const bool tm = c->timing && (it % 8 == 4) && it < last_it;
             const int nd = dir(first ? 1 : 0, par, pbuf[par_buf], pbuf[par_buf ^ 1],
                                first ? c->part[PB_INIT] : c->part[PB_UPD], first ? c->init_nblk : nl,
-                               c->part[PB_DIR]);
-            if (tm) (void)hipEventRecord(next_event(c), c->stream);
+                               c->part[PB_DIR], tm);
             finish();
-            k_cg_update<T><<<nl, UT, 0, c->stream>>>(ntot, nl, dinv, x, r, pbuf[par_buf ^ 1], q, st, par,
-                                                     c->part[PB_DIR], nd, c->part[PB_UPD]);
-            if (tm) (void)hipEventRecord(next_event(c), c->stream);
+            launch(c, tm, kid + 1, k_cg_update<T>, dim3(nl), dim3(UT), ntot, nl, dinv, x, r,
+                   (const T *)pbuf[par_buf ^ 1], (const T *)q, st, par, (const double *)c->part[PB_DIR], nd,
+                   c->part[PB_UPD]);
             par_buf ^= 1;
             first = false;
         }
         HIPCHK(c, hipGetLastError());
         HIPCHK(c, hipMemcpyAsync(c->h_st, st, sizeof(CgState), hipMemcpyDeviceToHost, c->stream));
         HIPCHK(c, hipStreamSynchronize(c->stream));
-        if (c->timing) harvest_events(c, kid);
+        if (c->timing) harvest_events(c);
         if (c->h_st->done) break;
         chunk = 8;
     }
@@ -1778,9 +1809,9 @@ template <class T>
 ccns_status jacobi_cg(ccns_ctx *c, PoisCoefT<T> pc, CgState *st, T *x, T *r, T *p0, T *p1, T *q, int &last_it,
                       ccns_solve_info *info) {
     T *pb[2] = {p0, p1};
-    auto dir = [&](int first, int par, T *pold, T *pnew, const double *pin, int nin2, double *pout) {
-        k_pois_dir<T><<<c->dp.nblk, NT, 0, c->stream>>>(c->dp, pc, r, pold, pnew, q, st, first, par, pin, nin2,
-                                                        pout);
+    auto dir = [&](int first, int par, T *pold, T *pnew, const double *pin, int nin2, double *pout, bool tm) {
+        launch(c, tm, 0, k_pois_dir<T>, dim3(c->dp.nblk), dim3(NT), c->dp, pc, (const T *)r, (const T *)pold, pnew, q,
+               st, first, par, pin, nin2, pout);
         return c->dp.nblk;
     };
     return cg_loop<T>(c, st, x, r, pb, c->pbuf_pois, q, pc.dinv, c->w.L.n, last_it, dir, [] {}, info, 0);
@@ -1913,9 +1944,6 @@ ccns_status mg_setup(ccns_ctx *c, const HostCoef &hc) {
     return CCNS_OK;
 }
 
-// z = V(b) on level l of a hierarchy; returns the array holding the result.
-// On level 0 the last kernel also writes the residual statistics, reduced to
-// one group in PB_MG.
 // First level of the fused coarse end of the cycle: the first level (after
 // the finest) of at most TAIL_CELLS cells.
 constexpr long TAIL_CELLS = 64 * 32;
@@ -1926,12 +1954,16 @@ size_t tail_start(const std::vector<ccns_ctx::LevelT<T>> &mg) {
     return mg.size() - 1;
 }
 
+// z = V(b) on level l of a hierarchy; returns the array holding the result.
+// On level 0 the last kernel also writes the residual statistics, reduced to
+// one group in PB_MG.  Every kernel returns at once when *done is set (a
+// cycle launched after the solve stopped).
 template <class T>
-T *vcycle(ccns_ctx *c, std::vector<ccns_ctx::LevelT<T>> &mg, size_t l, const T *b) {
+T *vcycle(ccns_ctx *c, std::vector<ccns_ctx::LevelT<T>> &mg, size_t l, const T *b, const int *done) {
     ccns_ctx::LevelT<T> &L = mg[l];
     hipStream_t s = c->stream;
     if (l + 1 == mg.size()) {
-        k_mg_coarsest<T><<<1, NT, 0, s>>>(c->ncoarse_act, c->pidx, c->pinv, b, L.x);
+        k_mg_coarsest<T><<<1, NT, 0, s>>>(c->ncoarse_act, c->pidx, c->pinv, b, L.x, done);
         return L.x;
     }
     if (l >= 1 && l == tail_start(mg)) {
@@ -1946,6 +1978,7 @@ T *vcycle(ccns_ctx *c, std::vector<ccns_ctx::LevelT<T>> &mg, size_t l, const T *
         d.idx = c->pidx;
         d.pinv = c->pinv;
         d.omega = (T)MG_OMEGA;
+        d.done = done;
         k_mg_tail<T><<<1, TT, 0, s>>>(d);
         return d.nlev >= 2 ? L.xt : L.x;
     }
@@ -1959,18 +1992,18 @@ T *vcycle(ccns_ctx *c, std::vector<ccns_ctx::LevelT<T>> &mg, size_t l, const T *
     // faster in the latency form at every level)
     if (l == 0 && sizeof(T) == 8)
         k_mg_down_staged<T><<<nb, NT, 0, s>>>(L.L.nx, L.L.ny, L.L.pitch, gx, pc, b, L.x, C.L.pitch, C.L.nx, C.L.ny,
-                                              C.dinv, C.b, om);
+                                              C.dinv, C.b, om, done);
     else
         k_mg_down<T><<<nb, NT, 0, s>>>(L.L.nx, L.L.ny, L.L.pitch, gx, pc, b, L.x, C.L.pitch, C.L.nx, C.L.ny,
-                                       C.dinv, C.b, om);
-    const T *xc = vcycle<T>(c, mg, l + 1, C.b);
+                                       C.dinv, C.b, om, done);
+    const T *xc = vcycle<T>(c, mg, l + 1, C.b, done);
     if (l == 0) {
         k_mg_up_staged<T, true><<<nb, NT, 0, s>>>(L.L.nx, L.L.ny, L.L.pitch, gx, pc, b, L.x, xc, C.L.pitch, L.xt,
-                                                  om, c->part[PB_UPD], nb);
+                                                  om, c->part[PB_UPD], nb, done);
         k_reduce_partials<4><<<1, NT, 0, s>>>(c->part[PB_UPD], nb, c->part[PB_MG]);
     } else {
         k_mg_up<T, false><<<nb, NT, 0, s>>>(L.L.nx, L.L.ny, L.L.pitch, gx, pc, b, L.x, xc, C.L.pitch, L.xt, om,
-                                            nullptr, nb);
+                                            nullptr, nb, done);
     }
     return L.xt;
 }
@@ -1986,27 +2019,25 @@ ccns_status mg_cg(ccns_ctx *c, std::vector<ccns_ctx::LevelT<T>> &mg, PoisCoefT<T
     const int nl = update_blocks(ntot);
     T *pb[2] = {p0, p1};
     int &pbuf = c->pbuf_pois;
-    T *z = vcycle<T>(c, mg, 0, r);
+    T *z = vcycle<T>(c, mg, 0, r, &st->done);
     int chunk = std::max(2, last_it + 1);
     int it = 0;
     for (;;) {
         for (int u = 0; u < chunk; ++u, ++it) {
             const int par = it & 1;
-            const bool tm = c->timing && (it % 2 == 0) && it < last_it;
-            if (tm) (void)hipEventRecord(next_event(c), c->stream);
-            k_pois_dir_z<T><<<dp.nblk, NT, 0, c->stream>>>(dp, pc, z, pb[pbuf], pb[pbuf ^ 1], q, st, it == 0 ? 1 : 0,
-                                                           par, c->part[PB_MG], 1, pinit, ninit, c->part[PB_DIR]);
-            if (tm) (void)hipEventRecord(next_event(c), c->stream);
-            k_cg_update<T><<<nl, UT, 0, c->stream>>>(ntot, nl, pc.dinv, x, r, pb[pbuf ^ 1], q, st, par,
-                                                     c->part[PB_DIR], dp.nblk, c->part[PB_UPD]);
-            if (tm) (void)hipEventRecord(next_event(c), c->stream);
+            const bool tm = c->timing && (it % 8 == 4) && it < last_it;
+            launch(c, tm, 0, k_pois_dir_z<T>, dim3(dp.nblk), dim3(NT), dp, pc, (const T *)z, (const T *)pb[pbuf],
+                   pb[pbuf ^ 1], q, st, it == 0 ? 1 : 0, par, (const double *)c->part[PB_MG], 1, pinit, ninit,
+                   c->part[PB_DIR]);
+            launch(c, tm, 1, k_cg_update<T>, dim3(nl), dim3(UT), ntot, nl, pc.dinv, x, r, (const T *)pb[pbuf ^ 1],
+                   (const T *)q, st, par, (const double *)c->part[PB_DIR], dp.nblk, c->part[PB_UPD]);
             pbuf ^= 1;
-            z = vcycle<T>(c, mg, 0, r);
+            z = vcycle<T>(c, mg, 0, r, &st->done);
         }
         HIPCHK(c, hipGetLastError());
         HIPCHK(c, hipMemcpyAsync(c->h_st, st, sizeof(CgState), hipMemcpyDeviceToHost, c->stream));
         HIPCHK(c, hipStreamSynchronize(c->stream));
-        if (c->timing) harvest_events(c, 0);
+        if (c->timing) harvest_events(c);
         if (c->h_st->done) break;
         chunk = 2;
     }
@@ -2036,6 +2067,7 @@ constexpr int MAX_OUTER = 20;
 constexpr double INNER_TOL_MIN = 1e-5, INNER_TOL_MAX = 0.1;
 
 double inner_tol(double reduction) {
+    if (!(reduction > 0.0)) return INNER_TOL_MAX;  // also a NaN
     return std::min(INNER_TOL_MAX, std::max(INNER_TOL_MIN, 0.5 * reduction));
 }
 
@@ -2148,23 +2180,17 @@ ccns_status pred_cg(ccns_ctx *c, PredCoefT<T> pc, CgState *st, T *x, T *const r[
             const T *rin = it == 0 ? r[0] : r[a];
             const double *tin = it == 0 ? c->part[PB_INIT] : c->part[PB_UPD];
             const int nin = it == 0 ? c->init_nblk : PRED_RED;
-            const bool tm = c->timing && (it % 4 == 0) && it < last_it;
-            if (tm) (void)hipEventRecord(next_event(c), c->stream);
-            if (geo)
-                k_pred_cg<T, true><<<nb, NT, 0, c->stream>>>(L.pitch, L.rows, gx, gy, L.n, pc, st, it, x, rin, r[b],
-                                                             p[a], p[b], q[a], q[b], tin, nin, c->part[PB_DIR]);
-            else
-                k_pred_cg<T, false><<<nb, NT, 0, c->stream>>>(L.pitch, L.rows, gx, gy, L.n, pc, st, it, x, rin,
-                                                              r[b], p[a], p[b], q[a], q[b], tin, nin,
-                                                              c->part[PB_DIR]);
-            if (tm) (void)hipEventRecord(next_event(c), c->stream);
-            k_reduce_partials_split<7><<<PRED_RED, NT, 0, c->stream>>>(c->part[PB_DIR], nb, c->part[PB_UPD]);
-            if (tm) (void)hipEventRecord(next_event(c), c->stream);
+            const bool tm = c->timing && (it % 8 == 4) && it < last_it;
+            launch(c, tm, 2, geo ? k_pred_cg<T, true> : k_pred_cg<T, false>, dim3(nb), dim3(NT), L.pitch, L.rows, gx,
+                   gy, L.n, pc, st, it, x, rin, r[b], (const T *)p[a], p[b], (const T *)q[a], q[b], tin, nin,
+                   c->part[PB_DIR]);
+            launch(c, tm, 3, k_reduce_partials_split<7>, dim3(PRED_RED), dim3(NT), (const double *)c->part[PB_DIR],
+                   nb, c->part[PB_UPD]);
         }
         HIPCHK(c, hipGetLastError());
         HIPCHK(c, hipMemcpyAsync(c->h_st, st, sizeof(CgState), hipMemcpyDeviceToHost, c->stream));
         HIPCHK(c, hipStreamSynchronize(c->stream));
-        if (c->timing) harvest_events(c, 2);
+        if (c->timing) harvest_events(c);
         if (c->h_st->done) break;
         chunk = 8;
     }
