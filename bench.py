@@ -431,11 +431,17 @@ def main():
     value = cells * args.steps / elapsed / 1e6
     div_max = max(i["div_rel"] for i in infos)
     n_cg = float(np.mean([i["cg_iters"] for i in infos]))
-    mean_us = [ms[k] / max(cnt[k], 1) * 1e3 for k in range(4)]
+    # mean duration per timed kernel (None: no launch of it was sampled, e.g. the
+    # short inner pressure solves of the mixed mode stop before iteration 4)
+    mean_us = [ms[k] / cnt[k] * 1e3 if cnt[k] > 0 else None for k in range(4)]
+
+    def rate(bytes_per_cell, us):
+        return esz * bytes_per_cell * cells / (us * 1e-6) / 1e9 if us else None
+
     # the timed kernels run in float in the inner solves of the mixed mode
     esz = 0.5 if mixed else 1.0
     kname = "k_pred_cg<float>" if mixed else "k_pred_cg"
-    achieved = esz * PRED_CG_BYTES_PER_CELL * cells / (mean_us[2] * 1e-6) / 1e9
+    achieved = rate(PRED_CG_BYTES_PER_CELL, mean_us[2])
     out = {
         "metric": "Mcell-steps/s at 1e-8 divergence",
         "value": value,
@@ -461,7 +467,7 @@ def main():
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS,
+            "frac": achieved / HBM_PEAK_GBS if achieved else None,
             "traffic": None if mixed else stored_traffic("k_pred_cg", case.name),
             "bytes_per_launch": esz * PRED_CG_BYTES_PER_CELL * cells,
             "mean_launch_us": mean_us[2],
@@ -470,10 +476,8 @@ def main():
         "kernels": {
             kname: {"us": mean_us[2], "GBs": achieved},
             "k_reduce_partials<7>": {"us": mean_us[3]},
-            "k_pois_dir_z": {"us": mean_us[0],
-                             "GBs": esz * POIS_DIR_BYTES_PER_CELL * cells / (mean_us[0] * 1e-6) / 1e9},
-            "k_cg_update (Poisson)": {"us": mean_us[1],
-                                      "GBs": esz * POIS_UPDATE_BYTES_PER_CELL * cells / (mean_us[1] * 1e-6) / 1e9},
+            "k_pois_dir_z": {"us": mean_us[0], "GBs": rate(POIS_DIR_BYTES_PER_CELL, mean_us[0])},
+            "k_cg_update (Poisson)": {"us": mean_us[1], "GBs": rate(POIS_UPDATE_BYTES_PER_CELL, mean_us[1])},
         },
         "cpu_baseline": None,
     }

@@ -1594,7 +1594,12 @@ struct ccns_ctx {
     int timing;
     std::vector<hipEvent_t> evpool;
     size_t evused;
-    std::vector<std::pair<size_t, int>> evlog;  // (first event of the pair, timing slot)
+    struct TimedLaunch {
+        size_t ev;  // first event of the pair
+        int kid;    // timing slot
+        int it;     // CG iteration of the launch
+    };
+    std::vector<TimedLaunch> evlog;
     double t_ms[4];    // Poisson direction, Poisson update, predictor CG iteration, its reduction
     long t_count[4];
     std::string err;
@@ -1713,9 +1718,11 @@ hipEvent_t next_event(ccns_ctx *c) {
 // Launches a kernel on the context's stream.  When tm, HIP start and stop
 // events are attached to the dispatch itself (hipExtLaunchKernelGGL), so the
 // sampled time is the kernel's own duration without the gap of a separate
-// event packet, and the pair is logged for timing slot kid.
+// event packet, and the pair is logged for timing slot kid with the CG
+// iteration it of the launch.
 template <typename... KArgs, typename... Args>
-void launch(ccns_ctx *c, bool tm, int kid, void (*kernel)(KArgs...), dim3 grid, dim3 block, Args... args) {
+void launch(ccns_ctx *c, bool tm, int kid, int it, void (*kernel)(KArgs...), dim3 grid, dim3 block,
+            Args... args) {
     hipEvent_t e0 = nullptr, e1 = nullptr;
     const size_t i0 = c->evused;
     if (tm) {
@@ -1723,20 +1730,22 @@ void launch(ccns_ctx *c, bool tm, int kid, void (*kernel)(KArgs...), dim3 grid, 
         e1 = e0 ? next_event(c) : nullptr;
     }
     if (e0 && e1) {
-        c->evlog.push_back({i0, kid});
+        c->evlog.push_back({i0, kid, it});
         hipExtLaunchKernelGGL(kernel, grid, block, 0, c->stream, e0, e1, 0, args...);
     } else {
         kernel<<<grid, block, 0, c->stream>>>(args...);
     }
 }
 
-// Adds the durations of the sampled launches logged since the last call.
-void harvest_events(ccns_ctx *c) {
+// Adds the durations of the sampled launches of a finished solve whose
+// iteration came before it_stop (the launch that stopped the solve, and any
+// after it, return early and are not the kernel's cost).
+void harvest_events(ccns_ctx *c, int it_stop) {
     for (const auto &e : c->evlog) {
         float ms = 0.f;
-        if (hipEventElapsedTime(&ms, c->evpool[e.first], c->evpool[e.first + 1]) == hipSuccess) {
-            c->t_ms[e.second] += ms;
-            c->t_count[e.second] += 1;
+        if (e.it < it_stop && hipEventElapsedTime(&ms, c->evpool[e.ev], c->evpool[e.ev + 1]) == hipSuccess) {
+            c->t_ms[e.kid] += ms;
+            c->t_count[e.kid] += 1;
         }
     }
     c->evlog.clear();
@@ -1745,9 +1754,9 @@ void harvest_events(ccns_ctx *c) {
 
 // Runs CG iterations (after the caller launched the init kernel, whose
 // partials are in PB_INIT) until the device flags the end of the solve.
-// dir(first, par, pold, pnew, pin, nin, pout, tm) launches the
-// direction+operator kernel (timed when tm) and returns the number of
-// partials it leaves in PB_DIR; finish() runs after it.  T is the storage type of the vectors.
+// dir(first, par, pold, pnew, pin, nin, pout, tm, it) launches the
+// direction+operator kernel of iteration it (timed when tm) and returns the
+// number of partials it leaves in PB_DIR; finish() runs after it.  T is the storage type of the vectors.
 template <class T, class Dir, class Finish>
 ccns_status cg_loop(ccns_ctx *c, CgState *st, T *x, T *r, T *const pbuf[2], int &par_buf, T *q, const T *dinv,
                     size_t ntot, int &last_it, Dir dir, Finish finish, ccns_solve_info *info, int kid) {
@@ -1761,9 +1770,9 @@ ccns_status cg_loop(ccns_ctx *c, CgState *st, T *x, T *r, T *const pbuf[2], int 
             const bool tm = c->timing && (it % 8 == 4) && it < last_it;
             const int nd = dir(first ? 1 : 0, par, pbuf[par_buf], pbuf[par_buf ^ 1],
                                first ? c->part[PB_INIT] : c->part[PB_UPD], first ? c->init_nblk : nl,
-                               c->part[PB_DIR], tm);
+                               c->part[PB_DIR], tm, it);
             finish();
-            launch(c, tm, kid + 1, k_cg_update<T>, dim3(nl), dim3(UT), ntot, nl, dinv, x, r,
+            launch(c, tm, kid + 1, it, k_cg_update<T>, dim3(nl), dim3(UT), ntot, nl, dinv, x, r,
                    (const T *)pbuf[par_buf ^ 1], (const T *)q, st, par, (const double *)c->part[PB_DIR], nd,
                    c->part[PB_UPD]);
             par_buf ^= 1;
@@ -1772,11 +1781,11 @@ ccns_status cg_loop(ccns_ctx *c, CgState *st, T *x, T *r, T *const pbuf[2], int 
         HIPCHK(c, hipGetLastError());
         HIPCHK(c, hipMemcpyAsync(c->h_st, st, sizeof(CgState), hipMemcpyDeviceToHost, c->stream));
         HIPCHK(c, hipStreamSynchronize(c->stream));
-        if (c->timing) harvest_events(c);
         if (c->h_st->done) break;
         chunk = 8;
     }
     last_it = c->h_st->it_final;
+    if (c->timing) harvest_events(c, c->h_st->it_final);
     if (info) {
         info->iterations = c->h_st->it_final;
         info->outer = 1;
@@ -1809,8 +1818,9 @@ template <class T>
 ccns_status jacobi_cg(ccns_ctx *c, PoisCoefT<T> pc, CgState *st, T *x, T *r, T *p0, T *p1, T *q, int &last_it,
                       ccns_solve_info *info) {
     T *pb[2] = {p0, p1};
-    auto dir = [&](int first, int par, T *pold, T *pnew, const double *pin, int nin2, double *pout, bool tm) {
-        launch(c, tm, 0, k_pois_dir<T>, dim3(c->dp.nblk), dim3(NT), c->dp, pc, (const T *)r, (const T *)pold, pnew, q,
+    auto dir = [&](int first, int par, T *pold, T *pnew, const double *pin, int nin2, double *pout, bool tm,
+                   int it) {
+        launch(c, tm, 0, it, k_pois_dir<T>, dim3(c->dp.nblk), dim3(NT), c->dp, pc, (const T *)r, (const T *)pold, pnew, q,
                st, first, par, pin, nin2, pout);
         return c->dp.nblk;
     };
@@ -2026,10 +2036,10 @@ ccns_status mg_cg(ccns_ctx *c, std::vector<ccns_ctx::LevelT<T>> &mg, PoisCoefT<T
         for (int u = 0; u < chunk; ++u, ++it) {
             const int par = it & 1;
             const bool tm = c->timing && (it % 8 == 4) && it < last_it;
-            launch(c, tm, 0, k_pois_dir_z<T>, dim3(dp.nblk), dim3(NT), dp, pc, (const T *)z, (const T *)pb[pbuf],
+            launch(c, tm, 0, it, k_pois_dir_z<T>, dim3(dp.nblk), dim3(NT), dp, pc, (const T *)z, (const T *)pb[pbuf],
                    pb[pbuf ^ 1], q, st, it == 0 ? 1 : 0, par, (const double *)c->part[PB_MG], 1, pinit, ninit,
                    c->part[PB_DIR]);
-            launch(c, tm, 1, k_cg_update<T>, dim3(nl), dim3(UT), ntot, nl, pc.dinv, x, r, (const T *)pb[pbuf ^ 1],
+            launch(c, tm, 1, it, k_cg_update<T>, dim3(nl), dim3(UT), ntot, nl, pc.dinv, x, r, (const T *)pb[pbuf ^ 1],
                    (const T *)q, st, par, (const double *)c->part[PB_DIR], dp.nblk, c->part[PB_UPD]);
             pbuf ^= 1;
             z = vcycle<T>(c, mg, 0, r, &st->done);
@@ -2037,11 +2047,11 @@ ccns_status mg_cg(ccns_ctx *c, std::vector<ccns_ctx::LevelT<T>> &mg, PoisCoefT<T
         HIPCHK(c, hipGetLastError());
         HIPCHK(c, hipMemcpyAsync(c->h_st, st, sizeof(CgState), hipMemcpyDeviceToHost, c->stream));
         HIPCHK(c, hipStreamSynchronize(c->stream));
-        if (c->timing) harvest_events(c);
         if (c->h_st->done) break;
         chunk = 2;
     }
     last_it = c->h_st->it_final;
+    if (c->timing) harvest_events(c, c->h_st->it_final);
     if (info) {
         info->iterations = c->h_st->it_final;
         info->outer = 1;
@@ -2181,20 +2191,20 @@ ccns_status pred_cg(ccns_ctx *c, PredCoefT<T> pc, CgState *st, T *x, T *const r[
             const double *tin = it == 0 ? c->part[PB_INIT] : c->part[PB_UPD];
             const int nin = it == 0 ? c->init_nblk : PRED_RED;
             const bool tm = c->timing && (it % 8 == 4) && it < last_it;
-            launch(c, tm, 2, geo ? k_pred_cg<T, true> : k_pred_cg<T, false>, dim3(nb), dim3(NT), L.pitch, L.rows, gx,
+            launch(c, tm, 2, it, geo ? k_pred_cg<T, true> : k_pred_cg<T, false>, dim3(nb), dim3(NT), L.pitch, L.rows, gx,
                    gy, L.n, pc, st, it, x, rin, r[b], (const T *)p[a], p[b], (const T *)q[a], q[b], tin, nin,
                    c->part[PB_DIR]);
-            launch(c, tm, 3, k_reduce_partials_split<7>, dim3(PRED_RED), dim3(NT), (const double *)c->part[PB_DIR],
+            launch(c, tm, 3, it, k_reduce_partials_split<7>, dim3(PRED_RED), dim3(NT), (const double *)c->part[PB_DIR],
                    nb, c->part[PB_UPD]);
         }
         HIPCHK(c, hipGetLastError());
         HIPCHK(c, hipMemcpyAsync(c->h_st, st, sizeof(CgState), hipMemcpyDeviceToHost, c->stream));
         HIPCHK(c, hipStreamSynchronize(c->stream));
-        if (c->timing) harvest_events(c);
         if (c->h_st->done) break;
         chunk = 8;
     }
     last_it = c->h_st->it_final;
+    if (c->timing) harvest_events(c, c->h_st->it_final);
     if (info) {
         info->iterations = c->h_st->it_final;
         info->outer = 1;
