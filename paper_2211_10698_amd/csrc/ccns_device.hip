@@ -454,7 +454,8 @@ __global__ __launch_bounds__(NT) void k_mg_down_staged(int nx, int ny, int P, in
 template <class T, bool STATS>
 __global__ __launch_bounds__(NT) void k_mg_up_staged(int nx, int ny, int P, int gx, PoisCoefT<T> c, const T *__restrict__ b,
                                               const T *__restrict__ x2, const T *__restrict__ xc, int Pc,
-                                              T *__restrict__ z, T omega, double *pout, int nblk, const int *done) {
+                                              T *__restrict__ z, T omega, T cgc, double *pout, int nblk,
+                                              const int *done) {
     if (*done) return;
     __shared__ T s1[MHt][MW];
     __shared__ T s2[MTY + 2][TX + 2];
@@ -469,7 +470,7 @@ __global__ __launch_bounds__(NT) void k_mg_up_staged(int nx, int ny, int P, int 
             const size_t k = in ? (size_t)j * P + i : 0;
             const size_t kc = in ? (size_t)((j + 1) >> 1) * Pc + ((i + 1) >> 1) : 0;
             const T dv = c.dinv[k], xv = x2[k], ec = xc[kc];
-            s1[ly][lx] = (in && dv > (T)0) ? xv + ec : (T)0;
+            s1[ly][lx] = (in && dv > (T)0) ? xv + cgc * ec : (T)0;
         }
     }
     __syncthreads();
@@ -613,7 +614,8 @@ __global__ __launch_bounds__(NT) void k_mg_down(int nx, int ny, int P, int gx, P
 template <class T, bool STATS>
 __global__ __launch_bounds__(NT) void k_mg_up(int nx, int ny, int P, int gx, PoisCoefT<T> c, const T *__restrict__ b,
                                               const T *__restrict__ x2, const T *__restrict__ xc, int Pc,
-                                              T *__restrict__ z, T omega, double *pout, int nblk, const int *done) {
+                                              T *__restrict__ z, T omega, T cgc, double *pout, int nblk,
+                                              const int *done) {
     if (*done) return;
     __shared__ T s2[MTY + 2][TX + 2];    // x after the first sweep, on the tile and a one-cell ring
     const MgTile t = mg_tile(gx);
@@ -629,7 +631,7 @@ __global__ __launch_bounds__(NT) void k_mg_up(int nx, int ny, int P, int gx, Poi
             const size_t kk = in ? k : 0;
             const size_t kc = in ? (size_t)((j + 1) >> 1) * Pc + ((i + 1) >> 1) : 0;
             const T dv = c.dinv[kk], xv = x2[kk], ec = xc[kc];
-            return (in && dv > (T)0) ? xv + ec : (T)0;
+            return (in && dv > (T)0) ? xv + cgc * ec : (T)0;
         };
         for (int e = threadIdx.x; e < (MTY + 2) * (TX + 2); e += NT) {
             const int ly = e / (TX + 2), lx = e - ly * (TX + 2);
@@ -696,7 +698,10 @@ struct TailDesc {
     const int *idx;
     const double *pinv;
     T omega;
+    T cgc;               // factor on the interpolated coarse correction
     const int *done;     // the solve's done flag: nothing to do once set
+    int lofs[MAX_TAIL];  // k_mg_tail_lds: offset of each level's arrays in LDS (elements)
+    T *out;              // k_mg_tail_lds: where the tail's first level's result goes
 };
 
 template <class T>
@@ -774,7 +779,7 @@ __global__ __launch_bounds__(TT) void k_mg_tail(TailDesc<T> d) {
             const size_t k = (size_t)j * L.P + i;
             const size_t kc = (size_t)((j + 1) >> 1) * C.P + ((i + 1) >> 1);
             const T dv = L.dinv[k], xv = L.x[k], ec = xc[kc];
-            L.xt[k] = dv > (T)0 ? xv + ec : (T)0;
+            L.xt[k] = dv > (T)0 ? xv + d.cgc * ec : (T)0;
         }
         __syncthreads();
         for (int e = threadIdx.x; e < ncell; e += TT) {
@@ -791,6 +796,150 @@ __global__ __launch_bounds__(TT) void k_mg_tail(TailDesc<T> d) {
             L.xt[k] = dv > (T)0 ? xv + om * dv * (bv - tail_Ax(L, L.x, k)) : (T)0;
         }
         __syncthreads();
+    }
+}
+
+// The coarse end of the cycle as k_mg_tail, with every level's arrays (the
+// coefficients, b, x and xt, in compact (nx+2) x (ny+2) rows) held in LDS:
+// each phase then waits for LDS instead of L2.  The levels are loaded once;
+// the result of the tail's first level is written to d.out.  Same arithmetic
+// per cell as k_mg_tail; the interpolated start value and the first sweep on
+// the way up, and the two sweeps from zero on the way down, are formed in one
+// phase each (the start values at the five points of the stencil).
+template <class T>
+__device__ inline T lds_Ax(const T *cx, const T *cy, const T *v, int k, int W) {
+    const T ce = cx[k], cw = cx[k - 1], cn = cy[k], cs = cy[k - W];
+    return (ce + cw + cn + cs) * v[k] - ce * v[k + 1] - cw * v[k - 1] - cn * v[k + W] - cs * v[k - W];
+}
+
+template <class T>
+__global__ __launch_bounds__(TT) void k_mg_tail_lds(TailDesc<T> d) {
+    if (*d.done) return;
+    extern __shared__ double tail_lds[];
+    T *const sm = reinterpret_cast<T *>(tail_lds);
+    const T om = d.omega;
+    // level l's six arrays start at sm + d.lofs[l], each (nx+2)(ny+2) long
+    auto arr = [&](int l, int a) { return sm + d.lofs[l] + a * (d.lv[l].nx + 2) * (d.lv[l].ny + 2); };
+    for (int l = 0; l < d.nlev; ++l) {
+        const TailLevel<T> &L = d.lv[l];
+        const int W = L.nx + 2, n = W * (L.ny + 2);
+        T *cx = arr(l, 0), *cy = arr(l, 1), *dv = arr(l, 2), *b = arr(l, 3), *x = arr(l, 4), *xt = arr(l, 5);
+        for (int e = threadIdx.x; e < n; e += TT) {
+            const int j = e / W, i = e - j * W;
+            const size_t k = (size_t)j * L.P + i;
+            cx[e] = L.cx[k];
+            cy[e] = L.cy[k];
+            dv[e] = L.dinv[k];
+            b[e] = l == 0 ? L.b[k] : (T)0;
+            x[e] = (T)0;
+            xt[e] = (T)0;
+        }
+    }
+    __syncthreads();
+    // down: two sweeps from zero (the first formed at the stencil's points),
+    // then the residual restricted to the next level
+    for (int l = 0; l + 1 < d.nlev; ++l) {
+        const TailLevel<T> &L = d.lv[l];
+        const int W = L.nx + 2;
+        const T *cx = arr(l, 0), *cy = arr(l, 1), *dv = arr(l, 2), *b = arr(l, 3);
+        T *x = arr(l, 4);
+        const int ncell = L.nx * L.ny;
+        auto x1 = [&](int k) { return dv[k] > (T)0 ? om * dv[k] * b[k] : (T)0; };
+        for (int e = threadIdx.x; e < ncell; e += TT) {
+            const int k = (e / L.nx + 1) * W + (e % L.nx + 1);
+            const T ce = cx[k], cw = cx[k - 1], cn = cy[k], cs = cy[k - W];
+            const T xv = x1(k);
+            const T Ax = (ce + cw + cn + cs) * xv - ce * x1(k + 1) - cw * x1(k - 1) - cn * x1(k + W) - cs * x1(k - W);
+            x[k] = dv[k] > (T)0 ? xv + om * dv[k] * (b[k] - Ax) : (T)0;
+        }
+        __syncthreads();
+        const TailLevel<T> &C = d.lv[l + 1];
+        const int Wc = C.nx + 2;
+        const T *dvc = arr(l + 1, 2);
+        T *bc = arr(l + 1, 3);
+        const int nc = C.nx * C.ny;
+        for (int e = threadIdx.x; e < nc; e += TT) {
+            const int I = e % C.nx + 1, J = e / C.nx + 1;
+            T r[2][2];
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int bb = 0; bb < 2; ++bb) {
+                    const int j = 2 * J - 1 + a, i = 2 * I - 1 + bb;
+                    T rv = (T)0;
+                    if (j <= L.ny && i <= L.nx) {
+                        const int k = j * W + i;
+                        if (dv[k] > (T)0) rv = b[k] - lds_Ax(cx, cy, x, k, W);
+                    }
+                    r[a][bb] = rv;
+                }
+            const int kc = J * Wc + I;
+            const T sum = (r[0][0] + r[0][1]) + (r[1][0] + r[1][1]);
+            bc[kc] = dvc[kc] > (T)0 ? sum : (T)0;
+        }
+        __syncthreads();
+    }
+    // coarsest: x = A^+ b with the dense pseudo-inverse (global, L2)
+    {
+        const int l = d.nlev - 1;
+        const TailLevel<T> &L = d.lv[l];
+        const int W = L.nx + 2;
+        const T *b = arr(l, 3);
+        T *x = arr(l, 4);
+        __shared__ double sb[1024];
+        for (int i = threadIdx.x; i < d.ncoarse; i += TT) {
+            const int k = d.idx[i];
+            sb[i] = b[(k / L.P) * W + k % L.P];
+        }
+        __syncthreads();
+        for (int i = threadIdx.x; i < d.ncoarse; i += TT) {
+            double acc = 0.0;
+            for (int j2 = 0; j2 < d.ncoarse; ++j2) acc += d.pinv[(size_t)i * d.ncoarse + j2] * sb[j2];
+            const int k = d.idx[i];
+            x[(k / L.P) * W + k % L.P] = (T)acc;
+        }
+        __syncthreads();
+    }
+    // up: the interpolated start value and the first sweep (into xt), then
+    // the second sweep (into x)
+    for (int l = d.nlev - 2; l >= 0; --l) {
+        const TailLevel<T> &L = d.lv[l];
+        const TailLevel<T> &C = d.lv[l + 1];
+        const int W = L.nx + 2, Wc = C.nx + 2;
+        const T *cx = arr(l, 0), *cy = arr(l, 1), *dv = arr(l, 2), *b = arr(l, 3), *xcs = arr(l + 1, 4);
+        T *x = arr(l, 4), *xt = arr(l, 5);
+        const int ncell = L.nx * L.ny;
+        auto start = [&](int j, int i) {
+            const bool in = (j >= 1) && (j <= L.ny) && (i >= 1) && (i <= L.nx);
+            const int k = in ? j * W + i : 0;
+            const int kc = in ? ((j + 1) >> 1) * Wc + ((i + 1) >> 1) : 0;
+            return (in && dv[k] > (T)0) ? x[k] + d.cgc * xcs[kc] : (T)0;
+        };
+        for (int e = threadIdx.x; e < ncell; e += TT) {
+            const int j = e / L.nx + 1, i = e % L.nx + 1;
+            const int k = j * W + i;
+            const T ce = cx[k], cw = cx[k - 1], cn = cy[k], cs = cy[k - W];
+            const T xv = start(j, i);
+            const T Ax = (ce + cw + cn + cs) * xv - ce * start(j, i + 1) - cw * start(j, i - 1) -
+                         cn * start(j + 1, i) - cs * start(j - 1, i);
+            xt[k] = dv[k] > (T)0 ? xv + om * dv[k] * (b[k] - Ax) : (T)0;
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < ncell; e += TT) {
+            const int k = (e / L.nx + 1) * W + (e % L.nx + 1);
+            x[k] = dv[k] > (T)0 ? xt[k] + om * dv[k] * (b[k] - lds_Ax(cx, cy, xt, k, W)) : (T)0;
+        }
+        __syncthreads();
+    }
+    // the tail's first level's result to global memory (interior cells)
+    {
+        const TailLevel<T> &L = d.lv[0];
+        const int W = L.nx + 2;
+        const T *x = arr(0, 4);
+        for (int e = threadIdx.x; e < L.nx * L.ny; e += TT) {
+            const int j = e / L.nx + 1, i = e % L.nx + 1;
+            d.out[(size_t)j * L.P + i] = x[j * W + i];
+        }
     }
 }
 
@@ -1590,6 +1739,7 @@ struct ccns_ctx {
     double *pinv;
     int *pidx;
     int ncoarse_act;
+    int tail_lds;       // bytes of dynamic LDS the LDS-resident coarse end may use (0: not used)
     // optional kernel timing: start/stop events attached to sampled launches
     int timing;
     std::vector<hipEvent_t> evpool;
@@ -1841,6 +1991,13 @@ ccns_status pressure_solve_dev(ccns_ctx *c, int nin, ccns_solve_info *info) {
 
 constexpr int MG_NU = 2;          // pre- and post-smoothing sweeps
 constexpr double MG_OMEGA = 0.8;  // weighted-Jacobi damping
+// Factor on the interpolated coarse correction.  A constant factor keeps the
+// cycle symmetric (pre- and post-smoothing are adjoint and restriction is the
+// transpose of interpolation) and positive definite below 2.  Measured on the
+// 2048x1024 channel: 1.0 needs 10 iterations per step, 0.9 needs 16 and 1.3
+// needs 31 (the coarse operator's half-sum weights already scale the
+// correction as a rediscretisation would).
+constexpr double MG_CGC = 1.0;
 
 // Builds the coarse levels on the host from the fine Poisson weights and
 // uploads them (and their float copies in precision 1); the coarsest grid
@@ -1988,9 +2145,19 @@ T *vcycle(ccns_ctx *c, std::vector<ccns_ctx::LevelT<T>> &mg, size_t l, const T *
         d.idx = c->pidx;
         d.pinv = c->pinv;
         d.omega = (T)MG_OMEGA;
+        d.cgc = (T)MG_CGC;
         d.done = done;
-        k_mg_tail<T><<<1, TT, 0, s>>>(d);
-        return d.nlev >= 2 ? L.xt : L.x;
+        d.out = d.nlev >= 2 ? L.xt : L.x;
+        size_t elems = 0;
+        for (int t = 0; t < d.nlev; ++t) {
+            d.lofs[t] = (int)elems;
+            elems += 6 * (size_t)(d.lv[t].nx + 2) * (d.lv[t].ny + 2);
+        }
+        if (elems * sizeof(T) <= (size_t)c->tail_lds)
+            k_mg_tail_lds<T><<<1, TT, elems * sizeof(T), s>>>(d);
+        else
+            k_mg_tail<T><<<1, TT, 0, s>>>(d);
+        return d.out;
     }
     PoisCoefT<T> pc{L.cx, L.cy, L.dinv};
     const int gx = (L.L.nx + TX - 1) / TX, gy = (L.L.ny + MTY - 1) / MTY;
@@ -2009,11 +2176,11 @@ T *vcycle(ccns_ctx *c, std::vector<ccns_ctx::LevelT<T>> &mg, size_t l, const T *
     const T *xc = vcycle<T>(c, mg, l + 1, C.b, done);
     if (l == 0) {
         k_mg_up_staged<T, true><<<nb, NT, 0, s>>>(L.L.nx, L.L.ny, L.L.pitch, gx, pc, b, L.x, xc, C.L.pitch, L.xt,
-                                                  om, c->part[PB_UPD], nb, done);
+                                                  om, (T)MG_CGC, c->part[PB_UPD], nb, done);
         k_reduce_partials<4><<<1, NT, 0, s>>>(c->part[PB_UPD], nb, c->part[PB_MG]);
     } else {
         k_mg_up<T, false><<<nb, NT, 0, s>>>(L.L.nx, L.L.ny, L.L.pitch, gx, pc, b, L.x, xc, C.L.pitch, L.xt, om,
-                                            nullptr, nb, done);
+                                            (T)MG_CGC, nullptr, nb, done);
     }
     return L.xt;
 }
@@ -2386,6 +2553,23 @@ ccns_status ccns_ctx_create(const ccns_grid *grid, const ccns_params *params, co
     c->last_pois_in = c->last_pred_in = 8;
     c->pbuf_pois = 0;
     c->timing = 0;
+    {
+        // LDS for the coarse end of the cycle: what one work-group may hold,
+        // less the kernel's static arrays
+        int dev = 0, lmax = 0;
+        c->tail_lds = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&lmax, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess &&
+            lmax > 16384) {
+            const int dyn = lmax - 16384;
+            if (hipFuncSetAttribute((const void *)k_mg_tail_lds<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    dyn) == hipSuccess &&
+                hipFuncSetAttribute((const void *)k_mg_tail_lds<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    dyn) == hipSuccess)
+                c->tail_lds = dyn;
+        }
+        (void)hipGetLastError();
+    }
     c->evused = 0;
     for (int k = 0; k < 4; ++k) { c->t_ms[k] = 0.0; c->t_count[k] = 0; }
 
