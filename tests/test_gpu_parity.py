@@ -183,3 +183,24 @@ def test_breakdown_and_maxit_are_reported():
     phi, info, status = ctx.pressure_solve(_dev(b), check=False)
     assert status == ccns.ENOTCONV and info.iterations == 3
     assert np.all(np.isfinite(_host(phi)))
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_pressure_solve_long_thin_box(precision):
+    """A 4096x4 box: its multigrid hierarchy ends in seven levels of at most
+    2048 cells (1024x1 .. 16x1) whose arrays need 295 KB in FP64, more than
+    one work-group's LDS, so the coarse end of the cycle runs on global memory
+    (in FP32 the same levels fit in LDS).  The solution must meet the
+    oracle's residual test in FP64."""
+    g = W.GridSpec(4096, 4, 0.0, 0.0, 64.0, 0.0625)
+    case = W.Case("box_4096x4", g, [], re=100.0, steps=1, pcg_tol=1e-10, noise=0.0, seed=7)
+    caps, pr, st, ctx, Dx, Dy = case_setup(case, pcg_tol=1e-10, precond="mg", precision=precision, div_tol=0.0)
+    rng = np.random.default_rng(13)
+    b = np.where(pr.act_p, rng.uniform(-1, 1, pr.act_p.shape), 0.0)
+    phi_d, info, status = ctx.pressure_solve(_dev(b))
+    assert status == 0
+    bm = b - np.where(pr.act_p, b[pr.act_p].mean(), 0.0)
+    pd = _host(phi_d)
+    res = bm - derived.laplacian(pr, pd)
+    assert np.linalg.norm(res[pr.act_p]) <= 1.01 * 1e-10 * np.linalg.norm(bm[pr.act_p])
+    ctx.close()
