@@ -1056,44 +1056,6 @@ __global__ __launch_bounds__(NT) void k_pois_dir_z(Dims d, PoisCoefT<T> pc, cons
 // predictor (eq:pm_prediction): H = (rho/tau) V - mu visc(strain(., 0))
 // ---------------------------------------------------------------------------
 
-// conv^n, the predictor right-hand side, and U* := U^n as the start value.
-__global__ __launch_bounds__(NT) void k_pred_rhs(Dims d, PredCoef pc, const double *__restrict__ ax,
-                                                 const double *__restrict__ ay, const double *__restrict__ hbx,
-                                                 const double *__restrict__ hby, const double *__restrict__ dx,
-                                                 const double *__restrict__ dy, const double *__restrict__ ux,
-                                                 const double *__restrict__ uy, const double *__restrict__ pr,
-                                                 const double *__restrict__ vdx, const double *__restrict__ vdy,
-                                                 double *__restrict__ convx, double *__restrict__ convy,
-                                                 double *__restrict__ rhs, double *__restrict__ xs, double rho,
-                                                 double gxv, double gyv, int conv_valid) {
-    const size_t P = d.pitch, n = d.n;
-    for_cells(d, [&](int comp, int j, int i, size_t k) {
-        auto pxm = [&](size_t kk) { return pc.vu[kk] > 0.0 ? ux[kk] : 0.0; };
-        auto pym = [&](size_t kk) { return pc.vv[kk] > 0.0 ? uy[kk] : 0.0; };
-        if (comp == 0) {
-            xs[k] = ux[k];
-            if (!(pc.vu[k] > 0.0)) { rhs[k] = 0.0; return; }
-            const double cv = conv_x(ax, ay, ux, uy, hbx, dx, k, P);
-            const double cold = conv_valid ? convx[k] : cv;
-            convx[k] = cv;
-            const double presv = ax[k] * (pr[k + 1] - pr[k]);
-            const double kv = visc_x(pc.vc, k, P, pxm, pym);
-            rhs[k] = pc.rt * pc.vu[k] * ux[k] - 1.5 * rho * cv + 0.5 * rho * cold - presv +
-                     pc.mu * (kv + 2.0 * vdx[k]) + rho * pc.vu[k] * gxv;
-        } else {
-            xs[n + k] = uy[k];
-            if (!(pc.vv[k] > 0.0)) { rhs[n + k] = 0.0; return; }
-            const double cv = conv_y(ax, ay, ux, uy, hby, dy, k, P);
-            const double cold = conv_valid ? convy[k] : cv;
-            convy[k] = cv;
-            const double presv = ay[k] * (pr[k + P] - pr[k]);
-            const double kv = visc_y(pc.vc, k, P, pxm, pym);
-            rhs[n + k] = pc.rt * pc.vv[k] * uy[k] - 1.5 * rho * cv + 0.5 * rho * cold - presv +
-                         pc.mu * (kv + 2.0 * vdy[k]) + rho * pc.vv[k] * gyv;
-        }
-    });
-}
-
 // Predictor kernels work on tiles of 64 x 8 faces of both velocity
 // components per work-group, staged in LDS with a one-face halo.
 constexpr int HTY = 8;
@@ -1431,6 +1393,72 @@ __global__ __launch_bounds__(NT) void k_pred_resid(int P, int rows, int gx, int 
     } else {
         double w[5] = {v[0], v[1], v[2], v[3], v[4]};
         put_partials<5>(w, pout, gridDim.x);
+    }
+}
+
+// conv^n (eq:convective), the predictor right-hand side (eq:pm_prediction):
+// (rho/tau) M U^n - (3/2) rho conv^n + (1/2) rho conv^{n-1} - pres(P) +
+// mu (K U^n + 2 visc(strain(0, D))) + rho M g, and U* := U^n as the start
+// value, on the tiles of k_pred_cg: K U^n from the masked U^n staged in LDS
+// with its strains formed once per cell and node; convection and the
+// pressure gradient in index form.
+template <bool GEO>
+__global__ __launch_bounds__(NT) void k_pred_rhs(int P, int rows, int gx, int gy, size_t n, PredCoefT<double> pc,
+                                                 const double *__restrict__ ax, const double *__restrict__ ay,
+                                                 const double *__restrict__ hbx, const double *__restrict__ hby,
+                                                 const double *__restrict__ dx, const double *__restrict__ dy,
+                                                 const double *__restrict__ ux, const double *__restrict__ uy,
+                                                 const double *__restrict__ pr, const double *__restrict__ vdx,
+                                                 const double *__restrict__ vdy, double *__restrict__ convx,
+                                                 double *__restrict__ convy, double *__restrict__ rhs,
+                                                 double *__restrict__ xs, double rho, double gxv, double gyv,
+                                                 int conv_valid) {
+    __shared__ PredTile<double> s;
+    const int L = logical_group(((gridDim.x + 7) / 8) * 8);
+    if (L >= gx * gy) return;
+    const int c0 = (L % gx) * TX, r0 = (L / gx) * HTY;
+    for (int e = threadIdx.x; e < (HTY + 2) * (TX + 2); e += NT) {
+        const int ly = e / (TX + 2), lx = e - ly * (TX + 2);
+        const int j = r0 - 1 + ly, i = c0 - 1 + lx;
+        const bool in = (j >= 0) && (j < rows) && (i >= 0) && (i < P);
+        const size_t k = in ? (size_t)j * P + i : 0;
+        const double mx = pc.vu[k], my = pc.vv[k], u = ux[k], v = uy[k];
+        s.spx[ly][lx] = (in && mx > 0.0) ? u : 0.0;
+        s.spy[ly][lx] = (in && my > 0.0) ? v : 0.0;
+    }
+    __syncthreads();
+    pred_tile_strains<double, GEO>(s, pc.vc, P, rows, c0, r0);
+    __syncthreads();
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    for (int ly = ty; ly < HTY; ly += 4) {
+        const int j = r0 + ly, i = c0 + tx;
+        if (j >= rows) break;
+        const size_t k = (size_t)j * P + i;
+        double kx, ky;
+        pred_tile_K<double>(s, pc.vc, k, ly, tx, kx, ky);
+        const double u = ux[k], v = uy[k], mx = pc.vu[k], my = pc.vv[k];
+        xs[k] = u;
+        xs[n + k] = v;
+        if (mx > 0.0) {
+            const double cv = conv_x(ax, ay, ux, uy, hbx, dx, k, P);
+            const double cold = conv_valid ? convx[k] : cv;
+            convx[k] = cv;
+            const double presv = ax[k] * (pr[k + 1] - pr[k]);
+            rhs[k] = pc.rt * mx * u - 1.5 * rho * cv + 0.5 * rho * cold - presv + pc.mu * (kx + 2.0 * vdx[k]) +
+                     rho * mx * gxv;
+        } else {
+            rhs[k] = 0.0;
+        }
+        if (my > 0.0) {
+            const double cv = conv_y(ax, ay, ux, uy, hby, dy, k, P);
+            const double cold = conv_valid ? convy[k] : cv;
+            convy[k] = cv;
+            const double presv = ay[k] * (pr[k + P] - pr[k]);
+            rhs[n + k] = pc.rt * my * v - 1.5 * rho * cv + 0.5 * rho * cold - presv + pc.mu * (ky + 2.0 * vdy[k]) +
+                         rho * my * gyv;
+        } else {
+            rhs[n + k] = 0.0;
+        }
     }
 }
 
@@ -2328,12 +2356,15 @@ ccns_status pressure_solve_any(ccns_ctx *c, int nin, ccns_solve_info *info) {
 
 // conv^n and the predictor right-hand side; U* := U^n.
 void predictor_rhs(ccns_ctx *c) {
-    PredCoef pc = pred_coef(c);
-    k_pred_rhs<<<c->df.nblk, NT, 0, c->stream>>>(c->df, pc, c->a[A_AX], c->a[A_AY], c->a[A_HBX], c->a[A_HBY],
-                                                 c->a[A_DX], c->a[A_DY], c->a[A_UX], c->a[A_UY], c->a[A_P],
-                                                 c->a[A_VDX], c->a[A_VDY], c->a[A_CONVX], c->a[A_CONVY],
-                                                 c->a[A_RHSX], c->a[A_USX], c->prm.rho, c->prm.gx, c->prm.gy,
-                                                 c->conv_valid);
+    PredCoefT<double> pc = pred_coef_t(c);
+    const Layout &L = c->w.L;
+    const int gx = L.pitch / TX, gy = (L.rows + HTY - 1) / HTY;
+    const int nb = ((gx * gy + 7) / 8) * 8;
+    auto k = c->prm.visc_form == 0 ? k_pred_rhs<true> : k_pred_rhs<false>;
+    k<<<nb, NT, 0, c->stream>>>(L.pitch, L.rows, gx, gy, L.n, pc, c->a[A_AX], c->a[A_AY], c->a[A_HBX], c->a[A_HBY],
+                                c->a[A_DX], c->a[A_DY], c->a[A_UX], c->a[A_UY], c->a[A_P], c->a[A_VDX], c->a[A_VDY],
+                                c->a[A_CONVX], c->a[A_CONVY], c->a[A_RHSX], c->a[A_USX], c->prm.rho, c->prm.gx,
+                                c->prm.gy, c->conv_valid);
     c->conv_valid = 1;
 }
 
