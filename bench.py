@@ -46,8 +46,8 @@ PRED_CG_BYTES_PER_CELL = 28 * 8.0
 # Poisson direction+operator (multigrid path): reads z, p_old, 1/diag, c^x,
 # c^y; writes p, A p.
 POIS_DIR_BYTES_PER_CELL = 7 * 8.0
-# Poisson CG update: reads 1/diag, x, p, r, A p; writes x, r.
-POIS_UPDATE_BYTES_PER_CELL = 7 * 8.0
+# Poisson CG update (multigrid path): reads x, p, r, A p; writes x, r.
+POIS_UPDATE_BYTES_PER_CELL = 6 * 8.0
 
 WORKLOADS = {
     "channel_cylinder_2048x1024": W.channel_cylinder_2048,

@@ -283,12 +283,14 @@ __global__ __launch_bounds__(NT) void k_pois_dir(Dims d, PoisCoefT<T> pc, const 
     put_partials<1>(v, pout, d.nblk);
 }
 
-// x += alpha p; r -= alpha q; statistics of the new residual.  Flat over
-// ntot entries (inactive entries hold zeros); each group works on contiguous
+// x += alpha p; r -= alpha q; with STATS, the statistics of the new
+// residual (without: the preconditioner that follows forms them, as the
+// multigrid cycle's last kernel does, and dinv is not read).  Flat over ntot
+// entries (inactive entries hold zeros); each group works on contiguous
 // chunks of UPT*NT entries with every load issued before any arithmetic.
 constexpr int UPT = 4;
 constexpr int UT = 1024;  // threads per work-group of the update (16 wavefronts)
-template <class T>
+template <class T, bool STATS = true>
 __global__ __launch_bounds__(UT) void k_cg_update(size_t ntot, int nblk, const T *__restrict__ dinv,
                                                   T *__restrict__ x, T *__restrict__ r,
                                                   const T *__restrict__ p, const T *__restrict__ q,
@@ -314,7 +316,7 @@ __global__ __launch_bounds__(UT) void k_cg_update(size_t ntot, int nblk, const T
         for (int u = 0; u < UPT; ++u) {
             const size_t k0 = base + (size_t)u * UT + threadIdx.x;
             const size_t k = k0 < ntot ? k0 : ntot - 1;
-            dv[u] = dinv[k];
+            dv[u] = STATS ? dinv[k] : (T)1;
             xv[u] = x[k];
             pv[u] = p[k];
             rv[u] = r[k];
@@ -323,20 +325,24 @@ __global__ __launch_bounds__(UT) void k_cg_update(size_t ntot, int nblk, const T
 #pragma unroll
         for (int u = 0; u < UPT; ++u) {
             const size_t k = base + (size_t)u * UT + threadIdx.x;
+            // without STATS every entry is written: p and q are 0 where
+            // inactive, so x and r keep their values there
             if (k < ntot && dv[u] > (T)0) {
                 x[k] = xv[u] + a * pv[u];
                 const T rn = rv[u] - a * qv[u];
                 r[k] = rn;
-                const T sv = dv[u] * rn;
-                const double rd = rn, sd = sv;
-                v[0] += rd * sd;
-                v[1] += sd;
-                v[2] += rd;
-                v[3] += rd * rd;
+                if (STATS) {
+                    const T sv = dv[u] * rn;
+                    const double rd = rn, sd = sv;
+                    v[0] += rd * sd;
+                    v[1] += sd;
+                    v[2] += rd;
+                    v[3] += rd * rd;
+                }
             }
         }
     }
-    put_partials<4, 0, UT>(v, pout, nblk);
+    if (STATS) put_partials<4, 0, UT>(v, pout, nblk);
 }
 
 // x += dx (float correction of an inner solve) over ntot entries.
@@ -2234,8 +2240,9 @@ ccns_status mg_cg(ccns_ctx *c, std::vector<ccns_ctx::LevelT<T>> &mg, PoisCoefT<T
             launch(c, tm, 0, it, k_pois_dir_z<T>, dim3(dp.nblk), dim3(NT), dp, pc, (const T *)z, (const T *)pb[pbuf],
                    pb[pbuf ^ 1], q, st, it == 0 ? 1 : 0, par, (const double *)c->part[PB_MG], 1, pinit, ninit,
                    c->part[PB_DIR]);
-            launch(c, tm, 1, it, k_cg_update<T>, dim3(nl), dim3(UT), ntot, nl, pc.dinv, x, r, (const T *)pb[pbuf ^ 1],
-                   (const T *)q, st, par, (const double *)c->part[PB_DIR], dp.nblk, c->part[PB_UPD]);
+            launch(c, tm, 1, it, k_cg_update<T, false>, dim3(nl), dim3(UT), ntot, nl, pc.dinv, x, r,
+                   (const T *)pb[pbuf ^ 1], (const T *)q, st, par, (const double *)c->part[PB_DIR], dp.nblk,
+                   c->part[PB_UPD]);
             pbuf ^= 1;
             z = vcycle<T>(c, mg, 0, r, &st->done);
         }
