@@ -363,6 +363,14 @@ __global__ __launch_bounds__(NT) void k_add_correction(size_t ntot, double *__re
 // iteration requires.
 // ---------------------------------------------------------------------------
 
+// Factor on the interpolated coarse correction.  A constant factor keeps the
+// cycle symmetric (pre- and post-smoothing are adjoint and restriction is the
+// transpose of interpolation) and positive definite below 2.  Measured on the
+// 2048x1024 channel: 1.0 needs 10 iterations per step, 0.9 needs 16 and 1.3
+// needs 31 (the coarse operator's half-sum weights already scale the
+// correction as a rediscretisation would).
+constexpr double MG_CGC = 1.0;
+
 // Fused cycle kernels.  Tiles cover the real cells, starting at cell (1, 1)
 // so that every 2x2 group of children that forms a coarse cell lies inside
 // one tile (64 = 32 coarse columns, 16 = 8 coarse rows).  One tile per
@@ -460,8 +468,7 @@ __global__ __launch_bounds__(NT) void k_mg_down_staged(int nx, int ny, int P, in
 template <class T, bool STATS>
 __global__ __launch_bounds__(NT) void k_mg_up_staged(int nx, int ny, int P, int gx, PoisCoefT<T> c, const T *__restrict__ b,
                                               const T *__restrict__ x2, const T *__restrict__ xc, int Pc,
-                                              T *__restrict__ z, T omega, T cgc, double *pout, int nblk,
-                                              const int *done) {
+                                              T *__restrict__ z, T omega, double *pout, int nblk, const int *done) {
     if (*done) return;
     __shared__ T s1[MHt][MW];
     __shared__ T s2[MTY + 2][TX + 2];
@@ -476,7 +483,7 @@ __global__ __launch_bounds__(NT) void k_mg_up_staged(int nx, int ny, int P, int 
             const size_t k = in ? (size_t)j * P + i : 0;
             const size_t kc = in ? (size_t)((j + 1) >> 1) * Pc + ((i + 1) >> 1) : 0;
             const T dv = c.dinv[k], xv = x2[k], ec = xc[kc];
-            s1[ly][lx] = (in && dv > (T)0) ? xv + cgc * ec : (T)0;
+            s1[ly][lx] = (in && dv > (T)0) ? xv + (T)MG_CGC * ec : (T)0;
         }
     }
     __syncthreads();
@@ -620,8 +627,7 @@ __global__ __launch_bounds__(NT) void k_mg_down(int nx, int ny, int P, int gx, P
 template <class T, bool STATS>
 __global__ __launch_bounds__(NT) void k_mg_up(int nx, int ny, int P, int gx, PoisCoefT<T> c, const T *__restrict__ b,
                                               const T *__restrict__ x2, const T *__restrict__ xc, int Pc,
-                                              T *__restrict__ z, T omega, T cgc, double *pout, int nblk,
-                                              const int *done) {
+                                              T *__restrict__ z, T omega, double *pout, int nblk, const int *done) {
     if (*done) return;
     __shared__ T s2[MTY + 2][TX + 2];    // x after the first sweep, on the tile and a one-cell ring
     const MgTile t = mg_tile(gx);
@@ -637,7 +643,7 @@ __global__ __launch_bounds__(NT) void k_mg_up(int nx, int ny, int P, int gx, Poi
             const size_t kk = in ? k : 0;
             const size_t kc = in ? (size_t)((j + 1) >> 1) * Pc + ((i + 1) >> 1) : 0;
             const T dv = c.dinv[kk], xv = x2[kk], ec = xc[kc];
-            return (in && dv > (T)0) ? xv + cgc * ec : (T)0;
+            return (in && dv > (T)0) ? xv + (T)MG_CGC * ec : (T)0;
         };
         for (int e = threadIdx.x; e < (MTY + 2) * (TX + 2); e += NT) {
             const int ly = e / (TX + 2), lx = e - ly * (TX + 2);
@@ -704,7 +710,6 @@ struct TailDesc {
     const int *idx;
     const double *pinv;
     T omega;
-    T cgc;               // factor on the interpolated coarse correction
     const int *done;     // the solve's done flag: nothing to do once set
     int lofs[MAX_TAIL];  // k_mg_tail_lds: offset of each level's arrays in LDS (elements)
     T *out;              // k_mg_tail_lds: where the tail's first level's result goes
@@ -785,7 +790,7 @@ __global__ __launch_bounds__(TT) void k_mg_tail(TailDesc<T> d) {
             const size_t k = (size_t)j * L.P + i;
             const size_t kc = (size_t)((j + 1) >> 1) * C.P + ((i + 1) >> 1);
             const T dv = L.dinv[k], xv = L.x[k], ec = xc[kc];
-            L.xt[k] = dv > (T)0 ? xv + d.cgc * ec : (T)0;
+            L.xt[k] = dv > (T)0 ? xv + (T)MG_CGC * ec : (T)0;
         }
         __syncthreads();
         for (int e = threadIdx.x; e < ncell; e += TT) {
@@ -919,7 +924,7 @@ __global__ __launch_bounds__(TT) void k_mg_tail_lds(TailDesc<T> d) {
             const bool in = (j >= 1) && (j <= L.ny) && (i >= 1) && (i <= L.nx);
             const int k = in ? j * W + i : 0;
             const int kc = in ? ((j + 1) >> 1) * Wc + ((i + 1) >> 1) : 0;
-            return (in && dv[k] > (T)0) ? x[k] + d.cgc * xcs[kc] : (T)0;
+            return (in && dv[k] > (T)0) ? x[k] + (T)MG_CGC * xcs[kc] : (T)0;
         };
         for (int e = threadIdx.x; e < ncell; e += TT) {
             const int j = e / L.nx + 1, i = e % L.nx + 1;
@@ -2025,13 +2030,6 @@ ccns_status pressure_solve_dev(ccns_ctx *c, int nin, ccns_solve_info *info) {
 
 constexpr int MG_NU = 2;          // pre- and post-smoothing sweeps
 constexpr double MG_OMEGA = 0.8;  // weighted-Jacobi damping
-// Factor on the interpolated coarse correction.  A constant factor keeps the
-// cycle symmetric (pre- and post-smoothing are adjoint and restriction is the
-// transpose of interpolation) and positive definite below 2.  Measured on the
-// 2048x1024 channel: 1.0 needs 10 iterations per step, 0.9 needs 16 and 1.3
-// needs 31 (the coarse operator's half-sum weights already scale the
-// correction as a rediscretisation would).
-constexpr double MG_CGC = 1.0;
 
 // Builds the coarse levels on the host from the fine Poisson weights and
 // uploads them (and their float copies in precision 1); the coarsest grid
@@ -2179,7 +2177,6 @@ T *vcycle(ccns_ctx *c, std::vector<ccns_ctx::LevelT<T>> &mg, size_t l, const T *
         d.idx = c->pidx;
         d.pinv = c->pinv;
         d.omega = (T)MG_OMEGA;
-        d.cgc = (T)MG_CGC;
         d.done = done;
         d.out = d.nlev >= 2 ? L.xt : L.x;
         size_t elems = 0;
@@ -2210,11 +2207,11 @@ T *vcycle(ccns_ctx *c, std::vector<ccns_ctx::LevelT<T>> &mg, size_t l, const T *
     const T *xc = vcycle<T>(c, mg, l + 1, C.b, done);
     if (l == 0) {
         k_mg_up_staged<T, true><<<nb, NT, 0, s>>>(L.L.nx, L.L.ny, L.L.pitch, gx, pc, b, L.x, xc, C.L.pitch, L.xt,
-                                                  om, (T)MG_CGC, c->part[PB_UPD], nb, done);
+                                                  om, c->part[PB_UPD], nb, done);
         k_reduce_partials<4><<<1, NT, 0, s>>>(c->part[PB_UPD], nb, c->part[PB_MG]);
     } else {
         k_mg_up<T, false><<<nb, NT, 0, s>>>(L.L.nx, L.L.ny, L.L.pitch, gx, pc, b, L.x, xc, C.L.pitch, L.xt, om,
-                                            (T)MG_CGC, nullptr, nb, done);
+                                            nullptr, nb, done);
     }
     return L.xt;
 }
