@@ -12,6 +12,10 @@ Readings (the paper states the scheme with unit mass matrices and density):
   * Predictor: Jacobi-PCG on H = (rho/tau) M - mu K, K U = visc(strain(U, 0)),
     started from U^n, relative tolerance 1e-12; Poisson: Jacobi-PCG with the
     zero-mean projection, started from Phi^n.
+  * Dirichlet data: eq:pm_prediction carries D at both time levels; with data
+    that change in time (Stepper.step(..., D_next)), convection and the
+    explicit viscous half use D^n, the implicit half, U* on the non-unknown
+    faces and the rest of the step D^{n+1}.
 """
 
 from __future__ import annotations
@@ -75,15 +79,25 @@ class Stepper:
         self.Vu = pr.Mu if pr.Mu is not None else np.where(pr.act_u, c["Vu"], 0.0)
         self.Vv = pr.Mv if pr.Mv is not None else np.where(pr.act_v, c["Vv"], 0.0)
         self.mask2 = np.stack([pr.act_u, pr.act_v])
-        # Dirichlet contribution of the viscous term: visc(strain(U~, D)) with
-        # U~ = D on the non-unknown faces and 0 on unknowns
-        ix, iy = inactive_dirichlet(pr, Dx, Dy)
-        vdx, vdy = ops.viscous(c, ix, iy, Dx, Dy, prm.visc_form)
-        self.vD = np.stack([np.where(pr.act_u, vdx, 0.0), np.where(pr.act_v, vdy, 0.0)])
+        self.vD = self.dirichlet_viscous(Dx, Dy)
         # Jacobi diagonal of H, probed on unit combs
         self.Hdiag = coloured_diagonal(self.apply_H, self.mask2.shape, self.mask2)
         self.Hdinv = np.where(self.mask2 & (self.Hdiag > 0), 1.0 / np.where(self.Hdiag > 0, self.Hdiag, 1.0), 0.0)
         self.Pdinv = np.where(pr.act_p & (pr.diag > 0), 1.0 / np.where(pr.diag > 0, pr.diag, 1.0), 0.0)
+
+    def dirichlet_viscous(self, Dx, Dy):
+        """Dirichlet contribution of the viscous term, visc(strain(U~, D)) with
+        U~ = D on the non-unknown faces and 0 on unknowns."""
+        pr = self.pr
+        ix, iy = inactive_dirichlet(pr, Dx, Dy)
+        vdx, vdy = ops.viscous(pr.caps, ix, iy, Dx, Dy, self.prm.visc_form)
+        return np.stack([np.where(pr.act_u, vdx, 0.0), np.where(pr.act_v, vdy, 0.0)])
+
+    def set_dirichlet(self, Dx, Dy):
+        """Make (Dx, Dy) the current Dirichlet data (time-dependent data: the
+        next time level's, set inside the step)."""
+        self.Dx, self.Dy = Dx, Dy
+        self.vD = self.dirichlet_viscous(Dx, Dy)
 
     # --- linear operators -------------------------------------------------
     def apply_K(self, U2):
@@ -109,22 +123,35 @@ class Stepper:
         cx, cy = ops.conv(self.pr.caps, Ux, Uy, Ux, Uy, self.Dx, self.Dy, self.Dx, self.Dy)
         return np.stack([np.where(self.pr.act_u, cx, 0.0), np.where(self.pr.act_v, cy, 0.0)])
 
-    def predictor_rhs(self, st: State, conv_n, conv_prev):
+    def predictor_rhs(self, st: State, conv_n, conv_prev, vD_next=None):
+        """Right-hand side of eq:pm_prediction.  The explicit half of the
+        viscous term is visc(strain(U^n, D^n)); the implicit half contributes
+        the Dirichlet part of D^{n+1} (vD_next; the current data when D is
+        constant in time)."""
         prm, pr = self.prm, self.pr
+        vD_next = self.vD if vD_next is None else vD_next
         px, py = ops.pres(pr.caps, np.where(pr.act_p, st.P, 0.0))
         vx, vy = ops.viscous(pr.caps, st.Ux, st.Uy, self.Dx, self.Dy, prm.visc_form)
         V2 = np.stack([self.Vu, self.Vv])
         U2 = np.stack([st.Ux, st.Uy])
         g2 = np.stack([np.full_like(self.Vu, prm.gx), np.full_like(self.Vv, prm.gy)])
         rhs = ((prm.rho / prm.tau) * V2 * U2 - 1.5 * prm.rho * conv_n + 0.5 * prm.rho * conv_prev
-               - np.stack([px, py]) + prm.mu * np.stack([vx, vy]) + prm.mu * self.vD
+               - np.stack([px, py]) + prm.mu * np.stack([vx, vy]) + prm.mu * vD_next
                + prm.rho * V2 * g2)
         return np.where(self.mask2, rhs, 0.0)
 
-    def predict(self, st: State, info: StepInfo):
+    def predict(self, st: State, info: StepInfo, D_next=None):
+        """U* of eq:pm_prediction.  With D_next (time-dependent Dirichlet
+        data), convection and the explicit viscous half use the current data
+        D^n, the implicit half and U* on the non-unknown faces D^{n+1}, which
+        becomes the current data for the rest of the step."""
         conv_n = self.convection(st.Ux, st.Uy)
         conv_prev = conv_n if st.conv_prev is None else st.conv_prev
-        rhs = self.predictor_rhs(st, conv_n, conv_prev)
+        vD_next = None if D_next is None else self.dirichlet_viscous(*D_next)
+        rhs = self.predictor_rhs(st, conv_n, conv_prev, vD_next)
+        if D_next is not None:
+            self.Dx, self.Dy = D_next
+            self.vD = vD_next
         U0 = np.stack([st.Ux, st.Uy])
         Us, it, rr, status = pcg(self.apply_H, rhs, U0, self.Hdinv, self.mask2,
                                  self.prm.pred_tol, self.prm.pred_maxit)
@@ -194,9 +221,11 @@ class Stepper:
         st.Ux, st.Uy = self.correct(st.Ux, st.Uy, phi)
         return self.diagnostics(st.Ux, st.Uy, info)
 
-    def step(self, st: State, solver="pcg") -> StepInfo:
+    def step(self, st: State, solver="pcg", D_next=None) -> StepInfo:
+        """One PmII step; D_next: Dirichlet data of the next time level when
+        it changes in time (else the current data holds at both levels)."""
         info = StepInfo()
-        (Usx, Usy), conv_n = self.predict(st, info)
+        (Usx, Usy), conv_n = self.predict(st, info, D_next)
         b = self.poisson_rhs(Usx, Usy)
         phi = self.solve_poisson(b, st.Phi, info, solver=solver)
         Ux, Uy = self.correct(Usx, Usy, phi)
