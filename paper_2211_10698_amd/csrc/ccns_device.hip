@@ -27,6 +27,7 @@
 #include <atomic>
 #include <string>
 #include <thread>
+#include <type_traits>
 #include <vector>
 
 #include "ccns.h"
@@ -1079,14 +1080,23 @@ struct PredTile {
     T sxx[HTY][TX + 1], syy[HTY + 1][TX];
     T snx[HTY + 1][TX + 1], sny[HTY + 1][TX + 1];
 };
+// The same without the cell strains S_xx, which the last phase then forms
+// where it needs them (smaller LDS: one more work-group per compute unit).
+template <class T>
+struct PredTileNx {
+    T spx[HTY + 2][TX + 2], spy[HTY + 2][TX + 2];
+    T syy[HTY + 1][TX];
+    T snx[HTY + 1][TX + 1], sny[HTY + 1][TX + 1];
+};
 
 // The strains of the staged field (rows r0-1 .. r0+HTY, cols c0-1 .. c0+TX
 // staged in spx, spy), formed once per cell and node.  GEO: the node weights
 // are the symmetric geometric form (cross weight = sqrt of the product of the
 // two diagonal ones), so the cross weights are formed instead of read.
-template <class T, bool GEO>
-__device__ inline void pred_tile_strains(PredTile<T> &s, const ViscCoefT<T> &c, int P, int rows, int c0, int r0) {
+template <class T, bool GEO, class Tile = PredTile<T>>
+__device__ inline void pred_tile_strains(Tile &s, const ViscCoefT<T> &c, int P, int rows, int c0, int r0) {
     // S_xx at cells (rows r0.., cols c0 .. c0+TX): x-faces i-1, i
+    if constexpr (!std::is_same<Tile, PredTileNx<T>>::value)
     for (int e = threadIdx.x; e < HTY * (TX + 1); e += NT) {
         const int ly = e / (TX + 1), lx = e - ly * (TX + 1);
         const int j = r0 + ly, i = c0 + lx;
@@ -1132,6 +1142,23 @@ __device__ inline void pred_tile_K(const PredTile<T> &s, const ViscCoefT<T> &c, 
                                    T &ky) {
     const T bxx = c.bxx[k], bxy = c.bxy[k], byy = c.byy[k], byx = c.byx[k];
     kx = bxx * (s.sxx[ly][tx + 1] - s.sxx[ly][tx]) + bxy * (s.snx[ly + 1][tx + 1] - s.snx[ly][tx + 1]);
+    ky = byy * (s.syy[ly + 1][tx] - s.syy[ly][tx]) + byx * (s.sny[ly + 1][tx + 1] - s.sny[ly + 1][tx]);
+}
+
+// K v at tile entry (ly, tx) of a tile without stored S_xx: the two cell
+// strains of the x-face are formed here, with the same operations as in
+// pred_tile_strains.
+template <class T>
+__device__ inline void pred_tile_K(const PredTileNx<T> &s, const ViscCoefT<T> &c, size_t k, int ly, int tx, int i,
+                                   int P, T &kx, T &ky) {
+    const T bxx = c.bxx[k], bxy = c.bxy[k], byy = c.byy[k], byx = c.byx[k];
+    const bool in0 = i >= 1, in1 = i + 1 < P;
+    const size_t k0 = in0 ? k : 1, k1 = in1 ? k + 1 : 1;
+    const T w0 = c.wxx[k0], e0 = c.bxx[k0], b0 = c.bxx[k0 - 1];
+    const T w1 = c.wxx[k1], e1 = c.bxx[k1], b1 = c.bxx[k1 - 1];
+    const T s0 = in0 ? w0 * (e0 * s.spx[ly + 1][tx + 1] - b0 * s.spx[ly + 1][tx]) : (T)0;
+    const T s1 = in1 ? w1 * (e1 * s.spx[ly + 1][tx + 2] - b1 * s.spx[ly + 1][tx + 1]) : (T)0;
+    kx = bxx * (s1 - s0) + bxy * (s.snx[ly + 1][tx + 1] - s.snx[ly][tx + 1]);
     ky = byy * (s.syy[ly + 1][tx] - s.syy[ly][tx]) + byx * (s.sny[ly + 1][tx + 1] - s.sny[ly + 1][tx]);
 }
 
@@ -1212,7 +1239,7 @@ __global__ __launch_bounds__(NT) void k_pred_cg(int P, int rows, int gx, int gy,
         }
         return;
     }
-    __shared__ PredTile<T> s;
+    __shared__ PredTileNx<T> s;
     double v[7] = {0, 0, 0, 0, 0, 0, 0};
     // r' and M^-1 of this thread's tile faces stay in registers for the
     // products of the last phase (rows ty and ty + 4 of the tile)
@@ -1277,7 +1304,7 @@ __global__ __launch_bounds__(NT) void k_pred_cg(int P, int rows, int gx, int gy,
         }
     }
     __syncthreads();
-    if (live) pred_tile_strains<T, GEO>(s, pc.vc, P, rows, c0, r0);
+    if (live) pred_tile_strains<T, GEO, PredTileNx<T>>(s, pc.vc, P, rows, c0, r0);
     __syncthreads();
     if (live) {
         const T rt = (T)pc.rt, mu = (T)pc.mu;
@@ -1291,7 +1318,7 @@ __global__ __launch_bounds__(NT) void k_pred_cg(int P, int rows, int gx, int gy,
             const T rx = rxs[m], ry = rys[m], hx = hxs[m], hy = hys[m];
             const T px = s.spx[ly + 1][tx + 1], py = s.spy[ly + 1][tx + 1];
             T kx, ky;
-            pred_tile_K<T>(s, pc.vc, k, ly, tx, kx, ky);
+            pred_tile_K<T>(s, pc.vc, k, ly, tx, i, P, kx, ky);
             const T qx = vu > (T)0 ? rt * vu * px - mu * kx : (T)0;
             const T qy = vv > (T)0 ? rt * vv * py - mu * ky : (T)0;
             const T pxo = vu > (T)0 ? px : (T)0, pyo = vv > (T)0 ? py : (T)0;
