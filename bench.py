@@ -60,7 +60,7 @@ WORKLOADS = {
 
 # Device helpers whose text a kernel's counter readings also depend on.
 KERNEL_DEPS = {
-    "k_pred_cg": ["ViscCoefT", "PredCoefT", "PredTile", "pred_tile_strains", "pred_tile_K"],
+    "k_pred_cg": ["ViscCoefT", "PredCoefT", "PredTile", "PredTileNx", "pred_tile_strains", "pred_tile_K"],
 }
 
 
@@ -78,11 +78,13 @@ def kernel_digest(name):
         return None
     h = hashlib.sha1(m.group(0).encode())
     for dep in KERNEL_DEPS.get(name, []):
-        d = re.search(r"^(?:template <[^\n]*>\n)?(?:struct " + re.escape(dep) + r"\b|__device__[^\n]*\b"
-                      + re.escape(dep) + r"\().*?^};?$", src, re.S | re.M)
-        if d is None:
+        # every definition of the name (overloads included)
+        ds = list(re.finditer(r"^(?:template <[^\n]*>\n)?(?:struct " + re.escape(dep) + r"\b|__device__[^\n]*\b"
+                              + re.escape(dep) + r"\().*?^};?$", src, re.S | re.M))
+        if not ds:
             return None
-        h.update(d.group(0).encode())
+        for d in ds:
+            h.update(d.group(0).encode())
     h.update(open(KERNEL_HDR, "rb").read())
     return h.hexdigest()
 

@@ -1080,12 +1080,11 @@ struct PredTile {
     T sxx[HTY][TX + 1], syy[HTY + 1][TX];
     T snx[HTY + 1][TX + 1], sny[HTY + 1][TX + 1];
 };
-// The same without the cell strains S_xx, which the last phase then forms
-// where it needs them (smaller LDS: one more work-group per compute unit).
+// The same without the cell strains S_xx and S_yy, which the last phase then
+// forms where it needs them (smaller LDS: more work-groups per compute unit).
 template <class T>
 struct PredTileNx {
     T spx[HTY + 2][TX + 2], spy[HTY + 2][TX + 2];
-    T syy[HTY + 1][TX];
     T snx[HTY + 1][TX + 1], sny[HTY + 1][TX + 1];
 };
 
@@ -1106,6 +1105,7 @@ __device__ inline void pred_tile_strains(Tile &s, const ViscCoefT<T> &c, int P, 
         s.sxx[ly][lx] = in ? w * (be * s.spx[ly + 1][lx + 1] - bw * s.spx[ly + 1][lx]) : (T)0;
     }
     // S_yy at cells (rows r0 .. r0+HTY, cols c0..): y-faces j-1, j
+    if constexpr (!std::is_same<Tile, PredTileNx<T>>::value)
     for (int e = threadIdx.x; e < (HTY + 1) * TX; e += NT) {
         const int ly = e / TX, lx = e - ly * TX;
         const int j = r0 + ly, i = c0 + lx;
@@ -1145,12 +1145,12 @@ __device__ inline void pred_tile_K(const PredTile<T> &s, const ViscCoefT<T> &c, 
     ky = byy * (s.syy[ly + 1][tx] - s.syy[ly][tx]) + byx * (s.sny[ly + 1][tx + 1] - s.sny[ly + 1][tx]);
 }
 
-// K v at tile entry (ly, tx) of a tile without stored S_xx: the two cell
-// strains of the x-face are formed here, with the same operations as in
-// pred_tile_strains.
+// K v at tile entry (ly, tx) of a tile without stored cell strains: the two
+// cell strains S_xx of the x-face and S_yy of the y-face are formed here,
+// with the same operations as in pred_tile_strains.
 template <class T>
 __device__ inline void pred_tile_K(const PredTileNx<T> &s, const ViscCoefT<T> &c, size_t k, int ly, int tx, int i,
-                                   int P, T &kx, T &ky) {
+                                   int P, int rows, T &kx, T &ky) {
     const T bxx = c.bxx[k], bxy = c.bxy[k], byy = c.byy[k], byx = c.byx[k];
     const bool in0 = i >= 1, in1 = i + 1 < P;
     const size_t k0 = in0 ? k : 1, k1 = in1 ? k + 1 : 1;
@@ -1159,7 +1159,15 @@ __device__ inline void pred_tile_K(const PredTileNx<T> &s, const ViscCoefT<T> &c
     const T s0 = in0 ? w0 * (e0 * s.spx[ly + 1][tx + 1] - b0 * s.spx[ly + 1][tx]) : (T)0;
     const T s1 = in1 ? w1 * (e1 * s.spx[ly + 1][tx + 2] - b1 * s.spx[ly + 1][tx + 1]) : (T)0;
     kx = bxx * (s1 - s0) + bxy * (s.snx[ly + 1][tx + 1] - s.snx[ly][tx + 1]);
-    ky = byy * (s.syy[ly + 1][tx] - s.syy[ly][tx]) + byx * (s.sny[ly + 1][tx + 1] - s.sny[ly + 1][tx]);
+    // the y-face's two cell strains S_yy (cells j and j+1 of column i)
+    const int j = (int)(k / (size_t)P);
+    const bool iny0 = j >= 1, iny1 = j + 1 < rows;
+    const size_t q0 = iny0 ? k : (size_t)P, q1 = iny1 ? k + P : (size_t)P;
+    const T wy0 = c.wyy[q0], n0 = c.byy[q0], m0 = c.byy[q0 - P];
+    const T wy1 = c.wyy[q1], n1 = c.byy[q1], m1 = c.byy[q1 - P];
+    const T t0 = iny0 ? wy0 * (n0 * s.spy[ly + 1][tx + 1] - m0 * s.spy[ly][tx + 1]) : (T)0;
+    const T t1 = iny1 ? wy1 * (n1 * s.spy[ly + 2][tx + 1] - m1 * s.spy[ly + 1][tx + 1]) : (T)0;
+    ky = byy * (t1 - t0) + byx * (s.sny[ly + 1][tx + 1] - s.sny[ly + 1][tx]);
 }
 
 // Predictor CG with one launch per iteration (Jacobi-preconditioned CG on
@@ -1180,13 +1188,15 @@ __device__ inline void pred_tile_K(const PredTileNx<T> &s, const ViscCoefT<T> &c
 // statistics (f.f, r.Mr, -, -, r.r) with beta = 0 and no update.  r, p and
 // H p alternate between two buffers (the halo of the old value is read while
 // the new one is written); x is updated in place (tile only).  Launches
-// after the one that stopped return at once (stop_it).
+// after the one that stopped return at once (stop_it).  The tile keeps no
+// cell strains (20 KB of LDS in FP64) and the register budget is set for
+// seven waves per SIMD (70 VGPRs, no spills): the launch is bound by HBM
+// latency, and more resident waves hide more of it.
 template <class T, bool GEO>
-__global__ __launch_bounds__(NT) void k_pred_cg(int P, int rows, int gx, int gy, size_t n, PredCoefT<T> pc,
-                                                CgState *st, int it, T *__restrict__ x, const T *__restrict__ rin,
-                                                T *__restrict__ rout, const T *__restrict__ pold,
-                                                T *__restrict__ pnew, const T *__restrict__ qin,
-                                                T *__restrict__ qout, const double *tin, int nin, double *part) {
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(7))) void k_pred_cg(
+    int P, int rows, int gx, int gy, size_t n, PredCoefT<T> pc, CgState *st, int it, T *__restrict__ x,
+    const T *__restrict__ rin, T *__restrict__ rout, const T *__restrict__ pold, T *__restrict__ pnew,
+    const T *__restrict__ qin, T *__restrict__ qout, const double *tin, int nin, double *part) {
     if (st->stop_it < it) return;
     double fn2, rr, alpha = 0.0, beta = 0.0;
     bool breakdown = false;
@@ -1318,7 +1328,7 @@ __global__ __launch_bounds__(NT) void k_pred_cg(int P, int rows, int gx, int gy,
             const T rx = rxs[m], ry = rys[m], hx = hxs[m], hy = hys[m];
             const T px = s.spx[ly + 1][tx + 1], py = s.spy[ly + 1][tx + 1];
             T kx, ky;
-            pred_tile_K<T>(s, pc.vc, k, ly, tx, i, P, kx, ky);
+            pred_tile_K<T>(s, pc.vc, k, ly, tx, i, P, rows, kx, ky);
             const T qx = vu > (T)0 ? rt * vu * px - mu * kx : (T)0;
             const T qy = vv > (T)0 ? rt * vv * py - mu * ky : (T)0;
             const T pxo = vu > (T)0 ? px : (T)0, pyo = vv > (T)0 ? py : (T)0;
