@@ -378,15 +378,19 @@ constexpr double MG_CGC = 1.0;
 // work-group.  Values needed beyond the tile are recomputed on a one-cell
 // ring (in LDS) instead of being exchanged through a second kernel.
 constexpr int MTY = 16;
+// Tile height of the cycle kernels on the coarser levels that would get
+// fewer than MG_SMALL_GROUPS tiles of height MTY.
+constexpr int MTY_SMALL = 4;
+constexpr int MG_SMALL_GROUPS = 256;
 
 struct MgTile {
     int c0, r0;  // first real cell of the tile
 };
-__device__ inline MgTile mg_tile(int gx) {
+__device__ inline MgTile mg_tile(int gx, int ty = MTY) {
     const int L = logical_group(((gridDim.x + 7) / 8) * 8);
     MgTile t;
     t.c0 = 1 + (L % gx) * TX;
-    t.r0 = 1 + (L / gx) * MTY;
+    t.r0 = 1 + (L / gx) * ty;
     return t;
 }
 
@@ -535,17 +539,16 @@ __global__ __launch_bounds__(NT) void k_mg_up_staged(int nx, int ny, int P, int 
 // weights.  They do not depend on the sweep before, so every thread loads
 // its cells' operands at the start of the kernel and the loads overlap the
 // first phase.
-constexpr int MROWS = MTY / 4;  // tile rows per thread (NT / 64 = 4 row groups)
-template <class T>
+template <class T, int R>
 struct MgCellOps {
-    T d[MROWS], b[MROWS], e[MROWS], w[MROWS], n[MROWS], s[MROWS];
+    T d[R], b[R], e[R], w[R], n[R], s[R];
 };
-template <class T>
-__device__ inline void mg_load_tile_ops(MgCellOps<T> &o, const PoisCoefT<T> &c, const T *b, int nx, int ny, int P,
+template <class T, int R>
+__device__ inline void mg_load_tile_ops(MgCellOps<T, R> &o, const PoisCoefT<T> &c, const T *b, int nx, int ny, int P,
                                         const MgTile &t) {
     const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
 #pragma unroll
-    for (int m = 0; m < MROWS; ++m) {
+    for (int m = 0; m < R; ++m) {
         const int j = t.r0 + ty + 4 * m, i = t.c0 + tx;
         const bool in = (j <= ny) && (i <= nx);
         const size_t k = in ? (size_t)j * P + i : 0;
@@ -562,26 +565,31 @@ __device__ inline void mg_load_tile_ops(MgCellOps<T> &o, const PoisCoefT<T> &c, 
 // restriction: x2 (written to x2out) and b_coarse.  The first sweep from
 // zero is pointwise (x1 = omega D^-1 b), so it is formed at the five points
 // of the second sweep's stencil instead of being staged: two phases with one
-// barrier between the sweeps and the residual.
-template <class T>
+// barrier between the sweeps and the residual.  Tiles of TX x TY cells: TY =
+// MTY, or MTY_SMALL on levels too small to give every compute unit a tile
+// (there each work-group's serial chain of loads is what the launch waits
+// for, and shorter tiles shorten it).
+template <class T, int TY = MTY>
 __global__ __launch_bounds__(NT) void k_mg_down(int nx, int ny, int P, int gx, PoisCoefT<T> c,
                                                 const T *__restrict__ b, T *__restrict__ x2out,
                                                 int Pc, int nxc, int nyc, const T *__restrict__ dinvc,
                                                 T *__restrict__ bc, T omega, const int *done) {
     if (*done) return;
-    __shared__ T s2[MTY + 2][TX + 2];    // x after two sweeps, on the tile and a one-cell ring
-    __shared__ T sr[MTY][TX];            // residual on the tile
-    const MgTile t = mg_tile(gx);
+    static_assert(TY % 4 == 0 && TY <= MTY, "tile rows: a multiple of the 4 row groups, at most MTY");
+    __shared__ T s2[TY + 2][TX + 2];    // x after two sweeps, on the tile and a one-cell ring
+    __shared__ T sr[TY][TX];            // residual on the tile
+    const MgTile t = mg_tile(gx, TY);
     if (t.r0 > ny || t.c0 > nx) return;
-    MgCellOps<T> o;
-    mg_load_tile_ops<T>(o, c, b, nx, ny, P, t);
-    // one coarse cell per thread for the restriction: 32 x 8 coarse cells per tile
+    MgCellOps<T, TY / 4> o;
+    mg_load_tile_ops<T, TY / 4>(o, c, b, nx, ny, P, t);
+    // one coarse cell per thread for the restriction: 32 x (TY / 2) coarse
+    // cells per tile
     const int cxl = threadIdx.x & 31, cyl = threadIdx.x >> 5;
     const int I = (t.c0 + 1) / 2 + cxl, J = (t.r0 + 1) / 2 + cyl;
-    const bool cin = (I <= nxc) && (J <= nyc);
+    const bool cin = (cyl < TY / 2) && (I <= nxc) && (J <= nyc);
     const size_t kc = cin ? (size_t)J * Pc + I : 0;
     const T dcv = dinvc[kc];
-    for (int e = threadIdx.x; e < (MTY + 2) * (TX + 2); e += NT) {
+    for (int e = threadIdx.x; e < (TY + 2) * (TX + 2); e += NT) {
         const int ly = e / (TX + 2), lx = e - ly * (TX + 2);
         const int j = t.r0 - 1 + ly, i = t.c0 - 1 + lx;
         const bool in = (j >= 1) && (j <= ny) && (i >= 1) && (i <= nx);
@@ -601,7 +609,7 @@ __global__ __launch_bounds__(NT) void k_mg_down(int nx, int ny, int P, int gx, P
     {
         const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
 #pragma unroll
-        for (int m = 0; m < MROWS; ++m) {
+        for (int m = 0; m < TY / 4; ++m) {
             const int ly = ty + 4 * m;
             const int j = t.r0 + ly, i = t.c0 + tx;
             const bool in = (j <= ny) && (i <= nx);
@@ -625,18 +633,20 @@ __global__ __launch_bounds__(NT) void k_mg_down(int nx, int ny, int P, int gx, P
 // sweeps: z.  With STATS, partials of (b.z, z, b, b.b).  The interpolated
 // start value is pointwise, so it is formed at the five points of the first
 // sweep's stencil instead of being staged: one barrier, between the sweeps.
-template <class T, bool STATS>
+// Tiles of TX x TY cells, as in k_mg_down.
+template <class T, bool STATS, int TY = MTY>
 __global__ __launch_bounds__(NT) void k_mg_up(int nx, int ny, int P, int gx, PoisCoefT<T> c, const T *__restrict__ b,
                                               const T *__restrict__ x2, const T *__restrict__ xc, int Pc,
                                               T *__restrict__ z, T omega, double *pout, int nblk, const int *done) {
     if (*done) return;
-    __shared__ T s2[MTY + 2][TX + 2];    // x after the first sweep, on the tile and a one-cell ring
-    const MgTile t = mg_tile(gx);
+    static_assert(TY % 4 == 0 && TY <= MTY, "tile rows: a multiple of the 4 row groups, at most MTY");
+    __shared__ T s2[TY + 2][TX + 2];    // x after the first sweep, on the tile and a one-cell ring
+    const MgTile t = mg_tile(gx, TY);
     double v[4] = {0, 0, 0, 0};
     const bool live = !(t.r0 > ny || t.c0 > nx);
-    MgCellOps<T> o;
+    MgCellOps<T, TY / 4> o;
     if (live) {
-        mg_load_tile_ops<T>(o, c, b, nx, ny, P, t);
+        mg_load_tile_ops<T, TY / 4>(o, c, b, nx, ny, P, t);
         // start value x2 + interpolated correction at cell (j, i): 0 outside
         // the real cells and at inactive ones
         auto start = [&](int j, int i, size_t k) -> T {
@@ -646,7 +656,7 @@ __global__ __launch_bounds__(NT) void k_mg_up(int nx, int ny, int P, int gx, Poi
             const T dv = c.dinv[kk], xv = x2[kk], ec = xc[kc];
             return (in && dv > (T)0) ? xv + (T)MG_CGC * ec : (T)0;
         };
-        for (int e = threadIdx.x; e < (MTY + 2) * (TX + 2); e += NT) {
+        for (int e = threadIdx.x; e < (TY + 2) * (TX + 2); e += NT) {
             const int ly = e / (TX + 2), lx = e - ly * (TX + 2);
             const int j = t.r0 - 1 + ly, i = t.c0 - 1 + lx;
             const bool in = (j >= 1) && (j <= ny) && (i >= 1) && (i <= nx);
@@ -665,7 +675,7 @@ __global__ __launch_bounds__(NT) void k_mg_up(int nx, int ny, int P, int gx, Poi
     if (live) {
         const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
 #pragma unroll
-        for (int m = 0; m < MROWS; ++m) {
+        for (int m = 0; m < TY / 4; ++m) {
             const int ly = ty + 4 * m;
             const int j = t.r0 + ly, i = t.c0 + tx;
             const bool in = (j <= ny) && (i <= nx);
@@ -2228,7 +2238,12 @@ T *vcycle(ccns_ctx *c, std::vector<ccns_ctx::LevelT<T>> &mg, size_t l, const T *
         return d.out;
     }
     PoisCoefT<T> pc{L.cx, L.cy, L.dinv};
-    const int gx = (L.L.nx + TX - 1) / TX, gy = (L.L.ny + MTY - 1) / MTY;
+    const int gx = (L.L.nx + TX - 1) / TX;
+    // below the finest level, short tiles where tall ones would leave compute
+    // units idle
+    const bool small = l >= 1 && gx * ((L.L.ny + MTY - 1) / MTY) < MG_SMALL_GROUPS;
+    const int ty = small ? MTY_SMALL : MTY;
+    const int gy = (L.L.ny + ty - 1) / ty;
     const int nb = ((gx * gy + 7) / 8) * 8;
     ccns_ctx::LevelT<T> &C = mg[l + 1];
     const T om = (T)MG_OMEGA;
@@ -2238,6 +2253,9 @@ T *vcycle(ccns_ctx *c, std::vector<ccns_ctx::LevelT<T>> &mg, size_t l, const T *
     if (l == 0 && sizeof(T) == 8)
         k_mg_down_staged<T><<<nb, NT, 0, s>>>(L.L.nx, L.L.ny, L.L.pitch, gx, pc, b, L.x, C.L.pitch, C.L.nx, C.L.ny,
                                               C.dinv, C.b, om, done);
+    else if (small)
+        k_mg_down<T, MTY_SMALL><<<nb, NT, 0, s>>>(L.L.nx, L.L.ny, L.L.pitch, gx, pc, b, L.x, C.L.pitch, C.L.nx,
+                                                  C.L.ny, C.dinv, C.b, om, done);
     else
         k_mg_down<T><<<nb, NT, 0, s>>>(L.L.nx, L.L.ny, L.L.pitch, gx, pc, b, L.x, C.L.pitch, C.L.nx, C.L.ny,
                                        C.dinv, C.b, om, done);
@@ -2246,6 +2264,9 @@ T *vcycle(ccns_ctx *c, std::vector<ccns_ctx::LevelT<T>> &mg, size_t l, const T *
         k_mg_up_staged<T, true><<<nb, NT, 0, s>>>(L.L.nx, L.L.ny, L.L.pitch, gx, pc, b, L.x, xc, C.L.pitch, L.xt,
                                                   om, c->part[PB_UPD], nb, done);
         k_reduce_partials<4><<<1, NT, 0, s>>>(c->part[PB_UPD], nb, c->part[PB_MG]);
+    } else if (small) {
+        k_mg_up<T, false, MTY_SMALL><<<nb, NT, 0, s>>>(L.L.nx, L.L.ny, L.L.pitch, gx, pc, b, L.x, xc, C.L.pitch,
+                                                       L.xt, om, nullptr, nb, done);
     } else {
         k_mg_up<T, false><<<nb, NT, 0, s>>>(L.L.nx, L.L.ny, L.L.pitch, gx, pc, b, L.x, xc, C.L.pitch, L.xt, om,
                                             nullptr, nb, done);
