@@ -402,138 +402,6 @@ __device__ inline MgTile mg_tile(int gx, int ty = MTY) {
 constexpr int MH = 2;  // halo width of the staged first sweep
 constexpr int MW = TX + 2 * MH, MHt = MTY + 2 * MH;
 
-// Two weighted-Jacobi sweeps from a zero guess, the residual, and its
-// restriction: x2 (written to x2out) and b_coarse.
-template <class T>
-__global__ __launch_bounds__(NT) void k_mg_down_staged(int nx, int ny, int P, int gx, PoisCoefT<T> c,
-                                                const T *__restrict__ b, T *__restrict__ x2out,
-                                                int Pc, int nxc, int nyc, const T *__restrict__ dinvc,
-                                                T *__restrict__ bc, T omega, const int *done) {
-    if (*done) return;
-    __shared__ T s1[MHt][MW];            // first sweep on the 2-ring region
-    __shared__ T s2[MTY + 2][TX + 2];    // second sweep on the 1-ring region
-    __shared__ T sr[MTY][TX];            // residual on the tile
-    const MgTile t = mg_tile(gx);
-    if (t.r0 > ny || t.c0 > nx) return;
-    for (int e = threadIdx.x; e < MHt * MW; e += NT) {
-        const int ly = e / MW, lx = e - ly * MW;
-        const int j = t.r0 - MH + ly, i = t.c0 - MH + lx;
-        const bool in = (j >= 0) && (j <= ny + 1) && (i >= 0) && (i <= nx + 1);
-        const size_t k = in ? (size_t)j * P + i : 0;
-        const T dv = c.dinv[k], bv = b[k];
-        s1[ly][lx] = (in && dv > (T)0) ? omega * dv * bv : (T)0;
-    }
-    __syncthreads();
-    for (int e = threadIdx.x; e < (MTY + 2) * (TX + 2); e += NT) {
-        const int ly = e / (TX + 2), lx = e - ly * (TX + 2);
-        const int j = t.r0 - 1 + ly, i = t.c0 - 1 + lx;
-        const bool in = (j >= 1) && (j <= ny) && (i >= 1) && (i <= nx);
-        const size_t k = in ? (size_t)j * P + i : 0;
-        const T dv = c.dinv[k], bv = b[k];
-        const T ce = c.cx[k], cw = c.cx[in ? k - 1 : 0], cn = c.cy[k], cs = c.cy[in ? k - P : 0];
-        const int y = ly + 1, x = lx + 1;  // position in s1
-        const T xv = s1[y][x];
-        const T Ax = (ce + cw + cn + cs) * xv - ce * s1[y][x + 1] - cw * s1[y][x - 1] - cn * s1[y + 1][x] -
-                          cs * s1[y - 1][x];
-        s2[ly][lx] = (in && dv > (T)0) ? xv + omega * dv * (bv - Ax) : (T)0;
-    }
-    __syncthreads();
-    {
-        const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-        for (int ly = ty; ly < MTY; ly += 4) {
-            const int j = t.r0 + ly, i = t.c0 + tx;
-            const bool in = (j <= ny) && (i <= nx);
-            const size_t k = in ? (size_t)j * P + i : 0;
-            const T dv = c.dinv[k], bv = b[k];
-            const T ce = c.cx[k], cw = c.cx[in ? k - 1 : 0], cn = c.cy[k], cs = c.cy[in ? k - P : 0];
-            const int y = ly + 1, x = tx + 1;
-            const T xv = s2[y][x];
-            const T Ax = (ce + cw + cn + cs) * xv - ce * s2[y][x + 1] - cw * s2[y][x - 1] - cn * s2[y + 1][x] -
-                              cs * s2[y - 1][x];
-            sr[ly][tx] = (in && dv > (T)0) ? bv - Ax : (T)0;
-            if (in) x2out[k] = xv;
-        }
-    }
-    __syncthreads();
-    {
-        // one coarse cell per thread: 32 x 8 coarse cells per tile
-        const int cxl = threadIdx.x & 31, cyl = threadIdx.x >> 5;
-        const int I = (t.c0 + 1) / 2 + cxl, J = (t.r0 + 1) / 2 + cyl;
-        if (I <= nxc && J <= nyc) {
-            const T sum = (sr[2 * cyl][2 * cxl] + sr[2 * cyl][2 * cxl + 1]) +
-                               (sr[2 * cyl + 1][2 * cxl] + sr[2 * cyl + 1][2 * cxl + 1]);
-            const size_t kc = (size_t)J * Pc + I;
-            bc[kc] = dinvc[kc] > (T)0 ? sum : (T)0;
-        }
-    }
-}
-
-// The coarse correction interpolated onto x2, then two weighted-Jacobi
-// sweeps: z.  With STATS, partials of (b.z, z, b, b.b).
-template <class T, bool STATS>
-__global__ __launch_bounds__(NT) void k_mg_up_staged(int nx, int ny, int P, int gx, PoisCoefT<T> c, const T *__restrict__ b,
-                                              const T *__restrict__ x2, const T *__restrict__ xc, int Pc,
-                                              T *__restrict__ z, T omega, double *pout, int nblk, const int *done) {
-    if (*done) return;
-    __shared__ T s1[MHt][MW];
-    __shared__ T s2[MTY + 2][TX + 2];
-    const MgTile t = mg_tile(gx);
-    double v[4] = {0, 0, 0, 0};
-    const bool live = !(t.r0 > ny || t.c0 > nx);
-    if (live) {
-        for (int e = threadIdx.x; e < MHt * MW; e += NT) {
-            const int ly = e / MW, lx = e - ly * MW;
-            const int j = t.r0 - MH + ly, i = t.c0 - MH + lx;
-            const bool in = (j >= 1) && (j <= ny) && (i >= 1) && (i <= nx);
-            const size_t k = in ? (size_t)j * P + i : 0;
-            const size_t kc = in ? (size_t)((j + 1) >> 1) * Pc + ((i + 1) >> 1) : 0;
-            const T dv = c.dinv[k], xv = x2[k], ec = xc[kc];
-            s1[ly][lx] = (in && dv > (T)0) ? xv + (T)MG_CGC * ec : (T)0;
-        }
-    }
-    __syncthreads();
-    if (live) {
-        for (int e = threadIdx.x; e < (MTY + 2) * (TX + 2); e += NT) {
-            const int ly = e / (TX + 2), lx = e - ly * (TX + 2);
-            const int j = t.r0 - 1 + ly, i = t.c0 - 1 + lx;
-            const bool in = (j >= 1) && (j <= ny) && (i >= 1) && (i <= nx);
-            const size_t k = in ? (size_t)j * P + i : 0;
-            const T dv = c.dinv[k], bv = b[k];
-            const T ce = c.cx[k], cw = c.cx[in ? k - 1 : 0], cn = c.cy[k], cs = c.cy[in ? k - P : 0];
-            const int y = ly + 1, x = lx + 1;
-            const T xv = s1[y][x];
-            const T Ax = (ce + cw + cn + cs) * xv - ce * s1[y][x + 1] - cw * s1[y][x - 1] - cn * s1[y + 1][x] -
-                              cs * s1[y - 1][x];
-            s2[ly][lx] = (in && dv > (T)0) ? xv + omega * dv * (bv - Ax) : (T)0;
-        }
-    }
-    __syncthreads();
-    if (live) {
-        const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-        for (int ly = ty; ly < MTY; ly += 4) {
-            const int j = t.r0 + ly, i = t.c0 + tx;
-            const bool in = (j <= ny) && (i <= nx);
-            const size_t k = in ? (size_t)j * P + i : 0;
-            const T dv = c.dinv[k], bv = b[k];
-            const T ce = c.cx[k], cw = c.cx[in ? k - 1 : 0], cn = c.cy[k], cs = c.cy[in ? k - P : 0];
-            const int y = ly + 1, x = tx + 1;
-            const T xv = s2[y][x];
-            const T Ax = (ce + cw + cn + cs) * xv - ce * s2[y][x + 1] - cw * s2[y][x - 1] - cn * s2[y + 1][x] -
-                              cs * s2[y - 1][x];
-            const T zv = (in && dv > (T)0) ? xv + omega * dv * (bv - Ax) : (T)0;
-            if (in) z[k] = zv;
-            if (STATS && in) {
-                const double bd = bv, zd = zv;
-                v[0] += bd * zd;
-                v[1] += zd;
-                v[2] += bd;
-                v[3] += bd * bd;
-            }
-        }
-    }
-    if (STATS) put_partials<4>(v, pout, nblk);
-}
-
 // Stencil operands of one cell of the tile phase (the residual of k_mg_down,
 // the last sweep of k_mg_up): 1/diag, right-hand side and the four face
 // weights.  They do not depend on the sweep before, so every thread loads
@@ -559,6 +427,202 @@ __device__ inline void mg_load_tile_ops(MgCellOps<T, R> &o, const PoisCoefT<T> &
         o.n[m] = c.cy[k];
         o.s[m] = c.cy[in ? k - P : 0];
     }
+}
+
+// Every phase of these kernels issues all of its thread's loads before the
+// first use (the loop over the phase's cells is unrolled into a loop of loads
+// and a loop of arithmetic), and the loads of the next phase are issued
+// before the barrier that ends this one: a work-group then waits for one
+// memory round trip per phase instead of one per cell it handles.
+constexpr int MS1 = MHt * MW, MI1 = (MS1 + NT - 1) / NT;                  // 2-ring region
+constexpr int MS2 = (MTY + 2) * (TX + 2), MI2 = (MS2 + NT - 1) / NT;      // 1-ring region
+template <class T>
+struct MgRingOps {
+    T d[MI2], b[MI2], e[MI2], w[MI2], n[MI2], s[MI2];
+};
+// Operands of the 1-ring region's cells (entry q of this thread: cell e =
+// threadIdx.x + q NT of the (MTY+2) x (TX+2) region).
+template <class T>
+__device__ inline void mg_load_ring_ops(MgRingOps<T> &o, const PoisCoefT<T> &c, const T *b, int nx, int ny, int P,
+                                        const MgTile &t) {
+#pragma unroll
+    for (int q = 0; q < MI2; ++q) {
+        const int e = threadIdx.x + q * NT;
+        const int ly = e / (TX + 2), lx = e - ly * (TX + 2);
+        const int j = t.r0 - 1 + ly, i = t.c0 - 1 + lx;
+        const bool in = (e < MS2) && (j >= 1) && (j <= ny) && (i >= 1) && (i <= nx);
+        const size_t k = in ? (size_t)j * P + i : 0;
+        o.d[q] = c.dinv[k];
+        o.b[q] = b[k];
+        o.e[q] = c.cx[k];
+        o.w[q] = c.cx[in ? k - 1 : 0];
+        o.n[q] = c.cy[k];
+        o.s[q] = c.cy[in ? k - P : 0];
+    }
+}
+// The sweep x' = x + omega D^-1 (b - A x) on the 1-ring region, x read from
+// the 2-ring array s1, written to the 1-ring array s2.
+template <class T>
+__device__ inline void mg_ring_sweep(const MgRingOps<T> &o, const T (*s1)[MW], T (*s2)[TX + 2], int nx, int ny,
+                                     const MgTile &t, T omega) {
+#pragma unroll
+    for (int q = 0; q < MI2; ++q) {
+        const int e = threadIdx.x + q * NT;
+        if (e < MS2) {
+            const int ly = e / (TX + 2), lx = e - ly * (TX + 2);
+            const int j = t.r0 - 1 + ly, i = t.c0 - 1 + lx;
+            const bool in = (j >= 1) && (j <= ny) && (i >= 1) && (i <= nx);
+            const T ce = o.e[q], cw = o.w[q], cn = o.n[q], cs = o.s[q], dv = o.d[q];
+            const int y = ly + 1, x = lx + 1;  // position in s1
+            const T xv = s1[y][x];
+            const T Ax = (ce + cw + cn + cs) * xv - ce * s1[y][x + 1] - cw * s1[y][x - 1] - cn * s1[y + 1][x] -
+                         cs * s1[y - 1][x];
+            s2[ly][lx] = (in && dv > (T)0) ? xv + omega * dv * (o.b[q] - Ax) : (T)0;
+        }
+    }
+}
+
+// Two weighted-Jacobi sweeps from a zero guess, the residual, and its
+// restriction: x2 (written to x2out) and b_coarse.
+template <class T>
+__global__ __launch_bounds__(NT) void k_mg_down_staged(int nx, int ny, int P, int gx, PoisCoefT<T> c,
+                                                const T *__restrict__ b, T *__restrict__ x2out,
+                                                int Pc, int nxc, int nyc, const T *__restrict__ dinvc,
+                                                T *__restrict__ bc, T omega, const int *done) {
+    if (*done) return;
+    __shared__ T s1[MHt][MW];            // first sweep on the 2-ring region
+    __shared__ T s2[MTY + 2][TX + 2];    // second sweep on the 1-ring region
+    __shared__ T sr[MTY][TX];            // residual on the tile
+    const MgTile t = mg_tile(gx);
+    if (t.r0 > ny || t.c0 > nx) return;
+    {
+        T dv[MI1], bv[MI1];
+#pragma unroll
+        for (int q = 0; q < MI1; ++q) {
+            const int e = threadIdx.x + q * NT;
+            const int ly = e / MW, lx = e - ly * MW;
+            const int j = t.r0 - MH + ly, i = t.c0 - MH + lx;
+            const bool in = (e < MS1) && (j >= 0) && (j <= ny + 1) && (i >= 0) && (i <= nx + 1);
+            const size_t k = in ? (size_t)j * P + i : 0;
+            dv[q] = c.dinv[k];
+            bv[q] = b[k];
+        }
+#pragma unroll
+        for (int q = 0; q < MI1; ++q) {
+            const int e = threadIdx.x + q * NT;
+            if (e < MS1) {
+                const int ly = e / MW, lx = e - ly * MW;
+                const int j = t.r0 - MH + ly, i = t.c0 - MH + lx;
+                const bool in = (j >= 0) && (j <= ny + 1) && (i >= 0) && (i <= nx + 1);
+                s1[ly][lx] = (in && dv[q] > (T)0) ? omega * dv[q] * bv[q] : (T)0;
+            }
+        }
+    }
+    MgRingOps<T> ro;
+    mg_load_ring_ops<T>(ro, c, b, nx, ny, P, t);
+    __syncthreads();
+    mg_ring_sweep<T>(ro, s1, s2, nx, ny, t, omega);
+    MgCellOps<T, MTY / 4> o;
+    mg_load_tile_ops<T, MTY / 4>(o, c, b, nx, ny, P, t);
+    // one coarse cell per thread for the restriction: 32 x 8 coarse cells per tile
+    const int cxl = threadIdx.x & 31, cyl = threadIdx.x >> 5;
+    const int I = (t.c0 + 1) / 2 + cxl, J = (t.r0 + 1) / 2 + cyl;
+    const bool cin = (I <= nxc) && (J <= nyc);
+    const size_t kc = cin ? (size_t)J * Pc + I : 0;
+    const T dcv = dinvc[kc];
+    __syncthreads();
+    {
+        const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+#pragma unroll
+        for (int m = 0; m < MTY / 4; ++m) {
+            const int ly = ty + 4 * m;
+            const int j = t.r0 + ly, i = t.c0 + tx;
+            const bool in = (j <= ny) && (i <= nx);
+            const int y = ly + 1, x = tx + 1;
+            const T xv = s2[y][x];
+            const T Ax = (o.e[m] + o.w[m] + o.n[m] + o.s[m]) * xv - o.e[m] * s2[y][x + 1] -
+                         o.w[m] * s2[y][x - 1] - o.n[m] * s2[y + 1][x] - o.s[m] * s2[y - 1][x];
+            sr[ly][tx] = (in && o.d[m] > (T)0) ? o.b[m] - Ax : (T)0;
+            if (in) x2out[(size_t)j * P + i] = xv;
+        }
+    }
+    __syncthreads();
+    if (cin) {
+        const T sum = (sr[2 * cyl][2 * cxl] + sr[2 * cyl][2 * cxl + 1]) +
+                      (sr[2 * cyl + 1][2 * cxl] + sr[2 * cyl + 1][2 * cxl + 1]);
+        bc[kc] = dcv > (T)0 ? sum : (T)0;
+    }
+}
+
+// The coarse correction interpolated onto x2, then two weighted-Jacobi
+// sweeps: z.  With STATS, partials of (b.z, z, b, b.b).
+template <class T, bool STATS>
+__global__ __launch_bounds__(NT) void k_mg_up_staged(int nx, int ny, int P, int gx, PoisCoefT<T> c, const T *__restrict__ b,
+                                              const T *__restrict__ x2, const T *__restrict__ xc, int Pc,
+                                              T *__restrict__ z, T omega, double *pout, int nblk, const int *done) {
+    if (*done) return;
+    __shared__ T s1[MHt][MW];
+    __shared__ T s2[MTY + 2][TX + 2];
+    const MgTile t = mg_tile(gx);
+    double v[4] = {0, 0, 0, 0};
+    const bool live = !(t.r0 > ny || t.c0 > nx);
+    MgCellOps<T, MTY / 4> o;
+    if (live) {
+        T dv[MI1], xv[MI1], ec[MI1];
+#pragma unroll
+        for (int q = 0; q < MI1; ++q) {
+            const int e = threadIdx.x + q * NT;
+            const int ly = e / MW, lx = e - ly * MW;
+            const int j = t.r0 - MH + ly, i = t.c0 - MH + lx;
+            const bool in = (e < MS1) && (j >= 1) && (j <= ny) && (i >= 1) && (i <= nx);
+            const size_t k = in ? (size_t)j * P + i : 0;
+            const size_t kc = in ? (size_t)((j + 1) >> 1) * Pc + ((i + 1) >> 1) : 0;
+            dv[q] = c.dinv[k];
+            xv[q] = x2[k];
+            ec[q] = xc[kc];
+        }
+#pragma unroll
+        for (int q = 0; q < MI1; ++q) {
+            const int e = threadIdx.x + q * NT;
+            if (e < MS1) {
+                const int ly = e / MW, lx = e - ly * MW;
+                const int j = t.r0 - MH + ly, i = t.c0 - MH + lx;
+                const bool in = (j >= 1) && (j <= ny) && (i >= 1) && (i <= nx);
+                s1[ly][lx] = (in && dv[q] > (T)0) ? xv[q] + (T)MG_CGC * ec[q] : (T)0;
+            }
+        }
+        MgRingOps<T> ro;
+        mg_load_ring_ops<T>(ro, c, b, nx, ny, P, t);
+        __syncthreads();
+        mg_ring_sweep<T>(ro, s1, s2, nx, ny, t, omega);
+        mg_load_tile_ops<T, MTY / 4>(o, c, b, nx, ny, P, t);
+    } else {
+        __syncthreads();
+    }
+    __syncthreads();
+    if (live) {
+        const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+#pragma unroll
+        for (int m = 0; m < MTY / 4; ++m) {
+            const int ly = ty + 4 * m;
+            const int j = t.r0 + ly, i = t.c0 + tx;
+            const bool in = (j <= ny) && (i <= nx);
+            const int y = ly + 1, x = tx + 1;
+            const T xv = s2[y][x];
+            const T Ax = (o.e[m] + o.w[m] + o.n[m] + o.s[m]) * xv - o.e[m] * s2[y][x + 1] -
+                         o.w[m] * s2[y][x - 1] - o.n[m] * s2[y + 1][x] - o.s[m] * s2[y - 1][x];
+            const T zv = (in && o.d[m] > (T)0) ? xv + omega * o.d[m] * (o.b[m] - Ax) : (T)0;
+            if (in) z[(size_t)j * P + i] = zv;
+            if (STATS && in) {
+                const double bd = o.b[m], zd = zv;
+                v[0] += bd * zd;
+                v[1] += zd;
+                v[2] += bd;
+                v[3] += bd * bd;
+            }
+        }
+    }
+    if (STATS) put_partials<4>(v, pout, nblk);
 }
 
 // Two weighted-Jacobi sweeps from a zero guess, the residual, and its
