@@ -42,7 +42,12 @@ KERNEL_HDR = os.path.join(ROOT, "paper_2211_10698_amd", "csrc", "ccns_kern.h")
 # each), M^x, M^y, B^xx, B^xy, B^yy, B^yx, 1/W^xx, 1/W^yy and the two diagonal
 # node weights (the cross weight of the symmetric form is their geometric
 # mean, formed in the kernel); writes r, x, p and H p (2 each).
-PRED_CG_BYTES_PER_CELL = 28 * 8.0
+PRED_CG_VALUES_PER_CELL = 28
+# The same kernel reading its coefficients through the class table: the 12
+# coefficient values become one 4-byte class index per entry (the table rows
+# are shared by every entry of a class and stay in cache).
+PRED_CG_VALUES_PER_CELL_CLS = 16
+PRED_CG_INDEX_BYTES = 4.0
 # Poisson direction+operator (multigrid path): reads z, p_old, 1/diag, c^x,
 # c^y; writes p, A p.
 POIS_DIR_BYTES_PER_CELL = 7 * 8.0
@@ -60,7 +65,8 @@ WORKLOADS = {
 
 # Device helpers whose text a kernel's counter readings also depend on.
 KERNEL_DEPS = {
-    "k_pred_cg": ["ViscCoefT", "PredCoefT", "PredTile", "PredTileNx", "pred_tile_strains", "pred_tile_K"],
+    "k_pred_cg": ["ViscCoefT", "PredCoefT", "PredTile", "PredTileNx", "pred_tile_strains", "pred_tile_K",
+                  "pred_tile_K_row"],
 }
 
 
@@ -89,19 +95,21 @@ def kernel_digest(name):
     return h.hexdigest()
 
 
-def stored_traffic(name, workload):
+def stored_traffic(name, workload, classes):
     """HBM bytes per launch of `name` from the committed counter summary, or
-    None when there is none for this workload or the kernel has changed."""
+    None when there is none for this workload and coefficient path, or the
+    kernel has changed."""
     try:
         t = json.load(open(TRAFFIC_FILE)).get(name)
     except (OSError, ValueError):
         return None
-    if not t or t.get("workload") != workload or t.get("kernel_sha1") != kernel_digest(name):
+    if (not t or t.get("workload") != workload or t.get("kernel_sha1") != kernel_digest(name)
+            or t.get("coef_classes", False) != classes):
         return None
     return t["bytes_per_launch"]
 
 
-def summarize_counters(root, kernel, workload):
+def summarize_counters(root, kernel, workload, classes):
     """Turns four rocprofv3 --pmc runs into the stored traffic figure:
     root/fetch and root/write hold FETCH_SIZE and WRITE_SIZE of the bench
     run, root/cfetch and root/cwrite the same counters over the plain copies
@@ -128,7 +136,8 @@ def summarize_counters(root, kernel, workload):
     fk, nf = med("fetch", kernel, "FETCH_SIZE")
     wk, nw = med("write", kernel, "WRITE_SIZE")
     sf, sw = copy_kib / cf, copy_kib / cw
-    rec = {"workload": workload, "kernel_sha1": kernel_digest(kernel), "fetch_kib": fk, "write_kib": wk,
+    rec = {"workload": workload, "coef_classes": classes, "kernel_sha1": kernel_digest(kernel),
+           "fetch_kib": fk, "write_kib": wk,
            "launches": [nf, nw], "copy_fetch_kib": cf, "copy_write_kib": cw, "fetch_scale": sf,
            "write_scale": sw, "bytes_per_launch": (fk * sf + wk * sw) * 1024.0}
     try:
@@ -220,12 +229,13 @@ def host_inputs(ccns, case):
     return caps, Dx, Dy, np.where(au, case.u_inf + px, Dx), np.where(av, py, Dy)
 
 
-def setup_context(ccns, case, precision, stream, host):
+def setup_context(ccns, case, precision, stream, host, coef_tables=0):
     """Context, initial field and initial projection of one simulation (set-up,
     outside any timed region)."""
     caps, Dx, Dy, ux0, uy0 = host
     params = ccns.make_params(case.rho, case.mu, case.tau, u_ref=case.u_inf, pcg_tol=case.pcg_tol,
-                              pred_tol=1e-12, precision=precision, div_tol=1e-8, mass_floor=case.mass_floor)
+                              pred_tol=1e-12, precision=precision, div_tol=1e-8, mass_floor=case.mass_floor,
+                              coef_tables=coef_tables)
     ctx = ccns.Context(case.grid, params, caps, Dx, Dy, stream=stream)
     ctx.set_field(ccns.F_UX, ux0)
     ctx.set_field(ccns.F_UY, uy0)
@@ -251,7 +261,7 @@ def run_batched(args):
     ctxs = []
     with cf.ThreadPoolExecutor(max_workers=8) as ex:
         for case, stream, host in zip(cases, streams, ex.map(lambda c: host_inputs(ccns, c), cases)):
-            ctxs.append(setup_context(ccns, case, prec, stream, host))
+            ctxs.append(setup_context(ccns, case, prec, stream, host, 0 if args.coef_tables == "auto" else 1))
     torch.cuda.synchronize()
     cells = sum(c.grid.nx * c.grid.ny for c in cases)
     print(f"[bench] setup {time.perf_counter() - t_setup:.1f}s: {len(cases)} simulations, {cells} cells",
@@ -288,6 +298,7 @@ def run_batched(args):
         "dtype": "f32+f64" if prec else "f64",
         "data": "synthetic",
         "config": {"workload": "batched_cylinders_256", "simulations": len(cases), "cells": cells,
+                   "coef_classes_used": sum(1 for c in ctxs if c.coef_classes() > 0),
                    "sizes": {str(k): v for k, v in sorted(sizes.items())}, "precond": "multigrid",
                    "precision": "fp32 inner + fp64 refinement, div_rel <= 1e-8" if prec else "fp64",
                    "host_threads": 16},
@@ -364,9 +375,12 @@ def main():
                     help="only run the plain copies that calibrate the HBM byte counters")
     ap.add_argument("--summarize-counters", metavar="DIR",
                     help="store the HBM traffic of the predictor kernel from rocprofv3 counter runs under DIR")
+    ap.add_argument("--coef-tables", default="auto", choices=["auto", "off"],
+                    help="auto: the predictor CG reads its coefficients through the class table when it "
+                         "fits (the library's default); off: from the coefficient arrays")
     args = ap.parse_args()
     if args.summarize_counters:
-        summarize_counters(args.summarize_counters, "k_pred_cg", args.workload)
+        summarize_counters(args.summarize_counters, "k_pred_cg", args.workload, args.coef_tables == "auto")
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -394,7 +408,7 @@ def main():
     mixed = args.precision == "mixed"
     params = ccns.make_params(case.rho, case.mu, case.tau, u_ref=case.u_inf, pcg_tol=case.pcg_tol,
                               pred_tol=1e-12, precision=1 if mixed else 0, div_tol=1e-8,
-                              mass_floor=case.mass_floor)
+                              mass_floor=case.mass_floor, coef_tables=0 if args.coef_tables == "auto" else 1)
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
     ctx = ccns.Context(g, params, caps, Dx, Dy, stream=stream)
@@ -403,6 +417,7 @@ def main():
     ctx.set_field(ccns.F_UX, np.where(au, case.u_inf + px, Dx))
     ctx.set_field(ccns.F_UY, np.where(av, py, Dy))
     ctx.project()
+    ncls = ctx.coef_classes()
     setup_s = time.perf_counter() - t_setup
     print(f"[bench] setup {setup_s:.1f}s: {case.name} {g.nx}x{g.ny}", file=sys.stderr, flush=True)
 
@@ -443,7 +458,11 @@ def main():
     # the timed kernels run in float in the inner solves of the mixed mode
     esz = 0.5 if mixed else 1.0
     kname = "k_pred_cg<float>" if mixed else "k_pred_cg"
-    achieved = rate(PRED_CG_BYTES_PER_CELL, mean_us[2])
+    if ncls:
+        pred_bytes = esz * 8.0 * PRED_CG_VALUES_PER_CELL_CLS + PRED_CG_INDEX_BYTES
+    else:
+        pred_bytes = esz * 8.0 * PRED_CG_VALUES_PER_CELL
+    achieved = pred_bytes * cells / (mean_us[2] * 1e-6) / 1e9 if mean_us[2] else None
     out = {
         "metric": "Mcell-steps/s at 1e-8 divergence",
         "value": value,
@@ -459,7 +478,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": case.name, "nx": g.nx, "ny": g.ny, "re": case.re, "cfl": case.cfl,
                    "pcg_tol": case.pcg_tol, "pred_tol": 1e-12, "precond": "multigrid",
-                   "precision": "fp32 inner + fp64 refinement, div_rel <= 1e-8" if mixed else "fp64"},
+                   "precision": "fp32 inner + fp64 refinement, div_rel <= 1e-8" if mixed else "fp64",
+                   "coef_classes": ncls},
         "div_rel_max": div_max,
         "cg_iters_per_step": n_cg,
         "pred_iters_per_step": float(np.mean([i["pred_iters"] for i in infos])),
@@ -470,8 +490,8 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS if achieved else None,
-            "traffic": None if mixed else stored_traffic("k_pred_cg", case.name),
-            "bytes_per_launch": esz * PRED_CG_BYTES_PER_CELL * cells,
+            "traffic": None if mixed else stored_traffic("k_pred_cg", case.name, ncls > 0),
+            "bytes_per_launch": pred_bytes * cells,
             "mean_launch_us": mean_us[2],
             "timed_launches": cnt[2],
         },

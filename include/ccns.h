@@ -132,7 +132,14 @@ ccns_status ccns_capacities(const ccns_grid *grid, const ccns_body *bodies, int 
  *                 multigrid V-cycle (2x2 cell agglomeration, weighted-Jacobi
  *                 smoothing, pseudo-inverse on the coarsest grid).  The
  *                 paper does not fix the solver; both converge to the same
- *                 solution of eq:pm_poisson. */
+ *                 solution of eq:pm_poisson.
+ *  coef_tables    0: the predictor's FP64 CG reads its coefficients through
+ *                 a table of the distinct coefficient neighbourhoods (one
+ *                 index per entry) when there are at most max(1024, n/16) of
+ *                 them (n: entries of the padded layout), else from the
+ *                 coefficient arrays; 1: always from the arrays.  Both read
+ *                 the same values: the results are identical bit for bit.
+ *                 The float inner solves of precision 1 read the arrays. */
 typedef struct {
     double rho, mu, tau, u_ref, gx, gy;
     double pcg_tol, pred_tol, div_tol;
@@ -142,6 +149,7 @@ typedef struct {
     int poisson_weight;
     int precond;
     double mass_floor;
+    int coef_tables;
 } ccns_params;
 
 typedef struct ccns_ctx ccns_ctx;
@@ -166,6 +174,11 @@ ccns_status ccns_ctx_create(const ccns_grid *grid, const ccns_params *params,
                             ccns_ctx **out);
 void ccns_ctx_destroy(ccns_ctx *ctx);
 const char *ccns_last_error(const ccns_ctx *ctx);
+
+/* Number of coefficient classes the predictor's FP64 CG of this context
+ * reads (see coef_tables in ccns_params); 0 when it reads the coefficient
+ * arrays, -1 for a null context. */
+int ccns_coef_classes(const ccns_ctx *ctx);
 
 /* Fields held in the workspace (FP64). */
 enum {

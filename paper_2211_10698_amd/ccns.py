@@ -42,7 +42,7 @@ class Params(C.Structure):
                 ("gx", C.c_double), ("gy", C.c_double), ("pcg_tol", C.c_double), ("pred_tol", C.c_double),
                 ("div_tol", C.c_double), ("pcg_maxit", C.c_int), ("pred_maxit", C.c_int),
                 ("precision", C.c_int), ("visc_form", C.c_int), ("poisson_weight", C.c_int),
-                ("precond", C.c_int), ("mass_floor", C.c_double)]
+                ("precond", C.c_int), ("mass_floor", C.c_double), ("coef_tables", C.c_int)]
 
 
 class SolveInfo(C.Structure):
@@ -88,6 +88,8 @@ def lib():
         L.ccns_ctx_destroy.argtypes = [C.c_void_p]
         L.ccns_last_error.restype = C.c_char_p
         L.ccns_last_error.argtypes = [C.c_void_p]
+        L.ccns_coef_classes.restype = C.c_int
+        L.ccns_coef_classes.argtypes = [C.c_void_p]
         for name in ("ccns_field_set", "ccns_field_get"):
             f = getattr(L, name)
             f.restype = C.c_int
@@ -117,7 +119,7 @@ def lib():
 
 
 EXPORTED = ("ccns_caps_count", "ccns_capacities", "ccns_workspace_bytes", "ccns_ctx_create",
-            "ccns_ctx_destroy", "ccns_last_error", "ccns_field_set", "ccns_field_get", "ccns_apply",
+            "ccns_ctx_destroy", "ccns_last_error", "ccns_coef_classes", "ccns_field_set", "ccns_field_get", "ccns_apply",
             "ccns_pressure_solve", "ccns_project", "ccns_step", "ccns_predict", "ccns_correct",
             "ccns_diagnostics", "ccns_timing", "ccns_batch_create", "ccns_batch_step", "ccns_batch_destroy")
 
@@ -157,9 +159,9 @@ PRECOND_JACOBI, PRECOND_MG = 0, 1
 
 def make_params(rho, mu, tau, u_ref=1.0, pcg_tol=1e-10, pred_tol=1e-12, div_tol=1e-8, pcg_maxit=200000,
                 pred_maxit=500, precision=0, visc_form=0, poisson_weight=0, gx=0.0, gy=0.0,
-                precond=PRECOND_MG, mass_floor=0.05) -> Params:
+                precond=PRECOND_MG, mass_floor=0.05, coef_tables=0) -> Params:
     return Params(rho, mu, tau, u_ref, gx, gy, pcg_tol, pred_tol, div_tol, pcg_maxit, pred_maxit, precision,
-                  visc_form, poisson_weight, precond, mass_floor)
+                  visc_form, poisson_weight, precond, mass_floor, coef_tables)
 
 
 class Context:
@@ -281,6 +283,10 @@ class Context:
         if check:
             self._chk(st, "step")
         return info
+
+    def coef_classes(self) -> int:
+        """Coefficient classes the predictor's CG reads (0: the arrays)."""
+        return int(lib().ccns_coef_classes(self.h))
 
     def timing(self, enable=-1):
         """Accumulated (ms, count) per timed kernel; see ccns_timing."""

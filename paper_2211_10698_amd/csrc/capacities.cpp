@@ -446,9 +446,16 @@ struct GridOut {
     std::vector<double> V, X, Y, E, N, Bv, Bh, We, Wn;
 };
 
+// A rectangle or segment entirely in the fluid has the exact measures of its
+// extent.  Extents differ from the mesh spacing only by the rounding of the
+// node coordinates; one within 1e-9 relative of hx (hy) is taken as hx (hy),
+// so that every full cell, face and strip away from the interface carries
+// the same capacities bit for bit (V = hx hy, A = B = h, W = hx hy).
+inline double snap(double len, double h) { return std::fabs(len - h) <= 1e-9 * h ? h : len; }
+
 GridOut grid_caps(const Fluid &fl, const Integrator &in, const std::vector<double> &ex,
                   const std::vector<double> &ey, double bx0, double bx1, double by0, double by1,
-                  bool wall_faces_wet, double epsV, double margin) {
+                  bool wall_faces_wet, double epsV, double margin, double hx, double hy) {
     const int ni = (int)ex.size() - 1, nj = (int)ey.size() - 1;
     GridOut g;
     size_t n = (size_t)ni * nj;
@@ -458,9 +465,10 @@ GridOut grid_caps(const Fluid &fl, const Integrator &in, const std::vector<doubl
         ya = std::max(ya, by0); yb = std::min(yb, by1);
         if (!(xb > xa) || !(yb > ya)) return Moments{0, 0, 0};
         const int cl = fl.classify(xa, xb, ya, yb, margin);
-        if (cl > 0)
-            return Moments{(xb - xa) * (yb - ya), 0.5 * (xb * xb - xa * xa) * (yb - ya),
-                           0.5 * (yb * yb - ya * ya) * (xb - xa)};
+        if (cl > 0) {
+            const double w = snap(xb - xa, hx), t = snap(yb - ya, hy);
+            return Moments{w * t, 0.5 * (xb * xb - xa * xa) * t, 0.5 * (yb * yb - ya * ya) * w};
+        }
         if (cl < 0) return Moments{0, 0, 0};
         return in.rect(xa, xb, ya, yb);
     };
@@ -470,7 +478,7 @@ GridOut grid_caps(const Fluid &fl, const Integrator &in, const std::vector<doubl
         ya = std::max(ya, by0); yb = std::min(yb, by1);
         if (!(yb > ya)) return 0.0;
         const int cl = fl.classify(x, x, ya, yb, margin);
-        if (cl != 0) return cl > 0 ? yb - ya : 0.0;
+        if (cl != 0) return cl > 0 ? snap(yb - ya, hy) : 0.0;
         return in.vseg(x, ya, yb);
     };
     auto hseg = [&](double y, double xa, double xb, bool wet) -> double {
@@ -479,7 +487,7 @@ GridOut grid_caps(const Fluid &fl, const Integrator &in, const std::vector<doubl
         xa = std::max(xa, bx0); xb = std::min(xb, bx1);
         if (!(xb > xa)) return 0.0;
         const int cl = fl.classify(xa, xb, y, y, margin);
-        if (cl != 0) return cl > 0 ? xb - xa : 0.0;
+        if (cl != 0) return cl > 0 ? snap(xb - xa, hx) : 0.0;
         return in.hseg(y, xa, xb);
     };
 #pragma omp parallel for schedule(dynamic, 4)
@@ -543,9 +551,9 @@ extern "C" ccns_status ccns_capacities(const ccns_grid *grid, const ccns_body *b
     for (int i = 0; i < nx + 3; ++i) { xe[i] = x0 + (i - 1.0) * hx; xc[i] = x0 + (i - 0.5) * hx; }
     for (int j = 0; j < ny + 3; ++j) { ye[j] = y0 + (j - 1.0) * hy; yc[j] = y0 + (j - 0.5) * hy; }
     const double epsV = 1e-12 * hx * hy, margin = 2.0 * std::max(hx, hy);
-    GridOut p = grid_caps(fl, in, xe, ye, x0, x1, y0, y1, true, epsV, margin);
-    GridOut u = grid_caps(fl, in, xc, ye, x0 - 0.5 * hx, x1 + 0.5 * hx, y0, y1, false, epsV, margin);
-    GridOut v = grid_caps(fl, in, xe, yc, x0, x1, y0 - 0.5 * hy, y1 + 0.5 * hy, false, epsV, margin);
+    GridOut p = grid_caps(fl, in, xe, ye, x0, x1, y0, y1, true, epsV, margin, hx, hy);
+    GridOut u = grid_caps(fl, in, xc, ye, x0 - 0.5 * hx, x1 + 0.5 * hx, y0, y1, false, epsV, margin, hx, hy);
+    GridOut v = grid_caps(fl, in, xe, yc, x0, x1, y0 - 0.5 * hy, y1 + 0.5 * hy, false, epsV, margin, hx, hy);
     const size_t W = nx + 2, H = ny + 2, n = W * H;
     std::memset(caps, 0, sizeof(double) * n * CCNS_NCAPS);
     auto at = [&](int cap) { return caps + (size_t)cap * n; };

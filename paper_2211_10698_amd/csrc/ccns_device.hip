@@ -28,6 +28,7 @@
 #include <string>
 #include <thread>
 #include <type_traits>
+#include <unordered_map>
 #include <vector>
 
 #include "ccns.h"
@@ -80,7 +81,27 @@ struct PredCoefT {
     ViscCoefT<T> vc;
     const T *vu, *vv, *hdx, *hdy;
     double rt, mu;
+    const int *cls;  // coefficient classes of the predictor CG (or null)
+    const T *tab;
 };
+
+// Coefficient classes of the predictor CG.  Away from the bodies and the
+// walls the capacities repeat, so every entry k of the face layout can name
+// a row of a small table that holds each value the CG kernel reads for it:
+// the Jacobi diagonal and face volumes at k, and the capacities and weights
+// of the strain stencils at k and its neighbours.  The kernel then reads one
+// index per entry instead of twelve coefficient arrays; the values, and so
+// the arithmetic, are those of the arrays.
+enum PredRow {
+    PR_HDX, PR_HDY, PR_VU, PR_VV,
+    PR_BXX_W, PR_BXX, PR_BXX_E, PR_WXX, PR_WXX_E,    // B^xx at k-1, k, k+1; 1/W^xx at k, k+1
+    PR_BYY_S, PR_BYY, PR_BYY_N, PR_WYY, PR_WYY_N,    // B^yy at k-P, k, k+P; 1/W^yy at k, k+P
+    PR_BXY, PR_BYX, PR_BXY_N, PR_BYX_E,              // B^xy at k, k+P; B^yx at k, k+1
+    PR_NXX, PR_NYY, PR_NXY, PR_NYX,                  // node weights at k
+    PR_COUNT
+};
+constexpr int PCW = 24;  // row width (PR_COUNT, padded)
+static_assert(PR_COUNT <= PCW, "class row too narrow");
 struct PredCoef {
     ViscCoef vc;
     const double *vu, *vv, *hdx, *hdy;
@@ -910,15 +931,34 @@ __global__ __launch_bounds__(TT) void k_mg_tail_lds(TailDesc<T> d) {
         const TailLevel<T> &L = d.lv[l];
         const int W = L.nx + 2, n = W * (L.ny + 2);
         T *cx = arr(l, 0), *cy = arr(l, 1), *dv = arr(l, 2), *b = arr(l, 3), *x = arr(l, 4), *xt = arr(l, 5);
-        for (int e = threadIdx.x; e < n; e += TT) {
-            const int j = e / W, i = e - j * W;
-            const size_t k = (size_t)j * L.P + i;
-            cx[e] = L.cx[k];
-            cy[e] = L.cy[k];
-            dv[e] = L.dinv[k];
-            b[e] = l == 0 ? L.b[k] : (T)0;
-            x[e] = (T)0;
-            xt[e] = (T)0;
+        // TL entries per thread at a time, every load issued before the
+        // first store
+        constexpr int TL = 4;
+        for (int e0 = 0; e0 < n; e0 += TL * TT) {
+            T vcx[TL], vcy[TL], vdv[TL], vb[TL];
+#pragma unroll
+            for (int u = 0; u < TL; ++u) {
+                const int e = e0 + u * TT + threadIdx.x;
+                const int ee = e < n ? e : 0;
+                const int j = ee / W, i = ee - j * W;
+                const size_t k = (size_t)j * L.P + i;
+                vcx[u] = L.cx[k];
+                vcy[u] = L.cy[k];
+                vdv[u] = L.dinv[k];
+                vb[u] = l == 0 ? L.b[k] : (T)0;
+            }
+#pragma unroll
+            for (int u = 0; u < TL; ++u) {
+                const int e = e0 + u * TT + threadIdx.x;
+                if (e < n) {
+                    cx[e] = vcx[u];
+                    cy[e] = vcy[u];
+                    dv[e] = vdv[u];
+                    b[e] = vb[u];
+                    x[e] = (T)0;
+                    xt[e] = (T)0;
+                }
+            }
         }
     }
     __syncthreads();
@@ -965,7 +1005,10 @@ __global__ __launch_bounds__(TT) void k_mg_tail_lds(TailDesc<T> d) {
         }
         __syncthreads();
     }
-    // coarsest: x = A^+ b with the dense pseudo-inverse (global, L2)
+    // coarsest: x = A^+ b with the dense pseudo-inverse (global, L2).  Eight
+    // threads per row: thread s of a row sums the columns s, s+8, s+16, ...
+    // in order, with CL loads in flight at a time; the row's eight partial
+    // sums are then combined by lane exchanges (a fixed order).
     {
         const int l = d.nlev - 1;
         const TailLevel<T> &L = d.lv[l];
@@ -973,16 +1016,39 @@ __global__ __launch_bounds__(TT) void k_mg_tail_lds(TailDesc<T> d) {
         const T *b = arr(l, 3);
         T *x = arr(l, 4);
         __shared__ double sb[1024];
-        for (int i = threadIdx.x; i < d.ncoarse; i += TT) {
+        const int n = d.ncoarse;
+        for (int i = threadIdx.x; i < n; i += TT) {
             const int k = d.idx[i];
             sb[i] = b[(k / L.P) * W + k % L.P];
         }
         __syncthreads();
-        for (int i = threadIdx.x; i < d.ncoarse; i += TT) {
+        constexpr int CL = 16;
+        const int sl = threadIdx.x & 7;
+        for (int i0 = 0; i0 < n; i0 += TT / 8) {
+            const int i = i0 + (threadIdx.x >> 3);
+            const bool row = i < n;
+            const double *prow = d.pinv + (size_t)(row ? i : 0) * n;
             double acc = 0.0;
-            for (int j2 = 0; j2 < d.ncoarse; ++j2) acc += d.pinv[(size_t)i * d.ncoarse + j2] * sb[j2];
-            const int k = d.idx[i];
-            x[(k / L.P) * W + k % L.P] = (T)acc;
+            for (int c0 = sl; c0 < n; c0 += 8 * CL) {
+                double a[CL];
+#pragma unroll
+                for (int u = 0; u < CL; ++u) {
+                    const int c = c0 + 8 * u;
+                    a[u] = prow[c < n ? c : 0];
+                }
+#pragma unroll
+                for (int u = 0; u < CL; ++u) {
+                    const int c = c0 + 8 * u;
+                    if (c < n) acc += a[u] * sb[c];
+                }
+            }
+            acc += __shfl_xor(acc, 1);
+            acc += __shfl_xor(acc, 2);
+            acc += __shfl_xor(acc, 4);
+            if (row && sl == 0) {
+                const int k = d.idx[i];
+                x[(k / L.P) * W + k % L.P] = (T)acc;
+            }
         }
         __syncthreads();
     }
@@ -1166,8 +1232,9 @@ struct PredTileNx {
 // staged in spx, spy), formed once per cell and node.  GEO: the node weights
 // are the symmetric geometric form (cross weight = sqrt of the product of the
 // two diagonal ones), so the cross weights are formed instead of read.
-template <class T, bool GEO, class Tile = PredTile<T>>
-__device__ inline void pred_tile_strains(Tile &s, const ViscCoefT<T> &c, int P, int rows, int c0, int r0) {
+template <class T, bool GEO, class Tile = PredTile<T>, bool CLS = false>
+__device__ inline void pred_tile_strains(Tile &s, const ViscCoefT<T> &c, int P, int rows, int c0, int r0,
+                                         const int *cls = nullptr, const T *tab = nullptr) {
     // S_xx at cells (rows r0.., cols c0 .. c0+TX): x-faces i-1, i
     if constexpr (!std::is_same<Tile, PredTileNx<T>>::value)
     for (int e = threadIdx.x; e < HTY * (TX + 1); e += NT) {
@@ -1194,16 +1261,25 @@ __device__ inline void pred_tile_strains(Tile &s, const ViscCoefT<T> &c, int P, 
         const int j = r0 - 1 + ly, i = c0 - 1 + lx;
         const bool in = (j >= 0) && (j + 1 < rows) && (i >= 0) && (i + 1 < P);
         const size_t k = in ? (size_t)j * P + i : 0;
-        const T bxn = c.bxy[k + P], bxs = c.bxy[k], bye = c.byx[k + 1], byw = c.byx[k];
+        T bxn, bxs, bye, byw, a, dd, nxy, nyx;
+        if constexpr (CLS) {
+            const T *row = tab + (size_t)cls[k] * PCW;
+            bxn = row[PR_BXY_N], bxs = row[PR_BXY], bye = row[PR_BYX_E], byw = row[PR_BYX];
+            a = row[PR_NXX], dd = row[PR_NYY];
+            if (!GEO) nxy = row[PR_NXY], nyx = row[PR_NYX];
+        } else {
+            bxn = c.bxy[k + P], bxs = c.bxy[k], bye = c.byx[k + 1], byw = c.byx[k];
+            a = c.nxx[k], dd = c.nyy[k];
+            if (!GEO) nxy = c.nxy[k], nyx = c.nyx[k];
+        }
         const T gxv = bxn * s.spx[ly + 1][lx] - bxs * s.spx[ly][lx];
         const T gyv = bye * s.spy[ly][lx + 1] - byw * s.spy[ly][lx];
-        const T a = c.nxx[k], dd = c.nyy[k];
         T b, cc;
         if (GEO) {
             b = cc = sqrt(a * dd);
         } else {
-            b = c.nxy[k];
-            cc = c.nyx[k];
+            b = nxy;
+            cc = nyx;
         }
         s.snx[ly][lx] = in ? (T)0.5 * (a * gxv + b * gyv) : (T)0;
         s.sny[ly][lx] = in ? (T)0.5 * (cc * gxv + dd * gyv) : (T)0;
@@ -1233,7 +1309,7 @@ __device__ inline void pred_tile_K(const PredTileNx<T> &s, const ViscCoefT<T> &c
     const T s0 = in0 ? w0 * (e0 * s.spx[ly + 1][tx + 1] - b0 * s.spx[ly + 1][tx]) : (T)0;
     const T s1 = in1 ? w1 * (e1 * s.spx[ly + 1][tx + 2] - b1 * s.spx[ly + 1][tx + 1]) : (T)0;
     kx = bxx * (s1 - s0) + bxy * (s.snx[ly + 1][tx + 1] - s.snx[ly][tx + 1]);
-    // the y-face's two cell strains S_yy (cells j and j+1 of column i)
+    // the y-face's two cell strains S_yy (cells j and j + 1 of column i)
     const int j = (int)(k / (size_t)P);
     const bool iny0 = j >= 1, iny1 = j + 1 < rows;
     const size_t q0 = iny0 ? k : (size_t)P, q1 = iny1 ? k + P : (size_t)P;
@@ -1241,6 +1317,27 @@ __device__ inline void pred_tile_K(const PredTileNx<T> &s, const ViscCoefT<T> &c
     const T wy1 = c.wyy[q1], n1 = c.byy[q1], m1 = c.byy[q1 - P];
     const T t0 = iny0 ? wy0 * (n0 * s.spy[ly + 1][tx + 1] - m0 * s.spy[ly][tx + 1]) : (T)0;
     const T t1 = iny1 ? wy1 * (n1 * s.spy[ly + 2][tx + 1] - m1 * s.spy[ly + 1][tx + 1]) : (T)0;
+    ky = byy * (t1 - t0) + byx * (s.sny[ly + 1][tx + 1] - s.sny[ly + 1][tx]);
+}
+
+// The same with the values from the entry's row of the class table (where a
+// neighbour is outside the grid the strain is 0, as above).
+template <class T>
+__device__ inline void pred_tile_K_row(const PredTileNx<T> &s, const T *row, size_t k, int ly, int tx, int i, int P,
+                                       int rows, T &kx, T &ky) {
+    const T bxx = row[PR_BXX], bxy = row[PR_BXY], byy = row[PR_BYY], byx = row[PR_BYX];
+    const bool in0 = i >= 1, in1 = i + 1 < P;
+    const T w0 = row[PR_WXX], b0 = row[PR_BXX_W];
+    const T w1 = row[PR_WXX_E], e1 = row[PR_BXX_E];
+    const T s0 = in0 ? w0 * (bxx * s.spx[ly + 1][tx + 1] - b0 * s.spx[ly + 1][tx]) : (T)0;
+    const T s1 = in1 ? w1 * (e1 * s.spx[ly + 1][tx + 2] - bxx * s.spx[ly + 1][tx + 1]) : (T)0;
+    kx = bxx * (s1 - s0) + bxy * (s.snx[ly + 1][tx + 1] - s.snx[ly][tx + 1]);
+    const int j = (int)(k / (size_t)P);
+    const bool iny0 = j >= 1, iny1 = j + 1 < rows;
+    const T wy0 = row[PR_WYY], m0 = row[PR_BYY_S];
+    const T wy1 = row[PR_WYY_N], n1 = row[PR_BYY_N];
+    const T t0 = iny0 ? wy0 * (byy * s.spy[ly + 1][tx + 1] - m0 * s.spy[ly][tx + 1]) : (T)0;
+    const T t1 = iny1 ? wy1 * (n1 * s.spy[ly + 2][tx + 1] - byy * s.spy[ly + 1][tx + 1]) : (T)0;
     ky = byy * (t1 - t0) + byx * (s.sny[ly + 1][tx + 1] - s.sny[ly + 1][tx]);
 }
 
@@ -1265,8 +1362,9 @@ __device__ inline void pred_tile_K(const PredTileNx<T> &s, const ViscCoefT<T> &c
 // after the one that stopped return at once (stop_it).  The tile keeps no
 // cell strains (20 KB of LDS in FP64) and the register budget is set for
 // seven waves per SIMD (70 VGPRs, no spills): the launch is bound by HBM
-// latency, and more resident waves hide more of it.
-template <class T, bool GEO>
+// latency, and more resident waves hide more of it.  With CLS the
+// coefficients come from the class table (pc.cls, pc.tab).
+template <class T, bool GEO, bool CLS = false>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(7))) void k_pred_cg(
     int P, int rows, int gx, int gy, size_t n, PredCoefT<T> pc, CgState *st, int it, T *__restrict__ x,
     const T *__restrict__ rin, T *__restrict__ rout, const T *__restrict__ pold, T *__restrict__ pnew,
@@ -1329,6 +1427,19 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(7))) void k_
     // products of the last phase (rows ty and ty + 4 of the tile)
     constexpr int RW = HTY / 4;
     T rxs[RW], rys[RW], hxs[RW], hys[RW];
+    int cl[RW];
+    // the Jacobi diagonal at entry k
+    auto jacobi = [&](size_t k, T &hx, T &hy, int &ck) {
+        if constexpr (CLS) {
+            ck = pc.cls[k];
+            const T *row = pc.tab + (size_t)ck * PCW;
+            hx = row[PR_HDX];
+            hy = row[PR_HDY];
+        } else {
+            hx = pc.hdx[k];
+            hy = pc.hdy[k];
+        }
+    };
     if (live) {
         // the tile: r', x += alpha p_old, p = M r' + beta p_old
 #pragma unroll
@@ -1337,7 +1448,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(7))) void k_
             const int j = r0 + ly, i = c0 + tx;
             const bool in = j < rows;
             const size_t k = in ? (size_t)j * P + i : 0;
-            const T hx = pc.hdx[k], hy = pc.hdy[k];
+            T hx, hy;
+            jacobi(k, hx, hy, cl[m]);
             T rx = rin[k], ry = rin[n + k];
             T px = hx * rx, py = hy * ry;
             if (it >= 1) {
@@ -1373,7 +1485,9 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(7))) void k_
             const int j = r0 - 1 + ly, i = c0 - 1 + lx;
             const bool in = (j >= 0) && (j < rows) && (i >= 0) && (i < P);
             const size_t k = in ? (size_t)j * P + i : 0;
-            const T hx = pc.hdx[k], hy = pc.hdy[k];
+            T hx, hy;
+            int ck;
+            jacobi(k, hx, hy, ck);
             T rx = rin[k], ry = rin[n + k];
             T px = hx * rx, py = hy * ry;
             if (it >= 1) {
@@ -1388,7 +1502,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(7))) void k_
         }
     }
     __syncthreads();
-    if (live) pred_tile_strains<T, GEO, PredTileNx<T>>(s, pc.vc, P, rows, c0, r0);
+    if (live) pred_tile_strains<T, GEO, PredTileNx<T>, CLS>(s, pc.vc, P, rows, c0, r0, pc.cls, pc.tab);
     __syncthreads();
     if (live) {
         const T rt = (T)pc.rt, mu = (T)pc.mu;
@@ -1398,11 +1512,19 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(7))) void k_
             const int j = r0 + ly, i = c0 + tx;
             if (j >= rows) break;
             const size_t k = (size_t)j * P + i;
-            const T vu = pc.vu[k], vv = pc.vv[k];
+            T vu, vv, kx, ky;
+            if constexpr (CLS) {
+                const T *row = pc.tab + (size_t)cl[m] * PCW;
+                vu = row[PR_VU];
+                vv = row[PR_VV];
+                pred_tile_K_row<T>(s, row, k, ly, tx, i, P, rows, kx, ky);
+            } else {
+                vu = pc.vu[k];
+                vv = pc.vv[k];
+                pred_tile_K<T>(s, pc.vc, k, ly, tx, i, P, rows, kx, ky);
+            }
             const T rx = rxs[m], ry = rys[m], hx = hxs[m], hy = hys[m];
             const T px = s.spx[ly + 1][tx + 1], py = s.spy[ly + 1][tx + 1];
-            T kx, ky;
-            pred_tile_K<T>(s, pc.vc, k, ly, tx, i, P, rows, kx, ky);
             const T qx = vu > (T)0 ? rt * vu * px - mu * kx : (T)0;
             const T qy = vv > (T)0 ? rt * vv * py - mu * ky : (T)0;
             const T pxo = vu > (T)0 ? px : (T)0, pyo = vv > (T)0 ? py : (T)0;
@@ -1805,6 +1927,10 @@ struct WsPlan {
     // precision 1 only (else 0): float arrays and float coarse levels
     size_t arr32_bytes, f32_off;
     std::vector<size_t> mg32_off;
+    // predictor coefficient classes: one int per entry, up to max_cls rows of
+    // PCW values (FP64)
+    size_t cls_off, tab_off;
+    int max_cls;
     size_t total;
 };
 
@@ -1846,6 +1972,11 @@ WsPlan plan(int nx, int ny, int precision) {
             off += MG_ARRS * align_up(w.mgL[l].n * sizeof(float), 256);
         }
     }
+    w.cls_off = off;
+    off += align_up(w.L.n * sizeof(int), 256);
+    w.max_cls = (int)std::max<size_t>(1024, w.L.n / 16);
+    w.tab_off = off;
+    off += align_up((size_t)w.max_cls * PCW * sizeof(double), 256);
     w.total = off;
     return w;
 }
@@ -1890,6 +2021,11 @@ struct ccns_ctx {
     int *pidx;
     int ncoarse_act;
     int tail_lds;       // bytes of dynamic LDS the LDS-resident coarse end may use (0: not used)
+    // predictor coefficient classes (ncls = 0: the predictor CG reads the
+    // coefficient arrays)
+    int ncls;
+    int *cls;
+    double *tab;
     // optional kernel timing: start/stop events attached to sampled launches
     int timing;
     std::vector<hipEvent_t> evpool;
@@ -1976,7 +2112,7 @@ PredCoefT<double> pred_coef_t(ccns_ctx *c) {
     PredCoef pc = pred_coef(c);
     return PredCoefT<double>{ViscCoefT<double>{pc.vc.bxx, pc.vc.bxy, pc.vc.byy, pc.vc.byx, pc.vc.wxx, pc.vc.wyy,
                                                pc.vc.nxx, pc.vc.nxy, pc.vc.nyx, pc.vc.nyy},
-                             pc.vu, pc.vv, pc.hdx, pc.hdy, pc.rt, pc.mu};
+                             pc.vu, pc.vv, pc.hdx, pc.hdy, pc.rt, pc.mu, nullptr, nullptr};
 }
 
 // dense (ny+2)x(nx+2) <-> padded device array
@@ -2145,6 +2281,76 @@ constexpr double MG_OMEGA = 0.8;  // weighted-Jacobi damping
 // Builds the coarse levels on the host from the fine Poisson weights and
 // uploads them (and their float copies in precision 1); the coarsest grid
 // gets a dense pseudo-inverse.
+// Coefficient classes of the predictor CG (PredRow): the row of every entry
+// of the face layout, with equal rows (bit for bit) sharing one class.  A
+// neighbour outside the grid contributes 0 (the kernel never uses such a
+// value).  Leaves ncls = 0 (the CG then reads the coefficient arrays) when
+// there are more classes than the workspace's table holds.
+ccns_status pred_classes(ccns_ctx *c, const HostCoef &hc) {
+    c->ncls = 0;
+    c->cls = (int *)(c->base + c->w.cls_off);
+    c->tab = (double *)(c->base + c->w.tab_off);
+    if (c->prm.coef_tables == 1) return CCNS_OK;
+    const Layout &L = c->w.L;
+    const long P = L.pitch, rows = L.rows, W = c->g.nx + 2;
+    auto at = [&](const std::vector<double> &v, long j, long i) -> double {
+        return (j >= 0 && j < rows && i >= 0 && i < W) ? v[(size_t)(j * W + i)] : 0.0;
+    };
+    std::vector<int> cls(L.n);
+    std::vector<double> tab;
+    std::unordered_map<std::string, int> index;
+    double row[PCW], last[PCW];
+    int lastc = -1;
+    for (long j = 0; j < rows; ++j)
+        for (long i = 0; i < P; ++i) {
+            row[PR_HDX] = at(hc.hdx, j, i);
+            row[PR_HDY] = at(hc.hdy, j, i);
+            row[PR_VU] = at(hc.vu, j, i);
+            row[PR_VV] = at(hc.vv, j, i);
+            row[PR_BXX_W] = at(hc.bxx, j, i - 1);
+            row[PR_BXX] = at(hc.bxx, j, i);
+            row[PR_BXX_E] = at(hc.bxx, j, i + 1);
+            row[PR_WXX] = at(hc.wxx, j, i);
+            row[PR_WXX_E] = at(hc.wxx, j, i + 1);
+            row[PR_BYY_S] = at(hc.byy, j - 1, i);
+            row[PR_BYY] = at(hc.byy, j, i);
+            row[PR_BYY_N] = at(hc.byy, j + 1, i);
+            row[PR_WYY] = at(hc.wyy, j, i);
+            row[PR_WYY_N] = at(hc.wyy, j + 1, i);
+            row[PR_BXY] = at(hc.bxy, j, i);
+            row[PR_BYX] = at(hc.byx, j, i);
+            row[PR_BXY_N] = at(hc.bxy, j + 1, i);
+            row[PR_BYX_E] = at(hc.byx, j, i + 1);
+            row[PR_NXX] = at(hc.nxx, j, i);
+            row[PR_NYY] = at(hc.nyy, j, i);
+            row[PR_NXY] = at(hc.nxy, j, i);
+            row[PR_NYX] = at(hc.nyx, j, i);
+            for (int u = PR_COUNT; u < PCW; ++u) row[u] = 0.0;
+            int id = lastc;
+            if (lastc < 0 || std::memcmp(row, last, sizeof row) != 0) {
+                std::string key((const char *)row, sizeof row);
+                auto f = index.find(key);
+                if (f == index.end()) {
+                    id = (int)(tab.size() / PCW);
+                    if (id >= c->w.max_cls) return CCNS_OK;
+                    index.emplace(std::move(key), id);
+                    tab.insert(tab.end(), row, row + PCW);
+                } else {
+                    id = f->second;
+                }
+                std::memcpy(last, row, sizeof row);
+                lastc = id;
+            }
+            cls[(size_t)(j * P + i)] = id;
+        }
+    HIPCHK(c, hipMemcpyAsync(c->cls, cls.data(), cls.size() * sizeof(int), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->tab, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    // the host vectors are released when this returns: wait for the copies
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->ncls = (int)(tab.size() / PCW);
+    return CCNS_OK;
+}
+
 ccns_status mg_setup(ccns_ctx *c, const HostCoef &hc) {
     const WsPlan &w = c->w;
     const bool mix = c->prm.precision == 1;
@@ -2506,6 +2712,8 @@ ccns_status pred_cg(ccns_ctx *c, PredCoefT<T> pc, CgState *st, T *x, T *const r[
     const int gx = L.pitch / TX, gy = (L.rows + HTY - 1) / HTY;
     const int nb = ((gx * gy + 7) / 8) * 8;
     const bool geo = c->prm.visc_form == 0;
+    auto kern = pc.cls ? (geo ? k_pred_cg<T, true, true> : k_pred_cg<T, false, true>)
+                       : (geo ? k_pred_cg<T, true, false> : k_pred_cg<T, false, false>);
     int chunk = std::max(4, last_it + 1);
     int it = 0;
     for (;;) {
@@ -2515,7 +2723,7 @@ ccns_status pred_cg(ccns_ctx *c, PredCoefT<T> pc, CgState *st, T *x, T *const r[
             const double *tin = it == 0 ? c->part[PB_INIT] : c->part[PB_UPD];
             const int nin = it == 0 ? c->init_nblk : PRED_RED;
             const bool tm = c->timing && (it % 8 == 4) && it < last_it;
-            launch(c, tm, 2, it, geo ? k_pred_cg<T, true> : k_pred_cg<T, false>, dim3(nb), dim3(NT), L.pitch, L.rows, gx,
+            launch(c, tm, 2, it, kern, dim3(nb), dim3(NT), L.pitch, L.rows, gx,
                    gy, L.n, pc, st, it, x, rin, r[b], (const T *)p[a], p[b], (const T *)q[a], q[b], tin, nin,
                    c->part[PB_DIR]);
             launch(c, tm, 3, it, k_reduce_partials_split<7>, dim3(PRED_RED), dim3(NT), (const double *)c->part[PB_DIR],
@@ -2567,6 +2775,10 @@ ccns_status predict_dev(ccns_ctx *c, ccns_solve_info *info) {
     predictor_rhs(c);
     pred_residual<false>(c, c->st_pred);
     PredCoefT<double> pd = pred_coef_t(c);
+    if (c->ncls) {
+        pd.cls = c->cls;
+        pd.tab = c->tab;
+    }
     double *r[2] = {c->a[A_PRX], c->a[A_PR1X]}, *p[2] = {c->a[A_PP0X], c->a[A_PP1X]},
            *q[2] = {c->a[A_PQX], c->a[A_PQ1X]};
     return pred_cg<double>(c, pd, c->st_pred, c->a[A_USX], r, p, q, c->last_pred_it, info);
@@ -2579,7 +2791,9 @@ ccns_status predict_mixed(ccns_ctx *c, ccns_solve_info *info) {
     PredCoef pc = pred_coef(c);
     PredCoefT<float> pf{ViscCoefT<float>{c->f[G_BXX], c->f[G_BXY], c->f[G_BYY], c->f[G_BYX], c->f[G_WXX],
                                          c->f[G_WYY], c->f[G_NXX], c->f[G_NXY], c->f[G_NYX], c->f[G_NYY]},
-                        c->f[G_VU], c->f[G_VV], c->f[G_HDX], c->f[G_HDY], pc.rt, pc.mu};
+                        c->f[G_VU], c->f[G_VV], c->f[G_HDX], c->f[G_HDY], pc.rt, pc.mu, nullptr, nullptr};
+    // the float CG reads the coefficient arrays: at half the bytes per value
+    // the class table's dependent load costs more than it saves (measured)
     const double tol = c->prm.pred_tol;
     predictor_rhs(c);
     double fn2 = 0.0, rn2 = 0.0;
@@ -2667,6 +2881,8 @@ size_t ccns_workspace_bytes(const ccns_grid *grid, const ccns_params *params) {
 }
 
 const char *ccns_last_error(const ccns_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+int ccns_coef_classes(const ccns_ctx *ctx) { return ctx ? ctx->ncls : -1; }
 
 ccns_status ccns_ctx_create(const ccns_grid *grid, const ccns_params *params, const double *caps_host,
                             const double *dirichlet_host, void *dev_workspace, size_t ws_bytes, void *hip_stream,
@@ -2787,6 +3003,10 @@ ccns_status ccns_ctx_create(const ccns_grid *grid, const ccns_params *params, co
     to_dev(c, c->a[A_UX], hc.dx.data(), hipMemcpyHostToDevice);
     to_dev(c, c->a[A_UY], hc.dy.data(), hipMemcpyHostToDevice);
     if (params->precond == 1 && (s = mg_setup(c, hc)) != CCNS_OK) {
+        ccns_ctx_destroy(c);
+        return s;
+    }
+    if ((s = pred_classes(c, hc)) != CCNS_OK) {
         ccns_ctx_destroy(c);
         return s;
     }

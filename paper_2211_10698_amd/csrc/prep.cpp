@@ -36,6 +36,7 @@ ccns_status prepare_coefficients(const ccns_grid &g, const ccns_params &prm, con
     if (nx < 2 || ny < 2 || !(g.hx > 0) || !(g.hy > 0)) { err = "bad grid"; return CCNS_EINVAL; }
     if (!(prm.rho > 0) || !(prm.mu >= 0) || !(prm.tau > 0)) { err = "rho, tau must be > 0 and mu >= 0"; return CCNS_EINVAL; }
     if (!(prm.mass_floor >= 0.0) || !(prm.mass_floor <= 1.0)) { err = "mass_floor must be in [0, 1]"; return CCNS_EINVAL; }
+    if (prm.coef_tables != 0 && prm.coef_tables != 1) { err = "coef_tables must be 0 or 1"; return CCNS_EINVAL; }
     if (prm.visc_form < 0 || prm.visc_form > 2 || prm.poisson_weight < 0 || prm.poisson_weight > 1) {
         err = "bad visc_form or poisson_weight"; return CCNS_EINVAL;
     }
