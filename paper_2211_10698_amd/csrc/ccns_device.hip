@@ -1232,9 +1232,33 @@ struct PredTileNx {
 // staged in spx, spy), formed once per cell and node.  GEO: the node weights
 // are the symmetric geometric form (cross weight = sqrt of the product of the
 // two diagonal ones), so the cross weights are formed instead of read.
-template <class T, bool GEO, class Tile = PredTile<T>, bool CLS = false>
-__device__ inline void pred_tile_strains(Tile &s, const ViscCoefT<T> &c, int P, int rows, int c0, int r0,
-                                         const int *cls = nullptr, const T *tab = nullptr) {
+// The strain arithmetic of the predictor tiles, shared by the kernels that
+// read the coefficient arrays and those that read the class table.  Every
+// product that meets a sum is written as an explicit fused multiply-add, so
+// the compiler has no contraction left to choose and both paths round alike.
+//   cell strain   w (e v_e - b v_w)                       (eq:diag)
+//   node strains  gx = bn v_n - bs v_s, gy = be u_e - bw u_w,
+//                 S = (a gx + b gy) / 2, (c gx + d gy) / 2  (eq:offdiag)
+//   face term     B^aa (S_+ - S_-) + B^ab (N_+ - N_-)      (eq:divD)
+template <class T>
+__device__ inline T strain_cell(T w, T e, T b, T ve, T vw) {
+    return w * fma(e, ve, -(b * vw));
+}
+template <class T>
+__device__ inline void strain_node(T bxn, T bxs, T bye, T byw, T a, T b, T cc, T dd, T pn, T ps, T qe, T qw, T &snx,
+                                   T &sny) {
+    const T gxv = fma(bxn, pn, -(bxs * ps));
+    const T gyv = fma(bye, qe, -(byw * qw));
+    snx = (T)0.5 * fma(a, gxv, b * gyv);
+    sny = (T)0.5 * fma(cc, gxv, dd * gyv);
+}
+template <class T>
+__device__ inline T strain_face(T baa, T sp, T sm, T bab, T np, T nm) {
+    return fma(baa, sp - sm, bab * (np - nm));
+}
+
+template <class T, bool GEO, class Tile = PredTile<T>>
+__device__ inline void pred_tile_strains(Tile &s, const ViscCoefT<T> &c, int P, int rows, int c0, int r0) {
     // S_xx at cells (rows r0.., cols c0 .. c0+TX): x-faces i-1, i
     if constexpr (!std::is_same<Tile, PredTileNx<T>>::value)
     for (int e = threadIdx.x; e < HTY * (TX + 1); e += NT) {
@@ -1243,7 +1267,7 @@ __device__ inline void pred_tile_strains(Tile &s, const ViscCoefT<T> &c, int P, 
         const bool in = (j < rows) && (i >= 1) && (i < P);
         const size_t k = in ? (size_t)j * P + i : 1;
         const T w = c.wxx[k], be = c.bxx[k], bw = c.bxx[k - 1];
-        s.sxx[ly][lx] = in ? w * (be * s.spx[ly + 1][lx + 1] - bw * s.spx[ly + 1][lx]) : (T)0;
+        s.sxx[ly][lx] = in ? strain_cell(w, be, bw, s.spx[ly + 1][lx + 1], s.spx[ly + 1][lx]) : (T)0;
     }
     // S_yy at cells (rows r0 .. r0+HTY, cols c0..): y-faces j-1, j
     if constexpr (!std::is_same<Tile, PredTileNx<T>>::value)
@@ -1253,7 +1277,7 @@ __device__ inline void pred_tile_strains(Tile &s, const ViscCoefT<T> &c, int P, 
         const bool in = (j >= 1) && (j < rows);
         const size_t k = in ? (size_t)j * P + i : (size_t)P;
         const T w = c.wyy[k], bn = c.byy[k], bs = c.byy[k - P];
-        s.syy[ly][lx] = in ? w * (bn * s.spy[ly + 1][lx + 1] - bs * s.spy[ly][lx + 1]) : (T)0;
+        s.syy[ly][lx] = in ? strain_cell(w, bn, bs, s.spy[ly + 1][lx + 1], s.spy[ly][lx + 1]) : (T)0;
     }
     // node strains (rows r0-1 .. r0+HTY-1, cols c0-1 .. c0+TX-1)
     for (int e = threadIdx.x; e < (HTY + 1) * (TX + 1); e += NT) {
@@ -1261,28 +1285,20 @@ __device__ inline void pred_tile_strains(Tile &s, const ViscCoefT<T> &c, int P, 
         const int j = r0 - 1 + ly, i = c0 - 1 + lx;
         const bool in = (j >= 0) && (j + 1 < rows) && (i >= 0) && (i + 1 < P);
         const size_t k = in ? (size_t)j * P + i : 0;
-        T bxn, bxs, bye, byw, a, dd, nxy, nyx;
-        if constexpr (CLS) {
-            const T *row = tab + (size_t)cls[k] * PCW;
-            bxn = row[PR_BXY_N], bxs = row[PR_BXY], bye = row[PR_BYX_E], byw = row[PR_BYX];
-            a = row[PR_NXX], dd = row[PR_NYY];
-            if (!GEO) nxy = row[PR_NXY], nyx = row[PR_NYX];
-        } else {
-            bxn = c.bxy[k + P], bxs = c.bxy[k], bye = c.byx[k + 1], byw = c.byx[k];
-            a = c.nxx[k], dd = c.nyy[k];
-            if (!GEO) nxy = c.nxy[k], nyx = c.nyx[k];
-        }
-        const T gxv = bxn * s.spx[ly + 1][lx] - bxs * s.spx[ly][lx];
-        const T gyv = bye * s.spy[ly][lx + 1] - byw * s.spy[ly][lx];
+        const T bxn = c.bxy[k + P], bxs = c.bxy[k], bye = c.byx[k + 1], byw = c.byx[k];
+        const T a = c.nxx[k], dd = c.nyy[k];
         T b, cc;
         if (GEO) {
             b = cc = sqrt(a * dd);
         } else {
-            b = nxy;
-            cc = nyx;
+            b = c.nxy[k];
+            cc = c.nyx[k];
         }
-        s.snx[ly][lx] = in ? (T)0.5 * (a * gxv + b * gyv) : (T)0;
-        s.sny[ly][lx] = in ? (T)0.5 * (cc * gxv + dd * gyv) : (T)0;
+        T sx, sy;
+        strain_node(bxn, bxs, bye, byw, a, b, cc, dd, s.spx[ly + 1][lx], s.spx[ly][lx], s.spy[ly][lx + 1],
+                    s.spy[ly][lx], sx, sy);
+        s.snx[ly][lx] = in ? sx : (T)0;
+        s.sny[ly][lx] = in ? sy : (T)0;
     }
 }
 
@@ -1291,8 +1307,8 @@ template <class T>
 __device__ inline void pred_tile_K(const PredTile<T> &s, const ViscCoefT<T> &c, size_t k, int ly, int tx, T &kx,
                                    T &ky) {
     const T bxx = c.bxx[k], bxy = c.bxy[k], byy = c.byy[k], byx = c.byx[k];
-    kx = bxx * (s.sxx[ly][tx + 1] - s.sxx[ly][tx]) + bxy * (s.snx[ly + 1][tx + 1] - s.snx[ly][tx + 1]);
-    ky = byy * (s.syy[ly + 1][tx] - s.syy[ly][tx]) + byx * (s.sny[ly + 1][tx + 1] - s.sny[ly + 1][tx]);
+    kx = strain_face(bxx, s.sxx[ly][tx + 1], s.sxx[ly][tx], bxy, s.snx[ly + 1][tx + 1], s.snx[ly][tx + 1]);
+    ky = strain_face(byy, s.syy[ly + 1][tx], s.syy[ly][tx], byx, s.sny[ly + 1][tx + 1], s.sny[ly + 1][tx]);
 }
 
 // K v at tile entry (ly, tx) of a tile without stored cell strains: the two
@@ -1306,18 +1322,38 @@ __device__ inline void pred_tile_K(const PredTileNx<T> &s, const ViscCoefT<T> &c
     const size_t k0 = in0 ? k : 1, k1 = in1 ? k + 1 : 1;
     const T w0 = c.wxx[k0], e0 = c.bxx[k0], b0 = c.bxx[k0 - 1];
     const T w1 = c.wxx[k1], e1 = c.bxx[k1], b1 = c.bxx[k1 - 1];
-    const T s0 = in0 ? w0 * (e0 * s.spx[ly + 1][tx + 1] - b0 * s.spx[ly + 1][tx]) : (T)0;
-    const T s1 = in1 ? w1 * (e1 * s.spx[ly + 1][tx + 2] - b1 * s.spx[ly + 1][tx + 1]) : (T)0;
-    kx = bxx * (s1 - s0) + bxy * (s.snx[ly + 1][tx + 1] - s.snx[ly][tx + 1]);
+    const T s0 = in0 ? strain_cell(w0, e0, b0, s.spx[ly + 1][tx + 1], s.spx[ly + 1][tx]) : (T)0;
+    const T s1 = in1 ? strain_cell(w1, e1, b1, s.spx[ly + 1][tx + 2], s.spx[ly + 1][tx + 1]) : (T)0;
+    kx = strain_face(bxx, s1, s0, bxy, s.snx[ly + 1][tx + 1], s.snx[ly][tx + 1]);
     // the y-face's two cell strains S_yy (cells j and j + 1 of column i)
     const int j = (int)(k / (size_t)P);
     const bool iny0 = j >= 1, iny1 = j + 1 < rows;
     const size_t q0 = iny0 ? k : (size_t)P, q1 = iny1 ? k + P : (size_t)P;
     const T wy0 = c.wyy[q0], n0 = c.byy[q0], m0 = c.byy[q0 - P];
     const T wy1 = c.wyy[q1], n1 = c.byy[q1], m1 = c.byy[q1 - P];
-    const T t0 = iny0 ? wy0 * (n0 * s.spy[ly + 1][tx + 1] - m0 * s.spy[ly][tx + 1]) : (T)0;
-    const T t1 = iny1 ? wy1 * (n1 * s.spy[ly + 2][tx + 1] - m1 * s.spy[ly + 1][tx + 1]) : (T)0;
-    ky = byy * (t1 - t0) + byx * (s.sny[ly + 1][tx + 1] - s.sny[ly + 1][tx]);
+    const T t0 = iny0 ? strain_cell(wy0, n0, m0, s.spy[ly + 1][tx + 1], s.spy[ly][tx + 1]) : (T)0;
+    const T t1 = iny1 ? strain_cell(wy1, n1, m1, s.spy[ly + 2][tx + 1], s.spy[ly + 1][tx + 1]) : (T)0;
+    ky = strain_face(byy, t1, t0, byx, s.sny[ly + 1][tx + 1], s.sny[ly + 1][tx]);
+}
+
+// Node strain at tile node (ly, lx) (node (r0 - 1 + ly, c0 - 1 + lx)) from the
+// node's row of the class table: the operations of pred_tile_strains.
+template <class T, bool GEO>
+__device__ inline void pred_node_strain_row(PredTileNx<T> &s, const T *row, int ly, int lx, bool in) {
+    const T bxn = row[PR_BXY_N], bxs = row[PR_BXY], bye = row[PR_BYX_E], byw = row[PR_BYX];
+    const T a = row[PR_NXX], dd = row[PR_NYY];
+    T b, cc;
+    if (GEO) {
+        b = cc = sqrt(a * dd);
+    } else {
+        b = row[PR_NXY];
+        cc = row[PR_NYX];
+    }
+    T sx, sy;
+    strain_node(bxn, bxs, bye, byw, a, b, cc, dd, s.spx[ly + 1][lx], s.spx[ly][lx], s.spy[ly][lx + 1],
+                s.spy[ly][lx], sx, sy);
+    s.snx[ly][lx] = in ? sx : (T)0;
+    s.sny[ly][lx] = in ? sy : (T)0;
 }
 
 // The same with the values from the entry's row of the class table (where a
@@ -1329,16 +1365,16 @@ __device__ inline void pred_tile_K_row(const PredTileNx<T> &s, const T *row, siz
     const bool in0 = i >= 1, in1 = i + 1 < P;
     const T w0 = row[PR_WXX], b0 = row[PR_BXX_W];
     const T w1 = row[PR_WXX_E], e1 = row[PR_BXX_E];
-    const T s0 = in0 ? w0 * (bxx * s.spx[ly + 1][tx + 1] - b0 * s.spx[ly + 1][tx]) : (T)0;
-    const T s1 = in1 ? w1 * (e1 * s.spx[ly + 1][tx + 2] - bxx * s.spx[ly + 1][tx + 1]) : (T)0;
-    kx = bxx * (s1 - s0) + bxy * (s.snx[ly + 1][tx + 1] - s.snx[ly][tx + 1]);
+    const T s0 = in0 ? strain_cell(w0, bxx, b0, s.spx[ly + 1][tx + 1], s.spx[ly + 1][tx]) : (T)0;
+    const T s1 = in1 ? strain_cell(w1, e1, bxx, s.spx[ly + 1][tx + 2], s.spx[ly + 1][tx + 1]) : (T)0;
+    kx = strain_face(bxx, s1, s0, bxy, s.snx[ly + 1][tx + 1], s.snx[ly][tx + 1]);
     const int j = (int)(k / (size_t)P);
     const bool iny0 = j >= 1, iny1 = j + 1 < rows;
     const T wy0 = row[PR_WYY], m0 = row[PR_BYY_S];
     const T wy1 = row[PR_WYY_N], n1 = row[PR_BYY_N];
-    const T t0 = iny0 ? wy0 * (byy * s.spy[ly + 1][tx + 1] - m0 * s.spy[ly][tx + 1]) : (T)0;
-    const T t1 = iny1 ? wy1 * (n1 * s.spy[ly + 2][tx + 1] - byy * s.spy[ly + 1][tx + 1]) : (T)0;
-    ky = byy * (t1 - t0) + byx * (s.sny[ly + 1][tx + 1] - s.sny[ly + 1][tx]);
+    const T t0 = iny0 ? strain_cell(wy0, byy, m0, s.spy[ly + 1][tx + 1], s.spy[ly][tx + 1]) : (T)0;
+    const T t1 = iny1 ? strain_cell(wy1, n1, byy, s.spy[ly + 2][tx + 1], s.spy[ly + 1][tx + 1]) : (T)0;
+    ky = strain_face(byy, t1, t0, byx, s.sny[ly + 1][tx + 1], s.sny[ly + 1][tx]);
 }
 
 // Predictor CG with one launch per iteration (Jacobi-preconditioned CG on
@@ -1502,7 +1538,29 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(7))) void k_
         }
     }
     __syncthreads();
-    if (live) pred_tile_strains<T, GEO, PredTileNx<T>, CLS>(s, pc.vc, P, rows, c0, r0, pc.cls, pc.tab);
+    if (live) {
+        if constexpr (CLS) {
+            // node strains: the nodes at this thread's own entries, whose class
+            // rows it already indexes, then the tile's first row and column of
+            // nodes
+#pragma unroll
+            for (int m = 0; m < RW; ++m) {
+                const int ly = ty + 4 * m;
+                const int j = r0 + ly, i = c0 + tx;
+                pred_node_strain_row<T, GEO>(s, pc.tab + (size_t)cl[m] * PCW, ly + 1, tx + 1,
+                                             (j + 1 < rows) && (i + 1 < P));
+            }
+            for (int e = threadIdx.x; e < TX + 1 + HTY; e += NT) {
+                const int ly = e <= TX ? 0 : e - TX, lx = e <= TX ? e : 0;
+                const int j = r0 - 1 + ly, i = c0 - 1 + lx;
+                const bool in = (j >= 0) && (j + 1 < rows) && (i >= 0) && (i + 1 < P);
+                const size_t k = in ? (size_t)j * P + i : 0;
+                pred_node_strain_row<T, GEO>(s, pc.tab + (size_t)pc.cls[k] * PCW, ly, lx, in);
+            }
+        } else {
+            pred_tile_strains<T, GEO, PredTileNx<T>>(s, pc.vc, P, rows, c0, r0);
+        }
+    }
     __syncthreads();
     if (live) {
         const T rt = (T)pc.rt, mu = (T)pc.mu;
