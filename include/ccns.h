@@ -167,7 +167,10 @@ size_t ccns_workspace_bytes(const ccns_grid *grid, const ccns_params *params);
  *              the staggered Dirichlet data of Sec. 4, constant in time.
  *  dev_workspace   device buffer of ws_bytes >= ccns_workspace_bytes()
  *  hip_stream  hipStream_t (NULL = default stream)
- * Errors: CCNS_EINVAL, CCNS_ENOMEM, CCNS_EDEVICE. */
+ * With coef_tables = 0 it also builds the predictor's coefficient classes
+ * (host work of one pass over the layout) and uploads their table.
+ * Errors: CCNS_EINVAL (also for precision, precond or coef_tables out of
+ * range), CCNS_ENOMEM, CCNS_EDEVICE. */
 ccns_status ccns_ctx_create(const ccns_grid *grid, const ccns_params *params,
                             const double *caps_host, const double *dirichlet_host,
                             void *dev_workspace, size_t ws_bytes, void *hip_stream,

@@ -2948,7 +2948,8 @@ ccns_status ccns_ctx_create(const ccns_grid *grid, const ccns_params *params, co
     if (!out) return CCNS_EINVAL;
     *out = nullptr;
     if (!grid || !params || !caps_host || !dirichlet_host || !dev_workspace) return CCNS_EINVAL;
-    if (params->precision < 0 || params->precision > 1 || params->precond < 0 || params->precond > 1)
+    if (params->precision < 0 || params->precision > 1 || params->precond < 0 || params->precond > 1 ||
+        params->coef_tables < 0 || params->coef_tables > 1)
         return CCNS_EINVAL;
     ccns_ctx *c = new (std::nothrow) ccns_ctx();
     if (!c) return CCNS_ENOMEM;
