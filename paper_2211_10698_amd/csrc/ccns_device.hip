@@ -2575,10 +2575,10 @@ T *vcycle(ccns_ctx *c, std::vector<ccns_ctx::LevelT<T>> &mg, size_t l, const T *
     const int nb = ((gx * gy + 7) / 8) * 8;
     ccns_ctx::LevelT<T> &C = mg[l + 1];
     const T om = (T)MG_OMEGA;
-    // the finest level in the staged forms (measured: faster on the way down
-    // in FP64 and on the way up in both precisions; the FP32 way down is
+    // levels with tall tiles in the staged forms (measured: faster on the way
+    // down in FP64 and on the way up in both precisions; the FP32 way down is
     // faster in the latency form at every level)
-    if (l == 0 && sizeof(T) == 8)
+    if (!small && sizeof(T) == 8)
         k_mg_down_staged<T><<<nb, NT, 0, s>>>(L.L.nx, L.L.ny, L.L.pitch, gx, pc, b, L.x, C.L.pitch, C.L.nx, C.L.ny,
                                               C.dinv, C.b, om, done);
     else if (small)
@@ -2592,12 +2592,12 @@ T *vcycle(ccns_ctx *c, std::vector<ccns_ctx::LevelT<T>> &mg, size_t l, const T *
         k_mg_up_staged<T, true><<<nb, NT, 0, s>>>(L.L.nx, L.L.ny, L.L.pitch, gx, pc, b, L.x, xc, C.L.pitch, L.xt,
                                                   om, c->part[PB_UPD], nb, done);
         k_reduce_partials<4><<<1, NT, 0, s>>>(c->part[PB_UPD], nb, c->part[PB_MG]);
-    } else if (small) {
+    } else if (!small) {
+        k_mg_up_staged<T, false><<<nb, NT, 0, s>>>(L.L.nx, L.L.ny, L.L.pitch, gx, pc, b, L.x, xc, C.L.pitch, L.xt,
+                                                   om, nullptr, nb, done);
+    } else {
         k_mg_up<T, false, MTY_SMALL><<<nb, NT, 0, s>>>(L.L.nx, L.L.ny, L.L.pitch, gx, pc, b, L.x, xc, C.L.pitch,
                                                        L.xt, om, nullptr, nb, done);
-    } else {
-        k_mg_up<T, false><<<nb, NT, 0, s>>>(L.L.nx, L.L.ny, L.L.pitch, gx, pc, b, L.x, xc, C.L.pitch, L.xt, om,
-                                            nullptr, nb, done);
     }
     return L.xt;
 }
