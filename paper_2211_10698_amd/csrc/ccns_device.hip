@@ -1614,42 +1614,107 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(7))) void k_
 //  MIX = true (precision 1): r is rounded to float into r32 (right-hand side
 //  of the inner solve, whose start value x32 is cleared); partials
 //  (r32.r32, r32.z, z, r32, r32.r32, f.f, r.r) with z = M32^-1 r32.
-template <bool MIX, bool GEO>
+// With CLS the coefficients come from the class table, as in k_pred_cg.
+template <bool MIX, bool GEO, bool CLS = false>
 __global__ __launch_bounds__(NT) void k_pred_resid(int P, int rows, int gx, int gy, size_t n, PredCoefT<double> pc,
                                                    const double *__restrict__ rhs, const double *__restrict__ xs,
                                                    double *__restrict__ r, CgState *st, double *pout,
                                                    float *__restrict__ r32, float *__restrict__ x32,
                                                    const float *__restrict__ hd32) {
-    __shared__ PredTile<double> s;
+    __shared__ PredTileNx<double> s;
     const int L = logical_group(((gridDim.x + 7) / 8) * 8);
     const bool live = L < gx * gy;
     const int c0 = (L % gx) * TX, r0 = (L / gx) * HTY;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
     double v[7] = {0, 0, 0, 0, 0, 0, 0};
+    constexpr int RW = HTY / 4;
+    int cl[RW];
+    // face volumes at entry k (they mark the unknowns)
+    auto volumes = [&](size_t k, double &mx, double &my, int &ck) {
+        if constexpr (CLS) {
+            ck = pc.cls[k];
+            const double *row = pc.tab + (size_t)ck * PCW;
+            mx = row[PR_VU];
+            my = row[PR_VV];
+        } else {
+            mx = pc.vu[k];
+            my = pc.vv[k];
+        }
+    };
     if (live) {
-        for (int e = threadIdx.x; e < (HTY + 2) * (TX + 2); e += NT) {
-            const int ly = e / (TX + 2), lx = e - ly * (TX + 2);
+#pragma unroll
+        for (int m = 0; m < RW; ++m) {
+            const int ly = ty + 4 * m;
+            const int j = r0 + ly, i = c0 + tx;
+            const bool in = j < rows;
+            const size_t k = in ? (size_t)j * P + i : 0;
+            double mx, my;
+            volumes(k, mx, my, cl[m]);
+            const double ux = xs[k], uy = xs[n + k];
+            s.spx[ly + 1][tx + 1] = (in && mx > 0.0) ? ux : 0.0;
+            s.spy[ly + 1][tx + 1] = (in && my > 0.0) ? uy : 0.0;
+        }
+        // the one-face halo, as in k_pred_cg
+        for (int e = threadIdx.x; e < 2 * (TX + 2) + 2 * HTY; e += NT) {
+            int ly, lx;
+            if (e < 2 * (TX + 2)) {
+                ly = e < TX + 2 ? 0 : HTY + 1;
+                lx = e < TX + 2 ? e : e - (TX + 2);
+            } else {
+                const int f = e - 2 * (TX + 2);
+                ly = 1 + (f >> 1);
+                lx = (f & 1) ? TX + 1 : 0;
+            }
             const int j = r0 - 1 + ly, i = c0 - 1 + lx;
             const bool in = (j >= 0) && (j < rows) && (i >= 0) && (i < P);
             const size_t k = in ? (size_t)j * P + i : 0;
-            const double mx = pc.vu[k], my = pc.vv[k], ux = xs[k], uy = xs[n + k];
+            double mx, my;
+            int ck;
+            volumes(k, mx, my, ck);
+            const double ux = xs[k], uy = xs[n + k];
             s.spx[ly][lx] = (in && mx > 0.0) ? ux : 0.0;
             s.spy[ly][lx] = (in && my > 0.0) ? uy : 0.0;
         }
     }
     __syncthreads();
-    if (live) pred_tile_strains<double, GEO>(s, pc.vc, P, rows, c0, r0);
+    if (live) {
+        if constexpr (CLS) {
+#pragma unroll
+            for (int m = 0; m < RW; ++m) {
+                const int ly = ty + 4 * m;
+                const int j = r0 + ly, i = c0 + tx;
+                pred_node_strain_row<double, GEO>(s, pc.tab + (size_t)cl[m] * PCW, ly + 1, tx + 1,
+                                                  (j + 1 < rows) && (i + 1 < P));
+            }
+            for (int e = threadIdx.x; e < TX + 1 + HTY; e += NT) {
+                const int ly = e <= TX ? 0 : e - TX, lx = e <= TX ? e : 0;
+                const int j = r0 - 1 + ly, i = c0 - 1 + lx;
+                const bool in = (j >= 0) && (j + 1 < rows) && (i >= 0) && (i + 1 < P);
+                const size_t k = in ? (size_t)j * P + i : 0;
+                pred_node_strain_row<double, GEO>(s, pc.tab + (size_t)pc.cls[k] * PCW, ly, lx, in);
+            }
+        } else {
+            pred_tile_strains<double, GEO, PredTileNx<double>>(s, pc.vc, P, rows, c0, r0);
+        }
+    }
     __syncthreads();
     if (live) {
-        const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-        for (int ly = ty; ly < HTY; ly += 4) {
+#pragma unroll
+        for (int m = 0; m < RW; ++m) {
+            const int ly = ty + 4 * m;
             const int j = r0 + ly, i = c0 + tx;
             if (j >= rows) break;
             const size_t k = (size_t)j * P + i;
-            double kv[2];
-            pred_tile_K<double>(s, pc.vc, k, ly, tx, kv[0], kv[1]);
-            const double m[2] = {pc.vu[k], pc.vv[k]};
+            double kv[2], mv[2], hd[2];
+            if constexpr (CLS) {
+                const double *row = pc.tab + (size_t)cl[m] * PCW;
+                pred_tile_K_row<double>(s, row, k, ly, tx, i, P, rows, kv[0], kv[1]);
+                mv[0] = row[PR_VU], mv[1] = row[PR_VV], hd[0] = row[PR_HDX], hd[1] = row[PR_HDY];
+            } else {
+                pred_tile_K<double>(s, pc.vc, k, ly, tx, i, P, rows, kv[0], kv[1]);
+                mv[0] = pc.vu[k], mv[1] = pc.vv[k], hd[0] = pc.hdx[k], hd[1] = pc.hdy[k];
+            }
             const double xv[2] = {s.spx[ly + 1][tx + 1], s.spy[ly + 1][tx + 1]};
-            const double hd[2] = {pc.hdx[k], pc.hdy[k]};
 #pragma unroll
             for (int comp = 0; comp < 2; ++comp) {
                 const size_t o = comp == 0 ? k : n + k;
@@ -1657,9 +1722,9 @@ __global__ __launch_bounds__(NT) void k_pred_resid(int P, int rows, int gx, int 
                     x32[o] = 0.0f;
                     r32[o] = 0.0f;
                 }
-                if (!(m[comp] > 0.0)) continue;
+                if (!(mv[comp] > 0.0)) continue;
                 const double f = rhs[o];
-                const double rv = f - (pc.rt * m[comp] * xv[comp] - pc.mu * kv[comp]);
+                const double rv = f - (pc.rt * mv[comp] * xv[comp] - pc.mu * kv[comp]);
                 if (MIX) {
                     const float rf = (float)rv;
                     r32[o] = rf;
@@ -2815,14 +2880,15 @@ void pred_residual(ccns_ctx *c, CgState *st) {
     const int nb = ((gx * gy + 7) / 8) * 8;
     float *r32 = MIX ? c->f[G_PRX] : nullptr, *x32 = MIX ? c->f[G_PXX] : nullptr;
     const float *hd32 = MIX ? c->f[G_HDX] : nullptr;
-    if (c->prm.visc_form == 0)
-        k_pred_resid<MIX, true><<<nb, NT, 0, c->stream>>>(L.pitch, L.rows, gx, gy, L.n, pd, c->a[A_RHSX],
-                                                          c->a[A_USX], c->a[A_PRX], st, c->part[PB_RHS], r32, x32,
-                                                          hd32);
-    else
-        k_pred_resid<MIX, false><<<nb, NT, 0, c->stream>>>(L.pitch, L.rows, gx, gy, L.n, pd, c->a[A_RHSX],
-                                                           c->a[A_USX], c->a[A_PRX], st, c->part[PB_RHS], r32, x32,
-                                                           hd32);
+    if (c->ncls) {
+        pd.cls = c->cls;
+        pd.tab = c->tab;
+    }
+    const bool geo = c->prm.visc_form == 0;
+    auto kern = c->ncls ? (geo ? k_pred_resid<MIX, true, true> : k_pred_resid<MIX, false, true>)
+                        : (geo ? k_pred_resid<MIX, true, false> : k_pred_resid<MIX, false, false>);
+    kern<<<nb, NT, 0, c->stream>>>(L.pitch, L.rows, gx, gy, L.n, pd, c->a[A_RHSX], c->a[A_USX], c->a[A_PRX], st,
+                                   c->part[PB_RHS], r32, x32, hd32);
     if (MIX)
         k_reduce_partials<7><<<1, NT, 0, c->stream>>>(c->part[PB_RHS], nb, c->part[PB_INIT]);
     else
