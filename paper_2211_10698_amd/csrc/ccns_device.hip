@@ -27,7 +27,6 @@
 #include <atomic>
 #include <string>
 #include <thread>
-#include <type_traits>
 #include <unordered_map>
 #include <vector>
 
@@ -1213,15 +1212,8 @@ __global__ __launch_bounds__(NT) void k_pois_dir_z(Dims d, PoisCoefT<T> pc, cons
 constexpr int HTY = 8;
 
 // LDS of a predictor tile: the staged face field on the tile and a one-face
-// halo, and its strains (cells and nodes) of eq:diag / eq:offdiag.
-template <class T>
-struct PredTile {
-    T spx[HTY + 2][TX + 2], spy[HTY + 2][TX + 2];
-    T sxx[HTY][TX + 1], syy[HTY + 1][TX];
-    T snx[HTY + 1][TX + 1], sny[HTY + 1][TX + 1];
-};
-// The same without the cell strains S_xx and S_yy, which the last phase then
-// forms where it needs them (smaller LDS: more work-groups per compute unit).
+// halo, and its node strains (eq:offdiag).  The cell strains (eq:diag) are
+// formed where a face needs them, which keeps the tile at 20 KB in FP64.
 template <class T>
 struct PredTileNx {
     T spx[HTY + 2][TX + 2], spy[HTY + 2][TX + 2];
@@ -1257,29 +1249,10 @@ __device__ inline T strain_face(T baa, T sp, T sm, T bab, T np, T nm) {
     return fma(baa, sp - sm, bab * (np - nm));
 }
 
-template <class T, bool GEO, class Tile = PredTile<T>>
-__device__ inline void pred_tile_strains(Tile &s, const ViscCoefT<T> &c, int P, int rows, int c0, int r0) {
-    // S_xx at cells (rows r0.., cols c0 .. c0+TX): x-faces i-1, i
-    if constexpr (!std::is_same<Tile, PredTileNx<T>>::value)
-    for (int e = threadIdx.x; e < HTY * (TX + 1); e += NT) {
-        const int ly = e / (TX + 1), lx = e - ly * (TX + 1);
-        const int j = r0 + ly, i = c0 + lx;
-        const bool in = (j < rows) && (i >= 1) && (i < P);
-        const size_t k = in ? (size_t)j * P + i : 1;
-        const T w = c.wxx[k], be = c.bxx[k], bw = c.bxx[k - 1];
-        s.sxx[ly][lx] = in ? strain_cell(w, be, bw, s.spx[ly + 1][lx + 1], s.spx[ly + 1][lx]) : (T)0;
-    }
-    // S_yy at cells (rows r0 .. r0+HTY, cols c0..): y-faces j-1, j
-    if constexpr (!std::is_same<Tile, PredTileNx<T>>::value)
-    for (int e = threadIdx.x; e < (HTY + 1) * TX; e += NT) {
-        const int ly = e / TX, lx = e - ly * TX;
-        const int j = r0 + ly, i = c0 + lx;
-        const bool in = (j >= 1) && (j < rows);
-        const size_t k = in ? (size_t)j * P + i : (size_t)P;
-        const T w = c.wyy[k], bn = c.byy[k], bs = c.byy[k - P];
-        s.syy[ly][lx] = in ? strain_cell(w, bn, bs, s.spy[ly + 1][lx + 1], s.spy[ly][lx + 1]) : (T)0;
-    }
-    // node strains (rows r0-1 .. r0+HTY-1, cols c0-1 .. c0+TX-1)
+// Node strains of the tile (eq:offdiag) from the coefficient arrays: nodes
+// (r0 - 1 .. r0 + HTY - 1) x (c0 - 1 .. c0 + TX - 1).
+template <class T, bool GEO>
+__device__ inline void pred_tile_strains(PredTileNx<T> &s, const ViscCoefT<T> &c, int P, int rows, int c0, int r0) {
     for (int e = threadIdx.x; e < (HTY + 1) * (TX + 1); e += NT) {
         const int ly = e / (TX + 1), lx = e - ly * (TX + 1);
         const int j = r0 - 1 + ly, i = c0 - 1 + lx;
@@ -1302,18 +1275,9 @@ __device__ inline void pred_tile_strains(Tile &s, const ViscCoefT<T> &c, int P, 
     }
 }
 
-// K v = visc(strain(v, 0)) (Sec. 4.3) at tile entry (ly, tx), index k.
-template <class T>
-__device__ inline void pred_tile_K(const PredTile<T> &s, const ViscCoefT<T> &c, size_t k, int ly, int tx, T &kx,
-                                   T &ky) {
-    const T bxx = c.bxx[k], bxy = c.bxy[k], byy = c.byy[k], byx = c.byx[k];
-    kx = strain_face(bxx, s.sxx[ly][tx + 1], s.sxx[ly][tx], bxy, s.snx[ly + 1][tx + 1], s.snx[ly][tx + 1]);
-    ky = strain_face(byy, s.syy[ly + 1][tx], s.syy[ly][tx], byx, s.sny[ly + 1][tx + 1], s.sny[ly + 1][tx]);
-}
-
-// K v at tile entry (ly, tx) of a tile without stored cell strains: the two
-// cell strains S_xx of the x-face and S_yy of the y-face are formed here,
-// with the same operations as in pred_tile_strains.
+// K v = visc(strain(v, 0)) (Sec. 4.3) at tile entry (ly, tx), index k: the two
+// cell strains S_xx of the x-face and S_yy of the y-face are formed here
+// (eq:diag), the node strains come from the tile.
 template <class T>
 __device__ inline void pred_tile_K(const PredTileNx<T> &s, const ViscCoefT<T> &c, size_t k, int ly, int tx, int i,
                                    int P, int rows, T &kx, T &ky) {
@@ -1558,7 +1522,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(7))) void k_
                 pred_node_strain_row<T, GEO>(s, pc.tab + (size_t)pc.cls[k] * PCW, ly, lx, in);
             }
         } else {
-            pred_tile_strains<T, GEO, PredTileNx<T>>(s, pc.vc, P, rows, c0, r0);
+            pred_tile_strains<T, GEO>(s, pc.vc, P, rows, c0, r0);
         }
     }
     __syncthreads();
@@ -1694,7 +1658,7 @@ __global__ __launch_bounds__(NT) void k_pred_resid(int P, int rows, int gx, int 
                 pred_node_strain_row<double, GEO>(s, pc.tab + (size_t)pc.cls[k] * PCW, ly, lx, in);
             }
         } else {
-            pred_tile_strains<double, GEO, PredTileNx<double>>(s, pc.vc, P, rows, c0, r0);
+            pred_tile_strains<double, GEO>(s, pc.vc, P, rows, c0, r0);
         }
     }
     __syncthreads();
@@ -1767,9 +1731,10 @@ __global__ __launch_bounds__(NT) void k_pred_resid(int P, int rows, int gx, int 
 // (rho/tau) M U^n - (3/2) rho conv^n + (1/2) rho conv^{n-1} - pres(P) +
 // mu (K U^n + 2 visc(strain(0, D))) + rho M g, and U* := U^n as the start
 // value, on the tiles of k_pred_cg: K U^n from the masked U^n staged in LDS
-// with its strains formed once per cell and node; convection and the
-// pressure gradient in index form.
-template <bool GEO>
+// with its node strains formed once per node (cell strains where a face
+// needs them); convection and the pressure gradient in index form.  With CLS
+// the viscous coefficients come from the class table, as in k_pred_cg.
+template <bool GEO, bool CLS = false>
 __global__ __launch_bounds__(NT) void k_pred_rhs(int P, int rows, int gx, int gy, size_t n, PredCoefT<double> pc,
                                                  const double *__restrict__ ax, const double *__restrict__ ay,
                                                  const double *__restrict__ hbx, const double *__restrict__ hby,
@@ -1780,30 +1745,94 @@ __global__ __launch_bounds__(NT) void k_pred_rhs(int P, int rows, int gx, int gy
                                                  double *__restrict__ convy, double *__restrict__ rhs,
                                                  double *__restrict__ xs, double rho, double gxv, double gyv,
                                                  int conv_valid) {
-    __shared__ PredTile<double> s;
+    __shared__ PredTileNx<double> s;
     const int L = logical_group(((gridDim.x + 7) / 8) * 8);
     if (L >= gx * gy) return;
     const int c0 = (L % gx) * TX, r0 = (L / gx) * HTY;
-    for (int e = threadIdx.x; e < (HTY + 2) * (TX + 2); e += NT) {
-        const int ly = e / (TX + 2), lx = e - ly * (TX + 2);
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    constexpr int RW = HTY / 4;
+    int cl[RW];
+    // face volumes at entry k (they mark the unknowns)
+    auto volumes = [&](size_t k, double &mx, double &my, int &ck) {
+        if constexpr (CLS) {
+            ck = pc.cls[k];
+            const double *row = pc.tab + (size_t)ck * PCW;
+            mx = row[PR_VU];
+            my = row[PR_VV];
+        } else {
+            mx = pc.vu[k];
+            my = pc.vv[k];
+        }
+    };
+#pragma unroll
+    for (int m = 0; m < RW; ++m) {
+        const int ly = ty + 4 * m;
+        const int j = r0 + ly, i = c0 + tx;
+        const bool in = j < rows;
+        const size_t k = in ? (size_t)j * P + i : 0;
+        double mx, my;
+        volumes(k, mx, my, cl[m]);
+        const double u = ux[k], v = uy[k];
+        s.spx[ly + 1][tx + 1] = (in && mx > 0.0) ? u : 0.0;
+        s.spy[ly + 1][tx + 1] = (in && my > 0.0) ? v : 0.0;
+    }
+    // the one-face halo, as in k_pred_cg
+    for (int e = threadIdx.x; e < 2 * (TX + 2) + 2 * HTY; e += NT) {
+        int ly, lx;
+        if (e < 2 * (TX + 2)) {
+            ly = e < TX + 2 ? 0 : HTY + 1;
+            lx = e < TX + 2 ? e : e - (TX + 2);
+        } else {
+            const int f = e - 2 * (TX + 2);
+            ly = 1 + (f >> 1);
+            lx = (f & 1) ? TX + 1 : 0;
+        }
         const int j = r0 - 1 + ly, i = c0 - 1 + lx;
         const bool in = (j >= 0) && (j < rows) && (i >= 0) && (i < P);
         const size_t k = in ? (size_t)j * P + i : 0;
-        const double mx = pc.vu[k], my = pc.vv[k], u = ux[k], v = uy[k];
+        double mx, my;
+        int ck;
+        volumes(k, mx, my, ck);
+        const double u = ux[k], v = uy[k];
         s.spx[ly][lx] = (in && mx > 0.0) ? u : 0.0;
         s.spy[ly][lx] = (in && my > 0.0) ? v : 0.0;
     }
     __syncthreads();
-    pred_tile_strains<double, GEO>(s, pc.vc, P, rows, c0, r0);
+    if constexpr (CLS) {
+#pragma unroll
+        for (int m = 0; m < RW; ++m) {
+            const int ly = ty + 4 * m;
+            const int j = r0 + ly, i = c0 + tx;
+            pred_node_strain_row<double, GEO>(s, pc.tab + (size_t)cl[m] * PCW, ly + 1, tx + 1,
+                                              (j + 1 < rows) && (i + 1 < P));
+        }
+        for (int e = threadIdx.x; e < TX + 1 + HTY; e += NT) {
+            const int ly = e <= TX ? 0 : e - TX, lx = e <= TX ? e : 0;
+            const int j = r0 - 1 + ly, i = c0 - 1 + lx;
+            const bool in = (j >= 0) && (j + 1 < rows) && (i >= 0) && (i + 1 < P);
+            const size_t k = in ? (size_t)j * P + i : 0;
+            pred_node_strain_row<double, GEO>(s, pc.tab + (size_t)pc.cls[k] * PCW, ly, lx, in);
+        }
+    } else {
+        pred_tile_strains<double, GEO>(s, pc.vc, P, rows, c0, r0);
+    }
     __syncthreads();
-    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-    for (int ly = ty; ly < HTY; ly += 4) {
+#pragma unroll
+    for (int m = 0; m < RW; ++m) {
+        const int ly = ty + 4 * m;
         const int j = r0 + ly, i = c0 + tx;
         if (j >= rows) break;
         const size_t k = (size_t)j * P + i;
-        double kx, ky;
-        pred_tile_K<double>(s, pc.vc, k, ly, tx, kx, ky);
-        const double u = ux[k], v = uy[k], mx = pc.vu[k], my = pc.vv[k];
+        double kx, ky, mx, my;
+        if constexpr (CLS) {
+            const double *row = pc.tab + (size_t)cl[m] * PCW;
+            pred_tile_K_row<double>(s, row, k, ly, tx, i, P, rows, kx, ky);
+            mx = row[PR_VU], my = row[PR_VV];
+        } else {
+            pred_tile_K<double>(s, pc.vc, k, ly, tx, i, P, rows, kx, ky);
+            mx = pc.vu[k], my = pc.vv[k];
+        }
+        const double u = ux[k], v = uy[k];
         xs[k] = u;
         xs[n + k] = v;
         if (mx > 0.0) {
@@ -2815,7 +2844,13 @@ void predictor_rhs(ccns_ctx *c) {
     const Layout &L = c->w.L;
     const int gx = L.pitch / TX, gy = (L.rows + HTY - 1) / HTY;
     const int nb = ((gx * gy + 7) / 8) * 8;
-    auto k = c->prm.visc_form == 0 ? k_pred_rhs<true> : k_pred_rhs<false>;
+    if (c->ncls) {
+        pc.cls = c->cls;
+        pc.tab = c->tab;
+    }
+    const bool geo = c->prm.visc_form == 0;
+    auto k = c->ncls ? (geo ? k_pred_rhs<true, true> : k_pred_rhs<false, true>)
+                     : (geo ? k_pred_rhs<true, false> : k_pred_rhs<false, false>);
     k<<<nb, NT, 0, c->stream>>>(L.pitch, L.rows, gx, gy, L.n, pc, c->a[A_AX], c->a[A_AY], c->a[A_HBX], c->a[A_HBY],
                                 c->a[A_DX], c->a[A_DY], c->a[A_UX], c->a[A_UY], c->a[A_P], c->a[A_VDX], c->a[A_VDY],
                                 c->a[A_CONVX], c->a[A_CONVY], c->a[A_RHSX], c->a[A_USX], c->prm.rho, c->prm.gx,
