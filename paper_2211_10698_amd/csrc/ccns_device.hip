@@ -1221,9 +1221,10 @@ struct PredTileNx {
 };
 
 // The strains of the staged field (rows r0-1 .. r0+HTY, cols c0-1 .. c0+TX
-// staged in spx, spy), formed once per cell and node.  GEO: the node weights
-// are the symmetric geometric form (cross weight = sqrt of the product of the
-// two diagonal ones), so the cross weights are formed instead of read.
+// staged in spx, spy).  GEO: the node weights are the symmetric geometric form
+// (cross weight = sqrt of the product of the two diagonal ones), so the cross
+// weights are formed instead of read.
+//
 // The strain arithmetic of the predictor tiles, shared by the kernels that
 // read the coefficient arrays and those that read the class table.  Every
 // product that meets a sum is written as an explicit fused multiply-add, so
