@@ -155,10 +155,18 @@ __global__ __launch_bounds__(NT) void k_pois_rhs(Dims d, PoisCoef pc, const doub
                                                  double *__restrict__ b, double scale, double *pout) {
     const size_t P = d.pitch;
     double v[1] = {0.0};
-    for_cells(d, [&](int, int j, int i, size_t k) {
+    struct In {
+        double ae, ue, aw, uw, an, vn, as, vs, h, dv;
+    };
+    auto load = [&](size_t k) {
+        // the west and south neighbours exist for every real cell
+        const size_t kw = k >= 1 ? k - 1 : k, ks = k >= P ? k - P : k;
+        return In{ax[k], usx[k], ax[kw], usx[kw], ay[k], usy[k], ay[ks], usy[ks], het[k], pc.dinv[k]};
+    };
+    for_cells_batched<TY / 4>(d, load, [&](int, int j, int i, size_t k, const In &q) {
         if (i < 1 || i > d.nx || j < 1 || j > d.ny) return;
-        const double c = ax[k] * usx[k] - ax[k - 1] * usx[k - 1] + ay[k] * usy[k] - ay[k - P] * usy[k - P] + het[k];
-        const double bv = pc.dinv[k] > 0.0 ? scale * c : 0.0;
+        const double c = q.ae * q.ue - q.aw * q.uw + q.an * q.vn - q.as * q.vs + q.h;
+        const double bv = q.dv > 0.0 ? scale * c : 0.0;
         b[k] = bv;
         v[0] += bv;
     });
@@ -1869,10 +1877,17 @@ __global__ __launch_bounds__(NT) void k_correct(Dims d, const double *__restrict
                                                 const double *__restrict__ phi, double *__restrict__ ux,
                                                 double *__restrict__ uy, double s) {
     const size_t P = d.pitch;
-    for_cells(d, [&](int, int j, int i, size_t k) {
-        const double g1 = gx[k], g2 = gy[k];
-        ux[k] = (g1 != 0.0) ? usx[k] - s * g1 * (phi[k + 1] - phi[k]) : usx[k];
-        uy[k] = (g2 != 0.0) ? usy[k] - s * g2 * (phi[k + P] - phi[k]) : usy[k];
+    struct In {
+        double g1, g2, us, vs, p0, pe, pn;
+    };
+    auto load = [&](size_t k) {
+        // the east and north neighbours exist wherever g1, g2 are nonzero
+        const size_t ke = k + 1 < d.n ? k + 1 : k, kn = k + P < d.n ? k + P : k;
+        return In{gx[k], gy[k], usx[k], usy[k], phi[k], phi[ke], phi[kn]};
+    };
+    for_cells_batched<TY / 4>(d, load, [&](int, int, int, size_t k, const In &v) {
+        ux[k] = (v.g1 != 0.0) ? v.us - s * v.g1 * (v.pe - v.p0) : v.us;
+        uy[k] = (v.g2 != 0.0) ? v.vs - s * v.g2 * (v.pn - v.p0) : v.vs;
     });
 }
 
@@ -2042,7 +2057,6 @@ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 // Partial-sum buffers: each holds up to 8 slots of NBMAX groups.
 enum Part { PB_RHS, PB_INIT, PB_DIR, PB_UPD, PB_DIAG, PB_MG, PB_COUNT };
-constexpr int TY = 8;   // tile rows of the face kernels and simple cell kernels
 
 // Multigrid levels: grid sizes from the fine one by halving (rounding up)
 // until both sides are at most 16 cells.

@@ -12,6 +12,7 @@ namespace ccns {
 
 constexpr int NT = 256;     // threads per work-group (4 wavefronts)
 constexpr int TX = 64;      // tile width: one wavefront per tile row
+constexpr int TY = 8;       // tile rows of the face kernels and simple cell kernels
 constexpr int NBMAX = 512;  // at most this many work-groups per kernel
 
 // A field grid split in tiles of TX x ty entries.  Work-group b works on a
@@ -53,6 +54,30 @@ __device__ inline void for_cells(const Dims &d, F f) {
         for (int rr = ty; rr < d.ty; rr += 4) {
             const int j = r0 + rr;
             if (j < d.rows) f(comp, j, i, (size_t)j * d.pitch + i);
+        }
+    });
+}
+
+// The same for tiles of exactly 4 R rows, in two passes per tile: load(k)
+// for each of the thread's R entries (k = 0 stands in for entries past the
+// last row), then f(comp, j, i, k, loaded value) for the real ones.  All of
+// a thread's loads are then in flight together instead of one entry's loads
+// waiting for the previous entry's.
+template <int R, class LD, class F>
+__device__ inline void for_cells_batched(const Dims &d, LD load, F f) {
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    for_tiles(d, [&](int comp, int c0, int r0) {
+        const int i = c0 + tx;
+        decltype(load((size_t)0)) vals[R];
+#pragma unroll
+        for (int m = 0; m < R; ++m) {
+            const int j = r0 + ty + 4 * m;
+            vals[m] = load(j < d.rows ? (size_t)j * d.pitch + i : (size_t)0);
+        }
+#pragma unroll
+        for (int m = 0; m < R; ++m) {
+            const int j = r0 + ty + 4 * m;
+            if (j < d.rows) f(comp, j, i, (size_t)j * d.pitch + i, vals[m]);
         }
     });
 }
