@@ -201,22 +201,33 @@ __global__ __launch_bounds__(NT) void k_pois_init(Dims d, PoisCoef pc, double *_
     }
     const size_t P = d.pitch;
     double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    for_cells(d, [&](int, int j, int i, size_t k) {
-        const double dv = pc.dinv[k];
+    struct In {
+        double dv, bk, ce, cw, cn, cs, x0, xe, xw, xn, xs;
+        float d32;
+    };
+    auto load = [&](size_t k) {
+        // the four neighbours exist for every unknown
+        const size_t kw = k >= 1 ? k - 1 : k, ks = k >= P ? k - P : k;
+        const size_t ke = k + 1 < d.n ? k + 1 : k, kn = k + P < d.n ? k + P : k;
+        return In{pc.dinv[k], b[k], pc.cx[k], pc.cx[kw], pc.cy[k], pc.cy[ks], x[k], x[ke], x[kw], x[kn], x[ks],
+                  MIX ? dinv32[k] : 0.0f};
+    };
+    for_cells_batched<TY / 4>(d, load, [&](int, int, int, size_t k, const In &q) {
+        const double dv = q.dv;
         if (MIX) {
             x32[k] = 0.0f;
             r32[k] = 0.0f;
         }
         if (!(dv > 0.0)) return;
-        const double bp = b[k] - mb;
+        const double bp = q.bk - mb;
         if (pin) b[k] = bp;
-        const double ce = pc.cx[k], cw = pc.cx[k - 1], cn = pc.cy[k], cs = pc.cy[k - P];
-        const double Axv = (ce + cw + cn + cs) * x[k] - ce * x[k + 1] - cw * x[k - 1] - cn * x[k + P] - cs * x[k - P];
+        const double ce = q.ce, cw = q.cw, cn = q.cn, cs = q.cs;
+        const double Axv = (ce + cw + cn + cs) * q.x0 - ce * q.xe - cw * q.xw - cn * q.xn - cs * q.xs;
         const double rv = -bp - Axv;
         if (MIX) {
             const float rf = (float)rv;
             r32[k] = rf;
-            const float sf = dinv32[k] * rf;
+            const float sf = q.d32 * rf;
             const double rd = rf, sd = sf;
             v[0] += rd * rd;
             v[1] += rd * sd;
