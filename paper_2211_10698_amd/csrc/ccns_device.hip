@@ -1191,27 +1191,55 @@ __global__ __launch_bounds__(NT) void k_pois_dir_z(Dims d, PoisCoefT<T> pc, cons
     const int P = d.pitch;
     const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
     double v[1] = {0.0};
+    // every load of a phase is issued before its first use, and the tile
+    // phase's operands before the barrier (as in the staged cycle kernels)
+    constexpr int NS = (PTY + 2) * (TX + 2), IS = (NS + NT - 1) / NT, R = PTY / 4;
     for_tiles(d, [&](int, int c0, int r0) {
-        for (int e = threadIdx.x; e < (PTY + 2) * (TX + 2); e += NT) {
-            const int ly = e / (TX + 2), lx = e - ly * (TX + 2);
-            const int j = r0 - 1 + ly, i = c0 - 1 + lx;
-            const bool in = (j >= 0) && (j < d.rows) && (i >= 0) && (i < P);
+        {
+            T di[IS], zv[IS], po[IS];
+#pragma unroll
+            for (int u = 0; u < IS; ++u) {
+                const int e = threadIdx.x + u * NT;
+                const int ly = e / (TX + 2), lx = e - ly * (TX + 2);
+                const int j = r0 - 1 + ly, i = c0 - 1 + lx;
+                const bool in = (e < NS) && (j >= 0) && (j < d.rows) && (i >= 0) && (i < P);
+                const size_t k = in ? (size_t)j * P + i : 0;
+                di[u] = pc.dinv[k];
+                zv[u] = z[k];
+                po[u] = first ? (T)0 : pold[k];
+            }
+#pragma unroll
+            for (int u = 0; u < IS; ++u) {
+                const int e = threadIdx.x + u * NT;
+                if (e < NS) {
+                    const int ly = e / (TX + 2), lx = e - ly * (TX + 2);
+                    const int j = r0 - 1 + ly, i = c0 - 1 + lx;
+                    const bool in = (j >= 0) && (j < d.rows) && (i >= 0) && (i < P);
+                    sp[ly][lx] = (in && di[u] > (T)0) ? (zv[u] - m) + beta * po[u] : (T)0;
+                }
+            }
+        }
+        const int i = c0 + tx;
+        T dv[R], ce[R], cw[R], cn[R], cs[R];
+#pragma unroll
+        for (int u = 0; u < R; ++u) {
+            const int j = r0 + ty + 4 * u;
+            const bool in = j < d.rows;
             const size_t k = in ? (size_t)j * P + i : 0;
-            const T di = pc.dinv[k], zv = z[k], po = first ? (T)0 : pold[k];
-            sp[ly][lx] = (in && di > (T)0) ? (zv - m) + beta * po : (T)0;
+            const size_t kw = in && i > 0 ? k - 1 : k, ks = in && j > 0 ? k - P : k;
+            dv[u] = pc.dinv[k], ce[u] = pc.cx[k], cw[u] = pc.cx[kw], cn[u] = pc.cy[k], cs[u] = pc.cy[ks];
         }
         __syncthreads();
-        const int i = c0 + tx;
-        for (int lj = ty; lj < PTY; lj += 4) {
+#pragma unroll
+        for (int u = 0; u < R; ++u) {
+            const int lj = ty + 4 * u;
             const int j = r0 + lj;
             if (j < d.rows) {
                 const size_t k = (size_t)j * P + i;
-                const size_t kw = i > 0 ? k - 1 : k, ks = j > 0 ? k - P : k;
-                const T dv = pc.dinv[k], ce = pc.cx[k], cw = pc.cx[kw], cn = pc.cy[k], cs = pc.cy[ks];
                 const T pcv = sp[lj + 1][tx + 1];
-                T qv = (ce + cw + cn + cs) * pcv - ce * sp[lj + 1][tx + 2] - cw * sp[lj + 1][tx] -
-                       cn * sp[lj + 2][tx + 1] - cs * sp[lj][tx + 1];
-                qv = dv > (T)0 ? qv : (T)0;
+                T qv = (ce[u] + cw[u] + cn[u] + cs[u]) * pcv - ce[u] * sp[lj + 1][tx + 2] - cw[u] * sp[lj + 1][tx] -
+                       cn[u] * sp[lj + 2][tx + 1] - cs[u] * sp[lj][tx + 1];
+                qv = dv[u] > (T)0 ? qv : (T)0;
                 pnew[k] = pcv;
                 q[k] = qv;
                 v[0] += (double)pcv * (double)qv;
