@@ -458,7 +458,7 @@ def main():
     # the timed kernels run in float in the inner solves of the mixed mode
     esz = 0.5 if mixed else 1.0
     kname = "k_pred_cg<float>" if mixed else "k_pred_cg"
-    if ncls and not mixed:    # the float CG of the mixed mode reads the arrays
+    if ncls:
         pred_bytes = esz * 8.0 * PRED_CG_VALUES_PER_CELL_CLS + PRED_CG_INDEX_BYTES
     else:
         pred_bytes = esz * 8.0 * PRED_CG_VALUES_PER_CELL
@@ -491,7 +491,7 @@ def main():
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS if achieved else None,
             "traffic": None if mixed else stored_traffic("k_pred_cg", case.name, ncls > 0),
-            "coef_classes": bool(ncls and not mixed),
+            "coef_classes": bool(ncls),
             "bytes_per_launch": pred_bytes * cells,
             "mean_launch_us": mean_us[2],
             "timed_launches": cnt[2],

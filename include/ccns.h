@@ -133,13 +133,14 @@ ccns_status ccns_capacities(const ccns_grid *grid, const ccns_body *bodies, int 
  *                 smoothing, pseudo-inverse on the coarsest grid).  The
  *                 paper does not fix the solver; both converge to the same
  *                 solution of eq:pm_poisson.
- *  coef_tables    0: the predictor's FP64 CG reads its coefficients through
- *                 a table of the distinct coefficient neighbourhoods (one
- *                 index per entry) when there are at most max(1024, n/16) of
- *                 them (n: entries of the padded layout), else from the
- *                 coefficient arrays; 1: always from the arrays.  Both read
- *                 the same values: the results are identical bit for bit.
- *                 The float inner solves of precision 1 read the arrays. */
+ *  coef_tables    0: the predictor's kernels (right-hand side, residual and
+ *                 CG, FP64 and the float inner CG of precision 1) read their
+ *                 coefficients through a table of the distinct coefficient
+ *                 neighbourhoods (one index per entry) when there are at
+ *                 most max(1024, n/16) of them (n: entries of the padded
+ *                 layout), else from the coefficient arrays; 1: always from
+ *                 the arrays.  Both read the same values: the results are
+ *                 identical bit for bit. */
 typedef struct {
     double rho, mu, tau, u_ref, gx, gy;
     double pcg_tol, pred_tol, div_tol;
@@ -178,8 +179,8 @@ ccns_status ccns_ctx_create(const ccns_grid *grid, const ccns_params *params,
 void ccns_ctx_destroy(ccns_ctx *ctx);
 const char *ccns_last_error(const ccns_ctx *ctx);
 
-/* Number of coefficient classes the predictor's FP64 CG of this context
- * reads (see coef_tables in ccns_params); 0 when it reads the coefficient
+/* Number of coefficient classes the predictor's kernels of this context
+ * read (see coef_tables in ccns_params); 0 when they read the coefficient
  * arrays, -1 for a null context. */
 int ccns_coef_classes(const ccns_ctx *ctx);
 

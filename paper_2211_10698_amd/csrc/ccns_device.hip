@@ -2135,7 +2135,7 @@ struct WsPlan {
     std::vector<size_t> mg32_off;
     // predictor coefficient classes: one int per entry, up to max_cls rows of
     // PCW values (FP64)
-    size_t cls_off, tab_off;
+    size_t cls_off, tab_off, tab32_off;
     int max_cls;
     size_t total;
 };
@@ -2183,6 +2183,8 @@ WsPlan plan(int nx, int ny, int precision) {
     w.max_cls = (int)std::max<size_t>(1024, w.L.n / 16);
     w.tab_off = off;
     off += align_up((size_t)w.max_cls * PCW * sizeof(double), 256);
+    w.tab32_off = off;  // the same rows in float (precision 1)
+    if (precision == 1) off += align_up((size_t)w.max_cls * PCW * sizeof(float), 256);
     w.total = off;
     return w;
 }
@@ -2232,6 +2234,7 @@ struct ccns_ctx {
     int ncls;
     int *cls;
     double *tab;
+    float *tab32;      // the table in float (precision 1), or null
     // optional kernel timing: start/stop events attached to sampled launches
     int timing;
     std::vector<hipEvent_t> evpool;
@@ -2496,6 +2499,7 @@ ccns_status pred_classes(ccns_ctx *c, const HostCoef &hc) {
     c->ncls = 0;
     c->cls = (int *)(c->base + c->w.cls_off);
     c->tab = (double *)(c->base + c->w.tab_off);
+    c->tab32 = c->prm.precision == 1 ? (float *)(c->base + c->w.tab32_off) : nullptr;
     if (c->prm.coef_tables == 1) return CCNS_OK;
     const Layout &L = c->w.L;
     const long P = L.pitch, rows = L.rows, W = c->g.nx + 2;
@@ -2551,6 +2555,13 @@ ccns_status pred_classes(ccns_ctx *c, const HostCoef &hc) {
         }
     HIPCHK(c, hipMemcpyAsync(c->cls, cls.data(), cls.size() * sizeof(int), hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipMemcpyAsync(c->tab, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    // the float rows are the float arrays' values (each converted once)
+    std::vector<float> tab32;
+    if (c->tab32) {
+        tab32.assign(tab.begin(), tab.end());
+        HIPCHK(c, hipMemcpyAsync(c->tab32, tab32.data(), tab32.size() * sizeof(float), hipMemcpyHostToDevice,
+                                 c->stream));
+    }
     // the host vectors are released when this returns: wait for the copies
     HIPCHK(c, hipStreamSynchronize(c->stream));
     c->ncls = (int)(tab.size() / PCW);
@@ -3005,8 +3016,10 @@ ccns_status predict_mixed(ccns_ctx *c, ccns_solve_info *info) {
     PredCoefT<float> pf{ViscCoefT<float>{c->f[G_BXX], c->f[G_BXY], c->f[G_BYY], c->f[G_BYX], c->f[G_WXX],
                                          c->f[G_WYY], c->f[G_NXX], c->f[G_NXY], c->f[G_NYX], c->f[G_NYY]},
                         c->f[G_VU], c->f[G_VV], c->f[G_HDX], c->f[G_HDY], pc.rt, pc.mu, nullptr, nullptr};
-    // the float CG reads the coefficient arrays: at half the bytes per value
-    // the class table's dependent load costs more than it saves (measured)
+    if (c->ncls) {
+        pf.cls = c->cls;
+        pf.tab = c->tab32;
+    }
     const double tol = c->prm.pred_tol;
     predictor_rhs(c);
     double fn2 = 0.0, rn2 = 0.0;
