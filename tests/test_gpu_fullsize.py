@@ -71,6 +71,11 @@ def test_step_full_size_against_oracle_systems(full):
     from paper_2211_10698_amd import ccns
     case, (caps, pr, st, ctx, Dx, Dy) = full
     prm = st.prm
+    # the predictor's kernels read the coefficient class table here, so the
+    # checks below hold for that path (the array path is the same bit for bit)
+    ncls = ctx.coef_classes()
+    print(f"[fullsize] coefficient classes {ncls}", flush=True)
+    assert ncls > 0
     s0 = pmii.initial_state(pr, Dx, Dy, case.u_inf, W.perturbation(case))
     ctx.set_field(ccns.F_UX, s0.Ux)
     ctx.set_field(ccns.F_UY, s0.Uy)
