@@ -1,12 +1,15 @@
 """Throughput of the cut-cell projection step on one MI355X.
 
-Workload (default): the 2048x1024 channel [0,20]x[0,10] with a cylinder of
-diameter 1 at (5,5), free stream 1 plus seeded 1e-3 divergence-free noise,
-Re = 100, CFL 0.5, FP64, pressure solve to a relative residual of 1e-10
-(which keeps max|cont(U, D)| / (U h) below 1e-8 every step).  A step is one
-full projection-method-II step: convection and predictor right-hand side,
-the viscous predictor solve, the Poisson right-hand side, the pressure
-solve, the corrector and the pressure update, with the diagnostics.
+Workload (default): the 4096x2048 box [0,8]x[0,4] around a NACA0012 section
+(chord 1 at 5 degrees, leading edge at (2,2)), free stream 1 plus seeded
+1e-3 divergence-free noise, Re = 1000, CFL 0.5, FP64, pressure solve to a
+relative residual of 1e-10 (which keeps max|cont(U, D)| / (U h) below 1e-8
+every step).  `--workload channel_cylinder_2048x1024` runs the 2048x1024
+channel cylinder instead, `--precision mixed` the FP32 inner solves with FP64
+refinement.  A step is one full projection-method-II step: convection and
+predictor right-hand side, the viscous predictor solve, the Poisson
+right-hand side, the pressure solve, the corrector and the pressure update,
+with the diagnostics.
 
 Prints one JSON line.  `value` is whole-job cell-steps per second (in
 millions) with the state resident in HBM.  `roofline` reports the dominant
@@ -36,7 +39,12 @@ HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 DEVICE_SRC = os.path.join(ROOT, "paper_2211_10698_amd", "csrc", "ccns_device.hip")
 KERNEL_HDR = os.path.join(ROOT, "paper_2211_10698_amd", "csrc", "ccns_kern.h")
-# Algorithmic bytes per cell of the timed kernels (FP64 = 8 bytes per value).
+# Algorithmic bytes per cell of one predictor CG iteration: the scope's figure
+# for the method (27 values of 8 bytes per cell: the CG vectors and the
+# viscous and mass coefficients of both face components), the roofline's
+# `achieved`.  Half of it for the float vectors of the mixed mode.
+PRED_CG_SCOPE_BYTES_PER_CELL = 216.0
+# What the kernel itself has to move.
 # Predictor CG iteration (k_pred_cg), per cell = one x-face and one y-face:
 # reads r, H p and p of the previous iteration, x and M^-1 (2 components
 # each), M^x, M^y, B^xx, B^xy, B^yy, B^yx, 1/W^xx, 1/W^yy and the two diagonal
@@ -55,9 +63,9 @@ POIS_DIR_BYTES_PER_CELL = 7 * 8.0
 POIS_UPDATE_BYTES_PER_CELL = 6 * 8.0
 
 WORKLOADS = {
+    "naca0012_4096x2048": W.naca_4096,
     "channel_cylinder_2048x1024": W.channel_cylinder_2048,
     "cylinder_64": W.cylinder_64,
-    "naca0012_4096x2048": W.naca_4096,
     "batched_cylinders_256": None,   # ragged batch, see run_batched
     "serving_trace": None,           # served requests, see run_serving
 }
@@ -100,7 +108,7 @@ def stored_traffic(name, workload, classes):
     None when there is none for this workload and coefficient path, or the
     kernel has changed."""
     try:
-        t = json.load(open(TRAFFIC_FILE)).get(name)
+        t = json.load(open(TRAFFIC_FILE)).get(f"{name}@{workload}")
     except (OSError, ValueError):
         return None
     if (not t or t.get("workload") != workload or t.get("kernel_sha1") != kernel_digest(name)
@@ -144,7 +152,7 @@ def summarize_counters(root, kernel, workload, classes):
         data = json.load(open(TRAFFIC_FILE))
     except (OSError, ValueError):
         data = {}
-    data[kernel] = rec
+    data[f"{kernel}@{workload}"] = rec
     with open(TRAFFIC_FILE, "w") as f:
         json.dump(data, f, indent=1)
         f.write("\n")
@@ -177,44 +185,82 @@ def unknown_masks(caps, nx, ny):
     return au, av
 
 
-def cpu_baseline(case, n_cg_per_step, iters_sample=20):
-    """Times the oracle on the host: one full predictor phase, a fixed number
-    of its Poisson PCG (Jacobi) iterations, and the corrector/pressure update
-    of the same workload; the Poisson part is scaled to the number of Jacobi
-    iterations one step of this workload needs (n_cg_per_step)."""
-    from oracle import derived, geometry, pmii, solvers
+def host_cpu():
+    """Model name and logical core count of the host."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return model, os.cpu_count()
+
+
+def cpu_baseline(case, caps_arr, n_pred, n_cg, iters_sample=5):
+    """Times the FP64 oracle on the host on the full grid of the workload:
+    the explicit phases of one step whole (convection and the predictor
+    right-hand side; the Poisson right-hand side; the corrector and the
+    pressure update with the diagnostics), and `iters_sample` iterations of
+    each of its two Jacobi-PCG solves.  A whole step is then the explicit
+    phases plus the per-iteration times scaled to the iteration counts one
+    step needs with that algorithm (n_pred predictor and n_cg Poisson
+    iterations, see the caller): an extrapolation, labelled as such.  The
+    oracle's operators are vectorised numpy on one thread."""
+    from oracle import derived, pmii, solvers
 
     g = case.grid
-    caps = geometry.capacities(g, case.bodies)
+    names = ("V", "Ax", "Ay", "Bx", "By", "Wx", "Wy", "Vu", "Axx", "Axy", "Bxx", "Bxy", "Wxx", "Wxy",
+             "Vv", "Ayy", "Ayx", "Byy", "Byx", "Wyy", "Wyx")
+    caps = {k: caps_arr[i] for i, k in enumerate(names)}
     pr = derived.prepare(caps, g.nx, g.ny, vol_floor=case.mass_floor * g.hx * g.hy)
     Dx, Dy = W.dirichlet(case)
     prm = pmii.Params(rho=case.rho, mu=case.mu, tau=case.tau, pcg_tol=case.pcg_tol)
-    st = pmii.Stepper(pr, prm, Dx, Dy, min(g.hx, g.hy))
+    st = pmii.Stepper(pr, prm, Dx, Dy, min(g.hx, g.hy), jacobi=False)
     s0 = pmii.initial_state(pr, Dx, Dy, case.u_inf, W.perturbation(case))
     t0 = time.perf_counter()
-    (usx, usy), _ = st.predict(s0, pmii.StepInfo())
-    b = st.poisson_rhs(usx, usy)
+    conv_n = st.convection(s0.Ux, s0.Uy)
+    rhs = st.predictor_rhs(s0, conv_n, conv_n)
     t1 = time.perf_counter()
-    phi, it, _, _ = solvers.pcg(st.apply_A, -b, s0.Phi, st.Pdinv, pr.act_p, 0.0, iters_sample, zero_mean=True)
+    # the cost of an iteration does not depend on the preconditioner's values:
+    # the mass part of H's diagonal stands in for the probed diagonal
+    dmass = np.where(st.mask2, 1.0 / np.maximum((prm.rho / prm.tau) * np.stack([st.Vu, st.Vv]), 1e-300), 0.0)
+    U0 = np.stack([s0.Ux, s0.Uy])
+    _, itp, _, _ = solvers.pcg(st.apply_H, rhs, U0, dmass, st.mask2, 0.0, iters_sample)
     t2 = time.perf_counter()
-    ux, uy = st.correct(usx, usy, phi)
+    b = st.poisson_rhs(s0.Ux, s0.Uy)
+    t3 = time.perf_counter()
+    phi, itc, _, _ = solvers.pcg(st.apply_A, -b, s0.Phi, st.Pdinv, pr.act_p, 0.0, iters_sample, zero_mean=True)
+    t4 = time.perf_counter()
+    ux, uy = st.correct(s0.Ux, s0.Uy, phi)
     st.pressure_update(s0.P, phi)
     st.diagnostics(ux, uy, pmii.StepInfo())
-    t3 = time.perf_counter()
-    per_it = (t2 - t1) / max(it, 1)
-    step_s = (t1 - t0) + (t3 - t2) + per_it * n_cg_per_step
+    t5 = time.perf_counter()
+    per_pred = (t2 - t1) / max(itp, 1)
+    per_cg = (t4 - t3) / max(itc, 1)
+    explicit = (t1 - t0) + (t3 - t2) + (t5 - t4)
+    step_s = explicit + per_pred * n_pred + per_cg * n_cg
+    model, ncpu = host_cpu()
     return {
         "value": g.nx * g.ny / step_s / 1e6,
         "unit": "Mcell-steps/s",
         "cores": 1,
         "kind": "oracle",
-        "sample": (f"one step of the {case.name} workload on the full grid: predictor phase "
-                   f"({t1 - t0:.2f} s) and corrector/pressure update ({t3 - t2:.2f} s) timed whole; "
-                   f"{it} of the oracle's Jacobi-PCG Poisson iterations timed ({per_it * 1e3:.1f} ms each) "
-                   f"and scaled to {n_cg_per_step:.0f} iterations, the count one step's pressure solve needs "
-                   f"with that algorithm (taken from the library's Jacobi-PCG on the same right-hand side, "
-                   f"which matches the oracle's count within 2); numpy runs single-threaded"),
+        "sample": (f"the FP64 oracle (numpy, one thread) on the full {g.nx}x{g.ny} grid of {case.name}: the "
+                   f"explicit phases of one step timed whole ({explicit:.2f} s: convection and predictor "
+                   f"right-hand side {t1 - t0:.2f} s, Poisson right-hand side {t3 - t2:.2f} s, corrector, "
+                   f"pressure update and diagnostics {t5 - t4:.2f} s), {itp} predictor Jacobi-PCG iterations "
+                   f"({per_pred:.2f} s each) and {itc} Poisson Jacobi-PCG iterations ({per_cg:.2f} s each) timed; "
+                   f"a step is EXTRAPOLATED to {n_pred} predictor and {n_cg} Poisson iterations, the counts of "
+                   f"one step of this workload with the oracle's algorithm (Jacobi-PCG for both solves; the "
+                   f"counts were taken by the library's Jacobi-PCG on the same step, which matches the "
+                   f"oracle's count within 2 in the parity tests); host {model}, {ncpu} logical cores"),
         "seconds_per_step": step_s,
+        "extrapolated": True,
+        "host_cpu": model,
+        "host_logical_cores": ncpu,
+        "threads": 1,
     }
 
 
@@ -267,14 +313,26 @@ def run_batched(args):
     print(f"[bench] setup {time.perf_counter() - t_setup:.1f}s: {len(cases)} simulations, {cells} cells",
           file=sys.stderr, flush=True)
     batch = ccns.Batch(ctxs, nthreads=16)
+    failures = []
+
+    def record(tag, st, infos, sts):
+        # a simulation whose solve did not converge: its figures and the
+        # statuses of its inner solves (precision 1)
+        for k, (i, s) in enumerate(zip(infos, sts)):
+            if s != ccns.OK:
+                failures.append({"step": tag, "simulation": cases[k].name, "status": int(s), **i.as_dict()})
+                print(f"[bench] {tag}: {cases[k].name} status {s}: {i.as_dict()}", file=sys.stderr, flush=True)
+
     for k in range(args.warmup):
-        st, infos, _ = batch.step(1)
+        st, infos, sts = batch.step(1, check=False)
+        record(f"warmup {k}", st, infos, sts)
         print(f"[bench] warmup {k}: worst div_rel {max(i.div_rel for i in infos):.2e}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     divs, cg, pred = [], [], []
     for k in range(args.steps):
-        st, infos, _ = batch.step(1)
+        st, infos, sts = batch.step(1, check=False)
+        record(f"step {k}", st, infos, sts)
         divs.append(max(i.div_rel for i in infos))
         cg.append(float(np.mean([i.poisson.iterations for i in infos])))
         pred.append(float(np.mean([i.pred.iterations for i in infos])))
@@ -307,9 +365,12 @@ def run_batched(args):
         "pred_iters_per_step_mean": float(np.mean(pred)),
         "roofline": None,
         "cpu_baseline": None,
+        "failures": failures,
     }
     if max(divs) > 1e-8:
         out["warning"] = "divergence above 1e-8 in a timed step"
+    if failures:
+        out["warning"] = f"{len(failures)} simulation steps ended with a solver status other than OK"
     print(json.dumps(out), flush=True)
     batch.close()
     for c in ctxs:
@@ -365,7 +426,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="channel_cylinder_2048x1024", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="naca0012_4096x2048", choices=sorted(WORKLOADS))
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"],
                     help="fp64, or mixed: FP32 inner solves with FP64 residuals and refinement to "
                          "div_rel <= 1e-8")
@@ -375,6 +436,9 @@ def main():
                     help="only run the plain copies that calibrate the HBM byte counters")
     ap.add_argument("--summarize-counters", metavar="DIR",
                     help="store the HBM traffic of the predictor kernel from rocprofv3 counter runs under DIR")
+    ap.add_argument("--mass-floor", type=float, default=None,
+                    help="small-volume floor theta (default: the workload's, 0.05); 0 is the paper's mass "
+                         "matrix M = diag(V)")
     ap.add_argument("--coef-tables", default="auto", choices=["auto", "off"],
                     help="auto: the predictor CG reads its coefficients through the class table when it "
                          "fits (the library's default); off: from the coefficient arrays")
@@ -401,6 +465,8 @@ def main():
     from paper_2211_10698_amd import ccns
 
     case = WORKLOADS[args.workload]()
+    if args.mass_floor is not None:
+        case.mass_floor = args.mass_floor
     g = case.grid
     t_setup = time.perf_counter()
     caps = ccns.ccns_capacities(g, case.bodies)
@@ -458,11 +524,19 @@ def main():
     # the timed kernels run in float in the inner solves of the mixed mode
     esz = 0.5 if mixed else 1.0
     kname = "k_pred_cg<float>" if mixed else "k_pred_cg"
+    # algorithmic bytes of a predictor CG iteration: the scope's figure for
+    # the method (the roofline's `achieved`), and what this kernel moves (the
+    # coefficient class table replaces twelve coefficient values per cell by
+    # one 4-byte index)
+    scope_bytes = esz * PRED_CG_SCOPE_BYTES_PER_CELL
     if ncls:
         pred_bytes = esz * 8.0 * PRED_CG_VALUES_PER_CELL_CLS + PRED_CG_INDEX_BYTES
     else:
         pred_bytes = esz * 8.0 * PRED_CG_VALUES_PER_CELL
-    achieved = pred_bytes * cells / (mean_us[2] * 1e-6) / 1e9 if mean_us[2] else None
+    us = mean_us[2]
+    achieved = scope_bytes * cells / (us * 1e-6) / 1e9 if us else None
+    moved = pred_bytes * cells / (us * 1e-6) / 1e9 if us else None
+    traffic = None if mixed else stored_traffic("k_pred_cg", case.name, ncls > 0)
     out = {
         "metric": "Mcell-steps/s at 1e-8 divergence",
         "value": value,
@@ -479,7 +553,7 @@ def main():
         "config": {"workload": case.name, "nx": g.nx, "ny": g.ny, "re": case.re, "cfl": case.cfl,
                    "pcg_tol": case.pcg_tol, "pred_tol": 1e-12, "precond": "multigrid",
                    "precision": "fp32 inner + fp64 refinement, div_rel <= 1e-8" if mixed else "fp64",
-                   "coef_classes": ncls},
+                   "coef_classes": ncls, "mass_floor": case.mass_floor},
         "div_rel_max": div_max,
         "cg_iters_per_step": n_cg,
         "pred_iters_per_step": float(np.mean([i["pred_iters"] for i in infos])),
@@ -490,14 +564,20 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS if achieved else None,
-            "traffic": None if mixed else stored_traffic("k_pred_cg", case.name, ncls > 0),
+            "traffic": traffic,
+            "bytes_per_cell": scope_bytes,
+            "bytes_per_launch": scope_bytes * cells,
+            "kernel_bytes_per_cell": pred_bytes,
+            "kernel_bytes_per_launch": pred_bytes * cells,
+            "achieved_kernel_bytes": moved,
+            "frac_kernel_bytes": moved / HBM_PEAK_GBS if moved else None,
+            "traffic_rate": traffic / (us * 1e-6) / 1e9 if (traffic and us) else None,
             "coef_classes": bool(ncls),
-            "bytes_per_launch": pred_bytes * cells,
-            "mean_launch_us": mean_us[2],
+            "mean_launch_us": us,
             "timed_launches": cnt[2],
         },
         "kernels": {
-            kname: {"us": mean_us[2], "GBs": achieved},
+            kname: {"us": mean_us[2], "GBs": moved},
             "k_reduce_partials<7>": {"us": mean_us[3]},
             "k_pois_dir_z": {"us": mean_us[0], "GBs": rate(POIS_DIR_BYTES_PER_CELL, mean_us[0])},
             "k_cg_update (Poisson)": {"us": mean_us[1], "GBs": rate(POIS_UPDATE_BYTES_PER_CELL, mean_us[1])},
@@ -507,21 +587,23 @@ def main():
     if div_max > 1e-8:
         out["warning"] = "divergence above 1e-8 in a timed step"
     if not args.no_cpu_baseline:
-        # the oracle solves the pressure with Jacobi-PCG: count the iterations
-        # that algorithm needs on this step's right-hand side (library, same
+        # the oracle solves both systems with Jacobi-PCG: count the iterations
+        # that algorithm needs in one step of this workload (an FP64 Jacobi
+        # context of the library stepped once from the current state: same
         # algorithm as the oracle), to scale the oracle's timed sample
         pj = ccns.make_params(case.rho, case.mu, case.tau, u_ref=case.u_inf, pcg_tol=case.pcg_tol,
-                              precond=ccns.PRECOND_JACOBI, mass_floor=case.mass_floor)
+                              pred_tol=1e-12, precond=ccns.PRECOND_JACOBI, mass_floor=case.mass_floor)
         cj = ccns.Context(g, pj, caps, Dx, Dy, stream=stream)
-        phi_prev = ctx.get_field(ccns.F_PHI)
-        ctx.step(1)                      # one more (untimed) step: its warm start and right-hand side
-        cj.set_field(ccns.F_PHI, phi_prev)
-        _, jinfo, _ = cj.pressure_solve(ctx.get_field(ccns.F_B), check=False)
-        n_jac = jinfo.iterations
+        for f in (ccns.F_UX, ccns.F_UY, ccns.F_P, ccns.F_PHI, ccns.F_CONVX, ccns.F_CONVY):
+            cj.set_field(f, ctx.get_field(f))
+        jinfo = cj.step(1, check=False)
+        n_pred, n_jac = jinfo.pred.iterations, jinfo.poisson.iterations
         cj.close()
-        print(f"[bench] cpu baseline (oracle), Jacobi iterations per step {n_jac} ...", file=sys.stderr, flush=True)
-        cb = cpu_baseline(case, n_jac)
-        out["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample")}
+        print(f"[bench] cpu baseline (oracle): Jacobi-PCG iterations per step {n_pred} predictor, {n_jac} "
+              f"pressure ...", file=sys.stderr, flush=True)
+        cb = cpu_baseline(case, caps, n_pred, n_jac)
+        out["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample", "extrapolated",
+                                                  "host_cpu", "host_logical_cores", "threads")}
     print(json.dumps(out), flush=True)
 
 

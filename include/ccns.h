@@ -96,6 +96,27 @@ size_t ccns_caps_count(const ccns_grid *grid);
 ccns_status ccns_capacities(const ccns_grid *grid, const ccns_body *bodies, int nbody,
                             ccns_levelset_fn fn, void *user, double *caps_host);
 
+/* The capacities of ccns_capacities computed on the device, for bodies bounded
+ * by conics (circles and ellipses, at most 16, whose circumscribed discs do
+ * not overlap; no user level set): the same arrays, layout and readings (each
+ * grid's box, wet pressure-grid wall faces, centroid of an empty control
+ * volume at its centre, exact measures of full control volumes, faces and
+ * strips, capacities below 1e-12 h or 1e-12 hx hy set to 0).  The measure of
+ * the fluid in a rectangle or on a segment is in closed form: the chords of a
+ * conic along vertical and horizontal lines, integrated piecewise between the
+ * points where they cross the rectangle's rows (Sec. 3.2-3.4).
+ *  caps_dev     device buffer of ccns_caps_count() doubles (caller-owned)
+ *  dev_scratch  device buffer of ccns_capacities_scratch_bytes() bytes for
+ *               the control volumes' centroids (caller-owned)
+ *  hip_stream   the work is enqueued on it; the call does not wait
+ * Errors: CCNS_EINVAL (bad grid, a body that is not a circle or an ellipse,
+ * overlapping bodies, more than 16 bodies), CCNS_ENOMEM (scratch too small),
+ * CCNS_EDEVICE. */
+size_t ccns_capacities_scratch_bytes(const ccns_grid *grid);
+ccns_status ccns_capacities_device(const ccns_grid *grid, const ccns_body *bodies, int nbody,
+                                   double *caps_dev, void *dev_scratch, size_t scratch_bytes,
+                                   void *hip_stream);
+
 /* Solver parameters.
  *  rho, mu, tau   density, dynamic viscosity, time step (> 0)
  *  u_ref          reference velocity of the divergence diagnostic
@@ -179,6 +200,7 @@ ccns_status ccns_ctx_create(const ccns_grid *grid, const ccns_params *params,
 void ccns_ctx_destroy(ccns_ctx *ctx);
 const char *ccns_last_error(const ccns_ctx *ctx);
 
+
 /* Number of coefficient classes the predictor's kernels of this context
  * read (see coef_tables in ccns_params); 0 when they read the coefficient
  * arrays, -1 for a null context. */
@@ -227,6 +249,12 @@ typedef struct {
     int outer;             /* refinement sweeps (precision 1), else 1 */
     double rel_residual;   /* final ||r||_2 / ||b||_2 (FP64) */
     int status;            /* ccns_status of this solve */
+    int inner_status;      /* precision 1: CCNS_EBREAKDOWN if an inner solve broke down, else
+                              CCNS_ENOTCONV if one hit its iteration limit, else CCNS_OK;
+                              precision 0: CCNS_OK */
+    int inner_fail_sweep;  /* precision 1: first sweep whose inner solve did not converge, -1 if
+                              none.  An inner breakdown before its first update ends the solve
+                              with status CCNS_EBREAKDOWN (the next sweep would repeat it). */
 } ccns_solve_info;
 
 typedef struct {
@@ -240,8 +268,10 @@ typedef struct {
 } ccns_step_info;
 
 /* Pressure solve (eq:pm_poisson, Sec. 4.6 with the zero-mean projection):
- * solves L phi = b on the pressure unknowns by Jacobi-preconditioned CG,
- * starting from the current CCNS_F_PHI, after removing the mean of b.
+ * solves L phi = b on the pressure unknowns by CG with the context's
+ * preconditioner (params.precond: Jacobi or the multigrid V-cycle; in
+ * precision 1 inside the FP64 refinement loop), starting from the current
+ * CCNS_F_PHI, after removing the mean of b.
  * b, phi: dense device arrays (phi may be NULL: the result stays in
  * CCNS_F_PHI).  Errors: CCNS_ENOTCONV, CCNS_EBREAKDOWN (outputs written). */
 ccns_status ccns_pressure_solve(ccns_ctx *ctx, const double *b, double *phi, ccns_solve_info *info);

@@ -15,7 +15,6 @@ Modules
   derived    activity masks and coefficient fields used by the time stepper
   solvers    Jacobi-preconditioned CG and a direct sparse solve
   pmii       projection method II time step (Sec. 4.6)
-  dense      matrix assembly of the linear operators on small grids
 
 Parity status: every function is pinned by a test under tests/ except the
 ones whose header says "parity unpinned".

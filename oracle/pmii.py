@@ -68,7 +68,10 @@ class StepInfo:
 
 
 class Stepper:
-    def __init__(self, pr: Prepared, prm: Params, Dx, Dy, h):
+    def __init__(self, pr: Prepared, prm: Params, Dx, Dy, h, jacobi=True):
+        """jacobi=False skips probing the predictor's Jacobi diagonal (a
+        stepper used only to apply the operators and to check residuals,
+        not to solve)."""
         self.pr = pr
         self.prm = prm
         self.Dx = Dx
@@ -81,8 +84,11 @@ class Stepper:
         self.mask2 = np.stack([pr.act_u, pr.act_v])
         self.vD = self.dirichlet_viscous(Dx, Dy)
         # Jacobi diagonal of H, probed on unit combs
-        self.Hdiag = coloured_diagonal(self.apply_H, self.mask2.shape, self.mask2)
-        self.Hdinv = np.where(self.mask2 & (self.Hdiag > 0), 1.0 / np.where(self.Hdiag > 0, self.Hdiag, 1.0), 0.0)
+        self.Hdiag = self.Hdinv = None
+        if jacobi:
+            self.Hdiag = coloured_diagonal(self.apply_H, self.mask2.shape, self.mask2)
+            self.Hdinv = np.where(self.mask2 & (self.Hdiag > 0), 1.0 / np.where(self.Hdiag > 0, self.Hdiag, 1.0),
+                                  0.0)
         self.Pdinv = np.where(pr.act_p & (pr.diag > 0), 1.0 / np.where(pr.diag > 0, pr.diag, 1.0), 0.0)
 
     def dirichlet_viscous(self, Dx, Dy):

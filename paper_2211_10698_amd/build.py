@@ -44,7 +44,7 @@ def build(verbose: bool = True) -> str:
         obj = os.path.join(BUILD, src + ".o")
         _run(["g++", *HOST_FLAGS, "-I", INC, "-I", CSRC, "-c", os.path.join(CSRC, src), "-o", obj])
         objs.append(obj)
-    for src in ("ccns_device.hip",):
+    for src in ("ccns_device.hip", "caps_device.hip"):
         obj = os.path.join(BUILD, src + ".o")
         _run([hipcc, *HIP_FLAGS, "-I", INC, "-I", CSRC, "-c", os.path.join(CSRC, src), "-o", obj])
         objs.append(obj)

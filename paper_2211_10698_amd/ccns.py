@@ -46,7 +46,8 @@ class Params(C.Structure):
 
 
 class SolveInfo(C.Structure):
-    _fields_ = [("iterations", C.c_int), ("outer", C.c_int), ("rel_residual", C.c_double), ("status", C.c_int)]
+    _fields_ = [("iterations", C.c_int), ("outer", C.c_int), ("rel_residual", C.c_double), ("status", C.c_int),
+                ("inner_status", C.c_int), ("inner_fail_sweep", C.c_int)]
 
 
 class StepInfo(C.Structure):
@@ -55,8 +56,10 @@ class StepInfo(C.Structure):
 
     def as_dict(self):
         return {"pred_iters": self.pred.iterations, "pred_status": self.pred.status,
+                "pred_outer": self.pred.outer, "pred_inner_status": self.pred.inner_status,
                 "cg_iters": self.poisson.iterations, "cg_outer": self.poisson.outer,
                 "cg_relres": self.poisson.rel_residual, "cg_status": self.poisson.status,
+                "cg_inner_status": self.poisson.inner_status, "cg_inner_fail_sweep": self.poisson.inner_fail_sweep,
                 "div_max": self.div_max, "div_rel": self.div_rel, "ke": self.ke, "mass": self.mass,
                 "mom_x": self.mom_x, "mom_y": self.mom_y}
 
@@ -79,6 +82,11 @@ def lib():
         L.ccns_caps_count.argtypes = [P(Grid)]
         L.ccns_capacities.restype = C.c_int
         L.ccns_capacities.argtypes = [P(Grid), P(BodyC), C.c_int, LEVELSET_FN, C.c_void_p, C.c_void_p]
+        L.ccns_capacities_scratch_bytes.restype = C.c_size_t
+        L.ccns_capacities_scratch_bytes.argtypes = [P(Grid)]
+        L.ccns_capacities_device.restype = C.c_int
+        L.ccns_capacities_device.argtypes = [P(Grid), P(BodyC), C.c_int, C.c_void_p, C.c_void_p, C.c_size_t,
+                                             C.c_void_p]
         L.ccns_workspace_bytes.restype = C.c_size_t
         L.ccns_workspace_bytes.argtypes = [P(Grid), P(Params)]
         L.ccns_ctx_create.restype = C.c_int
@@ -118,7 +126,8 @@ def lib():
     return _lib
 
 
-EXPORTED = ("ccns_caps_count", "ccns_capacities", "ccns_workspace_bytes", "ccns_ctx_create",
+EXPORTED = ("ccns_caps_count", "ccns_capacities", "ccns_capacities_scratch_bytes", "ccns_capacities_device",
+            "ccns_workspace_bytes", "ccns_ctx_create",
             "ccns_ctx_destroy", "ccns_last_error", "ccns_coef_classes", "ccns_field_set", "ccns_field_get", "ccns_apply",
             "ccns_pressure_solve", "ccns_project", "ccns_step", "ccns_predict", "ccns_correct",
             "ccns_diagnostics", "ccns_timing", "ccns_batch_create", "ccns_batch_step", "ccns_batch_destroy")
@@ -154,6 +163,31 @@ def ccns_capacities(spec, bodies, fn=None) -> np.ndarray:
     return out.reshape(NCAPS, spec.ny + 2, spec.nx + 2)
 
 
+def ccns_capacities_device(spec, bodies, stream=None):
+    """Capacities (21, ny+2, nx+2) computed on the device (circles and
+    ellipses): a float64 tensor on the current device, ready when the
+    stream's queued work is."""
+    import torch
+
+    L = lib()
+    g = make_grid(spec)
+    n = L.ccns_caps_count(C.byref(g))
+    nscr = L.ccns_capacities_scratch_bytes(C.byref(g))
+    caps = torch.empty(n, dtype=torch.float64, device="cuda")
+    scratch = torch.empty(nscr, dtype=torch.uint8, device="cuda")
+    s = stream if stream is not None else torch.cuda.current_stream()
+    cur = torch.cuda.current_stream()
+    if cur.cuda_stream != s.cuda_stream:
+        cur.synchronize()
+    st = L.ccns_capacities_device(C.byref(g), make_bodies(bodies), len(bodies), C.c_void_p(caps.data_ptr()),
+                                  C.c_void_p(scratch.data_ptr()), nscr, C.c_void_p(s.cuda_stream))
+    if st != OK:
+        raise CcnsError(st, "ccns_capacities_device")
+    if cur.cuda_stream != s.cuda_stream:
+        s.synchronize()   # the scratch tensor is freed on return
+    return caps.view(NCAPS, spec.ny + 2, spec.nx + 2)
+
+
 PRECOND_JACOBI, PRECOND_MG = 0, 1
 
 
@@ -177,17 +211,29 @@ class Context:
         L = lib()
         self.g = make_grid(spec)
         self.params = params
-        nbytes = L.ccns_workspace_bytes(C.byref(self.g), C.byref(params))
-        if nbytes == 0:
-            raise CcnsError(EINVAL, "bad grid")
-        self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
-        base = self.ws.data_ptr()
-        self.ws_ptr = (base + 255) // 256 * 256
-        self.ws_bytes = nbytes
-        self.stream = stream if stream is not None else torch.cuda.current_stream(device)
+        self.device = torch.device(device)
+        if self.device.index is None:
+            self.device = torch.device(self.device.type, torch.cuda.current_device())
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         caps = np.ascontiguousarray(caps, dtype=np.float64)
         dirichlet = np.ascontiguousarray(np.stack([dx, dy]), dtype=np.float64)
         h = C.c_void_p()
+        nbytes = L.ccns_workspace_bytes(C.byref(self.g), C.byref(params))
+        if nbytes == 0:
+            raise CcnsError(EINVAL, "bad grid")
+        self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        base = self.ws.data_ptr()
+        self.ws_ptr = (base + 255) // 256 * 256
+        self.ws_bytes = nbytes
+        # The workspace was allocated on torch's current stream, whose caching
+        # allocator may hand out a block that work still queued on that stream
+        # uses; the library clears and fills it on the context's own stream.
+        # Wait for the current stream first, and tell the allocator that the
+        # block is in use on the context's stream (so that it is not handed
+        # out again while work queued there may still touch it).
+        self._ready()
+        if self.stream.cuda_stream != torch.cuda.current_stream(self.device).cuda_stream:
+            self.ws.record_stream(self.stream)
         st = L.ccns_ctx_create(C.byref(self.g), C.byref(params), caps.ctypes.data, dirichlet.ctypes.data,
                                C.c_void_p(self.ws_ptr), nbytes, C.c_void_p(self.stream.cuda_stream), C.byref(h))
         if st != OK:
@@ -212,14 +258,14 @@ class Context:
         return st
 
     def _dense(self):
-        return self.torch.zeros(self.shape, dtype=self.torch.float64, device=self.ws.device)
+        return self.torch.zeros(self.shape, dtype=self.torch.float64, device=self.device)
 
     def _ready(self):
         """Tensors handed to the library were made (allocated, filled,
         converted) on torch's current stream; the library works on the
         context's stream.  Wait for the former before a call: the library
         synchronizes its own stream before it returns."""
-        cur = self.torch.cuda.current_stream(self.ws.device)
+        cur = self.torch.cuda.current_stream(self.device)
         if cur.cuda_stream != self.stream.cuda_stream:
             cur.synchronize()
 
@@ -241,7 +287,7 @@ class Context:
     def apply(self, op: int, inputs: Sequence):
         t = self.torch
         nin, nout = _OP_ARITY[op]
-        ins = [x if not isinstance(x, np.ndarray) else t.from_numpy(np.ascontiguousarray(x)).to(self.ws.device)
+        ins = [x if not isinstance(x, np.ndarray) else t.from_numpy(np.ascontiguousarray(x)).to(self.device)
                for x in inputs]
         ins = [x.to(dtype=t.float64).contiguous() for x in ins]
         outs = [self._dense() for _ in range(nout)]
@@ -267,14 +313,18 @@ class Context:
         self._chk(lib().ccns_project(self.h, C.byref(info)), "project")
         return info
 
-    def predict(self):
+    def predict(self, check=True):
         info = SolveInfo()
-        self._chk(lib().ccns_predict(self.h, C.byref(info)), "predict")
+        st = lib().ccns_predict(self.h, C.byref(info))
+        if check:
+            self._chk(st, "predict")
         return info
 
-    def correct(self):
+    def correct(self, check=True):
         info = StepInfo()
-        self._chk(lib().ccns_correct(self.h, C.byref(info)), "correct")
+        st = lib().ccns_correct(self.h, C.byref(info))
+        if check:
+            self._chk(st, "correct")
         return info
 
     def step(self, n=1, check=True):

@@ -2257,6 +2257,17 @@ ccns_status fail(ccns_ctx *c, ccns_status s, const std::string &msg) {
     return s;
 }
 
+// Frees a context (after its stream's work).
+void destroy_ctx(ccns_ctx *ctx) {
+    if (!ctx) return;
+    (void)hipStreamSynchronize(ctx->stream);
+    if (ctx->h_st) (void)hipHostFree(ctx->h_st);
+    if (ctx->h_diag) (void)hipHostFree(ctx->h_diag);
+    if (ctx->h_outer) (void)hipHostFree(ctx->h_outer);
+    for (hipEvent_t e : ctx->evpool) (void)hipEventDestroy(e);
+    delete ctx;
+}
+
 #define HIPCHK(ctx, call)                                                                   \
     do {                                                                                    \
         hipError_t e_ = (call);                                                             \
@@ -2437,6 +2448,8 @@ ccns_status cg_loop(ccns_ctx *c, CgState *st, T *x, T *r, T *const pbuf[2], int 
         info->rel_residual =
             c->h_st->fnorm2 > 0 ? std::sqrt(c->h_st->rnorm2_final / c->h_st->fnorm2) : 0.0;
         info->status = c->h_st->status;
+        info->inner_status = CCNS_OK;
+        info->inner_fail_sweep = -1;
     }
     return (ccns_status)c->h_st->status;
 }
@@ -2801,6 +2814,8 @@ ccns_status mg_cg(ccns_ctx *c, std::vector<ccns_ctx::LevelT<T>> &mg, PoisCoefT<T
         info->outer = 1;
         info->rel_residual = c->h_st->fnorm2 > 0 ? std::sqrt(c->h_st->rnorm2_final / c->h_st->fnorm2) : 0.0;
         info->status = c->h_st->status;
+        info->inner_status = CCNS_OK;
+        info->inner_fail_sweep = -1;
     }
     return (ccns_status)c->h_st->status;
 }
@@ -2832,6 +2847,19 @@ ccns_status read_outer(ccns_ctx *c, const double *src, int n) {
     return CCNS_OK;
 }
 
+// Statuses of the inner solves of a refinement loop: the worst one (a
+// breakdown before a solve that hit its iteration limit) and the first sweep
+// whose inner solve did not converge (-1: every one converged).
+struct InnerRecord {
+    ccns_status status = CCNS_OK;
+    int sweep = -1;
+};
+void note_inner(InnerRecord &r, int status, int sweep) {
+    if (status == CCNS_OK) return;
+    if (r.sweep < 0) r.sweep = sweep;
+    if (r.status == CCNS_OK || status == CCNS_EBREAKDOWN) r.status = (ccns_status)status;
+}
+
 // Pressure solve in precision 1: iterative refinement.  Each sweep forms the
 // residual r = f - A phi in FP64 (FP64 coefficients), solves A d = r in float
 // (float coefficients and vectors, FP64 dot products) to a relative
@@ -2845,6 +2873,7 @@ ccns_status pressure_solve_mixed(ccns_ctx *c, int nin, ccns_solve_info *info) {
     const double sdiv = (p.tau / p.rho) / (p.u_ref * std::min(c->g.hx, c->g.hy));
     double bn2 = 0.0, rn2 = 0.0;
     int inner_its = 0, sweeps = 0;
+    InnerRecord inner;
     ccns_status st = CCNS_ENOTCONV;
     for (int o = 0;; ++o) {
         k_pois_init<true><<<c->dc.nblk, NT, 0, c->stream>>>(c->dc, pc, c->a[A_B], c->a[A_PHI], nullptr,
@@ -2884,6 +2913,13 @@ ccns_status pressure_solve_mixed(ccns_ctx *c, int nin, ccns_solve_info *info) {
         if (si.status == CCNS_EDEVICE) return CCNS_EDEVICE;
         inner_its += si.iterations;
         ++sweeps;
+        note_inner(inner, si.status, o);
+        // an inner solve that broke down before its first update leaves the
+        // correction at zero: the next sweep would start from the same state
+        if (si.status == CCNS_EBREAKDOWN && si.iterations == 0) {
+            st = CCNS_EBREAKDOWN;
+            break;
+        }
         k_add_correction<<<flat_blocks(c->w.L.n), NT, 0, c->stream>>>(c->w.L.n, c->a[A_PHI], c->f[G_X]);
     }
     c->last_pois_it = inner_its;
@@ -2892,6 +2928,8 @@ ccns_status pressure_solve_mixed(ccns_ctx *c, int nin, ccns_solve_info *info) {
         info->outer = sweeps;
         info->rel_residual = bn2 > 0.0 ? std::sqrt(rn2 / bn2) : 0.0;
         info->status = st;
+        info->inner_status = inner.status;
+        info->inner_fail_sweep = inner.sweep;
     }
     return st;
 }
@@ -2966,6 +3004,8 @@ ccns_status pred_cg(ccns_ctx *c, PredCoefT<T> pc, CgState *st, T *x, T *const r[
         info->rel_residual = c->h_st->fnorm2 > 0 ? std::sqrt(std::max(c->h_st->rnorm2_final, 0.0) / c->h_st->fnorm2)
                                                  : 0.0;
         info->status = c->h_st->status;
+        info->inner_status = CCNS_OK;
+        info->inner_fail_sweep = -1;
     }
     return (ccns_status)c->h_st->status;
 }
@@ -3024,6 +3064,7 @@ ccns_status predict_mixed(ccns_ctx *c, ccns_solve_info *info) {
     predictor_rhs(c);
     double fn2 = 0.0, rn2 = 0.0;
     int inner_its = 0, sweeps = 0;
+    InnerRecord inner;
     ccns_status st = CCNS_ENOTCONV;
     for (int o = 0;; ++o) {
         pred_residual<true>(c, c->st_pred_in);
@@ -3045,6 +3086,11 @@ ccns_status predict_mixed(ccns_ctx *c, ccns_solve_info *info) {
         if (si.status == CCNS_EDEVICE) return CCNS_EDEVICE;
         inner_its += si.iterations;
         ++sweeps;
+        note_inner(inner, si.status, o);
+        if (si.status == CCNS_EBREAKDOWN && si.iterations == 0) {
+            st = CCNS_EBREAKDOWN;
+            break;
+        }
         k_add_correction<<<flat_blocks(2 * c->w.L.n), NT, 0, c->stream>>>(2 * c->w.L.n, c->a[A_USX], c->f[G_PXX]);
     }
     c->last_pred_it = inner_its;
@@ -3053,6 +3099,8 @@ ccns_status predict_mixed(ccns_ctx *c, ccns_solve_info *info) {
         info->outer = sweeps;
         info->rel_residual = fn2 > 0.0 ? std::sqrt(rn2 / fn2) : 0.0;
         info->status = st;
+        info->inner_status = inner.status;
+        info->inner_fail_sweep = inner.sweep;
     }
     return st;
 }
@@ -3097,6 +3145,16 @@ ccns_status correct_dev(ccns_ctx *c, int update_p, ccns_step_info *info) {
     return s;
 }
 
+// Clears n 8-byte words (the workspace at context creation: a kernel rather
+// than a memset node, so that the clear orders like every other launch).
+__global__ __launch_bounds__(NT) void k_zero(size_t n, unsigned long long *__restrict__ p) {
+    for (size_t k = (size_t)blockIdx.x * NT + threadIdx.x; k < n; k += (size_t)gridDim.x * NT) p[k] = 0ull;
+}
+
+ccns_status create_ctx(const ccns_grid *grid, const ccns_params *params, const double *caps_host,
+                       const double *dirichlet_host, void *dev_workspace, size_t ws_bytes, void *hip_stream,
+                       ccns_ctx **out);
+
 }  // namespace
 
 extern "C" {
@@ -3113,6 +3171,17 @@ int ccns_coef_classes(const ccns_ctx *ctx) { return ctx ? ctx->ncls : -1; }
 ccns_status ccns_ctx_create(const ccns_grid *grid, const ccns_params *params, const double *caps_host,
                             const double *dirichlet_host, void *dev_workspace, size_t ws_bytes, void *hip_stream,
                             ccns_ctx **out) {
+    return create_ctx(grid, params, caps_host, dirichlet_host, dev_workspace, ws_bytes, hip_stream, out);
+}
+
+
+}  // extern "C"
+
+namespace {
+
+ccns_status create_ctx(const ccns_grid *grid, const ccns_params *params, const double *caps_host,
+                       const double *dirichlet_host, void *dev_workspace, size_t ws_bytes, void *hip_stream,
+                       ccns_ctx **out) {
     if (!out) return CCNS_EINVAL;
     *out = nullptr;
     if (!grid || !params || !caps_host || !dirichlet_host || !dev_workspace) return CCNS_EINVAL;
@@ -3184,12 +3253,14 @@ ccns_status ccns_ctx_create(const ccns_grid *grid, const ccns_params *params, co
     if (hipHostMalloc((void **)&c->h_st, sizeof(CgState)) != hipSuccess ||
         hipHostMalloc((void **)&c->h_diag, sizeof(DiagState)) != hipSuccess ||
         hipHostMalloc((void **)&c->h_outer, 8 * sizeof(double)) != hipSuccess) {
-        ccns_ctx_destroy(c);
+        destroy_ctx(c);
         return CCNS_EDEVICE;
     }
-    // zero the whole workspace, then upload the coefficient fields
-    if (hipMemsetAsync(c->base, 0, c->w.total, c->stream) != hipSuccess) {
-        ccns_ctx_destroy(c);
+    // zero the whole workspace (it is a multiple of 256 bytes), then upload
+    // the coefficient fields
+    k_zero<<<flat_blocks(c->w.total / 8), NT, 0, c->stream>>>(c->w.total / 8, (unsigned long long *)c->base);
+    if (hipGetLastError() != hipSuccess) {
+        destroy_ctx(c);
         return CCNS_EDEVICE;
     }
     const std::vector<double> *src[] = {&hc.cx, &hc.cy, &hc.dinv, &hc.gx, &hc.gy, &hc.ax, &hc.ay, &hc.het,
@@ -3198,7 +3269,7 @@ ccns_status ccns_ctx_create(const ccns_grid *grid, const ccns_params *params, co
                                         &hc.hdx, &hc.hdy, &hc.vinv, &hc.vur, &hc.vvr, &hc.vdx, &hc.vdy};
     for (int k = 0; k <= A_VDY; ++k) {
         if ((s = to_dev(c, c->a[k], src[k]->data(), hipMemcpyHostToDevice)) != CCNS_OK) {
-            ccns_ctx_destroy(c);
+            destroy_ctx(c);
             return s;
         }
     }
@@ -3222,7 +3293,7 @@ ccns_status ccns_ctx_create(const ccns_grid *grid, const ccns_params *params, co
         for (int k = 0; k < 3 && ok; ++k) ok = up32(c->f[d32[k]], *s32[k]);
         for (int k = 0; k < 14 && ok; ++k) ok = up32(c->f[q32[k]], *p32[k]);
         if (!ok) {
-            ccns_ctx_destroy(c);
+            destroy_ctx(c);
             return CCNS_EDEVICE;
         }
     }
@@ -3230,11 +3301,11 @@ ccns_status ccns_ctx_create(const ccns_grid *grid, const ccns_params *params, co
     to_dev(c, c->a[A_UX], hc.dx.data(), hipMemcpyHostToDevice);
     to_dev(c, c->a[A_UY], hc.dy.data(), hipMemcpyHostToDevice);
     if (params->precond == 1 && (s = mg_setup(c, hc)) != CCNS_OK) {
-        ccns_ctx_destroy(c);
+        destroy_ctx(c);
         return s;
     }
     if ((s = pred_classes(c, hc)) != CCNS_OK) {
-        ccns_ctx_destroy(c);
+        destroy_ctx(c);
         return s;
     }
     set_cg(c, c->st_pred, params->pred_tol, params->pred_maxit, 0, hc.n_uact + hc.n_vact);
@@ -3242,22 +3313,18 @@ ccns_status ccns_ctx_create(const ccns_grid *grid, const ccns_params *params, co
     set_cg(c, c->st_pred_in, INNER_TOL_MIN, params->pred_maxit, 0, hc.n_uact + hc.n_vact);
     set_cg(c, c->st_pois_in, INNER_TOL_MIN, params->pcg_maxit, 1, hc.n_active);
     if (hipStreamSynchronize(c->stream) != hipSuccess) {
-        ccns_ctx_destroy(c);
+        destroy_ctx(c);
         return CCNS_EDEVICE;
     }
     *out = c;
     return CCNS_OK;
 }
 
-void ccns_ctx_destroy(ccns_ctx *ctx) {
-    if (!ctx) return;
-    (void)hipStreamSynchronize(ctx->stream);
-    if (ctx->h_st) (void)hipHostFree(ctx->h_st);
-    if (ctx->h_diag) (void)hipHostFree(ctx->h_diag);
-    if (ctx->h_outer) (void)hipHostFree(ctx->h_outer);
-    for (hipEvent_t e : ctx->evpool) (void)hipEventDestroy(e);
-    delete ctx;
-}
+}  // namespace
+
+extern "C" {
+
+void ccns_ctx_destroy(ccns_ctx *ctx) { destroy_ctx(ctx); }
 
 static const int kFieldArr[CCNS_NFIELDS] = {A_UX, A_UY, A_P, A_PHI, A_CONVX, A_CONVY, A_USX, A_USY, A_B};
 

@@ -6,10 +6,11 @@ with an arrival time.  The server
   * admits requests in arrival order (first come, first served) while their
     device footprint (ccns_workspace_bytes plus field buffers) fits in an HBM
     budget; a request that does not fit waits at the head of the queue;
-  * prepares each admitted request: capacities from the level set and the
-    seeded inputs on a host worker, overlapping the GPU work of the running
-    batch; then, on the driver thread, a context on a stream of its own and
-    the initial projection;
+  * prepares each admitted request on a preparation worker, overlapping the
+    GPU work of the running batch: the capacities (on the device, in closed
+    form, when every body is a circle or an ellipse; else from the level set
+    on the host), the seeded inputs, a context on a stream of its own and the
+    initial projection;
   * runs every prepared simulation on a step worker of its own (continuous
     batching without rounds: a simulation joins the GPU as soon as it is
     prepared, shares it with the others, each on its own stream, and leaves
@@ -49,6 +50,8 @@ class Record:
     bytes: int
     arrival: float
     admit: float = float("nan")
+    prepared: float = float("nan")
+    caps_s: float = float("nan")
     start: float = float("nan")
     completion: float = float("nan")
     div_rel_max: float = 0.0
@@ -68,6 +71,10 @@ class Record:
     def service(self):
         return self.completion - self.admit
 
+    @property
+    def preparation(self):
+        return self.prepared - self.admit
+
 
 def _seeded_inputs(case):
     """The synthetic requests' inputs: free-stream Dirichlet data with
@@ -81,13 +88,16 @@ def _seeded_inputs(case):
 
 def footprint(case, params) -> int:
     """Device bytes one simulation holds while it is served: the workspace
-    plus the dense field buffers used while its inputs are uploaded."""
+    plus the dense field buffers used while its inputs are uploaded, or the
+    capacity arrays and their scratch while the capacities are computed on
+    the device (21 + 6 arrays), whichever is more."""
     import ctypes as C
 
     L = ccns.lib()
     g = ccns.make_grid(case.grid)
     ws = L.ccns_workspace_bytes(C.byref(g), C.byref(params))
-    return int(ws + 256 + 8 * (case.grid.nx + 2) * (case.grid.ny + 2) * 8)
+    n = (case.grid.nx + 2) * (case.grid.ny + 2)
+    return int(ws + 256 + max(8, ccns.NCAPS + 6) * n * 8)
 
 
 def default_budget(fraction=0.85) -> int:
@@ -102,12 +112,13 @@ class Server:
     """Continuous-batching server for simulation requests on one GPU."""
 
     def __init__(self, hbm_budget: Optional[int] = None, precision: int = 1, threads: int = 16,
-                 prep_workers: int = 4, keep_fields: bool = False, inputs=None):
+                 prep_workers: int = 4, keep_fields: bool = False, inputs=None, device_caps: bool = True):
         self.budget = hbm_budget if hbm_budget is not None else default_budget()
         self.precision = precision
         self.threads = threads
         self.prep_workers = prep_workers
         self.keep_fields = keep_fields
+        self.device_caps = device_caps
         # inputs(case) -> (Dx, Dy, ux_perturbation, uy_perturbation)
         self.inputs = inputs if inputs is not None else _seeded_inputs
         self.max_used = 0      # largest admitted footprint total seen by the last run
@@ -120,31 +131,33 @@ class Server:
                                 pred_tol=1e-12, precision=self.precision, div_tol=1e-8,
                                 mass_floor=case.mass_floor, pcg_maxit=self.pcg_maxit, pred_maxit=500)
 
-    def _host_prepare(self, case):
-        """Host worker (no GPU calls): capacities from the level set and the
-        request's seeded inputs."""
+    def _prepare(self, case):
+        """Preparation worker: capacities (closed form on the device for
+        circles and ellipses, else the host quadrature), the request's seeded
+        inputs, a context on a fresh stream, the initial field and the initial
+        projection.  Returns (context, stream, projection info, seconds spent
+        on the capacities)."""
+        import torch
+
         g = case.grid
-        caps = ccns.ccns_capacities(g, case.bodies)
+        stream = torch.cuda.Stream()
+        t0 = time.perf_counter()
+        if self.device_caps and case.bodies and all(b.kind in (ccns.CIRCLE, ccns.ELLIPSE) for b in case.bodies):
+            with torch.cuda.stream(stream):
+                caps = ccns.ccns_capacities_device(g, case.bodies, stream).cpu().numpy()
+        else:
+            caps = ccns.ccns_capacities(g, case.bodies)
+        t_caps = time.perf_counter() - t0
         Dx, Dy, px, py = self.inputs(case)
         sh = (g.ny + 2, g.nx + 2)
         J, I = np.indices(sh)
         au = (I >= 1) & (I <= g.nx - 1) & (J >= 1) & (J <= g.ny) & (caps[7] > 0) & (caps[1] > 0)
         av = (I >= 1) & (I <= g.nx) & (J >= 1) & (J <= g.ny - 1) & (caps[14] > 0) & (caps[2] > 0)
-        return caps, Dx, Dy, np.where(au, case.u_inf + px, Dx), np.where(av, py, Dy)
-
-    def _device_prepare(self, case, host):
-        """Driver thread: context on a fresh stream, initial field, initial
-        projection.  Device memory is allocated and freed only on the driver
-        thread; the step workers only call ccns_step on their own context."""
-        import torch
-
-        caps, Dx, Dy, ux0, uy0 = host
-        stream = torch.cuda.Stream()
-        ctx = ccns.Context(case.grid, self._params(case), caps, Dx, Dy, stream=stream)
-        ctx.set_field(ccns.F_UX, ux0)
-        ctx.set_field(ccns.F_UY, uy0)
+        ctx = ccns.Context(g, self._params(case), caps, Dx, Dy, stream=stream)
+        ctx.set_field(ccns.F_UX, np.where(au, case.u_inf + px, Dx))
+        ctx.set_field(ccns.F_UY, np.where(av, py, Dy))
         info = ctx.project()
-        return ctx, stream, info
+        return ctx, stream, info, t_caps
 
     @staticmethod
     def _run_steps(ctx, steps, clock):
@@ -161,7 +174,8 @@ class Server:
                 if si.status != ccns.OK and status == ccns.OK:
                     status = si.status
                     note = (f"step {n}: {name} solve status {si.status} after {si.iterations} iterations, "
-                            f"{si.outer} sweeps, relative residual {si.rel_residual:.2e}")
+                            f"{si.outer} sweeps, relative residual {si.rel_residual:.2e}, inner status "
+                            f"{si.inner_status} (first at sweep {si.inner_fail_sweep})")
             if status != ccns.OK:
                 break
         return start, clock(), div, status, note
@@ -206,10 +220,11 @@ class Server:
                     free -= r.bytes
                     self.max_used = max(self.max_used, self.budget - free)
                     r.admit = clock()
-                    preparing[prep_pool.submit(self._host_prepare, cases[r.index])] = r
+                    preparing[prep_pool.submit(self._prepare, cases[r.index])] = r
                 for fut in [f for f in preparing if f.done()]:
                     r = preparing.pop(fut)
-                    ctx, stream, info = self._device_prepare(cases[r.index], fut.result())
+                    ctx, stream, info, r.caps_s = fut.result()
+                    r.prepared = clock()
                     r.div_rel_max = info.div_rel
                     running[step_pool.submit(self._run_steps, ctx, r.steps, clock)] = (r, ctx)
                 for fut in [f for f in running if f.done()]:
@@ -253,6 +268,9 @@ def summarize(recs: Sequence[Record], wall: float) -> dict:
         "queue_p99_s": float(np.percentile(que, 99)),
         "service_p50_s": float(np.percentile(svc, 50)),
         "service_p99_s": float(np.percentile(svc, 99)),
+        "preparation_p50_s": float(np.percentile([r.preparation for r in recs], 50)),
+        "preparation_p99_s": float(np.percentile([r.preparation for r in recs], 99)),
+        "capacities_p50_s": float(np.percentile([r.caps_s for r in recs], 50)),
         "throughput_mcell_steps_s": cell_steps / wall / 1e6,
         "wall_s": wall,
         "div_rel_max": float(max(r.div_rel_max for r in recs)),

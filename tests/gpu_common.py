@@ -38,3 +38,84 @@ def rel(a, b, mask=None):
         a, b = a[mask], b[mask]
     den = max(np.max(np.abs(b)), 1e-300)
     return float(np.max(np.abs(a - b)) / den)
+
+
+def budgets_match(ccns_info, st, ux, uy, Dx, Dy):
+    """The device's FP64 budgets of a state (ccns_step_info: net flux,
+    kinetic energy, momentum of the mass matrix) against the oracle's sums
+    of the same state: mass = sum over real cells of cont(U, D), ke = sum of
+    kinetic(U) (Sec. 4.5), mom = rho sum M U over the velocity unknowns.
+    Each difference is compared with the sum of the magnitudes of its terms
+    (different summation orders of the same terms)."""
+    from oracle import operators as ops
+
+    caps, rho = st.pr.caps, st.prm.rho
+    d = ops.cont(caps, ux, uy, Dx, Dy)[1:-1, 1:-1]
+    flux = np.abs(caps["Ax"] * ux).sum() + np.abs(caps["Ay"] * uy).sum()
+    ke = ops.kinetic(caps, ux, uy)[1:-1, 1:-1]
+    mx, my = rho * st.Vu * ux, rho * st.Vv * uy
+    return {
+        "mass": abs(ccns_info.mass - d.sum()) / max(flux, 1e-300),
+        "ke": abs(ccns_info.ke - ke.sum()) / max(np.abs(ke).sum(), 1e-300),
+        "mom_x": abs(ccns_info.mom_x - mx.sum()) / max(np.abs(mx).sum(), 1e-300),
+        "mom_y": abs(ccns_info.mom_y - my.sum()) / max(np.abs(my).sum(), 1e-300),
+    }
+
+
+def step_against_oracle_systems(case, pr, st, ctx, Dx, Dy, tag=""):
+    """One projection step of the device checked against the oracle at any
+    size: from the device's projected state, conv^n element by element; U*
+    satisfies the oracle's predictor system; b element by element; Phi
+    satisfies the oracle's Poisson system; the corrector and the pressure
+    update recomputed by the oracle from the device's U* and Phi match
+    element by element; the new state's divergence and budgets.  Returns the
+    device's step info."""
+    import workloads as W
+    from oracle import derived, pmii
+    from paper_2211_10698_amd import ccns
+
+    prm = st.prm
+    host = lambda t: t.cpu().numpy()  # noqa: E731
+    s0 = pmii.initial_state(pr, Dx, Dy, case.u_inf, W.perturbation(case))
+    ctx.set_field(ccns.F_UX, s0.Ux)
+    ctx.set_field(ccns.F_UY, s0.Uy)
+    pinfo = ctx.project()
+    assert pinfo.div_rel < 1e-8
+    Un = (host(ctx.get_field(ccns.F_UX)), host(ctx.get_field(ccns.F_UY)))
+    Pn = host(ctx.get_field(ccns.F_P))
+    od = st.diagnostics(Un[0], Un[1], pmii.StepInfo())
+    assert od.div_rel < 1e-8
+    sn = pmii.State(Un[0].copy(), Un[1].copy(), Pn.copy(), np.zeros_like(Pn))
+    print(f"[oracle-systems{tag}] predictor", flush=True)
+    info_p = ctx.predict()
+    assert info_p.status == 0
+    conv_n = st.convection(*Un)
+    assert rel(host(ctx.get_field(ccns.F_CONVX)), conv_n[0], pr.act_u) < 1e-13
+    assert rel(host(ctx.get_field(ccns.F_CONVY)), conv_n[1], pr.act_v) < 1e-13
+    rhs = st.predictor_rhs(sn, conv_n, conv_n)
+    Us = (host(ctx.get_field(ccns.F_USX)), host(ctx.get_field(ccns.F_USY)))
+    assert np.array_equal(Us[0][~pr.act_u], Dx[~pr.act_u]) and np.array_equal(Us[1][~pr.act_v], Dy[~pr.act_v])
+    U2 = np.stack([np.where(pr.act_u, Us[0], 0.0), np.where(pr.act_v, Us[1], 0.0)])
+    res = np.where(st.mask2, rhs - st.apply_H(U2), 0.0)
+    # the device tests its own residual against pred_tol; its recurrence and
+    # the true residual drift apart by rounding, hence the factor
+    assert np.linalg.norm(res) <= 5 * prm.pred_tol * np.linalg.norm(rhs)
+    print(f"[oracle-systems{tag}] correction", flush=True)
+    info = ctx.correct()
+    assert info.poisson.status == 0
+    b = st.poisson_rhs(*Us)
+    assert rel(host(ctx.get_field(ccns.F_B)), b, pr.act_p) < 1e-12
+    phi = host(ctx.get_field(ccns.F_PHI))
+    r = np.where(pr.act_p, b - derived.laplacian(pr, phi), 0.0)
+    assert np.linalg.norm(r) <= 1.05 * prm.pcg_tol * np.linalg.norm(b)
+    ux, uy = st.correct(Us[0], Us[1], phi)
+    assert rel(host(ctx.get_field(ccns.F_UX)), ux) < 1e-13
+    assert rel(host(ctx.get_field(ccns.F_UY)), uy) < 1e-13
+    P1 = st.pressure_update(Pn, phi)
+    assert rel(host(ctx.get_field(ccns.F_P)), P1, pr.act_p) < 1e-12
+    od = st.diagnostics(ux, uy, pmii.StepInfo())
+    assert od.div_rel < 1e-8 and info.div_rel < 1e-8
+    errs = budgets_match(info, st, ux, uy, Dx, Dy)
+    print(f"[oracle-systems{tag}] budgets {errs}", flush=True)
+    assert all(e < 1e-12 for e in errs.values()), errs
+    return info

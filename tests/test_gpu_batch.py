@@ -86,21 +86,24 @@ def test_batch_matches_solo_runs_bit_for_bit():
         c.close()
 
 
-def test_batch_member_matches_oracle():
-    """The 64x64 cylinder inside a batch against the oracle (10 steps at
-    tight tolerances, as the solo trajectory test)."""
+@pytest.mark.parametrize("theta", [0.0, 0.05])
+@pytest.mark.parametrize("name", ["cylinder_64", "flat_top_64"])
+def test_batch_member_matches_oracle(name, theta):
+    """A 64x64 case inside a batch against the oracle (10 steps at tight
+    tolerances, as the solo trajectory test), at the paper's mass matrix
+    (theta = 0) and with the small-volume floor."""
     from paper_2211_10698_amd import ccns
     from oracle import derived
-    case = W.cylinder_64()
+    case = W.cylinder_64() if name == "cylinder_64" else W.flat_top_cylinder(64)
     g = case.grid
     caps = geometry.capacities(g, case.bodies)
-    pr = derived.prepare(caps, g.nx, g.ny, vol_floor=case.mass_floor * g.hx * g.hy)
+    pr = derived.prepare(caps, g.nx, g.ny, vol_floor=theta * g.hx * g.hy)
     Dx, Dy = W.dirichlet(case)
     st = pmii.Stepper(pr, pmii.Params(rho=case.rho, mu=case.mu, tau=case.tau, pcg_tol=1e-13, pred_tol=1e-14),
                       Dx, Dy, g.hx)
     s0 = pmii.initial_state(pr, Dx, Dy, case.u_inf, W.perturbation(case))
     capsarr = np.stack([caps[k] for k in ccns.CAP_NAMES])
-    prm = ccns.make_params(case.rho, case.mu, case.tau, pcg_tol=1e-13, pred_tol=1e-14, mass_floor=case.mass_floor)
+    prm = ccns.make_params(case.rho, case.mu, case.tau, pcg_tol=1e-13, pred_tol=1e-14, mass_floor=theta)
     streams = [torch.cuda.Stream() for _ in range(3)]
     ctxs = [ccns.Context(g, prm, capsarr, Dx, Dy, stream=s) for s in streams]
     for c in ctxs:

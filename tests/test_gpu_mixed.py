@@ -20,7 +20,10 @@ torch = pytest.importorskip("torch")
 CASES = {
     "cylinder_64": lambda: W.cylinder_64(),
     "channel_130x73": lambda: W.scaled_cylinder(130, 73, 2.6, 1.46, seed=5),
+    "flat_top_64": lambda: W.flat_top_cylinder(64),
 }
+# small-volume floor: 0 is the paper's mass matrix, 0.05 the floored reading
+THETAS = (0.0, 0.05)
 
 
 def _dev(a):
@@ -52,15 +55,17 @@ def test_mixed_pressure_solve_meets_fp64_residual(name, precond):
         assert rel(pz, phi_o, pr.act_p) < 1e-6
 
 
+@pytest.mark.parametrize("theta", THETAS)
 @pytest.mark.parametrize("name", sorted(CASES))
-def test_mixed_trajectory_against_fp64_oracle(name):
+def test_mixed_trajectory_against_fp64_oracle(name, theta):
     from paper_2211_10698_amd import ccns
     case = CASES[name]()
     # oracle: FP64 with tight tolerances; device: precision 1 at its defaults
-    caps, pr, st, ctx, Dx, Dy = case_setup(case, pcg_tol=1e-13, pred_tol=1e-14, precision=1, div_tol=1e-8)
+    caps, pr, st, ctx, Dx, Dy = case_setup(case, pcg_tol=1e-13, pred_tol=1e-14, precision=1, div_tol=1e-8,
+                                           mass_floor=theta)
     ctx.close()
     cp = ccns.make_params(case.rho, case.mu, case.tau, u_ref=case.u_inf, pcg_tol=1e-10, pred_tol=1e-10,
-                          div_tol=1e-8, precision=1, mass_floor=case.mass_floor)
+                          div_tol=1e-8, precision=1, mass_floor=theta)
     ctx = ccns.Context(case.grid, cp, np.stack([caps[k] for k in ccns.CAP_NAMES]), Dx, Dy)
     s0 = pmii.initial_state(pr, Dx, Dy, case.u_inf, W.perturbation(case))
     ctx.set_field(ccns.F_UX, s0.Ux)

@@ -16,7 +16,7 @@ import pytest
 
 import workloads as W
 from oracle import derived, operators as ops
-from tests.gpu_common import rel
+from tests.gpu_common import rel, step_against_oracle_systems
 
 pytestmark = pytest.mark.gpu
 
@@ -66,6 +66,25 @@ def test_naca_operator_applies_full_size(naca):
     assert rel(cx.cpu().numpy(), kx) < 1e-13 and rel(cy.cpu().numpy(), ky) < 1e-13
     (q,) = ctx.apply(ccns.OP_LAP, [dev(P)])
     assert rel(q.cpu().numpy(), derived.laplacian(pr, P)) < 1e-13
+    ctx.close()
+
+
+def test_naca_step_against_oracle_systems(naca):
+    from oracle import pmii
+    from paper_2211_10698_amd import ccns
+    case, capsarr = naca
+    g = case.grid
+    caps = {k: capsarr[i] for i, k in enumerate(ccns.CAP_NAMES)}
+    pr = derived.prepare(caps, g.nx, g.ny, vol_floor=case.mass_floor * g.hx * g.hy)
+    Dx, Dy = W.dirichlet(case)
+    prm = pmii.Params(rho=case.rho, mu=case.mu, tau=case.tau, u_inf=case.u_inf, pcg_tol=case.pcg_tol,
+                      pred_tol=1e-12)
+    # the oracle stepper only applies operators here (no solve)
+    st = pmii.Stepper(pr, prm, Dx, Dy, min(g.hx, g.hy), jacobi=False)
+    ctx = ccns.Context(g, ccns.make_params(case.rho, case.mu, case.tau, u_ref=case.u_inf, pcg_tol=case.pcg_tol,
+                                           pred_tol=1e-12, mass_floor=case.mass_floor), capsarr, Dx, Dy)
+    assert ctx.coef_classes() > 0
+    step_against_oracle_systems(case, pr, st, ctx, Dx, Dy, "-naca")
     ctx.close()
 
 

@@ -26,15 +26,23 @@ CASES = {
     "cylinder_64": lambda: W.cylinder_64(),
     # several tiles and a ragged tail in both directions (pitch 192, rows 75)
     "channel_130x73": lambda: W.scaled_cylinder(130, 73, 2.6, 1.46, seed=5),
+    # velocity unknowns and pressure cells with less than 5% of a cell's volume
+    "flat_top_64": lambda: W.flat_top_cylinder(64),
 }
+# The small-volume floor theta: 0 is the paper's mass matrix M = diag(V)
+# (eq:semidiscrete); 0.05 floors every volume the step divides by at 5% of a
+# cell (a departure wherever a volume is below it: on channel_130x73 eight
+# pressure cells, on flat_top_64 velocity unknowns and cells; on cylinder_64
+# none, so there both values give the same step).
+THETAS = (0.0, 0.05)
 
 
-@pytest.fixture(scope="module", params=[(c, p) for c in CASES for p in ("jacobi", "mg")],
-                ids=lambda cp: f"{cp[0]}-{cp[1]}")
+@pytest.fixture(scope="module", params=[(c, p, th) for c in CASES for p in ("jacobi", "mg") for th in THETAS],
+                ids=lambda cp: f"{cp[0]}-{cp[1]}-theta{cp[2]}")
 def setup(request):
-    name, precond = request.param
+    name, precond, theta = request.param
     case = CASES[name]()
-    return case, case_setup(case, precond=precond), precond
+    return case, case_setup(case, precond=precond, mass_floor=theta), precond
 
 
 def _fields(case, pr, Dx, Dy, seed):
@@ -140,14 +148,17 @@ def test_step_phases_match(setup):
     assert abs(info.ke - od.ke) < 1e-10 * od.ke
 
 
+@pytest.mark.parametrize("theta", THETAS)
+@pytest.mark.parametrize("name", ["cylinder_64", "flat_top_64"])
 @pytest.mark.parametrize("precond", ["jacobi", "mg"])
-def test_trajectory_tight_tolerance(precond):
-    """Ten steps on the 64x64 cylinder with tight solver tolerances: the
-    trajectories agree to 1e-11 relative (both solves converge far below
-    the differences that rounding order can cause)."""
+def test_trajectory_tight_tolerance(precond, name, theta):
+    """Ten steps with tight solver tolerances: the trajectories agree to
+    1e-11 relative (both solves converge far below the differences that
+    rounding order can cause), at the paper's mass matrix (theta = 0) and
+    with the small-volume floor."""
     from paper_2211_10698_amd import ccns
-    case = W.cylinder_64()
-    caps, pr, st, ctx, Dx, Dy = case_setup(case, pcg_tol=1e-13, pred_tol=1e-14, precond=precond)
+    case = CASES[name]()
+    caps, pr, st, ctx, Dx, Dy = case_setup(case, pcg_tol=1e-13, pred_tol=1e-14, precond=precond, mass_floor=theta)
     s0 = pmii.initial_state(pr, Dx, Dy, case.u_inf, W.perturbation(case))
     ctx.set_field(ccns.F_UX, s0.Ux)
     ctx.set_field(ccns.F_UY, s0.Uy)

@@ -345,7 +345,8 @@ def test_linear_shear_between_mesh_aligned_walls_is_exact():
 
 def test_classical_mac_away_from_bodies():
     """No body, uniform grid: the operators reduce to the textbook MAC formulas
-    (P:240-243 style reductions, written here directly in h)."""
+    (the full-cell reductions of the 1-D example of Sec. 2.3, written here
+    directly in h)."""
     g = W.GridSpec(7, 6, 0.0, 0.0, 0.7, 0.9)
     hx, hy = g.hx, g.hy
     c = geometry.capacities(g, [])

@@ -144,6 +144,55 @@ def naca_4096() -> Case:
                 pcg_tol=1e-10, noise=1e-3, seed=3)
 
 
+def naca_section(nx: int = 64, ny: int = 32, seed: int = 11, steps: int = 10, re: float = 200.0) -> Case:
+    """A coarse NACA0012 case, [0,2]x[0,1], chord 1 at 5 degrees with its
+    leading edge at (0.45, 0.55): at 64x32 some x-face control volumes near
+    the trailing edge hold less than 5% of a cell, so the small-volume floor
+    acts on velocity unknowns as well as on pressure cells.  CFL 0.25."""
+    g = GridSpec(nx, ny, 0.0, 0.0, 2.0, 1.0)
+    body = Body(NACA4, 0.45, 0.55, angle=math.radians(5.0), chord=1.0, t=0.12)
+    return Case(f"naca0012_{nx}x{ny}", g, [body], re=re, steps=steps, cfl=0.25,
+                pcg_tol=1e-10, noise=1e-2, seed=seed)
+
+
+def flat_top_cylinder(n: int = 64, seed: int = 14, steps: int = 10) -> Case:
+    """Unit box, circle of radius 0.3 centred on the line x = 0.5 whose top
+    lies 0.02 h below a grid line: over the width of a cell the circle is
+    nearly flat there, so the cells and face control volumes just below that
+    line keep a fluid strip of 2-4% of a cell (velocity unknowns and pressure
+    cells below a small-volume floor of 5%).  Re 100, CFL 0.25."""
+    g = GridSpec(n, n, 0.0, 0.0, 1.0, 1.0)
+    h = 1.0 / n
+    r = 0.3
+    top = math.floor((0.5 + r) / h) * h - 0.02 * h
+    return Case(f"flat_top_cylinder_{n}", g, [Body(CIRCLE, 0.5, top - r, a=r)], re=100.0, steps=steps,
+                cfl=0.25, pcg_tol=1e-10, noise=1e-2, seed=seed)
+
+
+def ellipses(n: int = 96, seed: int = 12, steps: int = 10) -> Case:
+    """Three ellipses in the unit box (the serving trace's body family):
+    semi-axes 0.05-0.12, several orientations, at least 4h apart.  Re 200
+    on twice the largest semi-axis, CFL 0.25."""
+    g = GridSpec(n, n, 0.0, 0.0, 1.0, 1.0)
+    bodies = [Body(ELLIPSE, 0.32, 0.33, a=0.12, b=0.06, angle=0.4),
+              Body(ELLIPSE, 0.68, 0.40, a=0.09, b=0.05, angle=2.1),
+              Body(ELLIPSE, 0.47, 0.70, a=0.10, b=0.07, angle=1.2)]
+    return Case(f"ellipses3_{n}", g, bodies, re=200.0, steps=steps, cfl=0.25,
+                pcg_tol=1e-10, noise=1e-2, seed=seed)
+
+
+def pocket(n: int = 64, seed: int = 13, steps: int = 5) -> Case:
+    """Four overlapping circles around (0.5, 0.5) that enclose a small fluid
+    pocket cut off from the rest of the fluid (its cells are no pressure
+    unknowns).  Re 100 on the circles' diameter, CFL 0.25."""
+    g = GridSpec(n, n, 0.0, 0.0, 1.0, 1.0)
+    d, r = 0.125, 0.1
+    bodies = [Body(CIRCLE, 0.5 + d, 0.5, a=r), Body(CIRCLE, 0.5 - d, 0.5, a=r),
+              Body(CIRCLE, 0.5, 0.5 + d, a=r), Body(CIRCLE, 0.5, 0.5 - d, a=r)]
+    return Case(f"pocket_{n}", g, bodies, re=100.0, steps=steps, cfl=0.25,
+                pcg_tol=1e-10, noise=1e-2, seed=seed)
+
+
 def scaled_cylinder(nx: int, ny: int, lx: float, ly: float, seed: int = 2,
                     steps: int = 10) -> Case:
     """A smaller member of the channel-cylinder family (same geometry ratios)."""
