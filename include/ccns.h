@@ -200,6 +200,27 @@ ccns_status ccns_ctx_create(const ccns_grid *grid, const ccns_params *params,
 void ccns_ctx_destroy(ccns_ctx *ctx);
 const char *ccns_last_error(const ccns_ctx *ctx);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): ccns_ctx_create without a
+ * workspace argument.  The context uses the library's static workspace of
+ * the current device, an array of CCNS_STATIC_WORKSPACE_BYTES (64 MiB) that
+ * each device the library runs on holds until the process ends, and calls no
+ * hipMalloc, hipHostMalloc, hipFree or other allocating routine (its host
+ * copies of the solver state live in the context record, which is on the host
+ * heap as every context is).  Everything else is as ccns_ctx_create: the same
+ * kernels, the same results bit for bit.
+ *  - Size limit: ccns_workspace_bytes(grid, params) <= 64 MiB, e.g. grids up to
+ *    256 x 256 cells in either precision; larger ones fail with CCNS_ENOMEM.
+ *  - One such context per device at a time: the workspace is shared, so a
+ *    second call while one lives on the current device fails with
+ *    CCNS_ESTATE; ccns_ctx_destroy releases it.  The workspace keeps the last
+ *    context's contents; creation clears all of it.
+ *  - ccns_timing cannot be enabled on it (HIP events are allocated).
+ * Errors: as ccns_ctx_create, plus CCNS_ENOMEM (too large) and CCNS_ESTATE. */
+#define CCNS_STATIC_WORKSPACE_BYTES ((size_t)64 << 20)
+ccns_status ccns_ctx_create_static(const ccns_grid *grid, const ccns_params *params,
+                                   const double *caps_host, const double *dirichlet_host,
+                                   void *hip_stream, ccns_ctx **out);
 
 /* Number of coefficient classes the predictor's kernels of this context
  * read (see coef_tables in ccns_params); 0 when they read the coefficient

@@ -92,6 +92,9 @@ def lib():
         L.ccns_ctx_create.restype = C.c_int
         L.ccns_ctx_create.argtypes = [P(Grid), P(Params), C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t,
                                       C.c_void_p, P(C.c_void_p)]
+        L.ccns_ctx_create_static.restype = C.c_int
+        L.ccns_ctx_create_static.argtypes = [P(Grid), P(Params), C.c_void_p, C.c_void_p, C.c_void_p,
+                                             P(C.c_void_p)]
         L.ccns_ctx_destroy.restype = None
         L.ccns_ctx_destroy.argtypes = [C.c_void_p]
         L.ccns_last_error.restype = C.c_char_p
@@ -127,7 +130,7 @@ def lib():
 
 
 EXPORTED = ("ccns_caps_count", "ccns_capacities", "ccns_capacities_scratch_bytes", "ccns_capacities_device",
-            "ccns_workspace_bytes", "ccns_ctx_create",
+            "ccns_workspace_bytes", "ccns_ctx_create", "ccns_ctx_create_static",
             "ccns_ctx_destroy", "ccns_last_error", "ccns_coef_classes", "ccns_field_set", "ccns_field_get", "ccns_apply",
             "ccns_pressure_solve", "ccns_project", "ccns_step", "ccns_predict", "ccns_correct",
             "ccns_diagnostics", "ccns_timing", "ccns_batch_create", "ccns_batch_step", "ccns_batch_destroy")
@@ -198,11 +201,16 @@ def make_params(rho, mu, tau, u_ref=1.0, pcg_tol=1e-10, pred_tol=1e-12, div_tol=
                   visc_form, poisson_weight, precond, mass_floor, coef_tables)
 
 
+STATIC_WORKSPACE_BYTES = 64 << 20
+
+
 class Context:
-    """One simulation on the device.  Owns a torch workspace tensor."""
+    """One simulation on the device.  Owns a torch workspace tensor, or with
+    static=True uses the library's static workspace (ccns_ctx_create_static:
+    no allocation; one such context per device at a time)."""
 
     def __init__(self, spec, params: Params, caps: np.ndarray, dx: np.ndarray, dy: np.ndarray,
-                 device="cuda", stream=None):
+                 device="cuda", stream=None, static=False):
         import torch
 
         self.torch = torch
@@ -218,6 +226,14 @@ class Context:
         caps = np.ascontiguousarray(caps, dtype=np.float64)
         dirichlet = np.ascontiguousarray(np.stack([dx, dy]), dtype=np.float64)
         h = C.c_void_p()
+        if static:
+            self.ws = None
+            st = L.ccns_ctx_create_static(C.byref(self.g), C.byref(params), caps.ctypes.data, dirichlet.ctypes.data,
+                                          C.c_void_p(self.stream.cuda_stream), C.byref(h))
+            if st != OK:
+                raise CcnsError(st, "ccns_ctx_create_static")
+            self.h = h
+            return
         nbytes = L.ccns_workspace_bytes(C.byref(self.g), C.byref(params))
         if nbytes == 0:
             raise CcnsError(EINVAL, "bad grid")

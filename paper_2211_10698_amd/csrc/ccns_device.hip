@@ -25,6 +25,7 @@
 #include <cstring>
 #include <new>
 #include <atomic>
+#include <mutex>
 #include <string>
 #include <thread>
 #include <unordered_map>
@@ -2203,9 +2204,13 @@ struct ccns_ctx {
     CgState *st_pred_in, *st_pois_in;  // inner solves of precision 1
     DiagState *diag;
     double *outer;      // totals of the FP64 residual statistics (precision 1)
-    CgState *h_st;      // pinned host copies
+    CgState *h_st;      // pinned host copies (for a context without allocations: the members below)
     DiagState *h_diag;
     double *h_outer;
+    int static_dev;     // device whose static workspace the context uses, or -1
+    CgState st_host;
+    DiagState diag_host;
+    double outer_host[8];
     float *f[G_COUNT];  // precision 1 arrays
     int last_pois_in, last_pred_in;
     Dims dc, df;        // cell tiles (1 component) and face tiles (2 components)
@@ -2257,14 +2262,20 @@ ccns_status fail(ccns_ctx *c, ccns_status s, const std::string &msg) {
     return s;
 }
 
-// Frees a context (after its stream's work).
-void destroy_ctx(ccns_ctx *ctx) {
+void release_static(int dev);
+
+// Frees a context (after its stream's work); release: the context was
+// handed out, so its static workspace, if any, becomes free for the next one.
+void destroy_ctx(ccns_ctx *ctx, bool release) {
     if (!ctx) return;
     (void)hipStreamSynchronize(ctx->stream);
-    if (ctx->h_st) (void)hipHostFree(ctx->h_st);
-    if (ctx->h_diag) (void)hipHostFree(ctx->h_diag);
-    if (ctx->h_outer) (void)hipHostFree(ctx->h_outer);
+    if (ctx->static_dev < 0) {
+        if (ctx->h_st) (void)hipHostFree(ctx->h_st);
+        if (ctx->h_diag) (void)hipHostFree(ctx->h_diag);
+        if (ctx->h_outer) (void)hipHostFree(ctx->h_outer);
+    }
     for (hipEvent_t e : ctx->evpool) (void)hipEventDestroy(e);
+    if (release && ctx->static_dev >= 0) release_static(ctx->static_dev);
     delete ctx;
 }
 
@@ -3151,9 +3162,39 @@ __global__ __launch_bounds__(NT) void k_zero(size_t n, unsigned long long *__res
     for (size_t k = (size_t)blockIdx.x * NT + threadIdx.x; k < n; k += (size_t)gridDim.x * NT) p[k] = 0ull;
 }
 
+}  // namespace
+
+// Workspace of the contexts that allocate nothing (ccns_ctx_create_static):
+// one array per device, which the device holds until the process ends.  In
+// host code `scratch` only names the symbol; its device address comes from
+// hipGetSymbolAddress, once per device (static_workspace below).
+constexpr size_t STATIC_WS_BYTES = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[STATIC_WS_BYTES];
+
+namespace {
+
+constexpr int MAX_DEVICES = 64;
+struct StaticSlot {
+    std::once_flag once;
+    void *ptr = nullptr;           // device address of `scratch` on this device
+    hipError_t err = hipSuccess;
+    std::atomic<int> used{0};      // 1 while a context uses it
+};
+StaticSlot g_static[MAX_DEVICES];
+
+void release_static(int dev) { g_static[dev].used.store(0); }
+
+// Device address of the static workspace on the current device (taken once
+// per device, with that device current), or null.
+void *static_workspace(int dev) {
+    StaticSlot &s = g_static[dev];
+    std::call_once(s.once, [&] { s.err = hipGetSymbolAddress(&s.ptr, HIP_SYMBOL(scratch)); });
+    return s.err == hipSuccess ? s.ptr : nullptr;
+}
+
 ccns_status create_ctx(const ccns_grid *grid, const ccns_params *params, const double *caps_host,
                        const double *dirichlet_host, void *dev_workspace, size_t ws_bytes, void *hip_stream,
-                       ccns_ctx **out);
+                       int static_dev, ccns_ctx **out);
 
 }  // namespace
 
@@ -3171,9 +3212,28 @@ int ccns_coef_classes(const ccns_ctx *ctx) { return ctx ? ctx->ncls : -1; }
 ccns_status ccns_ctx_create(const ccns_grid *grid, const ccns_params *params, const double *caps_host,
                             const double *dirichlet_host, void *dev_workspace, size_t ws_bytes, void *hip_stream,
                             ccns_ctx **out) {
-    return create_ctx(grid, params, caps_host, dirichlet_host, dev_workspace, ws_bytes, hip_stream, out);
+    return create_ctx(grid, params, caps_host, dirichlet_host, dev_workspace, ws_bytes, hip_stream, -1, out);
 }
 
+ccns_status ccns_ctx_create_static(const ccns_grid *grid, const ccns_params *params, const double *caps_host,
+                                   const double *dirichlet_host, void *hip_stream, ccns_ctx **out) {
+    if (!out) return CCNS_EINVAL;
+    *out = nullptr;
+    if (!grid || !params || !caps_host || !dirichlet_host) return CCNS_EINVAL;
+    const size_t need = ccns_workspace_bytes(grid, params);
+    if (need == 0) return CCNS_EINVAL;
+    if (need > STATIC_WS_BYTES) return CCNS_ENOMEM;
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAX_DEVICES) return CCNS_EDEVICE;
+    void *ws = static_workspace(dev);
+    if (!ws) return CCNS_EDEVICE;
+    int expect = 0;
+    if (!g_static[dev].used.compare_exchange_strong(expect, 1)) return CCNS_ESTATE;
+    const ccns_status st = create_ctx(grid, params, caps_host, dirichlet_host, ws, STATIC_WS_BYTES, hip_stream,
+                                      dev, out);
+    if (st != CCNS_OK) g_static[dev].used.store(0);
+    return st;
+}
 
 }  // extern "C"
 
@@ -3181,7 +3241,7 @@ namespace {
 
 ccns_status create_ctx(const ccns_grid *grid, const ccns_params *params, const double *caps_host,
                        const double *dirichlet_host, void *dev_workspace, size_t ws_bytes, void *hip_stream,
-                       ccns_ctx **out) {
+                       int static_dev, ccns_ctx **out) {
     if (!out) return CCNS_EINVAL;
     *out = nullptr;
     if (!grid || !params || !caps_host || !dirichlet_host || !dev_workspace) return CCNS_EINVAL;
@@ -3192,6 +3252,7 @@ ccns_status create_ctx(const ccns_grid *grid, const ccns_params *params, const d
     if (!c) return CCNS_ENOMEM;
     c->g = *grid;
     c->prm = *params;
+    c->static_dev = static_dev;
     c->w = plan(grid->nx, grid->ny, params->precision);
     if (ws_bytes < c->w.total) {
         delete c;
@@ -3250,17 +3311,24 @@ ccns_status create_ctx(const ccns_grid *grid, const ccns_params *params, const d
         return s;
     }
     c->n_active = hc.n_active;
-    if (hipHostMalloc((void **)&c->h_st, sizeof(CgState)) != hipSuccess ||
-        hipHostMalloc((void **)&c->h_diag, sizeof(DiagState)) != hipSuccess ||
-        hipHostMalloc((void **)&c->h_outer, 8 * sizeof(double)) != hipSuccess) {
-        destroy_ctx(c);
+    if (static_dev >= 0) {
+        // no allocation: the host copies of the solver state live in the
+        // context record (the device-to-host copies then go through pageable
+        // memory, and the calls wait for them as they do for pinned memory)
+        c->h_st = &c->st_host;
+        c->h_diag = &c->diag_host;
+        c->h_outer = c->outer_host;
+    } else if (hipHostMalloc((void **)&c->h_st, sizeof(CgState)) != hipSuccess ||
+               hipHostMalloc((void **)&c->h_diag, sizeof(DiagState)) != hipSuccess ||
+               hipHostMalloc((void **)&c->h_outer, 8 * sizeof(double)) != hipSuccess) {
+        destroy_ctx(c, false);
         return CCNS_EDEVICE;
     }
     // zero the whole workspace (it is a multiple of 256 bytes), then upload
     // the coefficient fields
     k_zero<<<flat_blocks(c->w.total / 8), NT, 0, c->stream>>>(c->w.total / 8, (unsigned long long *)c->base);
     if (hipGetLastError() != hipSuccess) {
-        destroy_ctx(c);
+        destroy_ctx(c, false);
         return CCNS_EDEVICE;
     }
     const std::vector<double> *src[] = {&hc.cx, &hc.cy, &hc.dinv, &hc.gx, &hc.gy, &hc.ax, &hc.ay, &hc.het,
@@ -3269,7 +3337,7 @@ ccns_status create_ctx(const ccns_grid *grid, const ccns_params *params, const d
                                         &hc.hdx, &hc.hdy, &hc.vinv, &hc.vur, &hc.vvr, &hc.vdx, &hc.vdy};
     for (int k = 0; k <= A_VDY; ++k) {
         if ((s = to_dev(c, c->a[k], src[k]->data(), hipMemcpyHostToDevice)) != CCNS_OK) {
-            destroy_ctx(c);
+            destroy_ctx(c, false);
             return s;
         }
     }
@@ -3293,7 +3361,7 @@ ccns_status create_ctx(const ccns_grid *grid, const ccns_params *params, const d
         for (int k = 0; k < 3 && ok; ++k) ok = up32(c->f[d32[k]], *s32[k]);
         for (int k = 0; k < 14 && ok; ++k) ok = up32(c->f[q32[k]], *p32[k]);
         if (!ok) {
-            destroy_ctx(c);
+            destroy_ctx(c, false);
             return CCNS_EDEVICE;
         }
     }
@@ -3301,11 +3369,11 @@ ccns_status create_ctx(const ccns_grid *grid, const ccns_params *params, const d
     to_dev(c, c->a[A_UX], hc.dx.data(), hipMemcpyHostToDevice);
     to_dev(c, c->a[A_UY], hc.dy.data(), hipMemcpyHostToDevice);
     if (params->precond == 1 && (s = mg_setup(c, hc)) != CCNS_OK) {
-        destroy_ctx(c);
+        destroy_ctx(c, false);
         return s;
     }
     if ((s = pred_classes(c, hc)) != CCNS_OK) {
-        destroy_ctx(c);
+        destroy_ctx(c, false);
         return s;
     }
     set_cg(c, c->st_pred, params->pred_tol, params->pred_maxit, 0, hc.n_uact + hc.n_vact);
@@ -3313,7 +3381,7 @@ ccns_status create_ctx(const ccns_grid *grid, const ccns_params *params, const d
     set_cg(c, c->st_pred_in, INNER_TOL_MIN, params->pred_maxit, 0, hc.n_uact + hc.n_vact);
     set_cg(c, c->st_pois_in, INNER_TOL_MIN, params->pcg_maxit, 1, hc.n_active);
     if (hipStreamSynchronize(c->stream) != hipSuccess) {
-        destroy_ctx(c);
+        destroy_ctx(c, false);
         return CCNS_EDEVICE;
     }
     *out = c;
@@ -3324,7 +3392,7 @@ ccns_status create_ctx(const ccns_grid *grid, const ccns_params *params, const d
 
 extern "C" {
 
-void ccns_ctx_destroy(ccns_ctx *ctx) { destroy_ctx(ctx); }
+void ccns_ctx_destroy(ccns_ctx *ctx) { destroy_ctx(ctx, true); }
 
 static const int kFieldArr[CCNS_NFIELDS] = {A_UX, A_UY, A_P, A_PHI, A_CONVX, A_CONVY, A_USX, A_USY, A_B};
 
@@ -3450,6 +3518,8 @@ ccns_status ccns_step(ccns_ctx *c, int nsteps, ccns_step_info *info) {
 
 ccns_status ccns_timing(ccns_ctx *c, int enable, double *ms, long *count) {
     if (!c) return CCNS_EINVAL;
+    // timing creates HIP events: not for a context that allocates nothing
+    if (enable == 1 && c->static_dev >= 0) return fail(c, CCNS_ESTATE, "timing needs events: not available on a static context");
     if (ms && count)
         for (int k = 0; k < 4; ++k) { ms[k] = c->t_ms[k]; count[k] = c->t_count[k]; }
     if (enable >= 0) {
