@@ -144,17 +144,6 @@ def naca_4096() -> Case:
                 pcg_tol=1e-10, noise=1e-3, seed=3)
 
 
-def naca_section(nx: int = 64, ny: int = 32, seed: int = 11, steps: int = 10, re: float = 200.0) -> Case:
-    """A coarse NACA0012 case, [0,2]x[0,1], chord 1 at 5 degrees with its
-    leading edge at (0.45, 0.55): at 64x32 some x-face control volumes near
-    the trailing edge hold less than 5% of a cell, so the small-volume floor
-    acts on velocity unknowns as well as on pressure cells.  CFL 0.25."""
-    g = GridSpec(nx, ny, 0.0, 0.0, 2.0, 1.0)
-    body = Body(NACA4, 0.45, 0.55, angle=math.radians(5.0), chord=1.0, t=0.12)
-    return Case(f"naca0012_{nx}x{ny}", g, [body], re=re, steps=steps, cfl=0.25,
-                pcg_tol=1e-10, noise=1e-2, seed=seed)
-
-
 def flat_top_cylinder(n: int = 64, seed: int = 14, steps: int = 10) -> Case:
     """Unit box, circle of radius 0.3 centred on the line x = 0.5 whose top
     lies 0.02 h below a grid line: over the width of a cell the circle is
