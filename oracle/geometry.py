@@ -508,18 +508,17 @@ def capacities(grid: GridSpec, bodies, geo=None, eps_rel=1e-12):
         else:
             geo = LevelSetGeometry(bodies, bbox_margin=max(grid.hx, grid.hy))
     nx, ny, hx, hy = grid.nx, grid.ny, grid.hx, grid.hy
-    x0, y0 = grid.x0, grid.y0
-    x1, y1 = x0 + grid.lx, y0 + grid.ly
-    # cell-edge abscissas x_{i-1/2}, i = 0..nx+2  and cell centres x_i
-    xe = x0 + (np.arange(nx + 3) - 1.0) * hx
-    ye = y0 + (np.arange(ny + 3) - 1.0) * hy
-    xc = x0 + (np.arange(nx + 3) - 0.5) * hx
-    yc = y0 + (np.arange(ny + 3) - 0.5) * hy
-
+    # cell-edge abscissas x_{i-1/2}, i = 0..nx+2, and cell centres x_i (one
+    # ghost cell each side; on a stretched mesh the user's abscissas, Sec. 3.1)
+    xe, ye = grid.edges(0), grid.edges(1)
+    xc, yc = grid.centres(0), grid.centres(1)
+    x0, x1, y0, y1 = xe[1], xe[nx + 1], ye[1], ye[ny + 1]
+    # the velocity grids' boxes reach half a cell across their normal walls:
+    # to the centres of the ghost cells
     epsV = eps_rel * hx * hy
     p = _grid_caps(geo, xe, ye, (x0, x1, y0, y1), True, epsV)
-    u = _grid_caps(geo, xc, ye, (x0 - 0.5 * hx, x1 + 0.5 * hx, y0, y1), False, epsV)
-    v = _grid_caps(geo, xe, yc, (x0, x1, y0 - 0.5 * hy, y1 + 0.5 * hy), False, epsV)
+    u = _grid_caps(geo, xc, ye, (xc[0], xc[nx + 1], y0, y1), False, epsV)
+    v = _grid_caps(geo, xe, yc, (x0, x1, yc[0], yc[ny + 1]), False, epsV)
 
     c = {
         "V": p.V, "X": p.X, "Y": p.Y,

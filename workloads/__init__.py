@@ -21,7 +21,13 @@ import numpy as np
 
 @dataclasses.dataclass(frozen=True)
 class GridSpec:
-    """Uniform Cartesian grid of nx*ny cells covering [x0, x0+lx] x [y0, y0+ly]."""
+    """Cartesian grid of nx*ny cells covering [x0, x0+lx] x [y0, y0+ly].
+
+    Uniform unless xf / yf give the cell-edge abscissas x_{1/2} .. x_{nx+1/2}
+    (nx+1 values, increasing, from x0 to x0+lx) and likewise in y: the
+    user-defined abscissas of a rectilinear mesh.  hx, hy are then the
+    smallest spacings (the scale of the time step, the small-volume floor and
+    the divergence diagnostic)."""
 
     nx: int
     ny: int
@@ -29,14 +35,52 @@ class GridSpec:
     y0: float
     lx: float
     ly: float
+    xf: Optional[tuple] = None
+    yf: Optional[tuple] = None
+
+    @property
+    def uniform(self) -> bool:
+        return self.xf is None and self.yf is None
 
     @property
     def hx(self) -> float:
-        return self.lx / self.nx
+        return self.lx / self.nx if self.xf is None else float(np.min(np.diff(self.xf)))
 
     @property
     def hy(self) -> float:
-        return self.ly / self.ny
+        return self.ly / self.ny if self.yf is None else float(np.min(np.diff(self.yf)))
+
+    def edges(self, axis: int) -> np.ndarray:
+        """Cell edges along x (axis 0) or y (axis 1) with one ghost cell on
+        each side (whose width repeats the neighbouring cell's): n+3 values,
+        entry i = x_{i-1/2}."""
+        n, o, h, f = (self.nx, self.x0, self.lx / self.nx, self.xf) if axis == 0 else \
+            (self.ny, self.y0, self.ly / self.ny, self.yf)
+        if f is None:
+            return o + (np.arange(n + 3) - 1.0) * h
+        f = np.asarray(f, dtype=np.float64)
+        return np.concatenate([[f[0] - (f[1] - f[0])], f, [f[-1] + (f[-1] - f[-2])]])
+
+    def centres(self, axis: int) -> np.ndarray:
+        """Cell centres x_i, i = 0 .. n+2 (ghost cells included; the last one
+        lies beyond the ghost cell, one more mirrored width out): n+3 values."""
+        n, o, h, f = (self.nx, self.x0, self.lx / self.nx, self.xf) if axis == 0 else \
+            (self.ny, self.y0, self.ly / self.ny, self.yf)
+        if f is None:
+            return o + (np.arange(n + 3) - 0.5) * h
+        e = self.edges(axis)
+        c = 0.5 * (e[:-1] + e[1:])
+        return np.concatenate([c, [e[-1] + 0.5 * (e[-1] - e[-2])]])
+
+
+def stretched_edges(n: int, x0: float, length: float, amp: float) -> tuple:
+    """n+1 edges of a smoothly stretched mesh on [x0, x0+length]:
+    x = x0 + length (s + amp sin(2 pi s) / (2 pi)), s = k/n, so the spacing
+    varies between (1 - amp) and (1 + amp) times the uniform one."""
+    s = np.arange(n + 1) / n
+    x = x0 + length * (s + amp * np.sin(2.0 * np.pi * s) / (2.0 * np.pi))
+    x[0], x[-1] = x0, x0 + length
+    return tuple(float(v) for v in x)
 
 
 # Body kinds (the same integer codes are used by the C interface).
@@ -279,10 +323,8 @@ def stream_noise(case: Case) -> np.ndarray:
     rng = np.random.default_rng(case.seed)
     psi = rng.uniform(-1.0, 1.0, size=(g.ny + 2, g.nx + 2))
     h = min(g.hx, g.hy)
-    i = np.arange(g.nx + 2)
-    j = np.arange(g.ny + 2)
-    xs = g.x0 + i * g.hx
-    ys = g.y0 + j * g.hy
+    xs = g.edges(0)[1:]      # node (i+1/2, j+1/2) at [j, i]
+    ys = g.edges(1)[1:]
     X, Y = np.meshgrid(xs, ys)
     wall = (X < g.x0 + 3 * h) | (X > g.x0 + g.lx - 3 * h) | (Y < g.y0 + 3 * h) | (Y > g.y0 + g.ly - 3 * h)
     body = _near_body_mask(g, case.bodies, X, Y, 3 * h)
@@ -291,15 +333,22 @@ def stream_noise(case: Case) -> np.ndarray:
 
 
 def perturbation(case: Case):
-    """Face velocity perturbation (ux', uy') built as the uniform-grid curl of the
-    stream noise: ux'[j,i] = (psi[j,i]-psi[j-1,i])/hy at x-face (i+1/2, j),
-    uy'[j,i] = -(psi[j,i]-psi[j,i-1])/hx at y-face (i, j+1/2).  Arrays (ny+2, nx+2)."""
+    """Face velocity perturbation (ux', uy') built as the grid curl of the
+    stream noise: ux'[j,i] = (psi[j,i]-psi[j-1,i])/dy_j at x-face (i+1/2, j),
+    uy'[j,i] = -(psi[j,i]-psi[j,i-1])/dx_i at y-face (i, j+1/2), with the cell
+    sizes dx_i, dy_j (hx, hy on a uniform grid).  Arrays (ny+2, nx+2)."""
     g = case.grid
     psi = stream_noise(case)
     ux = np.zeros_like(psi)
     uy = np.zeros_like(psi)
-    ux[1:, :] = (psi[1:, :] - psi[:-1, :]) / g.hy
-    uy[:, 1:] = -(psi[:, 1:] - psi[:, :-1]) / g.hx
+    if g.uniform:
+        ux[1:, :] = (psi[1:, :] - psi[:-1, :]) / g.hy
+        uy[:, 1:] = -(psi[:, 1:] - psi[:, :-1]) / g.hx
+    else:
+        dy = np.diff(g.edges(1))[: g.ny + 2]     # cell heights, rows 0 .. ny+1
+        dx = np.diff(g.edges(0))[: g.nx + 2]
+        ux[1:, :] = (psi[1:, :] - psi[:-1, :]) / dy[1:, None]
+        uy[:, 1:] = -(psi[:, 1:] - psi[:, :-1]) / dx[None, 1:]
     return ux, uy
 
 
@@ -309,11 +358,9 @@ def dirichlet(case: Case):
     no-slip (0) on faces whose staggered control volume lies within 2h of a body."""
     g = case.grid
     h = min(g.hx, g.hy)
-    i = np.arange(g.nx + 2)
-    j = np.arange(g.ny + 2)
     # centres of the x-staggered control volumes: (x_{i+1/2}, y_j)
-    xu = g.x0 + i * g.hx
-    yu = g.y0 + (j - 0.5) * g.hy
+    xu = g.edges(0)[1:]
+    yu = g.centres(1)[: g.ny + 2]
     XU, YU = np.meshgrid(xu, yu)
     dx = np.full((g.ny + 2, g.nx + 2), case.u_inf)
     dx[_near_body_mask(g, case.bodies, XU, YU, 2 * h + 0.5 * h)] = 0.0
