@@ -45,11 +45,24 @@ typedef enum {
     CCNS_ESTATE = -6       /* call not valid in the context's current state */
 } ccns_status;
 
-/* Uniform Cartesian grid: nx*ny cells of size hx*hy, lower-left corner
- * (x0, y0).  The cell edges are the abscissas of Sec. 3.1. */
+/* Cartesian grid of nx*ny cells, lower-left corner (x0, y0).  The cell
+ * edges are the abscissas of Sec. 3.1.
+ *
+ * xf = yf = NULL: a uniform grid of cells hx*hy.
+ * xf != NULL: the nx+1 cell-edge abscissas x_{1/2} .. x_{nx+1/2}, finite and
+ *   strictly increasing, with xf[0] = x0 (likewise yf, ny+1 ordinates): a
+ *   stretched rectilinear mesh.  The ghost cells beyond the walls repeat the
+ *   width of their neighbours.  The metric enters the method through the
+ *   capacities alone, so hx and hy are then reference spacings (the smallest
+ *   ones, say): they scale the small-capacity thresholds, the mass floor
+ *   theta hx hy and the divergence diagnostic.
+ * Only ccns_capacities reads xf and yf, during the call (the caller keeps
+ * ownership); the other entry points take the grid for its sizes and
+ * reference spacings and the capacities for its geometry. */
 typedef struct {
     int nx, ny;
     double x0, y0, hx, hy;
+    const double *xf, *yf;
 } ccns_grid;
 
 /* Synthetic bodies.  Fluid is where the body's level set is positive.
@@ -92,7 +105,10 @@ size_t ccns_caps_count(const ccns_grid *grid);
  * tangential walls are dry; pressure-grid wall faces are wetted.
  * caps_host: caller-owned host buffer of ccns_caps_count() doubles.
  * Capacities below 1e-12 h (lengths) or 1e-12 hx hy (volumes) are 0.
- * Errors: CCNS_EINVAL for a bad grid or body. */
+ * On a stretched grid (xf or yf set) every control volume, face and strip
+ * takes the extents of its own edges and centroids.
+ * Errors: CCNS_EINVAL for a bad grid (abscissas not finite and strictly
+ * increasing, xf[0] != x0, yf[0] != y0) or body. */
 ccns_status ccns_capacities(const ccns_grid *grid, const ccns_body *bodies, int nbody,
                             ccns_levelset_fn fn, void *user, double *caps_host);
 
@@ -109,8 +125,9 @@ ccns_status ccns_capacities(const ccns_grid *grid, const ccns_body *bodies, int 
  *  dev_scratch  device buffer of ccns_capacities_scratch_bytes() bytes for
  *               the control volumes' centroids (caller-owned)
  *  hip_stream   the work is enqueued on it; the call does not wait
- * Errors: CCNS_EINVAL (bad grid, a body that is not a circle or an ellipse,
- * overlapping bodies, more than 16 bodies), CCNS_ENOMEM (scratch too small),
+ * Errors: CCNS_EINVAL (bad grid, a stretched grid, a body that is not a
+ * circle or an ellipse, overlapping bodies, more than 16 bodies),
+ * CCNS_ENOMEM (scratch too small),
  * CCNS_EDEVICE. */
 size_t ccns_capacities_scratch_bytes(const ccns_grid *grid);
 ccns_status ccns_capacities_device(const ccns_grid *grid, const ccns_body *bodies, int nbody,

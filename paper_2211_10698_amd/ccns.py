@@ -29,7 +29,8 @@ _OP_ARITY = {OP_CONT: (2, 1), OP_PRES: (1, 2), OP_VISC: (2, 2), OP_CONV: (2, 2),
 
 class Grid(C.Structure):
     _fields_ = [("nx", C.c_int), ("ny", C.c_int), ("x0", C.c_double), ("y0", C.c_double),
-                ("hx", C.c_double), ("hy", C.c_double)]
+                ("hx", C.c_double), ("hy", C.c_double),
+                ("xf", C.POINTER(C.c_double)), ("yf", C.POINTER(C.c_double))]
 
 
 class BodyC(C.Structure):
@@ -143,7 +144,15 @@ class CcnsError(RuntimeError):
 
 
 def make_grid(spec) -> Grid:
-    return Grid(spec.nx, spec.ny, spec.x0, spec.y0, spec.hx, spec.hy)
+    """The C grid of a GridSpec; a stretched spec's abscissas are copied into
+    ctypes arrays that the structure keeps alive."""
+    g = Grid(spec.nx, spec.ny, spec.x0, spec.y0, spec.hx, spec.hy)
+    xf, yf = getattr(spec, "xf", None), getattr(spec, "yf", None)
+    if xf is not None:
+        g.xf = (C.c_double * len(xf))(*xf)
+    if yf is not None:
+        g.yf = (C.c_double * len(yf))(*yf)
+    return g
 
 
 def make_bodies(bodies):

@@ -447,11 +447,52 @@ struct GridOut {
 };
 
 // A rectangle or segment entirely in the fluid has the exact measures of its
-// extent.  Extents differ from the mesh spacing only by the rounding of the
-// node coordinates; one within 1e-9 relative of hx (hy) is taken as hx (hy),
-// so that every full cell, face and strip away from the interface carries
-// the same capacities bit for bit (V = hx hy, A = B = h, W = hx hy).
+// extent.  On a uniform axis extents differ from the mesh spacing only by the
+// rounding of the node coordinates; one within 1e-9 relative of hx (hy) is
+// taken as hx (hy), so that every full cell, face and strip away from the
+// interface carries the same capacities bit for bit (V = hx hy, A = B = h,
+// W = hx hy).  A stretched axis passes h = 0: its extents are kept as they are.
 inline double snap(double len, double h) { return std::fabs(len - h) <= 1e-9 * h ? h : len; }
+
+// One axis of the three grids: the cell edges e[i] = x_{i-1/2} and centres
+// c[i] = x_i, i = 0 .. n+2 (one ghost cell each side), the pressure grid's
+// box [lo, hi] and the velocity grid's [clo, chi], which reaches half a cell
+// across the walls (to the ghost cells' centres), and the snapping spacing.
+struct Axis {
+    std::vector<double> e, c;
+    double lo, hi, clo, chi, snap_h, hmax;
+};
+
+Axis make_axis(int n, double o, double h, const double *f) {
+    Axis a;
+    a.e.resize(n + 3);
+    a.c.resize(n + 3);
+    if (!f) {
+        for (int i = 0; i < n + 3; ++i) { a.e[i] = o + (i - 1.0) * h; a.c[i] = o + (i - 0.5) * h; }
+        a.lo = o; a.hi = o + n * h; a.clo = a.lo - 0.5 * h; a.chi = a.hi + 0.5 * h;
+        a.snap_h = h; a.hmax = h;
+        return a;
+    }
+    // user abscissas (Sec. 3.1); the ghost cells repeat the wall cells' widths
+    for (int i = 0; i <= n; ++i) a.e[i + 1] = f[i];
+    a.e[0] = f[0] - (f[1] - f[0]);
+    a.e[n + 2] = f[n] + (f[n] - f[n - 1]);
+    for (int i = 0; i < n + 2; ++i) a.c[i] = 0.5 * (a.e[i] + a.e[i + 1]);
+    a.c[n + 2] = a.e[n + 2] + 0.5 * (a.e[n + 2] - a.e[n + 1]);
+    a.lo = a.e[1]; a.hi = a.e[n + 1]; a.clo = a.c[0]; a.chi = a.c[n + 1];
+    a.snap_h = 0.0;
+    a.hmax = 0.0;
+    for (int i = 0; i < n; ++i) a.hmax = std::max(a.hmax, f[i + 1] - f[i]);
+    return a;
+}
+
+bool valid_abscissas(const double *f, int n, double o) {
+    if (!f) return true;
+    if (f[0] != o) return false;
+    for (int i = 0; i <= n; ++i)
+        if (!std::isfinite(f[i]) || (i > 0 && !(f[i] > f[i - 1]))) return false;
+    return true;
+}
 
 GridOut grid_caps(const Fluid &fl, const Integrator &in, const std::vector<double> &ex,
                   const std::vector<double> &ey, double bx0, double bx1, double by0, double by1,
@@ -532,7 +573,8 @@ extern "C" size_t ccns_caps_count(const ccns_grid *grid) {
 extern "C" ccns_status ccns_capacities(const ccns_grid *grid, const ccns_body *bodies, int nbody,
                                        ccns_levelset_fn fn, void *user, double *caps) {
     if (!grid || !caps || grid->nx < 2 || grid->ny < 2 || !(grid->hx > 0) || !(grid->hy > 0) ||
-        nbody < 0 || (nbody > 0 && !bodies))
+        nbody < 0 || (nbody > 0 && !bodies) || !valid_abscissas(grid->xf, grid->nx, grid->x0) ||
+        !valid_abscissas(grid->yf, grid->ny, grid->y0))
         return CCNS_EINVAL;
     for (int k = 0; k < nbody; ++k) {
         const ccns_body &b = bodies[k];
@@ -542,18 +584,16 @@ extern "C" ccns_status ccns_capacities(const ccns_grid *grid, const ccns_body *b
         if (b.kind == CCNS_NACA4 && !(b.chord > 0 && b.t > 0)) return CCNS_EINVAL;
     }
     const int nx = grid->nx, ny = grid->ny;
-    const double hx = grid->hx, hy = grid->hy, x0 = grid->x0, y0 = grid->y0;
-    const double x1 = x0 + nx * hx, y1 = y0 + ny * hy;
+    const double hx = grid->hx, hy = grid->hy;
     Fluid fl{bodies, nbody, fn, user};
     fl.lip = fl.lipschitz();
     Integrator in(fl);
-    std::vector<double> xe(nx + 3), ye(ny + 3), xc(nx + 3), yc(ny + 3);
-    for (int i = 0; i < nx + 3; ++i) { xe[i] = x0 + (i - 1.0) * hx; xc[i] = x0 + (i - 0.5) * hx; }
-    for (int j = 0; j < ny + 3; ++j) { ye[j] = y0 + (j - 1.0) * hy; yc[j] = y0 + (j - 0.5) * hy; }
-    const double epsV = 1e-12 * hx * hy, margin = 2.0 * std::max(hx, hy);
-    GridOut p = grid_caps(fl, in, xe, ye, x0, x1, y0, y1, true, epsV, margin, hx, hy);
-    GridOut u = grid_caps(fl, in, xc, ye, x0 - 0.5 * hx, x1 + 0.5 * hx, y0, y1, false, epsV, margin, hx, hy);
-    GridOut v = grid_caps(fl, in, xe, yc, x0, x1, y0 - 0.5 * hy, y1 + 0.5 * hy, false, epsV, margin, hx, hy);
+    const Axis ax = make_axis(nx, grid->x0, hx, grid->xf), ay = make_axis(ny, grid->y0, hy, grid->yf);
+    const double epsV = 1e-12 * hx * hy, margin = 2.0 * std::max(ax.hmax, ay.hmax);
+    const double sx = ax.snap_h, sy = ay.snap_h;
+    GridOut p = grid_caps(fl, in, ax.e, ay.e, ax.lo, ax.hi, ay.lo, ay.hi, true, epsV, margin, sx, sy);
+    GridOut u = grid_caps(fl, in, ax.c, ay.e, ax.clo, ax.chi, ay.lo, ay.hi, false, epsV, margin, sx, sy);
+    GridOut v = grid_caps(fl, in, ax.e, ay.c, ax.lo, ax.hi, ay.clo, ay.chi, false, epsV, margin, sx, sy);
     const size_t W = nx + 2, H = ny + 2, n = W * H;
     std::memset(caps, 0, sizeof(double) * n * CCNS_NCAPS);
     auto at = [&](int cap) { return caps + (size_t)cap * n; };

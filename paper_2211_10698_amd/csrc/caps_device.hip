@@ -342,8 +342,9 @@ struct CapsPlan {
 
 ccns_status plan_caps(const ccns_grid *grid, const ccns_body *bodies, int nbody, double *cap, double *scr,
                       CapsPlan &pl) {
-    if (!grid || grid->nx < 2 || grid->ny < 2 || !(grid->hx > 0) || !(grid->hy > 0) || nbody < 0 ||
-        nbody > MAXB || (nbody > 0 && !bodies))
+    // the kernels place the edges at x0 + i hx: uniform grids only
+    if (!grid || grid->nx < 2 || grid->ny < 2 || !(grid->hx > 0) || !(grid->hy > 0) || grid->xf || grid->yf ||
+        nbody < 0 || nbody > MAXB || (nbody > 0 && !bodies))
         return CCNS_EINVAL;
     Conics &cs = pl.cs;
     cs.n = nbody;

@@ -412,6 +412,27 @@ __global__ __launch_bounds__(NT) void k_add_correction(size_t ntot, double *__re
 // correction as a rediscretisation would).
 constexpr double MG_CGC = 1.0;
 
+// Weights of the two smoothing sweeps x' = x + w D^-1 (b - A x) on the way
+// down (first w1, then w2) and on the way up (the same two).  Both sweeps are
+// polynomials in D^-1 A, so they commute and the cycle stays symmetric
+// whatever their order.  With w1 = w2 this is weighted Jacobi; two different
+// weights are the degree-2 Chebyshev smoother on an interval [lo, 2] of the
+// spectrum of D^-1 A (which lies in [0, 2] for these diagonally dominant
+// operators): w = 1 / ((2 + lo) / 2 +- (2 - lo) / 2 cos(pi / 4)).  The
+// default is weighted Jacobi at 0.8.  Chebyshev on [2/3, 2] takes 15.8
+// Poisson iterations per FP64 step on the 4096x2048 NACA 0012 case against 17
+// (the same 10 on the 2048x1024 channel), but where a pressure cell holds
+// 2.5e-12 of a cell's volume and the mass matrix is not floored, its solve
+// stops on r.z <= 0 at a relative residual of 1.3e-12, above the 1e-13 that
+// weighted Jacobi reaches there.
+#ifndef CCNS_MG_W1
+#define CCNS_MG_W1 0.8
+#endif
+#ifndef CCNS_MG_W2
+#define CCNS_MG_W2 0.8
+#endif
+constexpr double MG_W1 = CCNS_MG_W1, MG_W2 = CCNS_MG_W2;
+
 // Fused cycle kernels.  Tiles cover the real cells, starting at cell (1, 1)
 // so that every 2x2 group of children that forms a coarse cell lies inside
 // one tile (64 = 32 coarse columns, 16 = 8 coarse rows).  One tile per
@@ -528,7 +549,7 @@ template <class T>
 __global__ __launch_bounds__(NT) void k_mg_down_staged(int nx, int ny, int P, int gx, PoisCoefT<T> c,
                                                 const T *__restrict__ b, T *__restrict__ x2out,
                                                 int Pc, int nxc, int nyc, const T *__restrict__ dinvc,
-                                                T *__restrict__ bc, T omega, const int *done) {
+                                                T *__restrict__ bc, const int *done) {
     if (*done) return;
     __shared__ T s1[MHt][MW];            // first sweep on the 2-ring region
     __shared__ T s2[MTY + 2][TX + 2];    // second sweep on the 1-ring region
@@ -554,14 +575,14 @@ __global__ __launch_bounds__(NT) void k_mg_down_staged(int nx, int ny, int P, in
                 const int ly = e / MW, lx = e - ly * MW;
                 const int j = t.r0 - MH + ly, i = t.c0 - MH + lx;
                 const bool in = (j >= 0) && (j <= ny + 1) && (i >= 0) && (i <= nx + 1);
-                s1[ly][lx] = (in && dv[q] > (T)0) ? omega * dv[q] * bv[q] : (T)0;
+                s1[ly][lx] = (in && dv[q] > (T)0) ? (T)MG_W1 * dv[q] * bv[q] : (T)0;
             }
         }
     }
     MgRingOps<T> ro;
     mg_load_ring_ops<T>(ro, c, b, nx, ny, P, t);
     __syncthreads();
-    mg_ring_sweep<T>(ro, s1, s2, nx, ny, t, omega);
+    mg_ring_sweep<T>(ro, s1, s2, nx, ny, t, (T)MG_W2);
     MgCellOps<T, MTY / 4> o;
     mg_load_tile_ops<T, MTY / 4>(o, c, b, nx, ny, P, t);
     // one coarse cell per thread for the restriction: 32 x 8 coarse cells per tile
@@ -599,7 +620,7 @@ __global__ __launch_bounds__(NT) void k_mg_down_staged(int nx, int ny, int P, in
 template <class T, bool STATS>
 __global__ __launch_bounds__(NT) void k_mg_up_staged(int nx, int ny, int P, int gx, PoisCoefT<T> c, const T *__restrict__ b,
                                               const T *__restrict__ x2, const T *__restrict__ xc, int Pc,
-                                              T *__restrict__ z, T omega, double *pout, int nblk, const int *done) {
+                                              T *__restrict__ z, double *pout, int nblk, const int *done) {
     if (*done) return;
     __shared__ T s1[MHt][MW];
     __shared__ T s2[MTY + 2][TX + 2];
@@ -634,7 +655,7 @@ __global__ __launch_bounds__(NT) void k_mg_up_staged(int nx, int ny, int P, int 
         MgRingOps<T> ro;
         mg_load_ring_ops<T>(ro, c, b, nx, ny, P, t);
         __syncthreads();
-        mg_ring_sweep<T>(ro, s1, s2, nx, ny, t, omega);
+        mg_ring_sweep<T>(ro, s1, s2, nx, ny, t, (T)MG_W1);
         mg_load_tile_ops<T, MTY / 4>(o, c, b, nx, ny, P, t);
     } else {
         __syncthreads();
@@ -651,7 +672,7 @@ __global__ __launch_bounds__(NT) void k_mg_up_staged(int nx, int ny, int P, int 
             const T xv = s2[y][x];
             const T Ax = (o.e[m] + o.w[m] + o.n[m] + o.s[m]) * xv - o.e[m] * s2[y][x + 1] -
                          o.w[m] * s2[y][x - 1] - o.n[m] * s2[y + 1][x] - o.s[m] * s2[y - 1][x];
-            const T zv = (in && o.d[m] > (T)0) ? xv + omega * o.d[m] * (o.b[m] - Ax) : (T)0;
+            const T zv = (in && o.d[m] > (T)0) ? xv + (T)MG_W2 * o.d[m] * (o.b[m] - Ax) : (T)0;
             if (in) z[(size_t)j * P + i] = zv;
             if (STATS && in) {
                 const double bd = o.b[m], zd = zv;
@@ -677,7 +698,7 @@ template <class T, int TY = MTY>
 __global__ __launch_bounds__(NT) void k_mg_down(int nx, int ny, int P, int gx, PoisCoefT<T> c,
                                                 const T *__restrict__ b, T *__restrict__ x2out,
                                                 int Pc, int nxc, int nyc, const T *__restrict__ dinvc,
-                                                T *__restrict__ bc, T omega, const int *done) {
+                                                T *__restrict__ bc, const int *done) {
     if (*done) return;
     static_assert(TY % 4 == 0 && TY <= MTY, "tile rows: a multiple of the 4 row groups, at most MTY");
     __shared__ T s2[TY + 2][TX + 2];    // x after two sweeps, on the tile and a one-cell ring
@@ -703,11 +724,12 @@ __global__ __launch_bounds__(NT) void k_mg_down(int nx, int ny, int P, int gx, P
         const T de = c.dinv[k + 1], dw = c.dinv[k - 1], dn = c.dinv[k + P], ds = c.dinv[k - P];
         const T be = b[k + 1], bw = b[k - 1], bn = b[k + P], bs = b[k - P];
         const T ce = c.cx[k], cw = c.cx[k - 1], cn = c.cy[k], cs = c.cy[k - P];
-        const T xv = dv > (T)0 ? omega * dv * bv : (T)0;
-        const T xe = de > (T)0 ? omega * de * be : (T)0, xw = dw > (T)0 ? omega * dw * bw : (T)0;
-        const T xn = dn > (T)0 ? omega * dn * bn : (T)0, xs = ds > (T)0 ? omega * ds * bs : (T)0;
+        const T w1 = (T)MG_W1;
+        const T xv = dv > (T)0 ? w1 * dv * bv : (T)0;
+        const T xe = de > (T)0 ? w1 * de * be : (T)0, xw = dw > (T)0 ? w1 * dw * bw : (T)0;
+        const T xn = dn > (T)0 ? w1 * dn * bn : (T)0, xs = ds > (T)0 ? w1 * ds * bs : (T)0;
         const T Ax = (ce + cw + cn + cs) * xv - ce * xe - cw * xw - cn * xn - cs * xs;
-        s2[ly][lx] = (in && dv > (T)0) ? xv + omega * dv * (bv - Ax) : (T)0;
+        s2[ly][lx] = (in && dv > (T)0) ? xv + (T)MG_W2 * dv * (bv - Ax) : (T)0;
     }
     __syncthreads();
     {
@@ -741,7 +763,7 @@ __global__ __launch_bounds__(NT) void k_mg_down(int nx, int ny, int P, int gx, P
 template <class T, bool STATS, int TY = MTY>
 __global__ __launch_bounds__(NT) void k_mg_up(int nx, int ny, int P, int gx, PoisCoefT<T> c, const T *__restrict__ b,
                                               const T *__restrict__ x2, const T *__restrict__ xc, int Pc,
-                                              T *__restrict__ z, T omega, double *pout, int nblk, const int *done) {
+                                              T *__restrict__ z, double *pout, int nblk, const int *done) {
     if (*done) return;
     static_assert(TY % 4 == 0 && TY <= MTY, "tile rows: a multiple of the 4 row groups, at most MTY");
     __shared__ T s2[TY + 2][TX + 2];    // x after the first sweep, on the tile and a one-cell ring
@@ -772,7 +794,7 @@ __global__ __launch_bounds__(NT) void k_mg_up(int nx, int ny, int P, int gx, Poi
             const T xe = start(jj, ii + 1, k + 1), xw = start(jj, ii - 1, k - 1);
             const T xn = start(jj + 1, ii, k + P), xs = start(jj - 1, ii, k - P);
             const T Ax = (ce + cw + cn + cs) * xv - ce * xe - cw * xw - cn * xn - cs * xs;
-            s2[ly][lx] = (in && dv > (T)0) ? xv + omega * dv * (bv - Ax) : (T)0;
+            s2[ly][lx] = (in && dv > (T)0) ? xv + (T)MG_W1 * dv * (bv - Ax) : (T)0;
         }
     }
     __syncthreads();
@@ -787,7 +809,7 @@ __global__ __launch_bounds__(NT) void k_mg_up(int nx, int ny, int P, int gx, Poi
             const T xv = s2[y][x];
             const T Ax = (o.e[m] + o.w[m] + o.n[m] + o.s[m]) * xv - o.e[m] * s2[y][x + 1] -
                          o.w[m] * s2[y][x - 1] - o.n[m] * s2[y + 1][x] - o.s[m] * s2[y - 1][x];
-            const T zv = (in && o.d[m] > (T)0) ? xv + omega * o.d[m] * (o.b[m] - Ax) : (T)0;
+            const T zv = (in && o.d[m] > (T)0) ? xv + (T)MG_W2 * o.d[m] * (o.b[m] - Ax) : (T)0;
             if (in) z[(size_t)j * P + i] = zv;
             if (STATS && in) {
                 const double bd = o.b[m], zd = zv;
@@ -824,7 +846,6 @@ struct TailDesc {
     int ncoarse;         // unknowns of the coarsest grid
     const int *idx;
     const double *pinv;
-    T omega;
     const int *done;     // the solve's done flag: nothing to do once set
     int lofs[MAX_TAIL];  // k_mg_tail_lds: offset of each level's arrays in LDS (elements)
     T *out;              // k_mg_tail_lds: where the tail's first level's result goes
@@ -839,7 +860,7 @@ __device__ inline T tail_Ax(const TailLevel<T> &L, const T *v, size_t k) {
 template <class T>
 __global__ __launch_bounds__(TT) void k_mg_tail(TailDesc<T> d) {
     if (*d.done) return;
-    const T om = d.omega;
+    const T w1 = (T)MG_W1, w2 = (T)MG_W2;
     // down: two sweeps from zero, the residual restricted to the next level
     for (int l = 0; l + 1 < d.nlev; ++l) {
         const TailLevel<T> &L = d.lv[l];
@@ -848,14 +869,14 @@ __global__ __launch_bounds__(TT) void k_mg_tail(TailDesc<T> d) {
         for (int e = threadIdx.x; e < ncell; e += TT) {
             const size_t k = (size_t)(e / L.nx + 1) * L.P + (e % L.nx + 1);
             const T dv = L.dinv[k], bv = L.b[k];
-            L.xt[k] = dv > (T)0 ? om * dv * bv : (T)0;
+            L.xt[k] = dv > (T)0 ? w1 * dv * bv : (T)0;
         }
         __syncthreads();
         for (int e = threadIdx.x; e < ncell; e += TT) {
             const size_t k = (size_t)(e / L.nx + 1) * L.P + (e % L.nx + 1);
             const T dv = L.dinv[k], bv = L.b[k];
             const T xv = L.xt[k];
-            L.x[k] = dv > (T)0 ? xv + om * dv * (bv - tail_Ax(L, L.xt, k)) : (T)0;
+            L.x[k] = dv > (T)0 ? xv + w2 * dv * (bv - tail_Ax(L, L.xt, k)) : (T)0;
         }
         __syncthreads();
         const int nc = C.nx * C.ny;
@@ -912,14 +933,14 @@ __global__ __launch_bounds__(TT) void k_mg_tail(TailDesc<T> d) {
             const size_t k = (size_t)(e / L.nx + 1) * L.P + (e % L.nx + 1);
             const T dv = L.dinv[k], bv = L.b[k];
             const T xv = L.xt[k];
-            L.x[k] = dv > (T)0 ? xv + om * dv * (bv - tail_Ax(L, L.xt, k)) : (T)0;
+            L.x[k] = dv > (T)0 ? xv + w1 * dv * (bv - tail_Ax(L, L.xt, k)) : (T)0;
         }
         __syncthreads();
         for (int e = threadIdx.x; e < ncell; e += TT) {
             const size_t k = (size_t)(e / L.nx + 1) * L.P + (e % L.nx + 1);
             const T dv = L.dinv[k], bv = L.b[k];
             const T xv = L.x[k];
-            L.xt[k] = dv > (T)0 ? xv + om * dv * (bv - tail_Ax(L, L.x, k)) : (T)0;
+            L.xt[k] = dv > (T)0 ? xv + w2 * dv * (bv - tail_Ax(L, L.x, k)) : (T)0;
         }
         __syncthreads();
     }
@@ -943,7 +964,7 @@ __global__ __launch_bounds__(TT) void k_mg_tail_lds(TailDesc<T> d) {
     if (*d.done) return;
     extern __shared__ double tail_lds[];
     T *const sm = reinterpret_cast<T *>(tail_lds);
-    const T om = d.omega;
+    const T w1 = (T)MG_W1, w2 = (T)MG_W2;
     // level l's six arrays start at sm + d.lofs[l], each (nx+2)(ny+2) long
     auto arr = [&](int l, int a) { return sm + d.lofs[l] + a * (d.lv[l].nx + 2) * (d.lv[l].ny + 2); };
     for (int l = 0; l < d.nlev; ++l) {
@@ -989,13 +1010,13 @@ __global__ __launch_bounds__(TT) void k_mg_tail_lds(TailDesc<T> d) {
         const T *cx = arr(l, 0), *cy = arr(l, 1), *dv = arr(l, 2), *b = arr(l, 3);
         T *x = arr(l, 4);
         const int ncell = L.nx * L.ny;
-        auto x1 = [&](int k) { return dv[k] > (T)0 ? om * dv[k] * b[k] : (T)0; };
+        auto x1 = [&](int k) { return dv[k] > (T)0 ? w1 * dv[k] * b[k] : (T)0; };
         for (int e = threadIdx.x; e < ncell; e += TT) {
             const int k = (e / L.nx + 1) * W + (e % L.nx + 1);
             const T ce = cx[k], cw = cx[k - 1], cn = cy[k], cs = cy[k - W];
             const T xv = x1(k);
             const T Ax = (ce + cw + cn + cs) * xv - ce * x1(k + 1) - cw * x1(k - 1) - cn * x1(k + W) - cs * x1(k - W);
-            x[k] = dv[k] > (T)0 ? xv + om * dv[k] * (b[k] - Ax) : (T)0;
+            x[k] = dv[k] > (T)0 ? xv + w2 * dv[k] * (b[k] - Ax) : (T)0;
         }
         __syncthreads();
         const TailLevel<T> &C = d.lv[l + 1];
@@ -1093,12 +1114,12 @@ __global__ __launch_bounds__(TT) void k_mg_tail_lds(TailDesc<T> d) {
             const T xv = start(j, i);
             const T Ax = (ce + cw + cn + cs) * xv - ce * start(j, i + 1) - cw * start(j, i - 1) -
                          cn * start(j + 1, i) - cs * start(j - 1, i);
-            xt[k] = dv[k] > (T)0 ? xv + om * dv[k] * (b[k] - Ax) : (T)0;
+            xt[k] = dv[k] > (T)0 ? xv + w1 * dv[k] * (b[k] - Ax) : (T)0;
         }
         __syncthreads();
         for (int e = threadIdx.x; e < ncell; e += TT) {
             const int k = (e / L.nx + 1) * W + (e % L.nx + 1);
-            x[k] = dv[k] > (T)0 ? xt[k] + om * dv[k] * (b[k] - lds_Ax(cx, cy, xt, k, W)) : (T)0;
+            x[k] = dv[k] > (T)0 ? xt[k] + w2 * dv[k] * (b[k] - lds_Ax(cx, cy, xt, k, W)) : (T)0;
         }
         __syncthreads();
     }
@@ -2509,7 +2530,6 @@ ccns_status pressure_solve_dev(ccns_ctx *c, int nin, ccns_solve_info *info) {
 }
 
 constexpr int MG_NU = 2;          // pre- and post-smoothing sweeps
-constexpr double MG_OMEGA = 0.8;  // weighted-Jacobi damping
 
 // Builds the coarse levels on the host from the fine Poisson weights and
 // uploads them (and their float copies in precision 1); the coarsest grid
@@ -2734,7 +2754,6 @@ T *vcycle(ccns_ctx *c, std::vector<ccns_ctx::LevelT<T>> &mg, size_t l, const T *
         d.ncoarse = c->ncoarse_act;
         d.idx = c->pidx;
         d.pinv = c->pinv;
-        d.omega = (T)MG_OMEGA;
         d.done = done;
         d.out = d.nlev >= 2 ? L.xt : L.x;
         size_t elems = 0;
@@ -2757,30 +2776,29 @@ T *vcycle(ccns_ctx *c, std::vector<ccns_ctx::LevelT<T>> &mg, size_t l, const T *
     const int gy = (L.L.ny + ty - 1) / ty;
     const int nb = ((gx * gy + 7) / 8) * 8;
     ccns_ctx::LevelT<T> &C = mg[l + 1];
-    const T om = (T)MG_OMEGA;
     // levels with tall tiles in the staged forms (measured: faster on the way
     // down in FP64 and on the way up in both precisions; the FP32 way down is
     // faster in the latency form at every level)
     if (!small && sizeof(T) == 8)
         k_mg_down_staged<T><<<nb, NT, 0, s>>>(L.L.nx, L.L.ny, L.L.pitch, gx, pc, b, L.x, C.L.pitch, C.L.nx, C.L.ny,
-                                              C.dinv, C.b, om, done);
+                                              C.dinv, C.b, done);
     else if (small)
         k_mg_down<T, MTY_SMALL><<<nb, NT, 0, s>>>(L.L.nx, L.L.ny, L.L.pitch, gx, pc, b, L.x, C.L.pitch, C.L.nx,
-                                                  C.L.ny, C.dinv, C.b, om, done);
+                                                  C.L.ny, C.dinv, C.b, done);
     else
         k_mg_down<T><<<nb, NT, 0, s>>>(L.L.nx, L.L.ny, L.L.pitch, gx, pc, b, L.x, C.L.pitch, C.L.nx, C.L.ny,
-                                       C.dinv, C.b, om, done);
+                                       C.dinv, C.b, done);
     const T *xc = vcycle<T>(c, mg, l + 1, C.b, done);
     if (l == 0) {
         k_mg_up_staged<T, true><<<nb, NT, 0, s>>>(L.L.nx, L.L.ny, L.L.pitch, gx, pc, b, L.x, xc, C.L.pitch, L.xt,
-                                                  om, c->part[PB_UPD], nb, done);
+                                                  c->part[PB_UPD], nb, done);
         k_reduce_partials<4><<<1, NT, 0, s>>>(c->part[PB_UPD], nb, c->part[PB_MG]);
     } else if (!small) {
         k_mg_up_staged<T, false><<<nb, NT, 0, s>>>(L.L.nx, L.L.ny, L.L.pitch, gx, pc, b, L.x, xc, C.L.pitch, L.xt,
-                                                   om, nullptr, nb, done);
+                                                   nullptr, nb, done);
     } else {
         k_mg_up<T, false, MTY_SMALL><<<nb, NT, 0, s>>>(L.L.nx, L.L.ny, L.L.pitch, gx, pc, b, L.x, xc, C.L.pitch,
-                                                       L.xt, om, nullptr, nb, done);
+                                                       L.xt, nullptr, nb, done);
     }
     return L.xt;
 }
@@ -3251,6 +3269,7 @@ ccns_status create_ctx(const ccns_grid *grid, const ccns_params *params, const d
     ccns_ctx *c = new (std::nothrow) ccns_ctx();
     if (!c) return CCNS_ENOMEM;
     c->g = *grid;
+    c->g.xf = c->g.yf = nullptr;   // the geometry is in the capacities; the abscissas are the caller's
     c->prm = *params;
     c->static_dev = static_dev;
     c->w = plan(grid->nx, grid->ny, params->precision);

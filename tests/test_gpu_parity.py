@@ -1,6 +1,7 @@
 """Parity of the HIP path (through the C interface) with the oracle, on the
 same capacities and seeded inputs: operator applies element by element,
-the pressure solve, the phases of one step, and multi-step trajectories."""
+the pressure solve, the phases of one step, and multi-step trajectories, on
+uniform and stretched meshes."""
 
 import numpy as np
 import pytest
@@ -28,6 +29,9 @@ CASES = {
     "channel_130x73": lambda: W.scaled_cylinder(130, 73, 2.6, 1.46, seed=5),
     # velocity unknowns and pressure cells with less than 5% of a cell's volume
     "flat_top_64": lambda: W.flat_top_cylinder(64),
+    # a stretched rectilinear mesh (cells from 0.5 to 1.5 times the uniform
+    # size): the metric is carried by the capacities alone
+    "stretched_96x48": lambda: W.stretched_cylinder(48),
 }
 # The small-volume floor theta: 0 is the paper's mass matrix M = diag(V)
 # (eq:semidiscrete); 0.05 floors every volume the step divides by at 5% of a
@@ -149,7 +153,7 @@ def test_step_phases_match(setup):
 
 
 @pytest.mark.parametrize("theta", THETAS)
-@pytest.mark.parametrize("name", ["cylinder_64", "flat_top_64"])
+@pytest.mark.parametrize("name", ["cylinder_64", "flat_top_64", "stretched_96x48"])
 @pytest.mark.parametrize("precond", ["jacobi", "mg"])
 def test_trajectory_tight_tolerance(precond, name, theta):
     """Ten steps with tight solver tolerances: the trajectories agree to

@@ -102,3 +102,33 @@ def test_library_capacities_match_oracle_ellipse_and_naca():
             scale = h * h if n[0] in "VW" else h
             tol = 1e-10 if n[0] in "VA" else (1e-8 if n[0] == "W" else 1e-6)
             assert np.max(np.abs(a[k] - b[n])) <= tol * scale, n
+
+
+def test_library_capacities_on_a_stretched_mesh():
+    """User abscissas (Sec. 3.1): the library's capacities against the
+    oracle's closed-form circle path on the same stretched mesh, and the
+    abscissas are validated."""
+    import ctypes as C
+    from paper_2211_10698_amd import ccns
+    case = W.stretched_cylinder(24)
+    g = case.grid
+    a = ccns.ccns_capacities(g, case.bodies)
+    b = geometry.capacities(g, case.bodies)
+    h = max(np.diff(g.xf).max(), np.diff(g.yf).max())
+    for k, n in enumerate(ccns.CAP_NAMES):
+        scale = h * h if n[0] == "V" or n[0] == "W" else h
+        tol = 1e-11 if n[0] in "VA" else (1e-8 if n[0] == "W" else 1e-6)
+        assert np.max(np.abs(a[k] - b[n])) <= tol * scale, n
+    # the full cells carry their own widths and heights
+    dx, dy = np.diff(g.xf), np.diff(g.yf)
+    V = a[ccns.CAP_NAMES.index("V")]
+    assert abs(V[1, 1] - dx[0] * dy[0]) < 1e-15 and abs(V[1, 5] - dx[4] * dy[0]) < 1e-15
+    assert abs(V[1:-1, 1:-1].sum() - (g.lx * g.ly - np.pi * 0.25 ** 2)) < 1e-12
+    L = ccns.lib()
+    bad = list(g.xf)
+    bad[3], bad[4] = bad[4], bad[3]
+    for xf in (bad, [g.x0 + 1e-3] + list(g.xf[1:]), list(g.xf[:-1]) + [float("nan")]):
+        gc = ccns.make_grid(g)
+        gc.xf = (C.c_double * len(xf))(*xf)
+        out = np.zeros(L.ccns_caps_count(C.byref(gc)))
+        assert L.ccns_capacities(C.byref(gc), None, 0, ccns.LEVELSET_FN(), None, out.ctypes.data) == ccns.EINVAL

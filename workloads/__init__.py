@@ -226,6 +226,18 @@ def pocket(n: int = 64, seed: int = 13, steps: int = 5) -> Case:
                 pcg_tol=1e-10, noise=1e-2, seed=seed)
 
 
+def stretched_cylinder(n: int = 64, amp: float = 0.5, seed: int = 15, steps: int = 10) -> Case:
+    """Channel [0,4]x[0,2] of 2n x n cells on a smoothly stretched mesh whose
+    spacing is smallest through the middle, where a circle of diameter 0.5
+    sits at (2, 1): the cells there are (1 - amp) and at the walls (1 + amp)
+    times the uniform size (user-defined abscissas, Sec. 3.1).  Re 100 on
+    the diameter, CFL 0.25 on the smallest spacing."""
+    g = GridSpec(2 * n, n, 0.0, 0.0, 4.0, 2.0, xf=stretched_edges(2 * n, 0.0, 4.0, amp),
+                 yf=stretched_edges(n, 0.0, 2.0, amp))
+    return Case(f"stretched_cylinder_{2 * n}x{n}", g, [Body(CIRCLE, 2.0, 1.0, a=0.25)], re=100.0,
+                steps=steps, cfl=0.25, pcg_tol=1e-10, noise=1e-2, seed=seed)
+
+
 def scaled_cylinder(nx: int, ny: int, lx: float, ly: float, seed: int = 2,
                     steps: int = 10) -> Case:
     """A smaller member of the channel-cylinder family (same geometry ratios)."""
