@@ -23,6 +23,14 @@ Readings taken where the paper is silent:
   * A cell is a pressure unknown when it has fluid and belongs to the largest
     set of cells connected through faces with c_f > 0; cells outside it (fluid
     pockets cut off by the body) hold Phi = P = 0.
+  * Outflow walls (end of Sec. 4.6): the faces on such a wall, normal to it,
+    are corrected by the projection like interior unknowns, and the pressure
+    beyond the wall (the ghost cell) is held at zero, so pres on those faces
+    is still the negative transpose of cont (eq:compatibility).  Their
+    control volume is the staggered one that straddles the wall, mass
+    M_f = max(V_f, vol_floor), and the Poisson operator gains their weight
+    c_f on the diagonal of the cell inside: with one such face it is no
+    longer singular.
 """
 
 from __future__ import annotations
@@ -53,26 +61,66 @@ class Prepared:
     Mu: np.ndarray = None    # mass matrix of the x-face unknowns (0 elsewhere)
     Mv: np.ndarray = None
     Vp: np.ndarray = None    # cell volumes of the pressure update (floored)
+    out_u: np.ndarray = None  # bool, x-faces on outflow walls that the projection corrects
+    out_v: np.ndarray = None
+    outflow: str = ""        # the outflow walls, letters of "WESN"
+    singular: bool = True    # no outflow face: Phi is known up to a constant
+
+    @property
+    def proj_u(self):
+        """x-faces the projection corrects: unknowns and outflow faces."""
+        return self.act_u if self.out_u is None else self.act_u | self.out_u
+
+    @property
+    def proj_v(self):
+        return self.act_v if self.out_v is None else self.act_v | self.out_v
 
 
-def prepare(caps: dict, nx: int, ny: int, weight: str = "volume", vol_floor: float = 0.0) -> Prepared:
+def outflow_faces(caps: dict, nx: int, ny: int, outflow: str):
+    """Faces normal to an outflow wall (W: i = 0, E: i = nx in the x-face
+    layout; S: j = 0, N: j = ny in the y-face layout) whose staggered control
+    volume has fluid and whose aperture is open."""
+    shape = (ny + 2, nx + 2)
+    J, I = np.indices(shape)
+    wall_u = np.zeros(shape, bool)
+    wall_v = np.zeros(shape, bool)
+    rows, cols = (J >= 1) & (J <= ny), (I >= 1) & (I <= nx)
+    if "W" in outflow:
+        wall_u |= rows & (I == 0)
+    if "E" in outflow:
+        wall_u |= rows & (I == nx)
+    if "S" in outflow:
+        wall_v |= cols & (J == 0)
+    if "N" in outflow:
+        wall_v |= cols & (J == ny)
+    out_u = wall_u & (caps["Vu"] > 0.0) & (caps["Ax"] > 0.0)
+    out_v = wall_v & (caps["Vv"] > 0.0) & (caps["Ay"] > 0.0)
+    return out_u, out_v
+
+
+def prepare(caps: dict, nx: int, ny: int, weight: str = "volume", vol_floor: float = 0.0,
+            outflow: str = "") -> Prepared:
     """vol_floor: the smallest volume the step divides by (theta hx hy): the
     mass matrix of the velocity unknowns is max(V_f, vol_floor) and the
-    pressure update divides by max(V, vol_floor)."""
+    pressure update divides by max(V, vol_floor).  outflow: the walls (any of
+    "WESN") with a homogeneous Neumann velocity and a zero pressure beyond."""
+    if any(w not in "WESN" for w in outflow):
+        raise ValueError(outflow)
     shape = (ny + 2, nx + 2)
     J, I = np.indices(shape)
     act_u = (I >= 1) & (I <= nx - 1) & (J >= 1) & (J <= ny) & (caps["Vu"] > 0.0) & (caps["Ax"] > 0.0)
     act_v = (I >= 1) & (I <= nx) & (J >= 1) & (J <= ny - 1) & (caps["Vv"] > 0.0) & (caps["Ay"] > 0.0)
-    Mu = np.where(act_u, np.maximum(caps["Vu"], vol_floor), 0.0)
-    Mv = np.where(act_v, np.maximum(caps["Vv"], vol_floor), 0.0)
+    out_u, out_v = outflow_faces(caps, nx, ny, outflow)
+    Mu = np.where(act_u | out_u, np.maximum(caps["Vu"], vol_floor), 0.0)
+    Mv = np.where(act_v | out_v, np.maximum(caps["Vv"], vol_floor), 0.0)
     if weight == "volume":
         wu, wv = safe_inv(Mu), safe_inv(Mv)
     elif weight == "literal":
         wu, wv = np.ones(shape), np.ones(shape)
     else:
         raise ValueError(weight)
-    cx = np.where(act_u, caps["Ax"] ** 2 * wu, 0.0)
-    cy = np.where(act_v, caps["Ay"] ** 2 * wv, 0.0)
+    cx = np.where(act_u | out_u, caps["Ax"] ** 2 * wu, 0.0)
+    cy = np.where(act_v | out_v, caps["Ay"] ** 2 * wv, 0.0)
 
     fluid = (I >= 1) & (I <= nx) & (J >= 1) & (J <= ny) & (caps["V"] > 0.0)
     idx = -np.ones(shape, dtype=np.int64)
@@ -96,16 +144,21 @@ def prepare(caps: dict, nx: int, ny: int, weight: str = "volume", vol_floor: flo
         sizes = np.bincount(lab, minlength=ncomp)
         big = int(np.argmax(sizes))
         act_p[fluid] = lab == big
-    # a face couples pressures only between two active cells
-    cx = np.where(act_p & np.roll(act_p, -1, axis=1), cx, 0.0)
-    cy = np.where(act_p & np.roll(act_p, -1, axis=0), cy, 0.0)
+    # a face couples pressures only between two active cells; an outflow face
+    # needs an active cell inside the wall (beyond it the pressure is zero)
+    cx = np.where((act_p & np.roll(act_p, -1, axis=1)) | (out_u & (act_p | np.roll(act_p, -1, axis=1))), cx, 0.0)
+    cy = np.where((act_p & np.roll(act_p, -1, axis=0)) | (out_v & (act_p | np.roll(act_p, -1, axis=0))), cy, 0.0)
+    out_u = out_u & (cx > 0.0)
+    out_v = out_v & (cy > 0.0)
     gx = np.where(cx > 0.0, caps["Ax"] * wu, 0.0)
     gy = np.where(cy > 0.0, caps["Ay"] * wv, 0.0)
     diag = np.zeros(shape)
     diag[1:-1, 1:-1] = cx[1:-1, 1:-1] + cx[1:-1, :-2] + cy[1:-1, 1:-1] + cy[:-2, 1:-1]
     diag = np.where(act_p, diag, 0.0)
     Vp = np.where(caps["V"] > 0.0, np.maximum(caps["V"], vol_floor), 0.0)
-    return Prepared(caps, nx, ny, act_u, act_v, act_p, cx, cy, gx, gy, diag, int(act_p.sum()), Mu, Mv, Vp)
+    singular = not (out_u.any() or out_v.any())
+    return Prepared(caps, nx, ny, act_u, act_v, act_p, cx, cy, gx, gy, diag, int(act_p.sum()), Mu, Mv, Vp,
+                    out_u, out_v, "".join(w for w in "WESN" if w in outflow), singular)
 
 
 def laplacian(pr: Prepared, phi):

@@ -7,8 +7,8 @@ Readings (the paper states the scheme with unit mass matrices and density):
   * pressure:  P^{n+1/2} = P^{n-1/2} + Phi - (tau mu / 2 rho) V^-1 cont(M^-1 pres(Phi), 0)
     With M = V = 1 and rho = 1 these are the printed equations.
   * AB2 start: conv^{-1} := conv^0; P^{-1/2} = 0; Phi^0 = 0.
-  * The Poisson right-hand side has its mean over the pressure unknowns
-    removed (the problem is singular: pure Neumann in Phi).
+  * Without outflow walls the Poisson right-hand side has its mean over the
+    pressure unknowns removed (the problem is singular: pure Neumann in Phi).
   * Predictor: Jacobi-PCG on H = (rho/tau) M - mu K, K U = visc(strain(U, 0)),
     started from U^n, relative tolerance 1e-12; Poisson: Jacobi-PCG with the
     zero-mean projection, started from Phi^n.
@@ -16,6 +16,17 @@ Readings (the paper states the scheme with unit mass matrices and density):
     that change in time (Stepper.step(..., D_next)), convection and the
     explicit viscous half use D^n, the implicit half, U* on the non-unknown
     faces and the rest of the step D^{n+1}.
+  * Outflow walls (homogeneous Neumann velocity, zero pressure beyond the
+    wall; end of Sec. 4.6): each step takes D^{n+1} on such a wall from U^n
+    by a zero normal gradient (explicitly): a face normal to the wall gets
+    the velocity of the interior face next to it, and the tangential
+    velocity beyond the wall (the ghost row or column, which the convective
+    flux through the wall reads) that of the first row or column inside.
+    U* on the outflow faces is that D^{n+1}; the projection then corrects
+    them with the zero pressure beyond the wall, which makes the Poisson
+    problem non-singular: no mean is removed from its right-hand side or
+    solution.  The tangential stress on every wall is zero already: the node
+    lines on the walls are dry, so the strain there carries no flux.
 """
 
 from __future__ import annotations
@@ -79,8 +90,8 @@ class Stepper:
         self.h = h
         c = pr.caps
         # mass matrix of the unknowns (the cut-cell volumes, floored)
-        self.Vu = pr.Mu if pr.Mu is not None else np.where(pr.act_u, c["Vu"], 0.0)
-        self.Vv = pr.Mv if pr.Mv is not None else np.where(pr.act_v, c["Vv"], 0.0)
+        self.Vu = np.where(pr.act_u, pr.Mu if pr.Mu is not None else c["Vu"], 0.0)
+        self.Vv = np.where(pr.act_v, pr.Mv if pr.Mv is not None else c["Vv"], 0.0)
         self.mask2 = np.stack([pr.act_u, pr.act_v])
         self.vD = self.dirichlet_viscous(Dx, Dy)
         # Jacobi diagonal of H, probed on unit combs
@@ -164,11 +175,31 @@ class Stepper:
         info.pred_iters, info.pred_status = it, status
         return self.full_velocity(Us), conv_n
 
+    def outflow_data(self, Ux, Uy):
+        """D^{n+1} on the outflow walls from U^n (zero normal gradient); the
+        current data everywhere else."""
+        pr = self.pr
+        Dx, Dy = self.Dx.copy(), self.Dy.copy()
+        nx, ny = pr.nx, pr.ny
+        if "W" in pr.outflow:
+            Dx[:, 0] = np.where(pr.out_u[:, 0], Ux[:, 1], Dx[:, 0])
+            Dy[1:ny, 0] = Uy[1:ny, 1]
+        if "E" in pr.outflow:
+            Dx[:, nx] = np.where(pr.out_u[:, nx], Ux[:, nx - 1], Dx[:, nx])
+            Dy[1:ny, nx + 1] = Uy[1:ny, nx]
+        if "S" in pr.outflow:
+            Dy[0, :] = np.where(pr.out_v[0, :], Uy[1, :], Dy[0, :])
+            Dx[0, 1:nx] = Ux[1, 1:nx]
+        if "N" in pr.outflow:
+            Dy[ny, :] = np.where(pr.out_v[ny, :], Uy[ny - 1, :], Dy[ny, :])
+            Dx[ny + 1, 1:nx] = Ux[ny, 1:nx]
+        return Dx, Dy
+
     def poisson_rhs(self, Ux, Uy):
         prm, pr = self.prm, self.pr
         b = (prm.rho / prm.tau) * ops.cont(pr.caps, Ux, Uy, self.Dx, self.Dy)
         b = np.where(pr.act_p, b, 0.0)
-        if pr.n_active:
+        if pr.n_active and pr.singular:
             b = np.where(pr.act_p, b - b[pr.act_p].sum() / pr.n_active, 0.0)
         return b
 
@@ -176,17 +207,19 @@ class Stepper:
         pr = self.pr
         tol = self.prm.pcg_tol if tol is None else tol
         if solver == "direct":
+            from scipy.sparse.linalg import spsolve
             from .solvers import assemble, direct_zero_mean
             A, idx = assemble(self.apply_A, pr.act_p)
             x = np.zeros(pr.act_p.size)
-            x[idx] = direct_zero_mean(A, -b.ravel()[idx])
+            rhs = -b.ravel()[idx]
+            x[idx] = direct_zero_mean(A, rhs) if pr.singular else spsolve(A.tocsc(), rhs)
             phi = x.reshape(b.shape)
             info.cg_iters, info.cg_status = 0, OK
         else:
             phi, it, rr, status = pcg(self.apply_A, -b, phi0, self.Pdinv, pr.act_p, tol,
-                                      self.prm.pcg_maxit, zero_mean=True)
+                                      self.prm.pcg_maxit, zero_mean=pr.singular)
             info.cg_iters, info.cg_relres, info.cg_status = it, rr, status
-        if pr.n_active:
+        if pr.n_active and pr.singular:
             phi = np.where(pr.act_p, phi - phi[pr.act_p].sum() / pr.n_active, 0.0)
         return phi
 
@@ -199,8 +232,8 @@ class Stepper:
         dpy = np.zeros_like(phi)
         dpx[:, :-1] = phi[:, 1:] - phi[:, :-1]
         dpy[:-1, :] = phi[1:, :] - phi[:-1, :]
-        Ux = np.where(pr.act_u, Ux - s * pr.gx * dpx, Ux)
-        Uy = np.where(pr.act_v, Uy - s * pr.gy * dpy, Uy)
+        Ux = np.where(pr.proj_u, Ux - s * pr.gx * dpx, Ux)
+        Uy = np.where(pr.proj_v, Uy - s * pr.gy * dpy, Uy)
         return Ux, Uy
 
     def pressure_update(self, P, phi):
@@ -231,6 +264,8 @@ class Stepper:
         """One PmII step; D_next: Dirichlet data of the next time level when
         it changes in time (else the current data holds at both levels)."""
         info = StepInfo()
+        if D_next is None and not self.pr.singular:
+            D_next = self.outflow_data(st.Ux, st.Uy)
         (Usx, Usy), conv_n = self.predict(st, info, D_next)
         b = self.poisson_rhs(Usx, Usy)
         phi = self.solve_poisson(b, st.Phi, info, solver=solver)

@@ -148,6 +148,9 @@ class Case:
     seed: int = 0
     # smallest volume the step divides by, as a fraction of a cell
     mass_floor: float = 0.05
+    # walls (letters of "WESN") with a homogeneous Neumann velocity and a zero
+    # pressure beyond them; the others hold the Dirichlet data
+    outflow: str = ""
 
     @property
     def ref_length(self) -> float:
@@ -236,6 +239,16 @@ def stretched_cylinder(n: int = 64, amp: float = 0.5, seed: int = 15, steps: int
                  yf=stretched_edges(n, 0.0, 2.0, amp))
     return Case(f"stretched_cylinder_{2 * n}x{n}", g, [Body(CIRCLE, 2.0, 1.0, a=0.25)], re=100.0,
                 steps=steps, cfl=0.25, pcg_tol=1e-10, noise=1e-2, seed=seed)
+
+
+def outflow_cylinder(n: int = 48, seed: int = 16, steps: int = 10, outflow: str = "ESN") -> Case:
+    """The paper's cylinder set-up on a small grid: channel [0,4]x[0,2] of
+    2n x n cells, circle of diameter 0.5 at (1.2, 1), free stream entering
+    through the west wall, homogeneous Neumann velocity with a zero pressure
+    on the other three (outflow) walls.  Re 100 on the diameter, CFL 0.25."""
+    g = GridSpec(2 * n, n, 0.0, 0.0, 4.0, 2.0)
+    return Case(f"outflow_cylinder_{2 * n}x{n}", g, [Body(CIRCLE, 1.2, 1.0, a=0.25)], re=100.0, steps=steps,
+                cfl=0.25, pcg_tol=1e-10, noise=1e-2, seed=seed, outflow=outflow)
 
 
 def scaled_cylinder(nx: int, ny: int, lx: float, ly: float, seed: int = 2,
