@@ -178,7 +178,24 @@ ccns_status ccns_capacities_device(const ccns_grid *grid, const ccns_body *bodie
  *                 most max(1024, n/16) of them (n: entries of the padded
  *                 layout), else from the coefficient arrays; 1: always from
  *                 the arrays.  Both read the same values: the results are
- *                 identical bit for bit. */
+ *                 identical bit for bit.
+ *  outflow        walls with a homogeneous Neumann velocity and a zero
+ *                 pressure beyond them (end of Sec. 4.6), a sum of
+ *                 CCNS_WALL_W/E/S/N (0: Dirichlet data on every wall).  Each
+ *                 step takes the velocity of the faces normal to such a wall
+ *                 from the interior face next to them (zero normal gradient,
+ *                 from U^n), likewise the tangential velocity beyond the wall
+ *                 that the convective flux through it reads; the projection
+ *                 corrects the outflow faces with the pressure beyond the
+ *                 wall held at zero, so the Poisson problem is not singular
+ *                 and no mean is removed.  The Dirichlet data of those faces
+ *                 are then unused: the cells next to an outflow wall must be
+ *                 uncut (CCNS_EINVAL otherwise), where the data cancel out of
+ *                 every operator. */
+#define CCNS_WALL_W 1
+#define CCNS_WALL_E 2
+#define CCNS_WALL_S 4
+#define CCNS_WALL_N 8
 typedef struct {
     double rho, mu, tau, u_ref, gx, gy;
     double pcg_tol, pred_tol, div_tol;
@@ -189,6 +206,7 @@ typedef struct {
     int precond;
     double mass_floor;
     int coef_tables;
+    int outflow;
 } ccns_params;
 
 typedef struct ccns_ctx ccns_ctx;
@@ -262,7 +280,9 @@ enum {
  * `is_device` != 0: the array is device memory, else host memory.
  * Setting CCNS_F_UX/UY: faces that are not velocity unknowns (on a wall
  * normal to them, without fluid in their control volume, or closed, A = 0)
- * take the Dirichlet value whatever the array holds there.
+ * take the Dirichlet value whatever the array holds there, except the
+ * outflow faces and the tangential velocity beyond an outflow wall, which
+ * the step carries as state.
  * Setting CCNS_F_CONVX/Y marks conv^{n-1} as valid (otherwise the first
  * step takes conv^{-1} := conv^0).  Errors: CCNS_EINVAL (bad field). */
 ccns_status ccns_field_set(ccns_ctx *ctx, int field, const double *src, int is_device);
@@ -276,8 +296,10 @@ ccns_status ccns_field_get(ccns_ctx *ctx, int field, double *dst, int is_device)
  *  CCNS_OP_LAP  : in = {phi}     out = {q}     q = L phi = cont(M^-1 pres(phi), 0), active cells
  *  CCNS_OP_H    : in = {px, py}  out = {hx, hy} H p = (rho/tau) V p - mu visc(strain(p, 0)), unknown faces
  *  CCNS_OP_KINETIC: in = {Ux, Uy} out = {k}    kinetic(U) (Sec. 4.5), cells
- * D is the context's Dirichlet data.  Outputs are written on the index range
- * stated and set to 0 elsewhere.  in/out: arrays of device pointers to dense
+ * D is the context's Dirichlet data.  U is read on the unknowns and, for
+ * CCNS_OP_CONT, CCNS_OP_VISC and CCNS_OP_CONV, on every face (outflow faces
+ * included; elsewhere the caller passes D there).  Outputs are written on
+ * the index range stated and set to 0 elsewhere.  in/out: arrays of device pointers to dense
  * (ny+2)x(nx+2) doubles.  Errors: CCNS_EINVAL (unknown op). */
 enum { CCNS_OP_CONT = 0, CCNS_OP_PRES, CCNS_OP_VISC, CCNS_OP_CONV, CCNS_OP_LAP, CCNS_OP_H, CCNS_OP_KINETIC };
 ccns_status ccns_apply(ccns_ctx *ctx, int op, const double *const *in, double *const *out);

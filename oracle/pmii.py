@@ -161,7 +161,10 @@ class Stepper:
         """U* of eq:pm_prediction.  With D_next (time-dependent Dirichlet
         data), convection and the explicit viscous half use the current data
         D^n, the implicit half and U* on the non-unknown faces D^{n+1}, which
-        becomes the current data for the rest of the step."""
+        becomes the current data for the rest of the step.  With outflow
+        walls and no D_next, D^{n+1} is the outflow data of U^n."""
+        if D_next is None and not self.pr.singular:
+            D_next = self.outflow_data(st.Ux, st.Uy)
         conv_n = self.convection(st.Ux, st.Uy)
         conv_prev = conv_n if st.conv_prev is None else st.conv_prev
         vD_next = None if D_next is None else self.dirichlet_viscous(*D_next)
@@ -264,8 +267,6 @@ class Stepper:
         """One PmII step; D_next: Dirichlet data of the next time level when
         it changes in time (else the current data holds at both levels)."""
         info = StepInfo()
-        if D_next is None and not self.pr.singular:
-            D_next = self.outflow_data(st.Ux, st.Uy)
         (Usx, Usy), conv_n = self.predict(st, info, D_next)
         b = self.poisson_rhs(Usx, Usy)
         phi = self.solve_poisson(b, st.Phi, info, solver=solver)

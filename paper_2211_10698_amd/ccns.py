@@ -43,7 +43,8 @@ class Params(C.Structure):
                 ("gx", C.c_double), ("gy", C.c_double), ("pcg_tol", C.c_double), ("pred_tol", C.c_double),
                 ("div_tol", C.c_double), ("pcg_maxit", C.c_int), ("pred_maxit", C.c_int),
                 ("precision", C.c_int), ("visc_form", C.c_int), ("poisson_weight", C.c_int),
-                ("precond", C.c_int), ("mass_floor", C.c_double), ("coef_tables", C.c_int)]
+                ("precond", C.c_int), ("mass_floor", C.c_double), ("coef_tables", C.c_int),
+                ("outflow", C.c_int)]
 
 
 class SolveInfo(C.Structure):
@@ -201,13 +202,19 @@ def ccns_capacities_device(spec, bodies, stream=None):
 
 
 PRECOND_JACOBI, PRECOND_MG = 0, 1
+WALL_BITS = {"W": 1, "E": 2, "S": 4, "N": 8}
 
 
 def make_params(rho, mu, tau, u_ref=1.0, pcg_tol=1e-10, pred_tol=1e-12, div_tol=1e-8, pcg_maxit=200000,
                 pred_maxit=500, precision=0, visc_form=0, poisson_weight=0, gx=0.0, gy=0.0,
-                precond=PRECOND_MG, mass_floor=0.05, coef_tables=0) -> Params:
+                precond=PRECOND_MG, mass_floor=0.05, coef_tables=0, outflow="") -> Params:
+    """outflow: the outflow walls as letters of "WESN" (or the C bitmask)."""
+    if isinstance(outflow, str):
+        if any(w not in "WESN" for w in outflow):
+            raise ValueError(f"outflow walls {outflow!r}: letters of 'WESN'")
+        outflow = sum(WALL_BITS[w] for w in set(outflow))
     return Params(rho, mu, tau, u_ref, gx, gy, pcg_tol, pred_tol, div_tol, pcg_maxit, pred_maxit, precision,
-                  visc_form, poisson_weight, precond, mass_floor, coef_tables)
+                  visc_form, poisson_weight, precond, mass_floor, coef_tables, outflow)
 
 
 STATIC_WORKSPACE_BYTES = 64 << 20

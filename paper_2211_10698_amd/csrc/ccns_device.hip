@@ -195,7 +195,7 @@ __global__ __launch_bounds__(NT) void k_pois_init(Dims d, PoisCoef pc, double *_
                                                   const double *pin, int nin, double *pout, float *__restrict__ r32,
                                                   float *__restrict__ x32, const float *__restrict__ dinv32) {
     double mb = 0.0;
-    if (pin) {
+    if (pin && st->zero_mean) {
         double t[1];
         get_totals<1>(pin, nin, t);
         mb = t[0] / (double)st->n_active;
@@ -1804,6 +1804,24 @@ __global__ __launch_bounds__(NT) void k_pred_resid(int P, int rows, int gx, int 
 // with its node strains formed once per node (cell strains where a face
 // needs them); convection and the pressure gradient in index form.  With CLS
 // the viscous coefficients come from the class table, as in k_pred_cg.
+//
+// Outflow walls (wall bits `ofl`, faces with a corrector factor gf != 0 but
+// no mass): U* on such a face is U^n of the interior face next to it (zero
+// normal gradient), as is U* of the tangential velocity beyond the wall.
+// Both halves of the viscous term see the face's own velocity (U^n in the
+// explicit half, U* in the implicit one), so K is applied to U^n + U* there;
+// the constant Dirichlet part vd leaves those faces out.
+struct OutflowDesc {
+    int nx, ny, ofl;
+    const double *gfx, *gfy;  // corrector factors: nonzero on the outflow faces the projection corrects
+};
+__device__ inline bool outflow_xface(const OutflowDesc &o, int j, int i) {
+    return j >= 1 && j <= o.ny && (((o.ofl & CCNS_WALL_W) && i == 0) || ((o.ofl & CCNS_WALL_E) && i == o.nx));
+}
+__device__ inline bool outflow_yface(const OutflowDesc &o, int j, int i) {
+    return i >= 1 && i <= o.nx && (((o.ofl & CCNS_WALL_S) && j == 0) || ((o.ofl & CCNS_WALL_N) && j == o.ny));
+}
+
 template <bool GEO, bool CLS = false>
 __global__ __launch_bounds__(NT) void k_pred_rhs(int P, int rows, int gx, int gy, size_t n, PredCoefT<double> pc,
                                                  const double *__restrict__ ax, const double *__restrict__ ay,
@@ -1814,7 +1832,7 @@ __global__ __launch_bounds__(NT) void k_pred_rhs(int P, int rows, int gx, int gy
                                                  const double *__restrict__ vdy, double *__restrict__ convx,
                                                  double *__restrict__ convy, double *__restrict__ rhs,
                                                  double *__restrict__ xs, double rho, double gxv, double gyv,
-                                                 int conv_valid) {
+                                                 int conv_valid, OutflowDesc of) {
     __shared__ PredTileNx<double> s;
     const int L = logical_group(((gridDim.x + 7) / 8) * 8);
     if (L >= gx * gy) return;
@@ -1834,6 +1852,19 @@ __global__ __launch_bounds__(NT) void k_pred_rhs(int P, int rows, int gx, int gy
             my = pc.vv[k];
         }
     };
+    // the value K sees at entry k: U^n on unknowns, U^n + U* on outflow faces
+    auto stage_x = [&](bool in, size_t k, int j, int i, double mx, double u) -> double {
+        if (!in) return 0.0;
+        if (mx > 0.0) return u;
+        if (of.ofl && outflow_xface(of, j, i) && of.gfx[k] != 0.0) return u + ux[i == 0 ? k + 1 : k - 1];
+        return 0.0;
+    };
+    auto stage_y = [&](bool in, size_t k, int j, int i, double my, double v) -> double {
+        if (!in) return 0.0;
+        if (my > 0.0) return v;
+        if (of.ofl && outflow_yface(of, j, i) && of.gfy[k] != 0.0) return v + uy[j == 0 ? k + P : k - P];
+        return 0.0;
+    };
 #pragma unroll
     for (int m = 0; m < RW; ++m) {
         const int ly = ty + 4 * m;
@@ -1843,8 +1874,8 @@ __global__ __launch_bounds__(NT) void k_pred_rhs(int P, int rows, int gx, int gy
         double mx, my;
         volumes(k, mx, my, cl[m]);
         const double u = ux[k], v = uy[k];
-        s.spx[ly + 1][tx + 1] = (in && mx > 0.0) ? u : 0.0;
-        s.spy[ly + 1][tx + 1] = (in && my > 0.0) ? v : 0.0;
+        s.spx[ly + 1][tx + 1] = stage_x(in, k, j, i, mx, u);
+        s.spy[ly + 1][tx + 1] = stage_y(in, k, j, i, my, v);
     }
     // the one-face halo, as in k_pred_cg
     for (int e = threadIdx.x; e < 2 * (TX + 2) + 2 * HTY; e += NT) {
@@ -1864,8 +1895,8 @@ __global__ __launch_bounds__(NT) void k_pred_rhs(int P, int rows, int gx, int gy
         int ck;
         volumes(k, mx, my, ck);
         const double u = ux[k], v = uy[k];
-        s.spx[ly][lx] = (in && mx > 0.0) ? u : 0.0;
-        s.spy[ly][lx] = (in && my > 0.0) ? v : 0.0;
+        s.spx[ly][lx] = stage_x(in, k, j, i, mx, u);
+        s.spy[ly][lx] = stage_y(in, k, j, i, my, v);
     }
     __syncthreads();
     if constexpr (CLS) {
@@ -1903,8 +1934,23 @@ __global__ __launch_bounds__(NT) void k_pred_rhs(int P, int rows, int gx, int gy
             mx = pc.vu[k], my = pc.vv[k];
         }
         const double u = ux[k], v = uy[k];
-        xs[k] = u;
-        xs[n + k] = v;
+        double us = u, vs = v;
+        if (of.ofl) {
+            // U* on outflow faces, and beyond the outflow walls, from the
+            // interior neighbour (zero normal gradient)
+            if (mx == 0.0 && outflow_xface(of, j, i) && of.gfx[k] != 0.0) us = ux[i == 0 ? k + 1 : k - 1];
+            if (my == 0.0 && outflow_yface(of, j, i) && of.gfy[k] != 0.0) vs = uy[j == 0 ? k + P : k - P];
+            if (i >= 1 && i <= of.nx - 1) {
+                if ((of.ofl & CCNS_WALL_S) && j == 0) us = ux[k + P];
+                if ((of.ofl & CCNS_WALL_N) && j == of.ny + 1) us = ux[k - P];
+            }
+            if (j >= 1 && j <= of.ny - 1) {
+                if ((of.ofl & CCNS_WALL_W) && i == 0) vs = uy[k + 1];
+                if ((of.ofl & CCNS_WALL_E) && i == of.nx + 1) vs = uy[k - 1];
+            }
+        }
+        xs[k] = us;
+        xs[n + k] = vs;
         if (mx > 0.0) {
             const double cv = conv_x(ax, ay, ux, uy, hbx, dx, k, P);
             const double cold = conv_valid ? convx[k] : cv;
@@ -1998,11 +2044,26 @@ __global__ __launch_bounds__(NT) void k_diag_final(const double *pin, int nin, D
 }
 
 // U = D on every face that is not a velocity unknown (vm = 0 there).
+// A set velocity field keeps the Dirichlet data on the faces that are no
+// unknowns, except where the step carries the velocity as state: outflow
+// faces (corrector factor gf != 0) and, beyond an outflow wall, the
+// tangential velocity (component 0: x, 1: y).
 __global__ __launch_bounds__(NT) void k_keep_dirichlet(Dims d, double *__restrict__ u,
                                                        const double *__restrict__ dd,
-                                                       const double *__restrict__ vm) {
-    for_cells(d, [&](int, int, int, size_t k) {
-        if (!(vm[k] > 0.0)) u[k] = dd[k];
+                                                       const double *__restrict__ vm,
+                                                       const double *__restrict__ gf, OutflowDesc of, int comp) {
+    for_cells(d, [&](int, int j, int i, size_t k) {
+        if (vm[k] > 0.0) return;
+        if (of.ofl) {
+            if (gf[k] != 0.0) return;
+            if (comp == 0 && i >= 1 && i <= of.nx - 1 &&
+                (((of.ofl & CCNS_WALL_S) && j == 0) || ((of.ofl & CCNS_WALL_N) && j == of.ny + 1)))
+                return;
+            if (comp == 1 && j >= 1 && j <= of.ny - 1 &&
+                (((of.ofl & CCNS_WALL_W) && i == 0) || ((of.ofl & CCNS_WALL_E) && i == of.nx + 1)))
+                return;
+        }
+        u[k] = dd[k];
     });
 }
 
@@ -2032,12 +2093,15 @@ __global__ __launch_bounds__(NT) void k_op_pres(Dims d, const double *ax, const 
 }
 
 // mode 0: visc(strain(U, D)) = K U_unknowns + vD; mode 1: H p (p masked).
+// mode 0: visc(strain(U, D)) with U given on the unknowns and on the outflow
+// faces (the faces without mass whose corrector factor gfx, gfy is nonzero;
+// the constant part vd leaves them out), D elsewhere; mode 1: H U.
 __global__ __launch_bounds__(NT) void k_op_visc(Dims d, PredCoef pc, const double *vdx, const double *vdy,
-                                                const double *ux, const double *uy, double *ox, double *oy,
-                                                int mode) {
+                                                const double *gfx, const double *gfy, const double *ux,
+                                                const double *uy, double *ox, double *oy, int mode) {
     const size_t P = d.pitch;
-    auto pxm = [&](size_t kk) { return pc.vu[kk] > 0.0 ? ux[kk] : 0.0; };
-    auto pym = [&](size_t kk) { return pc.vv[kk] > 0.0 ? uy[kk] : 0.0; };
+    auto pxm = [&](size_t kk) { return (pc.vu[kk] > 0.0 || (mode == 0 && gfx[kk] != 0.0)) ? ux[kk] : 0.0; };
+    auto pym = [&](size_t kk) { return (pc.vv[kk] > 0.0 || (mode == 0 && gfy[kk] != 0.0)) ? uy[kk] : 0.0; };
     for_cells(d, [&](int, int j, int i, size_t k) {
         double a = 0.0, b = 0.0;
         if (pc.vu[k] > 0.0) {
@@ -2484,6 +2548,10 @@ ccns_status cg_loop(ccns_ctx *c, CgState *st, T *x, T *r, T *const pbuf[2], int 
         info->inner_fail_sweep = -1;
     }
     return (ccns_status)c->h_st->status;
+}
+
+OutflowDesc outflow_desc(const ccns_ctx *c) {
+    return OutflowDesc{c->g.nx, c->g.ny, c->prm.outflow, c->a[A_GX], c->a[A_GY]};
 }
 
 void set_cg(ccns_ctx *c, CgState *st, double tol, int maxit, int zero_mean, int n_active) {
@@ -2986,7 +3054,7 @@ void predictor_rhs(ccns_ctx *c) {
     k<<<nb, NT, 0, c->stream>>>(L.pitch, L.rows, gx, gy, L.n, pc, c->a[A_AX], c->a[A_AY], c->a[A_HBX], c->a[A_HBY],
                                 c->a[A_DX], c->a[A_DY], c->a[A_UX], c->a[A_UY], c->a[A_P], c->a[A_VDX], c->a[A_VDY],
                                 c->a[A_CONVX], c->a[A_CONVY], c->a[A_RHSX], c->a[A_USX], c->prm.rho, c->prm.gx,
-                                c->prm.gy, c->conv_valid);
+                                c->prm.gy, c->conv_valid, outflow_desc(c));
     c->conv_valid = 1;
 }
 
@@ -3264,7 +3332,7 @@ ccns_status create_ctx(const ccns_grid *grid, const ccns_params *params, const d
     *out = nullptr;
     if (!grid || !params || !caps_host || !dirichlet_host || !dev_workspace) return CCNS_EINVAL;
     if (params->precision < 0 || params->precision > 1 || params->precond < 0 || params->precond > 1 ||
-        params->coef_tables < 0 || params->coef_tables > 1)
+        params->coef_tables < 0 || params->coef_tables > 1 || params->outflow < 0 || params->outflow > 15)
         return CCNS_EINVAL;
     ccns_ctx *c = new (std::nothrow) ccns_ctx();
     if (!c) return CCNS_ENOMEM;
@@ -3396,9 +3464,11 @@ ccns_status create_ctx(const ccns_grid *grid, const ccns_params *params, const d
         return s;
     }
     set_cg(c, c->st_pred, params->pred_tol, params->pred_maxit, 0, hc.n_uact + hc.n_vact);
-    set_cg(c, c->st_pois, params->pcg_tol, params->pcg_maxit, 1, hc.n_active);
+    // with outflow faces the pressure beyond them is held: not singular
+    const int singular = hc.n_out == 0;
+    set_cg(c, c->st_pois, params->pcg_tol, params->pcg_maxit, singular, hc.n_active);
     set_cg(c, c->st_pred_in, INNER_TOL_MIN, params->pred_maxit, 0, hc.n_uact + hc.n_vact);
-    set_cg(c, c->st_pois_in, INNER_TOL_MIN, params->pcg_maxit, 1, hc.n_active);
+    set_cg(c, c->st_pois_in, INNER_TOL_MIN, params->pcg_maxit, singular, hc.n_active);
     if (hipStreamSynchronize(c->stream) != hipSuccess) {
         destroy_ctx(c, false);
         return CCNS_EDEVICE;
@@ -3421,9 +3491,11 @@ ccns_status ccns_field_set(ccns_ctx *c, int field, const double *src, int is_dev
     if (s != CCNS_OK) return s;
     if (field == CCNS_F_CONVX || field == CCNS_F_CONVY) c->conv_valid = 1;
     if (field == CCNS_F_UX)
-        k_keep_dirichlet<<<c->dc.nblk, NT, 0, c->stream>>>(c->dc, c->a[A_UX], c->a[A_DX], c->a[A_VU]);
+        k_keep_dirichlet<<<c->dc.nblk, NT, 0, c->stream>>>(c->dc, c->a[A_UX], c->a[A_DX], c->a[A_VU], c->a[A_GX],
+                                                            outflow_desc(c), 0);
     if (field == CCNS_F_UY)
-        k_keep_dirichlet<<<c->dc.nblk, NT, 0, c->stream>>>(c->dc, c->a[A_UY], c->a[A_DY], c->a[A_VV]);
+        k_keep_dirichlet<<<c->dc.nblk, NT, 0, c->stream>>>(c->dc, c->a[A_UY], c->a[A_DY], c->a[A_VV], c->a[A_GY],
+                                                            outflow_desc(c), 1);
     HIPCHK(c, hipGetLastError());
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return CCNS_OK;
@@ -3456,7 +3528,8 @@ ccns_status ccns_apply(ccns_ctx *c, int op, const double *const *in, double *con
     case CCNS_OP_VISC:
     case CCNS_OP_H:
         if ((s = to_dev(c, t0, in[0], D2D)) || (s = to_dev(c, t1, in[1], D2D))) return s;
-        k_op_visc<<<c->dc.nblk, NT, 0, c->stream>>>(c->dc, pred_coef(c), c->a[A_VDX], c->a[A_VDY], t0, t1, t2, t3,
+        k_op_visc<<<c->dc.nblk, NT, 0, c->stream>>>(c->dc, pred_coef(c), c->a[A_VDX], c->a[A_VDY], c->a[A_GX],
+                                                    c->a[A_GY], t0, t1, t2, t3,
                                                        op == CCNS_OP_VISC ? 0 : 1);
         if ((s = from_dev(c, out[0], t2, D2D)) || (s = from_dev(c, out[1], t3, D2D))) return s;
         break;

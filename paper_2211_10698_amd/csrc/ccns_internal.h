@@ -41,6 +41,7 @@ struct HostCoef {
     std::vector<double> vdx, vdy;             // visc(strain(U~, D)) on unknown faces
     int n_active = 0;                         // pressure unknowns
     int n_uact = 0, n_vact = 0;               // velocity unknowns
+    int n_out = 0;                            // outflow faces the projection corrects
 };
 
 // Validates the inputs and derives every coefficient field (host, FP64).

@@ -9,6 +9,12 @@
 //  - node strain weights (eq:offdiag): the printed form uses two node volumes
 //    W^xy and W^yx; the symmetric default keeps 1/W^xy for the x rows,
 //    1/W^yx for the y rows and 1/sqrt(W^xy W^yx) for the cross coupling.
+//  - outflow walls (end of Sec. 4.6): the open faces normal to such a wall
+//    are corrected by the projection (mass max(V_f, floor), Poisson weight
+//    A^2/M on the diagonal of the cell inside, the pressure beyond the wall
+//    held at zero); they are no predictor unknowns and keep U = D out of the
+//    constant Dirichlet part of the viscous term, since the step replaces
+//    their velocity every time.
 #include <algorithm>
 #include <cmath>
 #include <queue>
@@ -37,6 +43,7 @@ ccns_status prepare_coefficients(const ccns_grid &g, const ccns_params &prm, con
     if (!(prm.rho > 0) || !(prm.mu >= 0) || !(prm.tau > 0)) { err = "rho, tau must be > 0 and mu >= 0"; return CCNS_EINVAL; }
     if (!(prm.mass_floor >= 0.0) || !(prm.mass_floor <= 1.0)) { err = "mass_floor must be in [0, 1]"; return CCNS_EINVAL; }
     if (prm.coef_tables != 0 && prm.coef_tables != 1) { err = "coef_tables must be 0 or 1"; return CCNS_EINVAL; }
+    if (prm.outflow < 0 || prm.outflow > 15) { err = "outflow must be a sum of CCNS_WALL_*"; return CCNS_EINVAL; }
     if (prm.visc_form < 0 || prm.visc_form > 2 || prm.poisson_weight < 0 || prm.poisson_weight > 1) {
         err = "bad visc_form or poisson_weight"; return CCNS_EINVAL;
     }
@@ -60,7 +67,8 @@ ccns_status prepare_coefficients(const ccns_grid &g, const ccns_params &prm, con
                     &o.nyy, &o.hdx, &o.hdy, &o.vinv, &o.utx, &o.uty, &o.vur, &o.vvr})
         v->assign(n, 0.0);
 
-    std::vector<char> au(n, 0), av(n, 0), fluid(n, 0), act(n, 0);
+    std::vector<char> au(n, 0), av(n, 0), fluid(n, 0), act(n, 0), ou(n, 0), ov(n, 0);
+    const int of = prm.outflow;
     for (int j = 0; j < H; ++j)
         for (int i = 0; i < W; ++i) {
             size_t k = id(j, i);
@@ -70,19 +78,48 @@ ccns_status prepare_coefficients(const ccns_grid &g, const ccns_params &prm, con
             au[k] = (i >= 1 && i <= nx - 1 && j >= 1 && j <= ny && Vu[k] > 0.0 && Ax[k] > 0.0);
             av[k] = (i >= 1 && i <= nx && j >= 1 && j <= ny - 1 && Vv[k] > 0.0 && Ay[k] > 0.0);
             fluid[k] = (i >= 1 && i <= nx && j >= 1 && j <= ny && V[k] > 0.0);
+            const bool wu = j >= 1 && j <= ny && (((of & CCNS_WALL_W) && i == 0) || ((of & CCNS_WALL_E) && i == nx));
+            const bool wv = i >= 1 && i <= nx && (((of & CCNS_WALL_S) && j == 0) || ((of & CCNS_WALL_N) && j == ny));
+            ou[k] = wu && Vu[k] > 0.0 && Ax[k] > 0.0;
+            ov[k] = wv && Vv[k] > 0.0 && Ay[k] > 0.0;
         }
-    // mass matrix of the velocity unknowns (with the optional floor)
+    if (of) {
+        // the Dirichlet data of an outflow face cancel out of cont, strain and
+        // the convective bracket where the first-kind and second-kind
+        // capacities next to the wall agree (uncut cells): then the data the
+        // step leaves in place act as the zero-gradient data it stands for
+        auto same = [](double a, double b) { return std::fabs(a - b) <= 1e-12 * std::max(std::fabs(a), std::fabs(b)); };
+        bool ok = true;
+        for (int j = 1; j <= ny && ok; ++j) {
+            if (of & CCNS_WALL_E)
+                ok = same(Ax[id(j, nx)], Bx[id(j, nx)]) && same(Bxx[id(j, nx)], Axx[id(j, nx)]) &&
+                     (j == ny || (same(Bxy[id(j, nx)], Axy[id(j, nx)]) && same(Bxy[id(j + 1, nx)], Axy[id(j, nx)])));
+            if ((of & CCNS_WALL_W) && ok)
+                ok = same(Ax[id(j, 0)], Bx[id(j, 1)]) && same(Bxx[id(j, 0)], Axx[id(j, 1)]) &&
+                     (j == ny || (same(Bxy[id(j, 0)], Axy[id(j, 0)]) && same(Bxy[id(j + 1, 0)], Axy[id(j, 0)])));
+        }
+        for (int i = 1; i <= nx && ok; ++i) {
+            if (of & CCNS_WALL_N)
+                ok = same(Ay[id(ny, i)], By[id(ny, i)]) && same(Byy[id(ny, i)], Ayy[id(ny, i)]) &&
+                     (i == nx || (same(Byx[id(ny, i)], Ayx[id(ny, i)]) && same(Byx[id(ny, i + 1)], Ayx[id(ny, i)])));
+            if ((of & CCNS_WALL_S) && ok)
+                ok = same(Ay[id(0, i)], By[id(1, i)]) && same(Byy[id(0, i)], Ayy[id(1, i)]) &&
+                     (i == nx || (same(Byx[id(0, i)], Ayx[id(0, i)]) && same(Byx[id(0, i + 1)], Ayx[id(0, i)])));
+        }
+        if (!ok) { err = "a body cuts the cells next to an outflow wall"; return CCNS_EINVAL; }
+    }
+    // mass matrix of the velocity unknowns and outflow faces (with the floor)
     const double mfloor = prm.mass_floor * g.hx * g.hy;
     std::vector<double> Mu(n, 0.0), Mv(n, 0.0);
     for (size_t k = 0; k < n; ++k) {
-        Mu[k] = au[k] ? std::max(Vu[k], mfloor) : Vu[k];
-        Mv[k] = av[k] ? std::max(Vv[k], mfloor) : Vv[k];
+        Mu[k] = (au[k] || ou[k]) ? std::max(Vu[k], mfloor) : Vu[k];
+        Mv[k] = (av[k] || ov[k]) ? std::max(Vv[k], mfloor) : Vv[k];
     }
     const bool volw = prm.poisson_weight == 0;
     for (size_t k = 0; k < n; ++k) {
         double wu = volw ? inv0(Mu[k]) : 1.0, wv = volw ? inv0(Mv[k]) : 1.0;
-        o.cx[k] = au[k] ? Ax[k] * Ax[k] * wu : 0.0;
-        o.cy[k] = av[k] ? Ay[k] * Ay[k] * wv : 0.0;
+        o.cx[k] = (au[k] || ou[k]) ? Ax[k] * Ax[k] * wu : 0.0;
+        o.cy[k] = (av[k] || ov[k]) ? Ay[k] * Ay[k] * wv : 0.0;
     }
     // largest set of fluid cells connected through faces with c > 0
     std::vector<int> lab(n, -1);
@@ -115,11 +152,15 @@ ccns_status prepare_coefficients(const ccns_grid &g, const ccns_params &prm, con
         act[k] = (lab[k] == best && best >= 0);
         o.n_active += act[k];
     }
+    o.n_out = 0;
     for (size_t k = 0; k < n; ++k) {
-        bool ex = (k + 1 < n) && act[k] && act[k + 1];
-        bool ey = (k + W < n) && act[k] && act[k + W];
+        // an outflow face couples the cell inside to the zero pressure beyond
+        const bool ae = (k + 1 < n) && act[k + 1], an = (k + W < n) && act[k + W];
+        bool ex = (act[k] && ae) || (ou[k] && (act[k] || ae));
+        bool ey = (act[k] && an) || (ov[k] && (act[k] || an));
         if (!ex) o.cx[k] = 0.0;
         if (!ey) o.cy[k] = 0.0;
+        o.n_out += (ou[k] && ex) + (ov[k] && ey);
         double wu = volw ? inv0(Mu[k]) : 1.0, wv = volw ? inv0(Mv[k]) : 1.0;
         o.gx[k] = o.cx[k] > 0.0 ? Ax[k] * wu : 0.0;
         o.gy[k] = o.cy[k] > 0.0 ? Ay[k] * wv : 0.0;
@@ -143,8 +184,8 @@ ccns_status prepare_coefficients(const ccns_grid &g, const ccns_params &prm, con
         o.vv[k] = av[k] ? Mv[k] : 0.0;
         o.vur[k] = Vu[k];
         o.vvr[k] = Vv[k];
-        o.utx[k] = au[k] ? 0.0 : Dx[k];
-        o.uty[k] = av[k] ? 0.0 : Dy[k];
+        o.utx[k] = (au[k] || o.gx[k] != 0.0) ? 0.0 : Dx[k];
+        o.uty[k] = (av[k] || o.gy[k] != 0.0) ? 0.0 : Dy[k];
         o.n_uact += au[k];
         o.n_vact += av[k];
     }
@@ -232,25 +273,33 @@ void coarsen_poisson(int nx, int ny, const std::vector<double> &cx, const std::v
                 }
             act[(size_t)J * Wc + I] = a;
         }
+    // a face on the box's wall (weights only where the pressure beyond the
+    // wall is held, on outflow walls) covers the fine wall faces: the east
+    // wall face of the last coarse column is the fine face nx even when that
+    // column has one fine column
     for (int J = 1; J <= nyc; ++J)
         for (int I = 0; I <= nxc; ++I) {
             double sum = 0.0;
+            const int i = std::min(2 * I, nx);
             for (int dj = 0; dj < 2; ++dj) {
                 int j = 2 * J - 1 + dj;
-                if (j <= ny) sum += cx[(size_t)j * W + 2 * I];
+                if (j <= ny) sum += cx[(size_t)j * W + i];
             }
             size_t k = (size_t)J * Wc + I;
-            cxc[k] = (I + 1 <= nxc + 1 && act[k] && act[k + 1]) ? 0.5 * sum : 0.0;
+            const bool wall = I == 0 || I == nxc;
+            cxc[k] = ((wall && (act[k] || act[k + 1])) || (act[k] && act[k + 1])) ? 0.5 * sum : 0.0;
         }
     for (int J = 0; J <= nyc; ++J)
         for (int I = 1; I <= nxc; ++I) {
             double sum = 0.0;
+            const int j = std::min(2 * J, ny);
             for (int di = 0; di < 2; ++di) {
                 int i = 2 * I - 1 + di;
-                if (i <= nx) sum += cy[(size_t)(2 * J) * W + i];
+                if (i <= nx) sum += cy[(size_t)j * W + i];
             }
             size_t k = (size_t)J * Wc + I;
-            cyc[k] = (act[k] && act[k + Wc]) ? 0.5 * sum : 0.0;
+            const bool wall = J == 0 || J == nyc;
+            cyc[k] = ((wall && (act[k] || act[k + Wc])) || (act[k] && act[k + Wc])) ? 0.5 * sum : 0.0;
         }
     for (int J = 1; J <= nyc; ++J)
         for (int I = 1; I <= nxc; ++I) {

@@ -16,7 +16,7 @@ def case_setup(case, pcg_tol=None, pred_tol=1e-12, visc_form="geometric", caps=N
     if caps is None:
         caps = geometry.capacities(g, case.bodies)
     theta = case.mass_floor if mass_floor is None else mass_floor
-    pr = derived.prepare(caps, g.nx, g.ny, vol_floor=theta * g.hx * g.hy)
+    pr = derived.prepare(caps, g.nx, g.ny, vol_floor=theta * g.hx * g.hy, outflow=case.outflow)
     Dx, Dy = W.dirichlet(case)
     tol = case.pcg_tol if pcg_tol is None else pcg_tol
     prm = pmii.Params(rho=case.rho, mu=case.mu, tau=case.tau, u_inf=case.u_inf, pcg_tol=tol,
@@ -24,11 +24,19 @@ def case_setup(case, pcg_tol=None, pred_tol=1e-12, visc_form="geometric", caps=N
     st = pmii.Stepper(pr, prm, Dx, Dy, min(g.hx, g.hy))
     form = {"geometric": 0, "literal": 1, "mean": 2}[visc_form]
     cp = ccns.make_params(case.rho, case.mu, case.tau, u_ref=case.u_inf, pcg_tol=tol, pred_tol=pred_tol,
-                          visc_form=form, precision=precision, div_tol=div_tol, mass_floor=theta,
+                          visc_form=form, precision=precision, div_tol=div_tol, mass_floor=theta, outflow=case.outflow,
                           precond={"jacobi": ccns.PRECOND_JACOBI, "mg": ccns.PRECOND_MG}[precond])
     capsarr = np.stack([caps[k] for k in ccns.CAP_NAMES])
     ctx = ccns.Context(g, cp, capsarr, Dx, Dy)
     return caps, pr, st, ctx, Dx, Dy
+
+
+def demean(pr, a):
+    """a minus its mean over the pressure unknowns where the pressure is
+    known up to a constant (no outflow wall); a on the unknowns otherwise."""
+    if pr.singular and pr.n_active:
+        return np.where(pr.act_p, a - a[pr.act_p].mean(), 0.0)
+    return np.where(pr.act_p, a, 0.0)
 
 
 def rel(a, b, mask=None):

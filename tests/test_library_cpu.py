@@ -50,7 +50,7 @@ def test_argument_validation_without_gpu():
     caps = np.zeros(L.ccns_caps_count(C.byref(g)))
     dir2 = np.zeros(2 * 10 * 10)
     for bad_p in (ccns.make_params(1.0, 0.01, 0.01, precision=2), ccns.make_params(1.0, 0.01, 0.01, precond=5),
-                  ccns.make_params(1.0, 0.01, 0.01, coef_tables=2)):
+                  ccns.make_params(1.0, 0.01, 0.01, coef_tables=2), ccns.make_params(1.0, 0.01, 0.01, outflow=16)):
         assert L.ccns_ctx_create(C.byref(g), C.byref(bad_p), caps.ctypes.data, dir2.ctypes.data,
                                  C.c_void_p(256), 1 << 30, None, C.byref(h)) == ccns.EINVAL
     # batches: empty, NULL member, repeated member (checked before any member is read)
