@@ -367,6 +367,23 @@ ccns_status ccns_timing(ccns_ctx *ctx, int enable, double *ms, long *count);
 /* Diagnostics of the current state (FP64 reductions on the device). */
 ccns_status ccns_diagnostics(ccns_ctx *ctx, ccns_step_info *info);
 
+/* Force of the fluid on the bodies for the current state (P of the last
+ * step, U), a reading of the drag and lift that Sec. 5 reports without a
+ * discrete formula: the momentum the fluid exchanges with the bodies through
+ * the capacities in eq:semidiscrete.  With S the strain of eq:diag and
+ * eq:offdiag on (U, D) (node strains S_x, S_y of the x and y rows):
+ *   F^p_x = sum_cells P (A^x_{i-1/2} - A^x_{i+1/2}),  F^p_y likewise in y
+ *   F^v_x = 2 mu [sum_cells S_xx (B^xx_{i+1/2} - B^xx_{i-1/2})
+ *                 + sum_nodes S_x (B^xy above - B^xy below)],  F^v_y likewise
+ * over the cells and the nodes off the box's walls; only cut cells and nodes
+ * contribute (bodies clear of the walls).  Summed by one work-group in a
+ * fixed order.  Drag and lift coefficients: (F^p + F^v) / (rho U^2 L / 2).
+ *  forces_host  caller-owned host array of 4 doubles:
+ *               {F^p_x, F^p_y, F^v_x, F^v_y}; the call waits for them
+ * Errors: CCNS_EINVAL (null argument), CCNS_ENOMEM (more cut cells or nodes
+ * than the context's table holds: 8 (nx + ny) + 1024 each), CCNS_EDEVICE. */
+ccns_status ccns_forces(ccns_ctx *ctx, double *forces_host);
+
 /* Batches of independent simulations of any sizes (the ragged batches of
  * many uneven simulations that share one GPU).  A batch borrows contexts
  * the caller created and still owns; each should have its own HIP stream,

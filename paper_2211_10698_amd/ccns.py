@@ -117,6 +117,8 @@ def lib():
             f.argtypes = [C.c_void_p, P(StepInfo)]
         L.ccns_predict.restype = C.c_int
         L.ccns_predict.argtypes = [C.c_void_p, P(SolveInfo)]
+        L.ccns_forces.restype = C.c_int
+        L.ccns_forces.argtypes = [C.c_void_p, P(C.c_double)]
         L.ccns_timing.restype = C.c_int
         L.ccns_timing.argtypes = [C.c_void_p, C.c_int, P(C.c_double), P(C.c_long)]
         L.ccns_step.restype = C.c_int
@@ -135,7 +137,8 @@ EXPORTED = ("ccns_caps_count", "ccns_capacities", "ccns_capacities_scratch_bytes
             "ccns_workspace_bytes", "ccns_ctx_create", "ccns_ctx_create_static",
             "ccns_ctx_destroy", "ccns_last_error", "ccns_coef_classes", "ccns_field_set", "ccns_field_get", "ccns_apply",
             "ccns_pressure_solve", "ccns_project", "ccns_step", "ccns_predict", "ccns_correct",
-            "ccns_diagnostics", "ccns_timing", "ccns_batch_create", "ccns_batch_step", "ccns_batch_destroy")
+            "ccns_diagnostics", "ccns_forces", "ccns_timing", "ccns_batch_create", "ccns_batch_step",
+            "ccns_batch_destroy")
 
 
 class CcnsError(RuntimeError):
@@ -381,6 +384,12 @@ class Context:
         info = StepInfo()
         self._chk(lib().ccns_diagnostics(self.h, C.byref(info)), "diagnostics")
         return info
+
+    def forces(self):
+        """(F^p_x, F^p_y, F^v_x, F^v_y) on the bodies; see ccns_forces."""
+        out = (C.c_double * 4)()
+        self._chk(lib().ccns_forces(self.h, out), "forces")
+        return tuple(out)
 
 
 class Batch:

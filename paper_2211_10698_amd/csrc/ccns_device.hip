@@ -1998,6 +1998,58 @@ __global__ __launch_bounds__(NT) void k_correct(Dims d, const double *__restrict
     });
 }
 
+// Force of the fluid on the bodies: the momentum it exchanges with them
+// through the capacities (pressure on the cut cells' projected surface,
+// strain on the second-kind capacities), from the table of cut cells and
+// nodes.  One work-group; each thread sums a strided share of the rows and
+// the shares are added in a fixed order.
+constexpr int FT = 1024;
+__global__ __launch_bounds__(FT) void k_forces(const double *__restrict__ tab, int nfc, int nfn, int cap, int P,
+                                               const double *__restrict__ dinv, const double *__restrict__ pr,
+                                               const double *__restrict__ ux, const double *__restrict__ uy,
+                                               const double *__restrict__ dx, const double *__restrict__ dy,
+                                               double two_mu, double *__restrict__ out) {
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int e = threadIdx.x; e < nfc; e += FT) {
+        const double *r = tab + (size_t)e * FORCE_W;
+        const size_t k = (size_t)r[FC_J] * P + (size_t)r[FC_I];
+        const double p = dinv[k] > 0.0 ? pr[k] : 0.0;
+        v[0] += p * r[FC_WPX];
+        v[1] += p * r[FC_WPY];
+        const double sxx = r[FC_WXX] * (r[FC_BXX_E] * (ux[k] - dx[k]) - r[FC_BXX_W] * (ux[k - 1] - dx[k - 1]) +
+                                        r[FC_AXX] * (dx[k] - dx[k - 1]));
+        const double syy = r[FC_WYY] * (r[FC_BYY_N] * (uy[k] - dy[k]) - r[FC_BYY_S] * (uy[k - P] - dy[k - P]) +
+                                        r[FC_AYY] * (dy[k] - dy[k - P]));
+        v[2] += sxx * r[FC_WVX];
+        v[3] += syy * r[FC_WVY];
+    }
+    const double *tn = tab + (size_t)cap * FORCE_W;
+    for (int e = threadIdx.x; e < nfn; e += FT) {
+        const double *r = tn + (size_t)e * FORCE_W;
+        const size_t k = (size_t)r[FN_J] * P + (size_t)r[FN_I];
+        const double gx = r[FN_BXY_A] * (ux[k + P] - dx[k + P]) - r[FN_BXY_B] * (ux[k] - dx[k]) +
+                          r[FN_AXY] * (dx[k + P] - dx[k]);
+        const double gy = r[FN_BYX_R] * (uy[k + 1] - dy[k + 1]) - r[FN_BYX_L] * (uy[k] - dy[k]) +
+                          r[FN_AYX] * (dy[k + 1] - dy[k]);
+        v[2] += 0.5 * (r[FN_NXX] * gx + r[FN_NXY] * gy) * r[FN_WNX];
+        v[3] += 0.5 * (r[FN_NYX] * gx + r[FN_NYY] * gy) * r[FN_WNY];
+    }
+    __shared__ double red[4][FT];
+    for (int q = 0; q < 4; ++q) red[q][threadIdx.x] = v[q];
+    __syncthreads();
+    for (int w = FT / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            for (int q = 0; q < 4; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[0] = red[0][0];
+        out[1] = red[1][0];
+        out[2] = two_mu * red[2][0];
+        out[3] = two_mu * red[3][0];
+    }
+}
+
 struct DiagCoef {
     const double *ax, *ay, *het, *dinv, *vur, *vvr, *vu, *vv, *cx, *cy, *vinv;
 };
@@ -2223,6 +2275,10 @@ struct WsPlan {
     // PCW values (FP64)
     size_t cls_off, tab_off, tab32_off;
     int max_cls;
+    // force tables (cells, nodes: up to force_cap rows of FORCE_W each) and
+    // the four sums
+    size_t force_off;
+    int force_cap;
     size_t total;
 };
 
@@ -2271,6 +2327,11 @@ WsPlan plan(int nx, int ny, int precision) {
     off += align_up((size_t)w.max_cls * PCW * sizeof(double), 256);
     w.tab32_off = off;  // the same rows in float (precision 1)
     if (precision == 1) off += align_up((size_t)w.max_cls * PCW * sizeof(float), 256);
+    // the cut cells and nodes of the bodies: a few per cell of their outline,
+    // well within eight box perimeters
+    w.force_cap = 8 * (nx + ny) + 1024;
+    w.force_off = off;
+    off += align_up(((size_t)2 * w.force_cap * FORCE_W + 8) * sizeof(double), 256);
     w.total = off;
     return w;
 }
@@ -2325,6 +2386,10 @@ struct ccns_ctx {
     int *cls;
     double *tab;
     float *tab32;      // the table in float (precision 1), or null
+    // force on the bodies: table rows (nfc cells, then nfn nodes; nfc < 0:
+    // more cut cells than the workspace holds) and the four sums
+    int nfc, nfn;
+    double *ftab, *fsum;
     // optional kernel timing: start/stop events attached to sampled launches
     int timing;
     std::vector<hipEvent_t> evpool;
@@ -3463,6 +3528,28 @@ ccns_status create_ctx(const ccns_grid *grid, const ccns_params *params, const d
         destroy_ctx(c, false);
         return s;
     }
+    // force tables: kept only when they fit the workspace's share
+    c->ftab = (double *)(c->base + c->w.force_off);
+    c->fsum = c->ftab + (size_t)2 * c->w.force_cap * FORCE_W;
+    c->nfc = (int)(hc.fcell.size() / FORCE_W);
+    c->nfn = (int)(hc.fnode.size() / FORCE_W);
+    if (c->nfc > c->w.force_cap || c->nfn > c->w.force_cap) {
+        c->nfc = c->nfn = -1;
+    } else {
+        // (the host rows live until the synchronisation below)
+        hipError_t e1 = hipSuccess, e2 = hipSuccess;
+        if (c->nfc)
+            e1 = hipMemcpyAsync(c->ftab, hc.fcell.data(), hc.fcell.size() * sizeof(double), hipMemcpyHostToDevice,
+                                c->stream);
+        if (c->nfn)
+            e2 = hipMemcpyAsync(c->ftab + (size_t)c->w.force_cap * FORCE_W, hc.fnode.data(),
+                                hc.fnode.size() * sizeof(double), hipMemcpyHostToDevice, c->stream);
+        if (e1 != hipSuccess || e2 != hipSuccess) {
+            hipStreamSynchronize(c->stream);
+            destroy_ctx(c, false);
+            return CCNS_EDEVICE;
+        }
+    }
     set_cg(c, c->st_pred, params->pred_tol, params->pred_maxit, 0, hc.n_uact + hc.n_vact);
     // with outflow faces the pressure beyond them is held: not singular
     const int singular = hc.n_out == 0;
@@ -3624,6 +3711,17 @@ ccns_status ccns_timing(ccns_ctx *c, int enable, double *ms, long *count) {
 ccns_status ccns_diagnostics(ccns_ctx *c, ccns_step_info *info) {
     if (!c) return CCNS_EINVAL;
     return diag_dev(c, 0, info);
+}
+
+ccns_status ccns_forces(ccns_ctx *c, double *forces_host) {
+    if (!c || !forces_host) return fail(c, CCNS_EINVAL, "null argument");
+    if (c->nfc < 0) return fail(c, CCNS_ENOMEM, "more cut cells than the workspace's force table holds");
+    k_forces<<<1, FT, 0, c->stream>>>(c->ftab, c->nfc, c->nfn, c->w.force_cap, c->w.L.pitch, c->a[A_DINV], c->a[A_P],
+                                      c->a[A_UX], c->a[A_UY], c->a[A_DX], c->a[A_DY], 2.0 * c->prm.mu, c->fsum);
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipMemcpyAsync(forces_host, c->fsum, 4 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return CCNS_OK;
 }
 
 }  // extern "C"

@@ -42,7 +42,24 @@ struct HostCoef {
     int n_active = 0;                         // pressure unknowns
     int n_uact = 0, n_vact = 0;               // velocity unknowns
     int n_out = 0;                            // outflow faces the projection corrects
+    // force on the bodies: the cells and nodes whose capacities differ across
+    // them (the cut ones), FORCE_W values each (see ForceCell / ForceNode)
+    std::vector<double> fcell, fnode;
 };
+
+// Entries of the force tables (one row of FORCE_W doubles each).
+enum ForceCell {
+    FC_J, FC_I, FC_WPX, FC_WPY, FC_WVX, FC_WVY,          // weights of P and of the cell strains
+    FC_WXX, FC_BXX_E, FC_BXX_W, FC_AXX,                  // S_xx = WXX (B_E (U-D)_E - B_W (U-D)_W + AXX (D_E - D_W))
+    FC_WYY, FC_BYY_N, FC_BYY_S, FC_AYY
+};
+enum ForceNode {
+    FN_J, FN_I, FN_WNX, FN_WNY,                          // weights of the node strains S_x, S_y
+    FN_BXY_A, FN_BXY_B, FN_AXY,                          // g_x from the x-faces above and below
+    FN_BYX_R, FN_BYX_L, FN_AYX,                          // g_y from the y-faces right and left
+    FN_NXX, FN_NXY, FN_NYX, FN_NYY
+};
+constexpr int FORCE_W = 14;
 
 // Validates the inputs and derives every coefficient field (host, FP64).
 ccns_status prepare_coefficients(const ccns_grid &g, const ccns_params &prm, const double *caps,

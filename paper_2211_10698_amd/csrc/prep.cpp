@@ -241,7 +241,32 @@ ccns_status prepare_coefficients(const ccns_grid &g, const ccns_params &prm, con
                 o.hdy[k] = inv0(rt * Mv[k] + prm.mu * kd);
             }
         }
-    (void)Axx; (void)Axy; (void)Ayy; (void)Ayx;
+    // force on the bodies (the momentum exchanged through the capacities):
+    // the cells where A^x, A^y, B^xx or B^yy differ across the cell and the
+    // nodes off the box's walls where B^xy or B^yx differ across the node;
+    // everywhere else the terms cancel
+    o.fcell.clear();
+    o.fnode.clear();
+    for (int j = 1; j <= ny; ++j)
+        for (int i = 1; i <= nx; ++i) {
+            const size_t k = id(j, i), kw = k - 1, ks = k - W;
+            const double wpx = Ax[kw] - Ax[k], wpy = Ay[ks] - Ay[k];
+            const double wvx = Bxx[k] - Bxx[kw], wvy = Byy[k] - Byy[ks];
+            if (wpx == 0.0 && wpy == 0.0 && wvx == 0.0 && wvy == 0.0) continue;
+            const double row[FORCE_W] = {(double)j, (double)i, wpx, wpy, wvx, wvy, o.wxx[k], Bxx[k], Bxx[kw], Axx[k],
+                                         o.wyy[k], Byy[k], Byy[ks], Ayy[k]};
+            o.fcell.insert(o.fcell.end(), row, row + FORCE_W);
+        }
+    for (int j = 0; j <= ny; ++j)
+        for (int i = 0; i <= nx; ++i) {
+            const size_t k = id(j, i);
+            const double wnx = (j >= 1 && j <= ny - 1) ? Bxy[k + W] - Bxy[k] : 0.0;
+            const double wny = (i >= 1 && i <= nx - 1) ? Byx[k + 1] - Byx[k] : 0.0;
+            if (wnx == 0.0 && wny == 0.0) continue;
+            const double row[FORCE_W] = {(double)j, (double)i, wnx, wny, Bxy[k + W], Bxy[k], Axy[k], Byx[k + 1], Byx[k],
+                                         Ayx[k], o.nxx[k], o.nxy[k], o.nyx[k], o.nyy[k]};
+            o.fnode.insert(o.fnode.end(), row, row + FORCE_W);
+        }
     // constant Dirichlet contribution of the viscous term on the unknowns
     host_viscous(g, caps, o, o.utx.data(), o.uty.data(), o.vdx, o.vdy);
     for (size_t k = 0; k < n; ++k) {
