@@ -586,6 +586,12 @@ def main():
     }
     if div_max > 1e-8:
         out["warning"] = "divergence above 1e-8 in a timed step"
+    if case.bodies:
+        # drag and lift of the final state (after the timed region)
+        F = ctx.forces()
+        q = 0.5 * case.rho * case.u_inf ** 2 * case.ref_length
+        out["forces"] = {"cd": (F[0] + F[2]) / q, "cl": (F[1] + F[3]) / q, "pressure_x": F[0], "pressure_y": F[1],
+                         "viscous_x": F[2], "viscous_y": F[3], "time": case.tau * (args.warmup + args.steps)}
     if not args.no_cpu_baseline:
         # the oracle solves both systems with Jacobi-PCG: count the iterations
         # that algorithm needs in one step of this workload (an FP64 Jacobi

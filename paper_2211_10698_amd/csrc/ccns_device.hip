@@ -3719,8 +3719,10 @@ ccns_status ccns_forces(ccns_ctx *c, double *forces_host) {
     k_forces<<<1, FT, 0, c->stream>>>(c->ftab, c->nfc, c->nfn, c->w.force_cap, c->w.L.pitch, c->a[A_DINV], c->a[A_P],
                                       c->a[A_UX], c->a[A_UY], c->a[A_DX], c->a[A_DY], 2.0 * c->prm.mu, c->fsum);
     HIPCHK(c, hipGetLastError());
-    HIPCHK(c, hipMemcpyAsync(forces_host, c->fsum, 4 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    // through the context's own (pinned) read-back buffer, as every other read-back
+    HIPCHK(c, hipMemcpyAsync(c->h_outer, c->fsum, 4 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
+    std::memcpy(forces_host, c->h_outer, 4 * sizeof(double));
     return CCNS_OK;
 }
 

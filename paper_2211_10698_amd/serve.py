@@ -55,6 +55,9 @@ class Record:
     start: float = float("nan")
     completion: float = float("nan")
     div_rel_max: float = 0.0
+    # drag and lift coefficients of the final state (ccns_forces)
+    cd: float = float("nan")
+    cl: float = float("nan")
     status: int = ccns.OK
     note: str = ""
     fields: Optional[Dict[str, np.ndarray]] = None
@@ -112,13 +115,17 @@ class Server:
     """Continuous-batching server for simulation requests on one GPU."""
 
     def __init__(self, hbm_budget: Optional[int] = None, precision: int = 1, threads: int = 16,
-                 prep_workers: int = 4, keep_fields: bool = False, inputs=None, device_caps: bool = True):
+                 prep_workers: int = 4, keep_fields: bool = False, inputs=None, device_caps: bool = True,
+                 forces: bool = False):
         self.budget = hbm_budget if hbm_budget is not None else default_budget()
         self.precision = precision
         self.threads = threads
         self.prep_workers = prep_workers
         self.keep_fields = keep_fields
         self.device_caps = device_caps
+        # drag and lift of each request's final state (off by default: the
+        # served trace has not been run with it)
+        self.forces = forces
         # inputs(case) -> (Dx, Dy, ux_perturbation, uy_perturbation)
         self.inputs = inputs if inputs is not None else _seeded_inputs
         self.max_used = 0      # largest admitted footprint total seen by the last run
@@ -160,11 +167,13 @@ class Server:
         return ctx, stream, info, t_caps
 
     @staticmethod
-    def _run_steps(ctx, steps, clock):
+    def _run_steps(ctx, case, clock, forces=False):
         """Step worker: advances one simulation through all its steps (the GPU
         is shared with the other running simulations, each on its own
-        stream), stopping at the first failed solve.  Returns (start,
-        completion, div_rel_max, status, note)."""
+        stream), stopping at the first failed solve, then takes the drag and
+        lift coefficients of the final state.  Returns (start, completion,
+        div_rel_max, status, note, (cd, cl))."""
+        steps = case.steps
         start = clock()
         div, status, note = 0.0, ccns.OK, ""
         for n in range(steps):
@@ -178,7 +187,16 @@ class Server:
                             f"{si.inner_status} (first at sweep {si.inner_fail_sweep})")
             if status != ccns.OK:
                 break
-        return start, clock(), div, status, note
+        end = clock()
+        coef = (float("nan"), float("nan"))
+        if forces and case.bodies:
+            try:
+                F = ctx.forces()
+                q = 0.5 * case.rho * case.u_inf ** 2 * case.ref_length
+                coef = ((F[0] + F[2]) / q, (F[1] + F[3]) / q)
+            except ccns.CcnsError:
+                pass
+        return start, end, div, status, note, coef
 
     def run(self, requests: Sequence, log=None) -> List[Record]:
         """Serves the requests (objects with .case and .arrival, arrival in
@@ -226,10 +244,10 @@ class Server:
                     ctx, stream, info, r.caps_s = fut.result()
                     r.prepared = clock()
                     r.div_rel_max = info.div_rel
-                    running[step_pool.submit(self._run_steps, ctx, r.steps, clock)] = (r, ctx)
+                    running[step_pool.submit(self._run_steps, ctx, cases[r.index], clock, self.forces)] = (r, ctx)
                 for fut in [f for f in running if f.done()]:
                     r, ctx = running.pop(fut)
-                    r.start, r.completion, div, r.status, r.note = fut.result()
+                    r.start, r.completion, div, r.status, r.note, (r.cd, r.cl) = fut.result()
                     r.div_rel_max = max(r.div_rel_max, div)
                     if self.keep_fields:
                         r.fields = {n: ctx.get_field(f).cpu().numpy()
@@ -275,4 +293,6 @@ def summarize(recs: Sequence[Record], wall: float) -> dict:
         "wall_s": wall,
         "div_rel_max": float(max(r.div_rel_max for r in recs)),
         "statuses": sorted({int(r.status) for r in recs}),
+        "drag_coefficient_range": [float(np.nanmin([r.cd for r in recs])), float(np.nanmax([r.cd for r in recs]))]
+        if any(np.isfinite(r.cd) for r in recs) else None,
     }
