@@ -34,6 +34,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 import workloads as W  # noqa: E402
+from paper_2211_10698_amd import tune  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
@@ -275,7 +276,7 @@ def host_inputs(ccns, case):
     return caps, Dx, Dy, np.where(au, case.u_inf + px, Dx), np.where(av, py, Dy)
 
 
-def setup_context(ccns, case, precision, stream, host, coef_tables=0):
+def setup_context(ccns, case, precision, stream, host, coef_tables=0, mg_forms=True):
     """Context, initial field and initial projection of one simulation (set-up,
     outside any timed region)."""
     caps, Dx, Dy, ux0, uy0 = host
@@ -286,6 +287,8 @@ def setup_context(ccns, case, precision, stream, host, coef_tables=0):
     ctx.set_field(ccns.F_UX, ux0)
     ctx.set_field(ccns.F_UY, uy0)
     ctx.project()
+    if mg_forms:
+        tune.apply_cached(ctx, precision)
     return ctx
 
 
@@ -307,7 +310,8 @@ def run_batched(args):
     ctxs = []
     with cf.ThreadPoolExecutor(max_workers=8) as ex:
         for case, stream, host in zip(cases, streams, ex.map(lambda c: host_inputs(ccns, c), cases)):
-            ctxs.append(setup_context(ccns, case, prec, stream, host, 0 if args.coef_tables == "auto" else 1))
+            ctxs.append(setup_context(ccns, case, prec, stream, host, 0 if args.coef_tables == "auto" else 1,
+                                      args.mg_forms == "tuned"))
     torch.cuda.synchronize()
     cells = sum(c.grid.nx * c.grid.ny for c in cases)
     print(f"[bench] setup {time.perf_counter() - t_setup:.1f}s: {len(cases)} simulations, {cells} cells",
@@ -439,6 +443,9 @@ def main():
     ap.add_argument("--mass-floor", type=float, default=None,
                     help="small-volume floor theta (default: the workload's, 0.05); 0 is the paper's mass "
                          "matrix M = diag(V)")
+    ap.add_argument("--mg-forms", default="tuned", choices=["tuned", "default"],
+                    help="multigrid cycle kernel forms: the tuned ones cached for this GPU's level sizes "
+                         "(paper_2211_10698_amd/mg_forms.json), or the library's defaults")
     ap.add_argument("--coef-tables", default="auto", choices=["auto", "off"],
                     help="auto: the predictor CG reads its coefficients through the class table when it "
                          "fits (the library's default); off: from the coefficient arrays")
@@ -484,6 +491,7 @@ def main():
     ctx.set_field(ccns.F_UY, np.where(av, py, Dy))
     ctx.project()
     ncls = ctx.coef_classes()
+    forms = tune.apply_cached(ctx, 1 if mixed else 0) if args.mg_forms == "tuned" else 0
     setup_s = time.perf_counter() - t_setup
     print(f"[bench] setup {setup_s:.1f}s: {case.name} {g.nx}x{g.ny}", file=sys.stderr, flush=True)
 
@@ -553,7 +561,8 @@ def main():
         "config": {"workload": case.name, "nx": g.nx, "ny": g.ny, "re": case.re, "cfl": case.cfl,
                    "pcg_tol": case.pcg_tol, "pred_tol": 1e-12, "precond": "multigrid",
                    "precision": "fp32 inner + fp64 refinement, div_rel <= 1e-8" if mixed else "fp64",
-                   "coef_classes": ncls, "mass_floor": case.mass_floor},
+                   "coef_classes": ncls, "mass_floor": case.mass_floor,
+                   "mg_forms": {"word": forms, "levels": ctx.mg_levels()}},
         "div_rel_max": div_max,
         "cg_iters_per_step": n_cg,
         "pred_iters_per_step": float(np.mean([i["pred_iters"] for i in infos])),

@@ -191,11 +191,26 @@ ccns_status ccns_capacities_device(const ccns_grid *grid, const ccns_body *bodie
  *                 and no mean is removed.  The Dirichlet data of those faces
  *                 are then unused: the cells next to an outflow wall must be
  *                 uncut (CCNS_EINVAL otherwise), where the data cancel out of
- *                 every operator. */
+ *                 every operator.
+ *  mg_forms       kernel forms of the multigrid cycle's down- and up-sweep
+ *                 kernels, per cycle level (level 0 the finest): level l in
+ *                 bits 6l..6l+2 (down) and 6l+3..6l+5 (up), for l < 10:
+ *                 0 the default, 1 staged first sweep with the tile ring's
+ *                 operands in registers, 2 the same with them in LDS, 3 first
+ *                 sweep pointwise on 64 x 16 tiles, 4 the same on 64 x 4
+ *                 tiles (not for level 0's up-sweep, whose tiles fix the
+ *                 order of the preconditioner's statistics).  Every form
+ *                 computes the same values bit for bit; they differ in speed
+ *                 by level size (see ccns_mg_levels).
+ */
 #define CCNS_WALL_W 1
 #define CCNS_WALL_E 2
 #define CCNS_WALL_S 4
 #define CCNS_WALL_N 8
+#define CCNS_MG_FORM_STAGED 1
+#define CCNS_MG_FORM_STAGED_LDS 2
+#define CCNS_MG_FORM_PLAIN 3
+#define CCNS_MG_FORM_PLAIN_SHORT 4
 typedef struct {
     double rho, mu, tau, u_ref, gx, gy;
     double pcg_tol, pred_tol, div_tol;
@@ -207,6 +222,7 @@ typedef struct {
     double mass_floor;
     int coef_tables;
     int outflow;
+    unsigned long long mg_forms;
 } ccns_params;
 
 typedef struct ccns_ctx ccns_ctx;
@@ -331,7 +347,8 @@ typedef struct {
  * solves L phi = b on the pressure unknowns by CG with the context's
  * preconditioner (params.precond: Jacobi or the multigrid V-cycle; in
  * precision 1 inside the FP64 refinement loop), starting from the current
- * CCNS_F_PHI, after removing the mean of b.
+ * CCNS_F_PHI, after removing the mean of b where the problem is singular
+ * (no outflow wall).
  * b, phi: dense device arrays (phi may be NULL: the result stays in
  * CCNS_F_PHI).  Errors: CCNS_ENOTCONV, CCNS_EBREAKDOWN (outputs written). */
 ccns_status ccns_pressure_solve(ccns_ctx *ctx, const double *b, double *phi, ccns_solve_info *info);
@@ -383,6 +400,17 @@ ccns_status ccns_diagnostics(ccns_ctx *ctx, ccns_step_info *info);
  * Errors: CCNS_EINVAL (null argument), CCNS_ENOMEM (more cut cells or nodes
  * than the context's table holds: 8 (nx + ny) + 1024 each), CCNS_EDEVICE. */
 ccns_status ccns_forces(ccns_ctx *ctx, double *forces_host);
+
+/* Multigrid cycle kernel forms (see ccns_params.mg_forms), for tuning.
+ * ccns_set_mg_forms: the forms of the context's next cycles (0 restores the
+ * defaults); the results do not change.  Errors: CCNS_EINVAL (a field above
+ * 4, level 0's up-sweep in form 4, or bits above level 9).
+ * ccns_mg_levels: the number of cycle levels (levels with down- and
+ * up-sweep kernels, at most 10; 0 without the multigrid preconditioner); for
+ * the first `cap` of them writes the cells nx[l] x ny[l] and the forms in
+ * use, forms[l] = down | up << 3 (host arrays, caller-owned, may be NULL). */
+ccns_status ccns_set_mg_forms(ccns_ctx *ctx, unsigned long long forms);
+int ccns_mg_levels(const ccns_ctx *ctx, int *nx, int *ny, int *forms, int cap);
 
 /* Batches of independent simulations of any sizes (the ragged batches of
  * many uneven simulations that share one GPU).  A batch borrows contexts

@@ -44,7 +44,7 @@ class Params(C.Structure):
                 ("div_tol", C.c_double), ("pcg_maxit", C.c_int), ("pred_maxit", C.c_int),
                 ("precision", C.c_int), ("visc_form", C.c_int), ("poisson_weight", C.c_int),
                 ("precond", C.c_int), ("mass_floor", C.c_double), ("coef_tables", C.c_int),
-                ("outflow", C.c_int)]
+                ("outflow", C.c_int), ("mg_forms", C.c_ulonglong)]
 
 
 class SolveInfo(C.Structure):
@@ -119,6 +119,10 @@ def lib():
         L.ccns_predict.argtypes = [C.c_void_p, P(SolveInfo)]
         L.ccns_forces.restype = C.c_int
         L.ccns_forces.argtypes = [C.c_void_p, P(C.c_double)]
+        L.ccns_set_mg_forms.restype = C.c_int
+        L.ccns_set_mg_forms.argtypes = [C.c_void_p, C.c_ulonglong]
+        L.ccns_mg_levels.restype = C.c_int
+        L.ccns_mg_levels.argtypes = [C.c_void_p, P(C.c_int), P(C.c_int), P(C.c_int), C.c_int]
         L.ccns_timing.restype = C.c_int
         L.ccns_timing.argtypes = [C.c_void_p, C.c_int, P(C.c_double), P(C.c_long)]
         L.ccns_step.restype = C.c_int
@@ -137,8 +141,8 @@ EXPORTED = ("ccns_caps_count", "ccns_capacities", "ccns_capacities_scratch_bytes
             "ccns_workspace_bytes", "ccns_ctx_create", "ccns_ctx_create_static",
             "ccns_ctx_destroy", "ccns_last_error", "ccns_coef_classes", "ccns_field_set", "ccns_field_get", "ccns_apply",
             "ccns_pressure_solve", "ccns_project", "ccns_step", "ccns_predict", "ccns_correct",
-            "ccns_diagnostics", "ccns_forces", "ccns_timing", "ccns_batch_create", "ccns_batch_step",
-            "ccns_batch_destroy")
+            "ccns_diagnostics", "ccns_forces", "ccns_set_mg_forms", "ccns_mg_levels", "ccns_timing",
+            "ccns_batch_create", "ccns_batch_step", "ccns_batch_destroy")
 
 
 class CcnsError(RuntimeError):
@@ -210,14 +214,15 @@ WALL_BITS = {"W": 1, "E": 2, "S": 4, "N": 8}
 
 def make_params(rho, mu, tau, u_ref=1.0, pcg_tol=1e-10, pred_tol=1e-12, div_tol=1e-8, pcg_maxit=200000,
                 pred_maxit=500, precision=0, visc_form=0, poisson_weight=0, gx=0.0, gy=0.0,
-                precond=PRECOND_MG, mass_floor=0.05, coef_tables=0, outflow="") -> Params:
-    """outflow: the outflow walls as letters of "WESN" (or the C bitmask)."""
+                precond=PRECOND_MG, mass_floor=0.05, coef_tables=0, outflow="", mg_forms=0) -> Params:
+    """outflow: the outflow walls as letters of "WESN" (or the C bitmask);
+    mg_forms: the multigrid cycle's kernel forms (paper_2211_10698_amd.tune)."""
     if isinstance(outflow, str):
         if any(w not in "WESN" for w in outflow):
             raise ValueError(f"outflow walls {outflow!r}: letters of 'WESN'")
         outflow = sum(WALL_BITS[w] for w in set(outflow))
     return Params(rho, mu, tau, u_ref, gx, gy, pcg_tol, pred_tol, div_tol, pcg_maxit, pred_maxit, precision,
-                  visc_form, poisson_weight, precond, mass_floor, coef_tables, outflow)
+                  visc_form, poisson_weight, precond, mass_floor, coef_tables, outflow, mg_forms)
 
 
 STATIC_WORKSPACE_BYTES = 64 << 20
@@ -390,6 +395,15 @@ class Context:
         out = (C.c_double * 4)()
         self._chk(lib().ccns_forces(self.h, out), "forces")
         return tuple(out)
+
+    def set_mg_forms(self, forms):
+        self._chk(lib().ccns_set_mg_forms(self.h, int(forms)), "set_mg_forms")
+
+    def mg_levels(self):
+        """[(nx, ny, down form, up form)] of the multigrid cycle levels."""
+        nx, ny, fm = (C.c_int * 10)(), (C.c_int * 10)(), (C.c_int * 10)()
+        n = lib().ccns_mg_levels(self.h, nx, ny, fm, 10)
+        return [(nx[k], ny[k], fm[k] & 7, fm[k] >> 3) for k in range(n)]
 
 
 class Batch:

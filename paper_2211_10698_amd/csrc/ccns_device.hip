@@ -444,6 +444,13 @@ constexpr int MTY = 16;
 constexpr int MTY_SMALL = 4;
 constexpr int MG_SMALL_GROUPS = 256;
 
+// Kernel forms of a cycle level's down- and up-sweep kernels (the values of
+// ccns_params.mg_forms): staged first sweep with the ring's operands in
+// registers; the same with every operand of the ring in LDS; the first
+// sweep formed pointwise on 64 x MTY tiles; the same on 64 x MTY_SMALL tiles.
+enum MgForm { MGF_AUTO = 0, MGF_STAGED = 1, MGF_STAGED_LDS = 2, MGF_PLAIN = 3, MGF_PLAIN_SHORT = 4 };
+constexpr int MG_FORM_BITS = 3, MG_FORM_LEVELS = 10;  // 6 bits (down, up) per level in a 64-bit word
+
 struct MgTile {
     int c0, r0;  // first real cell of the tile
 };
@@ -676,6 +683,193 @@ __global__ __launch_bounds__(NT) void k_mg_up_staged(int nx, int ny, int P, int 
             if (in) z[(size_t)j * P + i] = zv;
             if (STATS && in) {
                 const double bd = o.b[m], zd = zv;
+                v[0] += bd * zd;
+                v[1] += zd;
+                v[2] += bd;
+                v[3] += bd * bd;
+            }
+        }
+    }
+    if (STATS) put_partials<4>(v, pout, nblk);
+}
+
+// The staged forms with every operand of the tile's two-cell ring (1/diag,
+// b, c^x, c^y) loaded once into LDS (64 KB in FP64: two work-groups per
+// compute unit): the ring sweep and the tile phase read their stencil
+// weights from there instead of loading them again.  Same arithmetic, in the
+// same order, as the forms above.
+template <class T>
+__device__ inline void mg_stage_ops(T (*sd)[MW], T (*sb)[MW], T (*se)[MW], T (*sn)[MW], const PoisCoefT<T> &c,
+                                    const T *b, int nx, int ny, int P, const MgTile &t, T dv[MI1], T bv[MI1]) {
+    T ev[MI1], nv[MI1];
+#pragma unroll
+    for (int q = 0; q < MI1; ++q) {
+        const int e = threadIdx.x + q * NT;
+        const int ly = e / MW, lx = e - ly * MW;
+        const int j = t.r0 - MH + ly, i = t.c0 - MH + lx;
+        const bool in = (e < MS1) && (j >= 0) && (j <= ny + 1) && (i >= 0) && (i <= nx + 1);
+        const size_t k = in ? (size_t)j * P + i : 0;
+        dv[q] = c.dinv[k];
+        bv[q] = b[k];
+        ev[q] = c.cx[k];
+        nv[q] = c.cy[k];
+    }
+#pragma unroll
+    for (int q = 0; q < MI1; ++q) {
+        const int e = threadIdx.x + q * NT;
+        if (e < MS1) {
+            const int ly = e / MW, lx = e - ly * MW;
+            const int j = t.r0 - MH + ly, i = t.c0 - MH + lx;
+            const bool in = (j >= 0) && (j <= ny + 1) && (i >= 0) && (i <= nx + 1);
+            sd[ly][lx] = in ? dv[q] : (T)0;
+            sb[ly][lx] = in ? bv[q] : (T)0;
+            se[ly][lx] = in ? ev[q] : (T)0;
+            sn[ly][lx] = in ? nv[q] : (T)0;
+        }
+    }
+}
+
+// The sweep of mg_ring_sweep with the weights read from the staged arrays.
+template <class T>
+__device__ inline void mg_ring_sweep_lds(const T (*sd)[MW], const T (*sb)[MW], const T (*se)[MW], const T (*sn)[MW],
+                                         const T (*s1)[MW], T (*s2)[TX + 2], int nx, int ny, const MgTile &t,
+                                         T omega) {
+#pragma unroll
+    for (int q = 0; q < MI2; ++q) {
+        const int e = threadIdx.x + q * NT;
+        if (e < MS2) {
+            const int ly = e / (TX + 2), lx = e - ly * (TX + 2);
+            const int j = t.r0 - 1 + ly, i = t.c0 - 1 + lx;
+            const bool in = (j >= 1) && (j <= ny) && (i >= 1) && (i <= nx);
+            const int y = ly + 1, x = lx + 1;  // position in the two-ring arrays
+            const T ce = se[y][x], cw = se[y][x - 1], cn = sn[y][x], cs = sn[y - 1][x], dv = sd[y][x];
+            const T xv = s1[y][x];
+            const T Ax = (ce + cw + cn + cs) * xv - ce * s1[y][x + 1] - cw * s1[y][x - 1] - cn * s1[y + 1][x] -
+                         cs * s1[y - 1][x];
+            s2[ly][lx] = (in && dv > (T)0) ? xv + omega * dv * (sb[y][x] - Ax) : (T)0;
+        }
+    }
+}
+
+template <class T>
+__global__ __launch_bounds__(NT) void k_mg_down_lds(int nx, int ny, int P, int gx, PoisCoefT<T> c,
+                                                    const T *__restrict__ b, T *__restrict__ x2out, int Pc, int nxc,
+                                                    int nyc, const T *__restrict__ dinvc, T *__restrict__ bc,
+                                                    const int *done) {
+    if (*done) return;
+    __shared__ T sd[MHt][MW], sb[MHt][MW], se[MHt][MW], sn[MHt][MW];
+    __shared__ T s1[MHt][MW];            // first sweep; then the residual on the tile
+    __shared__ T s2[MTY + 2][TX + 2];    // second sweep on the 1-ring region
+    const MgTile t = mg_tile(gx);
+    if (t.r0 > ny || t.c0 > nx) return;
+    {
+        T dv[MI1], bv[MI1];
+        mg_stage_ops<T>(sd, sb, se, sn, c, b, nx, ny, P, t, dv, bv);
+#pragma unroll
+        for (int q = 0; q < MI1; ++q) {
+            const int e = threadIdx.x + q * NT;
+            if (e < MS1) {
+                const int ly = e / MW, lx = e - ly * MW;
+                const int j = t.r0 - MH + ly, i = t.c0 - MH + lx;
+                const bool in = (j >= 0) && (j <= ny + 1) && (i >= 0) && (i <= nx + 1);
+                s1[ly][lx] = (in && dv[q] > (T)0) ? (T)MG_W1 * dv[q] * bv[q] : (T)0;
+            }
+        }
+    }
+    // one coarse cell per thread for the restriction: 32 x 8 coarse cells per tile
+    const int cxl = threadIdx.x & 31, cyl = threadIdx.x >> 5;
+    const int I = (t.c0 + 1) / 2 + cxl, J = (t.r0 + 1) / 2 + cyl;
+    const bool cin = (I <= nxc) && (J <= nyc);
+    const size_t kc = cin ? (size_t)J * Pc + I : 0;
+    const T dcv = dinvc[kc];
+    __syncthreads();
+    mg_ring_sweep_lds<T>(sd, sb, se, sn, s1, s2, nx, ny, t, (T)MG_W2);
+    __syncthreads();
+    T (*sr)[TX] = reinterpret_cast<T (*)[TX]>(&s1[0][0]);
+    {
+        const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+#pragma unroll
+        for (int m = 0; m < MTY / 4; ++m) {
+            const int ly = ty + 4 * m;
+            const int j = t.r0 + ly, i = t.c0 + tx;
+            const bool in = (j <= ny) && (i <= nx);
+            const int y = ly + 1, x = tx + 1;          // in s2
+            const int Y = ly + MH, X = tx + MH;        // in the two-ring arrays
+            const T e = se[Y][X], w = se[Y][X - 1], n = sn[Y][X], so = sn[Y - 1][X];
+            const T xv = s2[y][x];
+            const T Ax = (e + w + n + so) * xv - e * s2[y][x + 1] - w * s2[y][x - 1] - n * s2[y + 1][x] -
+                         so * s2[y - 1][x];
+            sr[ly][tx] = (in && sd[Y][X] > (T)0) ? sb[Y][X] - Ax : (T)0;
+            if (in) x2out[(size_t)j * P + i] = xv;
+        }
+    }
+    __syncthreads();
+    if (cin) {
+        const T sum = (sr[2 * cyl][2 * cxl] + sr[2 * cyl][2 * cxl + 1]) +
+                      (sr[2 * cyl + 1][2 * cxl] + sr[2 * cyl + 1][2 * cxl + 1]);
+        bc[kc] = dcv > (T)0 ? sum : (T)0;
+    }
+}
+
+template <class T, bool STATS>
+__global__ __launch_bounds__(NT) void k_mg_up_lds(int nx, int ny, int P, int gx, PoisCoefT<T> c, const T *__restrict__ b,
+                                                  const T *__restrict__ x2, const T *__restrict__ xc, int Pc,
+                                                  T *__restrict__ z, double *pout, int nblk, const int *done) {
+    if (*done) return;
+    __shared__ T sd[MHt][MW], sb[MHt][MW], se[MHt][MW], sn[MHt][MW];
+    __shared__ T s1[MHt][MW];
+    __shared__ T s2[MTY + 2][TX + 2];
+    const MgTile t = mg_tile(gx);
+    double v[4] = {0, 0, 0, 0};
+    const bool live = !(t.r0 > ny || t.c0 > nx);
+    if (live) {
+        T xv[MI1], ec[MI1];
+#pragma unroll
+        for (int q = 0; q < MI1; ++q) {
+            const int e = threadIdx.x + q * NT;
+            const int ly = e / MW, lx = e - ly * MW;
+            const int j = t.r0 - MH + ly, i = t.c0 - MH + lx;
+            const bool in = (e < MS1) && (j >= 1) && (j <= ny) && (i >= 1) && (i <= nx);
+            const size_t k = in ? (size_t)j * P + i : 0;
+            const size_t kc = in ? (size_t)((j + 1) >> 1) * Pc + ((i + 1) >> 1) : 0;
+            xv[q] = x2[k];
+            ec[q] = xc[kc];
+        }
+        T dv[MI1], bv[MI1];
+        mg_stage_ops<T>(sd, sb, se, sn, c, b, nx, ny, P, t, dv, bv);
+#pragma unroll
+        for (int q = 0; q < MI1; ++q) {
+            const int e = threadIdx.x + q * NT;
+            if (e < MS1) {
+                const int ly = e / MW, lx = e - ly * MW;
+                const int j = t.r0 - MH + ly, i = t.c0 - MH + lx;
+                const bool in = (j >= 1) && (j <= ny) && (i >= 1) && (i <= nx);
+                s1[ly][lx] = (in && dv[q] > (T)0) ? xv[q] + (T)MG_CGC * ec[q] : (T)0;
+            }
+        }
+        __syncthreads();
+        mg_ring_sweep_lds<T>(sd, sb, se, sn, s1, s2, nx, ny, t, (T)MG_W1);
+    } else {
+        __syncthreads();
+    }
+    __syncthreads();
+    if (live) {
+        const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+#pragma unroll
+        for (int m = 0; m < MTY / 4; ++m) {
+            const int ly = ty + 4 * m;
+            const int j = t.r0 + ly, i = t.c0 + tx;
+            const bool in = (j <= ny) && (i <= nx);
+            const int y = ly + 1, x = tx + 1;
+            const int Y = ly + MH, X = tx + MH;
+            const T e = se[Y][X], w = se[Y][X - 1], n = sn[Y][X], so = sn[Y - 1][X], dd = sd[Y][X], bb = sb[Y][X];
+            const T xv = s2[y][x];
+            const T Ax = (e + w + n + so) * xv - e * s2[y][x + 1] - w * s2[y][x - 1] - n * s2[y + 1][x] -
+                         so * s2[y - 1][x];
+            const T zv = (in && dd > (T)0) ? xv + (T)MG_W2 * dd * (bb - Ax) : (T)0;
+            if (in) z[(size_t)j * P + i] = zv;
+            if (STATS && in) {
+                const double bd = bb, zd = zv;
                 v[0] += bd * zd;
                 v[1] += zd;
                 v[2] += bd;
@@ -2390,6 +2584,8 @@ struct ccns_ctx {
     // more cut cells than the workspace holds) and the four sums
     int nfc, nfn;
     double *ftab, *fsum;
+    // kernel form of each cycle level: [FP64][down, up][level]
+    unsigned char mgf[2][2][16];
     // optional kernel timing: start/stop events attached to sampled launches
     int timing;
     std::vector<hipEvent_t> evpool;
@@ -2864,6 +3060,48 @@ size_t tail_start(const std::vector<ccns_ctx::LevelT<T>> &mg) {
     return mg.size() - 1;
 }
 
+// The cycle levels (those with down- and up-sweep kernels, above the
+// LDS-resident coarse end) of a hierarchy.
+template <class T>
+size_t cycle_levels(const std::vector<ccns_ctx::LevelT<T>> &mg) {
+    return mg.size() > 1 ? tail_start(mg) : 0;
+}
+
+// The finest level's up-sweep writes the statistics of z per work-group, so
+// its tiles fix the order of those sums: it keeps 64 x MTY tiles (forms 1-3),
+// and every form then gives the same bits.
+bool mg_forms_valid(unsigned long long forms) {
+    for (int l = 0; l < MG_FORM_LEVELS; ++l)
+        for (int h = 0; h < 2; ++h)
+            if (((forms >> (2 * MG_FORM_BITS * l + MG_FORM_BITS * h)) & 7u) > MGF_PLAIN_SHORT) return false;
+    if (((forms >> MG_FORM_BITS) & 7u) == MGF_PLAIN_SHORT) return false;
+    return forms >> (2 * MG_FORM_BITS * MG_FORM_LEVELS) == 0;
+}
+
+// Each level's forms: the requested ones, and where none is given (0) the
+// default: below the finest level, 64 x MTY_SMALL tiles where 64 x MTY ones
+// would give fewer than MG_SMALL_GROUPS work-groups; otherwise the staged
+// forms, except the FP32 way down, which is faster pointwise at every level.
+template <class T>
+void resolve_mg_forms(ccns_ctx *c, const std::vector<ccns_ctx::LevelT<T>> &mg, unsigned long long forms) {
+    const int dbl = sizeof(T) == 8;
+    for (size_t l = 0; l < 16; ++l) {
+        int fd = MGF_AUTO, fu = MGF_AUTO;
+        if (l < (size_t)MG_FORM_LEVELS) {
+            fd = (int)((forms >> (2 * MG_FORM_BITS * l)) & 7u);
+            fu = (int)((forms >> (2 * MG_FORM_BITS * l + MG_FORM_BITS)) & 7u);
+        }
+        if (l < mg.size()) {
+            const int gx = (mg[l].L.nx + TX - 1) / TX;
+            const bool small = l >= 1 && gx * ((mg[l].L.ny + MTY - 1) / MTY) < MG_SMALL_GROUPS;
+            if (fd == MGF_AUTO) fd = small ? MGF_PLAIN_SHORT : (dbl ? MGF_STAGED : MGF_PLAIN);
+            if (fu == MGF_AUTO) fu = small ? MGF_PLAIN_SHORT : MGF_STAGED;
+        }
+        c->mgf[dbl][0][l] = (unsigned char)fd;
+        c->mgf[dbl][1][l] = (unsigned char)fu;
+    }
+}
+
 // z = V(b) on level l of a hierarchy; returns the array holding the result.
 // On level 0 the last kernel also writes the residual statistics, reduced to
 // one group in PB_MG.  Every kernel returns at once when *done is set (a
@@ -2902,36 +3140,58 @@ T *vcycle(ccns_ctx *c, std::vector<ccns_ctx::LevelT<T>> &mg, size_t l, const T *
     }
     PoisCoefT<T> pc{L.cx, L.cy, L.dinv};
     const int gx = (L.L.nx + TX - 1) / TX;
-    // below the finest level, short tiles where tall ones would leave compute
-    // units idle
-    const bool small = l >= 1 && gx * ((L.L.ny + MTY - 1) / MTY) < MG_SMALL_GROUPS;
-    const int ty = small ? MTY_SMALL : MTY;
-    const int gy = (L.L.ny + ty - 1) / ty;
-    const int nb = ((gx * gy + 7) / 8) * 8;
     ccns_ctx::LevelT<T> &C = mg[l + 1];
-    // levels with tall tiles in the staged forms (measured: faster on the way
-    // down in FP64 and on the way up in both precisions; the FP32 way down is
-    // faster in the latency form at every level)
-    if (!small && sizeof(T) == 8)
-        k_mg_down_staged<T><<<nb, NT, 0, s>>>(L.L.nx, L.L.ny, L.L.pitch, gx, pc, b, L.x, C.L.pitch, C.L.nx, C.L.ny,
-                                              C.dinv, C.b, done);
-    else if (small)
-        k_mg_down<T, MTY_SMALL><<<nb, NT, 0, s>>>(L.L.nx, L.L.ny, L.L.pitch, gx, pc, b, L.x, C.L.pitch, C.L.nx,
-                                                  C.L.ny, C.dinv, C.b, done);
-    else
-        k_mg_down<T><<<nb, NT, 0, s>>>(L.L.nx, L.L.ny, L.L.pitch, gx, pc, b, L.x, C.L.pitch, C.L.nx, C.L.ny,
-                                       C.dinv, C.b, done);
+    const int fd = c->mgf[sizeof(T) == 8][0][l], fu = c->mgf[sizeof(T) == 8][1][l];
+    auto blocks = [&](int form) {
+        const int ty = form == MGF_PLAIN_SHORT ? MTY_SMALL : MTY;
+        return ((gx * ((L.L.ny + ty - 1) / ty) + 7) / 8) * 8;
+    };
+    const int nbd = blocks(fd), nbu = blocks(fu);
+    switch (fd) {
+    case MGF_STAGED:
+        k_mg_down_staged<T><<<nbd, NT, 0, s>>>(L.L.nx, L.L.ny, L.L.pitch, gx, pc, b, L.x, C.L.pitch, C.L.nx,
+                                               C.L.ny, C.dinv, C.b, done);
+        break;
+    case MGF_STAGED_LDS:
+        k_mg_down_lds<T><<<nbd, NT, 0, s>>>(L.L.nx, L.L.ny, L.L.pitch, gx, pc, b, L.x, C.L.pitch, C.L.nx, C.L.ny,
+                                            C.dinv, C.b, done);
+        break;
+    case MGF_PLAIN:
+        k_mg_down<T><<<nbd, NT, 0, s>>>(L.L.nx, L.L.ny, L.L.pitch, gx, pc, b, L.x, C.L.pitch, C.L.nx, C.L.ny,
+                                        C.dinv, C.b, done);
+        break;
+    default:
+        k_mg_down<T, MTY_SMALL><<<nbd, NT, 0, s>>>(L.L.nx, L.L.ny, L.L.pitch, gx, pc, b, L.x, C.L.pitch, C.L.nx,
+                                                   C.L.ny, C.dinv, C.b, done);
+    }
     const T *xc = vcycle<T>(c, mg, l + 1, C.b, done);
+    // on level 0 the up-sweep also writes the statistics of z, reduced to PB_MG
+    auto up = [&](auto stats) {
+        constexpr bool S = decltype(stats)::value;
+        double *po = S ? c->part[PB_UPD] : nullptr;
+        switch (fu) {
+        case MGF_STAGED:
+            k_mg_up_staged<T, S><<<nbu, NT, 0, s>>>(L.L.nx, L.L.ny, L.L.pitch, gx, pc, b, L.x, xc, C.L.pitch, L.xt,
+                                                    po, nbu, done);
+            break;
+        case MGF_STAGED_LDS:
+            k_mg_up_lds<T, S><<<nbu, NT, 0, s>>>(L.L.nx, L.L.ny, L.L.pitch, gx, pc, b, L.x, xc, C.L.pitch, L.xt, po,
+                                                 nbu, done);
+            break;
+        case MGF_PLAIN:
+            k_mg_up<T, S><<<nbu, NT, 0, s>>>(L.L.nx, L.L.ny, L.L.pitch, gx, pc, b, L.x, xc, C.L.pitch, L.xt, po,
+                                             nbu, done);
+            break;
+        default:
+            k_mg_up<T, S, MTY_SMALL><<<nbu, NT, 0, s>>>(L.L.nx, L.L.ny, L.L.pitch, gx, pc, b, L.x, xc, C.L.pitch,
+                                                        L.xt, po, nbu, done);
+        }
+    };
     if (l == 0) {
-        k_mg_up_staged<T, true><<<nb, NT, 0, s>>>(L.L.nx, L.L.ny, L.L.pitch, gx, pc, b, L.x, xc, C.L.pitch, L.xt,
-                                                  c->part[PB_UPD], nb, done);
-        k_reduce_partials<4><<<1, NT, 0, s>>>(c->part[PB_UPD], nb, c->part[PB_MG]);
-    } else if (!small) {
-        k_mg_up_staged<T, false><<<nb, NT, 0, s>>>(L.L.nx, L.L.ny, L.L.pitch, gx, pc, b, L.x, xc, C.L.pitch, L.xt,
-                                                   nullptr, nb, done);
+        up(std::true_type{});
+        k_reduce_partials<4><<<1, NT, 0, s>>>(c->part[PB_UPD], nbu, c->part[PB_MG]);
     } else {
-        k_mg_up<T, false, MTY_SMALL><<<nb, NT, 0, s>>>(L.L.nx, L.L.ny, L.L.pitch, gx, pc, b, L.x, xc, C.L.pitch,
-                                                       L.xt, nullptr, nb, done);
+        up(std::false_type{});
     }
     return L.xt;
 }
@@ -3397,7 +3657,8 @@ ccns_status create_ctx(const ccns_grid *grid, const ccns_params *params, const d
     *out = nullptr;
     if (!grid || !params || !caps_host || !dirichlet_host || !dev_workspace) return CCNS_EINVAL;
     if (params->precision < 0 || params->precision > 1 || params->precond < 0 || params->precond > 1 ||
-        params->coef_tables < 0 || params->coef_tables > 1 || params->outflow < 0 || params->outflow > 15)
+        params->coef_tables < 0 || params->coef_tables > 1 || params->outflow < 0 || params->outflow > 15 ||
+        !mg_forms_valid(params->mg_forms))
         return CCNS_EINVAL;
     ccns_ctx *c = new (std::nothrow) ccns_ctx();
     if (!c) return CCNS_ENOMEM;
@@ -3524,6 +3785,8 @@ ccns_status create_ctx(const ccns_grid *grid, const ccns_params *params, const d
         destroy_ctx(c, false);
         return s;
     }
+    resolve_mg_forms<double>(c, c->mg, params->mg_forms);
+    resolve_mg_forms<float>(c, c->mg32, params->mg_forms);
     if ((s = pred_classes(c, hc)) != CCNS_OK) {
         destroy_ctx(c, false);
         return s;
@@ -3545,7 +3808,7 @@ ccns_status create_ctx(const ccns_grid *grid, const ccns_params *params, const d
             e2 = hipMemcpyAsync(c->ftab + (size_t)c->w.force_cap * FORCE_W, hc.fnode.data(),
                                 hc.fnode.size() * sizeof(double), hipMemcpyHostToDevice, c->stream);
         if (e1 != hipSuccess || e2 != hipSuccess) {
-            hipStreamSynchronize(c->stream);
+            (void)hipStreamSynchronize(c->stream);
             destroy_ctx(c, false);
             return CCNS_EDEVICE;
         }
@@ -3724,6 +3987,26 @@ ccns_status ccns_forces(ccns_ctx *c, double *forces_host) {
     HIPCHK(c, hipStreamSynchronize(c->stream));
     std::memcpy(forces_host, c->h_outer, 4 * sizeof(double));
     return CCNS_OK;
+}
+
+ccns_status ccns_set_mg_forms(ccns_ctx *c, unsigned long long forms) {
+    if (!c || !mg_forms_valid(forms)) return fail(c, CCNS_EINVAL, "bad multigrid forms");
+    c->prm.mg_forms = forms;
+    resolve_mg_forms<double>(c, c->mg, forms);
+    resolve_mg_forms<float>(c, c->mg32, forms);
+    return CCNS_OK;
+}
+
+int ccns_mg_levels(const ccns_ctx *c, int *nx, int *ny, int *forms, int cap) {
+    if (!c || c->prm.precond != 1) return 0;
+    const int dbl = c->prm.precision == 1 ? 0 : 1;
+    const int n = (int)std::min<size_t>(dbl ? cycle_levels(c->mg) : cycle_levels(c->mg32), MG_FORM_LEVELS);
+    for (int l = 0; l < n && l < cap; ++l) {
+        if (nx) nx[l] = c->mg[l].L.nx;
+        if (ny) ny[l] = c->mg[l].L.ny;
+        if (forms) forms[l] = c->mgf[dbl][0][l] | (c->mgf[dbl][1][l] << MG_FORM_BITS);
+    }
+    return n;
 }
 
 }  // extern "C"

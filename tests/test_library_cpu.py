@@ -50,7 +50,9 @@ def test_argument_validation_without_gpu():
     caps = np.zeros(L.ccns_caps_count(C.byref(g)))
     dir2 = np.zeros(2 * 10 * 10)
     for bad_p in (ccns.make_params(1.0, 0.01, 0.01, precision=2), ccns.make_params(1.0, 0.01, 0.01, precond=5),
-                  ccns.make_params(1.0, 0.01, 0.01, coef_tables=2), ccns.make_params(1.0, 0.01, 0.01, outflow=16)):
+                  ccns.make_params(1.0, 0.01, 0.01, coef_tables=2), ccns.make_params(1.0, 0.01, 0.01, outflow=16),
+                  ccns.make_params(1.0, 0.01, 0.01, mg_forms=5), ccns.make_params(1.0, 0.01, 0.01, mg_forms=1 << 60),
+                  ccns.make_params(1.0, 0.01, 0.01, mg_forms=4 << 3)):
         assert L.ccns_ctx_create(C.byref(g), C.byref(bad_p), caps.ctypes.data, dir2.ctypes.data,
                                  C.c_void_p(256), 1 << 30, None, C.byref(h)) == ccns.EINVAL
     # batches: empty, NULL member, repeated member (checked before any member is read)
@@ -132,3 +134,34 @@ def test_library_capacities_on_a_stretched_mesh():
         gc.xf = (C.c_double * len(xf))(*xf)
         out = np.zeros(L.ccns_caps_count(C.byref(gc)))
         assert L.ccns_capacities(C.byref(gc), None, 0, ccns.LEVELSET_FN(), None, out.ctypes.data) == ccns.EINVAL
+
+
+def test_multigrid_form_words_and_cache():
+    """The tuner's form words pack and unpack (3 bits per sweep and level),
+    and the committed cache holds forms 1-4 per device, precision and level
+    size."""
+    import json
+    from paper_2211_10698_amd import tune
+    pairs = [(2, 2), (1, 1), (3, 1), (4, 4)]
+    w = tune.pack(pairs)
+    assert tune.unpack(w, 4) == pairs and w < 1 << 24
+    with pytest.raises(ValueError):
+        tune.pack([(5, 1)])
+    with pytest.raises(ValueError):
+        tune.pack([(1, 4)])
+    cache = json.load(open(tune.CACHE))
+    assert cache
+    for dev, per in cache.items():
+        assert set(per) <= {"f64", "f32"}
+        for prec, table in per.items():
+            for size, forms in table.items():
+                nx, ny = (int(v) for v in size.split("x"))
+                assert nx > 0 and ny > 0 and len(forms) == 2 and all(1 <= f <= 4 for f in forms)
+    # lookups by level size; missing levels keep the defaults (0)
+    dev = next(iter(cache))
+    prec = next(iter(cache[dev]))
+    size = next(iter(cache[dev][prec]))
+    nx, ny = (int(v) for v in size.split("x"))
+    p = 1 if prec == "f32" else 0
+    w = tune.lookup([(nx, ny), (3, 3)], p, dev, cache)
+    assert tune.unpack(w, 2) == [tuple(cache[dev][prec][size]), (0, 0)]
