@@ -67,6 +67,7 @@ WORKLOADS = {
     "naca0012_4096x2048": W.naca_4096,
     "channel_cylinder_2048x1024": W.channel_cylinder_2048,
     "cylinder_64": W.cylinder_64,
+    "paper_cylinder_2048x1024": W.paper_cylinder,
     "batched_cylinders_256": None,   # ragged batch, see run_batched
     "serving_trace": None,           # served requests, see run_serving
 }
@@ -215,7 +216,7 @@ def cpu_baseline(case, caps_arr, n_pred, n_cg, iters_sample=5):
     names = ("V", "Ax", "Ay", "Bx", "By", "Wx", "Wy", "Vu", "Axx", "Axy", "Bxx", "Bxy", "Wxx", "Wxy",
              "Vv", "Ayy", "Ayx", "Byy", "Byx", "Wyy", "Wyx")
     caps = {k: caps_arr[i] for i, k in enumerate(names)}
-    pr = derived.prepare(caps, g.nx, g.ny, vol_floor=case.mass_floor * g.hx * g.hy)
+    pr = derived.prepare(caps, g.nx, g.ny, vol_floor=case.mass_floor * g.hx * g.hy, outflow=case.outflow)
     Dx, Dy = W.dirichlet(case)
     prm = pmii.Params(rho=case.rho, mu=case.mu, tau=case.tau, pcg_tol=case.pcg_tol)
     st = pmii.Stepper(pr, prm, Dx, Dy, min(g.hx, g.hy), jacobi=False)
@@ -232,7 +233,8 @@ def cpu_baseline(case, caps_arr, n_pred, n_cg, iters_sample=5):
     t2 = time.perf_counter()
     b = st.poisson_rhs(s0.Ux, s0.Uy)
     t3 = time.perf_counter()
-    phi, itc, _, _ = solvers.pcg(st.apply_A, -b, s0.Phi, st.Pdinv, pr.act_p, 0.0, iters_sample, zero_mean=True)
+    phi, itc, _, _ = solvers.pcg(st.apply_A, -b, s0.Phi, st.Pdinv, pr.act_p, 0.0, iters_sample,
+                                 zero_mean=pr.singular)
     t4 = time.perf_counter()
     ux, uy = st.correct(s0.Ux, s0.Uy, phi)
     st.pressure_update(s0.P, phi)
@@ -481,7 +483,8 @@ def main():
     mixed = args.precision == "mixed"
     params = ccns.make_params(case.rho, case.mu, case.tau, u_ref=case.u_inf, pcg_tol=case.pcg_tol,
                               pred_tol=1e-12, precision=1 if mixed else 0, div_tol=1e-8,
-                              mass_floor=case.mass_floor, coef_tables=0 if args.coef_tables == "auto" else 1)
+                              mass_floor=case.mass_floor, coef_tables=0 if args.coef_tables == "auto" else 1,
+                              outflow=case.outflow)
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
     ctx = ccns.Context(g, params, caps, Dx, Dy, stream=stream)
@@ -607,7 +610,8 @@ def main():
         # context of the library stepped once from the current state: same
         # algorithm as the oracle), to scale the oracle's timed sample
         pj = ccns.make_params(case.rho, case.mu, case.tau, u_ref=case.u_inf, pcg_tol=case.pcg_tol,
-                              pred_tol=1e-12, precond=ccns.PRECOND_JACOBI, mass_floor=case.mass_floor)
+                              pred_tol=1e-12, precond=ccns.PRECOND_JACOBI, mass_floor=case.mass_floor,
+                              outflow=case.outflow)
         cj = ccns.Context(g, pj, caps, Dx, Dy, stream=stream)
         for f in (ccns.F_UX, ccns.F_UY, ccns.F_P, ccns.F_PHI, ccns.F_CONVX, ccns.F_CONVY):
             cj.set_field(f, ctx.get_field(f))

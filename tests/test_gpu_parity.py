@@ -35,6 +35,8 @@ CASES = {
     # the paper's cylinder set-up: inflow on the west, outflow (Neumann
     # velocity, zero pressure beyond) on the other walls; non-singular Poisson
     "outflow_96x48": lambda: W.outflow_cylinder(48),
+    # both: the paper's cylinder set-up on a mesh refined around the body
+    "paper_96x48": lambda: W.paper_cylinder(48, steps=10),
 }
 # The small-volume floor theta: 0 is the paper's mass matrix M = diag(V)
 # (eq:semidiscrete); 0.05 floors every volume the step divides by at 5% of a

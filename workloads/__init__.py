@@ -73,12 +73,28 @@ class GridSpec:
         return np.concatenate([c, [e[-1] + 0.5 * (e[-1] - e[-2])]])
 
 
-def stretched_edges(n: int, x0: float, length: float, amp: float) -> tuple:
+def stretched_edges(n: int, x0: float, length: float, amp: float, focus: float = 0.5) -> tuple:
     """n+1 edges of a smoothly stretched mesh on [x0, x0+length]:
-    x = x0 + length (s + amp sin(2 pi s) / (2 pi)), s = k/n, so the spacing
-    varies between (1 - amp) and (1 + amp) times the uniform one."""
+    x = x0 + length (s + amp (sin(2 pi (s - c)) + sin(2 pi c)) / (2 pi)),
+    s = k/n, so the spacing varies between (1 - amp) and (1 + amp) times the
+    uniform one (0 <= amp < 1); the smallest spacing lies at x0 + focus
+    length (s = c + 1/2 maps there; c = 0 for focus = 1/2)."""
     s = np.arange(n + 1) / n
-    x = x0 + length * (s + amp * np.sin(2.0 * np.pi * s) / (2.0 * np.pi))
+    c = 0.0
+    if focus != 0.5:
+        # s_f - amp sin(2 pi s_f) / (2 pi) = focus, then c = s_f - 1/2
+        lo, hi = 0.0, 1.0
+        for _ in range(200):
+            mid = 0.5 * (lo + hi)
+            if mid - amp * np.sin(2.0 * np.pi * mid) / (2.0 * np.pi) < focus:
+                lo = mid
+            else:
+                hi = mid
+        c = 0.5 * (lo + hi) - 0.5
+    if c == 0.0:
+        x = x0 + length * (s + amp * np.sin(2.0 * np.pi * s) / (2.0 * np.pi))
+    else:
+        x = x0 + length * (s + amp * (np.sin(2.0 * np.pi * (s - c)) + np.sin(2.0 * np.pi * c)) / (2.0 * np.pi))
     x[0], x[-1] = x0, x0 + length
     return tuple(float(v) for v in x)
 
@@ -249,6 +265,18 @@ def outflow_cylinder(n: int = 48, seed: int = 16, steps: int = 10, outflow: str 
     g = GridSpec(2 * n, n, 0.0, 0.0, 4.0, 2.0)
     return Case(f"outflow_cylinder_{2 * n}x{n}", g, [Body(CIRCLE, 1.2, 1.0, a=0.25)], re=100.0, steps=steps,
                 cfl=0.25, pcg_tol=1e-10, noise=1e-2, seed=seed, outflow=outflow)
+
+
+def paper_cylinder(n: int = 1024, seed: int = 17, steps: int = 100) -> Case:
+    """The set-up of the paper's cylinder case (Sec. 5), synthetic: box
+    [0,16]x[0,8] in diameters, 2n x n cells on a mesh stretched around a
+    cylinder of diameter 1 at (4, 4) (spacing 0.4 times the uniform one there,
+    up to 1.6 times far from it), free stream entering through the west wall,
+    outflow on the other three, Re 100, CFL 0.5 on the smallest spacing."""
+    g = GridSpec(2 * n, n, 0.0, 0.0, 16.0, 8.0, xf=stretched_edges(2 * n, 0.0, 16.0, 0.6, focus=0.25),
+                 yf=stretched_edges(n, 0.0, 8.0, 0.6, focus=0.5))
+    return Case(f"paper_cylinder_{2 * n}x{n}", g, [Body(CIRCLE, 4.0, 4.0, a=0.5)], re=100.0, steps=steps,
+                cfl=0.5, pcg_tol=1e-10, noise=1e-3, seed=seed, outflow="ESN")
 
 
 def scaled_cylinder(nx: int, ny: int, lx: float, ly: float, seed: int = 2,
