@@ -62,9 +62,13 @@ def precision_key(precision: int) -> str:
 
 
 def device_key() -> str:
+    """The device's architecture (its gfx name): marketing names depend on
+    how the runtime finds them (a profiler can change them)."""
     import torch
 
-    return torch.cuda.get_device_name(torch.cuda.current_device())
+    p = torch.cuda.get_device_properties(torch.cuda.current_device())
+    arch = getattr(p, "gcnArchName", "") or torch.cuda.get_device_name(torch.cuda.current_device())
+    return arch.split(":")[0]
 
 
 def load_cache(path: str = CACHE) -> Dict:

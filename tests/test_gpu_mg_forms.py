@@ -66,3 +66,24 @@ def test_forms_agree_bit_for_bit(precision):
     with pytest.raises(ccns.CcnsError):
         ctx.set_mg_forms(4 << 3)
     ctx.close()
+
+
+def test_cached_forms_apply():
+    """The committed cache is keyed by this GPU's architecture and gives a
+    512 x 512 context its tuned forms."""
+    from paper_2211_10698_amd import tune
+    cache = tune.load_cache()
+    dev = tune.device_key()
+    print(f"[mg-forms] device {dev}", flush=True)
+    assert dev in cache
+    g = W.GridSpec(512, 512, 0.0, 0.0, 1.0, 1.0)
+    case = W.Case("forms_512", g, [W.Body(W.CIRCLE, 0.5, 0.5, a=0.15)], re=100.0)
+    from paper_2211_10698_amd import ccns
+    caps = ccns.ccns_capacities_device(g, case.bodies).cpu().numpy()
+    Dx, Dy = W.dirichlet(case)
+    ctx = ccns.Context(g, ccns.make_params(1.0, case.mu, case.tau), caps, Dx, Dy)
+    word = tune.apply_cached(ctx, 0)
+    assert word != 0
+    got = [(d, u) for _, _, d, u in ctx.mg_levels()]
+    assert got[0] == tuple(cache[dev]["f64"]["512x512"])
+    ctx.close()
