@@ -198,8 +198,9 @@ ccns_status ccns_capacities_device(const ccns_grid *grid, const ccns_body *bodie
  *                 0 the default, 1 staged first sweep with the tile ring's
  *                 operands in registers, 2 the same with them in LDS, 3 first
  *                 sweep pointwise on 64 x 16 tiles, 4 the same on 64 x 4
- *                 tiles (not for level 0's up-sweep, whose tiles fix the
- *                 order of the preconditioner's statistics).  Every form
+ *                 tiles, 5 form 2 on 64 x 8 tiles (4 and 5 not for level
+ *                 0's up-sweep, whose tiles fix the order of the
+ *                 preconditioner's statistics).  Every form
  *                 computes the same values bit for bit; they differ in speed
  *                 by level size (see ccns_mg_levels).
  */
@@ -211,6 +212,7 @@ ccns_status ccns_capacities_device(const ccns_grid *grid, const ccns_body *bodie
 #define CCNS_MG_FORM_STAGED_LDS 2
 #define CCNS_MG_FORM_PLAIN 3
 #define CCNS_MG_FORM_PLAIN_SHORT 4
+#define CCNS_MG_FORM_STAGED_LDS_HALF 5
 typedef struct {
     double rho, mu, tau, u_ref, gx, gy;
     double pcg_tol, pred_tol, div_tol;
@@ -404,7 +406,7 @@ ccns_status ccns_forces(ccns_ctx *ctx, double *forces_host);
 /* Multigrid cycle kernel forms (see ccns_params.mg_forms), for tuning.
  * ccns_set_mg_forms: the forms of the context's next cycles (0 restores the
  * defaults); the results do not change.  Errors: CCNS_EINVAL (a field above
- * 4, level 0's up-sweep in form 4, or bits above level 9).
+ * 5, level 0's up-sweep in form 4 or 5, or bits above level 9).
  * ccns_mg_levels: the number of cycle levels (levels with down- and
  * up-sweep kernels, at most 10; 0 without the multigrid preconditioner); for
  * the first `cap` of them writes the cells nx[l] x ny[l] and the forms in

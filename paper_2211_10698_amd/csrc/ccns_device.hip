@@ -447,8 +447,11 @@ constexpr int MG_SMALL_GROUPS = 256;
 // Kernel forms of a cycle level's down- and up-sweep kernels (the values of
 // ccns_params.mg_forms): staged first sweep with the ring's operands in
 // registers; the same with every operand of the ring in LDS; the first
-// sweep formed pointwise on 64 x MTY tiles; the same on 64 x MTY_SMALL tiles.
-enum MgForm { MGF_AUTO = 0, MGF_STAGED = 1, MGF_STAGED_LDS = 2, MGF_PLAIN = 3, MGF_PLAIN_SHORT = 4 };
+// sweep formed pointwise on 64 x MTY tiles; the same on 64 x MTY_SMALL tiles;
+// the LDS form on 64 x MTY/2 tiles.
+enum MgForm {
+    MGF_AUTO = 0, MGF_STAGED = 1, MGF_STAGED_LDS = 2, MGF_PLAIN = 3, MGF_PLAIN_SHORT = 4, MGF_STAGED_LDS_HALF = 5
+};
 constexpr int MG_FORM_BITS = 3, MG_FORM_LEVELS = 10;  // 6 bits (down, up) per level in a 64-bit word
 
 struct MgTile {
@@ -694,20 +697,27 @@ __global__ __launch_bounds__(NT) void k_mg_up_staged(int nx, int ny, int P, int 
 }
 
 // The staged forms with every operand of the tile's two-cell ring (1/diag,
-// b, c^x, c^y) loaded once into LDS (64 KB in FP64: two work-groups per
-// compute unit): the ring sweep and the tile phase read their stencil
-// weights from there instead of loading them again.  Same arithmetic, in the
-// same order, as the forms above.
-template <class T>
+// b, c^x, c^y) loaded once into LDS: the ring sweep and the tile phase read
+// their stencil weights from there instead of loading them again.  Same
+// arithmetic, in the same order, as the forms above.  Tiles of 64 x TY
+// cells: TY = MTY takes 64 KB of LDS in FP64 (two work-groups per compute
+// unit), TY = MTY / 2 about 38 KB (four), with more ring per tile cell.
+template <int TY>
+struct LdsTile {
+    static constexpr int Ht = TY + 2 * MH;                                  // rows of the 2-ring region
+    static constexpr int S1 = Ht * MW, I1 = (S1 + NT - 1) / NT;             // 2-ring region
+    static constexpr int S2 = (TY + 2) * (TX + 2), I2 = (S2 + NT - 1) / NT;  // 1-ring region
+};
+template <class T, int TY>
 __device__ inline void mg_stage_ops(T (*sd)[MW], T (*sb)[MW], T (*se)[MW], T (*sn)[MW], const PoisCoefT<T> &c,
-                                    const T *b, int nx, int ny, int P, const MgTile &t, T dv[MI1], T bv[MI1]) {
-    T ev[MI1], nv[MI1];
+                                    const T *b, int nx, int ny, int P, const MgTile &t, T dv[LdsTile<TY>::I1], T bv[LdsTile<TY>::I1]) {
+    T ev[LdsTile<TY>::I1], nv[LdsTile<TY>::I1];
 #pragma unroll
-    for (int q = 0; q < MI1; ++q) {
+    for (int q = 0; q < LdsTile<TY>::I1; ++q) {
         const int e = threadIdx.x + q * NT;
         const int ly = e / MW, lx = e - ly * MW;
         const int j = t.r0 - MH + ly, i = t.c0 - MH + lx;
-        const bool in = (e < MS1) && (j >= 0) && (j <= ny + 1) && (i >= 0) && (i <= nx + 1);
+        const bool in = (e < LdsTile<TY>::S1) && (j >= 0) && (j <= ny + 1) && (i >= 0) && (i <= nx + 1);
         const size_t k = in ? (size_t)j * P + i : 0;
         dv[q] = c.dinv[k];
         bv[q] = b[k];
@@ -715,9 +725,9 @@ __device__ inline void mg_stage_ops(T (*sd)[MW], T (*sb)[MW], T (*se)[MW], T (*s
         nv[q] = c.cy[k];
     }
 #pragma unroll
-    for (int q = 0; q < MI1; ++q) {
+    for (int q = 0; q < LdsTile<TY>::I1; ++q) {
         const int e = threadIdx.x + q * NT;
-        if (e < MS1) {
+        if (e < LdsTile<TY>::S1) {
             const int ly = e / MW, lx = e - ly * MW;
             const int j = t.r0 - MH + ly, i = t.c0 - MH + lx;
             const bool in = (j >= 0) && (j <= ny + 1) && (i >= 0) && (i <= nx + 1);
@@ -730,14 +740,14 @@ __device__ inline void mg_stage_ops(T (*sd)[MW], T (*sb)[MW], T (*se)[MW], T (*s
 }
 
 // The sweep of mg_ring_sweep with the weights read from the staged arrays.
-template <class T>
+template <class T, int TY>
 __device__ inline void mg_ring_sweep_lds(const T (*sd)[MW], const T (*sb)[MW], const T (*se)[MW], const T (*sn)[MW],
                                          const T (*s1)[MW], T (*s2)[TX + 2], int nx, int ny, const MgTile &t,
                                          T omega) {
 #pragma unroll
-    for (int q = 0; q < MI2; ++q) {
+    for (int q = 0; q < LdsTile<TY>::I2; ++q) {
         const int e = threadIdx.x + q * NT;
-        if (e < MS2) {
+        if (e < LdsTile<TY>::S2) {
             const int ly = e / (TX + 2), lx = e - ly * (TX + 2);
             const int j = t.r0 - 1 + ly, i = t.c0 - 1 + lx;
             const bool in = (j >= 1) && (j <= ny) && (i >= 1) && (i <= nx);
@@ -751,24 +761,24 @@ __device__ inline void mg_ring_sweep_lds(const T (*sd)[MW], const T (*sb)[MW], c
     }
 }
 
-template <class T>
+template <class T, int TY>
 __global__ __launch_bounds__(NT) void k_mg_down_lds(int nx, int ny, int P, int gx, PoisCoefT<T> c,
                                                     const T *__restrict__ b, T *__restrict__ x2out, int Pc, int nxc,
                                                     int nyc, const T *__restrict__ dinvc, T *__restrict__ bc,
                                                     const int *done) {
     if (*done) return;
-    __shared__ T sd[MHt][MW], sb[MHt][MW], se[MHt][MW], sn[MHt][MW];
-    __shared__ T s1[MHt][MW];            // first sweep; then the residual on the tile
-    __shared__ T s2[MTY + 2][TX + 2];    // second sweep on the 1-ring region
-    const MgTile t = mg_tile(gx);
+    __shared__ T sd[LdsTile<TY>::Ht][MW], sb[LdsTile<TY>::Ht][MW], se[LdsTile<TY>::Ht][MW], sn[LdsTile<TY>::Ht][MW];
+    __shared__ T s1[LdsTile<TY>::Ht][MW];            // first sweep; then the residual on the tile
+    __shared__ T s2[TY + 2][TX + 2];    // second sweep on the 1-ring region
+    const MgTile t = mg_tile(gx, TY);
     if (t.r0 > ny || t.c0 > nx) return;
     {
-        T dv[MI1], bv[MI1];
-        mg_stage_ops<T>(sd, sb, se, sn, c, b, nx, ny, P, t, dv, bv);
+        T dv[LdsTile<TY>::I1], bv[LdsTile<TY>::I1];
+        mg_stage_ops<T, TY>(sd, sb, se, sn, c, b, nx, ny, P, t, dv, bv);
 #pragma unroll
-        for (int q = 0; q < MI1; ++q) {
+        for (int q = 0; q < LdsTile<TY>::I1; ++q) {
             const int e = threadIdx.x + q * NT;
-            if (e < MS1) {
+            if (e < LdsTile<TY>::S1) {
                 const int ly = e / MW, lx = e - ly * MW;
                 const int j = t.r0 - MH + ly, i = t.c0 - MH + lx;
                 const bool in = (j >= 0) && (j <= ny + 1) && (i >= 0) && (i <= nx + 1);
@@ -779,17 +789,17 @@ __global__ __launch_bounds__(NT) void k_mg_down_lds(int nx, int ny, int P, int g
     // one coarse cell per thread for the restriction: 32 x 8 coarse cells per tile
     const int cxl = threadIdx.x & 31, cyl = threadIdx.x >> 5;
     const int I = (t.c0 + 1) / 2 + cxl, J = (t.r0 + 1) / 2 + cyl;
-    const bool cin = (I <= nxc) && (J <= nyc);
+    const bool cin = (cyl < TY / 2) && (I <= nxc) && (J <= nyc);
     const size_t kc = cin ? (size_t)J * Pc + I : 0;
     const T dcv = dinvc[kc];
     __syncthreads();
-    mg_ring_sweep_lds<T>(sd, sb, se, sn, s1, s2, nx, ny, t, (T)MG_W2);
+    mg_ring_sweep_lds<T, TY>(sd, sb, se, sn, s1, s2, nx, ny, t, (T)MG_W2);
     __syncthreads();
     T (*sr)[TX] = reinterpret_cast<T (*)[TX]>(&s1[0][0]);
     {
         const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
 #pragma unroll
-        for (int m = 0; m < MTY / 4; ++m) {
+        for (int m = 0; m < TY / 4; ++m) {
             const int ly = ty + 4 * m;
             const int j = t.r0 + ly, i = t.c0 + tx;
             const bool in = (j <= ny) && (i <= nx);
@@ -811,36 +821,36 @@ __global__ __launch_bounds__(NT) void k_mg_down_lds(int nx, int ny, int P, int g
     }
 }
 
-template <class T, bool STATS>
+template <class T, bool STATS, int TY>
 __global__ __launch_bounds__(NT) void k_mg_up_lds(int nx, int ny, int P, int gx, PoisCoefT<T> c, const T *__restrict__ b,
                                                   const T *__restrict__ x2, const T *__restrict__ xc, int Pc,
                                                   T *__restrict__ z, double *pout, int nblk, const int *done) {
     if (*done) return;
-    __shared__ T sd[MHt][MW], sb[MHt][MW], se[MHt][MW], sn[MHt][MW];
-    __shared__ T s1[MHt][MW];
-    __shared__ T s2[MTY + 2][TX + 2];
-    const MgTile t = mg_tile(gx);
+    __shared__ T sd[LdsTile<TY>::Ht][MW], sb[LdsTile<TY>::Ht][MW], se[LdsTile<TY>::Ht][MW], sn[LdsTile<TY>::Ht][MW];
+    __shared__ T s1[LdsTile<TY>::Ht][MW];
+    __shared__ T s2[TY + 2][TX + 2];
+    const MgTile t = mg_tile(gx, TY);
     double v[4] = {0, 0, 0, 0};
     const bool live = !(t.r0 > ny || t.c0 > nx);
     if (live) {
-        T xv[MI1], ec[MI1];
+        T xv[LdsTile<TY>::I1], ec[LdsTile<TY>::I1];
 #pragma unroll
-        for (int q = 0; q < MI1; ++q) {
+        for (int q = 0; q < LdsTile<TY>::I1; ++q) {
             const int e = threadIdx.x + q * NT;
             const int ly = e / MW, lx = e - ly * MW;
             const int j = t.r0 - MH + ly, i = t.c0 - MH + lx;
-            const bool in = (e < MS1) && (j >= 1) && (j <= ny) && (i >= 1) && (i <= nx);
+            const bool in = (e < LdsTile<TY>::S1) && (j >= 1) && (j <= ny) && (i >= 1) && (i <= nx);
             const size_t k = in ? (size_t)j * P + i : 0;
             const size_t kc = in ? (size_t)((j + 1) >> 1) * Pc + ((i + 1) >> 1) : 0;
             xv[q] = x2[k];
             ec[q] = xc[kc];
         }
-        T dv[MI1], bv[MI1];
-        mg_stage_ops<T>(sd, sb, se, sn, c, b, nx, ny, P, t, dv, bv);
+        T dv[LdsTile<TY>::I1], bv[LdsTile<TY>::I1];
+        mg_stage_ops<T, TY>(sd, sb, se, sn, c, b, nx, ny, P, t, dv, bv);
 #pragma unroll
-        for (int q = 0; q < MI1; ++q) {
+        for (int q = 0; q < LdsTile<TY>::I1; ++q) {
             const int e = threadIdx.x + q * NT;
-            if (e < MS1) {
+            if (e < LdsTile<TY>::S1) {
                 const int ly = e / MW, lx = e - ly * MW;
                 const int j = t.r0 - MH + ly, i = t.c0 - MH + lx;
                 const bool in = (j >= 1) && (j <= ny) && (i >= 1) && (i <= nx);
@@ -848,7 +858,7 @@ __global__ __launch_bounds__(NT) void k_mg_up_lds(int nx, int ny, int P, int gx,
             }
         }
         __syncthreads();
-        mg_ring_sweep_lds<T>(sd, sb, se, sn, s1, s2, nx, ny, t, (T)MG_W1);
+        mg_ring_sweep_lds<T, TY>(sd, sb, se, sn, s1, s2, nx, ny, t, (T)MG_W1);
     } else {
         __syncthreads();
     }
@@ -856,7 +866,7 @@ __global__ __launch_bounds__(NT) void k_mg_up_lds(int nx, int ny, int P, int gx,
     if (live) {
         const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
 #pragma unroll
-        for (int m = 0; m < MTY / 4; ++m) {
+        for (int m = 0; m < TY / 4; ++m) {
             const int ly = ty + 4 * m;
             const int j = t.r0 + ly, i = t.c0 + tx;
             const bool in = (j <= ny) && (i <= nx);
@@ -3073,8 +3083,9 @@ size_t cycle_levels(const std::vector<ccns_ctx::LevelT<T>> &mg) {
 bool mg_forms_valid(unsigned long long forms) {
     for (int l = 0; l < MG_FORM_LEVELS; ++l)
         for (int h = 0; h < 2; ++h)
-            if (((forms >> (2 * MG_FORM_BITS * l + MG_FORM_BITS * h)) & 7u) > MGF_PLAIN_SHORT) return false;
-    if (((forms >> MG_FORM_BITS) & 7u) == MGF_PLAIN_SHORT) return false;
+            if (((forms >> (2 * MG_FORM_BITS * l + MG_FORM_BITS * h)) & 7u) > MGF_STAGED_LDS_HALF) return false;
+    const unsigned up0 = (forms >> MG_FORM_BITS) & 7u;
+    if (up0 == MGF_PLAIN_SHORT || up0 == MGF_STAGED_LDS_HALF) return false;
     return forms >> (2 * MG_FORM_BITS * MG_FORM_LEVELS) == 0;
 }
 
@@ -3143,7 +3154,7 @@ T *vcycle(ccns_ctx *c, std::vector<ccns_ctx::LevelT<T>> &mg, size_t l, const T *
     ccns_ctx::LevelT<T> &C = mg[l + 1];
     const int fd = c->mgf[sizeof(T) == 8][0][l], fu = c->mgf[sizeof(T) == 8][1][l];
     auto blocks = [&](int form) {
-        const int ty = form == MGF_PLAIN_SHORT ? MTY_SMALL : MTY;
+        const int ty = form == MGF_PLAIN_SHORT ? MTY_SMALL : form == MGF_STAGED_LDS_HALF ? MTY / 2 : MTY;
         return ((gx * ((L.L.ny + ty - 1) / ty) + 7) / 8) * 8;
     };
     const int nbd = blocks(fd), nbu = blocks(fu);
@@ -3153,8 +3164,12 @@ T *vcycle(ccns_ctx *c, std::vector<ccns_ctx::LevelT<T>> &mg, size_t l, const T *
                                                C.L.ny, C.dinv, C.b, done);
         break;
     case MGF_STAGED_LDS:
-        k_mg_down_lds<T><<<nbd, NT, 0, s>>>(L.L.nx, L.L.ny, L.L.pitch, gx, pc, b, L.x, C.L.pitch, C.L.nx, C.L.ny,
-                                            C.dinv, C.b, done);
+        k_mg_down_lds<T, MTY><<<nbd, NT, 0, s>>>(L.L.nx, L.L.ny, L.L.pitch, gx, pc, b, L.x, C.L.pitch, C.L.nx,
+                                                 C.L.ny, C.dinv, C.b, done);
+        break;
+    case MGF_STAGED_LDS_HALF:
+        k_mg_down_lds<T, MTY / 2><<<nbd, NT, 0, s>>>(L.L.nx, L.L.ny, L.L.pitch, gx, pc, b, L.x, C.L.pitch, C.L.nx,
+                                                     C.L.ny, C.dinv, C.b, done);
         break;
     case MGF_PLAIN:
         k_mg_down<T><<<nbd, NT, 0, s>>>(L.L.nx, L.L.ny, L.L.pitch, gx, pc, b, L.x, C.L.pitch, C.L.nx, C.L.ny,
@@ -3175,8 +3190,12 @@ T *vcycle(ccns_ctx *c, std::vector<ccns_ctx::LevelT<T>> &mg, size_t l, const T *
                                                     po, nbu, done);
             break;
         case MGF_STAGED_LDS:
-            k_mg_up_lds<T, S><<<nbu, NT, 0, s>>>(L.L.nx, L.L.ny, L.L.pitch, gx, pc, b, L.x, xc, C.L.pitch, L.xt, po,
-                                                 nbu, done);
+            k_mg_up_lds<T, S, MTY><<<nbu, NT, 0, s>>>(L.L.nx, L.L.ny, L.L.pitch, gx, pc, b, L.x, xc, C.L.pitch, L.xt,
+                                                      po, nbu, done);
+            break;
+        case MGF_STAGED_LDS_HALF:
+            k_mg_up_lds<T, S, MTY / 2><<<nbu, NT, 0, s>>>(L.L.nx, L.L.ny, L.L.pitch, gx, pc, b, L.x, xc, C.L.pitch,
+                                                          L.xt, po, nbu, done);
             break;
         case MGF_PLAIN:
             k_mg_up<T, S><<<nbu, NT, 0, s>>>(L.L.nx, L.L.ny, L.L.pitch, gx, pc, b, L.x, xc, C.L.pitch, L.xt, po,

@@ -2,16 +2,19 @@
 
 Each cycle level runs a down-sweep kernel (two smoothing sweeps, the
 residual and its restriction) and an up-sweep kernel (the interpolated
-correction and two sweeps) in one of four forms (ccns_params.mg_forms):
+correction and two sweeps) in one of five forms (ccns_params.mg_forms):
 
   1  staged first sweep, the tile ring's operands in registers, 64 x 16 tiles
   2  the same with every operand of the ring in LDS (64 KB per work-group in
      FP64: fewer loads, two work-groups per compute unit)
   3  first sweep formed pointwise at the second sweep's stencil, 64 x 16 tiles
-  4  the same on 64 x 4 tiles (more work-groups on small levels; not for the
-     finest level's up-sweep, whose tiles fix the order of the statistics)
+  4  the same on 64 x 4 tiles (more work-groups on small levels)
+  5  form 2 on 64 x 8 tiles (about 38 KB of LDS: four work-groups per unit)
 
-All four compute the same values bit for bit; which is fastest depends on
+Forms 4 and 5 are not used for the finest level's up-sweep, whose tiles fix
+the order of the preconditioner's statistics.
+
+All of them compute the same values bit for bit; which is fastest depends on
 the level's size and the precision.  `tune` times pressure solves on a
 context with each form in turn, level by level, and keeps the fastest;
 `mg_forms.json` beside this module caches the choices per device, precision
@@ -37,6 +40,7 @@ FORMS = {
     2: "staged, ring operands in LDS, 64x16 tiles",
     3: "pointwise first sweep, 64x16 tiles",
     4: "pointwise first sweep, 64x4 tiles",
+    5: "staged, ring operands in LDS, 64x8 tiles",
 }
 CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "mg_forms.json")
 
@@ -45,7 +49,7 @@ def pack(pairs: Sequence[Tuple[int, int]]) -> int:
     """The mg_forms word of per-level (down, up) forms (0: the default)."""
     v = 0
     for level, (down, up) in enumerate(pairs):
-        if not (0 <= down <= 4 and 0 <= up <= 4) or level >= 10 or (level == 0 and up == 4):
+        if not (0 <= down <= 5 and 0 <= up <= 5) or level >= 10 or (level == 0 and up in (4, 5)):
             raise ValueError(f"level {level}: forms ({down}, {up})")
         v |= (down << (6 * level)) | (up << (6 * level + 3))
     return v
@@ -127,7 +131,7 @@ def tune(ctx, b, reps: int = 3, log=None) -> Dict:
         for half in (0, 1):
             res = {}
             for f in FORMS:
-                if lv == 0 and half == 1 and f == 4:
+                if lv == 0 and half == 1 and f in (4, 5):
                     continue
                 pairs = list(best)
                 pair = list(pairs[lv])

@@ -1,6 +1,6 @@
 """The multigrid cycle's kernel forms (ccns_params.mg_forms, chosen per level
 by the tuner) compute the same values bit for bit: pressure solves and a
-step with every level in each of the four forms (the finest level's
+step with every level in each of the five forms (the finest level's
 up-sweep, whose tiles fix the order of the statistics' sums, in the tall
 ones) equal the defaults' exactly, in FP64 and in precision 1, on a grid
 whose hierarchy has levels of both default forms (tall and short tiles)."""
@@ -38,9 +38,9 @@ def test_forms_agree_bit_for_bit(precision):
         return phi.cpu().numpy(), info.iterations
 
     ref, it_ref = solve(0)
-    for f in (1, 2, 3, 4):
+    for f in (1, 2, 3, 4, 5):
         # the finest level's up-sweep keeps tall tiles (its statistics' order)
-        pairs = [(f, min(f, 3))] + [(f, f)] * (len(levels) - 1)
+        pairs = [(f, f if f <= 3 else 2)] + [(f, f)] * (len(levels) - 1)
         word = tune.pack(pairs)
         ctx.set_mg_forms(word)
         assert [(d, u) for _, _, d, u in ctx.mg_levels()] == pairs
@@ -62,9 +62,13 @@ def test_forms_agree_bit_for_bit(precision):
     for a, c in zip(*out):
         assert np.array_equal(a, c)
     with pytest.raises(ccns.CcnsError):
-        ctx.set_mg_forms(5)
+        ctx.set_mg_forms(7)
     with pytest.raises(ccns.CcnsError):
         ctx.set_mg_forms(4 << 3)
+    with pytest.raises(ccns.CcnsError):
+        ctx.set_mg_forms(5 << 3)
+    with pytest.raises(ccns.CcnsError):
+        ctx.set_mg_forms(6)
     ctx.close()
 
 

@@ -51,7 +51,7 @@ def test_argument_validation_without_gpu():
     dir2 = np.zeros(2 * 10 * 10)
     for bad_p in (ccns.make_params(1.0, 0.01, 0.01, precision=2), ccns.make_params(1.0, 0.01, 0.01, precond=5),
                   ccns.make_params(1.0, 0.01, 0.01, coef_tables=2), ccns.make_params(1.0, 0.01, 0.01, outflow=16),
-                  ccns.make_params(1.0, 0.01, 0.01, mg_forms=5), ccns.make_params(1.0, 0.01, 0.01, mg_forms=1 << 60),
+                  ccns.make_params(1.0, 0.01, 0.01, mg_forms=6), ccns.make_params(1.0, 0.01, 0.01, mg_forms=1 << 60),
                   ccns.make_params(1.0, 0.01, 0.01, mg_forms=4 << 3)):
         assert L.ccns_ctx_create(C.byref(g), C.byref(bad_p), caps.ctypes.data, dir2.ctypes.data,
                                  C.c_void_p(256), 1 << 30, None, C.byref(h)) == ccns.EINVAL
@@ -146,7 +146,7 @@ def test_multigrid_form_words_and_cache():
     w = tune.pack(pairs)
     assert tune.unpack(w, 4) == pairs and w < 1 << 24
     with pytest.raises(ValueError):
-        tune.pack([(5, 1)])
+        tune.pack([(6, 1)])
     with pytest.raises(ValueError):
         tune.pack([(1, 4)])
     cache = json.load(open(tune.CACHE))
@@ -156,7 +156,7 @@ def test_multigrid_form_words_and_cache():
         for prec, table in per.items():
             for size, forms in table.items():
                 nx, ny = (int(v) for v in size.split("x"))
-                assert nx > 0 and ny > 0 and len(forms) == 2 and all(1 <= f <= 4 for f in forms)
+                assert nx > 0 and ny > 0 and len(forms) == 2 and all(1 <= f <= 5 for f in forms)
     # lookups by level size; missing levels keep the defaults (0)
     dev = next(iter(cache))
     prec = next(iter(cache[dev]))
