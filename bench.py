@@ -296,9 +296,12 @@ def setup_context(ccns, case, precision, stream, host, coef_tables=0, mg_forms=T
 
 def run_batched(args):
     """The ragged batch: 256 cylinder simulations of 128^2 .. 1024^2 cells
-    (seeded sizes, radii, centres and Reynolds numbers), each on its own
-    stream, advanced together by ccns_batch_step.  A step advances every
-    simulation by one projection step; value = total cell-steps / time."""
+    (seeded sizes, radii, centres and Reynolds numbers), advanced together
+    by ccns_batch_step: in FP64 by default as a fused batch (one launch per
+    phase over every simulation's work-groups), else (--batch-mode streams,
+    and always in precision 1) with 16 host threads and one stream per
+    simulation.  A step advances every simulation by one projection step;
+    value = total cell-steps / time."""
     import concurrent.futures as cf
 
     import torch
@@ -306,9 +309,14 @@ def run_batched(args):
 
     cases = W.batched_cylinders(256)
     prec = 1 if args.precision == "mixed" else 0
+    mode = args.batch_mode if args.batch_mode != "auto" else ("streams" if prec else "fused")
+    if mode == "fused" and prec:
+        raise SystemExit("the fused batch runs precision 0 (--precision fp64)")
     torch.cuda.set_device(0)
     t_setup = time.perf_counter()
-    streams = [torch.cuda.Stream() for _ in cases]
+    # a fused batch runs on its own stream: the contexts can share one
+    shared = torch.cuda.Stream()
+    streams = [shared if mode == "fused" else torch.cuda.Stream() for _ in cases]
     ctxs = []
     with cf.ThreadPoolExecutor(max_workers=8) as ex:
         for case, stream, host in zip(cases, streams, ex.map(lambda c: host_inputs(ccns, c), cases)):
@@ -318,7 +326,7 @@ def run_batched(args):
     cells = sum(c.grid.nx * c.grid.ny for c in cases)
     print(f"[bench] setup {time.perf_counter() - t_setup:.1f}s: {len(cases)} simulations, {cells} cells",
           file=sys.stderr, flush=True)
-    batch = ccns.Batch(ctxs, nthreads=16)
+    batch = ccns.Batch(ctxs, nthreads=16, fused=mode == "fused")
     failures = []
 
     def record(tag, st, infos, sts):
@@ -365,7 +373,8 @@ def run_batched(args):
                    "coef_classes_used": sum(1 for c in ctxs if c.coef_classes() > 0),
                    "sizes": {str(k): v for k, v in sorted(sizes.items())}, "precond": "multigrid",
                    "precision": "fp32 inner + fp64 refinement, div_rel <= 1e-8" if prec else "fp64",
-                   "host_threads": 16},
+                   "batch_mode": ("fused: one launch per phase over all simulations' work-groups" if mode == "fused"
+                                  else "streams: 16 host threads, one stream per simulation")},
         "div_rel_max": max(divs),
         "cg_iters_per_step_mean": float(np.mean(cg)),
         "pred_iters_per_step_mean": float(np.mean(pred)),
@@ -448,6 +457,9 @@ def main():
     ap.add_argument("--mg-forms", default="tuned", choices=["tuned", "default"],
                     help="multigrid cycle kernel forms: the tuned ones cached for this GPU's level sizes "
                          "(paper_2211_10698_amd/mg_forms.json), or the library's defaults")
+    ap.add_argument("--batch-mode", default="auto", choices=["auto", "fused", "streams"],
+                    help="batched_cylinders_256: fused launches (FP64) or a stream per simulation "
+                         "(auto: fused in FP64, streams in precision 1)")
     ap.add_argument("--coef-tables", default="auto", choices=["auto", "off"],
                     help="auto: the predictor CG reads its coefficients through the class table when it "
                          "fits (the library's default); off: from the coefficient arrays")

@@ -430,9 +430,28 @@ int ccns_mg_levels(const ccns_ctx *ctx, int *nx, int *ny, int *forms, int cap);
  *   per_status (may be NULL): n statuses.  Returns the worst status:
  *   CCNS_EDEVICE if any simulation hit a device error, else a solver status
  *   (CCNS_ENOTCONV, CCNS_EBREAKDOWN) if any, else CCNS_OK.
- * ccns_batch_destroy: frees the batch (not the contexts). */
+ * ccns_batch_destroy: frees the batch (not the contexts).
+ *
+ * ccns_batch_create_fused: a batch whose steps run each phase of every
+ *   simulation in one launch (one per kernel variant): the work-groups of
+ *   all simulations' grids side by side, each group on its own
+ *   simulation's arrays through a table of (simulation, group) entries, on
+ *   the batch's own HIP stream.  The conjugate-gradient solves run in
+ *   lockstep: each simulation keeps its own solver state, a simulation
+ *   whose solve has stopped does nothing in the later launches, and the
+ *   host reads all stopping flags in one read-back per chunk of iterations.
+ *   Each simulation's kernels, and so its results, are those of its solo
+ *   steps bit for bit.  1 <= n <= 1024 distinct contexts on the current
+ *   device, each with precision 0 and the multigrid preconditioner
+ *   (precond 1); ccns_batch_step and ccns_batch_destroy as above.  A step
+ *   waits for each context's stream before it starts and returns after its
+ *   own work ends; the contexts must not be used elsewhere meanwhile.
+ *   Errors: CCNS_EINVAL (n out of range, a NULL or repeated context, another
+ *   precision or preconditioner), CCNS_ENOMEM (device or host memory for the
+ *   batch's tables), CCNS_EDEVICE. */
 typedef struct ccns_batch ccns_batch;
 ccns_status ccns_batch_create(int n, ccns_ctx *const *ctxs, int nthreads, ccns_batch **out);
+ccns_status ccns_batch_create_fused(int n, ccns_ctx *const *ctxs, ccns_batch **out);
 ccns_status ccns_batch_step(ccns_batch *batch, int nsteps, ccns_step_info *per_sim, int *per_status);
 void ccns_batch_destroy(ccns_batch *batch);
 

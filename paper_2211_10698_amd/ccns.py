@@ -129,6 +129,8 @@ def lib():
         L.ccns_step.argtypes = [C.c_void_p, C.c_int, P(StepInfo)]
         L.ccns_batch_create.restype = C.c_int
         L.ccns_batch_create.argtypes = [C.c_int, P(C.c_void_p), C.c_int, P(C.c_void_p)]
+        L.ccns_batch_create_fused.restype = C.c_int
+        L.ccns_batch_create_fused.argtypes = [C.c_int, P(C.c_void_p), P(C.c_void_p)]
         L.ccns_batch_step.restype = C.c_int
         L.ccns_batch_step.argtypes = [C.c_void_p, C.c_int, P(StepInfo), P(C.c_int)]
         L.ccns_batch_destroy.restype = None
@@ -142,7 +144,7 @@ EXPORTED = ("ccns_caps_count", "ccns_capacities", "ccns_capacities_scratch_bytes
             "ccns_ctx_destroy", "ccns_last_error", "ccns_coef_classes", "ccns_field_set", "ccns_field_get", "ccns_apply",
             "ccns_pressure_solve", "ccns_project", "ccns_step", "ccns_predict", "ccns_correct",
             "ccns_diagnostics", "ccns_forces", "ccns_set_mg_forms", "ccns_mg_levels", "ccns_timing",
-            "ccns_batch_create", "ccns_batch_step", "ccns_batch_destroy")
+            "ccns_batch_create", "ccns_batch_create_fused", "ccns_batch_step", "ccns_batch_destroy")
 
 
 class CcnsError(RuntimeError):
@@ -408,15 +410,24 @@ class Context:
 
 class Batch:
     """A ragged batch of contexts stepped together (ccns_batch_*).  The
-    contexts stay owned by the caller and must outlive the batch."""
+    contexts stay owned by the caller and must outlive the batch.  fused:
+    one launch per phase over every simulation's work-groups
+    (ccns_batch_create_fused; precision 0 with the multigrid
+    preconditioner), else one host thread and stream per simulation."""
 
-    def __init__(self, contexts: Sequence["Context"], nthreads: int = 0):
+    def __init__(self, contexts: Sequence["Context"], nthreads: int = 0, fused: bool = False):
         self.contexts = list(contexts)
+        self.fused = fused
         arr = (C.c_void_p * len(self.contexts))(*[c.h.value for c in self.contexts])
         h = C.c_void_p()
-        st = lib().ccns_batch_create(len(self.contexts), arr, nthreads, C.byref(h))
-        if st != OK:
-            raise CcnsError(st, "ccns_batch_create")
+        if fused:
+            st = lib().ccns_batch_create_fused(len(self.contexts), arr, C.byref(h))
+            if st != OK:
+                raise CcnsError(st, "ccns_batch_create_fused")
+        else:
+            st = lib().ccns_batch_create(len(self.contexts), arr, nthreads, C.byref(h))
+            if st != OK:
+                raise CcnsError(st, "ccns_batch_create")
         self.h = h
 
     def step(self, n=1, check=True):

@@ -115,8 +115,9 @@ struct DirStep {
     bool stop;
     double rz, mean, beta;
 };
-__device__ inline DirStep cg_decide(CgState *st, int first, int par, double fnorm2, double rs, double s, double r,
-                                    double rr) {
+template <class G>
+__device__ inline DirStep cg_decide(const G &g, CgState *st, int first, int par, double fnorm2, double rs, double s,
+                                    double r, double rr) {
     DirStep o;
     const double m = st->zero_mean ? s / (double)st->n_active : 0.0;
     o.mean = m;
@@ -129,7 +130,7 @@ __device__ inline DirStep cg_decide(CgState *st, int first, int par, double fnor
     const bool lim = it >= st->maxit;
     o.stop = conv || lim || brk;
     o.beta = first ? 0.0 : o.rz / st->slot[par ^ 1].rz;
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (g.b() == 0 && threadIdx.x == 0) {
         if (first) st->fnorm2 = fnorm2;
         if (o.stop) {
             st->done = 1;
@@ -150,7 +151,8 @@ __device__ inline DirStep cg_decide(CgState *st, int first, int par, double fnor
 // ---------------------------------------------------------------------------
 
 // b = (rho/tau) cont(U*, D) on the pressure unknowns (eq:pm_poisson); sum b.
-__global__ __launch_bounds__(NT) void k_pois_rhs(Dims d, PoisCoef pc, const double *__restrict__ ax,
+template <class G>
+__device__ __forceinline__ void pois_rhs_body(const G &g, Dims d, PoisCoef pc, const double *__restrict__ ax,
                                                  const double *__restrict__ ay, const double *__restrict__ het,
                                                  const double *__restrict__ usx, const double *__restrict__ usy,
                                                  double *__restrict__ b, double scale, double *pout) {
@@ -164,14 +166,20 @@ __global__ __launch_bounds__(NT) void k_pois_rhs(Dims d, PoisCoef pc, const doub
         const size_t kw = k >= 1 ? k - 1 : k, ks = k >= P ? k - P : k;
         return In{ax[k], usx[k], ax[kw], usx[kw], ay[k], usy[k], ay[ks], usy[ks], het[k], pc.dinv[k]};
     };
-    for_cells_batched<TY / 4>(d, load, [&](int, int j, int i, size_t k, const In &q) {
+    for_cells_batched<TY / 4>(g, d, load, [&](int, int j, int i, size_t k, const In &q) {
         if (i < 1 || i > d.nx || j < 1 || j > d.ny) return;
         const double c = q.ae * q.ue - q.aw * q.uw + q.an * q.vn - q.as * q.vs + q.h;
         const double bv = q.dv > 0.0 ? scale * c : 0.0;
         b[k] = bv;
         v[0] += bv;
     });
-    put_partials<1>(v, pout, d.nblk);
+    put_partials<1>(g, v, pout, d.nblk);
+}
+__global__ __launch_bounds__(NT) void k_pois_rhs(Dims d, PoisCoef pc, const double *__restrict__ ax,
+                                                 const double *__restrict__ ay, const double *__restrict__ het,
+                                                 const double *__restrict__ usx, const double *__restrict__ usy,
+                                                 double *__restrict__ b, double scale, double *pout) {
+    pois_rhs_body(SoloGrid{}, d, pc, ax, ay, het, usx, usy, b, scale, pout);
 }
 
 // Sum of a caller-provided b over the unknowns.
@@ -189,8 +197,8 @@ __global__ __launch_bounds__(NT) void k_pois_sum(Dims d, PoisCoef pc, const doub
 //  MIX = true (precision 1): r is rounded to float into r32 (the right-hand
 //  side of the inner solve, whose start value x32 is cleared); partials
 //  (r32.r32, r32.z, z, r32, r32.r32 | f.f, r.r | max |r|) with z = D32^-1 r32.
-template <bool MIX>
-__global__ __launch_bounds__(NT) void k_pois_init(Dims d, PoisCoef pc, double *__restrict__ b,
+template <bool MIX, class G>
+__device__ __forceinline__ void pois_init_body(const G &g, Dims d, PoisCoef pc, double *__restrict__ b,
                                                   const double *__restrict__ x, double *__restrict__ r, CgState *st,
                                                   const double *pin, int nin, double *pout, float *__restrict__ r32,
                                                   float *__restrict__ x32, const float *__restrict__ dinv32) {
@@ -213,7 +221,7 @@ __global__ __launch_bounds__(NT) void k_pois_init(Dims d, PoisCoef pc, double *_
         return In{pc.dinv[k], b[k], pc.cx[k], pc.cx[kw], pc.cy[k], pc.cy[ks], x[k], x[ke], x[kw], x[kn], x[ks],
                   MIX ? dinv32[k] : 0.0f};
     };
-    for_cells_batched<TY / 4>(d, load, [&](int, int, int, size_t k, const In &q) {
+    for_cells_batched<TY / 4>(g, d, load, [&](int, int, int, size_t k, const In &q) {
         const double dv = q.dv;
         if (MIX) {
             x32[k] = 0.0f;
@@ -248,18 +256,25 @@ __global__ __launch_bounds__(NT) void k_pois_init(Dims d, PoisCoef pc, double *_
             v[4] += rv * rv;
         }
     });
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (g.b() == 0 && threadIdx.x == 0) {
         st->done = 0;
         st->status = 0;
         st->it_final = 0;
         st->stop_it = 0x7fffffff;
     }
     if (MIX) {
-        put_partials<7, 1>(v, pout, d.nblk);
+        put_partials<7, 1>(g, v, pout, d.nblk);
     } else {
         double w[5] = {v[0], v[1], v[2], v[3], v[4]};
-        put_partials<5>(w, pout, d.nblk);
+        put_partials<5>(g, w, pout, d.nblk);
     }
+}
+template <bool MIX>
+__global__ __launch_bounds__(NT) void k_pois_init(Dims d, PoisCoef pc, double *__restrict__ b,
+                                                  const double *__restrict__ x, double *__restrict__ r, CgState *st,
+                                                  const double *pin, int nin, double *pout, float *__restrict__ r32,
+                                                  float *__restrict__ x32, const float *__restrict__ dinv32) {
+    pois_init_body<MIX>(SoloGrid{}, d, pc, b, x, r, st, pin, nin, pout, r32, x32, dinv32);
 }
 
 // Tile of the Poisson stencil kernels: 64 columns x 16 rows (4 per thread).
@@ -284,7 +299,7 @@ __global__ __launch_bounds__(NT) void k_pois_dir(Dims d, PoisCoefT<T> pc, const 
         get_totals<4>(pin, nin, t);
         fn2 = st->fnorm2; rs = t[0]; sm = t[1]; rsum = t[2]; rr = t[3];
     }
-    const DirStep ds = cg_decide(st, first, par, fn2, rs, sm, rsum, rr);
+    const DirStep ds = cg_decide(SoloGrid{}, st, first, par, fn2, rs, sm, rsum, rr);
     if (ds.stop) return;
     const T beta = (T)ds.beta, m = (T)ds.mean;
     __shared__ T sp[PTY + 2][TX + 2];
@@ -331,8 +346,8 @@ __global__ __launch_bounds__(NT) void k_pois_dir(Dims d, PoisCoefT<T> pc, const 
 // chunks of UPT*NT entries with every load issued before any arithmetic.
 constexpr int UPT = 4;
 constexpr int UT = 1024;  // threads per work-group of the update (16 wavefronts)
-template <class T, bool STATS = true>
-__global__ __launch_bounds__(UT) void k_cg_update(size_t ntot, int nblk, const T *__restrict__ dinv,
+template <class T, bool STATS, class G>
+__device__ __forceinline__ void cg_update_body(const G &g, size_t ntot, int nblk, const T *__restrict__ dinv,
                                                   T *__restrict__ x, T *__restrict__ r,
                                                   const T *__restrict__ p, const T *__restrict__ q,
                                                   CgState *st, int par, const double *pin, int nin, double *pout) {
@@ -340,7 +355,7 @@ __global__ __launch_bounds__(UT) void k_cg_update(size_t ntot, int nblk, const T
     double t[1];
     get_totals<1, 0, UT>(pin, nin, t);
     if (!(t[0] > 0.0)) {
-        if (blockIdx.x == 0 && threadIdx.x == 0) {
+        if (g.b() == 0 && threadIdx.x == 0) {
             st->done = 1;
             st->status = CCNS_EBREAKDOWN;
             st->it_final = st->slot[par].it;
@@ -350,7 +365,7 @@ __global__ __launch_bounds__(UT) void k_cg_update(size_t ntot, int nblk, const T
     const T a = (T)(st->slot[par].rz / t[0]);
     double v[4] = {0, 0, 0, 0};
     const size_t chunk = (size_t)UPT * UT;
-    const int L = logical_group(nblk);
+    const int L = logical_group(g, nblk);
     for (size_t base = (size_t)L * chunk; base < ntot; base += (size_t)nblk * chunk) {
         T dv[UPT], xv[UPT], pv[UPT], rv[UPT], qv[UPT];
 #pragma unroll
@@ -383,7 +398,14 @@ __global__ __launch_bounds__(UT) void k_cg_update(size_t ntot, int nblk, const T
             }
         }
     }
-    if (STATS) put_partials<4, 0, UT>(v, pout, nblk);
+    if (STATS) put_partials<4, 0, UT>(g, v, pout, nblk);
+}
+template <class T, bool STATS = true>
+__global__ __launch_bounds__(UT) void k_cg_update(size_t ntot, int nblk, const T *__restrict__ dinv,
+                                                  T *__restrict__ x, T *__restrict__ r,
+                                                  const T *__restrict__ p, const T *__restrict__ q,
+                                                  CgState *st, int par, const double *pin, int nin, double *pout) {
+    cg_update_body<T, STATS>(SoloGrid{}, ntot, nblk, dinv, x, r, p, q, st, par, pin, nin, pout);
 }
 
 // x += dx (float correction of an inner solve) over ntot entries.
@@ -457,8 +479,9 @@ constexpr int MG_FORM_BITS = 3, MG_FORM_LEVELS = 10;  // 6 bits (down, up) per l
 struct MgTile {
     int c0, r0;  // first real cell of the tile
 };
-__device__ inline MgTile mg_tile(int gx, int ty = MTY) {
-    const int L = logical_group(((gridDim.x + 7) / 8) * 8);
+template <class G>
+__device__ inline MgTile mg_tile(const G &g, int gx, int ty = MTY) {
+    const int L = logical_group(g, ((g.n() + 7) / 8) * 8);
     MgTile t;
     t.c0 = 1 + (L % gx) * TX;
     t.r0 = 1 + (L / gx) * ty;
@@ -555,8 +578,8 @@ __device__ inline void mg_ring_sweep(const MgRingOps<T> &o, const T (*s1)[MW], T
 
 // Two weighted-Jacobi sweeps from a zero guess, the residual, and its
 // restriction: x2 (written to x2out) and b_coarse.
-template <class T>
-__global__ __launch_bounds__(NT) void k_mg_down_staged(int nx, int ny, int P, int gx, PoisCoefT<T> c,
+template <class T, class G>
+__device__ __forceinline__ void mg_down_staged_body(const G &g, int nx, int ny, int P, int gx, PoisCoefT<T> c,
                                                 const T *__restrict__ b, T *__restrict__ x2out,
                                                 int Pc, int nxc, int nyc, const T *__restrict__ dinvc,
                                                 T *__restrict__ bc, const int *done) {
@@ -564,7 +587,7 @@ __global__ __launch_bounds__(NT) void k_mg_down_staged(int nx, int ny, int P, in
     __shared__ T s1[MHt][MW];            // first sweep on the 2-ring region
     __shared__ T s2[MTY + 2][TX + 2];    // second sweep on the 1-ring region
     __shared__ T sr[MTY][TX];            // residual on the tile
-    const MgTile t = mg_tile(gx);
+    const MgTile t = mg_tile(g, gx);
     if (t.r0 > ny || t.c0 > nx) return;
     {
         T dv[MI1], bv[MI1];
@@ -624,17 +647,24 @@ __global__ __launch_bounds__(NT) void k_mg_down_staged(int nx, int ny, int P, in
         bc[kc] = dcv > (T)0 ? sum : (T)0;
     }
 }
+template <class T>
+__global__ __launch_bounds__(NT) void k_mg_down_staged(int nx, int ny, int P, int gx, PoisCoefT<T> c,
+                                                const T *__restrict__ b, T *__restrict__ x2out,
+                                                int Pc, int nxc, int nyc, const T *__restrict__ dinvc,
+                                                T *__restrict__ bc, const int *done) {
+    mg_down_staged_body<T>(SoloGrid{}, nx, ny, P, gx, c, b, x2out, Pc, nxc, nyc, dinvc, bc, done);
+}
 
 // The coarse correction interpolated onto x2, then two weighted-Jacobi
 // sweeps: z.  With STATS, partials of (b.z, z, b, b.b).
-template <class T, bool STATS>
-__global__ __launch_bounds__(NT) void k_mg_up_staged(int nx, int ny, int P, int gx, PoisCoefT<T> c, const T *__restrict__ b,
+template <class T, bool STATS, class G>
+__device__ __forceinline__ void mg_up_staged_body(const G &g, int nx, int ny, int P, int gx, PoisCoefT<T> c, const T *__restrict__ b,
                                               const T *__restrict__ x2, const T *__restrict__ xc, int Pc,
                                               T *__restrict__ z, double *pout, int nblk, const int *done) {
     if (*done) return;
     __shared__ T s1[MHt][MW];
     __shared__ T s2[MTY + 2][TX + 2];
-    const MgTile t = mg_tile(gx);
+    const MgTile t = mg_tile(g, gx);
     double v[4] = {0, 0, 0, 0};
     const bool live = !(t.r0 > ny || t.c0 > nx);
     MgCellOps<T, MTY / 4> o;
@@ -693,7 +723,13 @@ __global__ __launch_bounds__(NT) void k_mg_up_staged(int nx, int ny, int P, int 
             }
         }
     }
-    if (STATS) put_partials<4>(v, pout, nblk);
+    if (STATS) put_partials<4>(g, v, pout, nblk);
+}
+template <class T, bool STATS>
+__global__ __launch_bounds__(NT) void k_mg_up_staged(int nx, int ny, int P, int gx, PoisCoefT<T> c, const T *__restrict__ b,
+                                              const T *__restrict__ x2, const T *__restrict__ xc, int Pc,
+                                              T *__restrict__ z, double *pout, int nblk, const int *done) {
+    mg_up_staged_body<T, STATS>(SoloGrid{}, nx, ny, P, gx, c, b, x2, xc, Pc, z, pout, nblk, done);
 }
 
 // The staged forms with every operand of the tile's two-cell ring (1/diag,
@@ -761,8 +797,8 @@ __device__ inline void mg_ring_sweep_lds(const T (*sd)[MW], const T (*sb)[MW], c
     }
 }
 
-template <class T, int TY>
-__global__ __launch_bounds__(NT) void k_mg_down_lds(int nx, int ny, int P, int gx, PoisCoefT<T> c,
+template <class T, int TY, class G>
+__device__ __forceinline__ void mg_down_lds_body(const G &g, int nx, int ny, int P, int gx, PoisCoefT<T> c,
                                                     const T *__restrict__ b, T *__restrict__ x2out, int Pc, int nxc,
                                                     int nyc, const T *__restrict__ dinvc, T *__restrict__ bc,
                                                     const int *done) {
@@ -770,7 +806,7 @@ __global__ __launch_bounds__(NT) void k_mg_down_lds(int nx, int ny, int P, int g
     __shared__ T sd[LdsTile<TY>::Ht][MW], sb[LdsTile<TY>::Ht][MW], se[LdsTile<TY>::Ht][MW], sn[LdsTile<TY>::Ht][MW];
     __shared__ T s1[LdsTile<TY>::Ht][MW];            // first sweep; then the residual on the tile
     __shared__ T s2[TY + 2][TX + 2];    // second sweep on the 1-ring region
-    const MgTile t = mg_tile(gx, TY);
+    const MgTile t = mg_tile(g, gx, TY);
     if (t.r0 > ny || t.c0 > nx) return;
     {
         T dv[LdsTile<TY>::I1], bv[LdsTile<TY>::I1];
@@ -820,16 +856,23 @@ __global__ __launch_bounds__(NT) void k_mg_down_lds(int nx, int ny, int P, int g
         bc[kc] = dcv > (T)0 ? sum : (T)0;
     }
 }
+template <class T, int TY>
+__global__ __launch_bounds__(NT) void k_mg_down_lds(int nx, int ny, int P, int gx, PoisCoefT<T> c,
+                                                    const T *__restrict__ b, T *__restrict__ x2out, int Pc, int nxc,
+                                                    int nyc, const T *__restrict__ dinvc, T *__restrict__ bc,
+                                                    const int *done) {
+    mg_down_lds_body<T, TY>(SoloGrid{}, nx, ny, P, gx, c, b, x2out, Pc, nxc, nyc, dinvc, bc, done);
+}
 
-template <class T, bool STATS, int TY>
-__global__ __launch_bounds__(NT) void k_mg_up_lds(int nx, int ny, int P, int gx, PoisCoefT<T> c, const T *__restrict__ b,
+template <class T, bool STATS, int TY, class G>
+__device__ __forceinline__ void mg_up_lds_body(const G &g, int nx, int ny, int P, int gx, PoisCoefT<T> c, const T *__restrict__ b,
                                                   const T *__restrict__ x2, const T *__restrict__ xc, int Pc,
                                                   T *__restrict__ z, double *pout, int nblk, const int *done) {
     if (*done) return;
     __shared__ T sd[LdsTile<TY>::Ht][MW], sb[LdsTile<TY>::Ht][MW], se[LdsTile<TY>::Ht][MW], sn[LdsTile<TY>::Ht][MW];
     __shared__ T s1[LdsTile<TY>::Ht][MW];
     __shared__ T s2[TY + 2][TX + 2];
-    const MgTile t = mg_tile(gx, TY);
+    const MgTile t = mg_tile(g, gx, TY);
     double v[4] = {0, 0, 0, 0};
     const bool live = !(t.r0 > ny || t.c0 > nx);
     if (live) {
@@ -887,7 +930,13 @@ __global__ __launch_bounds__(NT) void k_mg_up_lds(int nx, int ny, int P, int gx,
             }
         }
     }
-    if (STATS) put_partials<4>(v, pout, nblk);
+    if (STATS) put_partials<4>(g, v, pout, nblk);
+}
+template <class T, bool STATS, int TY>
+__global__ __launch_bounds__(NT) void k_mg_up_lds(int nx, int ny, int P, int gx, PoisCoefT<T> c, const T *__restrict__ b,
+                                                  const T *__restrict__ x2, const T *__restrict__ xc, int Pc,
+                                                  T *__restrict__ z, double *pout, int nblk, const int *done) {
+    mg_up_lds_body<T, STATS, TY>(SoloGrid{}, nx, ny, P, gx, c, b, x2, xc, Pc, z, pout, nblk, done);
 }
 
 // Two weighted-Jacobi sweeps from a zero guess, the residual, and its
@@ -898,8 +947,8 @@ __global__ __launch_bounds__(NT) void k_mg_up_lds(int nx, int ny, int P, int gx,
 // MTY, or MTY_SMALL on levels too small to give every compute unit a tile
 // (there each work-group's serial chain of loads is what the launch waits
 // for, and shorter tiles shorten it).
-template <class T, int TY = MTY>
-__global__ __launch_bounds__(NT) void k_mg_down(int nx, int ny, int P, int gx, PoisCoefT<T> c,
+template <class T, int TY, class G>
+__device__ __forceinline__ void mg_down_body(const G &g, int nx, int ny, int P, int gx, PoisCoefT<T> c,
                                                 const T *__restrict__ b, T *__restrict__ x2out,
                                                 int Pc, int nxc, int nyc, const T *__restrict__ dinvc,
                                                 T *__restrict__ bc, const int *done) {
@@ -907,7 +956,7 @@ __global__ __launch_bounds__(NT) void k_mg_down(int nx, int ny, int P, int gx, P
     static_assert(TY % 4 == 0 && TY <= MTY, "tile rows: a multiple of the 4 row groups, at most MTY");
     __shared__ T s2[TY + 2][TX + 2];    // x after two sweeps, on the tile and a one-cell ring
     __shared__ T sr[TY][TX];            // residual on the tile
-    const MgTile t = mg_tile(gx, TY);
+    const MgTile t = mg_tile(g, gx, TY);
     if (t.r0 > ny || t.c0 > nx) return;
     MgCellOps<T, TY / 4> o;
     mg_load_tile_ops<T, TY / 4>(o, c, b, nx, ny, P, t);
@@ -958,20 +1007,27 @@ __global__ __launch_bounds__(NT) void k_mg_down(int nx, int ny, int P, int gx, P
         bc[kc] = dcv > (T)0 ? sum : (T)0;
     }
 }
+template <class T, int TY = MTY>
+__global__ __launch_bounds__(NT) void k_mg_down(int nx, int ny, int P, int gx, PoisCoefT<T> c,
+                                                const T *__restrict__ b, T *__restrict__ x2out,
+                                                int Pc, int nxc, int nyc, const T *__restrict__ dinvc,
+                                                T *__restrict__ bc, const int *done) {
+    mg_down_body<T, TY>(SoloGrid{}, nx, ny, P, gx, c, b, x2out, Pc, nxc, nyc, dinvc, bc, done);
+}
 
 // The coarse correction interpolated onto x2, then two weighted-Jacobi
 // sweeps: z.  With STATS, partials of (b.z, z, b, b.b).  The interpolated
 // start value is pointwise, so it is formed at the five points of the first
 // sweep's stencil instead of being staged: one barrier, between the sweeps.
 // Tiles of TX x TY cells, as in k_mg_down.
-template <class T, bool STATS, int TY = MTY>
-__global__ __launch_bounds__(NT) void k_mg_up(int nx, int ny, int P, int gx, PoisCoefT<T> c, const T *__restrict__ b,
+template <class T, bool STATS, int TY, class G>
+__device__ __forceinline__ void mg_up_body(const G &g, int nx, int ny, int P, int gx, PoisCoefT<T> c, const T *__restrict__ b,
                                               const T *__restrict__ x2, const T *__restrict__ xc, int Pc,
                                               T *__restrict__ z, double *pout, int nblk, const int *done) {
     if (*done) return;
     static_assert(TY % 4 == 0 && TY <= MTY, "tile rows: a multiple of the 4 row groups, at most MTY");
     __shared__ T s2[TY + 2][TX + 2];    // x after the first sweep, on the tile and a one-cell ring
-    const MgTile t = mg_tile(gx, TY);
+    const MgTile t = mg_tile(g, gx, TY);
     double v[4] = {0, 0, 0, 0};
     const bool live = !(t.r0 > ny || t.c0 > nx);
     MgCellOps<T, TY / 4> o;
@@ -1024,7 +1080,13 @@ __global__ __launch_bounds__(NT) void k_mg_up(int nx, int ny, int P, int gx, Poi
             }
         }
     }
-    if (STATS) put_partials<4>(v, pout, nblk);
+    if (STATS) put_partials<4>(g, v, pout, nblk);
+}
+template <class T, bool STATS, int TY = MTY>
+__global__ __launch_bounds__(NT) void k_mg_up(int nx, int ny, int P, int gx, PoisCoefT<T> c, const T *__restrict__ b,
+                                              const T *__restrict__ x2, const T *__restrict__ xc, int Pc,
+                                              T *__restrict__ z, double *pout, int nblk, const int *done) {
+    mg_up_body<T, STATS, TY>(SoloGrid{}, nx, ny, P, gx, c, b, x2, xc, Pc, z, pout, nblk, done);
 }
 
 // The coarse end of the cycle in one work-group of TT threads: every level
@@ -1062,7 +1124,7 @@ __device__ inline T tail_Ax(const TailLevel<T> &L, const T *v, size_t k) {
 }
 
 template <class T>
-__global__ __launch_bounds__(TT) void k_mg_tail(TailDesc<T> d) {
+__device__ __forceinline__ void mg_tail_body(const TailDesc<T> &d) {
     if (*d.done) return;
     const T w1 = (T)MG_W1, w2 = (T)MG_W2;
     // down: two sweeps from zero, the residual restricted to the next level
@@ -1149,6 +1211,10 @@ __global__ __launch_bounds__(TT) void k_mg_tail(TailDesc<T> d) {
         __syncthreads();
     }
 }
+template <class T>
+__global__ __launch_bounds__(TT) void k_mg_tail(TailDesc<T> d) {
+    mg_tail_body<T>(d);
+}
 
 // The coarse end of the cycle as k_mg_tail, with every level's arrays (the
 // coefficients, b, x and xt, in compact (nx+2) x (ny+2) rows) held in LDS:
@@ -1164,7 +1230,7 @@ __device__ inline T lds_Ax(const T *cx, const T *cy, const T *v, int k, int W) {
 }
 
 template <class T>
-__global__ __launch_bounds__(TT) void k_mg_tail_lds(TailDesc<T> d) {
+__device__ __forceinline__ void mg_tail_lds_body(const TailDesc<T> &d) {
     if (*d.done) return;
     extern __shared__ double tail_lds[];
     T *const sm = reinterpret_cast<T *>(tail_lds);
@@ -1338,24 +1404,32 @@ __global__ __launch_bounds__(TT) void k_mg_tail_lds(TailDesc<T> d) {
         }
     }
 }
+template <class T>
+__global__ __launch_bounds__(TT) void k_mg_tail_lds(TailDesc<T> d) {
+    mg_tail_lds_body<T>(d);
+}
 
 // One work-group sums the partials of a producer into a single group's worth
 // (so that consumers read N values instead of N per producer group).
-template <int NS, int NM = 0, int BT = NT>
-__global__ __launch_bounds__(BT) void k_reduce_partials(const double *pin, int nin, double *pout) {
+template <int NS, int NM, int BT>
+__device__ __forceinline__ void reduce_partials_body(const double *pin, int nin, double *pout) {
     double t[NS + NM];
     get_totals<NS, NM, BT>(pin, nin, t);
     if (threadIdx.x < NS + NM) pout[threadIdx.x] = t[threadIdx.x];
+}
+template <int NS, int NM = 0, int BT = NT>
+__global__ __launch_bounds__(BT) void k_reduce_partials(const double *pin, int nin, double *pout) {
+    reduce_partials_body<NS, NM, BT>(pin, nin, pout);
 }
 
 // G work-groups sum the partials of a producer into G sets (group g takes
 // the producers' groups [g nin / G, (g+1) nin / G)), stored slot-major for a
 // consumer that sums G values per slot.  Spreads a large reduction over
 // several compute units instead of one.
-template <int NS>
-__global__ __launch_bounds__(NT) void k_reduce_partials_split(const double *pin, int nin, double *pout) {
-    const int G = gridDim.x, g = blockIdx.x;
-    const int lo = (int)((long)g * nin / G), hi = (int)((long)(g + 1) * nin / G);
+template <int NS, class G>
+__device__ __forceinline__ void reduce_partials_split_body(const G &g, const double *pin, int nin, double *pout) {
+    const int ng = g.n(), ig = g.b();
+    const int lo = (int)((long)ig * nin / ng), hi = (int)((long)(ig + 1) * nin / ng);
     double a[NS];
 #pragma unroll
     for (int k = 0; k < NS; ++k) a[k] = 0.0;
@@ -1365,13 +1439,17 @@ __global__ __launch_bounds__(NT) void k_reduce_partials_split(const double *pin,
     }
     double t[NS];
     block_reduce<NS, 0>(a, t);
-    if (threadIdx.x < NS) pout[(size_t)threadIdx.x * G + g] = t[threadIdx.x];
+    if (threadIdx.x < NS) pout[(size_t)threadIdx.x * ng + ig] = t[threadIdx.x];
+}
+template <int NS>
+__global__ __launch_bounds__(NT) void k_reduce_partials_split(const double *pin, int nin, double *pout) {
+    reduce_partials_split_body<NS>(SoloGrid{}, pin, nin, pout);
 }
 constexpr int PRED_RED = 16;  // groups of the predictor CG's partial reduction
 
 // Coarsest grid: x = A^+ b with the dense pseudo-inverse on the n unknowns.
 template <class T>
-__global__ __launch_bounds__(NT) void k_mg_coarsest(int n, const int *__restrict__ idx,
+__device__ __forceinline__ void mg_coarsest_body(int n, const int *__restrict__ idx,
                                                     const double *__restrict__ pinv, const T *__restrict__ b,
                                                     T *__restrict__ x, const int *done) {
     if (*done) return;
@@ -1384,13 +1462,19 @@ __global__ __launch_bounds__(NT) void k_mg_coarsest(int n, const int *__restrict
         x[idx[i]] = (T)acc;
     }
 }
+template <class T>
+__global__ __launch_bounds__(NT) void k_mg_coarsest(int n, const int *__restrict__ idx,
+                                                    const double *__restrict__ pinv, const T *__restrict__ b,
+                                                    T *__restrict__ x, const int *done) {
+    mg_coarsest_body<T>(n, idx, pinv, b, x, done);
+}
 
 // Direction and operator for the multigrid-preconditioned solve:
 // p = (z - mean z) + beta p_old; q = A p.  Consumes the statistics written by
 // the last smoothing sweep (b.z, z, b, b.b) and, on the first iteration, |f|^2
 // from init (pinit; without it, the norm of the cycle's input b is taken).
-template <class T>
-__global__ __launch_bounds__(NT) void k_pois_dir_z(Dims d, PoisCoefT<T> pc, const T *__restrict__ z,
+template <class T, class G>
+__device__ __forceinline__ void pois_dir_z_body(const G &g, Dims d, PoisCoefT<T> pc, const T *__restrict__ z,
                                                    const T *__restrict__ pold, T *__restrict__ pnew,
                                                    T *__restrict__ q, CgState *st, int first, int par,
                                                    const double *pin, int nin, const double *pinit, int ninit,
@@ -1410,7 +1494,7 @@ __global__ __launch_bounds__(NT) void k_pois_dir_z(Dims d, PoisCoefT<T> pc, cons
     } else {
         fn2 = st->fnorm2;
     }
-    const DirStep ds = cg_decide(st, first, par, fn2, t[0], t[1], t[2], t[3]);
+    const DirStep ds = cg_decide(g, st, first, par, fn2, t[0], t[1], t[2], t[3]);
     if (ds.stop) return;
     const T beta = (T)ds.beta, m = (T)ds.mean;
     __shared__ T sp[PTY + 2][TX + 2];
@@ -1420,7 +1504,7 @@ __global__ __launch_bounds__(NT) void k_pois_dir_z(Dims d, PoisCoefT<T> pc, cons
     // every load of a phase is issued before its first use, and the tile
     // phase's operands before the barrier (as in the staged cycle kernels)
     constexpr int NS = (PTY + 2) * (TX + 2), IS = (NS + NT - 1) / NT, R = PTY / 4;
-    for_tiles(d, [&](int, int c0, int r0) {
+    for_tiles(g, d, [&](int, int c0, int r0) {
         {
             T di[IS], zv[IS], po[IS];
 #pragma unroll
@@ -1473,7 +1557,15 @@ __global__ __launch_bounds__(NT) void k_pois_dir_z(Dims d, PoisCoefT<T> pc, cons
         }
         __syncthreads();
     });
-    put_partials<1>(v, pout, d.nblk);
+    put_partials<1>(g, v, pout, d.nblk);
+}
+template <class T>
+__global__ __launch_bounds__(NT) void k_pois_dir_z(Dims d, PoisCoefT<T> pc, const T *__restrict__ z,
+                                                   const T *__restrict__ pold, T *__restrict__ pnew,
+                                                   T *__restrict__ q, CgState *st, int first, int par,
+                                                   const double *pin, int nin, const double *pinit, int ninit,
+                                                   double *pout) {
+    pois_dir_z_body<T>(SoloGrid{}, d, pc, z, pold, pnew, q, st, first, par, pin, nin, pinit, ninit, pout);
 }
 
 // ---------------------------------------------------------------------------
@@ -1638,8 +1730,8 @@ __device__ inline void pred_tile_K_row(const PredTileNx<T> &s, const T *row, siz
 // seven waves per SIMD (70 VGPRs, no spills): the launch is bound by HBM
 // latency, and more resident waves hide more of it.  With CLS the
 // coefficients come from the class table (pc.cls, pc.tab).
-template <class T, bool GEO, bool CLS = false>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(7))) void k_pred_cg(
+template <class T, bool GEO, bool CLS, class G>
+__device__ __forceinline__ void pred_cg_body(const G &g, 
     int P, int rows, int gx, int gy, size_t n, PredCoefT<T> pc, CgState *st, int it, T *__restrict__ x,
     const T *__restrict__ rin, T *__restrict__ rout, const T *__restrict__ pold, T *__restrict__ pnew,
     const T *__restrict__ qin, T *__restrict__ qout, const double *tin, int nin, double *part) {
@@ -1666,7 +1758,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(7))) void k_
     const bool conv = !breakdown && rr <= st->tol2 * fn2;
     if (!conv && !(rr < INFINITY && beta >= 0.0 && beta < INFINITY)) breakdown = true;
     const bool stop = breakdown || conv || it >= st->maxit;
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (g.b() == 0 && threadIdx.x == 0) {
         if (it == 0) st->fnorm2 = fn2;
         if (stop) {
             st->done = 1;
@@ -1676,7 +1768,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(7))) void k_
             st->stop_it = it;
         }
     }
-    const int L = logical_group(((gridDim.x + 7) / 8) * 8);
+    const int L = logical_group(g, ((g.n() + 7) / 8) * 8);
     const bool live = L < gx * gy;
     const int c0 = (L % gx) * TX, r0 = (L / gx) * HTY;
     const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
@@ -1843,7 +1935,14 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(7))) void k_
             v[6] += drx * drx + dry * dry;
         }
     }
-    put_partials<7>(v, part, gridDim.x);
+    put_partials<7>(g, v, part, g.n());
+}
+template <class T, bool GEO, bool CLS = false>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(7))) void k_pred_cg(
+    int P, int rows, int gx, int gy, size_t n, PredCoefT<T> pc, CgState *st, int it, T *__restrict__ x,
+    const T *__restrict__ rin, T *__restrict__ rout, const T *__restrict__ pold, T *__restrict__ pnew,
+    const T *__restrict__ qin, T *__restrict__ qout, const double *tin, int nin, double *part) {
+    pred_cg_body<T, GEO, CLS>(SoloGrid{}, P, rows, gx, gy, n, pc, st, it, x, rin, rout, pold, pnew, qin, qout, tin, nin, part);
 }
 
 // Predictor residual r = rhs - H x in FP64 on the tiles of k_pred_cg
@@ -1853,14 +1952,14 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(7))) void k_
 //  of the inner solve, whose start value x32 is cleared); partials
 //  (r32.r32, r32.z, z, r32, r32.r32, f.f, r.r) with z = M32^-1 r32.
 // With CLS the coefficients come from the class table, as in k_pred_cg.
-template <bool MIX, bool GEO, bool CLS = false>
-__global__ __launch_bounds__(NT) void k_pred_resid(int P, int rows, int gx, int gy, size_t n, PredCoefT<double> pc,
+template <bool MIX, bool GEO, bool CLS, class G>
+__device__ __forceinline__ void pred_resid_body(const G &g, int P, int rows, int gx, int gy, size_t n, PredCoefT<double> pc,
                                                    const double *__restrict__ rhs, const double *__restrict__ xs,
                                                    double *__restrict__ r, CgState *st, double *pout,
                                                    float *__restrict__ r32, float *__restrict__ x32,
                                                    const float *__restrict__ hd32) {
     __shared__ PredTileNx<double> s;
-    const int L = logical_group(((gridDim.x + 7) / 8) * 8);
+    const int L = logical_group(g, ((g.n() + 7) / 8) * 8);
     const bool live = L < gx * gy;
     const int c0 = (L % gx) * TX, r0 = (L / gx) * HTY;
     const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
@@ -1987,18 +2086,26 @@ __global__ __launch_bounds__(NT) void k_pred_resid(int P, int rows, int gx, int 
             }
         }
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (g.b() == 0 && threadIdx.x == 0) {
         st->done = 0;
         st->status = 0;
         st->it_final = 0;
         st->stop_it = 0x7fffffff;
     }
     if (MIX) {
-        put_partials<7>(v, pout, gridDim.x);
+        put_partials<7>(g, v, pout, g.n());
     } else {
         double w[5] = {v[0], v[1], v[2], v[3], v[4]};
-        put_partials<5>(w, pout, gridDim.x);
+        put_partials<5>(g, w, pout, g.n());
     }
+}
+template <bool MIX, bool GEO, bool CLS = false>
+__global__ __launch_bounds__(NT) void k_pred_resid(int P, int rows, int gx, int gy, size_t n, PredCoefT<double> pc,
+                                                   const double *__restrict__ rhs, const double *__restrict__ xs,
+                                                   double *__restrict__ r, CgState *st, double *pout,
+                                                   float *__restrict__ r32, float *__restrict__ x32,
+                                                   const float *__restrict__ hd32) {
+    pred_resid_body<MIX, GEO, CLS>(SoloGrid{}, P, rows, gx, gy, n, pc, rhs, xs, r, st, pout, r32, x32, hd32);
 }
 
 // conv^n (eq:convective), the predictor right-hand side (eq:pm_prediction):
@@ -2026,8 +2133,8 @@ __device__ inline bool outflow_yface(const OutflowDesc &o, int j, int i) {
     return i >= 1 && i <= o.nx && (((o.ofl & CCNS_WALL_S) && j == 0) || ((o.ofl & CCNS_WALL_N) && j == o.ny));
 }
 
-template <bool GEO, bool CLS = false>
-__global__ __launch_bounds__(NT) void k_pred_rhs(int P, int rows, int gx, int gy, size_t n, PredCoefT<double> pc,
+template <bool GEO, bool CLS, class G>
+__device__ __forceinline__ void pred_rhs_body(const G &g, int P, int rows, int gx, int gy, size_t n, PredCoefT<double> pc,
                                                  const double *__restrict__ ax, const double *__restrict__ ay,
                                                  const double *__restrict__ hbx, const double *__restrict__ hby,
                                                  const double *__restrict__ dx, const double *__restrict__ dy,
@@ -2038,7 +2145,7 @@ __global__ __launch_bounds__(NT) void k_pred_rhs(int P, int rows, int gx, int gy
                                                  double *__restrict__ xs, double rho, double gxv, double gyv,
                                                  int conv_valid, OutflowDesc of) {
     __shared__ PredTileNx<double> s;
-    const int L = logical_group(((gridDim.x + 7) / 8) * 8);
+    const int L = logical_group(g, ((g.n() + 7) / 8) * 8);
     if (L >= gx * gy) return;
     const int c0 = (L % gx) * TX, r0 = (L / gx) * HTY;
     const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
@@ -2177,13 +2284,27 @@ __global__ __launch_bounds__(NT) void k_pred_rhs(int P, int rows, int gx, int gy
         }
     }
 }
+template <bool GEO, bool CLS = false>
+__global__ __launch_bounds__(NT) void k_pred_rhs(int P, int rows, int gx, int gy, size_t n, PredCoefT<double> pc,
+                                                 const double *__restrict__ ax, const double *__restrict__ ay,
+                                                 const double *__restrict__ hbx, const double *__restrict__ hby,
+                                                 const double *__restrict__ dx, const double *__restrict__ dy,
+                                                 const double *__restrict__ ux, const double *__restrict__ uy,
+                                                 const double *__restrict__ pr, const double *__restrict__ vdx,
+                                                 const double *__restrict__ vdy, double *__restrict__ convx,
+                                                 double *__restrict__ convy, double *__restrict__ rhs,
+                                                 double *__restrict__ xs, double rho, double gxv, double gyv,
+                                                 int conv_valid, OutflowDesc of) {
+    pred_rhs_body<GEO, CLS>(SoloGrid{}, P, rows, gx, gy, n, pc, ax, ay, hbx, hby, dx, dy, ux, uy, pr, vdx, vdy, convx, convy, rhs, xs, rho, gxv, gyv, conv_valid, of);
+}
 
 // ---------------------------------------------------------------------------
 // corrector, pressure update and diagnostics
 // ---------------------------------------------------------------------------
 
 // U^{n+1} = U* - (tau/rho) (A/V_f) dPhi on pressure-coupled faces (eq:pm_projection).
-__global__ __launch_bounds__(NT) void k_correct(Dims d, const double *__restrict__ gx, const double *__restrict__ gy,
+template <class G>
+__device__ __forceinline__ void correct_body(const G &g, Dims d, const double *__restrict__ gx, const double *__restrict__ gy,
                                                 const double *__restrict__ usx, const double *__restrict__ usy,
                                                 const double *__restrict__ phi, double *__restrict__ ux,
                                                 double *__restrict__ uy, double s) {
@@ -2196,10 +2317,16 @@ __global__ __launch_bounds__(NT) void k_correct(Dims d, const double *__restrict
         const size_t ke = k + 1 < d.n ? k + 1 : k, kn = k + P < d.n ? k + P : k;
         return In{gx[k], gy[k], usx[k], usy[k], phi[k], phi[ke], phi[kn]};
     };
-    for_cells_batched<TY / 4>(d, load, [&](int, int, int, size_t k, const In &v) {
+    for_cells_batched<TY / 4>(g, d, load, [&](int, int, int, size_t k, const In &v) {
         ux[k] = (v.g1 != 0.0) ? v.us - s * v.g1 * (v.pe - v.p0) : v.us;
         uy[k] = (v.g2 != 0.0) ? v.vs - s * v.g2 * (v.pn - v.p0) : v.vs;
     });
+}
+__global__ __launch_bounds__(NT) void k_correct(Dims d, const double *__restrict__ gx, const double *__restrict__ gy,
+                                                const double *__restrict__ usx, const double *__restrict__ usy,
+                                                const double *__restrict__ phi, double *__restrict__ ux,
+                                                double *__restrict__ uy, double s) {
+    correct_body(SoloGrid{}, d, gx, gy, usx, usy, phi, ux, uy, s);
 }
 
 // Force of the fluid on the bodies: the momentum it exchanges with them
@@ -2260,13 +2387,14 @@ struct DiagCoef {
 
 // Divergence max / net flux, kinetic energy and momentum of U; optionally
 // P += Phi - (tau mu / 2 rho) V^-1 L Phi (eq:pm_update).
-__global__ __launch_bounds__(NT) void k_diag(Dims d, DiagCoef c, const double *__restrict__ ux,
+template <class G>
+__device__ __forceinline__ void diag_body(const G &g, Dims d, DiagCoef c, const double *__restrict__ ux,
                                              const double *__restrict__ uy, const double *__restrict__ phi,
                                              double *__restrict__ pr, double pcoef, int update_p, double rho,
                                              double *pout) {
     const size_t P = d.pitch;
     double v[5] = {0, 0, 0, 0, 0};
-    for_cells(d, [&](int, int j, int i, size_t k) {
+    for_cells(g, d, [&](int, int j, int i, size_t k) {
         v[2] += rho * c.vu[k] * ux[k];
         v[3] += rho * c.vv[k] * uy[k];
         if (i < 1 || i > d.nx || j < 1 || j > d.ny) return;
@@ -2284,10 +2412,16 @@ __global__ __launch_bounds__(NT) void k_diag(Dims d, DiagCoef c, const double *_
             }
         }
     });
-    put_partials<4, 1>(v, pout, d.nblk);
+    put_partials<4, 1>(g, v, pout, d.nblk);
+}
+__global__ __launch_bounds__(NT) void k_diag(Dims d, DiagCoef c, const double *__restrict__ ux,
+                                             const double *__restrict__ uy, const double *__restrict__ phi,
+                                             double *__restrict__ pr, double pcoef, int update_p, double rho,
+                                             double *pout) {
+    diag_body(SoloGrid{}, d, c, ux, uy, phi, pr, pcoef, update_p, rho, pout);
 }
 
-__global__ __launch_bounds__(NT) void k_diag_final(const double *pin, int nin, DiagState *ds) {
+__device__ __forceinline__ void diag_final_body(const double *pin, int nin, DiagState *ds) {
     double t[5];
     get_totals<4, 1>(pin, nin, t);
     if (threadIdx.x == 0) {
@@ -2297,6 +2431,9 @@ __global__ __launch_bounds__(NT) void k_diag_final(const double *pin, int nin, D
         ds->momy = t[3];
         ds->divmax = t[4];
     }
+}
+__global__ __launch_bounds__(NT) void k_diag_final(const double *pin, int nin, DiagState *ds) {
+    diag_final_body(pin, nin, ds);
 }
 
 // U = D on every face that is not a velocity unknown (vm = 0 there).
@@ -2440,10 +2577,12 @@ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 enum Part { PB_RHS, PB_INIT, PB_DIR, PB_UPD, PB_DIAG, PB_MG, PB_COUNT };
 
 // Multigrid levels: grid sizes from the fine one by halving (rounding up)
-// until both sides are at most 16 cells.
+// until both sides are at most 16 cells, and at least one coarse level (the
+// finest level's up-sweep writes the statistics the CG reads, so even a grid
+// of at most 16 x 16 cells gets a cycle level above its coarsest grid).
 std::vector<std::pair<int, int>> mg_sizes(int nx, int ny) {
     std::vector<std::pair<int, int>> v{{nx, ny}};
-    while (v.back().first > 16 || v.back().second > 16)
+    while (v.size() < 2 || v.back().first > 16 || v.back().second > 16)
         v.push_back({(v.back().first + 1) / 2, (v.back().second + 1) / 2});
     return v;
 }
@@ -3113,6 +3252,14 @@ void resolve_mg_forms(ccns_ctx *c, const std::vector<ccns_ctx::LevelT<T>> &mg, u
     }
 }
 
+// Work-groups of a cycle kernel of the given form on a level of nx x ny
+// cells (one tile of 64 x the form's rows each, a multiple of 8 groups).
+int mg_form_groups(int nx, int ny, int form) {
+    const int ty = form == MGF_PLAIN_SHORT ? MTY_SMALL : form == MGF_STAGED_LDS_HALF ? MTY / 2 : MTY;
+    const int gx = (nx + TX - 1) / TX;
+    return ((gx * ((ny + ty - 1) / ty) + 7) / 8) * 8;
+}
+
 // z = V(b) on level l of a hierarchy; returns the array holding the result.
 // On level 0 the last kernel also writes the residual statistics, reduced to
 // one group in PB_MG.  Every kernel returns at once when *done is set (a
@@ -3153,11 +3300,7 @@ T *vcycle(ccns_ctx *c, std::vector<ccns_ctx::LevelT<T>> &mg, size_t l, const T *
     const int gx = (L.L.nx + TX - 1) / TX;
     ccns_ctx::LevelT<T> &C = mg[l + 1];
     const int fd = c->mgf[sizeof(T) == 8][0][l], fu = c->mgf[sizeof(T) == 8][1][l];
-    auto blocks = [&](int form) {
-        const int ty = form == MGF_PLAIN_SHORT ? MTY_SMALL : form == MGF_STAGED_LDS_HALF ? MTY / 2 : MTY;
-        return ((gx * ((L.L.ny + ty - 1) / ty) + 7) / 8) * 8;
-    };
-    const int nbd = blocks(fd), nbu = blocks(fu);
+    const int nbd = mg_form_groups(L.L.nx, L.L.ny, fd), nbu = mg_form_groups(L.L.nx, L.L.ny, fu);
     switch (fd) {
     case MGF_STAGED:
         k_mg_down_staged<T><<<nbd, NT, 0, s>>>(L.L.nx, L.L.ny, L.L.pitch, gx, pc, b, L.x, C.L.pitch, C.L.nx,
@@ -4030,11 +4173,658 @@ int ccns_mg_levels(const ccns_ctx *c, int *nx, int *ny, int *forms, int cap) {
 
 }  // extern "C"
 
+// ===========================================================================
+// fused batches: one launch per phase over the tiles of every simulation
+// ===========================================================================
+
+namespace {
+
+// A simulation of a fused batch as the batched kernels see it: the
+// arguments its solo launches take, gathered once.  The cycle levels and
+// the coarse end are those of the context's multigrid hierarchy.
+constexpr int BATCH_LEVELS = 16;
+struct BatchLevel {
+    int nx, ny, P, gx;         // the level
+    PoisCoef pc;
+    const double *b;
+    double *x, *xt;
+    int Pc, nxc, nyc;          // the next coarser level
+    const double *dinvc;
+    double *bc;
+    const double *xc;          // the coarser level's result (its up-sweep, or the coarse end)
+    int fd, fu, nbd, nbu;      // kernel forms and work-groups of the down- and up-sweep
+};
+enum BatchBottom { BOT_COARSEST = 0, BOT_TAIL_LDS = 1, BOT_TAIL = 2 };
+struct BatchSim {
+    int P, rows, pgx, pgy, pnb;  // layout; predictor tiles and work-groups
+    size_t n;
+    PredCoefT<double> pd;
+    double rho, grav_x, grav_y, rho_tau, tau_rho, pcoef;
+    int conv_valid;
+    OutflowDesc of;
+    double *a[A_COUNT];
+    double *part[PB_COUNT];
+    CgState *st_pred, *st_pois;
+    DiagState *diag;
+    DiagCoef dgc;
+    Dims dc, dp;
+    int nl;                      // work-groups of the CG update
+    int ncyc;                    // cycle levels
+    BatchLevel lv[BATCH_LEVELS];
+    int bottom;                  // BatchBottom
+    TailDesc<double> tail;
+    int tail_bytes;              // LDS the tail's levels take (BOT_TAIL_LDS)
+    int ncoarse;                 // the coarsest grid (BOT_COARSEST)
+    const int *pidx;
+    const double *pinv;
+    const double *cb;
+    double *cxo;
+    const double *z;             // the cycle's result on the finest level
+};
+
+// Work-group table entries: simulation index (high bits) and the group's
+// index within that simulation's grid.
+constexpr int BATCH_SIM_SHIFT = 22;
+constexpr unsigned BATCH_LOCAL_MASK = (1u << BATCH_SIM_SHIFT) - 1;
+constexpr int BATCH_MAX_SIMS = 1 << (32 - BATCH_SIM_SHIFT);
+
+// The batched kernel of an operation: work-group blockIdx.x runs group
+// (map & mask) of simulation (map >> shift), with u the launch's uniform
+// argument (the CG iteration or the cycle level).
+template <class Op>
+__global__ __launch_bounds__(Op::BT) void k_batch(const BatchSim *__restrict__ sims, const unsigned *__restrict__ map,
+                                                  int u) {
+    const unsigned e = map[blockIdx.x];
+    const BatchSim &s = sims[e >> BATCH_SIM_SHIFT];
+    Op::run(SubGrid{(int)(e & BATCH_LOCAL_MASK), Op::groups(s, u)}, s, u);
+}
+// The same with the register budget of k_pred_cg (seven waves per SIMD).
+template <class Op>
+__global__ __launch_bounds__(Op::BT) __attribute__((amdgpu_waves_per_eu(7))) void k_batch_w7(
+    const BatchSim *__restrict__ sims, const unsigned *__restrict__ map, int u) {
+    const unsigned e = map[blockIdx.x];
+    const BatchSim &s = sims[e >> BATCH_SIM_SHIFT];
+    Op::run(SubGrid{(int)(e & BATCH_LOCAL_MASK), Op::groups(s, u)}, s, u);
+}
+
+template <bool GEO, bool CLS>
+struct OpPredRhs {
+    static constexpr int BT = NT;
+    __device__ static int groups(const BatchSim &s, int) { return s.pnb; }
+    __device__ static void run(const SubGrid &g, const BatchSim &s, int) {
+        pred_rhs_body<GEO, CLS>(g, s.P, s.rows, s.pgx, s.pgy, s.n, s.pd, s.a[A_AX], s.a[A_AY], s.a[A_HBX],
+                                s.a[A_HBY], s.a[A_DX], s.a[A_DY], s.a[A_UX], s.a[A_UY], s.a[A_P], s.a[A_VDX],
+                                s.a[A_VDY], s.a[A_CONVX], s.a[A_CONVY], s.a[A_RHSX], s.a[A_USX], s.rho, s.grav_x,
+                                s.grav_y, s.conv_valid, s.of);
+    }
+};
+template <bool GEO, bool CLS>
+struct OpPredResid {
+    static constexpr int BT = NT;
+    __device__ static int groups(const BatchSim &s, int) { return s.pnb; }
+    __device__ static void run(const SubGrid &g, const BatchSim &s, int) {
+        pred_resid_body<false, GEO, CLS>(g, s.P, s.rows, s.pgx, s.pgy, s.n, s.pd, s.a[A_RHSX], s.a[A_USX],
+                                         s.a[A_PRX], s.st_pred, s.part[PB_RHS], nullptr, nullptr, nullptr);
+    }
+};
+// Launch u = it of the predictor CG (r, p and H p alternate between two
+// buffers by the parity of it, as in the solo solve).
+template <bool GEO, bool CLS>
+struct OpPredCg {
+    static constexpr int BT = NT;
+    __device__ static int groups(const BatchSim &s, int) { return s.pnb; }
+    __device__ static void run(const SubGrid &g, const BatchSim &s, int it) {
+        const int b = it & 1;
+        double *r[2] = {s.a[A_PRX], s.a[A_PR1X]}, *p[2] = {s.a[A_PP0X], s.a[A_PP1X]},
+               *q[2] = {s.a[A_PQX], s.a[A_PQ1X]};
+        pred_cg_body<double, GEO, CLS>(g, s.P, s.rows, s.pgx, s.pgy, s.n, s.pd, s.st_pred, it, s.a[A_USX],
+                                       it == 0 ? r[0] : r[b ^ 1], r[b], p[b ^ 1], p[b], q[b ^ 1], q[b],
+                                       it == 0 ? s.part[PB_INIT] : s.part[PB_UPD], it == 0 ? 1 : PRED_RED,
+                                       s.part[PB_DIR]);
+    }
+};
+struct OpPredSplit {
+    static constexpr int BT = NT;
+    __device__ static int groups(const BatchSim &, int) { return PRED_RED; }
+    __device__ static void run(const SubGrid &g, const BatchSim &s, int) {
+        reduce_partials_split_body<7>(g, s.part[PB_DIR], s.pnb, s.part[PB_UPD]);
+    }
+};
+// One-group reductions: the predictor residual's statistics (u = 0), the
+// cycle's statistics (u = 1), the diagnostics (u = 2).
+struct OpReduce {
+    static constexpr int BT = NT;
+    __device__ static int groups(const BatchSim &, int) { return 1; }
+    __device__ static void run(const SubGrid &, const BatchSim &s, int u) {
+        if (u == 0)
+            reduce_partials_body<5, 0, NT>(s.part[PB_RHS], s.pnb, s.part[PB_INIT]);
+        else if (u == 1)
+            reduce_partials_body<4, 0, NT>(s.part[PB_UPD], s.lv[0].nbu, s.part[PB_MG]);
+        else
+            diag_final_body(s.part[PB_DIAG], s.dc.nblk, s.diag);
+    }
+};
+struct OpPoisRhs {
+    static constexpr int BT = NT;
+    __device__ static int groups(const BatchSim &s, int) { return s.dc.nblk; }
+    __device__ static void run(const SubGrid &g, const BatchSim &s, int) {
+        pois_rhs_body(g, s.dc, PoisCoef{s.a[A_CX], s.a[A_CY], s.a[A_DINV]}, s.a[A_AX], s.a[A_AY], s.a[A_HET],
+                      s.a[A_USX], s.a[A_USY], s.a[A_B], s.rho_tau, s.part[PB_RHS]);
+    }
+};
+struct OpPoisInit {
+    static constexpr int BT = NT;
+    __device__ static int groups(const BatchSim &s, int) { return s.dc.nblk; }
+    __device__ static void run(const SubGrid &g, const BatchSim &s, int) {
+        pois_init_body<false>(g, s.dc, PoisCoef{s.a[A_CX], s.a[A_CY], s.a[A_DINV]}, s.a[A_B], s.a[A_PHI], s.a[A_R],
+                              s.st_pois, s.part[PB_RHS], s.dc.nblk, s.part[PB_INIT], nullptr, nullptr, nullptr);
+    }
+};
+// The multigrid CG's direction and update of iteration u = it; the search
+// directions alternate between A_P0 and A_P1 from A_P0 (the first
+// direction reads no old one).
+struct OpDirZ {
+    static constexpr int BT = NT;
+    __device__ static int groups(const BatchSim &s, int) { return s.dp.nblk; }
+    __device__ static void run(const SubGrid &g, const BatchSim &s, int it) {
+        double *pold = (it & 1) ? s.a[A_P1] : s.a[A_P0], *pnew = (it & 1) ? s.a[A_P0] : s.a[A_P1];
+        pois_dir_z_body<double>(g, s.dp, PoisCoef{s.a[A_CX], s.a[A_CY], s.a[A_DINV]}, s.z, pold, pnew, s.a[A_Q],
+                                s.st_pois, it == 0 ? 1 : 0, it & 1, s.part[PB_MG], 1, s.part[PB_INIT], s.dc.nblk,
+                                s.part[PB_DIR]);
+    }
+};
+struct OpUpdate {
+    static constexpr int BT = UT;
+    __device__ static int groups(const BatchSim &s, int) { return s.nl; }
+    __device__ static void run(const SubGrid &g, const BatchSim &s, int it) {
+        const double *pnew = (it & 1) ? s.a[A_P0] : s.a[A_P1];
+        cg_update_body<double, false>(g, s.n, s.nl, s.a[A_DINV], s.a[A_PHI], s.a[A_R], pnew, s.a[A_Q], s.st_pois,
+                                      it & 1, s.part[PB_DIR], s.dp.nblk, s.part[PB_UPD]);
+    }
+};
+// Down- and up-sweep of cycle level u in form F (MgForm).
+template <int F>
+struct OpMgDown {
+    static constexpr int BT = NT;
+    __device__ static int groups(const BatchSim &s, int l) { return s.lv[l].nbd; }
+    __device__ static void run(const SubGrid &g, const BatchSim &s, int l) {
+        const BatchLevel &L = s.lv[l];
+        const int *done = &s.st_pois->done;
+        if constexpr (F == MGF_STAGED)
+            mg_down_staged_body<double>(g, L.nx, L.ny, L.P, L.gx, L.pc, L.b, L.x, L.Pc, L.nxc, L.nyc, L.dinvc, L.bc,
+                                        done);
+        else if constexpr (F == MGF_STAGED_LDS)
+            mg_down_lds_body<double, MTY>(g, L.nx, L.ny, L.P, L.gx, L.pc, L.b, L.x, L.Pc, L.nxc, L.nyc, L.dinvc,
+                                          L.bc, done);
+        else if constexpr (F == MGF_STAGED_LDS_HALF)
+            mg_down_lds_body<double, MTY / 2>(g, L.nx, L.ny, L.P, L.gx, L.pc, L.b, L.x, L.Pc, L.nxc, L.nyc, L.dinvc,
+                                              L.bc, done);
+        else if constexpr (F == MGF_PLAIN)
+            mg_down_body<double, MTY>(g, L.nx, L.ny, L.P, L.gx, L.pc, L.b, L.x, L.Pc, L.nxc, L.nyc, L.dinvc, L.bc,
+                                      done);
+        else
+            mg_down_body<double, MTY_SMALL>(g, L.nx, L.ny, L.P, L.gx, L.pc, L.b, L.x, L.Pc, L.nxc, L.nyc, L.dinvc,
+                                            L.bc, done);
+    }
+};
+// The finest level's up-sweep (STATS) writes the statistics of z.
+template <int F, bool STATS>
+struct OpMgUp {
+    static constexpr int BT = NT;
+    __device__ static int groups(const BatchSim &s, int l) { return s.lv[l].nbu; }
+    __device__ static void run(const SubGrid &g, const BatchSim &s, int l) {
+        const BatchLevel &L = s.lv[l];
+        const int *done = &s.st_pois->done;
+        double *po = STATS ? s.part[PB_UPD] : nullptr;
+        if constexpr (F == MGF_STAGED)
+            mg_up_staged_body<double, STATS>(g, L.nx, L.ny, L.P, L.gx, L.pc, L.b, L.x, L.xc, L.Pc, L.xt, po, L.nbu,
+                                             done);
+        else if constexpr (F == MGF_STAGED_LDS)
+            mg_up_lds_body<double, STATS, MTY>(g, L.nx, L.ny, L.P, L.gx, L.pc, L.b, L.x, L.xc, L.Pc, L.xt, po,
+                                               L.nbu, done);
+        else if constexpr (F == MGF_STAGED_LDS_HALF)
+            mg_up_lds_body<double, STATS, MTY / 2>(g, L.nx, L.ny, L.P, L.gx, L.pc, L.b, L.x, L.xc, L.Pc, L.xt, po,
+                                                   L.nbu, done);
+        else if constexpr (F == MGF_PLAIN)
+            mg_up_body<double, STATS, MTY>(g, L.nx, L.ny, L.P, L.gx, L.pc, L.b, L.x, L.xc, L.Pc, L.xt, po, L.nbu,
+                                           done);
+        else
+            mg_up_body<double, STATS, MTY_SMALL>(g, L.nx, L.ny, L.P, L.gx, L.pc, L.b, L.x, L.xc, L.Pc, L.xt, po,
+                                                 L.nbu, done);
+    }
+};
+struct OpCoarsest {
+    static constexpr int BT = NT;
+    __device__ static int groups(const BatchSim &, int) { return 1; }
+    __device__ static void run(const SubGrid &, const BatchSim &s, int) {
+        mg_coarsest_body<double>(s.ncoarse, s.pidx, s.pinv, s.cb, s.cxo, &s.st_pois->done);
+    }
+};
+template <bool LDS>
+struct OpTail {
+    static constexpr int BT = TT;
+    __device__ static int groups(const BatchSim &, int) { return 1; }
+    __device__ static void run(const SubGrid &, const BatchSim &s, int) {
+        if constexpr (LDS)
+            mg_tail_lds_body<double>(s.tail);
+        else
+            mg_tail_body<double>(s.tail);
+    }
+};
+struct OpCorrect {
+    static constexpr int BT = NT;
+    __device__ static int groups(const BatchSim &s, int) { return s.dc.nblk; }
+    __device__ static void run(const SubGrid &g, const BatchSim &s, int) {
+        correct_body(g, s.dc, s.a[A_GX], s.a[A_GY], s.a[A_USX], s.a[A_USY], s.a[A_PHI], s.a[A_UX], s.a[A_UY],
+                     s.tau_rho);
+    }
+};
+struct OpDiag {
+    static constexpr int BT = NT;
+    __device__ static int groups(const BatchSim &s, int) { return s.dc.nblk; }
+    __device__ static void run(const SubGrid &g, const BatchSim &s, int) {
+        diag_body(g, s.dc, s.dgc, s.a[A_UX], s.a[A_UY], s.a[A_PHI], s.a[A_P], s.pcoef, 1, s.rho, s.part[PB_DIAG]);
+    }
+};
+
+// Copies every simulation's solver state (which = 0: predictor, 1:
+// pressure) or diagnostics (which = 2) into one array for a single read-back.
+__global__ __launch_bounds__(NT) void k_batch_gather(const BatchSim *__restrict__ sims, int n, int which,
+                                                     CgState *__restrict__ cg, DiagState *__restrict__ dg) {
+    const int k = blockIdx.x * NT + threadIdx.x;
+    if (k >= n) return;
+    if (which == 0)
+        cg[k] = *sims[k].st_pred;
+    else if (which == 1)
+        cg[k] = *sims[k].st_pois;
+    else
+        dg[k] = *sims[k].diag;
+}
+
+// A launch of the fused batch: its slice of the work-group table.
+struct BatchTable {
+    size_t off = 0;
+    int nblk = 0;
+};
+
+}  // namespace
+
 struct ccns_batch {
     std::vector<ccns_ctx *> sims;
     std::vector<int> order;  // simulation indices, largest grid first
-    int nthreads;
+    int nthreads = 0;
+    // fused batches only
+    bool fused = false;
+    hipStream_t stream = nullptr;
+    BatchSim *dsims = nullptr;      // device copies of the descriptors
+    unsigned *dmap = nullptr;       // work-group tables
+    CgState *dcg = nullptr, *hcg = nullptr;       // gathered solver states (device, pinned host)
+    DiagState *ddg = nullptr, *hdg = nullptr;     // gathered diagnostics
+    std::vector<BatchSim> hsims;
+    std::vector<unsigned char> forms;  // the cycle forms the tables were built for
+    size_t map_cap = 0;
+    int maxcyc = 0, tail_lds = 0;
+    BatchTable pred[4], one, split, dc, dp, upd, correct;
+    BatchTable down[BATCH_LEVELS][6], up[BATCH_LEVELS][6], bot[3];
 };
+
+namespace {
+
+// The descriptor of context c (precision 0, multigrid preconditioner).
+BatchSim batch_sim(ccns_ctx *c) {
+    BatchSim s{};
+    const Layout &L = c->w.L;
+    s.P = (int)L.pitch;
+    s.rows = (int)L.rows;
+    s.pgx = (int)(L.pitch / TX);
+    s.pgy = (int)((L.rows + HTY - 1) / HTY);
+    s.pnb = ((s.pgx * s.pgy + 7) / 8) * 8;
+    s.n = L.n;
+    s.pd = pred_coef_t(c);
+    if (c->ncls) {
+        s.pd.cls = c->cls;
+        s.pd.tab = c->tab;
+    }
+    const ccns_params &p = c->prm;
+    s.rho = p.rho;
+    s.grav_x = p.gx;
+    s.grav_y = p.gy;
+    s.rho_tau = p.rho / p.tau;
+    s.tau_rho = p.tau / p.rho;
+    s.pcoef = p.tau * p.mu / (2.0 * p.rho);
+    s.conv_valid = c->conv_valid;
+    s.of = outflow_desc(c);
+    for (int k = 0; k < A_COUNT; ++k) s.a[k] = c->a[k];
+    for (int k = 0; k < PB_COUNT; ++k) s.part[k] = c->part[k];
+    s.st_pred = c->st_pred;
+    s.st_pois = c->st_pois;
+    s.diag = c->diag;
+    s.dgc = DiagCoef{c->a[A_AX], c->a[A_AY], c->a[A_HET], c->a[A_DINV], c->a[A_VUR], c->a[A_VVR],
+                     c->a[A_VU], c->a[A_VV], c->a[A_CX], c->a[A_CY], c->a[A_VINV]};
+    s.dc = c->dc;
+    s.dp = c->dp;
+    s.nl = update_blocks(L.n);
+    auto &mg = c->mg;
+    const int ncyc = (int)cycle_levels(mg);
+    s.ncyc = ncyc;
+    // the coarse end below the cycle levels: the coarsest grid's
+    // pseudo-inverse, or the one-group tail of the small levels
+    const size_t ts = (size_t)ncyc;
+    const double *bottom_out;
+    if (ts + 1 == mg.size()) {
+        s.bottom = BOT_COARSEST;
+        s.ncoarse = c->ncoarse_act;
+        s.pidx = c->pidx;
+        s.pinv = c->pinv;
+        s.cb = mg[ts].b;
+        s.cxo = mg[ts].x;
+        bottom_out = mg[ts].x;
+    } else {
+        TailDesc<double> &d = s.tail;
+        d.nlev = (int)(mg.size() - ts);
+        for (int t = 0; t < d.nlev; ++t) {
+            ccns_ctx::Level &M = mg[ts + t];
+            d.lv[t] = TailLevel<double>{M.cx, M.cy, M.dinv, M.b, M.x, M.xt, M.L.nx, M.L.ny, (int)M.L.pitch};
+        }
+        d.ncoarse = c->ncoarse_act;
+        d.idx = c->pidx;
+        d.pinv = c->pinv;
+        d.done = &c->st_pois->done;
+        d.out = d.nlev >= 2 ? mg[ts].xt : mg[ts].x;
+        size_t elems = 0;
+        for (int t = 0; t < d.nlev; ++t) {
+            d.lofs[t] = (int)elems;
+            elems += 6 * (size_t)(d.lv[t].nx + 2) * (d.lv[t].ny + 2);
+        }
+        s.bottom = elems * sizeof(double) <= (size_t)c->tail_lds ? BOT_TAIL_LDS : BOT_TAIL;
+        s.tail_bytes = (int)(elems * sizeof(double));
+        bottom_out = d.out;
+    }
+    for (int l = 0; l < ncyc; ++l) {
+        ccns_ctx::Level &F = mg[l], &C = mg[l + 1];
+        BatchLevel &v = s.lv[l];
+        v.nx = F.L.nx;
+        v.ny = F.L.ny;
+        v.P = (int)F.L.pitch;
+        v.gx = (F.L.nx + TX - 1) / TX;
+        v.pc = PoisCoef{F.cx, F.cy, F.dinv};
+        v.b = F.b;
+        v.x = F.x;
+        v.xt = F.xt;
+        v.Pc = (int)C.L.pitch;
+        v.nxc = C.L.nx;
+        v.nyc = C.L.ny;
+        v.dinvc = C.dinv;
+        v.bc = C.b;
+        v.xc = l + 1 < ncyc ? mg[l + 1].xt : bottom_out;
+        v.fd = c->mgf[1][0][l];
+        v.fu = c->mgf[1][1][l];
+        v.nbd = mg_form_groups(v.nx, v.ny, v.fd);
+        v.nbu = mg_form_groups(v.nx, v.ny, v.fu);
+    }
+    s.z = ncyc >= 1 ? mg[0].xt : bottom_out;
+    return s;
+}
+
+int pred_variant(const ccns_ctx *c) { return (c->prm.visc_form == 0 ? 1 : 0) | (c->ncls ? 2 : 0); }
+
+// Builds the descriptors and the work-group tables of every launch (the
+// simulations in the batch's order, largest first, so that the big grids'
+// groups are dispatched first), and uploads them.
+ccns_status batch_build(ccns_batch *b) {
+    const int n = (int)b->sims.size();
+    b->hsims.resize(n);
+    b->forms.clear();
+    b->maxcyc = 0;
+    b->tail_lds = 0;
+    for (int k = 0; k < n; ++k) {
+        ccns_ctx *c = b->sims[k];
+        // every level's forms resolved, the finest level's up-sweep in a
+        // form that writes the statistics (1-3), at least one cycle level
+        const int ncyc = (int)cycle_levels(c->mg);
+        if (ncyc < 1 || ncyc > BATCH_LEVELS) return CCNS_EINVAL;
+        for (int l = 0; l < ncyc; ++l) {
+            const int fd = c->mgf[1][0][l], fu = c->mgf[1][1][l];
+            if (fd < MGF_STAGED || fd > MGF_STAGED_LDS_HALF || fu < MGF_STAGED || fu > MGF_STAGED_LDS_HALF ||
+                (l == 0 && fu > MGF_PLAIN))
+                return CCNS_EINVAL;
+        }
+        b->hsims[k] = batch_sim(c);
+        b->forms.insert(b->forms.end(), &c->mgf[1][0][0], &c->mgf[1][0][0] + 2 * 16);
+        b->maxcyc = std::max(b->maxcyc, b->hsims[k].ncyc);
+        if (b->hsims[k].bottom == BOT_TAIL_LDS) b->tail_lds = std::max(b->tail_lds, b->hsims[k].tail_bytes);
+    }
+    // the LDS-resident coarse ends take up to the context's budget of dynamic LDS
+    if (b->tail_lds > 0 && hipFuncSetAttribute((const void *)k_batch<OpTail<true>>,
+                                               hipFuncAttributeMaxDynamicSharedMemorySize,
+                                               b->tail_lds) != hipSuccess)
+        return CCNS_EDEVICE;
+    std::vector<unsigned> map;
+    bool ok = true;
+    auto table = [&](auto pick, auto groups) {
+        BatchTable t;
+        t.off = map.size();
+        for (int k : b->order) {
+            if (!pick(k)) continue;
+            const long gcount = groups(k);
+            if (gcount > (long)BATCH_LOCAL_MASK + 1) ok = false;
+            for (long g = 0; g < gcount && ok; ++g) map.push_back(((unsigned)k << BATCH_SIM_SHIFT) | (unsigned)g);
+        }
+        t.nblk = (int)(map.size() - t.off);
+        return t;
+    };
+    const auto &S = b->hsims;
+    auto all = [](int) { return true; };
+    for (int v = 0; v < 4; ++v)
+        b->pred[v] = table([&](int k) { return pred_variant(b->sims[k]) == v; }, [&](int k) { return S[k].pnb; });
+    b->one = table(all, [](int) { return 1; });
+    b->split = table(all, [](int) { return PRED_RED; });
+    b->dc = table(all, [&](int k) { return S[k].dc.nblk; });
+    b->dp = table(all, [&](int k) { return S[k].dp.nblk; });
+    b->upd = table(all, [&](int k) { return S[k].nl; });
+    for (int l = 0; l < BATCH_LEVELS; ++l)
+        for (int f = 0; f < 6; ++f) {
+            b->down[l][f] = table([&](int k) { return l < S[k].ncyc && S[k].lv[l].fd == f; },
+                                  [&](int k) { return S[k].lv[l].nbd; });
+            b->up[l][f] = table([&](int k) { return l < S[k].ncyc && S[k].lv[l].fu == f; },
+                                [&](int k) { return S[k].lv[l].nbu; });
+        }
+    for (int t = 0; t < 3; ++t) b->bot[t] = table([&](int k) { return S[k].bottom == t; }, [](int) { return 1; });
+    if (!ok) return CCNS_EINVAL;
+    if (map.size() > b->map_cap) {
+        if (b->dmap) (void)hipFree(b->dmap);
+        b->dmap = nullptr;
+        if (hipMalloc(&b->dmap, map.size() * sizeof(unsigned)) != hipSuccess) return CCNS_ENOMEM;
+        b->map_cap = map.size();
+    }
+    if (hipMemcpyAsync(b->dmap, map.data(), map.size() * sizeof(unsigned), hipMemcpyHostToDevice, b->stream) !=
+            hipSuccess ||
+        hipMemcpyAsync(b->dsims, S.data(), S.size() * sizeof(BatchSim), hipMemcpyHostToDevice, b->stream) !=
+            hipSuccess ||
+        hipStreamSynchronize(b->stream) != hipSuccess)
+        return CCNS_EDEVICE;
+    return CCNS_OK;
+}
+
+template <class Op>
+void blaunch(ccns_batch *b, const BatchTable &t, int u, size_t lds = 0) {
+    if (t.nblk > 0)
+        hipLaunchKernelGGL(k_batch<Op>, dim3(t.nblk), dim3(Op::BT), lds, b->stream, b->dsims, b->dmap + t.off, u);
+}
+template <class Op>
+void blaunch_w7(ccns_batch *b, const BatchTable &t, int u) {
+    if (t.nblk > 0)
+        hipLaunchKernelGGL(k_batch_w7<Op>, dim3(t.nblk), dim3(Op::BT), 0, b->stream, b->dsims, b->dmap + t.off, u);
+}
+
+// One V-cycle of every simulation on its finest level's residual: the
+// down-sweeps level by level, the coarse ends, the up-sweeps back up, and
+// the reduction of the statistics of z.
+void batch_vcycle(ccns_batch *b) {
+    for (int l = 0; l < b->maxcyc; ++l) {
+        blaunch<OpMgDown<MGF_STAGED>>(b, b->down[l][MGF_STAGED], l);
+        blaunch<OpMgDown<MGF_STAGED_LDS>>(b, b->down[l][MGF_STAGED_LDS], l);
+        blaunch<OpMgDown<MGF_PLAIN>>(b, b->down[l][MGF_PLAIN], l);
+        blaunch<OpMgDown<MGF_PLAIN_SHORT>>(b, b->down[l][MGF_PLAIN_SHORT], l);
+        blaunch<OpMgDown<MGF_STAGED_LDS_HALF>>(b, b->down[l][MGF_STAGED_LDS_HALF], l);
+    }
+    blaunch<OpCoarsest>(b, b->bot[BOT_COARSEST], 0);
+    blaunch<OpTail<true>>(b, b->bot[BOT_TAIL_LDS], 0, (size_t)b->tail_lds);
+    blaunch<OpTail<false>>(b, b->bot[BOT_TAIL], 0);
+    for (int l = b->maxcyc - 1; l >= 1; --l) {
+        blaunch<OpMgUp<MGF_STAGED, false>>(b, b->up[l][MGF_STAGED], l);
+        blaunch<OpMgUp<MGF_STAGED_LDS, false>>(b, b->up[l][MGF_STAGED_LDS], l);
+        blaunch<OpMgUp<MGF_PLAIN, false>>(b, b->up[l][MGF_PLAIN], l);
+        blaunch<OpMgUp<MGF_PLAIN_SHORT, false>>(b, b->up[l][MGF_PLAIN_SHORT], l);
+        blaunch<OpMgUp<MGF_STAGED_LDS_HALF, false>>(b, b->up[l][MGF_STAGED_LDS_HALF], l);
+    }
+    blaunch<OpMgUp<MGF_STAGED, true>>(b, b->up[0][MGF_STAGED], 0);
+    blaunch<OpMgUp<MGF_STAGED_LDS, true>>(b, b->up[0][MGF_STAGED_LDS], 0);
+    blaunch<OpMgUp<MGF_PLAIN, true>>(b, b->up[0][MGF_PLAIN], 0);
+    blaunch<OpReduce>(b, b->one, 1);
+}
+
+// Reads every simulation's solver state (which = 0, 1) or diagnostics (2)
+// after the work queued so far.
+ccns_status batch_read(ccns_batch *b, int which) {
+    const int n = (int)b->sims.size();
+    hipLaunchKernelGGL(k_batch_gather, dim3((n + NT - 1) / NT), dim3(NT), 0, b->stream, b->dsims, n, which, b->dcg,
+                       b->ddg);
+    if (hipGetLastError() != hipSuccess) return CCNS_EDEVICE;
+    hipError_t e = which == 2
+                       ? hipMemcpyAsync(b->hdg, b->ddg, n * sizeof(DiagState), hipMemcpyDeviceToHost, b->stream)
+                       : hipMemcpyAsync(b->hcg, b->dcg, n * sizeof(CgState), hipMemcpyDeviceToHost, b->stream);
+    if (e != hipSuccess || hipStreamSynchronize(b->stream) != hipSuccess) return CCNS_EDEVICE;
+    return CCNS_OK;
+}
+
+ccns_solve_info solve_info(const CgState &h, bool clamp) {
+    ccns_solve_info i{};
+    i.iterations = h.it_final;
+    i.outer = 1;
+    const double r2 = clamp ? std::max(h.rnorm2_final, 0.0) : h.rnorm2_final;
+    i.rel_residual = h.fnorm2 > 0 ? std::sqrt(r2 / h.fnorm2) : 0.0;
+    i.status = h.status;
+    i.inner_status = CCNS_OK;
+    i.inner_fail_sweep = -1;
+    return i;
+}
+
+// One projection step of every simulation, each phase one launch (per
+// kernel variant) over all of their work-groups.  Each CG runs in lockstep:
+// a simulation whose solve has stopped returns at once from its groups, and
+// the host looks at all done flags in one read-back per chunk of iterations.
+ccns_status batch_fused_step(ccns_batch *b, std::vector<ccns_step_info> &info, std::vector<ccns_status> &st) {
+    const int n = (int)b->sims.size();
+    // the contexts' own work first (their set-up and any solo calls)
+    for (ccns_ctx *c : b->sims)
+        if (hipStreamSynchronize(c->stream) != hipSuccess) return CCNS_EDEVICE;
+    bool rebuild = false;
+    for (int k = 0; k < n && !rebuild; ++k) {
+        const ccns_ctx *c = b->sims[k];
+        rebuild = b->hsims[k].conv_valid != c->conv_valid ||
+                  std::memcmp(&b->forms[(size_t)k * 32], &c->mgf[1][0][0], 32) != 0;
+    }
+    if (rebuild) {
+        ccns_status s = batch_build(b);
+        if (s != CCNS_OK) return s;
+    }
+    // predictor
+    blaunch<OpPredRhs<false, false>>(b, b->pred[0], 0);
+    blaunch<OpPredRhs<true, false>>(b, b->pred[1], 0);
+    blaunch<OpPredRhs<false, true>>(b, b->pred[2], 0);
+    blaunch<OpPredRhs<true, true>>(b, b->pred[3], 0);
+    for (ccns_ctx *c : b->sims) c->conv_valid = 1;
+    blaunch<OpPredResid<false, false>>(b, b->pred[0], 0);
+    blaunch<OpPredResid<true, false>>(b, b->pred[1], 0);
+    blaunch<OpPredResid<false, true>>(b, b->pred[2], 0);
+    blaunch<OpPredResid<true, true>>(b, b->pred[3], 0);
+    blaunch<OpReduce>(b, b->one, 0);
+    int last = 0;
+    for (ccns_ctx *c : b->sims) last = std::max(last, c->last_pred_it);
+    int chunk = std::max(4, last + 1), it = 0;
+    for (;;) {
+        for (int u = 0; u < chunk; ++u, ++it) {
+            blaunch_w7<OpPredCg<false, false>>(b, b->pred[0], it);
+            blaunch_w7<OpPredCg<true, false>>(b, b->pred[1], it);
+            blaunch_w7<OpPredCg<false, true>>(b, b->pred[2], it);
+            blaunch_w7<OpPredCg<true, true>>(b, b->pred[3], it);
+            blaunch<OpPredSplit>(b, b->split, it);
+        }
+        ccns_status s = batch_read(b, 0);
+        if (s != CCNS_OK) return s;
+        bool all = true;
+        for (int k = 0; k < n; ++k) all = all && b->hcg[k].done;
+        if (all) break;
+        chunk = 8;
+    }
+    for (int k = 0; k < n; ++k) {
+        info[k].pred = solve_info(b->hcg[k], true);
+        b->sims[k]->last_pred_it = b->hcg[k].it_final;
+    }
+    // corrector: the pressure solve, the correction, the pressure update and
+    // the diagnostics
+    blaunch<OpPoisRhs>(b, b->dc, 0);
+    blaunch<OpPoisInit>(b, b->dc, 0);
+    batch_vcycle(b);
+    last = 0;
+    for (ccns_ctx *c : b->sims) last = std::max(last, c->last_pois_it);
+    chunk = std::max(2, last + 1);
+    it = 0;
+    for (;;) {
+        for (int u = 0; u < chunk; ++u, ++it) {
+            blaunch<OpDirZ>(b, b->dp, it);
+            blaunch<OpUpdate>(b, b->upd, it);
+            batch_vcycle(b);
+        }
+        ccns_status s = batch_read(b, 1);
+        if (s != CCNS_OK) return s;
+        bool all = true;
+        for (int k = 0; k < n; ++k) all = all && b->hcg[k].done;
+        if (all) break;
+        chunk = 2;
+    }
+    for (int k = 0; k < n; ++k) {
+        info[k].poisson = solve_info(b->hcg[k], false);
+        b->sims[k]->last_pois_it = b->hcg[k].it_final;
+        b->sims[k]->pbuf_pois = it & 1;
+    }
+    blaunch<OpCorrect>(b, b->dc, 0);
+    blaunch<OpDiag>(b, b->dc, 0);
+    blaunch<OpReduce>(b, b->one, 2);
+    ccns_status s = batch_read(b, 2);
+    if (s != CCNS_OK) return s;
+    for (int k = 0; k < n; ++k) {
+        const ccns_ctx *c = b->sims[k];
+        const DiagState &d = b->hdg[k];
+        info[k].div_max = d.divmax > 0 ? d.divmax : 0.0;
+        info[k].div_rel = info[k].div_max / (c->prm.u_ref * std::min(c->g.hx, c->g.hy));
+        info[k].ke = d.ke;
+        info[k].mass = d.mass;
+        info[k].mom_x = d.momx;
+        info[k].mom_y = d.momy;
+        ccns_status w = CCNS_OK;
+        if (info[k].pred.status != CCNS_OK) w = (ccns_status)info[k].pred.status;
+        if (info[k].poisson.status != CCNS_OK) w = (ccns_status)info[k].poisson.status;
+        if (w != CCNS_OK) st[k] = w;
+    }
+    return CCNS_OK;
+}
+
+void batch_free(ccns_batch *b) {
+    if (!b) return;
+    if (b->stream) (void)hipStreamSynchronize(b->stream);
+    if (b->dsims) (void)hipFree(b->dsims);
+    if (b->dmap) (void)hipFree(b->dmap);
+    if (b->dcg) (void)hipFree(b->dcg);
+    if (b->ddg) (void)hipFree(b->ddg);
+    if (b->hcg) (void)hipHostFree(b->hcg);
+    if (b->hdg) (void)hipHostFree(b->hdg);
+    if (b->stream) (void)hipStreamDestroy(b->stream);
+    delete b;
+}
+
+}  // namespace
 
 namespace {
 // Severity order of statuses for the batch result.
@@ -4086,6 +4876,36 @@ ccns_status ccns_batch_create(int n, ccns_ctx *const *ctxs, int nthreads, ccns_b
     return CCNS_OK;
 }
 
+ccns_status ccns_batch_create_fused(int n, ccns_ctx *const *ctxs, ccns_batch **out) {
+    if (!out) return CCNS_EINVAL;
+    *out = nullptr;
+    if (n < 1 || n > BATCH_MAX_SIMS || !ctxs) return CCNS_EINVAL;
+    for (int k = 0; k < n; ++k)
+        if (!ctxs[k] || ctxs[k]->prm.precision != 0 || ctxs[k]->prm.precond != 1) return CCNS_EINVAL;
+    ccns_batch *b = nullptr;
+    ccns_status s = ccns_batch_create(n, ctxs, 1, &b);
+    if (s != CCNS_OK) return s;
+    b->fused = true;
+    s = CCNS_ENOMEM;
+    if (hipStreamCreate(&b->stream) == hipSuccess && hipMalloc(&b->dsims, n * sizeof(BatchSim)) == hipSuccess &&
+        hipMalloc(&b->dcg, n * sizeof(CgState)) == hipSuccess &&
+        hipMalloc(&b->ddg, n * sizeof(DiagState)) == hipSuccess &&
+        hipHostMalloc(&b->hcg, n * sizeof(CgState)) == hipSuccess &&
+        hipHostMalloc(&b->hdg, n * sizeof(DiagState)) == hipSuccess) {
+        try {
+            s = batch_build(b);
+        } catch (...) {
+            s = CCNS_ENOMEM;
+        }
+    }
+    if (s != CCNS_OK) {
+        batch_free(b);
+        return s;
+    }
+    *out = b;
+    return CCNS_OK;
+}
+
 ccns_status ccns_batch_step(ccns_batch *b, int nsteps, ccns_step_info *per_sim, int *per_status) {
     if (!b || nsteps < 0) return CCNS_EINVAL;
     const int n = (int)b->sims.size();
@@ -4096,6 +4916,28 @@ ccns_status ccns_batch_step(ccns_batch *b, int nsteps, ccns_step_info *per_sim, 
         info.resize(n);
     } catch (...) {
         return CCNS_ENOMEM;
+    }
+    if (b->fused) {
+        ccns_status e = CCNS_OK;
+        try {
+            for (int k = 0; k < nsteps && e == CCNS_OK; ++k) e = batch_fused_step(b, info, st);
+        } catch (...) {
+            e = CCNS_ENOMEM;
+        }
+        if (e != CCNS_OK) {
+            for (int k = 0; k < n; ++k) {
+                if (per_sim) per_sim[k] = info[k];
+                if (per_status) per_status[k] = e;
+            }
+            return e;
+        }
+        ccns_status worst = CCNS_OK;
+        for (int k = 0; k < n; ++k) {
+            if (severity(st[k]) > severity(worst)) worst = st[k];
+            if (per_sim) per_sim[k] = info[k];
+            if (per_status) per_status[k] = st[k];
+        }
+        return worst;
     }
     std::atomic<int> next{0};
     auto worker = [&]() {
@@ -4125,6 +4967,6 @@ ccns_status ccns_batch_step(ccns_batch *b, int nsteps, ccns_step_info *per_sim, 
     return worst;
 }
 
-void ccns_batch_destroy(ccns_batch *b) { delete b; }
+void ccns_batch_destroy(ccns_batch *b) { batch_free(b); }
 
 }  // extern "C"

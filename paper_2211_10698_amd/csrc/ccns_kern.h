@@ -28,15 +28,33 @@ struct Dims {
     size_t n;                  // entries per component array (rows * pitch)
 };
 
-__device__ inline int logical_group(int nblk) {
-    const int b = blockIdx.x;
+// The work-group's place in the grid of one simulation.  A kernel launched
+// for one simulation is that grid (SoloGrid: blockIdx.x of gridDim.x); a
+// batched launch runs the work-groups of many simulations' grids side by
+// side, and each group gets its index and count within its own simulation's
+// share (SubGrid).  The kernels' arithmetic sees only these two numbers, so a
+// simulation computes the same values in either kind of launch.
+struct SoloGrid {
+    __device__ int b() const { return (int)blockIdx.x; }
+    __device__ int n() const { return (int)gridDim.x; }
+};
+struct SubGrid {
+    int bb, nn;
+    __device__ int b() const { return bb; }
+    __device__ int n() const { return nn; }
+};
+
+template <class G>
+__device__ inline int logical_group(const G &g, int nblk) {
+    const int b = g.b();
     return (b & 7) * (nblk >> 3) + (b >> 3);
 }
+__device__ inline int logical_group(int nblk) { return logical_group(SoloGrid{}, nblk); }
 
 // Calls f(comp, c0, r0) for every tile of this work-group.
-template <class F>
-__device__ inline void for_tiles(const Dims &d, F f) {
-    const int L = logical_group(d.nblk);
+template <class G, class F>
+__device__ inline void for_tiles(const G &g, const Dims &d, F f) {
+    const int L = logical_group(g, d.nblk);
     const int total = d.ntile * d.ncomp;
     const int t0 = L * d.tpb, t1 = min(t0 + d.tpb, total);
     for (int t = t0; t < t1; ++t) {
@@ -44,12 +62,16 @@ __device__ inline void for_tiles(const Dims &d, F f) {
         f(comp, (tt % d.gx) * TX, (tt / d.gx) * d.ty);
     }
 }
+template <class F>
+__device__ inline void for_tiles(const Dims &d, F f) {
+    for_tiles(SoloGrid{}, d, f);
+}
 
 // Calls f(comp, j, i, k) for every entry of this work-group's tiles.
-template <class F>
-__device__ inline void for_cells(const Dims &d, F f) {
+template <class G, class F>
+__device__ inline void for_cells(const G &g, const Dims &d, F f) {
     const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-    for_tiles(d, [&](int comp, int c0, int r0) {
+    for_tiles(g, d, [&](int comp, int c0, int r0) {
         const int i = c0 + tx;
         for (int rr = ty; rr < d.ty; rr += 4) {
             const int j = r0 + rr;
@@ -57,16 +79,20 @@ __device__ inline void for_cells(const Dims &d, F f) {
         }
     });
 }
+template <class F>
+__device__ inline void for_cells(const Dims &d, F f) {
+    for_cells(SoloGrid{}, d, f);
+}
 
 // The same for tiles of exactly 4 R rows, in two passes per tile: load(k)
 // for each of the thread's R entries (k = 0 stands in for entries past the
 // last row), then f(comp, j, i, k, loaded value) for the real ones.  All of
 // a thread's loads are then in flight together instead of one entry's loads
 // waiting for the previous entry's.
-template <int R, class LD, class F>
-__device__ inline void for_cells_batched(const Dims &d, LD load, F f) {
+template <int R, class G, class LD, class F>
+__device__ inline void for_cells_batched(const G &g, const Dims &d, LD load, F f) {
     const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-    for_tiles(d, [&](int comp, int c0, int r0) {
+    for_tiles(g, d, [&](int comp, int c0, int r0) {
         const int i = c0 + tx;
         decltype(load((size_t)0)) vals[R];
 #pragma unroll
@@ -80,6 +106,10 @@ __device__ inline void for_cells_batched(const Dims &d, LD load, F f) {
             if (j < d.rows) f(comp, j, i, (size_t)j * d.pitch + i, vals[m]);
         }
     });
+}
+template <int R, class LD, class F>
+__device__ inline void for_cells_batched(const Dims &d, LD load, F f) {
+    for_cells_batched<R>(SoloGrid{}, d, load, f);
 }
 
 // ---------------------------------------------------------------------------
@@ -128,14 +158,19 @@ __device__ inline void block_reduce(const double (&v)[NS + NM], double (&out)[NS
     __syncthreads();
 }
 
-template <int NS, int NM = 0, int BT = NT>
-__device__ inline void put_partials(const double (&v)[NS + NM], double *part, int nblk) {
+template <int NS, int NM = 0, int BT = NT, class G>
+__device__ inline void put_partials(const G &g, const double (&v)[NS + NM], double *part, int nblk) {
     double t[NS + NM];
     block_reduce<NS, NM, BT>(v, t);
     if (threadIdx.x == 0) {
+        const int b = g.b();
 #pragma unroll
-        for (int k = 0; k < NS + NM; ++k) part[(size_t)k * nblk + blockIdx.x] = t[k];
+        for (int k = 0; k < NS + NM; ++k) part[(size_t)k * nblk + b] = t[k];
     }
+}
+template <int NS, int NM = 0, int BT = NT>
+__device__ inline void put_partials(const double (&v)[NS + NM], double *part, int nblk) {
+    put_partials<NS, NM, BT>(SoloGrid{}, v, part, nblk);
 }
 
 template <int NS, int NM = 0, int BT = NT>

@@ -85,10 +85,17 @@ def load_cache(path: str = CACHE) -> Dict:
 
 def lookup(levels: Sequence[Tuple[int, int]], precision: int, device: str, cache: Optional[Dict] = None) -> int:
     """The cached forms of these level sizes ((nx, ny) per level), 0 where
-    none is cached."""
+    none is cached.  A size tuned as a coarse level may be a grid's finest
+    one, whose up-sweep cannot take forms 4 and 5: it keeps the default."""
     cache = load_cache() if cache is None else cache
     table = cache.get(device, {}).get(precision_key(precision), {})
-    return pack([tuple(table.get(f"{nx}x{ny}", (0, 0))) for nx, ny in levels])
+    pairs = []
+    for level, (nx, ny) in enumerate(levels):
+        down, up = table.get(f"{nx}x{ny}", (0, 0))
+        if level == 0 and up in (4, 5):
+            up = 0
+        pairs.append((down, up))
+    return pack(pairs)
 
 
 def apply_cached(ctx, precision: int, cache: Optional[Dict] = None) -> int:

@@ -37,6 +37,10 @@ CASES = {
     "outflow_96x48": lambda: W.outflow_cylinder(48),
     # both: the paper's cylinder set-up on a mesh refined around the body
     "paper_96x48": lambda: W.paper_cylinder(48, steps=10),
+    # a grid within one 16 x 16 coarsest grid: the multigrid hierarchy still
+    # gets a cycle level above it (whose up-sweep forms the CG's statistics)
+    "tiny_12x12": lambda: W.Case("tiny_12x12", W.GridSpec(12, 12, 0.0, 0.0, 1.0, 1.0),
+                                 [W.Body(W.CIRCLE, 0.47, 0.52, a=0.2)], re=100.0, steps=10, noise=1e-2, seed=11),
 }
 # The small-volume floor theta: 0 is the paper's mass matrix M = diag(V)
 # (eq:semidiscrete); 0.05 floors every volume the step divides by at 5% of a
@@ -156,7 +160,7 @@ def test_step_phases_match(setup):
 
 
 @pytest.mark.parametrize("theta", THETAS)
-@pytest.mark.parametrize("name", ["cylinder_64", "flat_top_64", "stretched_96x48", "outflow_96x48"])
+@pytest.mark.parametrize("name", ["cylinder_64", "flat_top_64", "stretched_96x48", "outflow_96x48", "tiny_12x12"])
 @pytest.mark.parametrize("precond", ["jacobi", "mg"])
 def test_trajectory_tight_tolerance(precond, name, theta):
     """Ten steps with tight solver tolerances: the trajectories agree to

@@ -165,3 +165,8 @@ def test_multigrid_form_words_and_cache():
     p = 1 if prec == "f32" else 0
     w = tune.lookup([(nx, ny), (3, 3)], p, dev, cache)
     assert tune.unpack(w, 2) == [tuple(cache[dev][prec][size]), (0, 0)]
+    # a size cached with a short-tile up-sweep (tuned as a coarse level) as a
+    # grid's finest level keeps the default up-sweep there
+    small = {dev: {prec: {"128x128": [4, 5], "64x64": [5, 4]}}}
+    w = tune.lookup([(128, 128), (64, 64)], p, dev, small)
+    assert tune.unpack(w, 2) == [(4, 0), (5, 4)]
