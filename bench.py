@@ -297,11 +297,10 @@ def setup_context(ccns, case, precision, stream, host, coef_tables=0, mg_forms=T
 def run_batched(args):
     """The ragged batch: 256 cylinder simulations of 128^2 .. 1024^2 cells
     (seeded sizes, radii, centres and Reynolds numbers), advanced together
-    by ccns_batch_step: in FP64 by default as a fused batch (one launch per
-    phase over every simulation's work-groups), else (--batch-mode streams,
-    and always in precision 1) with 16 host threads and one stream per
-    simulation.  A step advances every simulation by one projection step;
-    value = total cell-steps / time."""
+    by ccns_batch_step: by default as a fused batch (one launch per phase
+    over every simulation's work-groups), else (--batch-mode streams) with
+    16 host threads and one stream per simulation.  A step advances every
+    simulation by one projection step; value = total cell-steps / time."""
     import concurrent.futures as cf
 
     import torch
@@ -309,9 +308,7 @@ def run_batched(args):
 
     cases = W.batched_cylinders(256)
     prec = 1 if args.precision == "mixed" else 0
-    mode = args.batch_mode if args.batch_mode != "auto" else ("streams" if prec else "fused")
-    if mode == "fused" and prec:
-        raise SystemExit("the fused batch runs precision 0 (--precision fp64)")
+    mode = "streams" if args.batch_mode == "streams" else "fused"
     torch.cuda.set_device(0)
     t_setup = time.perf_counter()
     # a fused batch runs on its own stream: the contexts can share one
@@ -457,9 +454,9 @@ def main():
     ap.add_argument("--mg-forms", default="tuned", choices=["tuned", "default"],
                     help="multigrid cycle kernel forms: the tuned ones cached for this GPU's level sizes "
                          "(paper_2211_10698_amd/mg_forms.json), or the library's defaults")
-    ap.add_argument("--batch-mode", default="auto", choices=["auto", "fused", "streams"],
-                    help="batched_cylinders_256: fused launches (FP64) or a stream per simulation "
-                         "(auto: fused in FP64, streams in precision 1)")
+    ap.add_argument("--batch-mode", default="fused", choices=["fused", "streams"],
+                    help="batched_cylinders_256: one launch per phase over all simulations (fused) "
+                         "or 16 host threads with a stream per simulation")
     ap.add_argument("--coef-tables", default="auto", choices=["auto", "off"],
                     help="auto: the predictor CG reads its coefficients through the class table when it "
                          "fits (the library's default); off: from the coefficient arrays")

@@ -440,15 +440,20 @@ int ccns_mg_levels(const ccns_ctx *ctx, int *nx, int *ny, int *forms, int cap);
  *   lockstep: each simulation keeps its own solver state, a simulation
  *   whose solve has stopped does nothing in the later launches, and the
  *   host reads all stopping flags in one read-back per chunk of iterations.
- *   Each simulation's kernels, and so its results, are those of its solo
- *   steps bit for bit.  1 <= n <= 1024 distinct contexts on the current
- *   device, each with precision 0 and the multigrid preconditioner
- *   (precond 1); ccns_batch_step and ccns_batch_destroy as above.  A step
- *   waits for each context's stream before it starts and returns after its
- *   own work ends; the contexts must not be used elsewhere meanwhile.
- *   Errors: CCNS_EINVAL (n out of range, a NULL or repeated context, another
- *   precision or preconditioner), CCNS_ENOMEM (device or host memory for the
- *   batch's tables), CCNS_EDEVICE. */
+ *   In precision 1 the refinement sweeps run in lockstep too: each sweep
+ *   forms every simulation's FP64 residual, reads all of their statistics
+ *   in one read-back, takes each simulation's decisions (converged, or the
+ *   tolerance of its inner float solve) as its solo solve does, and runs
+ *   the inner solves of the simulations still refining together.  Each
+ *   simulation's kernels, and so its results, are those of its solo steps
+ *   bit for bit.  1 <= n <= 1024 distinct contexts on the current device,
+ *   all of one precision, each with the multigrid preconditioner (precond
+ *   1); ccns_batch_step and ccns_batch_destroy as above.  A step waits for
+ *   each context's stream before it starts and returns after its own work
+ *   ends; the contexts must not be used elsewhere meanwhile.  Errors:
+ *   CCNS_EINVAL (n out of range, a NULL or repeated context, precisions
+ *   that differ, the Jacobi preconditioner), CCNS_ENOMEM (device or host
+ *   memory for the batch's tables), CCNS_EDEVICE. */
 typedef struct ccns_batch ccns_batch;
 ccns_status ccns_batch_create(int n, ccns_ctx *const *ctxs, int nthreads, ccns_batch **out);
 ccns_status ccns_batch_create_fused(int n, ccns_ctx *const *ctxs, ccns_batch **out);

@@ -412,7 +412,7 @@ class Batch:
     """A ragged batch of contexts stepped together (ccns_batch_*).  The
     contexts stay owned by the caller and must outlive the batch.  fused:
     one launch per phase over every simulation's work-groups
-    (ccns_batch_create_fused; precision 0 with the multigrid
+    (ccns_batch_create_fused; one precision for all, the multigrid
     preconditioner), else one host thread and stream per simulation."""
 
     def __init__(self, contexts: Sequence["Context"], nthreads: int = 0, fused: bool = False):

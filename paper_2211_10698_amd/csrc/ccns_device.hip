@@ -29,6 +29,7 @@
 #include <string>
 #include <thread>
 #include <unordered_map>
+#include <type_traits>
 #include <vector>
 
 #include "ccns.h"
@@ -409,10 +410,14 @@ __global__ __launch_bounds__(UT) void k_cg_update(size_t ntot, int nblk, const T
 }
 
 // x += dx (float correction of an inner solve) over ntot entries.
+template <class G>
+__device__ __forceinline__ void add_correction_body(const G &g, size_t ntot, double *__restrict__ x,
+                                                    const float *__restrict__ dx) {
+    for (size_t k = (size_t)g.b() * NT + threadIdx.x; k < ntot; k += (size_t)g.n() * NT) x[k] += (double)dx[k];
+}
 __global__ __launch_bounds__(NT) void k_add_correction(size_t ntot, double *__restrict__ x,
                                                        const float *__restrict__ dx) {
-    for (size_t k = (size_t)blockIdx.x * NT + threadIdx.x; k < ntot; k += (size_t)gridDim.x * NT)
-        x[k] += (double)dx[k];
+    add_correction_body(SoloGrid{}, ntot, x, dx);
 }
 
 // ---------------------------------------------------------------------------
@@ -4181,46 +4186,70 @@ namespace {
 
 // A simulation of a fused batch as the batched kernels see it: the
 // arguments its solo launches take, gathered once.  The cycle levels and
-// the coarse end are those of the context's multigrid hierarchy.
+// the coarse end are those of the context's multigrid hierarchy (FP64, and
+// in precision 1 the float one of the inner solves).
 constexpr int BATCH_LEVELS = 16;
-struct BatchLevel {
+template <class T>
+struct BatchLevelT {
     int nx, ny, P, gx;         // the level
-    PoisCoef pc;
-    const double *b;
-    double *x, *xt;
+    PoisCoefT<T> pc;
+    const T *b;
+    T *x, *xt;
     int Pc, nxc, nyc;          // the next coarser level
-    const double *dinvc;
-    double *bc;
-    const double *xc;          // the coarser level's result (its up-sweep, or the coarse end)
+    const T *dinvc;
+    T *bc;
+    const T *xc;               // the coarser level's result (its up-sweep, or the coarse end)
     int fd, fu, nbd, nbu;      // kernel forms and work-groups of the down- and up-sweep
 };
 enum BatchBottom { BOT_COARSEST = 0, BOT_TAIL_LDS = 1, BOT_TAIL = 2 };
+template <class T>
+struct BatchCycle {
+    int ncyc;                  // cycle levels
+    BatchLevelT<T> lv[BATCH_LEVELS];
+    int bottom;                // BatchBottom
+    TailDesc<T> tail;
+    int tail_bytes;            // LDS the tail's levels take (BOT_TAIL_LDS)
+    const T *cb;               // the coarsest grid's b and x (BOT_COARSEST)
+    T *cxo;
+    const T *z;                // the cycle's result on the finest level
+};
 struct BatchSim {
+    const int *active;           // precision 1: 1 while the simulation takes part in the sweep
     int P, rows, pgx, pgy, pnb;  // layout; predictor tiles and work-groups
     size_t n;
     PredCoefT<double> pd;
+    PredCoefT<float> pf;         // precision 1: the inner predictor solve's coefficients
     double rho, grav_x, grav_y, rho_tau, tau_rho, pcoef;
     int conv_valid;
     OutflowDesc of;
     double *a[A_COUNT];
+    float *f[G_COUNT];
     double *part[PB_COUNT];
-    CgState *st_pred, *st_pois;
+    double *outer;
+    CgState *st_pred, *st_pois, *st_pred_in, *st_pois_in;
     DiagState *diag;
     DiagCoef dgc;
     Dims dc, dp;
     int nl;                      // work-groups of the CG update
-    int ncyc;                    // cycle levels
-    BatchLevel lv[BATCH_LEVELS];
-    int bottom;                  // BatchBottom
-    TailDesc<double> tail;
-    int tail_bytes;              // LDS the tail's levels take (BOT_TAIL_LDS)
-    int ncoarse;                 // the coarsest grid (BOT_COARSEST)
+    int fb1, fb2;                // work-groups of the correction over n and 2n entries
+    int ncoarse;
     const int *pidx;
     const double *pinv;
-    const double *cb;
-    double *cxo;
-    const double *z;             // the cycle's result on the finest level
+    BatchCycle<double> mg;
+    BatchCycle<float> mg32;
 };
+template <class T>
+__host__ __device__ inline const BatchCycle<T> &cycle_of(const BatchSim &s) {
+    if constexpr (std::is_same<T, double>::value)
+        return s.mg;
+    else
+        return s.mg32;
+}
+// The pressure CG's state: the FP64 solve, or the inner float solve.
+template <class T>
+__device__ inline CgState *pois_state(const BatchSim &s) {
+    return std::is_same<T, double>::value ? s.st_pois : s.st_pois_in;
+}
 
 // Work-group table entries: simulation index (high bits) and the group's
 // index within that simulation's grid.
@@ -4230,12 +4259,14 @@ constexpr int BATCH_MAX_SIMS = 1 << (32 - BATCH_SIM_SHIFT);
 
 // The batched kernel of an operation: work-group blockIdx.x runs group
 // (map & mask) of simulation (map >> shift), with u the launch's uniform
-// argument (the CG iteration or the cycle level).
+// argument (the CG iteration, the cycle level or the sweep).  A simulation
+// outside the current refinement sweep (precision 1) does nothing.
 template <class Op>
 __global__ __launch_bounds__(Op::BT) void k_batch(const BatchSim *__restrict__ sims, const unsigned *__restrict__ map,
                                                   int u) {
     const unsigned e = map[blockIdx.x];
     const BatchSim &s = sims[e >> BATCH_SIM_SHIFT];
+    if (s.active && !*s.active) return;
     Op::run(SubGrid{(int)(e & BATCH_LOCAL_MASK), Op::groups(s, u)}, s, u);
 }
 // The same with the register budget of k_pred_cg (seven waves per SIMD).
@@ -4244,6 +4275,7 @@ __global__ __launch_bounds__(Op::BT) __attribute__((amdgpu_waves_per_eu(7))) voi
     const BatchSim *__restrict__ sims, const unsigned *__restrict__ map, int u) {
     const unsigned e = map[blockIdx.x];
     const BatchSim &s = sims[e >> BATCH_SIM_SHIFT];
+    if (s.active && !*s.active) return;
     Op::run(SubGrid{(int)(e & BATCH_LOCAL_MASK), Op::groups(s, u)}, s, u);
 }
 
@@ -4258,29 +4290,45 @@ struct OpPredRhs {
                                 s.grav_y, s.conv_valid, s.of);
     }
 };
-template <bool GEO, bool CLS>
+// The predictor residual rhs - H U*: FP64 (MIX = false), or rounded to the
+// float right-hand side of the inner solve (MIX).
+template <bool MIX, bool GEO, bool CLS>
 struct OpPredResid {
     static constexpr int BT = NT;
     __device__ static int groups(const BatchSim &s, int) { return s.pnb; }
     __device__ static void run(const SubGrid &g, const BatchSim &s, int) {
-        pred_resid_body<false, GEO, CLS>(g, s.P, s.rows, s.pgx, s.pgy, s.n, s.pd, s.a[A_RHSX], s.a[A_USX],
-                                         s.a[A_PRX], s.st_pred, s.part[PB_RHS], nullptr, nullptr, nullptr);
+        if constexpr (MIX)
+            pred_resid_body<true, GEO, CLS>(g, s.P, s.rows, s.pgx, s.pgy, s.n, s.pd, s.a[A_RHSX], s.a[A_USX],
+                                            s.a[A_PRX], s.st_pred_in, s.part[PB_RHS], s.f[G_PRX], s.f[G_PXX],
+                                            s.f[G_HDX]);
+        else
+            pred_resid_body<false, GEO, CLS>(g, s.P, s.rows, s.pgx, s.pgy, s.n, s.pd, s.a[A_RHSX], s.a[A_USX],
+                                             s.a[A_PRX], s.st_pred, s.part[PB_RHS], nullptr, nullptr, nullptr);
     }
 };
-// Launch u = it of the predictor CG (r, p and H p alternate between two
-// buffers by the parity of it, as in the solo solve).
-template <bool GEO, bool CLS>
+// Launch u = it of the predictor CG in storage type T (r, p and H p
+// alternate between two buffers by the parity of it, as in the solo solve).
+template <class T, bool GEO, bool CLS>
 struct OpPredCg {
     static constexpr int BT = NT;
     __device__ static int groups(const BatchSim &s, int) { return s.pnb; }
     __device__ static void run(const SubGrid &g, const BatchSim &s, int it) {
         const int b = it & 1;
-        double *r[2] = {s.a[A_PRX], s.a[A_PR1X]}, *p[2] = {s.a[A_PP0X], s.a[A_PP1X]},
-               *q[2] = {s.a[A_PQX], s.a[A_PQ1X]};
-        pred_cg_body<double, GEO, CLS>(g, s.P, s.rows, s.pgx, s.pgy, s.n, s.pd, s.st_pred, it, s.a[A_USX],
-                                       it == 0 ? r[0] : r[b ^ 1], r[b], p[b ^ 1], p[b], q[b ^ 1], q[b],
-                                       it == 0 ? s.part[PB_INIT] : s.part[PB_UPD], it == 0 ? 1 : PRED_RED,
-                                       s.part[PB_DIR]);
+        const double *tin = it == 0 ? s.part[PB_INIT] : s.part[PB_UPD];
+        const int nin = it == 0 ? 1 : PRED_RED;
+        if constexpr (std::is_same<T, double>::value) {
+            double *r[2] = {s.a[A_PRX], s.a[A_PR1X]}, *p[2] = {s.a[A_PP0X], s.a[A_PP1X]},
+                   *q[2] = {s.a[A_PQX], s.a[A_PQ1X]};
+            pred_cg_body<double, GEO, CLS>(g, s.P, s.rows, s.pgx, s.pgy, s.n, s.pd, s.st_pred, it, s.a[A_USX],
+                                           it == 0 ? r[0] : r[b ^ 1], r[b], p[b ^ 1], p[b], q[b ^ 1], q[b], tin,
+                                           nin, s.part[PB_DIR]);
+        } else {
+            float *r[2] = {s.f[G_PRX], s.f[G_PR1X]}, *p[2] = {s.f[G_PP0X], s.f[G_PP1X]},
+                  *q[2] = {s.f[G_PQX], s.f[G_PQ1X]};
+            pred_cg_body<float, GEO, CLS>(g, s.P, s.rows, s.pgx, s.pgy, s.n, s.pf, s.st_pred_in, it, s.f[G_PXX],
+                                          it == 0 ? r[0] : r[b ^ 1], r[b], p[b ^ 1], p[b], q[b ^ 1], q[b], tin,
+                                          nin, s.part[PB_DIR]);
+        }
     }
 };
 struct OpPredSplit {
@@ -4290,18 +4338,27 @@ struct OpPredSplit {
         reduce_partials_split_body<7>(g, s.part[PB_DIR], s.pnb, s.part[PB_UPD]);
     }
 };
-// One-group reductions: the predictor residual's statistics (u = 0), the
-// cycle's statistics (u = 1), the diagnostics (u = 2).
+// One-group reductions.
+enum BatchReduce {
+    RED_PRED = 0,      // the FP64 predictor residual's statistics
+    RED_CYCLE = 1,     // the FP64 cycle's statistics of z
+    RED_DIAG = 2,      // the diagnostics
+    RED_PRED_MIX = 3,  // the precision-1 predictor residual's statistics
+    RED_POIS_MIX = 4,  // the precision-1 pressure residual's statistics (to `outer`)
+    RED_CYCLE32 = 5    // the float cycle's statistics of z
+};
 struct OpReduce {
     static constexpr int BT = NT;
     __device__ static int groups(const BatchSim &, int) { return 1; }
     __device__ static void run(const SubGrid &, const BatchSim &s, int u) {
-        if (u == 0)
-            reduce_partials_body<5, 0, NT>(s.part[PB_RHS], s.pnb, s.part[PB_INIT]);
-        else if (u == 1)
-            reduce_partials_body<4, 0, NT>(s.part[PB_UPD], s.lv[0].nbu, s.part[PB_MG]);
-        else
-            diag_final_body(s.part[PB_DIAG], s.dc.nblk, s.diag);
+        switch (u) {
+        case RED_PRED: reduce_partials_body<5, 0, NT>(s.part[PB_RHS], s.pnb, s.part[PB_INIT]); break;
+        case RED_CYCLE: reduce_partials_body<4, 0, NT>(s.part[PB_UPD], s.mg.lv[0].nbu, s.part[PB_MG]); break;
+        case RED_DIAG: diag_final_body(s.part[PB_DIAG], s.dc.nblk, s.diag); break;
+        case RED_PRED_MIX: reduce_partials_body<7, 0, NT>(s.part[PB_RHS], s.pnb, s.part[PB_INIT]); break;
+        case RED_POIS_MIX: reduce_partials_body<7, 1, NT>(s.part[PB_INIT], s.dc.nblk, s.outer); break;
+        default: reduce_partials_body<4, 0, NT>(s.part[PB_UPD], s.mg32.lv[0].nbu, s.part[PB_MG]);
+        }
     }
 };
 struct OpPoisRhs {
@@ -4312,103 +4369,137 @@ struct OpPoisRhs {
                       s.a[A_USX], s.a[A_USY], s.a[A_B], s.rho_tau, s.part[PB_RHS]);
     }
 };
+// The pressure solve's first residual (FP64), or the residual of sweep u of
+// the refinement (MIX; sweep 0 also removes the mean of b where needed).
+template <bool MIX>
 struct OpPoisInit {
     static constexpr int BT = NT;
     __device__ static int groups(const BatchSim &s, int) { return s.dc.nblk; }
-    __device__ static void run(const SubGrid &g, const BatchSim &s, int) {
-        pois_init_body<false>(g, s.dc, PoisCoef{s.a[A_CX], s.a[A_CY], s.a[A_DINV]}, s.a[A_B], s.a[A_PHI], s.a[A_R],
-                              s.st_pois, s.part[PB_RHS], s.dc.nblk, s.part[PB_INIT], nullptr, nullptr, nullptr);
+    __device__ static void run(const SubGrid &g, const BatchSim &s, int u) {
+        const PoisCoef pc{s.a[A_CX], s.a[A_CY], s.a[A_DINV]};
+        if constexpr (MIX)
+            pois_init_body<true>(g, s.dc, pc, s.a[A_B], s.a[A_PHI], nullptr, s.st_pois_in,
+                                 u == 0 ? s.part[PB_RHS] : nullptr, s.dc.nblk, s.part[PB_INIT], s.f[G_R], s.f[G_X],
+                                 s.f[G_DINV]);
+        else
+            pois_init_body<false>(g, s.dc, pc, s.a[A_B], s.a[A_PHI], s.a[A_R], s.st_pois, s.part[PB_RHS], s.dc.nblk,
+                                  s.part[PB_INIT], nullptr, nullptr, nullptr);
     }
 };
-// The multigrid CG's direction and update of iteration u = it; the search
-// directions alternate between A_P0 and A_P1 from A_P0 (the first
-// direction reads no old one).
+// The multigrid CG's direction and update of iteration u = it, in storage
+// type T; the search directions alternate between the two p buffers from
+// the first (the first direction reads no old one).
+template <class T>
 struct OpDirZ {
     static constexpr int BT = NT;
     __device__ static int groups(const BatchSim &s, int) { return s.dp.nblk; }
     __device__ static void run(const SubGrid &g, const BatchSim &s, int it) {
-        double *pold = (it & 1) ? s.a[A_P1] : s.a[A_P0], *pnew = (it & 1) ? s.a[A_P0] : s.a[A_P1];
-        pois_dir_z_body<double>(g, s.dp, PoisCoef{s.a[A_CX], s.a[A_CY], s.a[A_DINV]}, s.z, pold, pnew, s.a[A_Q],
-                                s.st_pois, it == 0 ? 1 : 0, it & 1, s.part[PB_MG], 1, s.part[PB_INIT], s.dc.nblk,
-                                s.part[PB_DIR]);
+        if constexpr (std::is_same<T, double>::value) {
+            double *pold = (it & 1) ? s.a[A_P1] : s.a[A_P0], *pnew = (it & 1) ? s.a[A_P0] : s.a[A_P1];
+            pois_dir_z_body<double>(g, s.dp, PoisCoef{s.a[A_CX], s.a[A_CY], s.a[A_DINV]}, s.mg.z, pold, pnew,
+                                    s.a[A_Q], s.st_pois, it == 0 ? 1 : 0, it & 1, s.part[PB_MG], 1, s.part[PB_INIT],
+                                    s.dc.nblk, s.part[PB_DIR]);
+        } else {
+            float *pold = (it & 1) ? s.f[G_P1] : s.f[G_P0], *pnew = (it & 1) ? s.f[G_P0] : s.f[G_P1];
+            pois_dir_z_body<float>(g, s.dp, PoisCoefT<float>{s.f[G_CX], s.f[G_CY], s.f[G_DINV]}, s.mg32.z, pold,
+                                   pnew, s.f[G_Q], s.st_pois_in, it == 0 ? 1 : 0, it & 1, s.part[PB_MG], 1, nullptr,
+                                   0, s.part[PB_DIR]);
+        }
     }
 };
+template <class T>
 struct OpUpdate {
     static constexpr int BT = UT;
     __device__ static int groups(const BatchSim &s, int) { return s.nl; }
     __device__ static void run(const SubGrid &g, const BatchSim &s, int it) {
-        const double *pnew = (it & 1) ? s.a[A_P0] : s.a[A_P1];
-        cg_update_body<double, false>(g, s.n, s.nl, s.a[A_DINV], s.a[A_PHI], s.a[A_R], pnew, s.a[A_Q], s.st_pois,
-                                      it & 1, s.part[PB_DIR], s.dp.nblk, s.part[PB_UPD]);
+        if constexpr (std::is_same<T, double>::value)
+            cg_update_body<double, false>(g, s.n, s.nl, s.a[A_DINV], s.a[A_PHI], s.a[A_R],
+                                          (it & 1) ? s.a[A_P0] : s.a[A_P1], s.a[A_Q], s.st_pois, it & 1,
+                                          s.part[PB_DIR], s.dp.nblk, s.part[PB_UPD]);
+        else
+            cg_update_body<float, false>(g, s.n, s.nl, s.f[G_DINV], s.f[G_X], s.f[G_R],
+                                         (it & 1) ? s.f[G_P0] : s.f[G_P1], s.f[G_Q], s.st_pois_in, it & 1,
+                                         s.part[PB_DIR], s.dp.nblk, s.part[PB_UPD]);
     }
 };
-// Down- and up-sweep of cycle level u in form F (MgForm).
-template <int F>
+// Down- and up-sweep of cycle level u in form F (MgForm), storage type T.
+template <class T, int F>
 struct OpMgDown {
     static constexpr int BT = NT;
-    __device__ static int groups(const BatchSim &s, int l) { return s.lv[l].nbd; }
+    __device__ static int groups(const BatchSim &s, int l) { return cycle_of<T>(s).lv[l].nbd; }
     __device__ static void run(const SubGrid &g, const BatchSim &s, int l) {
-        const BatchLevel &L = s.lv[l];
-        const int *done = &s.st_pois->done;
+        const BatchLevelT<T> &L = cycle_of<T>(s).lv[l];
+        const int *done = &pois_state<T>(s)->done;
         if constexpr (F == MGF_STAGED)
-            mg_down_staged_body<double>(g, L.nx, L.ny, L.P, L.gx, L.pc, L.b, L.x, L.Pc, L.nxc, L.nyc, L.dinvc, L.bc,
-                                        done);
+            mg_down_staged_body<T>(g, L.nx, L.ny, L.P, L.gx, L.pc, L.b, L.x, L.Pc, L.nxc, L.nyc, L.dinvc, L.bc,
+                                   done);
         else if constexpr (F == MGF_STAGED_LDS)
-            mg_down_lds_body<double, MTY>(g, L.nx, L.ny, L.P, L.gx, L.pc, L.b, L.x, L.Pc, L.nxc, L.nyc, L.dinvc,
-                                          L.bc, done);
+            mg_down_lds_body<T, MTY>(g, L.nx, L.ny, L.P, L.gx, L.pc, L.b, L.x, L.Pc, L.nxc, L.nyc, L.dinvc, L.bc,
+                                     done);
         else if constexpr (F == MGF_STAGED_LDS_HALF)
-            mg_down_lds_body<double, MTY / 2>(g, L.nx, L.ny, L.P, L.gx, L.pc, L.b, L.x, L.Pc, L.nxc, L.nyc, L.dinvc,
-                                              L.bc, done);
+            mg_down_lds_body<T, MTY / 2>(g, L.nx, L.ny, L.P, L.gx, L.pc, L.b, L.x, L.Pc, L.nxc, L.nyc, L.dinvc,
+                                         L.bc, done);
         else if constexpr (F == MGF_PLAIN)
-            mg_down_body<double, MTY>(g, L.nx, L.ny, L.P, L.gx, L.pc, L.b, L.x, L.Pc, L.nxc, L.nyc, L.dinvc, L.bc,
-                                      done);
+            mg_down_body<T, MTY>(g, L.nx, L.ny, L.P, L.gx, L.pc, L.b, L.x, L.Pc, L.nxc, L.nyc, L.dinvc, L.bc, done);
         else
-            mg_down_body<double, MTY_SMALL>(g, L.nx, L.ny, L.P, L.gx, L.pc, L.b, L.x, L.Pc, L.nxc, L.nyc, L.dinvc,
-                                            L.bc, done);
+            mg_down_body<T, MTY_SMALL>(g, L.nx, L.ny, L.P, L.gx, L.pc, L.b, L.x, L.Pc, L.nxc, L.nyc, L.dinvc, L.bc,
+                                       done);
     }
 };
 // The finest level's up-sweep (STATS) writes the statistics of z.
-template <int F, bool STATS>
+template <class T, int F, bool STATS>
 struct OpMgUp {
     static constexpr int BT = NT;
-    __device__ static int groups(const BatchSim &s, int l) { return s.lv[l].nbu; }
+    __device__ static int groups(const BatchSim &s, int l) { return cycle_of<T>(s).lv[l].nbu; }
     __device__ static void run(const SubGrid &g, const BatchSim &s, int l) {
-        const BatchLevel &L = s.lv[l];
-        const int *done = &s.st_pois->done;
+        const BatchLevelT<T> &L = cycle_of<T>(s).lv[l];
+        const int *done = &pois_state<T>(s)->done;
         double *po = STATS ? s.part[PB_UPD] : nullptr;
         if constexpr (F == MGF_STAGED)
-            mg_up_staged_body<double, STATS>(g, L.nx, L.ny, L.P, L.gx, L.pc, L.b, L.x, L.xc, L.Pc, L.xt, po, L.nbu,
-                                             done);
+            mg_up_staged_body<T, STATS>(g, L.nx, L.ny, L.P, L.gx, L.pc, L.b, L.x, L.xc, L.Pc, L.xt, po, L.nbu, done);
         else if constexpr (F == MGF_STAGED_LDS)
-            mg_up_lds_body<double, STATS, MTY>(g, L.nx, L.ny, L.P, L.gx, L.pc, L.b, L.x, L.xc, L.Pc, L.xt, po,
-                                               L.nbu, done);
+            mg_up_lds_body<T, STATS, MTY>(g, L.nx, L.ny, L.P, L.gx, L.pc, L.b, L.x, L.xc, L.Pc, L.xt, po, L.nbu,
+                                          done);
         else if constexpr (F == MGF_STAGED_LDS_HALF)
-            mg_up_lds_body<double, STATS, MTY / 2>(g, L.nx, L.ny, L.P, L.gx, L.pc, L.b, L.x, L.xc, L.Pc, L.xt, po,
-                                                   L.nbu, done);
+            mg_up_lds_body<T, STATS, MTY / 2>(g, L.nx, L.ny, L.P, L.gx, L.pc, L.b, L.x, L.xc, L.Pc, L.xt, po, L.nbu,
+                                              done);
         else if constexpr (F == MGF_PLAIN)
-            mg_up_body<double, STATS, MTY>(g, L.nx, L.ny, L.P, L.gx, L.pc, L.b, L.x, L.xc, L.Pc, L.xt, po, L.nbu,
-                                           done);
+            mg_up_body<T, STATS, MTY>(g, L.nx, L.ny, L.P, L.gx, L.pc, L.b, L.x, L.xc, L.Pc, L.xt, po, L.nbu, done);
         else
-            mg_up_body<double, STATS, MTY_SMALL>(g, L.nx, L.ny, L.P, L.gx, L.pc, L.b, L.x, L.xc, L.Pc, L.xt, po,
-                                                 L.nbu, done);
+            mg_up_body<T, STATS, MTY_SMALL>(g, L.nx, L.ny, L.P, L.gx, L.pc, L.b, L.x, L.xc, L.Pc, L.xt, po, L.nbu,
+                                            done);
     }
 };
+template <class T>
 struct OpCoarsest {
     static constexpr int BT = NT;
     __device__ static int groups(const BatchSim &, int) { return 1; }
     __device__ static void run(const SubGrid &, const BatchSim &s, int) {
-        mg_coarsest_body<double>(s.ncoarse, s.pidx, s.pinv, s.cb, s.cxo, &s.st_pois->done);
+        const BatchCycle<T> &y = cycle_of<T>(s);
+        mg_coarsest_body<T>(s.ncoarse, s.pidx, s.pinv, y.cb, y.cxo, &pois_state<T>(s)->done);
     }
 };
-template <bool LDS>
+template <class T, bool LDS>
 struct OpTail {
     static constexpr int BT = TT;
     __device__ static int groups(const BatchSim &, int) { return 1; }
     __device__ static void run(const SubGrid &, const BatchSim &s, int) {
         if constexpr (LDS)
-            mg_tail_lds_body<double>(s.tail);
+            mg_tail_lds_body<T>(cycle_of<T>(s).tail);
         else
-            mg_tail_body<double>(s.tail);
+            mg_tail_body<T>(cycle_of<T>(s).tail);
+    }
+};
+// x += dx after an inner solve of precision 1: the predictor's U* (u = 0)
+// or the pressure's Phi (u = 1).
+struct OpAddCorr {
+    static constexpr int BT = NT;
+    __device__ static int groups(const BatchSim &s, int u) { return u == 0 ? s.fb2 : s.fb1; }
+    __device__ static void run(const SubGrid &g, const BatchSim &s, int u) {
+        if (u == 0)
+            add_correction_body(g, 2 * s.n, s.a[A_USX], s.f[G_PXX]);
+        else
+            add_correction_body(g, s.n, s.a[A_PHI], s.f[G_X]);
     }
 };
 struct OpCorrect {
@@ -4427,18 +4518,46 @@ struct OpDiag {
     }
 };
 
-// Copies every simulation's solver state (which = 0: predictor, 1:
-// pressure) or diagnostics (which = 2) into one array for a single read-back.
+// What a gather reads from each simulation.
+enum BatchGather {
+    GAT_PRED = 0,      // the FP64 predictor CG's state
+    GAT_POIS = 1,      // the FP64 pressure CG's state
+    GAT_DIAG = 2,      // the diagnostics
+    GAT_PRED_IN = 3,   // the inner predictor CG's state (precision 1)
+    GAT_POIS_IN = 4,   // the inner pressure CG's state (precision 1)
+    GAT_PRED_RES = 5,  // the predictor residual's statistics (precision 1; 7 values)
+    GAT_POIS_RES = 6   // the pressure residual's statistics (precision 1; 8 values)
+};
+// Copies every simulation's solver state, diagnostics or residual
+// statistics into one array for a single read-back.
 __global__ __launch_bounds__(NT) void k_batch_gather(const BatchSim *__restrict__ sims, int n, int which,
-                                                     CgState *__restrict__ cg, DiagState *__restrict__ dg) {
+                                                     CgState *__restrict__ cg, DiagState *__restrict__ dg,
+                                                     double *__restrict__ st8) {
     const int k = blockIdx.x * NT + threadIdx.x;
     if (k >= n) return;
-    if (which == 0)
-        cg[k] = *sims[k].st_pred;
-    else if (which == 1)
-        cg[k] = *sims[k].st_pois;
-    else
-        dg[k] = *sims[k].diag;
+    const BatchSim &s = sims[k];
+    switch (which) {
+    case GAT_PRED: cg[k] = *s.st_pred; break;
+    case GAT_POIS: cg[k] = *s.st_pois; break;
+    case GAT_DIAG: dg[k] = *s.diag; break;
+    case GAT_PRED_IN: cg[k] = *s.st_pred_in; break;
+    case GAT_POIS_IN: cg[k] = *s.st_pois_in; break;
+    default: {
+        const double *src = which == GAT_PRED_RES ? s.part[PB_INIT] : s.outer;
+        const int m = which == GAT_PRED_RES ? 7 : 8;
+        for (int q = 0; q < 8; ++q) st8[(size_t)k * 8 + q] = q < m ? src[q] : 0.0;
+    }
+    }
+}
+// The relative tolerance of the next inner solve of every simulation in
+// the sweep (which = 0: predictor, 1: pressure), from tol2[k].
+__global__ __launch_bounds__(NT) void k_batch_set_tol(const BatchSim *__restrict__ sims, int n, int which,
+                                                      const double *__restrict__ tol2) {
+    const int k = blockIdx.x * NT + threadIdx.x;
+    if (k >= n) return;
+    const BatchSim &s = sims[k];
+    if (s.active && !*s.active) return;
+    (which == 0 ? s.st_pred_in : s.st_pois_in)->tol2 = tol2[k];
 }
 
 // A launch of the fused batch: its slice of the work-group table.
@@ -4455,24 +4574,104 @@ struct ccns_batch {
     int nthreads = 0;
     // fused batches only
     bool fused = false;
+    int prec = 0;                   // the precision of every simulation
     hipStream_t stream = nullptr;
     BatchSim *dsims = nullptr;      // device copies of the descriptors
     unsigned *dmap = nullptr;       // work-group tables
     CgState *dcg = nullptr, *hcg = nullptr;       // gathered solver states (device, pinned host)
     DiagState *ddg = nullptr, *hdg = nullptr;     // gathered diagnostics
+    double *dst8 = nullptr, *hst8 = nullptr;      // gathered residual statistics (8 per simulation)
+    // precision 1: the sweep's active flags and inner tolerances, uploaded
+    // from a ring of pinned slots (a slot is reused only after a read-back
+    // has waited for the stream, so no upload still reads it)
+    int *dact = nullptr;
+    double *dtol = nullptr;
+    char *hring = nullptr;
+    int ring_used = 0;
+    std::vector<int> act;
+    std::vector<double> tol2;
     std::vector<BatchSim> hsims;
     std::vector<unsigned char> forms;  // the cycle forms the tables were built for
     size_t map_cap = 0;
     int maxcyc = 0, tail_lds = 0;
-    BatchTable pred[4], one, split, dc, dp, upd, correct;
+    BatchTable pred[4], one, split, dc, dp, upd, fb1, fb2;
     BatchTable down[BATCH_LEVELS][6], up[BATCH_LEVELS][6], bot[3];
 };
 
 namespace {
 
-// The descriptor of context c (precision 0, multigrid preconditioner).
-BatchSim batch_sim(ccns_ctx *c) {
+constexpr int BATCH_RING = 8;
+
+size_t ring_slot_bytes(int n) { return align_up((size_t)n * (sizeof(int) + sizeof(double)), 256); }
+
+// The descriptor of cycle hierarchy mg (FP64 or float) of context c, whose
+// solve's done flag is *done.
+template <class T>
+void batch_cycle(BatchCycle<T> &y, ccns_ctx *c, std::vector<ccns_ctx::LevelT<T>> &mg, const int *done) {
+    const int dbl = std::is_same<T, double>::value ? 1 : 0;
+    const int ncyc = (int)cycle_levels(mg);
+    y.ncyc = ncyc;
+    // the coarse end below the cycle levels: the coarsest grid's
+    // pseudo-inverse, or the one-group tail of the small levels
+    const size_t ts = (size_t)ncyc;
+    const T *bottom_out;
+    if (ts + 1 == mg.size()) {
+        y.bottom = BOT_COARSEST;
+        y.cb = mg[ts].b;
+        y.cxo = mg[ts].x;
+        bottom_out = mg[ts].x;
+    } else {
+        TailDesc<T> &d = y.tail;
+        d.nlev = (int)(mg.size() - ts);
+        for (int t = 0; t < d.nlev; ++t) {
+            auto &M = mg[ts + t];
+            d.lv[t] = TailLevel<T>{M.cx, M.cy, M.dinv, M.b, M.x, M.xt, M.L.nx, M.L.ny, (int)M.L.pitch};
+        }
+        d.ncoarse = c->ncoarse_act;
+        d.idx = c->pidx;
+        d.pinv = c->pinv;
+        d.done = done;
+        d.out = d.nlev >= 2 ? mg[ts].xt : mg[ts].x;
+        size_t elems = 0;
+        for (int t = 0; t < d.nlev; ++t) {
+            d.lofs[t] = (int)elems;
+            elems += 6 * (size_t)(d.lv[t].nx + 2) * (d.lv[t].ny + 2);
+        }
+        y.bottom = elems * sizeof(T) <= (size_t)c->tail_lds ? BOT_TAIL_LDS : BOT_TAIL;
+        y.tail_bytes = (int)(elems * sizeof(T));
+        bottom_out = d.out;
+    }
+    for (int l = 0; l < ncyc; ++l) {
+        auto &F = mg[l];
+        auto &C = mg[l + 1];
+        BatchLevelT<T> &v = y.lv[l];
+        v.nx = F.L.nx;
+        v.ny = F.L.ny;
+        v.P = (int)F.L.pitch;
+        v.gx = (F.L.nx + TX - 1) / TX;
+        v.pc = PoisCoefT<T>{F.cx, F.cy, F.dinv};
+        v.b = F.b;
+        v.x = F.x;
+        v.xt = F.xt;
+        v.Pc = (int)C.L.pitch;
+        v.nxc = C.L.nx;
+        v.nyc = C.L.ny;
+        v.dinvc = C.dinv;
+        v.bc = C.b;
+        v.xc = l + 1 < ncyc ? mg[l + 1].xt : bottom_out;
+        v.fd = c->mgf[dbl][0][l];
+        v.fu = c->mgf[dbl][1][l];
+        v.nbd = mg_form_groups(v.nx, v.ny, v.fd);
+        v.nbu = mg_form_groups(v.nx, v.ny, v.fu);
+    }
+    y.z = ncyc >= 1 ? mg[0].xt : bottom_out;
+}
+
+// The descriptor of context c (multigrid preconditioner; precision 0 or 1).
+BatchSim batch_sim(ccns_batch *b, int k) {
+    ccns_ctx *c = b->sims[k];
     BatchSim s{};
+    s.active = b->prec == 1 ? b->dact + k : nullptr;
     const Layout &L = c->w.L;
     s.P = (int)L.pitch;
     s.rows = (int)L.rows;
@@ -4486,6 +4685,17 @@ BatchSim batch_sim(ccns_ctx *c) {
         s.pd.tab = c->tab;
     }
     const ccns_params &p = c->prm;
+    if (p.precision == 1) {
+        s.pf = PredCoefT<float>{ViscCoefT<float>{c->f[G_BXX], c->f[G_BXY], c->f[G_BYY], c->f[G_BYX], c->f[G_WXX],
+                                                 c->f[G_WYY], c->f[G_NXX], c->f[G_NXY], c->f[G_NYX], c->f[G_NYY]},
+                                c->f[G_VU], c->f[G_VV], c->f[G_HDX], c->f[G_HDY], p.rho / p.tau, p.mu, nullptr,
+                                nullptr};
+        if (c->ncls) {
+            s.pf.cls = c->cls;
+            s.pf.tab = c->tab32;
+        }
+        for (int q = 0; q < G_COUNT; ++q) s.f[q] = c->f[q];
+    }
     s.rho = p.rho;
     s.grav_x = p.gx;
     s.grav_y = p.gy;
@@ -4494,111 +4704,77 @@ BatchSim batch_sim(ccns_ctx *c) {
     s.pcoef = p.tau * p.mu / (2.0 * p.rho);
     s.conv_valid = c->conv_valid;
     s.of = outflow_desc(c);
-    for (int k = 0; k < A_COUNT; ++k) s.a[k] = c->a[k];
-    for (int k = 0; k < PB_COUNT; ++k) s.part[k] = c->part[k];
+    for (int q = 0; q < A_COUNT; ++q) s.a[q] = c->a[q];
+    for (int q = 0; q < PB_COUNT; ++q) s.part[q] = c->part[q];
+    s.outer = c->outer;
     s.st_pred = c->st_pred;
     s.st_pois = c->st_pois;
+    s.st_pred_in = c->st_pred_in;
+    s.st_pois_in = c->st_pois_in;
     s.diag = c->diag;
     s.dgc = DiagCoef{c->a[A_AX], c->a[A_AY], c->a[A_HET], c->a[A_DINV], c->a[A_VUR], c->a[A_VVR],
                      c->a[A_VU], c->a[A_VV], c->a[A_CX], c->a[A_CY], c->a[A_VINV]};
     s.dc = c->dc;
     s.dp = c->dp;
     s.nl = update_blocks(L.n);
-    auto &mg = c->mg;
-    const int ncyc = (int)cycle_levels(mg);
-    s.ncyc = ncyc;
-    // the coarse end below the cycle levels: the coarsest grid's
-    // pseudo-inverse, or the one-group tail of the small levels
-    const size_t ts = (size_t)ncyc;
-    const double *bottom_out;
-    if (ts + 1 == mg.size()) {
-        s.bottom = BOT_COARSEST;
-        s.ncoarse = c->ncoarse_act;
-        s.pidx = c->pidx;
-        s.pinv = c->pinv;
-        s.cb = mg[ts].b;
-        s.cxo = mg[ts].x;
-        bottom_out = mg[ts].x;
-    } else {
-        TailDesc<double> &d = s.tail;
-        d.nlev = (int)(mg.size() - ts);
-        for (int t = 0; t < d.nlev; ++t) {
-            ccns_ctx::Level &M = mg[ts + t];
-            d.lv[t] = TailLevel<double>{M.cx, M.cy, M.dinv, M.b, M.x, M.xt, M.L.nx, M.L.ny, (int)M.L.pitch};
-        }
-        d.ncoarse = c->ncoarse_act;
-        d.idx = c->pidx;
-        d.pinv = c->pinv;
-        d.done = &c->st_pois->done;
-        d.out = d.nlev >= 2 ? mg[ts].xt : mg[ts].x;
-        size_t elems = 0;
-        for (int t = 0; t < d.nlev; ++t) {
-            d.lofs[t] = (int)elems;
-            elems += 6 * (size_t)(d.lv[t].nx + 2) * (d.lv[t].ny + 2);
-        }
-        s.bottom = elems * sizeof(double) <= (size_t)c->tail_lds ? BOT_TAIL_LDS : BOT_TAIL;
-        s.tail_bytes = (int)(elems * sizeof(double));
-        bottom_out = d.out;
-    }
-    for (int l = 0; l < ncyc; ++l) {
-        ccns_ctx::Level &F = mg[l], &C = mg[l + 1];
-        BatchLevel &v = s.lv[l];
-        v.nx = F.L.nx;
-        v.ny = F.L.ny;
-        v.P = (int)F.L.pitch;
-        v.gx = (F.L.nx + TX - 1) / TX;
-        v.pc = PoisCoef{F.cx, F.cy, F.dinv};
-        v.b = F.b;
-        v.x = F.x;
-        v.xt = F.xt;
-        v.Pc = (int)C.L.pitch;
-        v.nxc = C.L.nx;
-        v.nyc = C.L.ny;
-        v.dinvc = C.dinv;
-        v.bc = C.b;
-        v.xc = l + 1 < ncyc ? mg[l + 1].xt : bottom_out;
-        v.fd = c->mgf[1][0][l];
-        v.fu = c->mgf[1][1][l];
-        v.nbd = mg_form_groups(v.nx, v.ny, v.fd);
-        v.nbu = mg_form_groups(v.nx, v.ny, v.fu);
-    }
-    s.z = ncyc >= 1 ? mg[0].xt : bottom_out;
+    s.fb1 = flat_blocks(L.n);
+    s.fb2 = flat_blocks(2 * L.n);
+    s.ncoarse = c->ncoarse_act;
+    s.pidx = c->pidx;
+    s.pinv = c->pinv;
+    batch_cycle<double>(s.mg, c, c->mg, &c->st_pois->done);
+    if (p.precision == 1) batch_cycle<float>(s.mg32, c, c->mg32, &c->st_pois_in->done);
     return s;
 }
 
 int pred_variant(const ccns_ctx *c) { return (c->prm.visc_form == 0 ? 1 : 0) | (c->ncls ? 2 : 0); }
+
+// The cycle levels' forms of context c in the batch's precision: every one
+// resolved, the finest level's up-sweep in a form that writes the
+// statistics (1-3), between 1 and BATCH_LEVELS cycle levels.
+template <class T>
+bool batch_forms_ok(const ccns_ctx *c, const std::vector<ccns_ctx::LevelT<T>> &mg) {
+    const int dbl = std::is_same<T, double>::value ? 1 : 0;
+    const int ncyc = (int)cycle_levels(mg);
+    if (ncyc < 1 || ncyc > BATCH_LEVELS) return false;
+    for (int l = 0; l < ncyc; ++l) {
+        const int fd = c->mgf[dbl][0][l], fu = c->mgf[dbl][1][l];
+        if (fd < MGF_STAGED || fd > MGF_STAGED_LDS_HALF || fu < MGF_STAGED || fu > MGF_STAGED_LDS_HALF ||
+            (l == 0 && fu > MGF_PLAIN))
+            return false;
+    }
+    return true;
+}
 
 // Builds the descriptors and the work-group tables of every launch (the
 // simulations in the batch's order, largest first, so that the big grids'
 // groups are dispatched first), and uploads them.
 ccns_status batch_build(ccns_batch *b) {
     const int n = (int)b->sims.size();
+    const int dbl = b->prec == 1 ? 0 : 1;  // the forms of the cycle the batch runs
     b->hsims.resize(n);
     b->forms.clear();
     b->maxcyc = 0;
     b->tail_lds = 0;
     for (int k = 0; k < n; ++k) {
         ccns_ctx *c = b->sims[k];
-        // every level's forms resolved, the finest level's up-sweep in a
-        // form that writes the statistics (1-3), at least one cycle level
-        const int ncyc = (int)cycle_levels(c->mg);
-        if (ncyc < 1 || ncyc > BATCH_LEVELS) return CCNS_EINVAL;
-        for (int l = 0; l < ncyc; ++l) {
-            const int fd = c->mgf[1][0][l], fu = c->mgf[1][1][l];
-            if (fd < MGF_STAGED || fd > MGF_STAGED_LDS_HALF || fu < MGF_STAGED || fu > MGF_STAGED_LDS_HALF ||
-                (l == 0 && fu > MGF_PLAIN))
-                return CCNS_EINVAL;
-        }
-        b->hsims[k] = batch_sim(c);
-        b->forms.insert(b->forms.end(), &c->mgf[1][0][0], &c->mgf[1][0][0] + 2 * 16);
-        b->maxcyc = std::max(b->maxcyc, b->hsims[k].ncyc);
-        if (b->hsims[k].bottom == BOT_TAIL_LDS) b->tail_lds = std::max(b->tail_lds, b->hsims[k].tail_bytes);
+        if (!(b->prec == 1 ? batch_forms_ok<float>(c, c->mg32) : batch_forms_ok<double>(c, c->mg)))
+            return CCNS_EINVAL;
+        b->hsims[k] = batch_sim(b, k);
+        b->forms.insert(b->forms.end(), &c->mgf[dbl][0][0], &c->mgf[dbl][0][0] + 2 * 16);
+        const int ncyc = b->prec == 1 ? b->hsims[k].mg32.ncyc : b->hsims[k].mg.ncyc;
+        const int bottom = b->prec == 1 ? b->hsims[k].mg32.bottom : b->hsims[k].mg.bottom;
+        const int tb = b->prec == 1 ? b->hsims[k].mg32.tail_bytes : b->hsims[k].mg.tail_bytes;
+        b->maxcyc = std::max(b->maxcyc, ncyc);
+        if (bottom == BOT_TAIL_LDS) b->tail_lds = std::max(b->tail_lds, tb);
     }
     // the LDS-resident coarse ends take up to the context's budget of dynamic LDS
-    if (b->tail_lds > 0 && hipFuncSetAttribute((const void *)k_batch<OpTail<true>>,
-                                               hipFuncAttributeMaxDynamicSharedMemorySize,
-                                               b->tail_lds) != hipSuccess)
-        return CCNS_EDEVICE;
+    if (b->tail_lds > 0) {
+        const void *kt = b->prec == 1 ? (const void *)k_batch<OpTail<float, true>>
+                                      : (const void *)k_batch<OpTail<double, true>>;
+        if (hipFuncSetAttribute(kt, hipFuncAttributeMaxDynamicSharedMemorySize, b->tail_lds) != hipSuccess)
+            return CCNS_EDEVICE;
+    }
     std::vector<unsigned> map;
     bool ok = true;
     auto table = [&](auto pick, auto groups) {
@@ -4622,14 +4798,23 @@ ccns_status batch_build(ccns_batch *b) {
     b->dc = table(all, [&](int k) { return S[k].dc.nblk; });
     b->dp = table(all, [&](int k) { return S[k].dp.nblk; });
     b->upd = table(all, [&](int k) { return S[k].nl; });
+    b->fb1 = table(all, [&](int k) { return b->prec == 1 ? S[k].fb1 : 0; });
+    b->fb2 = table(all, [&](int k) { return b->prec == 1 ? S[k].fb2 : 0; });
+    auto lvl = [&](int k, int l) -> const auto & { return S[k].mg.lv[l]; };
+    auto lvl32 = [&](int k, int l) -> const auto & { return S[k].mg32.lv[l]; };
+    auto ncyc = [&](int k) { return b->prec == 1 ? S[k].mg32.ncyc : S[k].mg.ncyc; };
+    auto fd = [&](int k, int l) { return b->prec == 1 ? lvl32(k, l).fd : lvl(k, l).fd; };
+    auto fu = [&](int k, int l) { return b->prec == 1 ? lvl32(k, l).fu : lvl(k, l).fu; };
+    auto nbd = [&](int k, int l) { return b->prec == 1 ? lvl32(k, l).nbd : lvl(k, l).nbd; };
+    auto nbu = [&](int k, int l) { return b->prec == 1 ? lvl32(k, l).nbu : lvl(k, l).nbu; };
     for (int l = 0; l < BATCH_LEVELS; ++l)
         for (int f = 0; f < 6; ++f) {
-            b->down[l][f] = table([&](int k) { return l < S[k].ncyc && S[k].lv[l].fd == f; },
-                                  [&](int k) { return S[k].lv[l].nbd; });
-            b->up[l][f] = table([&](int k) { return l < S[k].ncyc && S[k].lv[l].fu == f; },
-                                [&](int k) { return S[k].lv[l].nbu; });
+            b->down[l][f] = table([&](int k) { return l < ncyc(k) && fd(k, l) == f; }, [&](int k) { return nbd(k, l); });
+            b->up[l][f] = table([&](int k) { return l < ncyc(k) && fu(k, l) == f; }, [&](int k) { return nbu(k, l); });
         }
-    for (int t = 0; t < 3; ++t) b->bot[t] = table([&](int k) { return S[k].bottom == t; }, [](int) { return 1; });
+    for (int t = 0; t < 3; ++t)
+        b->bot[t] = table([&](int k) { return (b->prec == 1 ? S[k].mg32.bottom : S[k].mg.bottom) == t; },
+                          [](int) { return 1; });
     if (!ok) return CCNS_EINVAL;
     if (map.size() > b->map_cap) {
         if (b->dmap) (void)hipFree(b->dmap);
@@ -4643,6 +4828,7 @@ ccns_status batch_build(ccns_batch *b) {
             hipSuccess ||
         hipStreamSynchronize(b->stream) != hipSuccess)
         return CCNS_EDEVICE;
+    b->ring_used = 0;
     return CCNS_OK;
 }
 
@@ -4657,44 +4843,68 @@ void blaunch_w7(ccns_batch *b, const BatchTable &t, int u) {
         hipLaunchKernelGGL(k_batch_w7<Op>, dim3(t.nblk), dim3(Op::BT), 0, b->stream, b->dsims, b->dmap + t.off, u);
 }
 
-// One V-cycle of every simulation on its finest level's residual: the
-// down-sweeps level by level, the coarse ends, the up-sweeps back up, and
-// the reduction of the statistics of z.
+// One V-cycle of every simulation on its finest level's residual, in
+// storage type T: the down-sweeps level by level, the coarse ends, the
+// up-sweeps back up, and the reduction of the statistics of z.
+template <class T>
 void batch_vcycle(ccns_batch *b) {
     for (int l = 0; l < b->maxcyc; ++l) {
-        blaunch<OpMgDown<MGF_STAGED>>(b, b->down[l][MGF_STAGED], l);
-        blaunch<OpMgDown<MGF_STAGED_LDS>>(b, b->down[l][MGF_STAGED_LDS], l);
-        blaunch<OpMgDown<MGF_PLAIN>>(b, b->down[l][MGF_PLAIN], l);
-        blaunch<OpMgDown<MGF_PLAIN_SHORT>>(b, b->down[l][MGF_PLAIN_SHORT], l);
-        blaunch<OpMgDown<MGF_STAGED_LDS_HALF>>(b, b->down[l][MGF_STAGED_LDS_HALF], l);
+        blaunch<OpMgDown<T, MGF_STAGED>>(b, b->down[l][MGF_STAGED], l);
+        blaunch<OpMgDown<T, MGF_STAGED_LDS>>(b, b->down[l][MGF_STAGED_LDS], l);
+        blaunch<OpMgDown<T, MGF_PLAIN>>(b, b->down[l][MGF_PLAIN], l);
+        blaunch<OpMgDown<T, MGF_PLAIN_SHORT>>(b, b->down[l][MGF_PLAIN_SHORT], l);
+        blaunch<OpMgDown<T, MGF_STAGED_LDS_HALF>>(b, b->down[l][MGF_STAGED_LDS_HALF], l);
     }
-    blaunch<OpCoarsest>(b, b->bot[BOT_COARSEST], 0);
-    blaunch<OpTail<true>>(b, b->bot[BOT_TAIL_LDS], 0, (size_t)b->tail_lds);
-    blaunch<OpTail<false>>(b, b->bot[BOT_TAIL], 0);
+    blaunch<OpCoarsest<T>>(b, b->bot[BOT_COARSEST], 0);
+    blaunch<OpTail<T, true>>(b, b->bot[BOT_TAIL_LDS], 0, (size_t)b->tail_lds);
+    blaunch<OpTail<T, false>>(b, b->bot[BOT_TAIL], 0);
     for (int l = b->maxcyc - 1; l >= 1; --l) {
-        blaunch<OpMgUp<MGF_STAGED, false>>(b, b->up[l][MGF_STAGED], l);
-        blaunch<OpMgUp<MGF_STAGED_LDS, false>>(b, b->up[l][MGF_STAGED_LDS], l);
-        blaunch<OpMgUp<MGF_PLAIN, false>>(b, b->up[l][MGF_PLAIN], l);
-        blaunch<OpMgUp<MGF_PLAIN_SHORT, false>>(b, b->up[l][MGF_PLAIN_SHORT], l);
-        blaunch<OpMgUp<MGF_STAGED_LDS_HALF, false>>(b, b->up[l][MGF_STAGED_LDS_HALF], l);
+        blaunch<OpMgUp<T, MGF_STAGED, false>>(b, b->up[l][MGF_STAGED], l);
+        blaunch<OpMgUp<T, MGF_STAGED_LDS, false>>(b, b->up[l][MGF_STAGED_LDS], l);
+        blaunch<OpMgUp<T, MGF_PLAIN, false>>(b, b->up[l][MGF_PLAIN], l);
+        blaunch<OpMgUp<T, MGF_PLAIN_SHORT, false>>(b, b->up[l][MGF_PLAIN_SHORT], l);
+        blaunch<OpMgUp<T, MGF_STAGED_LDS_HALF, false>>(b, b->up[l][MGF_STAGED_LDS_HALF], l);
     }
-    blaunch<OpMgUp<MGF_STAGED, true>>(b, b->up[0][MGF_STAGED], 0);
-    blaunch<OpMgUp<MGF_STAGED_LDS, true>>(b, b->up[0][MGF_STAGED_LDS], 0);
-    blaunch<OpMgUp<MGF_PLAIN, true>>(b, b->up[0][MGF_PLAIN], 0);
-    blaunch<OpReduce>(b, b->one, 1);
+    blaunch<OpMgUp<T, MGF_STAGED, true>>(b, b->up[0][MGF_STAGED], 0);
+    blaunch<OpMgUp<T, MGF_STAGED_LDS, true>>(b, b->up[0][MGF_STAGED_LDS], 0);
+    blaunch<OpMgUp<T, MGF_PLAIN, true>>(b, b->up[0][MGF_PLAIN], 0);
+    blaunch<OpReduce>(b, b->one, std::is_same<T, double>::value ? RED_CYCLE : RED_CYCLE32);
 }
 
-// Reads every simulation's solver state (which = 0, 1) or diagnostics (2)
-// after the work queued so far.
+// Reads every simulation's solver state, diagnostics or residual
+// statistics (BatchGather) after the work queued so far.
 ccns_status batch_read(ccns_batch *b, int which) {
     const int n = (int)b->sims.size();
     hipLaunchKernelGGL(k_batch_gather, dim3((n + NT - 1) / NT), dim3(NT), 0, b->stream, b->dsims, n, which, b->dcg,
-                       b->ddg);
+                       b->ddg, b->dst8);
     if (hipGetLastError() != hipSuccess) return CCNS_EDEVICE;
-    hipError_t e = which == 2
-                       ? hipMemcpyAsync(b->hdg, b->ddg, n * sizeof(DiagState), hipMemcpyDeviceToHost, b->stream)
-                       : hipMemcpyAsync(b->hcg, b->dcg, n * sizeof(CgState), hipMemcpyDeviceToHost, b->stream);
+    hipError_t e;
+    if (which == GAT_DIAG)
+        e = hipMemcpyAsync(b->hdg, b->ddg, n * sizeof(DiagState), hipMemcpyDeviceToHost, b->stream);
+    else if (which == GAT_PRED_RES || which == GAT_POIS_RES)
+        e = hipMemcpyAsync(b->hst8, b->dst8, (size_t)n * 8 * sizeof(double), hipMemcpyDeviceToHost, b->stream);
+    else
+        e = hipMemcpyAsync(b->hcg, b->dcg, n * sizeof(CgState), hipMemcpyDeviceToHost, b->stream);
     if (e != hipSuccess || hipStreamSynchronize(b->stream) != hipSuccess) return CCNS_EDEVICE;
+    b->ring_used = 0;  // every upload queued so far has been read
+    return CCNS_OK;
+}
+
+// Uploads the active flags and inner tolerances (precision 1) for the
+// launches queued after this.
+ccns_status batch_upload(ccns_batch *b) {
+    const int n = (int)b->sims.size();
+    if (b->ring_used == BATCH_RING) {
+        if (hipStreamSynchronize(b->stream) != hipSuccess) return CCNS_EDEVICE;
+        b->ring_used = 0;
+    }
+    char *slot = b->hring + (size_t)b->ring_used++ * ring_slot_bytes(n);
+    std::memcpy(slot, b->act.data(), n * sizeof(int));
+    std::memcpy(slot + (size_t)n * sizeof(int), b->tol2.data(), n * sizeof(double));
+    if (hipMemcpyAsync(b->dact, slot, n * sizeof(int), hipMemcpyHostToDevice, b->stream) != hipSuccess ||
+        hipMemcpyAsync(b->dtol, slot + (size_t)n * sizeof(int), n * sizeof(double), hipMemcpyHostToDevice,
+                       b->stream) != hipSuccess)
+        return CCNS_EDEVICE;
     return CCNS_OK;
 }
 
@@ -4710,89 +4920,39 @@ ccns_solve_info solve_info(const CgState &h, bool clamp) {
     return i;
 }
 
-// One projection step of every simulation, each phase one launch (per
-// kernel variant) over all of their work-groups.  Each CG runs in lockstep:
-// a simulation whose solve has stopped returns at once from its groups, and
-// the host looks at all done flags in one read-back per chunk of iterations.
-ccns_status batch_fused_step(ccns_batch *b, std::vector<ccns_step_info> &info, std::vector<ccns_status> &st) {
+// The contexts' own work first (their set-up and any solo calls), and the
+// descriptors again where a context changed (its first convection, its
+// cycle forms).
+ccns_status batch_begin(ccns_batch *b) {
     const int n = (int)b->sims.size();
-    // the contexts' own work first (their set-up and any solo calls)
+    const int dbl = b->prec == 1 ? 0 : 1;
     for (ccns_ctx *c : b->sims)
         if (hipStreamSynchronize(c->stream) != hipSuccess) return CCNS_EDEVICE;
     bool rebuild = false;
     for (int k = 0; k < n && !rebuild; ++k) {
         const ccns_ctx *c = b->sims[k];
         rebuild = b->hsims[k].conv_valid != c->conv_valid ||
-                  std::memcmp(&b->forms[(size_t)k * 32], &c->mgf[1][0][0], 32) != 0;
+                  std::memcmp(&b->forms[(size_t)k * 32], &c->mgf[dbl][0][0], 32) != 0;
     }
-    if (rebuild) {
-        ccns_status s = batch_build(b);
-        if (s != CCNS_OK) return s;
-    }
-    // predictor
+    return rebuild ? batch_build(b) : CCNS_OK;
+}
+
+// The predictor's right-hand side of every simulation (conv^n; U* := U^n).
+void batch_pred_rhs(ccns_batch *b) {
     blaunch<OpPredRhs<false, false>>(b, b->pred[0], 0);
     blaunch<OpPredRhs<true, false>>(b, b->pred[1], 0);
     blaunch<OpPredRhs<false, true>>(b, b->pred[2], 0);
     blaunch<OpPredRhs<true, true>>(b, b->pred[3], 0);
     for (ccns_ctx *c : b->sims) c->conv_valid = 1;
-    blaunch<OpPredResid<false, false>>(b, b->pred[0], 0);
-    blaunch<OpPredResid<true, false>>(b, b->pred[1], 0);
-    blaunch<OpPredResid<false, true>>(b, b->pred[2], 0);
-    blaunch<OpPredResid<true, true>>(b, b->pred[3], 0);
-    blaunch<OpReduce>(b, b->one, 0);
-    int last = 0;
-    for (ccns_ctx *c : b->sims) last = std::max(last, c->last_pred_it);
-    int chunk = std::max(4, last + 1), it = 0;
-    for (;;) {
-        for (int u = 0; u < chunk; ++u, ++it) {
-            blaunch_w7<OpPredCg<false, false>>(b, b->pred[0], it);
-            blaunch_w7<OpPredCg<true, false>>(b, b->pred[1], it);
-            blaunch_w7<OpPredCg<false, true>>(b, b->pred[2], it);
-            blaunch_w7<OpPredCg<true, true>>(b, b->pred[3], it);
-            blaunch<OpPredSplit>(b, b->split, it);
-        }
-        ccns_status s = batch_read(b, 0);
-        if (s != CCNS_OK) return s;
-        bool all = true;
-        for (int k = 0; k < n; ++k) all = all && b->hcg[k].done;
-        if (all) break;
-        chunk = 8;
-    }
-    for (int k = 0; k < n; ++k) {
-        info[k].pred = solve_info(b->hcg[k], true);
-        b->sims[k]->last_pred_it = b->hcg[k].it_final;
-    }
-    // corrector: the pressure solve, the correction, the pressure update and
-    // the diagnostics
-    blaunch<OpPoisRhs>(b, b->dc, 0);
-    blaunch<OpPoisInit>(b, b->dc, 0);
-    batch_vcycle(b);
-    last = 0;
-    for (ccns_ctx *c : b->sims) last = std::max(last, c->last_pois_it);
-    chunk = std::max(2, last + 1);
-    it = 0;
-    for (;;) {
-        for (int u = 0; u < chunk; ++u, ++it) {
-            blaunch<OpDirZ>(b, b->dp, it);
-            blaunch<OpUpdate>(b, b->upd, it);
-            batch_vcycle(b);
-        }
-        ccns_status s = batch_read(b, 1);
-        if (s != CCNS_OK) return s;
-        bool all = true;
-        for (int k = 0; k < n; ++k) all = all && b->hcg[k].done;
-        if (all) break;
-        chunk = 2;
-    }
-    for (int k = 0; k < n; ++k) {
-        info[k].poisson = solve_info(b->hcg[k], false);
-        b->sims[k]->last_pois_it = b->hcg[k].it_final;
-        b->sims[k]->pbuf_pois = it & 1;
-    }
+}
+
+// The correction's end: U^{n+1}, the pressure update and the diagnostics.
+ccns_status batch_finish(ccns_batch *b, std::vector<ccns_step_info> &info, std::vector<ccns_status> &st) {
+    const int n = (int)b->sims.size();
     blaunch<OpCorrect>(b, b->dc, 0);
     blaunch<OpDiag>(b, b->dc, 0);
-    blaunch<OpReduce>(b, b->one, 2);
-    ccns_status s = batch_read(b, 2);
+    blaunch<OpReduce>(b, b->one, RED_DIAG);
+    ccns_status s = batch_read(b, GAT_DIAG);
     if (s != CCNS_OK) return s;
     for (int k = 0; k < n; ++k) {
         const ccns_ctx *c = b->sims[k];
@@ -4811,6 +4971,246 @@ ccns_status batch_fused_step(ccns_batch *b, std::vector<ccns_step_info> &info, s
     return CCNS_OK;
 }
 
+// Runs CG iterations of every simulation in lockstep until all of their
+// solves have stopped: iter(it) queues iteration it; the done flags come
+// back in one read-back (gather `which`) per chunk.  Returns the number of
+// iterations queued.
+template <class Iter>
+ccns_status batch_cg(ccns_batch *b, int first_chunk, int next_chunk, int which, Iter iter, int &its) {
+    const int n = (int)b->sims.size();
+    int chunk = first_chunk;
+    its = 0;
+    for (;;) {
+        for (int u = 0; u < chunk; ++u, ++its) iter(its);
+        ccns_status s = batch_read(b, which);
+        if (s != CCNS_OK) return s;
+        bool all = true;
+        for (int k = 0; k < n; ++k) all = all && (b->hcg[k].done || (b->prec == 1 && !b->act[k]));
+        if (all) return CCNS_OK;
+        chunk = next_chunk;
+    }
+}
+
+// One projection step of every simulation in precision 0.  Each phase is
+// one launch (per kernel variant) over all of their work-groups; each CG
+// runs in lockstep, a simulation whose solve has stopped returning at once
+// from its groups.
+ccns_status batch_fused_step(ccns_batch *b, std::vector<ccns_step_info> &info, std::vector<ccns_status> &st) {
+    const int n = (int)b->sims.size();
+    ccns_status s = batch_begin(b);
+    if (s != CCNS_OK) return s;
+    // predictor
+    batch_pred_rhs(b);
+    blaunch<OpPredResid<false, false, false>>(b, b->pred[0], 0);
+    blaunch<OpPredResid<false, true, false>>(b, b->pred[1], 0);
+    blaunch<OpPredResid<false, false, true>>(b, b->pred[2], 0);
+    blaunch<OpPredResid<false, true, true>>(b, b->pred[3], 0);
+    blaunch<OpReduce>(b, b->one, RED_PRED);
+    int last = 0, its = 0;
+    for (ccns_ctx *c : b->sims) last = std::max(last, c->last_pred_it);
+    s = batch_cg(b, std::max(4, last + 1), 8, GAT_PRED, [&](int it) {
+        blaunch_w7<OpPredCg<double, false, false>>(b, b->pred[0], it);
+        blaunch_w7<OpPredCg<double, true, false>>(b, b->pred[1], it);
+        blaunch_w7<OpPredCg<double, false, true>>(b, b->pred[2], it);
+        blaunch_w7<OpPredCg<double, true, true>>(b, b->pred[3], it);
+        blaunch<OpPredSplit>(b, b->split, it);
+    }, its);
+    if (s != CCNS_OK) return s;
+    for (int k = 0; k < n; ++k) {
+        info[k].pred = solve_info(b->hcg[k], true);
+        b->sims[k]->last_pred_it = b->hcg[k].it_final;
+    }
+    // corrector: the pressure solve, then the correction, the pressure
+    // update and the diagnostics
+    blaunch<OpPoisRhs>(b, b->dc, 0);
+    blaunch<OpPoisInit<false>>(b, b->dc, 0);
+    batch_vcycle<double>(b);
+    last = 0;
+    for (ccns_ctx *c : b->sims) last = std::max(last, c->last_pois_it);
+    s = batch_cg(b, std::max(2, last + 1), 2, GAT_POIS, [&](int it) {
+        blaunch<OpDirZ<double>>(b, b->dp, it);
+        blaunch<OpUpdate<double>>(b, b->upd, it);
+        batch_vcycle<double>(b);
+    }, its);
+    if (s != CCNS_OK) return s;
+    for (int k = 0; k < n; ++k) {
+        info[k].poisson = solve_info(b->hcg[k], false);
+        b->sims[k]->last_pois_it = b->hcg[k].it_final;
+        b->sims[k]->pbuf_pois = its & 1;
+    }
+    return batch_finish(b, info, st);
+}
+
+// Per-simulation record of a refinement loop (precision 1), as the solo
+// solves keep it.
+struct Refine {
+    double f2 = 0.0, r2 = 0.0;  // |f|^2 and |r|^2 of the FP64 residual
+    int inner_its = 0, sweeps = 0;
+    InnerRecord inner;
+    ccns_status status = CCNS_ENOTCONV;
+};
+
+// The inner solves of one sweep have ended: each active simulation's record
+// takes its inner solve's iterations and status; one that broke down before
+// its first update leaves the loop (its correction is zero), as in the solo
+// loop.  Returns whether any left, so that the flags go up again before the
+// correction.
+bool batch_note_inner(ccns_batch *b, std::vector<Refine> &rec, int o, bool pred) {
+    bool changed = false;
+    for (size_t k = 0; k < b->sims.size(); ++k) {
+        if (!b->act[k]) continue;
+        const CgState &h = b->hcg[k];
+        rec[k].inner_its += h.it_final;
+        ++rec[k].sweeps;
+        note_inner(rec[k].inner, h.status, o);
+        (pred ? b->sims[k]->last_pred_in : b->sims[k]->last_pois_in) = h.it_final;
+        if (h.status == CCNS_EBREAKDOWN && h.it_final == 0) {
+            rec[k].status = CCNS_EBREAKDOWN;
+            b->act[k] = 0;
+            changed = true;
+        }
+    }
+    return changed;
+}
+
+ccns_solve_info refine_info(const Refine &r) {
+    ccns_solve_info i{};
+    i.iterations = r.inner_its;
+    i.outer = r.sweeps;
+    i.rel_residual = r.f2 > 0.0 ? std::sqrt(r.r2 / r.f2) : 0.0;
+    i.status = r.status;
+    i.inner_status = r.inner.status;
+    i.inner_fail_sweep = r.inner.sweep;
+    return i;
+}
+
+// One projection step of every simulation in precision 1: the predictor and
+// the pressure solves are iterative refinements whose sweeps run in
+// lockstep.  Each sweep forms every active simulation's FP64 residual, reads
+// all of their statistics in one read-back, decides for each, as its solo
+// solve does, whether it has converged and to which tolerance its inner
+// float solve runs, then runs the inner solves in lockstep and adds the
+// corrections.  A simulation out of the sweep does nothing in its launches.
+ccns_status batch_fused_step_mixed(ccns_batch *b, std::vector<ccns_step_info> &info, std::vector<ccns_status> &st) {
+    const int n = (int)b->sims.size();
+    ccns_status s = batch_begin(b);
+    if (s != CCNS_OK) return s;
+    std::fill(b->act.begin(), b->act.end(), 1);
+    if ((s = batch_upload(b)) != CCNS_OK) return s;
+    batch_pred_rhs(b);
+    // predictor
+    std::vector<Refine> rec(n);
+    for (int o = 0;; ++o) {
+        blaunch<OpPredResid<true, false, false>>(b, b->pred[0], 0);
+        blaunch<OpPredResid<true, true, false>>(b, b->pred[1], 0);
+        blaunch<OpPredResid<true, false, true>>(b, b->pred[2], 0);
+        blaunch<OpPredResid<true, true, true>>(b, b->pred[3], 0);
+        blaunch<OpReduce>(b, b->one, RED_PRED_MIX);
+        if ((s = batch_read(b, GAT_PRED_RES)) != CCNS_OK) return s;
+        bool any = false;
+        int last = 0;
+        for (int k = 0; k < n; ++k) {
+            if (!b->act[k]) continue;
+            const double tol = b->sims[k]->prm.pred_tol;
+            rec[k].f2 = b->hst8[(size_t)k * 8 + 5];
+            rec[k].r2 = b->hst8[(size_t)k * 8 + 6];
+            const double f2 = rec[k].f2, r2 = rec[k].r2;
+            if (!(f2 > 0.0) || r2 <= tol * tol * f2) {
+                rec[k].status = CCNS_OK;
+                b->act[k] = 0;
+            } else if (o >= MAX_OUTER) {
+                b->act[k] = 0;
+            } else {
+                const double t = inner_tol(tol * std::sqrt(f2 / r2));
+                b->tol2[k] = t * t;
+                any = true;
+                last = std::max(last, b->sims[k]->last_pred_in);
+            }
+        }
+        if (!any) break;
+        if ((s = batch_upload(b)) != CCNS_OK) return s;
+        hipLaunchKernelGGL(k_batch_set_tol, dim3((n + NT - 1) / NT), dim3(NT), 0, b->stream, b->dsims, n, 0, b->dtol);
+        int its = 0;
+        s = batch_cg(b, std::max(4, last + 1), 8, GAT_PRED_IN, [&](int it) {
+            blaunch_w7<OpPredCg<float, false, false>>(b, b->pred[0], it);
+            blaunch_w7<OpPredCg<float, true, false>>(b, b->pred[1], it);
+            blaunch_w7<OpPredCg<float, false, true>>(b, b->pred[2], it);
+            blaunch_w7<OpPredCg<float, true, true>>(b, b->pred[3], it);
+            blaunch<OpPredSplit>(b, b->split, it);
+        }, its);
+        if (s != CCNS_OK) return s;
+        if (batch_note_inner(b, rec, o, true) && (s = batch_upload(b)) != CCNS_OK) return s;
+        blaunch<OpAddCorr>(b, b->fb2, 0);
+    }
+    for (int k = 0; k < n; ++k) {
+        info[k].pred = refine_info(rec[k]);
+        b->sims[k]->last_pred_it = rec[k].inner_its;
+    }
+    // corrector
+    std::fill(b->act.begin(), b->act.end(), 1);
+    if ((s = batch_upload(b)) != CCNS_OK) return s;
+    blaunch<OpPoisRhs>(b, b->dc, 0);
+    rec.assign(n, Refine{});
+    for (int o = 0;; ++o) {
+        blaunch<OpPoisInit<true>>(b, b->dc, o);
+        blaunch<OpReduce>(b, b->one, RED_POIS_MIX);
+        if ((s = batch_read(b, GAT_POIS_RES)) != CCNS_OK) return s;
+        bool any = false;
+        int last = 0;
+        for (int k = 0; k < n; ++k) {
+            if (!b->act[k]) continue;
+            const ccns_ctx *c = b->sims[k];
+            const ccns_params &p = c->prm;
+            const double sdiv = (p.tau / p.rho) / (p.u_ref * std::min(c->g.hx, c->g.hy));
+            const double *h = b->hst8 + (size_t)k * 8;
+            if (o == 0) rec[k].f2 = h[5];
+            rec[k].r2 = h[6];
+            const double bn2 = rec[k].f2, rn2 = rec[k].r2, rmax = h[7];
+            double need;
+            bool conv;
+            if (p.div_tol > 0.0) {
+                conv = sdiv * rmax <= 0.5 * p.div_tol;
+                need = rmax > 0.0 ? 0.5 * p.div_tol / (sdiv * rmax) : 1.0;
+            } else {
+                conv = rn2 <= p.pcg_tol * p.pcg_tol * bn2;
+                need = rn2 > 0.0 ? p.pcg_tol * std::sqrt(bn2 / rn2) : 1.0;
+            }
+            if (!(bn2 > 0.0) || c->n_active == 0) conv = true;
+            if (conv) {
+                rec[k].status = CCNS_OK;
+                b->act[k] = 0;
+            } else if (o >= MAX_OUTER) {
+                b->act[k] = 0;
+            } else {
+                const double t = inner_tol(need);
+                b->tol2[k] = t * t;
+                any = true;
+                last = std::max(last, c->last_pois_in);
+            }
+        }
+        if (!any) break;
+        if ((s = batch_upload(b)) != CCNS_OK) return s;
+        hipLaunchKernelGGL(k_batch_set_tol, dim3((n + NT - 1) / NT), dim3(NT), 0, b->stream, b->dsims, n, 1, b->dtol);
+        batch_vcycle<float>(b);
+        int its = 0;
+        s = batch_cg(b, std::max(2, last + 1), 2, GAT_POIS_IN, [&](int it) {
+            blaunch<OpDirZ<float>>(b, b->dp, it);
+            blaunch<OpUpdate<float>>(b, b->upd, it);
+            batch_vcycle<float>(b);
+        }, its);
+        if (s != CCNS_OK) return s;
+        if (batch_note_inner(b, rec, o, false) && (s = batch_upload(b)) != CCNS_OK) return s;
+        blaunch<OpAddCorr>(b, b->fb1, 1);
+    }
+    for (int k = 0; k < n; ++k) {
+        info[k].poisson = refine_info(rec[k]);
+        b->sims[k]->last_pois_it = rec[k].inner_its;
+    }
+    std::fill(b->act.begin(), b->act.end(), 1);
+    if ((s = batch_upload(b)) != CCNS_OK) return s;
+    return batch_finish(b, info, st);
+}
+
 void batch_free(ccns_batch *b) {
     if (!b) return;
     if (b->stream) (void)hipStreamSynchronize(b->stream);
@@ -4818,8 +5218,13 @@ void batch_free(ccns_batch *b) {
     if (b->dmap) (void)hipFree(b->dmap);
     if (b->dcg) (void)hipFree(b->dcg);
     if (b->ddg) (void)hipFree(b->ddg);
+    if (b->dst8) (void)hipFree(b->dst8);
+    if (b->dact) (void)hipFree(b->dact);
+    if (b->dtol) (void)hipFree(b->dtol);
     if (b->hcg) (void)hipHostFree(b->hcg);
     if (b->hdg) (void)hipHostFree(b->hdg);
+    if (b->hst8) (void)hipHostFree(b->hst8);
+    if (b->hring) (void)hipHostFree(b->hring);
     if (b->stream) (void)hipStreamDestroy(b->stream);
     delete b;
 }
@@ -4879,20 +5284,28 @@ ccns_status ccns_batch_create(int n, ccns_ctx *const *ctxs, int nthreads, ccns_b
 ccns_status ccns_batch_create_fused(int n, ccns_ctx *const *ctxs, ccns_batch **out) {
     if (!out) return CCNS_EINVAL;
     *out = nullptr;
-    if (n < 1 || n > BATCH_MAX_SIMS || !ctxs) return CCNS_EINVAL;
+    if (n < 1 || n > BATCH_MAX_SIMS || !ctxs || !ctxs[0]) return CCNS_EINVAL;
+    const int prec = ctxs[0]->prm.precision;
     for (int k = 0; k < n; ++k)
-        if (!ctxs[k] || ctxs[k]->prm.precision != 0 || ctxs[k]->prm.precond != 1) return CCNS_EINVAL;
+        if (!ctxs[k] || ctxs[k]->prm.precision != prec || ctxs[k]->prm.precond != 1) return CCNS_EINVAL;
     ccns_batch *b = nullptr;
     ccns_status s = ccns_batch_create(n, ctxs, 1, &b);
     if (s != CCNS_OK) return s;
     b->fused = true;
+    b->prec = prec;
     s = CCNS_ENOMEM;
     if (hipStreamCreate(&b->stream) == hipSuccess && hipMalloc(&b->dsims, n * sizeof(BatchSim)) == hipSuccess &&
         hipMalloc(&b->dcg, n * sizeof(CgState)) == hipSuccess &&
         hipMalloc(&b->ddg, n * sizeof(DiagState)) == hipSuccess &&
+        hipMalloc(&b->dst8, (size_t)n * 8 * sizeof(double)) == hipSuccess &&
+        hipMalloc(&b->dact, n * sizeof(int)) == hipSuccess && hipMalloc(&b->dtol, n * sizeof(double)) == hipSuccess &&
         hipHostMalloc(&b->hcg, n * sizeof(CgState)) == hipSuccess &&
-        hipHostMalloc(&b->hdg, n * sizeof(DiagState)) == hipSuccess) {
+        hipHostMalloc(&b->hdg, n * sizeof(DiagState)) == hipSuccess &&
+        hipHostMalloc(&b->hst8, (size_t)n * 8 * sizeof(double)) == hipSuccess &&
+        hipHostMalloc(&b->hring, BATCH_RING * ring_slot_bytes(n)) == hipSuccess) {
         try {
+            b->act.assign(n, 1);
+            b->tol2.assign(n, 0.0);
             s = batch_build(b);
         } catch (...) {
             s = CCNS_ENOMEM;
@@ -4920,7 +5333,8 @@ ccns_status ccns_batch_step(ccns_batch *b, int nsteps, ccns_step_info *per_sim, 
     if (b->fused) {
         ccns_status e = CCNS_OK;
         try {
-            for (int k = 0; k < nsteps && e == CCNS_OK; ++k) e = batch_fused_step(b, info, st);
+            for (int k = 0; k < nsteps && e == CCNS_OK; ++k)
+                e = b->prec == 1 ? batch_fused_step_mixed(b, info, st) : batch_fused_step(b, info, st);
         } catch (...) {
             e = CCNS_ENOMEM;
         }

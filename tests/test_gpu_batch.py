@@ -148,7 +148,7 @@ def _fused_cases():
     ]
 
 
-def _context_fp64(case, stream, extra):
+def _context_mg(case, stream, extra):
     from paper_2211_10698_amd import ccns
     g = case.grid
     key = (case.name, g.nx, g.ny)
@@ -170,23 +170,25 @@ def _context_fp64(case, stream, extra):
     return ctx
 
 
-def test_fused_batch_matches_solo_runs_bit_for_bit():
+@pytest.mark.parametrize("precision", [0, 1])
+def test_fused_batch_matches_solo_runs_bit_for_bit(precision):
     """Three steps of the fused batch give each simulation's solo fields and
-    step figures bit for bit; so do two fused steps followed by a solo step
-    on each context (the contexts carry on from a fused step as from their
-    own)."""
+    step figures bit for bit, in FP64 and in precision 1 (FP32 inner solves
+    with FP64 refinement, whose sweeps run in lockstep); so do two fused
+    steps followed by a solo step on each context (the contexts carry on
+    from a fused step as from their own)."""
     from paper_2211_10698_amd import ccns
-    cases = _fused_cases()
+    cases = [(name, case, dict(extra, precision=precision, div_tol=1e-8)) for name, case, extra in _fused_cases()]
     nsteps = 3
     solo = []
     for name, case, extra in cases:
-        print(f"[fused] solo {name}", flush=True)
-        ctx = _context_fp64(case, torch.cuda.current_stream(), extra)
+        print(f"[fused] solo {name} precision {precision}", flush=True)
+        ctx = _context_mg(case, torch.cuda.current_stream(), extra)
         infos = [ctx.step(1) for _ in range(nsteps)]
         solo.append((_state(ctx), infos[-1].as_dict()))
         ctx.close()
     for split in (False, True):
-        ctxs = [_context_fp64(case, torch.cuda.Stream(), extra) for _, case, extra in cases]
+        ctxs = [_context_mg(case, torch.cuda.Stream(), extra) for _, case, extra in cases]
         torch.cuda.synchronize()
         batch = ccns.Batch(ctxs, fused=True)
         print(f"[fused] batch steps (then a solo step: {split})", flush=True)
@@ -208,13 +210,14 @@ def test_fused_batch_matches_solo_runs_bit_for_bit():
 
 
 def test_fused_batch_refuses_other_solvers():
-    """The fused batch runs precision 0 with the multigrid preconditioner:
-    a context of precision 1 or with the Jacobi preconditioner is refused."""
+    """The fused batch runs the multigrid preconditioner with one precision
+    for all of its simulations: a context with the Jacobi preconditioner, or
+    of another precision than the others, is refused."""
     from paper_2211_10698_amd import ccns
     case = W.cylinder_64()
-    good = _context_fp64(case, torch.cuda.current_stream(), {})
+    good = _context_mg(case, torch.cuda.current_stream(), {})
     for extra in ({"precision": 1}, {"precond": ccns.PRECOND_JACOBI}):
-        other = _context_fp64(case, torch.cuda.current_stream(), extra)
+        other = _context_mg(case, torch.cuda.current_stream(), extra)
         with pytest.raises(ccns.CcnsError):
             ccns.Batch([good, other], fused=True)
         other.close()
