@@ -75,7 +75,7 @@ WORKLOADS = {
 
 # Device helpers whose text a kernel's counter readings also depend on.
 KERNEL_DEPS = {
-    "k_pred_cg": ["ViscCoefT", "PredCoefT", "PredTileNx", "pred_tile_strains", "pred_tile_K",
+    "k_pred_cg": ["pred_cg_body", "pred_rows", "ViscCoefT", "PredCoefT", "PredTileNx", "pred_tile_strains", "pred_tile_K",
                   "pred_tile_K_row", "pred_node_strain_row", "strain_cell", "strain_node", "strain_face"],
 }
 

@@ -1578,16 +1578,26 @@ __global__ __launch_bounds__(NT) void k_pois_dir_z(Dims d, PoisCoefT<T> pc, cons
 // ---------------------------------------------------------------------------
 
 // Predictor kernels work on tiles of 64 x 8 faces of both velocity
-// components per work-group, staged in LDS with a one-face halo.
+// components per work-group, staged in LDS with a one-face halo.  The float
+// CG of the inner solves of precision 1 takes tiles of 64 x 16 faces: its
+// launch waits on the same chain of dependent loads per tile as the FP64
+// one for half the bytes per face, so taller tiles put more of them in
+// flight per chain.
 constexpr int HTY = 8;
-
-// LDS of a predictor tile: the staged face field on the tile and a one-face
-// halo, and its node strains (eq:offdiag).  The cell strains (eq:diag) are
-// formed where a face needs them, which keeps the tile at 20 KB in FP64.
+constexpr int HTY_F32 = 16;
 template <class T>
+__device__ __host__ constexpr int pred_rows() {
+    return std::is_same<T, double>::value ? HTY : HTY_F32;
+}
+
+// LDS of a predictor tile of TH rows: the staged face field on the tile and
+// a one-face halo, and its node strains (eq:offdiag).  The cell strains
+// (eq:diag) are formed where a face needs them, which keeps the tile at
+// 20 KB in FP64.
+template <class T, int TH = HTY>
 struct PredTileNx {
-    T spx[HTY + 2][TX + 2], spy[HTY + 2][TX + 2];
-    T snx[HTY + 1][TX + 1], sny[HTY + 1][TX + 1];
+    T spx[TH + 2][TX + 2], spy[TH + 2][TX + 2];
+    T snx[TH + 1][TX + 1], sny[TH + 1][TX + 1];
 };
 
 // The strains of the staged field (rows r0-1 .. r0+HTY, cols c0-1 .. c0+TX
@@ -1621,10 +1631,11 @@ __device__ inline T strain_face(T baa, T sp, T sm, T bab, T np, T nm) {
 }
 
 // Node strains of the tile (eq:offdiag) from the coefficient arrays: nodes
-// (r0 - 1 .. r0 + HTY - 1) x (c0 - 1 .. c0 + TX - 1).
-template <class T, bool GEO>
-__device__ inline void pred_tile_strains(PredTileNx<T> &s, const ViscCoefT<T> &c, int P, int rows, int c0, int r0) {
-    for (int e = threadIdx.x; e < (HTY + 1) * (TX + 1); e += NT) {
+// (r0 - 1 .. r0 + TH - 1) x (c0 - 1 .. c0 + TX - 1).
+template <class T, bool GEO, int TH>
+__device__ inline void pred_tile_strains(PredTileNx<T, TH> &s, const ViscCoefT<T> &c, int P, int rows, int c0,
+                                         int r0) {
+    for (int e = threadIdx.x; e < (TH + 1) * (TX + 1); e += NT) {
         const int ly = e / (TX + 1), lx = e - ly * (TX + 1);
         const int j = r0 - 1 + ly, i = c0 - 1 + lx;
         const bool in = (j >= 0) && (j + 1 < rows) && (i >= 0) && (i + 1 < P);
@@ -1649,8 +1660,8 @@ __device__ inline void pred_tile_strains(PredTileNx<T> &s, const ViscCoefT<T> &c
 // K v = visc(strain(v, 0)) (Sec. 4.3) at tile entry (ly, tx), index k: the two
 // cell strains S_xx of the x-face and S_yy of the y-face are formed here
 // (eq:diag), the node strains come from the tile.
-template <class T>
-__device__ inline void pred_tile_K(const PredTileNx<T> &s, const ViscCoefT<T> &c, size_t k, int ly, int tx, int i,
+template <class T, int TH = HTY>
+__device__ inline void pred_tile_K(const PredTileNx<T, TH> &s, const ViscCoefT<T> &c, size_t k, int ly, int tx, int i,
                                    int P, int rows, T &kx, T &ky) {
     const T bxx = c.bxx[k], bxy = c.bxy[k], byy = c.byy[k], byx = c.byx[k];
     const bool in0 = i >= 1, in1 = i + 1 < P;
@@ -1673,8 +1684,8 @@ __device__ inline void pred_tile_K(const PredTileNx<T> &s, const ViscCoefT<T> &c
 
 // Node strain at tile node (ly, lx) (node (r0 - 1 + ly, c0 - 1 + lx)) from the
 // node's row of the class table: the operations of pred_tile_strains.
-template <class T, bool GEO>
-__device__ inline void pred_node_strain_row(PredTileNx<T> &s, const T *row, int ly, int lx, bool in) {
+template <class T, bool GEO, int TH = HTY>
+__device__ inline void pred_node_strain_row(PredTileNx<T, TH> &s, const T *row, int ly, int lx, bool in) {
     const T bxn = row[PR_BXY_N], bxs = row[PR_BXY], bye = row[PR_BYX_E], byw = row[PR_BYX];
     const T a = row[PR_NXX], dd = row[PR_NYY];
     T b, cc;
@@ -1693,8 +1704,8 @@ __device__ inline void pred_node_strain_row(PredTileNx<T> &s, const T *row, int 
 
 // The same with the values from the entry's row of the class table (where a
 // neighbour is outside the grid the strain is 0, as above).
-template <class T>
-__device__ inline void pred_tile_K_row(const PredTileNx<T> &s, const T *row, size_t k, int ly, int tx, int i, int P,
+template <class T, int TH = HTY>
+__device__ inline void pred_tile_K_row(const PredTileNx<T, TH> &s, const T *row, size_t k, int ly, int tx, int i, int P,
                                        int rows, T &kx, T &ky) {
     const T bxx = row[PR_BXX], bxy = row[PR_BXY], byy = row[PR_BYY], byx = row[PR_BYX];
     const bool in0 = i >= 1, in1 = i + 1 < P;
@@ -1733,13 +1744,15 @@ __device__ inline void pred_tile_K_row(const PredTileNx<T> &s, const T *row, siz
 // after the one that stopped return at once (stop_it).  The tile keeps no
 // cell strains (20 KB of LDS in FP64) and the register budget is set for
 // seven waves per SIMD (70 VGPRs, no spills): the launch is bound by HBM
-// latency, and more resident waves hide more of it.  With CLS the
-// coefficients come from the class table (pc.cls, pc.tab).
+// latency, and more resident waves hide more of it.  Tiles are 64 x 8 faces
+// in FP64 and 64 x 16 in float (pred_rows).  With CLS the coefficients come
+// from the class table (pc.cls, pc.tab).
 template <class T, bool GEO, bool CLS, class G>
 __device__ __forceinline__ void pred_cg_body(const G &g, 
     int P, int rows, int gx, int gy, size_t n, PredCoefT<T> pc, CgState *st, int it, T *__restrict__ x,
     const T *__restrict__ rin, T *__restrict__ rout, const T *__restrict__ pold, T *__restrict__ pnew,
     const T *__restrict__ qin, T *__restrict__ qout, const double *tin, int nin, double *part) {
+    constexpr int TH = pred_rows<T>();  // tile rows
     if (st->stop_it < it) return;
     double fn2, rr, alpha = 0.0, beta = 0.0;
     bool breakdown = false;
@@ -1775,13 +1788,13 @@ __device__ __forceinline__ void pred_cg_body(const G &g,
     }
     const int L = logical_group(g, ((g.n() + 7) / 8) * 8);
     const bool live = L < gx * gy;
-    const int c0 = (L % gx) * TX, r0 = (L / gx) * HTY;
+    const int c0 = (L % gx) * TX, r0 = (L / gx) * TH;
     const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
     const T a = (T)alpha, b = (T)beta;
     if (stop) {
         // the last update, x += alpha p_old, on the tile
         if (live && it >= 1 && !breakdown) {
-            for (int ly = ty; ly < HTY; ly += 4) {
+            for (int ly = ty; ly < TH; ly += 4) {
                 const int j = r0 + ly, i = c0 + tx;
                 if (j >= rows) break;
                 const size_t k = (size_t)j * P + i;
@@ -1792,11 +1805,11 @@ __device__ __forceinline__ void pred_cg_body(const G &g,
         }
         return;
     }
-    __shared__ PredTileNx<T> s;
+    __shared__ PredTileNx<T, TH> s;
     double v[7] = {0, 0, 0, 0, 0, 0, 0};
     // r' and M^-1 of this thread's tile faces stay in registers for the
-    // products of the last phase (rows ty and ty + 4 of the tile)
-    constexpr int RW = HTY / 4;
+    // products of the last phase (rows ty, ty + 4, ... of the tile)
+    constexpr int RW = TH / 4;
     T rxs[RW], rys[RW], hxs[RW], hys[RW];
     int cl[RW];
     // the Jacobi diagonal at entry k
@@ -1841,12 +1854,12 @@ __device__ __forceinline__ void pred_cg_body(const G &g,
             s.spx[ly + 1][tx + 1] = in ? px : (T)0;
             s.spy[ly + 1][tx + 1] = in ? py : (T)0;
         }
-        // the one-face halo: rows r0-1 and r0+HTY (TX+2 faces each), columns
-        // c0-1 and c0+TX (HTY faces each)
-        for (int e = threadIdx.x; e < 2 * (TX + 2) + 2 * HTY; e += NT) {
+        // the one-face halo: rows r0-1 and r0+TH (TX+2 faces each), columns
+        // c0-1 and c0+TX (TH faces each)
+        for (int e = threadIdx.x; e < 2 * (TX + 2) + 2 * TH; e += NT) {
             int ly, lx;
             if (e < 2 * (TX + 2)) {
-                ly = e < TX + 2 ? 0 : HTY + 1;
+                ly = e < TX + 2 ? 0 : TH + 1;
                 lx = e < TX + 2 ? e : e - (TX + 2);
             } else {
                 const int f = e - 2 * (TX + 2);
@@ -1885,7 +1898,7 @@ __device__ __forceinline__ void pred_cg_body(const G &g,
                 pred_node_strain_row<T, GEO>(s, pc.tab + (size_t)cl[m] * PCW, ly + 1, tx + 1,
                                              (j + 1 < rows) && (i + 1 < P));
             }
-            for (int e = threadIdx.x; e < TX + 1 + HTY; e += NT) {
+            for (int e = threadIdx.x; e < TX + 1 + TH; e += NT) {
                 const int ly = e <= TX ? 0 : e - TX, lx = e <= TX ? e : 0;
                 const int j = r0 - 1 + ly, i = c0 - 1 + lx;
                 const bool in = (j >= 0) && (j + 1 < rows) && (i >= 0) && (i + 1 < P);
@@ -3559,7 +3572,7 @@ ccns_status pred_cg(ccns_ctx *c, PredCoefT<T> pc, CgState *st, T *x, T *const r[
                     T *const q[2], int &last_it, ccns_solve_info *info) {
     c->init_nblk = 1;
     const Layout &L = c->w.L;
-    const int gx = L.pitch / TX, gy = (L.rows + HTY - 1) / HTY;
+    const int gx = L.pitch / TX, gy = (L.rows + pred_rows<T>() - 1) / pred_rows<T>();
     const int nb = ((gx * gy + 7) / 8) * 8;
     const bool geo = c->prm.visc_form == 0;
     auto kern = pc.cls ? (geo ? k_pred_cg<T, true, true> : k_pred_cg<T, false, true>)
@@ -4216,6 +4229,7 @@ struct BatchCycle {
 struct BatchSim {
     const int *active;           // precision 1: 1 while the simulation takes part in the sweep
     int P, rows, pgx, pgy, pnb;  // layout; predictor tiles and work-groups
+    int pgy32, pnb32;            // the same for the float predictor CG's taller tiles
     size_t n;
     PredCoefT<double> pd;
     PredCoefT<float> pf;         // precision 1: the inner predictor solve's coefficients
@@ -4311,7 +4325,9 @@ struct OpPredResid {
 template <class T, bool GEO, bool CLS>
 struct OpPredCg {
     static constexpr int BT = NT;
-    __device__ static int groups(const BatchSim &s, int) { return s.pnb; }
+    __device__ static int groups(const BatchSim &s, int) {
+        return std::is_same<T, double>::value ? s.pnb : s.pnb32;
+    }
     __device__ static void run(const SubGrid &g, const BatchSim &s, int it) {
         const int b = it & 1;
         const double *tin = it == 0 ? s.part[PB_INIT] : s.part[PB_UPD];
@@ -4325,17 +4341,19 @@ struct OpPredCg {
         } else {
             float *r[2] = {s.f[G_PRX], s.f[G_PR1X]}, *p[2] = {s.f[G_PP0X], s.f[G_PP1X]},
                   *q[2] = {s.f[G_PQX], s.f[G_PQ1X]};
-            pred_cg_body<float, GEO, CLS>(g, s.P, s.rows, s.pgx, s.pgy, s.n, s.pf, s.st_pred_in, it, s.f[G_PXX],
+            pred_cg_body<float, GEO, CLS>(g, s.P, s.rows, s.pgx, s.pgy32, s.n, s.pf, s.st_pred_in, it, s.f[G_PXX],
                                           it == 0 ? r[0] : r[b ^ 1], r[b], p[b ^ 1], p[b], q[b ^ 1], q[b], tin,
                                           nin, s.part[PB_DIR]);
         }
     }
 };
+template <class T>
 struct OpPredSplit {
     static constexpr int BT = NT;
     __device__ static int groups(const BatchSim &, int) { return PRED_RED; }
     __device__ static void run(const SubGrid &g, const BatchSim &s, int) {
-        reduce_partials_split_body<7>(g, s.part[PB_DIR], s.pnb, s.part[PB_UPD]);
+        reduce_partials_split_body<7>(g, s.part[PB_DIR], std::is_same<T, double>::value ? s.pnb : s.pnb32,
+                                      s.part[PB_UPD]);
     }
 };
 // One-group reductions.
@@ -4594,7 +4612,7 @@ struct ccns_batch {
     std::vector<unsigned char> forms;  // the cycle forms the tables were built for
     size_t map_cap = 0;
     int maxcyc = 0, tail_lds = 0;
-    BatchTable pred[4], one, split, dc, dp, upd, fb1, fb2;
+    BatchTable pred[4], pred32[4], one, split, dc, dp, upd, fb1, fb2;
     BatchTable down[BATCH_LEVELS][6], up[BATCH_LEVELS][6], bot[3];
 };
 
@@ -4678,6 +4696,8 @@ BatchSim batch_sim(ccns_batch *b, int k) {
     s.pgx = (int)(L.pitch / TX);
     s.pgy = (int)((L.rows + HTY - 1) / HTY);
     s.pnb = ((s.pgx * s.pgy + 7) / 8) * 8;
+    s.pgy32 = (int)((L.rows + HTY_F32 - 1) / HTY_F32);
+    s.pnb32 = ((s.pgx * s.pgy32 + 7) / 8) * 8;
     s.n = L.n;
     s.pd = pred_coef_t(c);
     if (c->ncls) {
@@ -4791,8 +4811,11 @@ ccns_status batch_build(ccns_batch *b) {
     };
     const auto &S = b->hsims;
     auto all = [](int) { return true; };
-    for (int v = 0; v < 4; ++v)
+    for (int v = 0; v < 4; ++v) {
         b->pred[v] = table([&](int k) { return pred_variant(b->sims[k]) == v; }, [&](int k) { return S[k].pnb; });
+        b->pred32[v] = table([&](int k) { return b->prec == 1 && pred_variant(b->sims[k]) == v; },
+                             [&](int k) { return S[k].pnb32; });
+    }
     b->one = table(all, [](int) { return 1; });
     b->split = table(all, [](int) { return PRED_RED; });
     b->dc = table(all, [&](int k) { return S[k].dc.nblk; });
@@ -5013,7 +5036,7 @@ ccns_status batch_fused_step(ccns_batch *b, std::vector<ccns_step_info> &info, s
         blaunch_w7<OpPredCg<double, true, false>>(b, b->pred[1], it);
         blaunch_w7<OpPredCg<double, false, true>>(b, b->pred[2], it);
         blaunch_w7<OpPredCg<double, true, true>>(b, b->pred[3], it);
-        blaunch<OpPredSplit>(b, b->split, it);
+        blaunch<OpPredSplit<double>>(b, b->split, it);
     }, its);
     if (s != CCNS_OK) return s;
     for (int k = 0; k < n; ++k) {
@@ -5132,11 +5155,11 @@ ccns_status batch_fused_step_mixed(ccns_batch *b, std::vector<ccns_step_info> &i
         hipLaunchKernelGGL(k_batch_set_tol, dim3((n + NT - 1) / NT), dim3(NT), 0, b->stream, b->dsims, n, 0, b->dtol);
         int its = 0;
         s = batch_cg(b, std::max(4, last + 1), 8, GAT_PRED_IN, [&](int it) {
-            blaunch_w7<OpPredCg<float, false, false>>(b, b->pred[0], it);
-            blaunch_w7<OpPredCg<float, true, false>>(b, b->pred[1], it);
-            blaunch_w7<OpPredCg<float, false, true>>(b, b->pred[2], it);
-            blaunch_w7<OpPredCg<float, true, true>>(b, b->pred[3], it);
-            blaunch<OpPredSplit>(b, b->split, it);
+            blaunch_w7<OpPredCg<float, false, false>>(b, b->pred32[0], it);
+            blaunch_w7<OpPredCg<float, true, false>>(b, b->pred32[1], it);
+            blaunch_w7<OpPredCg<float, false, true>>(b, b->pred32[2], it);
+            blaunch_w7<OpPredCg<float, true, true>>(b, b->pred32[3], it);
+            blaunch<OpPredSplit<float>>(b, b->split, it);
         }, its);
         if (s != CCNS_OK) return s;
         if (batch_note_inner(b, rec, o, true) && (s = batch_upload(b)) != CCNS_OK) return s;
