@@ -14,7 +14,12 @@ with an arrival time.  The server
   * runs every prepared simulation on a step worker of its own (continuous
     batching without rounds: a simulation joins the GPU as soon as it is
     prepared, shares it with the others, each on its own stream, and leaves
-    as soon as its last step is done, releasing its budget).
+    as soon as its last step is done, releasing its budget); or, with
+    rounds=True, batches the time steps of every prepared simulation: each
+    round advances all of them by one step in a fused batch (one launch per
+    phase over all of their work-groups), a simulation prepared during a
+    round joins at the next one, and one whose last step is done leaves,
+    releasing its budget.
 
 Latency = completion - arrival, split into queue time (arrival to admission)
 and service time (admission to completion, which includes preparation).
@@ -116,8 +121,10 @@ class Server:
 
     def __init__(self, hbm_budget: Optional[int] = None, precision: int = 1, threads: int = 16,
                  prep_workers: int = 4, keep_fields: bool = False, inputs=None, device_caps: bool = True,
-                 forces: bool = False):
+                 forces: bool = False, rounds: bool = False):
         self.budget = hbm_budget if hbm_budget is not None else default_budget()
+        # rounds: every running simulation steps in one fused batch per round
+        self.rounds = rounds
         self.precision = precision
         self.threads = threads
         self.prep_workers = prep_workers
@@ -179,15 +186,26 @@ class Server:
         for n in range(steps):
             info = ctx.step(1, check=False)
             div = max(div, info.div_rel)
-            for name, si in (("predictor", info.pred), ("pressure", info.poisson)):
-                if si.status != ccns.OK and status == ccns.OK:
-                    status = si.status
-                    note = (f"step {n}: {name} solve status {si.status} after {si.iterations} iterations, "
-                            f"{si.outer} sweeps, relative residual {si.rel_residual:.2e}, inner status "
-                            f"{si.inner_status} (first at sweep {si.inner_fail_sweep})")
+            status, note = Server._check(info, n, status, note)
             if status != ccns.OK:
                 break
         end = clock()
+        return start, end, div, status, note, Server._coefficients(ctx, case, forces)
+
+    @staticmethod
+    def _check(info, n, status, note):
+        """The first failed solve of step n (status and note), if any."""
+        for name, si in (("predictor", info.pred), ("pressure", info.poisson)):
+            if si.status != ccns.OK and status == ccns.OK:
+                status = si.status
+                note = (f"step {n}: {name} solve status {si.status} after {si.iterations} iterations, "
+                        f"{si.outer} sweeps, relative residual {si.rel_residual:.2e}, inner status "
+                        f"{si.inner_status} (first at sweep {si.inner_fail_sweep})")
+        return status, note
+
+    @staticmethod
+    def _coefficients(ctx, case, forces):
+        """(C_d, C_l) of the final state when asked for, else NaNs."""
         coef = (float("nan"), float("nan"))
         if forces and case.bodies:
             try:
@@ -196,7 +214,7 @@ class Server:
                 coef = ((F[0] + F[2]) / q, (F[1] + F[3]) / q)
             except ccns.CcnsError:
                 pass
-        return start, end, div, status, note, coef
+        return coef
 
     def run(self, requests: Sequence, log=None) -> List[Record]:
         """Serves the requests (objects with .case and .arrival, arrival in
@@ -205,7 +223,9 @@ class Server:
         Every running simulation is driven by a step worker of its own (at
         most `threads` at a time), so a simulation joins the GPU as soon as it
         is prepared and leaves as soon as its last step is done: no
-        simulation waits for another's step."""
+        simulation waits for another's step.  With rounds=True this thread
+        steps all running simulations together, one fused batch step per
+        round, while the preparation workers keep preparing."""
         order = sorted(range(len(requests)), key=lambda k: requests[k].arrival)
         recs = []
         for k in order:
@@ -222,6 +242,8 @@ class Server:
         nxt = 0
         preparing = {}       # host-preparation future -> record
         running = {}         # step future -> (record, context)
+        members = []         # rounds: [record, context, steps done] of every running simulation
+        batch, batch_key = None, None
         done = 0
         t0 = time.perf_counter()
         clock = lambda: time.perf_counter() - t0  # noqa: E731
@@ -239,16 +261,47 @@ class Server:
                     self.max_used = max(self.max_used, self.budget - free)
                     r.admit = clock()
                     preparing[prep_pool.submit(self._prepare, cases[r.index])] = r
+                finished = []
                 for fut in [f for f in preparing if f.done()]:
                     r = preparing.pop(fut)
                     ctx, stream, info, r.caps_s = fut.result()
                     r.prepared = clock()
                     r.div_rel_max = info.div_rel
-                    running[step_pool.submit(self._run_steps, ctx, cases[r.index], clock, self.forces)] = (r, ctx)
+                    if self.rounds:
+                        r.start = r.prepared
+                        members.append([r, ctx, 0])
+                    else:
+                        running[step_pool.submit(self._run_steps, ctx, cases[r.index], clock, self.forces)] = (r, ctx)
                 for fut in [f for f in running if f.done()]:
                     r, ctx = running.pop(fut)
                     r.start, r.completion, div, r.status, r.note, (r.cd, r.cl) = fut.result()
                     r.div_rel_max = max(r.div_rel_max, div)
+                    finished.append((r, ctx))
+                if self.rounds and members:
+                    # one round: every running simulation advances one step
+                    key = tuple(id(m[1]) for m in members)
+                    if batch is None or key != batch_key:
+                        if batch is not None:
+                            batch.close()
+                        batch, batch_key = ccns.Batch([m[1] for m in members], fused=True), key
+                    _, infos, _ = batch.step(1, check=False)
+                    stay = []
+                    for m, info in zip(members, infos):
+                        r, ctx, n = m
+                        r.div_rel_max = max(r.div_rel_max, info.div_rel)
+                        r.status, r.note = self._check(info, n, r.status, r.note)
+                        m[2] = n + 1
+                        if m[2] >= cases[r.index].steps or r.status != ccns.OK:
+                            r.completion = clock()
+                            r.cd, r.cl = self._coefficients(ctx, cases[r.index], self.forces)
+                            finished.append((r, ctx))
+                        else:
+                            stay.append(m)
+                    if len(stay) != len(members):
+                        batch.close()
+                        batch, batch_key = None, None
+                    members = stay
+                for r, ctx in finished:
                     if self.keep_fields:
                         r.fields = {n: ctx.get_field(f).cpu().numpy()
                                     for n, f in (("ux", ccns.F_UX), ("uy", ccns.F_UY), ("p", ccns.F_P))}
@@ -258,6 +311,8 @@ class Server:
                     if log:
                         log(f"[serve] {r.name} done: latency {r.latency:.2f}s "
                             f"(queue {r.queue:.2f}s, service {r.service:.2f}s){' ' + r.note if r.note else ''}")
+                if self.rounds and members:
+                    continue
                 waits = list(preparing) + list(running)
                 timeout = 0.005
                 if nxt < len(recs):
@@ -267,6 +322,8 @@ class Server:
                 else:
                     time.sleep(timeout)
         finally:
+            if batch is not None:
+                batch.close()
             step_pool.shutdown(wait=True)
             prep_pool.shutdown(wait=True)
         return sorted(recs, key=lambda r: r.index)

@@ -16,10 +16,15 @@ def _requests(n=6, steps=4):
     return trace
 
 
-def test_served_alone_equals_served_in_mix():
+@pytest.mark.parametrize("rounds", [False, True])
+def test_served_alone_equals_served_in_mix(rounds):
+    """Each request's fields are the same, bit for bit, served alone (one
+    simulation stepping on its own) as served in the mix: with a step worker
+    per simulation, and with the time steps of all running simulations
+    batched in fused rounds."""
     from paper_2211_10698_amd import serve
     reqs = _requests()
-    srv = serve.Server(hbm_budget=8 << 30, precision=1, threads=4, prep_workers=3, keep_fields=True)
+    srv = serve.Server(hbm_budget=8 << 30, precision=1, threads=4, prep_workers=3, keep_fields=True, rounds=rounds)
     mix = srv.run(reqs)
     assert all(r.status == 0 for r in mix)
     assert all(r.div_rel_max <= 1e-8 for r in mix)
@@ -31,10 +36,11 @@ def test_served_alone_equals_served_in_mix():
             assert np.array_equal(alone.fields[name], mix[k].fields[name]), (k, name)
 
 
-def test_admission_respects_budget_and_queues():
+@pytest.mark.parametrize("rounds", [False, True])
+def test_admission_respects_budget_and_queues(rounds):
     from paper_2211_10698_amd import serve
     reqs = _requests(n=8, steps=3)
-    srv = serve.Server(precision=0, threads=4, prep_workers=2)
+    srv = serve.Server(precision=0, threads=4, prep_workers=2, rounds=rounds)
     sizes = [serve.footprint(r.case, srv._params(r.case)) for r in reqs]
     srv.budget = 2 * max(sizes)          # at most a couple of simulations at a time
     recs = srv.run(reqs)
