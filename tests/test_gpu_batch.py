@@ -88,12 +88,14 @@ def test_batch_matches_solo_runs_bit_for_bit():
         c.close()
 
 
+@pytest.mark.parametrize("fused", [False, True])
 @pytest.mark.parametrize("theta", [0.0, 0.05])
 @pytest.mark.parametrize("name", ["cylinder_64", "flat_top_64"])
-def test_batch_member_matches_oracle(name, theta):
+def test_batch_member_matches_oracle(name, theta, fused):
     """A 64x64 case inside a batch against the oracle (10 steps at tight
     tolerances, as the solo trajectory test), at the paper's mass matrix
-    (theta = 0) and with the small-volume floor."""
+    (theta = 0) and with the small-volume floor; in a batch of streams and
+    in a fused batch."""
     from paper_2211_10698_amd import ccns
     from oracle import derived
     case = W.cylinder_64() if name == "cylinder_64" else W.flat_top_cylinder(64)
@@ -113,7 +115,7 @@ def test_batch_member_matches_oracle(name, theta):
         c.set_field(ccns.F_UY, s0.Uy)
         c.project()
     st.project(s0)
-    batch = ccns.Batch(ctxs, nthreads=3)
+    batch = ccns.Batch(ctxs, nthreads=3, fused=fused)
     for _ in range(case.steps):
         st.step(s0)
     status, infos, _ = batch.step(case.steps)
