@@ -323,7 +323,7 @@ def run_batched(args):
     cells = sum(c.grid.nx * c.grid.ny for c in cases)
     print(f"[bench] setup {time.perf_counter() - t_setup:.1f}s: {len(cases)} simulations, {cells} cells",
           file=sys.stderr, flush=True)
-    batch = ccns.Batch(ctxs, nthreads=16, fused=mode == "fused")
+    batch = ccns.Batch(ctxs, nthreads=16, fused=mode == "fused", graphs=args.batch_graphs == "on")
     failures = []
 
     def record(tag, st, infos, sts):
@@ -371,7 +371,8 @@ def run_batched(args):
                    "sizes": {str(k): v for k, v in sorted(sizes.items())}, "precond": "multigrid",
                    "precision": "fp32 inner + fp64 refinement, div_rel <= 1e-8" if prec else "fp64",
                    "batch_mode": ("fused: one launch per phase over all simulations' work-groups" if mode == "fused"
-                                  else "streams: 16 host threads, one stream per simulation")},
+                                  else "streams: 16 host threads, one stream per simulation"),
+                   "cg_iterations_as_graphs": mode == "fused" and args.batch_graphs == "on"},
         "div_rel_max": max(divs),
         "cg_iters_per_step_mean": float(np.mean(cg)),
         "pred_iters_per_step_mean": float(np.mean(pred)),
@@ -466,6 +467,8 @@ def main():
     ap.add_argument("--batch-mode", default="fused", choices=["fused", "streams"],
                     help="batched_cylinders_256: one launch per phase over all simulations (fused) "
                          "or 16 host threads with a stream per simulation")
+    ap.add_argument("--batch-graphs", default="on", choices=["on", "off"],
+                    help="batched_cylinders_256, fused: replay each CG iteration from a captured HIP graph")
     ap.add_argument("--coef-tables", default="auto", choices=["auto", "off"],
                     help="auto: the predictor CG reads its coefficients through the class table when it "
                          "fits (the library's default); off: from the coefficient arrays")

@@ -457,6 +457,15 @@ int ccns_mg_levels(const ccns_ctx *ctx, int *nx, int *ny, int *forms, int cap);
 typedef struct ccns_batch ccns_batch;
 ccns_status ccns_batch_create(int n, ccns_ctx *const *ctxs, int nthreads, ccns_batch **out);
 ccns_status ccns_batch_create_fused(int n, ccns_ctx *const *ctxs, ccns_batch **out);
+
+/* Fused batches: each conjugate-gradient iteration of all simulations (its
+ * launches of every kernel variant, the multigrid cycle included) is
+ * captured once as a HIP graph and replayed per iteration, the iteration
+ * number kept in device memory (enable = 1, the default); with enable = 0
+ * every launch is queued one by one.  The results are the same bit for bit.
+ * A capture the runtime refuses turns the graphs off.  Errors: CCNS_EINVAL
+ * (NULL, not a fused batch, enable not 0 or 1), CCNS_EDEVICE. */
+ccns_status ccns_batch_graphs(ccns_batch *batch, int enable);
 ccns_status ccns_batch_step(ccns_batch *batch, int nsteps, ccns_step_info *per_sim, int *per_status);
 void ccns_batch_destroy(ccns_batch *batch);
 

@@ -131,6 +131,8 @@ def lib():
         L.ccns_batch_create.argtypes = [C.c_int, P(C.c_void_p), C.c_int, P(C.c_void_p)]
         L.ccns_batch_create_fused.restype = C.c_int
         L.ccns_batch_create_fused.argtypes = [C.c_int, P(C.c_void_p), P(C.c_void_p)]
+        L.ccns_batch_graphs.restype = C.c_int
+        L.ccns_batch_graphs.argtypes = [C.c_void_p, C.c_int]
         L.ccns_batch_step.restype = C.c_int
         L.ccns_batch_step.argtypes = [C.c_void_p, C.c_int, P(StepInfo), P(C.c_int)]
         L.ccns_batch_destroy.restype = None
@@ -144,7 +146,8 @@ EXPORTED = ("ccns_caps_count", "ccns_capacities", "ccns_capacities_scratch_bytes
             "ccns_ctx_destroy", "ccns_last_error", "ccns_coef_classes", "ccns_field_set", "ccns_field_get", "ccns_apply",
             "ccns_pressure_solve", "ccns_project", "ccns_step", "ccns_predict", "ccns_correct",
             "ccns_diagnostics", "ccns_forces", "ccns_set_mg_forms", "ccns_mg_levels", "ccns_timing",
-            "ccns_batch_create", "ccns_batch_create_fused", "ccns_batch_step", "ccns_batch_destroy")
+            "ccns_batch_create", "ccns_batch_create_fused", "ccns_batch_graphs", "ccns_batch_step",
+            "ccns_batch_destroy")
 
 
 class CcnsError(RuntimeError):
@@ -415,7 +418,7 @@ class Batch:
     (ccns_batch_create_fused; one precision for all, the multigrid
     preconditioner), else one host thread and stream per simulation."""
 
-    def __init__(self, contexts: Sequence["Context"], nthreads: int = 0, fused: bool = False):
+    def __init__(self, contexts: Sequence["Context"], nthreads: int = 0, fused: bool = False, graphs: bool = True):
         self.contexts = list(contexts)
         self.fused = fused
         arr = (C.c_void_p * len(self.contexts))(*[c.h.value for c in self.contexts])
@@ -424,6 +427,11 @@ class Batch:
             st = lib().ccns_batch_create_fused(len(self.contexts), arr, C.byref(h))
             if st != OK:
                 raise CcnsError(st, "ccns_batch_create_fused")
+            if not graphs:
+                st = lib().ccns_batch_graphs(h, 0)
+                if st != OK:
+                    lib().ccns_batch_destroy(h)
+                    raise CcnsError(st, "ccns_batch_graphs")
         else:
             st = lib().ccns_batch_create(len(self.contexts), arr, nthreads, C.byref(h))
             if st != OK:

@@ -4253,7 +4253,7 @@ struct BatchSim {
     BatchCycle<float> mg32;
 };
 template <class T>
-__host__ __device__ inline const BatchCycle<T> &cycle_of(const BatchSim &s) {
+__host__ __device__ __forceinline__ const BatchCycle<T> &cycle_of(const BatchSim &s) {
     if constexpr (std::is_same<T, double>::value)
         return s.mg;
     else
@@ -4261,7 +4261,7 @@ __host__ __device__ inline const BatchCycle<T> &cycle_of(const BatchSim &s) {
 }
 // The pressure CG's state: the FP64 solve, or the inner float solve.
 template <class T>
-__device__ inline CgState *pois_state(const BatchSim &s) {
+__device__ __forceinline__ CgState *pois_state(const BatchSim &s) {
     return std::is_same<T, double>::value ? s.st_pois : s.st_pois_in;
 }
 
@@ -4274,7 +4274,11 @@ constexpr int BATCH_MAX_SIMS = 1 << (32 - BATCH_SIM_SHIFT);
 // The batched kernel of an operation: work-group blockIdx.x runs group
 // (map & mask) of simulation (map >> shift), with u the launch's uniform
 // argument (the CG iteration, the cycle level or the sweep).  A simulation
-// outside the current refinement sweep (precision 1) does nothing.
+// outside the current refinement sweep (precision 1) does nothing.  Every
+// operation's run is forced inline: an operation instantiated in two kernels
+// is otherwise compiled as a called function, with a stack frame and the
+// register budget of a call (measured: the predictor CG at 2.2 times its
+// time).
 template <class Op>
 __global__ __launch_bounds__(Op::BT) void k_batch(const BatchSim *__restrict__ sims, const unsigned *__restrict__ map,
                                                   int u) {
@@ -4292,12 +4296,37 @@ __global__ __launch_bounds__(Op::BT) __attribute__((amdgpu_waves_per_eu(7))) voi
     if (s.active && !*s.active) return;
     Op::run(SubGrid{(int)(e & BATCH_LOCAL_MASK), Op::groups(s, u)}, s, u);
 }
+// The same two with the CG iteration read from device memory (*itp): the
+// launches of one iteration are then the same for every iteration, and a
+// HIP graph captured once replays them; k_batch_count moves the counter.
+template <class Op>
+__global__ __launch_bounds__(Op::BT) void k_batch_it(const BatchSim *__restrict__ sims,
+                                                     const unsigned *__restrict__ map, const int *itp) {
+    const int u = *itp;
+    const unsigned e = map[blockIdx.x];
+    const BatchSim &s = sims[e >> BATCH_SIM_SHIFT];
+    if (s.active && !*s.active) return;
+    Op::run(SubGrid{(int)(e & BATCH_LOCAL_MASK), Op::groups(s, u)}, s, u);
+}
+template <class Op>
+__global__ __launch_bounds__(Op::BT) __attribute__((amdgpu_waves_per_eu(7))) void k_batch_it_w7(
+    const BatchSim *__restrict__ sims, const unsigned *__restrict__ map, const int *itp) {
+    const int u = *itp;
+    const unsigned e = map[blockIdx.x];
+    const BatchSim &s = sims[e >> BATCH_SIM_SHIFT];
+    if (s.active && !*s.active) return;
+    Op::run(SubGrid{(int)(e & BATCH_LOCAL_MASK), Op::groups(s, u)}, s, u);
+}
+// *itp = v (v >= 0), or *itp + 1 (v < 0).
+__global__ void k_batch_count(int *itp, int v) {
+    if (threadIdx.x == 0) *itp = v >= 0 ? v : *itp + 1;
+}
 
 template <bool GEO, bool CLS>
 struct OpPredRhs {
     static constexpr int BT = NT;
-    __device__ static int groups(const BatchSim &s, int) { return s.pnb; }
-    __device__ static void run(const SubGrid &g, const BatchSim &s, int) {
+    __device__ __forceinline__ static int groups(const BatchSim &s, int) { return s.pnb; }
+    __device__ __forceinline__ static void run(const SubGrid &g, const BatchSim &s, int) {
         pred_rhs_body<GEO, CLS>(g, s.P, s.rows, s.pgx, s.pgy, s.n, s.pd, s.a[A_AX], s.a[A_AY], s.a[A_HBX],
                                 s.a[A_HBY], s.a[A_DX], s.a[A_DY], s.a[A_UX], s.a[A_UY], s.a[A_P], s.a[A_VDX],
                                 s.a[A_VDY], s.a[A_CONVX], s.a[A_CONVY], s.a[A_RHSX], s.a[A_USX], s.rho, s.grav_x,
@@ -4309,8 +4338,8 @@ struct OpPredRhs {
 template <bool MIX, bool GEO, bool CLS>
 struct OpPredResid {
     static constexpr int BT = NT;
-    __device__ static int groups(const BatchSim &s, int) { return s.pnb; }
-    __device__ static void run(const SubGrid &g, const BatchSim &s, int) {
+    __device__ __forceinline__ static int groups(const BatchSim &s, int) { return s.pnb; }
+    __device__ __forceinline__ static void run(const SubGrid &g, const BatchSim &s, int) {
         if constexpr (MIX)
             pred_resid_body<true, GEO, CLS>(g, s.P, s.rows, s.pgx, s.pgy, s.n, s.pd, s.a[A_RHSX], s.a[A_USX],
                                             s.a[A_PRX], s.st_pred_in, s.part[PB_RHS], s.f[G_PRX], s.f[G_PXX],
@@ -4325,10 +4354,10 @@ struct OpPredResid {
 template <class T, bool GEO, bool CLS>
 struct OpPredCg {
     static constexpr int BT = NT;
-    __device__ static int groups(const BatchSim &s, int) {
+    __device__ __forceinline__ static int groups(const BatchSim &s, int) {
         return std::is_same<T, double>::value ? s.pnb : s.pnb32;
     }
-    __device__ static void run(const SubGrid &g, const BatchSim &s, int it) {
+    __device__ __forceinline__ static void run(const SubGrid &g, const BatchSim &s, int it) {
         const int b = it & 1;
         const double *tin = it == 0 ? s.part[PB_INIT] : s.part[PB_UPD];
         const int nin = it == 0 ? 1 : PRED_RED;
@@ -4350,8 +4379,8 @@ struct OpPredCg {
 template <class T>
 struct OpPredSplit {
     static constexpr int BT = NT;
-    __device__ static int groups(const BatchSim &, int) { return PRED_RED; }
-    __device__ static void run(const SubGrid &g, const BatchSim &s, int) {
+    __device__ __forceinline__ static int groups(const BatchSim &, int) { return PRED_RED; }
+    __device__ __forceinline__ static void run(const SubGrid &g, const BatchSim &s, int) {
         reduce_partials_split_body<7>(g, s.part[PB_DIR], std::is_same<T, double>::value ? s.pnb : s.pnb32,
                                       s.part[PB_UPD]);
     }
@@ -4367,8 +4396,8 @@ enum BatchReduce {
 };
 struct OpReduce {
     static constexpr int BT = NT;
-    __device__ static int groups(const BatchSim &, int) { return 1; }
-    __device__ static void run(const SubGrid &, const BatchSim &s, int u) {
+    __device__ __forceinline__ static int groups(const BatchSim &, int) { return 1; }
+    __device__ __forceinline__ static void run(const SubGrid &, const BatchSim &s, int u) {
         switch (u) {
         case RED_PRED: reduce_partials_body<5, 0, NT>(s.part[PB_RHS], s.pnb, s.part[PB_INIT]); break;
         case RED_CYCLE: reduce_partials_body<4, 0, NT>(s.part[PB_UPD], s.mg.lv[0].nbu, s.part[PB_MG]); break;
@@ -4381,8 +4410,8 @@ struct OpReduce {
 };
 struct OpPoisRhs {
     static constexpr int BT = NT;
-    __device__ static int groups(const BatchSim &s, int) { return s.dc.nblk; }
-    __device__ static void run(const SubGrid &g, const BatchSim &s, int) {
+    __device__ __forceinline__ static int groups(const BatchSim &s, int) { return s.dc.nblk; }
+    __device__ __forceinline__ static void run(const SubGrid &g, const BatchSim &s, int) {
         pois_rhs_body(g, s.dc, PoisCoef{s.a[A_CX], s.a[A_CY], s.a[A_DINV]}, s.a[A_AX], s.a[A_AY], s.a[A_HET],
                       s.a[A_USX], s.a[A_USY], s.a[A_B], s.rho_tau, s.part[PB_RHS]);
     }
@@ -4392,8 +4421,8 @@ struct OpPoisRhs {
 template <bool MIX>
 struct OpPoisInit {
     static constexpr int BT = NT;
-    __device__ static int groups(const BatchSim &s, int) { return s.dc.nblk; }
-    __device__ static void run(const SubGrid &g, const BatchSim &s, int u) {
+    __device__ __forceinline__ static int groups(const BatchSim &s, int) { return s.dc.nblk; }
+    __device__ __forceinline__ static void run(const SubGrid &g, const BatchSim &s, int u) {
         const PoisCoef pc{s.a[A_CX], s.a[A_CY], s.a[A_DINV]};
         if constexpr (MIX)
             pois_init_body<true>(g, s.dc, pc, s.a[A_B], s.a[A_PHI], nullptr, s.st_pois_in,
@@ -4410,8 +4439,8 @@ struct OpPoisInit {
 template <class T>
 struct OpDirZ {
     static constexpr int BT = NT;
-    __device__ static int groups(const BatchSim &s, int) { return s.dp.nblk; }
-    __device__ static void run(const SubGrid &g, const BatchSim &s, int it) {
+    __device__ __forceinline__ static int groups(const BatchSim &s, int) { return s.dp.nblk; }
+    __device__ __forceinline__ static void run(const SubGrid &g, const BatchSim &s, int it) {
         if constexpr (std::is_same<T, double>::value) {
             double *pold = (it & 1) ? s.a[A_P1] : s.a[A_P0], *pnew = (it & 1) ? s.a[A_P0] : s.a[A_P1];
             pois_dir_z_body<double>(g, s.dp, PoisCoef{s.a[A_CX], s.a[A_CY], s.a[A_DINV]}, s.mg.z, pold, pnew,
@@ -4428,8 +4457,8 @@ struct OpDirZ {
 template <class T>
 struct OpUpdate {
     static constexpr int BT = UT;
-    __device__ static int groups(const BatchSim &s, int) { return s.nl; }
-    __device__ static void run(const SubGrid &g, const BatchSim &s, int it) {
+    __device__ __forceinline__ static int groups(const BatchSim &s, int) { return s.nl; }
+    __device__ __forceinline__ static void run(const SubGrid &g, const BatchSim &s, int it) {
         if constexpr (std::is_same<T, double>::value)
             cg_update_body<double, false>(g, s.n, s.nl, s.a[A_DINV], s.a[A_PHI], s.a[A_R],
                                           (it & 1) ? s.a[A_P0] : s.a[A_P1], s.a[A_Q], s.st_pois, it & 1,
@@ -4444,8 +4473,8 @@ struct OpUpdate {
 template <class T, int F>
 struct OpMgDown {
     static constexpr int BT = NT;
-    __device__ static int groups(const BatchSim &s, int l) { return cycle_of<T>(s).lv[l].nbd; }
-    __device__ static void run(const SubGrid &g, const BatchSim &s, int l) {
+    __device__ __forceinline__ static int groups(const BatchSim &s, int l) { return cycle_of<T>(s).lv[l].nbd; }
+    __device__ __forceinline__ static void run(const SubGrid &g, const BatchSim &s, int l) {
         const BatchLevelT<T> &L = cycle_of<T>(s).lv[l];
         const int *done = &pois_state<T>(s)->done;
         if constexpr (F == MGF_STAGED)
@@ -4468,8 +4497,8 @@ struct OpMgDown {
 template <class T, int F, bool STATS>
 struct OpMgUp {
     static constexpr int BT = NT;
-    __device__ static int groups(const BatchSim &s, int l) { return cycle_of<T>(s).lv[l].nbu; }
-    __device__ static void run(const SubGrid &g, const BatchSim &s, int l) {
+    __device__ __forceinline__ static int groups(const BatchSim &s, int l) { return cycle_of<T>(s).lv[l].nbu; }
+    __device__ __forceinline__ static void run(const SubGrid &g, const BatchSim &s, int l) {
         const BatchLevelT<T> &L = cycle_of<T>(s).lv[l];
         const int *done = &pois_state<T>(s)->done;
         double *po = STATS ? s.part[PB_UPD] : nullptr;
@@ -4491,8 +4520,8 @@ struct OpMgUp {
 template <class T>
 struct OpCoarsest {
     static constexpr int BT = NT;
-    __device__ static int groups(const BatchSim &, int) { return 1; }
-    __device__ static void run(const SubGrid &, const BatchSim &s, int) {
+    __device__ __forceinline__ static int groups(const BatchSim &, int) { return 1; }
+    __device__ __forceinline__ static void run(const SubGrid &, const BatchSim &s, int) {
         const BatchCycle<T> &y = cycle_of<T>(s);
         mg_coarsest_body<T>(s.ncoarse, s.pidx, s.pinv, y.cb, y.cxo, &pois_state<T>(s)->done);
     }
@@ -4500,8 +4529,8 @@ struct OpCoarsest {
 template <class T, bool LDS>
 struct OpTail {
     static constexpr int BT = TT;
-    __device__ static int groups(const BatchSim &, int) { return 1; }
-    __device__ static void run(const SubGrid &, const BatchSim &s, int) {
+    __device__ __forceinline__ static int groups(const BatchSim &, int) { return 1; }
+    __device__ __forceinline__ static void run(const SubGrid &, const BatchSim &s, int) {
         if constexpr (LDS)
             mg_tail_lds_body<T>(cycle_of<T>(s).tail);
         else
@@ -4512,8 +4541,8 @@ struct OpTail {
 // or the pressure's Phi (u = 1).
 struct OpAddCorr {
     static constexpr int BT = NT;
-    __device__ static int groups(const BatchSim &s, int u) { return u == 0 ? s.fb2 : s.fb1; }
-    __device__ static void run(const SubGrid &g, const BatchSim &s, int u) {
+    __device__ __forceinline__ static int groups(const BatchSim &s, int u) { return u == 0 ? s.fb2 : s.fb1; }
+    __device__ __forceinline__ static void run(const SubGrid &g, const BatchSim &s, int u) {
         if (u == 0)
             add_correction_body(g, 2 * s.n, s.a[A_USX], s.f[G_PXX]);
         else
@@ -4522,16 +4551,16 @@ struct OpAddCorr {
 };
 struct OpCorrect {
     static constexpr int BT = NT;
-    __device__ static int groups(const BatchSim &s, int) { return s.dc.nblk; }
-    __device__ static void run(const SubGrid &g, const BatchSim &s, int) {
+    __device__ __forceinline__ static int groups(const BatchSim &s, int) { return s.dc.nblk; }
+    __device__ __forceinline__ static void run(const SubGrid &g, const BatchSim &s, int) {
         correct_body(g, s.dc, s.a[A_GX], s.a[A_GY], s.a[A_USX], s.a[A_USY], s.a[A_PHI], s.a[A_UX], s.a[A_UY],
                      s.tau_rho);
     }
 };
 struct OpDiag {
     static constexpr int BT = NT;
-    __device__ static int groups(const BatchSim &s, int) { return s.dc.nblk; }
-    __device__ static void run(const SubGrid &g, const BatchSim &s, int) {
+    __device__ __forceinline__ static int groups(const BatchSim &s, int) { return s.dc.nblk; }
+    __device__ __forceinline__ static void run(const SubGrid &g, const BatchSim &s, int) {
         diag_body(g, s.dc, s.dgc, s.a[A_UX], s.a[A_UY], s.a[A_PHI], s.a[A_P], s.pcoef, 1, s.rho, s.part[PB_DIAG]);
     }
 };
@@ -4612,6 +4641,12 @@ struct ccns_batch {
     std::vector<unsigned char> forms;  // the cycle forms the tables were built for
     size_t map_cap = 0;
     int maxcyc = 0, tail_lds = 0;
+    // CG iterations as HIP graphs (one iteration of the predictor CG and one
+    // of the pressure CG, with the iteration number in *dit), rebuilt with
+    // the tables; off: every launch is queued one by one
+    bool graphs = true;
+    int *dit = nullptr;
+    hipGraphExec_t gpred = nullptr, gpois = nullptr;
     BatchTable pred[4], pred32[4], one, split, dc, dp, upd, fb1, fb2;
     BatchTable down[BATCH_LEVELS][6], up[BATCH_LEVELS][6], bot[3];
 };
@@ -4766,12 +4801,15 @@ bool batch_forms_ok(const ccns_ctx *c, const std::vector<ccns_ctx::LevelT<T>> &m
     return true;
 }
 
+void batch_drop_graphs(ccns_batch *b);
+
 // Builds the descriptors and the work-group tables of every launch (the
 // simulations in the batch's order, largest first, so that the big grids'
 // groups are dispatched first), and uploads them.
 ccns_status batch_build(ccns_batch *b) {
     const int n = (int)b->sims.size();
     const int dbl = b->prec == 1 ? 0 : 1;  // the forms of the cycle the batch runs
+    batch_drop_graphs(b);
     b->hsims.resize(n);
     b->forms.clear();
     b->maxcyc = 0;
@@ -4865,6 +4903,26 @@ void blaunch_w7(ccns_batch *b, const BatchTable &t, int u) {
     if (t.nblk > 0)
         hipLaunchKernelGGL(k_batch_w7<Op>, dim3(t.nblk), dim3(Op::BT), 0, b->stream, b->dsims, b->dmap + t.off, u);
 }
+// Launches of a CG iteration: with it >= 0 the iteration is an argument;
+// with it < 0 (while a graph is captured) the kernels read it from *dit.
+template <class Op>
+void blaunch_iter(ccns_batch *b, const BatchTable &t, int it) {
+    if (t.nblk <= 0) return;
+    if (it >= 0)
+        hipLaunchKernelGGL(k_batch<Op>, dim3(t.nblk), dim3(Op::BT), 0, b->stream, b->dsims, b->dmap + t.off, it);
+    else
+        hipLaunchKernelGGL(k_batch_it<Op>, dim3(t.nblk), dim3(Op::BT), 0, b->stream, b->dsims, b->dmap + t.off,
+                           (const int *)b->dit);
+}
+template <class Op>
+void blaunch_iter_w7(ccns_batch *b, const BatchTable &t, int it) {
+    if (t.nblk <= 0) return;
+    if (it >= 0)
+        hipLaunchKernelGGL(k_batch_w7<Op>, dim3(t.nblk), dim3(Op::BT), 0, b->stream, b->dsims, b->dmap + t.off, it);
+    else
+        hipLaunchKernelGGL(k_batch_it_w7<Op>, dim3(t.nblk), dim3(Op::BT), 0, b->stream, b->dsims, b->dmap + t.off,
+                           (const int *)b->dit);
+}
 
 // One V-cycle of every simulation on its finest level's residual, in
 // storage type T: the down-sweeps level by level, the coarse ends, the
@@ -4892,6 +4950,74 @@ void batch_vcycle(ccns_batch *b) {
     blaunch<OpMgUp<T, MGF_STAGED_LDS, true>>(b, b->up[0][MGF_STAGED_LDS], 0);
     blaunch<OpMgUp<T, MGF_PLAIN, true>>(b, b->up[0][MGF_PLAIN], 0);
     blaunch<OpReduce>(b, b->one, std::is_same<T, double>::value ? RED_CYCLE : RED_CYCLE32);
+}
+
+// One iteration of every simulation's predictor CG in storage type T
+// (it < 0: the iteration number from *dit, which the last launch moves on).
+template <class T>
+void batch_pred_iter(ccns_batch *b, int it) {
+    const BatchTable *t = std::is_same<T, double>::value ? b->pred : b->pred32;
+    blaunch_iter_w7<OpPredCg<T, false, false>>(b, t[0], it);
+    blaunch_iter_w7<OpPredCg<T, true, false>>(b, t[1], it);
+    blaunch_iter_w7<OpPredCg<T, false, true>>(b, t[2], it);
+    blaunch_iter_w7<OpPredCg<T, true, true>>(b, t[3], it);
+    blaunch_iter<OpPredSplit<T>>(b, b->split, it);
+    if (it < 0) hipLaunchKernelGGL(k_batch_count, dim3(1), dim3(64), 0, b->stream, b->dit, -1);
+}
+// One iteration of every simulation's multigrid-preconditioned pressure CG.
+template <class T>
+void batch_pois_iter(ccns_batch *b, int it) {
+    blaunch_iter<OpDirZ<T>>(b, b->dp, it);
+    blaunch_iter<OpUpdate<T>>(b, b->upd, it);
+    batch_vcycle<T>(b);
+    if (it < 0) hipLaunchKernelGGL(k_batch_count, dim3(1), dim3(64), 0, b->stream, b->dit, -1);
+}
+
+void batch_drop_graphs(ccns_batch *b) {
+    if (b->gpred) (void)hipGraphExecDestroy(b->gpred);
+    if (b->gpois) (void)hipGraphExecDestroy(b->gpois);
+    b->gpred = b->gpois = nullptr;
+}
+
+// Captures the launches fill() queues as a graph.  A capture the runtime
+// refuses leaves the batch queueing its launches one by one.
+template <class F>
+void batch_capture(ccns_batch *b, hipGraphExec_t &exec, F fill) {
+    if (exec || !b->graphs) return;
+    hipGraph_t g = nullptr;
+    bool ok = hipStreamBeginCapture(b->stream, hipStreamCaptureModeRelaxed) == hipSuccess;
+    if (ok) {
+        fill();
+        ok = hipStreamEndCapture(b->stream, &g) == hipSuccess && g;
+    }
+    if (ok) ok = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0) == hipSuccess;
+    if (g) (void)hipGraphDestroy(g);
+    if (!ok) {
+        exec = nullptr;
+        (void)hipGetLastError();
+        batch_drop_graphs(b);
+        b->graphs = false;
+    }
+}
+
+// Queues one CG iteration it: by replaying the captured graph (the
+// iteration number then lives in *dit, set to 0 before the first), or
+// launch by launch.
+template <class T>
+ccns_status batch_iterate(ccns_batch *b, bool pred, int it) {
+    if (b->graphs) {
+        hipGraphExec_t &exec = pred ? b->gpred : b->gpois;
+        batch_capture(b, exec, [&] { pred ? batch_pred_iter<T>(b, -1) : batch_pois_iter<T>(b, -1); });
+    }
+    if (b->graphs) {
+        if (it == 0) hipLaunchKernelGGL(k_batch_count, dim3(1), dim3(64), 0, b->stream, b->dit, 0);
+        if (hipGraphLaunch(pred ? b->gpred : b->gpois, b->stream) != hipSuccess) return CCNS_EDEVICE;
+    } else if (pred) {
+        batch_pred_iter<T>(b, it);
+    } else {
+        batch_pois_iter<T>(b, it);
+    }
+    return CCNS_OK;
 }
 
 // Reads every simulation's solver state, diagnostics or residual
@@ -5004,7 +5130,10 @@ ccns_status batch_cg(ccns_batch *b, int first_chunk, int next_chunk, int which, 
     int chunk = first_chunk;
     its = 0;
     for (;;) {
-        for (int u = 0; u < chunk; ++u, ++its) iter(its);
+        for (int u = 0; u < chunk; ++u, ++its) {
+            ccns_status s = iter(its);
+            if (s != CCNS_OK) return s;
+        }
         ccns_status s = batch_read(b, which);
         if (s != CCNS_OK) return s;
         bool all = true;
@@ -5031,13 +5160,8 @@ ccns_status batch_fused_step(ccns_batch *b, std::vector<ccns_step_info> &info, s
     blaunch<OpReduce>(b, b->one, RED_PRED);
     int last = 0, its = 0;
     for (ccns_ctx *c : b->sims) last = std::max(last, c->last_pred_it);
-    s = batch_cg(b, std::max(4, last + 1), 8, GAT_PRED, [&](int it) {
-        blaunch_w7<OpPredCg<double, false, false>>(b, b->pred[0], it);
-        blaunch_w7<OpPredCg<double, true, false>>(b, b->pred[1], it);
-        blaunch_w7<OpPredCg<double, false, true>>(b, b->pred[2], it);
-        blaunch_w7<OpPredCg<double, true, true>>(b, b->pred[3], it);
-        blaunch<OpPredSplit<double>>(b, b->split, it);
-    }, its);
+    s = batch_cg(b, std::max(4, last + 1), 8, GAT_PRED, [&](int it) { return batch_iterate<double>(b, true, it); },
+                 its);
     if (s != CCNS_OK) return s;
     for (int k = 0; k < n; ++k) {
         info[k].pred = solve_info(b->hcg[k], true);
@@ -5050,11 +5174,8 @@ ccns_status batch_fused_step(ccns_batch *b, std::vector<ccns_step_info> &info, s
     batch_vcycle<double>(b);
     last = 0;
     for (ccns_ctx *c : b->sims) last = std::max(last, c->last_pois_it);
-    s = batch_cg(b, std::max(2, last + 1), 2, GAT_POIS, [&](int it) {
-        blaunch<OpDirZ<double>>(b, b->dp, it);
-        blaunch<OpUpdate<double>>(b, b->upd, it);
-        batch_vcycle<double>(b);
-    }, its);
+    s = batch_cg(b, std::max(2, last + 1), 2, GAT_POIS, [&](int it) { return batch_iterate<double>(b, false, it); },
+                 its);
     if (s != CCNS_OK) return s;
     for (int k = 0; k < n; ++k) {
         info[k].poisson = solve_info(b->hcg[k], false);
@@ -5154,13 +5275,8 @@ ccns_status batch_fused_step_mixed(ccns_batch *b, std::vector<ccns_step_info> &i
         if ((s = batch_upload(b)) != CCNS_OK) return s;
         hipLaunchKernelGGL(k_batch_set_tol, dim3((n + NT - 1) / NT), dim3(NT), 0, b->stream, b->dsims, n, 0, b->dtol);
         int its = 0;
-        s = batch_cg(b, std::max(4, last + 1), 8, GAT_PRED_IN, [&](int it) {
-            blaunch_w7<OpPredCg<float, false, false>>(b, b->pred32[0], it);
-            blaunch_w7<OpPredCg<float, true, false>>(b, b->pred32[1], it);
-            blaunch_w7<OpPredCg<float, false, true>>(b, b->pred32[2], it);
-            blaunch_w7<OpPredCg<float, true, true>>(b, b->pred32[3], it);
-            blaunch<OpPredSplit<float>>(b, b->split, it);
-        }, its);
+        s = batch_cg(b, std::max(4, last + 1), 8, GAT_PRED_IN,
+                     [&](int it) { return batch_iterate<float>(b, true, it); }, its);
         if (s != CCNS_OK) return s;
         if (batch_note_inner(b, rec, o, true) && (s = batch_upload(b)) != CCNS_OK) return s;
         blaunch<OpAddCorr>(b, b->fb2, 0);
@@ -5216,11 +5332,8 @@ ccns_status batch_fused_step_mixed(ccns_batch *b, std::vector<ccns_step_info> &i
         hipLaunchKernelGGL(k_batch_set_tol, dim3((n + NT - 1) / NT), dim3(NT), 0, b->stream, b->dsims, n, 1, b->dtol);
         batch_vcycle<float>(b);
         int its = 0;
-        s = batch_cg(b, std::max(2, last + 1), 2, GAT_POIS_IN, [&](int it) {
-            blaunch<OpDirZ<float>>(b, b->dp, it);
-            blaunch<OpUpdate<float>>(b, b->upd, it);
-            batch_vcycle<float>(b);
-        }, its);
+        s = batch_cg(b, std::max(2, last + 1), 2, GAT_POIS_IN,
+                     [&](int it) { return batch_iterate<float>(b, false, it); }, its);
         if (s != CCNS_OK) return s;
         if (batch_note_inner(b, rec, o, false) && (s = batch_upload(b)) != CCNS_OK) return s;
         blaunch<OpAddCorr>(b, b->fb1, 1);
@@ -5242,6 +5355,8 @@ void batch_free(ccns_batch *b) {
     if (b->dcg) (void)hipFree(b->dcg);
     if (b->ddg) (void)hipFree(b->ddg);
     if (b->dst8) (void)hipFree(b->dst8);
+    batch_drop_graphs(b);
+    if (b->dit) (void)hipFree(b->dit);
     if (b->dact) (void)hipFree(b->dact);
     if (b->dtol) (void)hipFree(b->dtol);
     if (b->hcg) (void)hipHostFree(b->hcg);
@@ -5322,6 +5437,7 @@ ccns_status ccns_batch_create_fused(int n, ccns_ctx *const *ctxs, ccns_batch **o
         hipMalloc(&b->ddg, n * sizeof(DiagState)) == hipSuccess &&
         hipMalloc(&b->dst8, (size_t)n * 8 * sizeof(double)) == hipSuccess &&
         hipMalloc(&b->dact, n * sizeof(int)) == hipSuccess && hipMalloc(&b->dtol, n * sizeof(double)) == hipSuccess &&
+        hipMalloc(&b->dit, sizeof(int)) == hipSuccess &&
         hipHostMalloc(&b->hcg, n * sizeof(CgState)) == hipSuccess &&
         hipHostMalloc(&b->hdg, n * sizeof(DiagState)) == hipSuccess &&
         hipHostMalloc(&b->hst8, (size_t)n * 8 * sizeof(double)) == hipSuccess &&
@@ -5402,6 +5518,14 @@ ccns_status ccns_batch_step(ccns_batch *b, int nsteps, ccns_step_info *per_sim, 
         if (per_status) per_status[s] = st[s];
     }
     return worst;
+}
+
+ccns_status ccns_batch_graphs(ccns_batch *b, int enable) {
+    if (!b || !b->fused || (enable != 0 && enable != 1)) return CCNS_EINVAL;
+    if (hipStreamSynchronize(b->stream) != hipSuccess) return CCNS_EDEVICE;
+    batch_drop_graphs(b);
+    b->graphs = enable == 1;
+    return CCNS_OK;
 }
 
 void ccns_batch_destroy(ccns_batch *b) { batch_free(b); }

@@ -172,13 +172,17 @@ def _context_mg(case, stream, extra):
     return ctx
 
 
+@pytest.mark.parametrize("graphs", [True, False])
 @pytest.mark.parametrize("precision", [0, 1])
-def test_fused_batch_matches_solo_runs_bit_for_bit(precision):
+def test_fused_batch_matches_solo_runs_bit_for_bit(precision, graphs):
     """Three steps of the fused batch give each simulation's solo fields and
     step figures bit for bit, in FP64 and in precision 1 (FP32 inner solves
-    with FP64 refinement, whose sweeps run in lockstep); so do two fused
-    steps followed by a solo step on each context (the contexts carry on
-    from a fused step as from their own)."""
+    with FP64 refinement, whose sweeps run in lockstep), with each CG
+    iteration replayed from a captured graph (every replay, with the
+    batch's read-backs between chunks of them, enters the compared fields)
+    and launched one by one; so do two fused steps followed by a solo step
+    on each context (the contexts carry on from a fused step as from their
+    own)."""
     from paper_2211_10698_amd import ccns
     cases = [(name, case, dict(extra, precision=precision, div_tol=1e-8)) for name, case, extra in _fused_cases()]
     nsteps = 3
@@ -192,8 +196,8 @@ def test_fused_batch_matches_solo_runs_bit_for_bit(precision):
     for split in (False, True):
         ctxs = [_context_mg(case, torch.cuda.Stream(), extra) for _, case, extra in cases]
         torch.cuda.synchronize()
-        batch = ccns.Batch(ctxs, fused=True)
-        print(f"[fused] batch steps (then a solo step: {split})", flush=True)
+        batch = ccns.Batch(ctxs, fused=True, graphs=graphs)
+        print(f"[fused] batch steps, graphs {graphs} (then a solo step: {split})", flush=True)
         if split:
             st, _, _ = batch.step(nsteps - 1)
             assert st == ccns.OK
