@@ -15,6 +15,9 @@ Modules
   derived    activity masks and coefficient fields used by the time stepper
   solvers    Jacobi-preconditioned CG and a direct sparse solve
   pmii       projection method II time step (Sec. 4.6)
+  geometry3d capacities of the first kind in three dimensions (spheres and
+             z-cylinders; Sec. 3.2-3.4 with a third index)
+  pmii3d     the projection step in three dimensions (Sec. 4.1, 4.6)
 
 Parity status: every function is pinned by a test under tests/ except the
 ones whose header says "parity unpinned".
