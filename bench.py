@@ -70,7 +70,14 @@ WORKLOADS = {
     "paper_cylinder_2048x1024": W.paper_cylinder,
     "batched_cylinders_256": None,   # ragged batch, see run_batched
     "serving_trace": None,           # served requests, see run_serving
+    "sphere_projection_256": None,   # the 3-D projection step, see run_projection3d
 }
+
+# The 3-D Poisson CG's direction-and-operator kernel: reads z, p_old and the
+# three face weights c^x, c^y, c^z of its cell; writes p and (-L) p.  The
+# update kernel reads 1/diag, p, (-L) p, x, r and writes x, r, z.
+DIR3_BYTES_PER_CELL = 7 * 8.0
+UPDATE3_BYTES_PER_ELEMENT = 8 * 8.0
 
 
 # Device helpers whose text a kernel's counter readings also depend on.
@@ -439,6 +446,100 @@ def run_serving(args):
     print(json.dumps(out), flush=True)
 
 
+def run_projection3d(args):
+    """The projection step in three dimensions: 256^3 cells around a sphere
+    in a closed box, U* seeded on every interior face.  A step resets U* (a
+    device-to-device copy) and Phi = 0, then runs one projection (b, the
+    Jacobi-PCG to 1e-12, the correction); value = cells projected per
+    second.  The roofline entry is the CG's direction-and-operator kernel,
+    timed live with HIP events around each of its launches."""
+    import torch
+    from oracle import geometry3d as G3, pmii3d as P3
+    from paper_2211_10698_amd import ccns3d
+    import workloads.three_d as T
+
+    torch.cuda.set_device(0)
+    case = T.sphere_box_256()
+    g = case.grid
+    t_setup = time.perf_counter()
+    caps = ccns3d.capacities(g, case.bodies)
+    ctx = ccns3d.Context3(g, ccns3d.make_params(case.rho, case.tau, tol=case.tol, mass_floor=case.mass_floor), caps)
+    U = [torch.from_numpy(u).cuda() for u in T.face_velocity(case)]
+    zero = torch.zeros(g.shape, dtype=torch.float64, device="cuda")
+    fields = (ccns3d.F_UX, ccns3d.F_UY, ccns3d.F_UZ)
+
+    def step():
+        for f, u in zip(fields, U):
+            ctx.set_field(f, u)
+        ctx.set_field(ccns3d.F_PHI, zero)
+        return ctx.project()
+
+    print(f"[bench] setup {time.perf_counter() - t_setup:.1f}s: {case.name} {g.nx}x{g.ny}x{g.nz}",
+          file=sys.stderr, flush=True)
+    for k in range(args.warmup):
+        info = step()
+        print(f"[bench] warmup {k}: cg {info.iterations} div_rel {info.div_rel:.2e}", file=sys.stderr, flush=True)
+    ctx.timing(1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = []
+    for k in range(args.steps):
+        infos.append(step())
+        print(f"[bench] step {k}: cg {infos[-1].iterations} div_rel {infos[-1].div_rel:.2e}", file=sys.stderr,
+              flush=True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    (dms, dn), (ums, un) = ctx.timing(0)
+    cells = g.cells
+    dir_us = dms * 1e3 / max(dn, 1)
+    upd_us = ums * 1e3 / max(un, 1)
+    achieved = DIR3_BYTES_PER_CELL * cells / (dir_us * 1e-6) / 1e9
+    n_elem = (g.nx + 2 + 15) // 16 * 16 * (g.ny + 2) * (g.nz + 2)
+    cpu = None
+    if not args.no_cpu_baseline:
+        # the oracle's projection (Jacobi-PCG to the same tolerance) on a 40^3
+        # sphere box, scaled to cells per second
+        sc = T.sphere_box(40)
+        t1 = time.perf_counter()
+        pr = P3.prepare(G3.capacities(sc.grid, sc.bodies), sc.grid, sc.mass_floor)
+        t2 = time.perf_counter()
+        _, _, oinfo = P3.project(pr, T.face_velocity(sc), sc.rho, sc.tau, solver="pcg", tol=sc.tol)
+        t3 = time.perf_counter()
+        cpu = {"value": sc.grid.cells / (t3 - t2) / 1e6, "unit": "Mcell-projections/s", "cores": 1,
+               "kind": "oracle",
+               "sample": f"one oracle projection of sphere_box(40) (64,000 cells, {oinfo['iterations']} Jacobi-PCG "
+                         f"iterations to {sc.tol:g}) in {t3 - t2:.1f} s after {t2 - t1:.1f} s of capacities; "
+                         f"the 256^3 case needs about {infos[-1].iterations / max(oinfo['iterations'], 1):.1f}x "
+                         f"the iterations per cell"}
+    out = {
+        "metric": "Mcell-projections/s (3-D projection step, div_rel <= 1e-10)",
+        "value": cells * args.steps / wall / 1e6,
+        "unit": "Mcell-projections/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "sphere_projection_256", "cells": cells, "grid": [g.nx, g.ny, g.nz],
+                   "bodies": "sphere r=0.3 in the unit box", "solver": "Jacobi-PCG, tol 1e-12",
+                   "mass_floor": case.mass_floor},
+        "cg_iterations": [i.iterations for i in infos],
+        "div_rel_max": max(i.div_rel for i in infos),
+        "kernels_us": {"k3_stencil<DIR>": dir_us, "k3_update": upd_us,
+                       "update_GBps": UPDATE3_BYTES_PER_ELEMENT * n_elem / (upd_us * 1e-6) / 1e9},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": 8000.0, "unit": "GB/s",
+                     "frac": achieved / 8000.0, "traffic": None,
+                     "kernel": "k3_stencil<DIR>", "bytes_per_cell": DIR3_BYTES_PER_CELL},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -491,6 +592,9 @@ def main():
         return
     if args.workload == "serving_trace":
         run_serving(args)
+        return
+    if args.workload == "sphere_projection_256":
+        run_projection3d(args)
         return
     from paper_2211_10698_amd import ccns
 

@@ -45,11 +45,15 @@ from workloads.three_d import ZCYLINDER, Body3, Grid3
 EPS_REL = 1e-12
 
 
-def _circle_primitive(t, rho):
-    """Integral of sqrt(rho^2 - x^2) from -rho to t (t in [-rho, rho])."""
+def _circle_primitive(t, rho, s=None):
+    """Integral of sqrt(rho^2 - x^2) from -rho to t (t in [-rho, rho]).  s is
+    the height sqrt(rho^2 - t^2) when it is known exactly (at the chord's
+    ends): the angle then comes from atan2(t, s), which rounding of t / rho
+    near +-1 would spoil by up to its square root."""
     t = min(max(t, -rho), rho)
-    s = math.sqrt(max(rho * rho - t * t, 0.0))
-    return 0.5 * (t * s + rho * rho * math.asin(t / rho)) + 0.25 * math.pi * rho * rho
+    if s is None:
+        s = math.sqrt(max(rho * rho - t * t, 0.0))
+    return 0.5 * (t * s + rho * rho * math.atan2(t, s)) + 0.25 * math.pi * rho * rho
 
 
 def _disc_quadrant(u, v, rho):
@@ -59,11 +63,15 @@ def _disc_quadrant(u, v, rho):
         return 0.0
     if v >= rho:
         return 2.0 * _circle_primitive(u, rho)
-    w = math.sqrt(rho * rho - v * v)   # the chord y = v meets the circle at x = +-w
+    av = abs(v)
+    w = math.sqrt(rho * rho - v * v)   # the chord y = v meets the circle at x = +-w (height |v|)
+    known = {-rho: 0.0, rho: 0.0, -w: av, w: av}
+
+    def prim(x):
+        return _circle_primitive(x, rho, known[x]) if x <= u else _circle_primitive(u, rho)
 
     def seg(a, b):                     # integral of sqrt(rho^2 - x^2) over [a, min(b, u)]
-        b = min(b, u)
-        return _circle_primitive(b, rho) - _circle_primitive(a, rho) if b > a else 0.0
+        return prim(b) - prim(a) if min(b, u) > a else 0.0
 
     def length(a, b):
         b = min(b, u)

@@ -40,11 +40,11 @@ def build(verbose: bool = True) -> str:
     os.makedirs(BUILD, exist_ok=True)
     hipcc = _hipcc()
     objs = []
-    for src in ("capacities.cpp", "prep.cpp"):
+    for src in ("capacities.cpp", "prep.cpp", "caps3d.cpp"):
         obj = os.path.join(BUILD, src + ".o")
         _run(["g++", *HOST_FLAGS, "-I", INC, "-I", CSRC, "-c", os.path.join(CSRC, src), "-o", obj])
         objs.append(obj)
-    for src in ("ccns_device.hip", "caps_device.hip"):
+    for src in ("ccns_device.hip", "caps_device.hip", "ccns3d.hip"):
         obj = os.path.join(BUILD, src + ".o")
         _run([hipcc, *HIP_FLAGS, "-I", INC, "-I", CSRC, "-c", os.path.join(CSRC, src), "-o", obj])
         objs.append(obj)

@@ -1,0 +1,659 @@
+// The projection step in three dimensions (Sec. 4.6 with the operators of
+// Sec. 4.1 on 7-point stencils; the paper extends its two-dimensional
+// statement by adding an index, Sec. 2.1) on gfx950.
+//
+// Device layout: every field is (nz+2)(ny+2) rows of `pitch` doubles (pitch
+// = nx+2 rounded up to 16), element (i, j, k) at (k (ny+2) + j) pitch + i,
+// the same index meaning as the dense host layout.
+//
+// The Poisson solve is Jacobi-preconditioned CG with two kernels per
+// iteration, both HBM-bound:
+//  * k3_stencil<DIR>: p = z + beta p_old on a tile of 64 x 4 columns and its
+//    one-cell halo, marching up a slab of 32 cells in z with the planes
+//    below and above each cell in registers and the current plane in LDS;
+//    q = (-L) p = sum over the six faces of c_f (p_c - p_nb); partial p.q;
+//  * k3_update: x += alpha p, r -= alpha q, z = r / diag; partials r.z, r.r.
+// Each launch reduces the previous launch's per-group partials itself, in a
+// fixed order, so alpha, beta and the stopping test are the same in every
+// group and the solve runs without host round trips inside a chunk of
+// iterations; the host looks at the solver state once per chunk.  Every
+// reduction has a fixed order, so results are reproducible bit for bit.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <climits>
+#include <cstdint>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "ccns3d.h"
+#include "ccns3d_internal.h"
+#include "ccns_kern.h"
+
+namespace ccns {
+namespace {
+
+constexpr int T3X = 64;     // tile columns in x (one wavefront)
+constexpr int T3Y = 4;      // tile rows in y (the four wavefronts of a group)
+constexpr int T3Z = 32;     // cells per column of a tile, marched in z
+constexpr int NB3 = 1024;   // at most this many work-groups per kernel
+constexpr int HALO3 = 2 * (T3X + 2) + 2 * T3Y;  // halo cells of one plane of a tile
+
+// Solver state in device memory.  stop_it: the iteration whose direction
+// launch stopped the solve (INT_MAX while it runs); rz[2]: r.z of the last
+// two iterations (alternating slots, written by group 0 of the direction
+// launch).
+struct Cg3 {
+    double bb, tol2, rr_final;
+    double rz[2];
+    int stop_it, status, it_final, maxit;
+};
+
+struct Dims3 {
+    int nx, ny, nz, pitch;
+    size_t plane, n;       // elements per z-plane and per field
+    int gxt, gyt, gzt;     // tiles per direction
+    int ntile, tpb, nblk;  // tiles, tiles per group, groups of the stencil kernel
+    int nflat;             // groups of the element-wise kernels
+};
+
+enum { S_APPLY = 0, S_RESID = 1, S_DIR = 2 };
+
+// The value the stencil acts on at element e: the input (apply), the
+// iterate x (residual) or the new direction z + beta p_old.
+template <int MODE>
+__device__ inline double stencil_value(size_t e, const double *__restrict__ a, const double *__restrict__ b2, double beta,
+                                       bool first) {
+    if (MODE == S_DIR) return first ? a[e] : fma(beta, b2[e], a[e]);
+    return a[e];
+}
+
+// (-L) v on tiles of 64 x 4 columns marched through T3Z cells in z.
+//  S_APPLY: out = (-L) in.
+//  S_RESID: b' = b - mean(b) on the unknowns (mean from the right-hand
+//    side kernel's partials), r = b' - (-L) x, z = r / diag, b' stored;
+//    partials (r.z, r.r, b'.b').
+//  S_DIR: iteration `it` of the CG (see the file comment); partial p.q.
+template <int MODE>
+__global__ __launch_bounds__(NT) void k3_stencil(Dims3 d, const double *__restrict__ cx, const double *__restrict__ cy,
+                                                 const double *__restrict__ cz, const double *__restrict__ dinv,
+                                                 const double *__restrict__ va, const double *__restrict__ vb,
+                                                 double *__restrict__ out1, double *__restrict__ out2,
+                                                 double *__restrict__ bvec, Cg3 *st, int it, const double *pin, int nin,
+                                                 int n_active, double *part) {
+    double beta = 0.0, mean = 0.0;
+    bool first = true;
+    if (MODE == S_DIR) {
+        if (st->stop_it < it) return;
+        double rz, rr, bb;
+        if (it == 0) {
+            double t[3];
+            get_totals<3>(pin, nin, t);
+            rz = t[0];
+            rr = t[1];
+            bb = t[2];
+        } else {
+            double t[2];
+            get_totals<2>(pin, nin, t);
+            rz = t[0];
+            rr = t[1];
+            bb = st->bb;
+            first = false;
+        }
+        // a NaN never counts as converged; a residual that is not finite, or
+        // r.z not positive, ends the solve as a breakdown
+        const bool conv = rr <= st->tol2 * bb;
+        const double rz_old = it == 0 ? 1.0 : st->rz[(it - 1) & 1];
+        const bool breakdown = !conv && !(rz > 0.0 && rz < INFINITY && rr < INFINITY);
+        beta = it == 0 ? 0.0 : rz / rz_old;
+        const bool stop = conv || breakdown || it >= st->maxit;
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            if (it == 0) st->bb = bb;
+            st->rz[it & 1] = rz;
+            if (stop) {
+                st->status = conv ? CCNS_OK : (breakdown ? CCNS_EBREAKDOWN : CCNS_ENOTCONV);
+                st->it_final = it;
+                st->rr_final = rr;
+                st->stop_it = it;
+            }
+        }
+        if (stop) return;
+    } else if (MODE == S_RESID) {
+        double t[1];
+        get_totals<1>(pin, nin, t);
+        mean = n_active > 0 ? t[0] / n_active : 0.0;
+    }
+    __shared__ double s[T3Y + 2][T3X + 2];
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    const int X = d.pitch;
+    const size_t PL = d.plane;
+    double acc[3] = {0.0, 0.0, 0.0};
+    const int L = logical_group(d.nblk);
+    const int t0 = L * d.tpb, t1 = min(t0 + d.tpb, d.ntile);
+    for (int t = t0; t < t1; ++t) {
+        const int txi = t % d.gxt, rest = t / d.gxt, tyj = rest % d.gyt, tz = rest / d.gyt;
+        const int i0 = 1 + T3X * txi, j0 = 1 + T3Y * tyj, k0 = 1 + T3Z * tz, k1 = min(k0 + T3Z, d.nz + 1);
+        const int i = i0 + tx, j = j0 + ty;
+        const bool own = i <= d.nx && j <= d.ny;
+        // this thread's halo cell of each plane (threads 0 .. HALO3-1)
+        int hx = 0, hy = 0;
+        bool hin = false;
+        if ((int)threadIdx.x < HALO3) {
+            const int e = threadIdx.x;
+            if (e < 2 * (T3X + 2)) {
+                hy = e < T3X + 2 ? 0 : T3Y + 1;
+                hx = e < T3X + 2 ? e : e - (T3X + 2);
+            } else {
+                const int f = e - 2 * (T3X + 2);
+                hy = 1 + (f >> 1);
+                hx = (f & 1) ? T3X + 1 : 0;
+            }
+            // beyond the ghost layer the slot holds 0 (no own cell reads it)
+            hin = i0 - 1 + hx <= d.nx + 1 && j0 - 1 + hy <= d.ny + 1;
+        }
+        const size_t hoff = (size_t)(j0 - 1 + hy) * X + (i0 - 1 + hx);
+        const size_t col = (size_t)j * X + i;
+        double prev = 0.0, cur = 0.0, czb = 0.0;
+        if (own) {
+            prev = stencil_value<MODE>((size_t)(k0 - 1) * PL + col, va, vb, beta, first);
+            cur = stencil_value<MODE>((size_t)k0 * PL + col, va, vb, beta, first);
+            czb = cz[(size_t)(k0 - 1) * PL + col];
+        }
+        for (int k = k0; k < k1; ++k) {
+            const size_t e = (size_t)k * PL + col;
+            double nxt = 0.0, ce = 0.0, cw = 0.0, cn = 0.0, cs = 0.0, ct = 0.0, dv = 0.0, bv = 0.0, hv = 0.0;
+            if (own) {
+                nxt = stencil_value<MODE>(e + PL, va, vb, beta, first);
+                ce = cx[e];
+                cw = cx[e - 1];
+                cn = cy[e];
+                cs = cy[e - X];
+                ct = cz[e];
+                if (MODE == S_RESID) {
+                    dv = dinv[e];
+                    bv = bvec[e];
+                }
+            }
+            if ((int)threadIdx.x < HALO3 && hin) hv = stencil_value<MODE>((size_t)k * PL + hoff, va, vb, beta, first);
+            s[ty + 1][tx + 1] = cur;
+            if ((int)threadIdx.x < HALO3) s[hy][hx] = hin ? hv : 0.0;
+            __syncthreads();
+            if (own) {
+                const double av = ce * (cur - s[ty + 1][tx + 2]) + cw * (cur - s[ty + 1][tx]) +
+                                  cn * (cur - s[ty + 2][tx + 1]) + cs * (cur - s[ty][tx + 1]) + ct * (cur - nxt) +
+                                  czb * (cur - prev);
+                if (MODE == S_APPLY) {
+                    out1[e] = av;
+                } else if (MODE == S_RESID) {
+                    const double bb = dv > 0.0 ? bv - mean : 0.0;
+                    const double r = dv > 0.0 ? bb - av : 0.0;
+                    const double z = dv * r;
+                    out1[e] = r;
+                    out2[e] = z;
+                    bvec[e] = bb;
+                    acc[0] += r * z;
+                    acc[1] += r * r;
+                    acc[2] += bb * bb;
+                } else {
+                    out1[e] = cur;
+                    out2[e] = av;
+                    acc[0] += cur * av;
+                }
+            }
+            czb = ct;
+            __syncthreads();
+            prev = cur;
+            cur = nxt;
+        }
+    }
+    if (MODE == S_RESID) {
+        double v[3] = {acc[0], acc[1], acc[2]};
+        put_partials<3>(v, part, gridDim.x);
+    } else if (MODE == S_DIR) {
+        double v[1] = {acc[0]};
+        put_partials<1>(v, part, gridDim.x);
+    }
+}
+
+// x += alpha p, r -= alpha q, z = r / diag over every element (the masks
+// keep the entries off the unknowns at zero); partials (r.z, r.r).
+__global__ __launch_bounds__(NT) void k3_update(Dims3 d, const double *__restrict__ dinv, const double *__restrict__ p,
+                                                const double *__restrict__ q, double *__restrict__ x,
+                                                double *__restrict__ r, double *__restrict__ z, Cg3 *st, int it,
+                                                const double *pin, int nin, double *part) {
+    if (st->stop_it <= it) return;
+    double t[1];
+    get_totals<1>(pin, nin, t);
+    const double pq = t[0];
+    if (!(pq > 0.0 && pq < INFINITY)) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            st->status = CCNS_EBREAKDOWN;
+            st->it_final = it;
+            st->stop_it = it;
+        }
+        return;
+    }
+    const double alpha = st->rz[it & 1] / pq;
+    double v[2] = {0.0, 0.0};
+    const size_t stride = (size_t)gridDim.x * NT;
+    for (size_t e = (size_t)blockIdx.x * NT + threadIdx.x; e < d.n; e += stride) {
+        const double dv = dinv[e], pe = p[e], qe = q[e];
+        const double xe = x[e], re = r[e];
+        x[e] = fma(alpha, pe, xe);
+        const double rn = fma(-alpha, qe, re);
+        const double zn = dv * rn;
+        r[e] = rn;
+        z[e] = zn;
+        v[0] += rn * zn;
+        v[1] += rn * rn;
+    }
+    put_partials<2>(v, part, gridDim.x);
+}
+
+// b = -(rho/tau) cont(U*, 0) on the pressure unknowns (eq:divergence with
+// D = 0; A is zero off the velocity unknowns, so U* is masked there);
+// partial sum of b.
+__global__ __launch_bounds__(NT) void k3_rhs(Dims3 d, const double *__restrict__ ax, const double *__restrict__ ay,
+                                             const double *__restrict__ az, const double *__restrict__ ux,
+                                             const double *__restrict__ uy, const double *__restrict__ uz,
+                                             const double *__restrict__ dinv, double scale, double *__restrict__ b,
+                                             double *part) {
+    double v[1] = {0.0};
+    const size_t stride = (size_t)gridDim.x * NT, X = d.pitch, PL = d.plane;
+    for (size_t e = (size_t)blockIdx.x * NT + threadIdx.x; e < d.n; e += stride) {
+        double be = 0.0;
+        if (dinv[e] > 0.0) {
+            const double div = (ax[e] * ux[e] - ax[e - 1] * ux[e - 1]) + (ay[e] * uy[e] - ay[e - X] * uy[e - X]) +
+                               (az[e] * uz[e] - az[e - PL] * uz[e - PL]);
+            be = -scale * div;
+        }
+        b[e] = be;
+        v[0] += be;
+    }
+    put_partials<1>(v, part, gridDim.x);
+}
+
+// Partial sums of x over the pressure unknowns.
+__global__ __launch_bounds__(NT) void k3_sum(Dims3 d, const double *__restrict__ dinv, const double *__restrict__ x,
+                                             double *part) {
+    double v[1] = {0.0};
+    const size_t stride = (size_t)gridDim.x * NT;
+    for (size_t e = (size_t)blockIdx.x * NT + threadIdx.x; e < d.n; e += stride)
+        if (dinv[e] > 0.0) v[0] += x[e];
+    put_partials<1>(v, part, gridDim.x);
+}
+
+// eq:pm_projection: U = U* - (tau/rho) (A/M) (Phi_nb - Phi_c) on the faces
+// with c > 0 (g = A/M there), U* on the other unknowns (a = A > 0), 0 on
+// every other face; the three faces on the high sides of each element.
+__global__ __launch_bounds__(NT) void k3_correct(Dims3 d, const double *__restrict__ gx, const double *__restrict__ gy,
+                                                 const double *__restrict__ gz, const double *__restrict__ ax,
+                                                 const double *__restrict__ ay, const double *__restrict__ az,
+                                                 const double *__restrict__ x, double tr, double *__restrict__ ux,
+                                                 double *__restrict__ uy, double *__restrict__ uz) {
+    const size_t stride = (size_t)gridDim.x * NT, X = d.pitch, PL = d.plane;
+    // g > 0 only on faces between two real cells, so the neighbour reads stay
+    // in the field
+    for (size_t e = (size_t)blockIdx.x * NT + threadIdx.x; e < d.n; e += stride) {
+        const double xc = x[e];
+        const double g0 = gx[e], g1 = gy[e], g2 = gz[e];
+        const double u0 = ux[e], u1 = uy[e], u2 = uz[e];
+        const double a0 = ax[e], a1 = ay[e], a2 = az[e];
+        ux[e] = g0 > 0.0 ? u0 - tr * g0 * (x[e + 1] - xc) : (a0 > 0.0 ? u0 : 0.0);
+        uy[e] = g1 > 0.0 ? u1 - tr * g1 * (x[e + X] - xc) : (a1 > 0.0 ? u1 : 0.0);
+        uz[e] = g2 > 0.0 ? u2 - tr * g2 * (x[e + PL] - xc) : (a2 > 0.0 ? u2 : 0.0);
+    }
+}
+
+// x -= mean(x) on the pressure unknowns (the zero-mean solution), and the
+// divergence figures of the corrected velocity: partial maxima of
+// |cont(U, 0)| over the unknowns and of the face fluxes |A U|.
+__global__ __launch_bounds__(NT) void k3_div_shift(Dims3 d, const double *__restrict__ ax, const double *__restrict__ ay,
+                                                   const double *__restrict__ az, const double *__restrict__ ux,
+                                                   const double *__restrict__ uy, const double *__restrict__ uz,
+                                                   const double *__restrict__ dinv, double *__restrict__ x,
+                                                   const double *pin, int nin, int n_active, double *part) {
+    double t[1];
+    get_totals<1>(pin, nin, t);
+    const double mean = n_active > 0 ? t[0] / n_active : 0.0;
+    double v[2] = {0.0, 0.0};
+    const size_t stride = (size_t)gridDim.x * NT, X = d.pitch, PL = d.plane;
+    for (size_t e = (size_t)blockIdx.x * NT + threadIdx.x; e < d.n; e += stride) {
+        if (dinv[e] > 0.0) {
+            const double f0 = ax[e] * ux[e], f1 = ay[e] * uy[e], f2 = az[e] * uz[e];
+            const double div = (f0 - ax[e - 1] * ux[e - 1]) + (f1 - ay[e - X] * uy[e - X]) + (f2 - az[e - PL] * uz[e - PL]);
+            v[0] = fmax(v[0], fabs(div));
+            x[e] = x[e] - mean;
+        }
+        if (e + PL < d.n)
+            v[1] = fmax(v[1], fmax(fabs(ax[e] * ux[e]), fmax(fabs(ay[e] * uy[e]), fabs(az[e] * uz[e]))));
+    }
+    put_partials<0, 2>(v, part, gridDim.x);
+}
+
+__global__ void k3_zero(size_t n, double *a) {
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) a[e] = 0.0;
+}
+
+// Workspace fields.
+enum { W_X, W_R, W_Z, W_P0, W_P1, W_Q, W_B, W_DINV, W_CX, W_CY, W_CZ, W_GX, W_GY, W_GZ, W_AX, W_AY, W_AZ, W_UX,
+       W_UY, W_UZ, W_COUNT };
+// Partial-sum buffers (NB3 groups each): residual (3), direction (1),
+// update (2), right-hand side and sums (1), divergence (2).
+constexpr int PART_DOUBLES = NB3 * (3 + 1 + 2 + 1 + 1 + 2);
+
+Dims3 make_dims(const ccns3_grid &g) {
+    Dims3 d{};
+    d.nx = g.nx;
+    d.ny = g.ny;
+    d.nz = g.nz;
+    d.pitch = (g.nx + 2 + 15) / 16 * 16;
+    d.plane = (size_t)(g.ny + 2) * d.pitch;
+    d.n = d.plane * (g.nz + 2);
+    d.gxt = (g.nx + T3X - 1) / T3X;
+    d.gyt = (g.ny + T3Y - 1) / T3Y;
+    d.gzt = (g.nz + T3Z - 1) / T3Z;
+    d.ntile = d.gxt * d.gyt * d.gzt;
+    int nb = std::min(d.ntile, NB3);
+    nb = (nb + 7) / 8 * 8;
+    d.tpb = (d.ntile + nb - 1) / nb;
+    d.nblk = nb;
+    size_t f = (d.n + (size_t)NT * 4 - 1) / ((size_t)NT * 4);
+    f = std::min<size_t>(std::max<size_t>(f, 8), NB3);
+    d.nflat = (int)((f + 7) / 8 * 8);
+    return d;
+}
+
+size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+
+}  // namespace
+}  // namespace ccns
+
+using namespace ccns;
+
+struct ccns3_ctx {
+    ccns3_grid g{};
+    ccns3_params p{};
+    Dims3 d{};
+    hipStream_t stream = nullptr;
+    double *w[W_COUNT] = {};
+    double *part = nullptr;
+    Cg3 *st = nullptr;
+    Cg3 *h_st = nullptr;       // pinned
+    double *h_part = nullptr;  // pinned, the divergence partials
+    int n_active = 0;
+    std::string err;
+    // optional timing of the CG kernels: an event pair around each launch of
+    // a chunk, direction (0) and update (1) kernels
+    bool timing = false;
+    hipEvent_t ev[2][64][2] = {};
+    double t_ms[2] = {0.0, 0.0};
+    long t_count[2] = {0, 0};
+};
+
+namespace {
+
+ccns_status fail3(ccns3_ctx *c, ccns_status s, const std::string &m) {
+    if (c) c->err = m;
+    return s;
+}
+
+#define HIP3(ctx, call)                                                                      \
+    do {                                                                                     \
+        hipError_t e_ = (call);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return fail3(ctx, CCNS_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+double *part_at(ccns3_ctx *c, int which) {
+    // 0 residual (3), 1 direction (1), 2 update (2), 3 rhs/sums (1), 4 divergence (2)
+    static const int off[5] = {0, 3, 4, 6, 7};
+    return c->part + (size_t)off[which] * NB3;
+}
+
+ccns_status upload(ccns3_ctx *c, double *dst, const double *src, hipMemcpyKind kind) {
+    const size_t W = c->g.nx + 2, rows = (size_t)(c->g.ny + 2) * (c->g.nz + 2);
+    HIP3(c, hipMemcpy2DAsync(dst, c->d.pitch * sizeof(double), src, W * sizeof(double), W * sizeof(double), rows, kind,
+                             c->stream));
+    return CCNS_OK;
+}
+ccns_status download(ccns3_ctx *c, double *dst, const double *src, hipMemcpyKind kind) {
+    const size_t W = c->g.nx + 2, rows = (size_t)(c->g.ny + 2) * (c->g.nz + 2);
+    HIP3(c, hipMemcpy2DAsync(dst, W * sizeof(double), src, c->d.pitch * sizeof(double), W * sizeof(double), rows, kind,
+                             c->stream));
+    return CCNS_OK;
+}
+
+bool params_ok(const ccns3_params *p) {
+    return p && p->rho > 0.0 && std::isfinite(p->rho) && p->tau > 0.0 && std::isfinite(p->tau) && p->tol >= 0.0 &&
+           std::isfinite(p->tol) && p->maxit >= 0 && p->mass_floor >= 0.0 && p->mass_floor <= 1.0;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t ccns3_workspace_bytes(const ccns3_grid *g) {
+    if (!grid3_valid(g)) return 0;
+    const Dims3 d = make_dims(*g);
+    return (size_t)W_COUNT * align256(d.n * sizeof(double)) + align256(PART_DOUBLES * sizeof(double)) +
+           align256(sizeof(Cg3));
+}
+
+ccns_status ccns3_ctx_create(const ccns3_grid *grid, const ccns3_params *params, const double *caps_host,
+                             void *workspace, size_t workspace_bytes, void *stream, ccns3_ctx **out) {
+    if (!out || !grid3_valid(grid) || !params_ok(params) || !caps_host || !workspace) return CCNS_EINVAL;
+    *out = nullptr;
+    if (((uintptr_t)workspace & 255) != 0) return CCNS_EINVAL;
+    if (workspace_bytes < ccns3_workspace_bytes(grid)) return CCNS_ENOMEM;
+    ccns3_ctx *c = new (std::nothrow) ccns3_ctx;
+    if (!c) return CCNS_ENOMEM;
+    c->g = *grid;
+    c->p = *params;
+    c->d = make_dims(*grid);
+    c->stream = (hipStream_t)stream;
+    HostCoef3 hc;
+    std::string err;
+    ccns_status s = prepare3(*grid, *params, caps_host, hc, err);
+    if (s != CCNS_OK) {
+        delete c;
+        return s;
+    }
+    c->n_active = hc.n_active;
+    char *base = (char *)workspace;
+    const size_t fb = align256(c->d.n * sizeof(double));
+    for (int k = 0; k < W_COUNT; ++k) c->w[k] = (double *)(base + (size_t)k * fb);
+    c->part = (double *)(base + (size_t)W_COUNT * fb);
+    c->st = (Cg3 *)(base + (size_t)W_COUNT * fb + align256(PART_DOUBLES * sizeof(double)));
+    if (hipHostMalloc((void **)&c->h_st, sizeof(Cg3)) != hipSuccess ||
+        hipHostMalloc((void **)&c->h_part, 2 * NB3 * sizeof(double)) != hipSuccess) {
+        ccns3_ctx_destroy(c);
+        return CCNS_EDEVICE;
+    }
+    const size_t total = ccns3_workspace_bytes(grid) / sizeof(double);
+    k3_zero<<<1024, NT, 0, c->stream>>>(total, (double *)workspace);
+    const std::vector<double> *src[] = {&hc.dinv, &hc.c[0], &hc.c[1], &hc.c[2], &hc.g[0],
+                                        &hc.g[1], &hc.g[2], &hc.a[0], &hc.a[1], &hc.a[2]};
+    const int dst[] = {W_DINV, W_CX, W_CY, W_CZ, W_GX, W_GY, W_GZ, W_AX, W_AY, W_AZ};
+    for (int k = 0; k < 10; ++k)
+        if ((s = upload(c, c->w[dst[k]], src[k]->data(), hipMemcpyHostToDevice)) != CCNS_OK) {
+            (void)hipStreamSynchronize(c->stream);
+            ccns3_ctx_destroy(c);
+            return s;
+        }
+    if (hipStreamSynchronize(c->stream) != hipSuccess || hipGetLastError() != hipSuccess) {
+        ccns3_ctx_destroy(c);
+        return CCNS_EDEVICE;
+    }
+    *out = c;
+    return CCNS_OK;
+}
+
+static void free_events(ccns3_ctx *c) {
+    for (auto &kk : c->ev)
+        for (auto &k : kk)
+            for (auto &e : k)
+                if (e) {
+                    (void)hipEventDestroy(e);
+                    e = nullptr;
+                }
+}
+
+void ccns3_ctx_destroy(ccns3_ctx *c) {
+    if (!c) return;
+    (void)hipStreamSynchronize(c->stream);
+    free_events(c);
+    if (c->h_st) (void)hipHostFree(c->h_st);
+    if (c->h_part) (void)hipHostFree(c->h_part);
+    delete c;
+}
+
+static const int kField3[CCNS3_NFIELDS] = {W_UX, W_UY, W_UZ, W_X};
+
+ccns_status ccns3_field_set(ccns3_ctx *c, int field, const double *src, int is_device) {
+    if (!c || !src || field < 0 || field >= CCNS3_NFIELDS) return fail3(c, CCNS_EINVAL, "bad field");
+    ccns_status s = upload(c, c->w[kField3[field]], src, is_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice);
+    if (s != CCNS_OK) return s;
+    HIP3(c, hipStreamSynchronize(c->stream));
+    return CCNS_OK;
+}
+
+ccns_status ccns3_field_get(ccns3_ctx *c, int field, double *dst, int is_device) {
+    if (!c || !dst || field < 0 || field >= CCNS3_NFIELDS) return fail3(c, CCNS_EINVAL, "bad field");
+    ccns_status s = download(c, dst, c->w[kField3[field]], is_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost);
+    if (s != CCNS_OK) return s;
+    HIP3(c, hipStreamSynchronize(c->stream));
+    return CCNS_OK;
+}
+
+ccns_status ccns3_apply_poisson(ccns3_ctx *c, const double *in_dev, double *out_dev) {
+    if (!c || !in_dev || !out_dev) return fail3(c, CCNS_EINVAL, "null argument");
+    ccns_status s = upload(c, c->w[W_R], in_dev, hipMemcpyDeviceToDevice);
+    if (s != CCNS_OK) return s;
+    const Dims3 &d = c->d;
+    double **w = c->w;
+    k3_stencil<S_APPLY><<<d.nblk, NT, 0, c->stream>>>(d, w[W_CX], w[W_CY], w[W_CZ], w[W_DINV], w[W_R], nullptr,
+                                                       w[W_Q], nullptr, nullptr, c->st, 0, nullptr, 0, 0, nullptr);
+    HIP3(c, hipGetLastError());
+    if ((s = download(c, out_dev, w[W_Q], hipMemcpyDeviceToDevice)) != CCNS_OK) return s;
+    HIP3(c, hipStreamSynchronize(c->stream));
+    return CCNS_OK;
+}
+
+ccns_status ccns3_project(ccns3_ctx *c, ccns3_info *info) {
+    if (!c) return CCNS_EINVAL;
+    const Dims3 &d = c->d;
+    double **w = c->w;
+    hipStream_t sm = c->stream;
+    double *pr = part_at(c, 0), *pd = part_at(c, 1), *pu = part_at(c, 2), *ps = part_at(c, 3), *pv = part_at(c, 4);
+    // solver state
+    Cg3 h{};
+    h.tol2 = c->p.tol * c->p.tol;
+    h.stop_it = INT_MAX;
+    h.maxit = c->p.maxit;
+    h.status = CCNS_ENOTCONV;
+    *c->h_st = h;
+    HIP3(c, hipMemcpyAsync(c->st, c->h_st, sizeof(Cg3), hipMemcpyHostToDevice, sm));
+    // b = -(rho/tau) cont(U*, 0); r = b - mean - (-L) x; z = r / diag
+    k3_rhs<<<d.nflat, NT, 0, sm>>>(d, w[W_AX], w[W_AY], w[W_AZ], w[W_UX], w[W_UY], w[W_UZ], w[W_DINV],
+                                   c->p.rho / c->p.tau, w[W_B], ps);
+    k3_stencil<S_RESID><<<d.nblk, NT, 0, sm>>>(d, w[W_CX], w[W_CY], w[W_CZ], w[W_DINV], w[W_X], nullptr, w[W_R],
+                                               w[W_Z], w[W_B], c->st, 0, ps, d.nflat, c->n_active, pr);
+    HIP3(c, hipGetLastError());
+    int it = 0, chunk = 8;
+    for (;;) {
+        const int it0 = it;
+        for (int k = 0; k < chunk; ++k, ++it) {
+            double *pnew = w[(it & 1) ? W_P1 : W_P0], *pold = w[(it & 1) ? W_P0 : W_P1];
+            if (c->timing) HIP3(c, hipEventRecord(c->ev[0][k][0], sm));
+            k3_stencil<S_DIR><<<d.nblk, NT, 0, sm>>>(d, w[W_CX], w[W_CY], w[W_CZ], w[W_DINV], w[W_Z], pold, pnew,
+                                                     w[W_Q], nullptr, c->st, it, it == 0 ? pr : pu,
+                                                     it == 0 ? d.nblk : d.nflat, c->n_active, pd);
+            if (c->timing) {
+                HIP3(c, hipEventRecord(c->ev[0][k][1], sm));
+                HIP3(c, hipEventRecord(c->ev[1][k][0], sm));
+            }
+            k3_update<<<d.nflat, NT, 0, sm>>>(d, w[W_DINV], pnew, w[W_Q], w[W_X], w[W_R], w[W_Z], c->st, it, pd,
+                                              d.nblk, pu);
+            if (c->timing) HIP3(c, hipEventRecord(c->ev[1][k][1], sm));
+        }
+        HIP3(c, hipGetLastError());
+        HIP3(c, hipMemcpyAsync(c->h_st, c->st, sizeof(Cg3), hipMemcpyDeviceToHost, sm));
+        HIP3(c, hipStreamSynchronize(sm));
+        if (c->timing) {
+            // launches that did the iteration's work (those at and after the
+            // stopping iteration return at once)
+            const int stop = c->h_st->stop_it;
+            for (int k = 0; k < chunk && it0 + k < stop; ++k)
+                for (int q = 0; q < 2; ++q) {
+                    float ms = 0.0f;
+                    HIP3(c, hipEventElapsedTime(&ms, c->ev[q][k][0], c->ev[q][k][1]));
+                    c->t_ms[q] += ms;
+                    ++c->t_count[q];
+                }
+        }
+        if (c->h_st->stop_it != INT_MAX || it > c->p.maxit + 1) break;
+        chunk = std::min(chunk * 2, 64);
+    }
+    // the correction (the mean of Phi cancels in its differences), then Phi
+    // minus its mean and the divergence figures
+    k3_sum<<<d.nflat, NT, 0, sm>>>(d, w[W_DINV], w[W_X], ps);
+    k3_correct<<<d.nflat, NT, 0, sm>>>(d, w[W_GX], w[W_GY], w[W_GZ], w[W_AX], w[W_AY], w[W_AZ], w[W_X],
+                                       c->p.tau / c->p.rho, w[W_UX], w[W_UY], w[W_UZ]);
+    k3_div_shift<<<d.nflat, NT, 0, sm>>>(d, w[W_AX], w[W_AY], w[W_AZ], w[W_UX], w[W_UY], w[W_UZ], w[W_DINV],
+                                         w[W_X], ps, d.nflat, c->n_active, pv);
+    HIP3(c, hipGetLastError());
+    HIP3(c, hipMemcpyAsync(c->h_part, pv, 2 * (size_t)d.nflat * sizeof(double), hipMemcpyDeviceToHost, sm));
+    HIP3(c, hipMemcpyAsync(c->h_st, c->st, sizeof(Cg3), hipMemcpyDeviceToHost, sm));
+    HIP3(c, hipStreamSynchronize(sm));
+    double dmax = 0.0, fmax_ = 0.0;
+    for (int b = 0; b < d.nflat; ++b) {
+        dmax = std::max(dmax, c->h_part[b]);
+        fmax_ = std::max(fmax_, c->h_part[d.nflat + b]);
+    }
+    const Cg3 &r = *c->h_st;
+    const ccns_status status = r.stop_it == INT_MAX ? CCNS_ENOTCONV : (ccns_status)r.status;
+    if (info) {
+        info->iterations = r.stop_it == INT_MAX ? it : r.it_final;
+        info->status = status;
+        info->rel_residual = r.bb > 0.0 ? std::sqrt(std::max(r.rr_final, 0.0) / r.bb) : 0.0;
+        info->div_rel = fmax_ > 0.0 ? dmax / fmax_ : 0.0;
+        info->n_active = c->n_active;
+    }
+    if (status != CCNS_OK) return fail3(c, status, "Poisson solve did not converge");
+    return CCNS_OK;
+}
+
+ccns_status ccns3_timing(ccns3_ctx *c, int enable, double *ms, long *count) {
+    if (!c || enable < -1 || enable > 1) return fail3(c, CCNS_EINVAL, "bad argument");
+    for (int q = 0; q < 2; ++q) {
+        if (ms) ms[q] = c->t_ms[q];
+        if (count) count[q] = c->t_count[q];
+    }
+    if (enable >= 0) {
+        c->t_ms[0] = c->t_ms[1] = 0.0;
+        c->t_count[0] = c->t_count[1] = 0;
+    }
+    if (enable == 1 && !c->timing) {
+        for (auto &kk : c->ev)
+            for (auto &k : kk)
+                for (auto &e : k)
+                    if (hipEventCreate(&e) != hipSuccess) {
+                        free_events(c);
+                        return fail3(c, CCNS_EDEVICE, "hipEventCreate");
+                    }
+        c->timing = true;
+    } else if (enable == 0 && c->timing) {
+        (void)hipStreamSynchronize(c->stream);
+        free_events(c);
+        c->timing = false;
+    }
+    return CCNS_OK;
+}
+
+const char *ccns3_last_error(const ccns3_ctx *c) { return c ? c->err.c_str() : "null context"; }
+
+}  // extern "C"

@@ -1,0 +1,190 @@
+"""The three-dimensional projection on the device against the oracle.
+
+The device runs on the library's capacities and the oracle on its own (the
+two agree to 1e-13 of a full cell, tests/test_library_3d_cpu.py); each case
+compares the Poisson operator element by element and the projection's Phi
+and U with the oracle's solution, on grids that span several tiles with
+ragged ends in every direction, a grid smaller than one tile, a single
+layer of cells, both readings of the mass matrix, and at the benchmark's
+full size on sampled cells and faces computed one by one."""
+
+import math
+
+import numpy as np
+import pytest
+
+import workloads.three_d as T
+from oracle import geometry3d as G3, pmii3d as P3
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+_ORACLE = {}
+
+
+def _oracle_caps(case):
+    key = (case.name, case.grid)
+    if key not in _ORACLE:
+        _ORACLE[key] = G3.capacities(case.grid, case.bodies)
+    return _ORACLE[key]
+
+
+def _context(case, tol=1e-12):
+    from paper_2211_10698_amd import ccns3d
+    caps = ccns3d.capacities(case.grid, case.bodies)
+    prm = ccns3d.make_params(case.rho, case.tau, tol=tol, mass_floor=case.mass_floor)
+    return ccns3d.Context3(case.grid, prm, caps)
+
+
+def _cases():
+    return [
+        ("tiny_7x5x6", T.tiny_box),
+        ("one_layer_70x20x1", lambda: T.Case3("one_layer", T.Grid3(70, 20, 1, 0.0, 0.0, 0.0, 1.0, 20 / 70, 1 / 70),
+                                               [T.Body3(T.ZCYLINDER, 0.43, 0.15, 0.0, 0.09)], tau=0.25 / 70, seed=36)),
+        ("two_spheres_70x20x36", lambda: T.two_spheres(70, 20, 36)),
+        ("two_spheres_70x20x36_theta0", lambda: T.two_spheres(70, 20, 36, mass_floor=0.0)),
+        ("sphere_24", lambda: T.sphere_box(24)),
+    ]
+
+
+@pytest.mark.parametrize("name,make", _cases(), ids=[c[0] for c in _cases()])
+def test_poisson_operator_matches_the_oracle(name, make):
+    case = make()
+    print(f"[3d] operator {name}", flush=True)
+    ctx = _context(case)
+    pr = P3.prepare(_oracle_caps(case), case.grid, case.mass_floor)
+    x = T.random_cells(case, 41)
+    got = ctx.apply_poisson(x).cpu().numpy()
+    ref = -P3.laplacian(pr, x)
+    assert np.abs(got - ref).max() <= 1e-11 * np.abs(ref).max()
+    # the same pressure unknowns: zero rows exactly where the oracle has none
+    assert np.array_equal(np.abs(got) > 0, np.abs(ref) > 0) or np.abs(got[~pr.act_p]).max() == 0.0
+    ctx.close()
+
+
+@pytest.mark.parametrize("name,make", _cases(), ids=[c[0] for c in _cases()])
+def test_projection_matches_the_oracle(name, make):
+    from paper_2211_10698_amd import ccns3d
+    case = make()
+    print(f"[3d] projection {name}", flush=True)
+    g = case.grid
+    ctx = _context(case)
+    U = T.face_velocity(case)
+    for f, u in zip((ccns3d.F_UX, ccns3d.F_UY, ccns3d.F_UZ), U):
+        ctx.set_field(f, u)
+    info = ctx.project()
+    pr = P3.prepare(_oracle_caps(case), g, case.mass_floor)
+    solver = "direct" if pr.n_active < 5000 else "pcg"
+    phi, Un, oinfo = P3.project(pr, U, case.rho, case.tau, solver=solver, tol=1e-13)
+    assert info.status == ccns3d.OK and info.n_active == pr.n_active
+    assert info.div_rel < 1e-10 and info.rel_residual <= 1e-12
+    dphi = ctx.get_field(ccns3d.F_PHI).cpu().numpy()
+    assert np.abs(dphi - phi).max() <= 1e-8 * np.abs(phi).max()
+    assert abs(dphi[pr.act_p].sum()) <= 1e-10 * np.abs(phi).max() * pr.n_active
+    umax = max(np.abs(u).max() for u in Un)
+    for f, u in zip((ccns3d.F_UX, ccns3d.F_UY, ccns3d.F_UZ), Un):
+        assert np.abs(ctx.get_field(f).cpu().numpy() - u).max() <= 1e-8 * umax
+    # projecting again changes nothing
+    info2 = ctx.project()
+    assert np.abs(ctx.get_field(ccns3d.F_PHI).cpu().numpy()).max() <= 1e-8 * np.abs(phi).max()
+    assert info2.div_rel < 1e-10
+    ctx.close()
+
+
+def test_projection_is_reproducible_bit_for_bit():
+    from paper_2211_10698_amd import ccns3d
+    case = T.two_spheres(70, 20, 36)
+    U = T.face_velocity(case)
+    out = []
+    for _ in range(2):
+        ctx = _context(case)
+        for f, u in zip((ccns3d.F_UX, ccns3d.F_UY, ccns3d.F_UZ), U):
+            ctx.set_field(f, u)
+        info = ctx.project()
+        out.append((info.iterations, [ctx.get_field(f).cpu().numpy() for f in range(4)]))
+        ctx.close()
+    assert out[0][0] == out[1][0]
+    for a, b in zip(out[0][1], out[1][1]):
+        assert np.array_equal(a, b)
+
+
+def _local_faces(case, i, j, k):
+    """The oracle's capacities on the 3 x 3 x 3 window of cells around cell
+    (i, j, k) of the case's grid (the window keeps the grid's spacing and
+    cell positions): its six faces' areas and control volumes."""
+    g = case.grid
+    w = T.Grid3(3, 3, 3, g.x0 + (i - 2) * g.hx, g.y0 + (j - 2) * g.hy, g.z0 + (k - 2) * g.hz, 3 * g.hx, 3 * g.hy,
+                3 * g.hz)
+    c = G3.capacities(w, case.bodies)
+    # in the window the cell is (2, 2, 2); its low faces are index 1, high 2
+    faces = []
+    for a, (A, V) in enumerate((("Ax", "Vx"), ("Ay", "Vy"), ("Az", "Vz"))):
+        for lo in (True, False):
+            idx = [2, 2, 2]
+            idx[a] = 1 if lo else 2
+            kk, jj, ii = idx[2], idx[1], idx[0]
+            faces.append((a, lo, c[A][kk, jj, ii], c[V][kk, jj, ii]))
+    return c["V"][2, 2, 2], faces
+
+
+def test_full_size_sphere_256_on_sampled_cells():
+    """256^3 cells: the Poisson operator at sampled cells and the corrected
+    velocity at their faces, each computed by the oracle one cell at a time
+    from its own capacities on a window around the cell; the whole
+    projection's divergence and zero-mean figures."""
+    from paper_2211_10698_amd import ccns3d
+    case = T.sphere_box_256()
+    g = case.grid
+    print("[3d] full size 256^3: set-up", flush=True)
+    ctx = _context(case)
+    x = T.random_cells(case, 43)
+    ax = ctx.apply_poisson(x).cpu().numpy()
+    U = T.face_velocity(case)
+    for f, u in zip((ccns3d.F_UX, ccns3d.F_UY, ccns3d.F_UZ), U):
+        ctx.set_field(f, u)
+    print("[3d] full size 256^3: projection", flush=True)
+    info = ctx.project()
+    assert info.status == ccns3d.OK and info.div_rel < 1e-10 and info.rel_residual <= 1e-12
+    phi = ctx.get_field(ccns3d.F_PHI).cpu().numpy()
+    Ud = [ctx.get_field(f).cpu().numpy() for f in (ccns3d.F_UX, ccns3d.F_UY, ccns3d.F_UZ)]
+    ctx.close()
+    floor = case.mass_floor * g.hx * g.hy * g.hz
+    # sampled cells near the sphere (cut cells and their neighbours) and away
+    # from it
+    rng = np.random.default_rng(44)
+    b = case.bodies[0]
+    samples = T.sample_cells(case, 12, 45)
+    while len(samples) < 40:
+        th, ph = rng.uniform(0, math.pi), rng.uniform(0, 2 * math.pi)
+        rr = b.r + rng.uniform(-1.5, 1.5) * g.hx
+        px, py, pz = b.cx + rr * math.sin(th) * math.cos(ph), b.cy + rr * math.sin(th) * math.sin(ph), b.cz + rr * math.cos(th)
+        samples.append((int(px / g.hx) + 1, int(py / g.hy) + 1, int(pz / g.hz) + 1))
+    checked = 0
+    for (i, j, k) in samples:
+        if not (2 <= i <= g.nx - 1 and 2 <= j <= g.ny - 1 and 2 <= k <= g.nz - 1):
+            continue
+        V, faces = _local_faces(case, i, j, k)
+        if not V > 0.0:
+            assert ax[k, j, i] == 0.0
+            continue
+        lap = 0.0
+        for a, lo, A, Vf in faces:
+            if not (A > 0.0 and Vf > 0.0):
+                continue
+            d = [0, 0, 0]
+            d[a] = -1 if lo else 1
+            nb = (k + d[2], j + d[1], i + d[0])
+            lap += A * A / max(Vf, floor) * (x[k, j, i] - x[nb])
+            # the corrected velocity of this face
+            fk, fj, fi = (k, j, i) if not lo else (k - (a == 2), j - (a == 1), i - (a == 0))
+            if phi[k, j, i] != 0.0 and phi[nb] != 0.0:
+                hi_c, lo_c = (nb, (k, j, i)) if not lo else ((k, j, i), nb)
+                ref = U[a][fk, fj, fi] - (case.tau / case.rho) * A / max(Vf, floor) * (phi[hi_c] - phi[lo_c])
+                assert abs(Ud[a][fk, fj, fi] - ref) <= 1e-10 * max(1.0, abs(ref)), (i, j, k, a, lo)
+        if ax[k, j, i] != 0.0 or lap != 0.0:
+            assert abs(ax[k, j, i] - lap) <= 1e-11 * max(abs(lap), 1e-300) + 1e-13, (i, j, k)
+        checked += 1
+    assert checked >= 30
+    act = phi != 0.0
+    assert abs(phi[act].sum()) <= 1e-9 * np.abs(phi).max() * act.sum()

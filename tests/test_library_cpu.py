@@ -15,8 +15,12 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def _declared():
-    txt = open(os.path.join(ROOT, "include", "ccns.h")).read()
-    return sorted(set(re.findall(r"\b(ccns_[a-z_]+)\s*\(", txt)))
+    names = set()
+    for h in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if h.endswith(".h"):
+            txt = open(os.path.join(ROOT, "include", h)).read()
+            names |= set(re.findall(r"\b(ccns3?_[a-z_]+)\s*\(", txt))
+    return sorted(names)
 
 
 def test_library_exports_every_declared_symbol():
@@ -27,6 +31,8 @@ def test_library_exports_every_declared_symbol():
     for n in names:
         assert hasattr(L, n), n
     assert set(ccns.EXPORTED) <= set(names)
+    from paper_2211_10698_amd import ccns3d
+    assert set(ccns3d.EXPORTED) <= set(names) and all(hasattr(ccns3d.lib(), n) for n in ccns3d.EXPORTED)
 
 
 def test_argument_validation_without_gpu():
