@@ -133,7 +133,10 @@ ccns_status ccns3_field_get(ccns3_ctx *ctx, int field, double *dst, int is_devic
  * on the faces with c_f > 0, U* on the other unknowns and 0 on every other
  * face.  info (may be NULL) receives the solve's figures.  Returns the
  * solve's status (CCNS_ENOTCONV or CCNS_EBREAKDOWN leave the last iterate in
- * PHI and its projection in U). */
+ * PHI and its projection in U).  The tolerance is relative to ||b||: a field
+ * that is already divergence-free has b at rounding level, which a solve
+ * started from a nonzero PHI cannot reach relative to itself, so such a
+ * projection starts from PHI = 0. */
 ccns_status ccns3_project(ccns3_ctx *ctx, ccns3_info *info);
 
 /* out = -L in on the cells (device arrays, dense layout): sum over the six
