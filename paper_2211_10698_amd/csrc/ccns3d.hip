@@ -39,7 +39,7 @@ namespace {
 constexpr int T3X = 64;     // tile columns in x (one wavefront)
 constexpr int T3Y = 4;      // tile rows in y (the four wavefronts of a group)
 constexpr int T3Z = 32;     // cells per column of a tile, marched in z
-constexpr int NB3 = 1024;   // at most this many work-groups per kernel
+constexpr int NB3 = 4096;   // at most this many work-groups per kernel
 constexpr int HALO3 = 2 * (T3X + 2) + 2 * T3Y;  // halo cells of one plane of a tile
 
 // Solver state in device memory.  stop_it: the iteration whose direction
@@ -126,13 +126,17 @@ __global__ __launch_bounds__(NT) void k3_stencil(Dims3 d, const double *__restri
         get_totals<1>(pin, nin, t);
         mean = n_active > 0 ? t[0] / n_active : 0.0;
     }
-    __shared__ double s[T3Y + 2][T3X + 2];
+    // two plane buffers, alternating: one barrier per plane suffices (a
+    // buffer is written again only after the barrier of the next plane,
+    // which every reader of its last contents has passed)
+    __shared__ double s2[2][T3Y + 2][T3X + 2];
     const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
     const int X = d.pitch;
     const size_t PL = d.plane;
     double acc[3] = {0.0, 0.0, 0.0};
     const int L = logical_group(d.nblk);
     const int t0 = L * d.tpb, t1 = min(t0 + d.tpb, d.ntile);
+    int ph = 0;  // the plane buffer: alternates with every plane of every tile
     for (int t = t0; t < t1; ++t) {
         const int txi = t % d.gxt, rest = t / d.gxt, tyj = rest % d.gyt, tz = rest / d.gyt;
         const int i0 = 1 + T3X * txi, j0 = 1 + T3Y * tyj, k0 = 1 + T3Z * tz, k1 = min(k0 + T3Z, d.nz + 1);
@@ -163,6 +167,8 @@ __global__ __launch_bounds__(NT) void k3_stencil(Dims3 d, const double *__restri
             czb = cz[(size_t)(k0 - 1) * PL + col];
         }
         for (int k = k0; k < k1; ++k) {
+            double(&s)[T3Y + 2][T3X + 2] = s2[ph];
+            ph ^= 1;
             const size_t e = (size_t)k * PL + col;
             double nxt = 0.0, ce = 0.0, cw = 0.0, cn = 0.0, cs = 0.0, ct = 0.0, dv = 0.0, bv = 0.0, hv = 0.0;
             if (own) {
@@ -204,7 +210,6 @@ __global__ __launch_bounds__(NT) void k3_stencil(Dims3 d, const double *__restri
                 }
             }
             czb = ct;
-            __syncthreads();
             prev = cur;
             cur = nxt;
         }
