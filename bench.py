@@ -507,10 +507,10 @@ def run_projection3d(args):
         t3 = time.perf_counter()
         cpu = {"value": sc.grid.cells / (t3 - t2) / 1e6, "unit": "Mcell-projections/s", "cores": 1,
                "kind": "oracle",
-               "sample": f"one oracle projection of sphere_box(40) (64,000 cells, {oinfo['iterations']} Jacobi-PCG "
-                         f"iterations to {sc.tol:g}) in {t3 - t2:.1f} s after {t2 - t1:.1f} s of capacities; "
-                         f"the 256^3 case needs about {infos[-1].iterations / max(oinfo['iterations'], 1):.1f}x "
-                         f"the iterations per cell"}
+               "sample": f"one oracle projection of sphere_box(40) (64,000 cells; the oracle's Jacobi-PCG, "
+                         f"{oinfo['iterations']} iterations to {sc.tol:g}) in {t3 - t2:.1f} s after {t2 - t1:.1f} s "
+                         f"of capacities; the device runs the multigrid-PCG ({infos[-1].iterations} iterations at "
+                         f"256^3), so the ratio mixes the two solvers' iteration counts with the hardware"}
     out = {
         "metric": "Mcell-projections/s (3-D projection step, div_rel <= 1e-10)",
         "value": cells * args.steps / wall / 1e6,
@@ -525,7 +525,8 @@ def run_projection3d(args):
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": "sphere_projection_256", "cells": cells, "grid": [g.nx, g.ny, g.nz],
-                   "bodies": "sphere r=0.3 in the unit box", "solver": "Jacobi-PCG, tol 1e-12",
+                   "bodies": "sphere r=0.3 in the unit box",
+                   "solver": "multigrid-PCG (V-cycle, 2x2x2 agglomeration), tol 1e-12",
                    "mass_floor": case.mass_floor},
         "cg_iterations": [i.iterations for i in infos],
         "div_rel_max": max(i.div_rel for i in infos),

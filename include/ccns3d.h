@@ -61,10 +61,16 @@ typedef struct {
  * Poisson solve, ||r||_2 <= tol ||b||_2; maxit: iteration limit of the
  * solve; mass_floor: theta, the smallest shifted volume the projection
  * divides by is theta hx hy hz (M_f = max(V_f, theta hx hy hz); 0 gives
- * M = diag(V) exactly). */
+ * M = diag(V) exactly); precond: the CG's preconditioner, 0 Jacobi
+ * (1 / diag), 1 a geometric multigrid V-cycle (2x2x2 agglomeration, half
+ * the sum of the covered fine face weights on each coarse face, weighted
+ * Jacobi two sweeps down and two up, the dense pseudo-inverse on a coarsest
+ * grid of at most 256 cells).  The projection method leaves the solver open
+ * (Sec. 4.6); both reach the same tolerance test. */
 typedef struct {
     double rho, tau, tol, mass_floor;
     int maxit;
+    int precond;
 } ccns3_params;
 
 /* Figures of one projection.  div_rel: max over the pressure unknowns of
@@ -127,8 +133,8 @@ ccns_status ccns3_field_set(ccns3_ctx *ctx, int field, const double *src, int is
 ccns_status ccns3_field_get(ccns3_ctx *ctx, int field, double *dst, int is_device);
 
 /* The projection step (Sec. 4.6 in three dimensions): b = -(rho/tau)
- * cont(U*, 0) on the pressure unknowns minus its mean; Jacobi-preconditioned
- * CG on (-L) Phi = b from the current PHI, L = cont(M^-1 pres(.), 0); PHI
+ * cont(U*, 0) on the pressure unknowns minus its mean; preconditioned CG
+ * (params.precond) on (-L) Phi = b from the current PHI, L = cont(M^-1 pres(.), 0); PHI
  * minus its mean over the unknowns; then U = U* - (tau/rho) M^-1 pres(PHI)
  * on the faces with c_f > 0, U* on the other unknowns and 0 on every other
  * face.  info (may be NULL) receives the solve's figures.  Returns the

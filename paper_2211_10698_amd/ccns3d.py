@@ -33,7 +33,7 @@ class Body3C(C.Structure):
 
 class Params3(C.Structure):
     _fields_ = [("rho", C.c_double), ("tau", C.c_double), ("tol", C.c_double), ("mass_floor", C.c_double),
-                ("maxit", C.c_int)]
+                ("maxit", C.c_int), ("precond", C.c_int)]
 
 
 class Info3(C.Structure):
@@ -107,8 +107,9 @@ def capacities(g, bodies) -> np.ndarray:
     return out.reshape(7, g.nz + 2, g.ny + 2, g.nx + 2)
 
 
-def make_params(rho, tau, tol=1e-12, mass_floor=0.05, maxit=100000) -> Params3:
-    return Params3(rho, tau, tol, mass_floor, maxit)
+def make_params(rho, tau, tol=1e-12, mass_floor=0.05, maxit=100000, precond=1) -> Params3:
+    """precond: 0 Jacobi, 1 the multigrid V-cycle (ccns3_params)."""
+    return Params3(rho, tau, tol, mass_floor, maxit, precond)
 
 
 class Context3:

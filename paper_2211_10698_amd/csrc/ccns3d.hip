@@ -22,6 +22,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <climits>
 #include <cstdint>
 #include <cmath>
@@ -31,6 +32,7 @@
 
 #include "ccns3d.h"
 #include "ccns3d_internal.h"
+#include "ccns_internal.h"
 #include "ccns_kern.h"
 
 namespace ccns {
@@ -339,16 +341,134 @@ __global__ __launch_bounds__(NT) void k3_div_shift(Dims3 d, const double *__rest
     put_partials<0, 2>(v, part, gridDim.x);
 }
 
+// ---------------------------------------------------------------------------
+// Geometric multigrid V-cycle on the Poisson weights, the preconditioner of
+// the 3-D CG (the two-dimensional cycle's design with a third index): 2x2x2
+// agglomeration, a coarse face weight of half the sum of the four fine faces
+// it covers, weighted Jacobi (omega = 0.8) two sweeps down and two up,
+// piecewise-constant interpolation and its transpose as restriction, and the
+// dense pseudo-inverse on the coarsest grid (at most MG3_MAXC cells).  The
+// same sweeps down and up make the cycle a symmetric operator, so the CG
+// stays valid.
+// ---------------------------------------------------------------------------
+
+constexpr double MG3_W = 0.8;   // Jacobi weight of the sweeps
+constexpr int MG3_MAXC = 256;   // cells of the coarsest grid at most
+
+// One level: dense (nz+2)(ny+2) rows of `pitch` doubles; b is the level's
+// right-hand side, x and xt its two iterates (the cycle's correction ends in
+// xt; on the finest level b is the CG's residual r and xt its z).
+struct Lev3 {
+    int nx, ny, nz, pitch;
+    size_t plane, n;
+    const double *cx, *cy, *cz, *dinv;
+    double *b, *x, *xt;
+};
+
+// (-L) u at element e of a pressure unknown (its six neighbours lie inside
+// the field's ghost layer)
+__device__ inline double lap3(const Lev3 &v, const double *__restrict__ u, size_t e) {
+    const size_t P = v.pitch, PL = v.plane;
+    const double c = u[e];
+    return v.cx[e] * (c - u[e + 1]) + v.cx[e - 1] * (c - u[e - 1]) + v.cy[e] * (c - u[e + P]) +
+           v.cy[e - P] * (c - u[e - P]) + v.cz[e] * (c - u[e + PL]) + v.cz[e - PL] * (c - u[e - PL]);
+}
+
+// x = omega D^-1 b: the first sweep from x = 0
+__global__ __launch_bounds__(NT) void k3_mg_first(Lev3 v, const Cg3 *st, int it) {
+    if (st->stop_it <= it) return;
+    const size_t stride = (size_t)gridDim.x * NT;
+    for (size_t e = (size_t)blockIdx.x * NT + threadIdx.x; e < v.n; e += stride)
+        v.x[e] = MG3_W * v.dinv[e] * v.b[e];
+}
+
+// xout = xin + omega D^-1 (b - (-L) xin) on the unknowns, 0 elsewhere.
+// NS = 2: partials (r.z, r.r) of the finest level (r = b, z = xout);
+// NS = 3: also b'.b' of the right-hand side `bp` (the first cycle of a
+// solve).
+template <int NS>
+__global__ __launch_bounds__(NT) void k3_mg_sweep(Lev3 v, const double *__restrict__ xin, double *__restrict__ xout,
+                                                  const double *__restrict__ bp, double *part, const Cg3 *st, int it) {
+    if (st->stop_it <= it) return;
+    double acc[NS > 0 ? NS : 1] = {};
+    const size_t stride = (size_t)gridDim.x * NT;
+    for (size_t e = (size_t)blockIdx.x * NT + threadIdx.x; e < v.n; e += stride) {
+        const double dv = v.dinv[e], be = v.b[e];
+        double o = 0.0;
+        if (dv > 0.0) o = xin[e] + MG3_W * dv * (be - lap3(v, xin, e));
+        xout[e] = o;
+        if constexpr (NS >= 2) {
+            acc[0] += be * o;
+            acc[1] += be * be;
+        }
+        if constexpr (NS >= 3) {
+            const double q = bp[e];
+            acc[2] += q * q;
+        }
+    }
+    if constexpr (NS > 0) put_partials<NS>(acc, part, gridDim.x);
+}
+
+// coarse b = the sum over the (up to eight) children of the fine residual
+// b - (-L) xf; 0 on the coarse ghost layer
+__global__ __launch_bounds__(NT) void k3_mg_restrict(Lev3 f, const double *__restrict__ xf, Lev3 c, const Cg3 *st,
+                                                     int it) {
+    if (st->stop_it <= it) return;
+    const size_t stride = (size_t)gridDim.x * NT;
+    for (size_t ec = (size_t)blockIdx.x * NT + threadIdx.x; ec < c.n; ec += stride) {
+        const int I = (int)(ec % c.pitch), J = (int)((ec / c.pitch) % (c.ny + 2)), K = (int)(ec / c.plane);
+        double s = 0.0;
+        if (I >= 1 && I <= c.nx && J >= 1 && J <= c.ny && K >= 1 && K <= c.nz)
+            for (int k = 2 * K - 1; k <= min(2 * K, f.nz); ++k)
+                for (int j = 2 * J - 1; j <= min(2 * J, f.ny); ++j)
+                    for (int i = 2 * I - 1; i <= min(2 * I, f.nx); ++i) {
+                        const size_t e = (size_t)k * f.plane + (size_t)j * f.pitch + i;
+                        if (f.dinv[e] > 0.0) s += f.b[e] - lap3(f, xf, e);
+                    }
+        c.b[ec] = s;
+    }
+}
+
+// xf += the parent's correction xc on the fine unknowns
+__global__ __launch_bounds__(NT) void k3_mg_prolong(Lev3 f, double *__restrict__ xf, Lev3 c,
+                                                    const double *__restrict__ xc, const Cg3 *st, int it) {
+    if (st->stop_it <= it) return;
+    const size_t stride = (size_t)gridDim.x * NT;
+    for (size_t e = (size_t)blockIdx.x * NT + threadIdx.x; e < f.n; e += stride) {
+        if (!(f.dinv[e] > 0.0)) continue;
+        const int i = (int)(e % f.pitch), j = (int)((e / f.pitch) % (f.ny + 2)), k = (int)(e / f.plane);
+        const size_t ec = (size_t)((k + 1) / 2) * c.plane + (size_t)((j + 1) / 2) * c.pitch + (i + 1) / 2;
+        xf[e] += xc[ec];
+    }
+}
+
+// coarsest grid: x = A^+ b on its n unknowns (element indices idx), one
+// work-group; n <= MG3_MAXC
+__global__ __launch_bounds__(NT) void k3_mg_coarsest(int n, const int *__restrict__ idx, const double *__restrict__ pinv,
+                                                     const double *__restrict__ b, double *__restrict__ x,
+                                                     const Cg3 *st, int it) {
+    if (st->stop_it <= it) return;
+    __shared__ double sb[MG3_MAXC];
+    for (int i = threadIdx.x; i < n; i += NT) sb[i] = b[idx[i]];
+    __syncthreads();
+    for (int i = threadIdx.x; i < n; i += NT) {
+        double acc = 0.0;
+        for (int j = 0; j < n; ++j) acc += pinv[(size_t)i * n + j] * sb[j];
+        x[idx[i]] = acc;
+    }
+}
+
 __global__ void k3_zero(size_t n, double *a) {
     for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) a[e] = 0.0;
 }
 
 // Workspace fields.
-enum { W_X, W_R, W_Z, W_P0, W_P1, W_Q, W_B, W_DINV, W_CX, W_CY, W_CZ, W_GX, W_GY, W_GZ, W_AX, W_AY, W_AZ, W_UX,
+enum { W_X, W_R, W_Z, W_ZT, W_P0, W_P1, W_Q, W_B, W_DINV, W_CX, W_CY, W_CZ, W_GX, W_GY, W_GZ, W_AX, W_AY, W_AZ, W_UX,
        W_UY, W_UZ, W_COUNT };
 // Partial-sum buffers (NB3 groups each): residual (3), direction (1),
-// update (2), right-hand side and sums (1), divergence (2).
-constexpr int PART_DOUBLES = NB3 * (3 + 1 + 2 + 1 + 1 + 2);
+// update (2), right-hand side and sums (1), divergence (2), the cycle's
+// statistics (3).
+constexpr int PART_DOUBLES = NB3 * (3 + 1 + 2 + 1 + 1 + 2 + 3);
 
 Dims3 make_dims(const ccns3_grid &g) {
     Dims3 d{};
@@ -374,6 +494,77 @@ Dims3 make_dims(const ccns3_grid &g) {
 
 size_t align256(size_t b) { return (b + 255) / 256 * 256; }
 
+// The cycle's coarse grids: each halves the one above (rounding up) until one
+// has at most MG3_MAXC cells; there is always at least one.
+std::vector<std::array<int, 3>> mg3_dims(const ccns3_grid &g) {
+    std::vector<std::array<int, 3>> v;
+    int nx = g.nx, ny = g.ny, nz = g.nz;
+    do {
+        nx = (nx + 1) / 2;
+        ny = (ny + 1) / 2;
+        nz = (nz + 1) / 2;
+        v.push_back({nx, ny, nz});
+    } while ((long)nx * ny * nz > MG3_MAXC);
+    return v;
+}
+size_t mg3_elems(const std::array<int, 3> &d) { return (size_t)(d[0] + 2) * (d[1] + 2) * (d[2] + 2); }
+constexpr int MG3_ARRS = 7;  // cx, cy, cz, dinv, b, x, xt of a coarse level
+size_t mg3_bytes(const ccns3_grid &g) {
+    size_t b = 0;
+    for (const auto &d : mg3_dims(g)) b += MG3_ARRS * align256(mg3_elems(d) * sizeof(double));
+    return b + align256((size_t)MG3_MAXC * MG3_MAXC * sizeof(double)) + align256(MG3_MAXC * sizeof(int));
+}
+
+// Coarse Poisson weights of a 2x2x2 agglomeration (dense layouts, one ghost
+// layer): the weight of a coarse face is half the sum of the weights of the
+// fine faces it covers; the coarse diagonal is the sum of the six.
+void coarsen3(int nx, int ny, int nz, const std::vector<double> (&c)[3], int NX, int NY, int NZ,
+              std::vector<double> (&cc)[3], std::vector<double> &dinv) {
+    const size_t fw = nx + 2, fp = fw * (ny + 2), cw = NX + 2, cp = cw * (NY + 2), n = cp * (NZ + 2);
+    auto f = [&](int i, int j, int k) { return (size_t)k * fp + (size_t)j * fw + i; };
+    auto C = [&](int i, int j, int k) { return (size_t)k * cp + (size_t)j * cw + i; };
+    for (auto &a : cc) a.assign(n, 0.0);
+    dinv.assign(n, 0.0);
+    for (int K = 1; K <= NZ; ++K)
+        for (int J = 1; J <= NY; ++J)
+            for (int I = 1; I <= NX; ++I) {
+                const int i0 = 2 * I - 1, i1 = std::min(2 * I, nx), j0 = 2 * J - 1, j1 = std::min(2 * J, ny);
+                const int k0 = 2 * K - 1, k1 = std::min(2 * K, nz);
+                double s = 0.0;
+                if (I < NX) {  // the fine faces between columns 2I and 2I+1
+                    for (int k = k0; k <= k1; ++k)
+                        for (int j = j0; j <= j1; ++j) s += c[0][f(2 * I, j, k)];
+                    cc[0][C(I, J, K)] = 0.5 * s;
+                }
+                if (J < NY) {
+                    s = 0.0;
+                    for (int k = k0; k <= k1; ++k)
+                        for (int i = i0; i <= i1; ++i) s += c[1][f(i, 2 * J, k)];
+                    cc[1][C(I, J, K)] = 0.5 * s;
+                }
+                if (K < NZ) {
+                    s = 0.0;
+                    for (int j = j0; j <= j1; ++j)
+                        for (int i = i0; i <= i1; ++i) s += c[2][f(i, j, 2 * K)];
+                    cc[2][C(I, J, K)] = 0.5 * s;
+                }
+            }
+    for (int K = 1; K <= NZ; ++K)
+        for (int J = 1; J <= NY; ++J)
+            for (int I = 1; I <= NX; ++I) {
+                const size_t e = C(I, J, K);
+                const double dg = cc[0][e] + cc[0][e - 1] + cc[1][e] + cc[1][e - cw] + cc[2][e] + cc[2][e - cp];
+                dinv[e] = dg > 0.0 ? 1.0 / dg : 0.0;
+            }
+}
+
+// Work-groups of an element-wise kernel over n elements.
+int flat3(size_t n) {
+    size_t f = (n + (size_t)NT * 4 - 1) / ((size_t)NT * 4);
+    f = std::min<size_t>(std::max<size_t>(f, 8), NB3);
+    return (int)((f + 7) / 8 * 8);
+}
+
 }  // namespace
 }  // namespace ccns
 
@@ -390,6 +581,12 @@ struct ccns3_ctx {
     Cg3 *h_st = nullptr;       // pinned
     double *h_part = nullptr;  // pinned, the divergence partials
     int n_active = 0;
+    // the multigrid cycle (precond = 1): the finest level and the coarse
+    // ones, the coarsest grid's unknowns and pseudo-inverse
+    std::vector<Lev3> lev;
+    int mg_n = 0;
+    int *mg_idx = nullptr;
+    double *mg_pinv = nullptr;
     std::string err;
     // optional timing of the CG kernels: an event pair around each launch of
     // a chunk, direction (0) and update (1) kernels
@@ -414,8 +611,9 @@ ccns_status fail3(ccns3_ctx *c, ccns_status s, const std::string &m) {
     } while (0)
 
 double *part_at(ccns3_ctx *c, int which) {
-    // 0 residual (3), 1 direction (1), 2 update (2), 3 rhs/sums (1), 4 divergence (2)
-    static const int off[5] = {0, 3, 4, 6, 7};
+    // 0 residual (3), 1 direction (1), 2 update (2), 3 rhs/sums (1), 4
+    // divergence (2), 5 the cycle's statistics (3)
+    static const int off[6] = {0, 3, 4, 6, 7, 9};
     return c->part + (size_t)off[which] * NB3;
 }
 
@@ -432,9 +630,111 @@ ccns_status download(ccns3_ctx *c, double *dst, const double *src, hipMemcpyKind
     return CCNS_OK;
 }
 
+// The cycle's levels: the finest on the context's fields (b = r, x = ZT,
+// xt = Z, so that the cycle's result is the CG's z), the coarse ones from
+// coarsen3 in the workspace at `mg`, and the coarsest grid's dense operator
+// on its unknowns with its pseudo-inverse (which also handles the null
+// space of the closed box).  Host rows stay in `keep` until the caller
+// synchronises the stream.
+ccns_status mg3_setup(ccns3_ctx *c, const HostCoef3 &hc, char *mg, std::vector<std::vector<double>> &keep) {
+    const Dims3 &d = c->d;
+    c->lev.clear();
+    c->lev.push_back(Lev3{c->g.nx, c->g.ny, c->g.nz, d.pitch, d.plane, d.n, c->w[W_CX], c->w[W_CY], c->w[W_CZ],
+                          c->w[W_DINV], c->w[W_R], c->w[W_ZT], c->w[W_Z]});
+    std::vector<double> cf[3] = {hc.c[0], hc.c[1], hc.c[2]}, dinv;
+    int nx = c->g.nx, ny = c->g.ny, nz = c->g.nz;
+    size_t off = 0;
+    for (const auto &D : mg3_dims(c->g)) {
+        std::vector<double> cc[3];
+        coarsen3(nx, ny, nz, cf, D[0], D[1], D[2], cc, dinv);
+        const size_t n = mg3_elems(D), ab = align256(n * sizeof(double));
+        double *a[MG3_ARRS];
+        for (int k = 0; k < MG3_ARRS; ++k) a[k] = (double *)(mg + off + k * ab);
+        off += MG3_ARRS * ab;
+        const std::vector<double> *src[4] = {&cc[0], &cc[1], &cc[2], &dinv};
+        for (int k = 0; k < 4; ++k) {
+            keep.push_back(*src[k]);
+            HIP3(c, hipMemcpyAsync(a[k], keep.back().data(), n * sizeof(double), hipMemcpyHostToDevice, c->stream));
+        }
+        const int pitch = D[0] + 2;
+        c->lev.push_back(Lev3{D[0], D[1], D[2], pitch, (size_t)pitch * (D[1] + 2), n, a[0], a[1], a[2], a[3], a[4],
+                              a[5], a[6]});
+        for (int k = 0; k < 3; ++k) cf[k].swap(cc[k]);
+        nx = D[0];
+        ny = D[1];
+        nz = D[2];
+    }
+    // the coarsest grid (dinv and cf now hold its fields)
+    const size_t cw = nx + 2, cp = cw * (ny + 2);
+    std::vector<int> idx, pos(dinv.size(), -1);
+    for (size_t e = 0; e < dinv.size(); ++e)
+        if (dinv[e] > 0.0) {
+            pos[e] = (int)idx.size();
+            idx.push_back((int)e);
+        }
+    const int n = (int)idx.size();
+    if (n > MG3_MAXC) return fail3(c, CCNS_EINVAL, "coarsest grid larger than its bound");
+    std::vector<double> A((size_t)n * n, 0.0);
+    for (int a = 0; a < n; ++a) {
+        const size_t e = idx[a];
+        A[(size_t)a * n + a] = 1.0 / dinv[e];
+        const size_t nb[6] = {e + 1, e - 1, e + cw, e - cw, e + cp, e - cp};
+        const double w[6] = {cf[0][e], cf[0][e - 1], cf[1][e], cf[1][e - cw], cf[2][e], cf[2][e - cp]};
+        for (int q = 0; q < 6; ++q)
+            if (w[q] > 0.0 && pos[nb[q]] >= 0) A[(size_t)a * n + pos[nb[q]]] -= w[q];
+    }
+    keep.push_back(n > 0 ? pseudo_inverse_spsd(A, n) : std::vector<double>(1, 0.0));
+    c->mg_pinv = (double *)(mg + off);
+    c->mg_idx = (int *)(mg + off + align256((size_t)MG3_MAXC * MG3_MAXC * sizeof(double)));
+    c->mg_n = n;
+    if (n > 0) {
+        HIP3(c, hipMemcpyAsync(c->mg_pinv, keep.back().data(), (size_t)n * n * sizeof(double), hipMemcpyHostToDevice,
+                               c->stream));
+        std::vector<double> idx_rows(((size_t)n * sizeof(int) + sizeof(double) - 1) / sizeof(double), 0.0);
+        std::memcpy(idx_rows.data(), idx.data(), (size_t)n * sizeof(int));
+        keep.push_back(std::move(idx_rows));
+        HIP3(c, hipMemcpyAsync(c->mg_idx, keep.back().data(), (size_t)n * sizeof(int), hipMemcpyHostToDevice,
+                               c->stream));
+    }
+    return CCNS_OK;
+}
+
+// One V-cycle, z = M^-1 r, on the context's stream.  ns = 2: the finest
+// level's last sweep writes the partials (r.z, r.r) at `part`; ns = 3 also
+// b'.b'.  it: the CG iteration whose update this cycle follows (-1 before the
+// first); every kernel returns at once when the solve stopped at or before it.
+ccns_status vcycle3(ccns3_ctx *c, int ns, double *part, int it) {
+    hipStream_t sm = c->stream;
+    const std::vector<Lev3> &lv = c->lev;
+    const int L = (int)lv.size() - 1;
+    for (int l = 0; l < L; ++l) {
+        const Lev3 &v = lv[l];
+        const int nb = flat3(v.n);
+        k3_mg_first<<<nb, NT, 0, sm>>>(v, c->st, it);
+        k3_mg_sweep<0><<<nb, NT, 0, sm>>>(v, v.x, v.xt, nullptr, nullptr, c->st, it);
+        k3_mg_restrict<<<flat3(lv[l + 1].n), NT, 0, sm>>>(v, v.xt, lv[l + 1], c->st, it);
+    }
+    k3_mg_coarsest<<<1, NT, 0, sm>>>(c->mg_n, c->mg_idx, c->mg_pinv, lv[L].b, lv[L].x, c->st, it);
+    for (int l = L - 1; l >= 0; --l) {
+        const Lev3 &v = lv[l];
+        const int nb = flat3(v.n);
+        k3_mg_prolong<<<nb, NT, 0, sm>>>(v, v.xt, lv[l + 1], l + 1 == L ? lv[L].x : lv[l + 1].xt, c->st, it);
+        k3_mg_sweep<0><<<nb, NT, 0, sm>>>(v, v.xt, v.x, nullptr, nullptr, c->st, it);
+        if (l > 0)
+            k3_mg_sweep<0><<<nb, NT, 0, sm>>>(v, v.x, v.xt, nullptr, nullptr, c->st, it);
+        else if (ns == 3)
+            k3_mg_sweep<3><<<nb, NT, 0, sm>>>(v, v.x, v.xt, c->w[W_B], part, c->st, it);
+        else
+            k3_mg_sweep<2><<<nb, NT, 0, sm>>>(v, v.x, v.xt, nullptr, part, c->st, it);
+    }
+    HIP3(c, hipGetLastError());
+    return CCNS_OK;
+}
+
 bool params_ok(const ccns3_params *p) {
     return p && p->rho > 0.0 && std::isfinite(p->rho) && p->tau > 0.0 && std::isfinite(p->tau) && p->tol >= 0.0 &&
-           std::isfinite(p->tol) && p->maxit >= 0 && p->mass_floor >= 0.0 && p->mass_floor <= 1.0;
+           std::isfinite(p->tol) && p->maxit >= 0 && p->mass_floor >= 0.0 && p->mass_floor <= 1.0 &&
+           (p->precond == 0 || p->precond == 1);
 }
 
 }  // namespace
@@ -445,7 +745,7 @@ size_t ccns3_workspace_bytes(const ccns3_grid *g) {
     if (!grid3_valid(g)) return 0;
     const Dims3 d = make_dims(*g);
     return (size_t)W_COUNT * align256(d.n * sizeof(double)) + align256(PART_DOUBLES * sizeof(double)) +
-           align256(sizeof(Cg3));
+           align256(sizeof(Cg3)) + mg3_bytes(*g);
 }
 
 ccns_status ccns3_ctx_create(const ccns3_grid *grid, const ccns3_params *params, const double *caps_host,
@@ -489,6 +789,14 @@ ccns_status ccns3_ctx_create(const ccns3_grid *grid, const ccns3_params *params,
             ccns3_ctx_destroy(c);
             return s;
         }
+    std::vector<std::vector<double>> keep;  // host rows of uploads in flight
+    if (c->p.precond == 1 && (s = mg3_setup(c, hc, base + (size_t)W_COUNT * fb + align256(PART_DOUBLES * sizeof(double)) +
+                                                      align256(sizeof(Cg3)),
+                                            keep)) != CCNS_OK) {
+        (void)hipStreamSynchronize(c->stream);
+        ccns3_ctx_destroy(c);
+        return s;
+    }
     if (hipStreamSynchronize(c->stream) != hipSuccess || hipGetLastError() != hipSuccess) {
         ccns3_ctx_destroy(c);
         return CCNS_EDEVICE;
@@ -554,6 +862,8 @@ ccns_status ccns3_project(ccns3_ctx *c, ccns3_info *info) {
     double **w = c->w;
     hipStream_t sm = c->stream;
     double *pr = part_at(c, 0), *pd = part_at(c, 1), *pu = part_at(c, 2), *ps = part_at(c, 3), *pv = part_at(c, 4);
+    double *pm = part_at(c, 5);
+    const bool mg = c->p.precond == 1;
     // solver state
     Cg3 h{};
     h.tol2 = c->p.tol * c->p.tol;
@@ -568,6 +878,10 @@ ccns_status ccns3_project(ccns3_ctx *c, ccns3_info *info) {
     k3_stencil<S_RESID><<<d.nblk, NT, 0, sm>>>(d, w[W_CX], w[W_CY], w[W_CZ], w[W_DINV], w[W_X], nullptr, w[W_R],
                                                w[W_Z], w[W_B], c->st, 0, ps, d.nflat, c->n_active, pr);
     HIP3(c, hipGetLastError());
+    // with the multigrid preconditioner z = M^-1 r comes from a cycle, whose
+    // last sweep writes (r.z, r.r) (and b'.b' before the first iteration)
+    ccns_status s = CCNS_OK;
+    if (mg && (s = vcycle3(c, 3, pm, -1)) != CCNS_OK) return s;
     int it = 0, chunk = 8;
     for (;;) {
         const int it0 = it;
@@ -575,8 +889,8 @@ ccns_status ccns3_project(ccns3_ctx *c, ccns3_info *info) {
             double *pnew = w[(it & 1) ? W_P1 : W_P0], *pold = w[(it & 1) ? W_P0 : W_P1];
             if (c->timing) HIP3(c, hipEventRecord(c->ev[0][k][0], sm));
             k3_stencil<S_DIR><<<d.nblk, NT, 0, sm>>>(d, w[W_CX], w[W_CY], w[W_CZ], w[W_DINV], w[W_Z], pold, pnew,
-                                                     w[W_Q], nullptr, c->st, it, it == 0 ? pr : pu,
-                                                     it == 0 ? d.nblk : d.nflat, c->n_active, pd);
+                                                     w[W_Q], nullptr, c->st, it, mg ? pm : (it == 0 ? pr : pu),
+                                                     (it == 0 && !mg) ? d.nblk : d.nflat, c->n_active, pd);
             if (c->timing) {
                 HIP3(c, hipEventRecord(c->ev[0][k][1], sm));
                 HIP3(c, hipEventRecord(c->ev[1][k][0], sm));
@@ -584,6 +898,7 @@ ccns_status ccns3_project(ccns3_ctx *c, ccns3_info *info) {
             k3_update<<<d.nflat, NT, 0, sm>>>(d, w[W_DINV], pnew, w[W_Q], w[W_X], w[W_R], w[W_Z], c->st, it, pd,
                                               d.nblk, pu);
             if (c->timing) HIP3(c, hipEventRecord(c->ev[1][k][1], sm));
+            if (mg && (s = vcycle3(c, 2, pm, it)) != CCNS_OK) return s;
         }
         HIP3(c, hipGetLastError());
         HIP3(c, hipMemcpyAsync(c->h_st, c->st, sizeof(Cg3), hipMemcpyDeviceToHost, sm));

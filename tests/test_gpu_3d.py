@@ -30,10 +30,10 @@ def _oracle_caps(case):
     return _ORACLE[key]
 
 
-def _context(case, tol=1e-12):
+def _context(case, tol=1e-12, precond=1):
     from paper_2211_10698_amd import ccns3d
     caps = ccns3d.capacities(case.grid, case.bodies)
-    prm = ccns3d.make_params(case.rho, case.tau, tol=tol, mass_floor=case.mass_floor)
+    prm = ccns3d.make_params(case.rho, case.tau, tol=tol, mass_floor=case.mass_floor, precond=precond)
     return ccns3d.Context3(case.grid, prm, caps)
 
 
@@ -63,13 +63,14 @@ def test_poisson_operator_matches_the_oracle(name, make):
     ctx.close()
 
 
+@pytest.mark.parametrize("precond", [0, 1], ids=["jacobi", "multigrid"])
 @pytest.mark.parametrize("name,make", _cases(), ids=[c[0] for c in _cases()])
-def test_projection_matches_the_oracle(name, make):
+def test_projection_matches_the_oracle(name, make, precond):
     from paper_2211_10698_amd import ccns3d
     case = make()
-    print(f"[3d] projection {name}", flush=True)
+    print(f"[3d] projection {name} precond {precond}", flush=True)
     g = case.grid
-    ctx = _context(case)
+    ctx = _context(case, precond=precond)
     U = T.face_velocity(case)
     for f, u in zip((ccns3d.F_UX, ccns3d.F_UY, ccns3d.F_UZ), U):
         ctx.set_field(f, u)
@@ -95,13 +96,15 @@ def test_projection_matches_the_oracle(name, make):
     ctx.close()
 
 
-def test_projection_is_reproducible_bit_for_bit():
+@pytest.mark.parametrize("precond", [0, 1], ids=["jacobi", "multigrid"])
+def test_projection_is_reproducible_bit_for_bit(precond):
     from paper_2211_10698_amd import ccns3d
     case = T.two_spheres(70, 20, 36)
+    print(f"[3d] reproducible, precond {precond}", flush=True)
     U = T.face_velocity(case)
     out = []
     for _ in range(2):
-        ctx = _context(case)
+        ctx = _context(case, precond=precond)
         for f, u in zip((ccns3d.F_UX, ccns3d.F_UY, ccns3d.F_UZ), U):
             ctx.set_field(f, u)
         info = ctx.project()
@@ -110,6 +113,28 @@ def test_projection_is_reproducible_bit_for_bit():
     assert out[0][0] == out[1][0]
     for a, b in zip(out[0][1], out[1][1]):
         assert np.array_equal(a, b)
+
+
+def test_multigrid_and_jacobi_reach_the_same_solution():
+    """The two preconditioners solve the same system to the same
+    tolerance: the same Phi to the tolerance's reach, the multigrid in a
+    small fraction of the Jacobi iterations."""
+    from paper_2211_10698_amd import ccns3d
+    case = T.sphere_box(40)
+    print("[3d] multigrid against Jacobi, sphere_40", flush=True)
+    U = T.face_velocity(case)
+    res = []
+    for precond in (0, 1):
+        ctx = _context(case, precond=precond)
+        for f, u in zip((ccns3d.F_UX, ccns3d.F_UY, ccns3d.F_UZ), U):
+            ctx.set_field(f, u)
+        info = ctx.project()
+        assert info.status == ccns3d.OK and info.rel_residual <= 1e-12 and info.div_rel < 1e-10
+        res.append((info.iterations, ctx.get_field(ccns3d.F_PHI).cpu().numpy()))
+        ctx.close()
+    (it_j, phi_j), (it_m, phi_m) = res
+    assert np.abs(phi_m - phi_j).max() <= 1e-8 * np.abs(phi_j).max()
+    assert it_m * 5 < it_j, (it_m, it_j)
 
 
 def _local_faces(case, i, j, k):
