@@ -150,10 +150,12 @@ ccns_status ccns3_project(ccns3_ctx *ctx, ccns3_info *info);
  * checking the operator the solve uses. */
 ccns_status ccns3_apply_poisson(ccns3_ctx *ctx, const double *in_dev, double *out_dev);
 
-/* Live timing of the Poisson CG's two kernels with HIP events around each
+/* Live timing of the Poisson CG's kernels with HIP events around each
  * launch on the context's stream: ms[0], count[0] the direction-and-operator
- * kernel, ms[1], count[1] the update kernel, accumulated over the launches
- * that did an iteration's work since the last reset.  enable: 1 on, 0 off,
+ * kernel, ms[1], count[1] the update kernel, ms[2], count[2] (multigrid
+ * only) the finest level's first up-sweep of the cycle, accumulated over the
+ * launches that did an iteration's work since the last reset; ms and count
+ * point to 3 elements each.  enable: 1 on, 0 off,
  * -1 leave unchanged; 0 and 1 also reset the accumulators (after they are
  * returned).  ms and count may be NULL. */
 ccns_status ccns3_timing(ccns3_ctx *ctx, int enable, double *ms, long *count);

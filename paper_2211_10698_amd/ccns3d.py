@@ -194,12 +194,13 @@ class Context3:
         return info
 
     def timing(self, enable=-1):
-        """((ms, count) of the direction kernel, (ms, count) of the update
-        kernel); see ccns3_timing."""
-        ms = (C.c_double * 2)()
-        cnt = (C.c_long * 2)()
+        """((ms, count) of the direction kernel, of the update kernel, of the
+        finest level's first up-sweep of the multigrid cycle); see
+        ccns3_timing."""
+        ms = (C.c_double * 3)()
+        cnt = (C.c_long * 3)()
         self._chk(lib().ccns3_timing(self.h, enable, ms, cnt), "timing")
-        return (ms[0], cnt[0]), (ms[1], cnt[1])
+        return (ms[0], cnt[0]), (ms[1], cnt[1]), (ms[2], cnt[2])
 
     def apply_poisson(self, x):
         """(-L) x on the cells (dense layout), a device tensor."""

@@ -349,7 +349,13 @@ __global__ __launch_bounds__(NT) void k3_div_shift(Dims3 d, const double *__rest
 // piecewise-constant interpolation and its transpose as restriction, and the
 // dense pseudo-inverse on the coarsest grid (at most MG3_MAXC cells).  The
 // same sweeps down and up make the cycle a symmetric operator, so the CG
-// stays valid.
+// stays valid.  Each level takes four launches: the two down-sweeps in one
+// (the first sweep from x = 0 is omega D^-1 b, formed where the second reads
+// it), the restriction of the residual, the first up-sweep with the
+// interpolated coarse correction added where it reads its input, and the
+// second up-sweep.  Every kernel loads all it needs of an interior element
+// before it looks at whether the element is an unknown (the loads of an
+// interior element stay inside the ghost layer), so no load waits on another.
 // ---------------------------------------------------------------------------
 
 constexpr double MG3_W = 0.8;   // Jacobi weight of the sweeps
@@ -357,7 +363,8 @@ constexpr int MG3_MAXC = 256;   // cells of the coarsest grid at most
 
 // One level: dense (nz+2)(ny+2) rows of `pitch` doubles; b is the level's
 // right-hand side, x and xt its two iterates (the cycle's correction ends in
-// xt; on the finest level b is the CG's residual r and xt its z).
+// xt; on the finest level b is the CG's residual r and xt its z).  Every
+// level has fewer than 2^31 elements.
 struct Lev3 {
     int nx, ny, nz, pitch;
     size_t plane, n;
@@ -365,37 +372,59 @@ struct Lev3 {
     double *b, *x, *xt;
 };
 
-// (-L) u at element e of a pressure unknown (its six neighbours lie inside
-// the field's ghost layer)
-__device__ inline double lap3(const Lev3 &v, const double *__restrict__ u, size_t e) {
-    const size_t P = v.pitch, PL = v.plane;
-    const double c = u[e];
-    return v.cx[e] * (c - u[e + 1]) + v.cx[e - 1] * (c - u[e - 1]) + v.cy[e] * (c - u[e + P]) +
-           v.cy[e - P] * (c - u[e - P]) + v.cz[e] * (c - u[e + PL]) + v.cz[e - PL] * (c - u[e - PL]);
+// (i, j, k) of element e of a level
+__device__ inline void ijk3(const Lev3 &v, unsigned e, int &i, int &j, int &k) {
+    const unsigned row = e / (unsigned)v.pitch;
+    i = (int)(e - row * (unsigned)v.pitch);
+    k = (int)(row / (unsigned)(v.ny + 2));
+    j = (int)(row - (unsigned)k * (unsigned)(v.ny + 2));
+}
+__device__ inline bool interior3(const Lev3 &v, int i, int j, int k) {
+    return i >= 1 && i <= v.nx && j >= 1 && j <= v.ny && k >= 1 && k <= v.nz;
 }
 
-// x = omega D^-1 b: the first sweep from x = 0
-__global__ __launch_bounds__(NT) void k3_mg_first(Lev3 v, const Cg3 *st, int it) {
-    if (st->stop_it <= it) return;
-    const size_t stride = (size_t)gridDim.x * NT;
-    for (size_t e = (size_t)blockIdx.x * NT + threadIdx.x; e < v.n; e += stride)
-        v.x[e] = MG3_W * v.dinv[e] * v.b[e];
+// The value a sweep acts on at element e (cell (i, j, k)):
+//  FROM_B: the first sweep's result omega D^-1 b;
+//  PRO:    u + the parent's coarse correction;
+//  else:   u.
+template <bool FROM_B, bool PRO>
+__device__ inline double sweep_in(const Lev3 &v, const double *__restrict__ u, const Lev3 &c,
+                                  const double *__restrict__ xc, size_t e, int i, int j, int k) {
+    if (FROM_B) return MG3_W * v.dinv[e] * v.b[e];
+    if (PRO)
+        return u[e] + xc[(size_t)((k + 1) >> 1) * c.plane + (size_t)((j + 1) >> 1) * c.pitch + ((i + 1) >> 1)];
+    return u[e];
 }
 
-// xout = xin + omega D^-1 (b - (-L) xin) on the unknowns, 0 elsewhere.
-// NS = 2: partials (r.z, r.r) of the finest level (r = b, z = xout);
-// NS = 3: also b'.b' of the right-hand side `bp` (the first cycle of a
-// solve).
-template <int NS>
+// xout = y + omega D^-1 (b - (-L) y) on the unknowns, 0 elsewhere, with y
+// given by sweep_in.  NS = 2: partials (r.z, r.r) of the finest level (r = b,
+// z = xout); NS = 3: also b'.b' of the right-hand side `bp` (the first cycle
+// of a solve).
+template <int NS, bool FROM_B, bool PRO>
 __global__ __launch_bounds__(NT) void k3_mg_sweep(Lev3 v, const double *__restrict__ xin, double *__restrict__ xout,
-                                                  const double *__restrict__ bp, double *part, const Cg3 *st, int it) {
+                                                  Lev3 c, const double *__restrict__ xc, const double *__restrict__ bp,
+                                                  double *part, const Cg3 *st, int it) {
     if (st->stop_it <= it) return;
     double acc[NS > 0 ? NS : 1] = {};
-    const size_t stride = (size_t)gridDim.x * NT;
+    const size_t stride = (size_t)gridDim.x * NT, P = v.pitch, PL = v.plane;
     for (size_t e = (size_t)blockIdx.x * NT + threadIdx.x; e < v.n; e += stride) {
-        const double dv = v.dinv[e], be = v.b[e];
-        double o = 0.0;
-        if (dv > 0.0) o = xin[e] + MG3_W * dv * (be - lap3(v, xin, e));
+        int i, j, k;
+        ijk3(v, (unsigned)e, i, j, k);
+        double o = 0.0, be = 0.0;
+        if (interior3(v, i, j, k)) {
+            be = v.b[e];
+            const double dv = v.dinv[e];
+            const double y = sweep_in<FROM_B, PRO>(v, xin, c, xc, e, i, j, k);
+            const double ye = sweep_in<FROM_B, PRO>(v, xin, c, xc, e + 1, i + 1, j, k);
+            const double yw = sweep_in<FROM_B, PRO>(v, xin, c, xc, e - 1, i - 1, j, k);
+            const double yn = sweep_in<FROM_B, PRO>(v, xin, c, xc, e + P, i, j + 1, k);
+            const double ys = sweep_in<FROM_B, PRO>(v, xin, c, xc, e - P, i, j - 1, k);
+            const double yt = sweep_in<FROM_B, PRO>(v, xin, c, xc, e + PL, i, j, k + 1);
+            const double yb = sweep_in<FROM_B, PRO>(v, xin, c, xc, e - PL, i, j, k - 1);
+            const double ax = v.cx[e] * (y - ye) + v.cx[e - 1] * (y - yw) + v.cy[e] * (y - yn) +
+                              v.cy[e - P] * (y - ys) + v.cz[e] * (y - yt) + v.cz[e - PL] * (y - yb);
+            o = dv > 0.0 ? y + MG3_W * dv * (be - ax) : 0.0;
+        }
         xout[e] = o;
         if constexpr (NS >= 2) {
             acc[0] += be * o;
@@ -410,35 +439,33 @@ __global__ __launch_bounds__(NT) void k3_mg_sweep(Lev3 v, const double *__restri
 }
 
 // coarse b = the sum over the (up to eight) children of the fine residual
-// b - (-L) xf; 0 on the coarse ghost layer
+// b - (-L) xf on the fine unknowns; 0 on the coarse ghost layer.  A child
+// index beyond the fine grid is clamped to the grid (its load repeats its
+// sibling's) and contributes nothing.
 __global__ __launch_bounds__(NT) void k3_mg_restrict(Lev3 f, const double *__restrict__ xf, Lev3 c, const Cg3 *st,
                                                      int it) {
     if (st->stop_it <= it) return;
-    const size_t stride = (size_t)gridDim.x * NT;
+    const size_t stride = (size_t)gridDim.x * NT, P = f.pitch, PL = f.plane;
     for (size_t ec = (size_t)blockIdx.x * NT + threadIdx.x; ec < c.n; ec += stride) {
-        const int I = (int)(ec % c.pitch), J = (int)((ec / c.pitch) % (c.ny + 2)), K = (int)(ec / c.plane);
+        int I, J, K;
+        ijk3(c, (unsigned)ec, I, J, K);
         double s = 0.0;
-        if (I >= 1 && I <= c.nx && J >= 1 && J <= c.ny && K >= 1 && K <= c.nz)
-            for (int k = 2 * K - 1; k <= min(2 * K, f.nz); ++k)
-                for (int j = 2 * J - 1; j <= min(2 * J, f.ny); ++j)
-                    for (int i = 2 * I - 1; i <= min(2 * I, f.nx); ++i) {
-                        const size_t e = (size_t)k * f.plane + (size_t)j * f.pitch + i;
-                        if (f.dinv[e] > 0.0) s += f.b[e] - lap3(f, xf, e);
-                    }
+        if (interior3(c, I, J, K)) {
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int i0 = 2 * I - 1 + (q & 1), j0 = 2 * J - 1 + ((q >> 1) & 1), k0 = 2 * K - 1 + (q >> 2);
+                const bool in = i0 <= f.nx && j0 <= f.ny && k0 <= f.nz;
+                const int i = min(i0, f.nx), j = min(j0, f.ny), k = min(k0, f.nz);
+                const size_t e = (size_t)k * PL + (size_t)j * P + i;
+                const double y = xf[e];
+                const double ax = f.cx[e] * (y - xf[e + 1]) + f.cx[e - 1] * (y - xf[e - 1]) +
+                                  f.cy[e] * (y - xf[e + P]) + f.cy[e - P] * (y - xf[e - P]) +
+                                  f.cz[e] * (y - xf[e + PL]) + f.cz[e - PL] * (y - xf[e - PL]);
+                const double r = f.b[e] - ax;
+                s += (in && f.dinv[e] > 0.0) ? r : 0.0;
+            }
+        }
         c.b[ec] = s;
-    }
-}
-
-// xf += the parent's correction xc on the fine unknowns
-__global__ __launch_bounds__(NT) void k3_mg_prolong(Lev3 f, double *__restrict__ xf, Lev3 c,
-                                                    const double *__restrict__ xc, const Cg3 *st, int it) {
-    if (st->stop_it <= it) return;
-    const size_t stride = (size_t)gridDim.x * NT;
-    for (size_t e = (size_t)blockIdx.x * NT + threadIdx.x; e < f.n; e += stride) {
-        if (!(f.dinv[e] > 0.0)) continue;
-        const int i = (int)(e % f.pitch), j = (int)((e / f.pitch) % (f.ny + 2)), k = (int)(e / f.plane);
-        const size_t ec = (size_t)((k + 1) / 2) * c.plane + (size_t)((j + 1) / 2) * c.pitch + (i + 1) / 2;
-        xf[e] += xc[ec];
     }
 }
 
@@ -589,11 +616,13 @@ struct ccns3_ctx {
     double *mg_pinv = nullptr;
     std::string err;
     // optional timing of the CG kernels: an event pair around each launch of
-    // a chunk, direction (0) and update (1) kernels
+    // a chunk, direction (0) and update (1) kernels, and the finest level's
+    // first up-sweep of the multigrid cycle that follows each update (2)
     bool timing = false;
-    hipEvent_t ev[2][64][2] = {};
-    double t_ms[2] = {0.0, 0.0};
-    long t_count[2] = {0, 0};
+    hipEvent_t ev[3][64][2] = {};
+    double t_ms[3] = {0.0, 0.0, 0.0};
+    long t_count[3] = {0, 0, 0};
+    int tslot = -1;  // the chunk slot of the cycle being enqueued (-1: not timed)
 };
 
 namespace {
@@ -709,23 +738,27 @@ ccns_status vcycle3(ccns3_ctx *c, int ns, double *part, int it) {
     const int L = (int)lv.size() - 1;
     for (int l = 0; l < L; ++l) {
         const Lev3 &v = lv[l];
-        const int nb = flat3(v.n);
-        k3_mg_first<<<nb, NT, 0, sm>>>(v, c->st, it);
-        k3_mg_sweep<0><<<nb, NT, 0, sm>>>(v, v.x, v.xt, nullptr, nullptr, c->st, it);
+        // the two down-sweeps from x = 0 in one launch, then the restriction
+        k3_mg_sweep<0, true, false><<<flat3(v.n), NT, 0, sm>>>(v, nullptr, v.xt, v, nullptr, nullptr, nullptr, c->st,
+                                                               it);
         k3_mg_restrict<<<flat3(lv[l + 1].n), NT, 0, sm>>>(v, v.xt, lv[l + 1], c->st, it);
     }
     k3_mg_coarsest<<<1, NT, 0, sm>>>(c->mg_n, c->mg_idx, c->mg_pinv, lv[L].b, lv[L].x, c->st, it);
     for (int l = L - 1; l >= 0; --l) {
         const Lev3 &v = lv[l];
         const int nb = flat3(v.n);
-        k3_mg_prolong<<<nb, NT, 0, sm>>>(v, v.xt, lv[l + 1], l + 1 == L ? lv[L].x : lv[l + 1].xt, c->st, it);
-        k3_mg_sweep<0><<<nb, NT, 0, sm>>>(v, v.xt, v.x, nullptr, nullptr, c->st, it);
+        // the first up-sweep on xt plus the interpolated coarse correction
+        const bool timed = l == 0 && c->tslot >= 0;
+        if (timed) HIP3(c, hipEventRecord(c->ev[2][c->tslot][0], sm));
+        k3_mg_sweep<0, false, true><<<nb, NT, 0, sm>>>(v, v.xt, v.x, lv[l + 1], l + 1 == L ? lv[L].x : lv[l + 1].xt,
+                                                       nullptr, nullptr, c->st, it);
+        if (timed) HIP3(c, hipEventRecord(c->ev[2][c->tslot][1], sm));
         if (l > 0)
-            k3_mg_sweep<0><<<nb, NT, 0, sm>>>(v, v.x, v.xt, nullptr, nullptr, c->st, it);
+            k3_mg_sweep<0, false, false><<<nb, NT, 0, sm>>>(v, v.x, v.xt, v, nullptr, nullptr, nullptr, c->st, it);
         else if (ns == 3)
-            k3_mg_sweep<3><<<nb, NT, 0, sm>>>(v, v.x, v.xt, c->w[W_B], part, c->st, it);
+            k3_mg_sweep<3, false, false><<<nb, NT, 0, sm>>>(v, v.x, v.xt, v, nullptr, c->w[W_B], part, c->st, it);
         else
-            k3_mg_sweep<2><<<nb, NT, 0, sm>>>(v, v.x, v.xt, nullptr, part, c->st, it);
+            k3_mg_sweep<2, false, false><<<nb, NT, 0, sm>>>(v, v.x, v.xt, v, nullptr, nullptr, part, c->st, it);
     }
     HIP3(c, hipGetLastError());
     return CCNS_OK;
@@ -898,7 +931,10 @@ ccns_status ccns3_project(ccns3_ctx *c, ccns3_info *info) {
             k3_update<<<d.nflat, NT, 0, sm>>>(d, w[W_DINV], pnew, w[W_Q], w[W_X], w[W_R], w[W_Z], c->st, it, pd,
                                               d.nblk, pu);
             if (c->timing) HIP3(c, hipEventRecord(c->ev[1][k][1], sm));
-            if (mg && (s = vcycle3(c, 2, pm, it)) != CCNS_OK) return s;
+            c->tslot = c->timing ? k : -1;
+            s = mg ? vcycle3(c, 2, pm, it) : CCNS_OK;
+            c->tslot = -1;
+            if (s != CCNS_OK) return s;
         }
         HIP3(c, hipGetLastError());
         HIP3(c, hipMemcpyAsync(c->h_st, c->st, sizeof(Cg3), hipMemcpyDeviceToHost, sm));
@@ -908,7 +944,7 @@ ccns_status ccns3_project(ccns3_ctx *c, ccns3_info *info) {
             // stopping iteration return at once)
             const int stop = c->h_st->stop_it;
             for (int k = 0; k < chunk && it0 + k < stop; ++k)
-                for (int q = 0; q < 2; ++q) {
+                for (int q = 0; q < (mg ? 3 : 2); ++q) {
                     float ms = 0.0f;
                     HIP3(c, hipEventElapsedTime(&ms, c->ev[q][k][0], c->ev[q][k][1]));
                     c->t_ms[q] += ms;
@@ -949,14 +985,15 @@ ccns_status ccns3_project(ccns3_ctx *c, ccns3_info *info) {
 
 ccns_status ccns3_timing(ccns3_ctx *c, int enable, double *ms, long *count) {
     if (!c || enable < -1 || enable > 1) return fail3(c, CCNS_EINVAL, "bad argument");
-    for (int q = 0; q < 2; ++q) {
+    for (int q = 0; q < 3; ++q) {
         if (ms) ms[q] = c->t_ms[q];
         if (count) count[q] = c->t_count[q];
     }
-    if (enable >= 0) {
-        c->t_ms[0] = c->t_ms[1] = 0.0;
-        c->t_count[0] = c->t_count[1] = 0;
-    }
+    if (enable >= 0)
+        for (int q = 0; q < 3; ++q) {
+            c->t_ms[q] = 0.0;
+            c->t_count[q] = 0;
+        }
     if (enable == 1 && !c->timing) {
         for (auto &kk : c->ev)
             for (auto &k : kk)
