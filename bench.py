@@ -539,12 +539,12 @@ def run_projection3d(args):
                    "mass_floor": case.mass_floor},
         "cg_iterations": [i.iterations for i in infos],
         "div_rel_max": max(i.div_rel for i in infos),
-        "kernels_us": {"k3_stencil<DIR>": dir_us, "k3_update": upd_us, "k3_mg_sweep (finest, up)": sw_us,
+        "kernels_us": {"k3_stencil<DIR>": dir_us, "k3_update": upd_us, "k3_mg_tile<T_POST1> (finest up-sweep)": sw_us,
                        "dir_GBps": DIR3_BYTES_PER_CELL * cells / (dir_us * 1e-6) / 1e9,
                        "update_GBps": UPDATE3_BYTES_PER_ELEMENT * n_elem / (upd_us * 1e-6) / 1e9},
         "roofline": ({"bound": "hbm", "achieved": achieved, "peak": 8000.0, "unit": "GB/s",
                       "frac": achieved / 8000.0, "traffic": None,
-                      "kernel": "k3_mg_sweep (the cycle's finest-level up-sweep)",
+                      "kernel": "k3_mg_tile<T_POST1> (the cycle's finest-level up-sweep)",
                       "bytes_per_cell": SWEEP3_BYTES_PER_CELL, "mean_launch_us": sw_us, "timed_launches": sn}
                      if precond else
                      {"bound": "hbm", "achieved": DIR3_BYTES_PER_CELL * cells / (dir_us * 1e-6) / 1e9,

@@ -469,6 +469,137 @@ __global__ __launch_bounds__(NT) void k3_mg_restrict(Lev3 f, const double *__res
     }
 }
 
+// The finest level's cycle kernels on the tiles of k3_stencil (64 x 4
+// columns marched up a slab of 32 cells in z, the current plane and its halo
+// in LDS), which read each value about once where the element-wise forms
+// re-read their plane and row neighbours from beyond L2:
+//  T_PRE:   both down-sweeps, xt from y = omega D^-1 b;
+//  T_RES:   the residual b - (-L) xt on the unknowns (for the restriction);
+//  T_POST1: the first up-sweep from y = xt + the parent's correction;
+//  T_POST2: the second up-sweep from y = x (NS: the partials of
+//           k3_mg_sweep).
+enum { T_PRE = 0, T_RES = 1, T_POST1 = 2, T_POST2 = 3 };
+template <int MODE>
+__device__ inline double tile_in(const Lev3 &v, const double *__restrict__ u, const Lev3 &c,
+                                 const double *__restrict__ xc, size_t e, int i, int j, int k) {
+    if (MODE == T_PRE) return MG3_W * v.dinv[e] * v.b[e];
+    if (MODE == T_POST1)
+        return u[e] + xc[(size_t)((k + 1) >> 1) * c.plane + (size_t)((j + 1) >> 1) * c.pitch + ((i + 1) >> 1)];
+    return u[e];
+}
+template <int MODE, int NS>
+__global__ __launch_bounds__(NT) void k3_mg_tile(Dims3 d, Lev3 v, const double *__restrict__ u, Lev3 c,
+                                                 const double *__restrict__ xc, double *__restrict__ out,
+                                                 const double *__restrict__ bp, double *part, const Cg3 *st, int it) {
+    if (st->stop_it <= it) return;
+    __shared__ double s2[2][T3Y + 2][T3X + 2];
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    const int X = d.pitch;
+    const size_t PL = d.plane;
+    double acc[NS > 0 ? NS : 1] = {};
+    const int L = logical_group(d.nblk);
+    const int t0 = L * d.tpb, t1 = min(t0 + d.tpb, d.ntile);
+    int ph = 0;
+    for (int t = t0; t < t1; ++t) {
+        const int txi = t % d.gxt, rest = t / d.gxt, tyj = rest % d.gyt, tz = rest / d.gyt;
+        const int i0 = 1 + T3X * txi, j0 = 1 + T3Y * tyj, k0 = 1 + T3Z * tz, k1 = min(k0 + T3Z, d.nz + 1);
+        const int i = i0 + tx, j = j0 + ty;
+        const bool own = i <= d.nx && j <= d.ny;
+        int hx = 0, hy = 0;
+        bool hin = false;
+        const bool hthr = (int)threadIdx.x < HALO3;
+        if (hthr) {
+            const int e = threadIdx.x;
+            if (e < 2 * (T3X + 2)) {
+                hy = e < T3X + 2 ? 0 : T3Y + 1;
+                hx = e < T3X + 2 ? e : e - (T3X + 2);
+            } else {
+                const int f = e - 2 * (T3X + 2);
+                hy = 1 + (f >> 1);
+                hx = (f & 1) ? T3X + 1 : 0;
+            }
+            hin = i0 - 1 + hx <= d.nx + 1 && j0 - 1 + hy <= d.ny + 1;
+        }
+        const int hi = i0 - 1 + hx, hj = j0 - 1 + hy;
+        const size_t hoff = (size_t)hj * X + hi;
+        const size_t col = (size_t)j * X + i;
+        double prev = 0.0, cur = 0.0, czb = 0.0;
+        if (own) {
+            prev = tile_in<MODE>(v, u, c, xc, (size_t)(k0 - 1) * PL + col, i, j, k0 - 1);
+            cur = tile_in<MODE>(v, u, c, xc, (size_t)k0 * PL + col, i, j, k0);
+            czb = v.cz[(size_t)(k0 - 1) * PL + col];
+        }
+        for (int k = k0; k < k1; ++k) {
+            double(&s)[T3Y + 2][T3X + 2] = s2[ph];
+            ph ^= 1;
+            const size_t e = (size_t)k * PL + col;
+            double nxt = 0.0, ce = 0.0, cw = 0.0, cn = 0.0, cs = 0.0, ct = 0.0, dv = 0.0, bv = 0.0, hv = 0.0;
+            if (own) {
+                nxt = tile_in<MODE>(v, u, c, xc, e + PL, i, j, k + 1);
+                ce = v.cx[e];
+                cw = v.cx[e - 1];
+                cn = v.cy[e];
+                cs = v.cy[e - X];
+                ct = v.cz[e];
+                dv = v.dinv[e];
+                bv = v.b[e];
+            }
+            if (hthr && hin) hv = tile_in<MODE>(v, u, c, xc, (size_t)k * PL + hoff, hi, hj, k);
+            s[ty + 1][tx + 1] = cur;
+            if (hthr) s[hy][hx] = hin ? hv : 0.0;
+            __syncthreads();
+            if (own) {
+                const double av = ce * (cur - s[ty + 1][tx + 2]) + cw * (cur - s[ty + 1][tx]) +
+                                  cn * (cur - s[ty + 2][tx + 1]) + cs * (cur - s[ty][tx + 1]) + ct * (cur - nxt) +
+                                  czb * (cur - prev);
+                double o;
+                if (MODE == T_RES)
+                    o = dv > 0.0 ? bv - av : 0.0;
+                else
+                    o = dv > 0.0 ? cur + MG3_W * dv * (bv - av) : 0.0;
+                out[e] = o;
+                if constexpr (NS >= 2) {
+                    acc[0] += bv * o;
+                    acc[1] += bv * bv;
+                }
+                if constexpr (NS >= 3) {
+                    const double q = bp[e];
+                    acc[2] += q * q;
+                }
+            }
+            czb = ct;
+            prev = cur;
+            cur = nxt;
+        }
+    }
+    if constexpr (NS > 0) put_partials<NS>(acc, part, gridDim.x);
+}
+
+// coarse b = the sum of the fine residual rf over the (up to eight)
+// children; 0 on the coarse ghost layer.  rf is 0 off the fine unknowns; a
+// child index beyond the fine grid is clamped and contributes nothing.
+__global__ __launch_bounds__(NT) void k3_mg_sum8(Lev3 f, const double *__restrict__ rf, Lev3 c, const Cg3 *st,
+                                                 int it) {
+    if (st->stop_it <= it) return;
+    const size_t stride = (size_t)gridDim.x * NT;
+    for (size_t ec = (size_t)blockIdx.x * NT + threadIdx.x; ec < c.n; ec += stride) {
+        int I, J, K;
+        ijk3(c, (unsigned)ec, I, J, K);
+        double s = 0.0;
+        if (interior3(c, I, J, K)) {
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int i0 = 2 * I - 1 + (q & 1), j0 = 2 * J - 1 + ((q >> 1) & 1), k0 = 2 * K - 1 + (q >> 2);
+                const bool in = i0 <= f.nx && j0 <= f.ny && k0 <= f.nz;
+                const size_t e = (size_t)min(k0, f.nz) * f.plane + (size_t)min(j0, f.ny) * f.pitch + min(i0, f.nx);
+                const double r = rf[e];
+                s += in ? r : 0.0;
+            }
+        }
+        c.b[ec] = s;
+    }
+}
+
 // coarsest grid: x = A^+ b on its n unknowns (element indices idx), one
 // work-group; n <= MG3_MAXC
 __global__ __launch_bounds__(NT) void k3_mg_coarsest(int n, const int *__restrict__ idx, const double *__restrict__ pinv,
@@ -728,7 +859,8 @@ ccns_status mg3_setup(ccns3_ctx *c, const HostCoef3 &hc, char *mg, std::vector<s
     return CCNS_OK;
 }
 
-// One V-cycle, z = M^-1 r, on the context's stream.  ns = 2: the finest
+// One V-cycle, z = M^-1 r, on the context's stream (the finest level on
+// the tiles of k3_stencil, with d.nblk work-groups).  ns = 2: the finest
 // level's last sweep writes the partials (r.z, r.r) at `part`; ns = 3 also
 // b'.b'.  it: the CG iteration whose update this cycle follows (-1 before the
 // first); every kernel returns at once when the solve stopped at or before it.
@@ -736,9 +868,17 @@ ccns_status vcycle3(ccns3_ctx *c, int ns, double *part, int it) {
     hipStream_t sm = c->stream;
     const std::vector<Lev3> &lv = c->lev;
     const int L = (int)lv.size() - 1;
+    const Dims3 &d = c->d;
     for (int l = 0; l < L; ++l) {
         const Lev3 &v = lv[l];
         // the two down-sweeps from x = 0 in one launch, then the restriction
+        // (on the finest level through its residual, in the free q field)
+        if (l == 0) {
+            k3_mg_tile<T_PRE, 0><<<d.nblk, NT, 0, sm>>>(d, v, nullptr, v, nullptr, v.xt, nullptr, nullptr, c->st, it);
+            k3_mg_tile<T_RES, 0><<<d.nblk, NT, 0, sm>>>(d, v, v.xt, v, nullptr, c->w[W_Q], nullptr, nullptr, c->st, it);
+            k3_mg_sum8<<<flat3(lv[1].n), NT, 0, sm>>>(v, c->w[W_Q], lv[1], c->st, it);
+            continue;
+        }
         k3_mg_sweep<0, true, false><<<flat3(v.n), NT, 0, sm>>>(v, nullptr, v.xt, v, nullptr, nullptr, nullptr, c->st,
                                                                it);
         k3_mg_restrict<<<flat3(lv[l + 1].n), NT, 0, sm>>>(v, v.xt, lv[l + 1], c->st, it);
@@ -748,17 +888,20 @@ ccns_status vcycle3(ccns3_ctx *c, int ns, double *part, int it) {
         const Lev3 &v = lv[l];
         const int nb = flat3(v.n);
         // the first up-sweep on xt plus the interpolated coarse correction
-        const bool timed = l == 0 && c->tslot >= 0;
-        if (timed) HIP3(c, hipEventRecord(c->ev[2][c->tslot][0], sm));
-        k3_mg_sweep<0, false, true><<<nb, NT, 0, sm>>>(v, v.xt, v.x, lv[l + 1], l + 1 == L ? lv[L].x : lv[l + 1].xt,
-                                                       nullptr, nullptr, c->st, it);
-        if (timed) HIP3(c, hipEventRecord(c->ev[2][c->tslot][1], sm));
-        if (l > 0)
+        const double *xc = l + 1 == L ? lv[L].x : lv[l + 1].xt;
+        if (l > 0) {
+            k3_mg_sweep<0, false, true><<<nb, NT, 0, sm>>>(v, v.xt, v.x, lv[l + 1], xc, nullptr, nullptr, c->st, it);
             k3_mg_sweep<0, false, false><<<nb, NT, 0, sm>>>(v, v.x, v.xt, v, nullptr, nullptr, nullptr, c->st, it);
-        else if (ns == 3)
-            k3_mg_sweep<3, false, false><<<nb, NT, 0, sm>>>(v, v.x, v.xt, v, nullptr, c->w[W_B], part, c->st, it);
+            continue;
+        }
+        const bool timed = c->tslot >= 0;
+        if (timed) HIP3(c, hipEventRecord(c->ev[2][c->tslot][0], sm));
+        k3_mg_tile<T_POST1, 0><<<d.nblk, NT, 0, sm>>>(d, v, v.xt, lv[1], xc, v.x, nullptr, nullptr, c->st, it);
+        if (timed) HIP3(c, hipEventRecord(c->ev[2][c->tslot][1], sm));
+        if (ns == 3)
+            k3_mg_tile<T_POST2, 3><<<d.nblk, NT, 0, sm>>>(d, v, v.x, v, nullptr, v.xt, c->w[W_B], part, c->st, it);
         else
-            k3_mg_sweep<2, false, false><<<nb, NT, 0, sm>>>(v, v.x, v.xt, v, nullptr, nullptr, part, c->st, it);
+            k3_mg_tile<T_POST2, 2><<<d.nblk, NT, 0, sm>>>(d, v, v.x, v, nullptr, v.xt, nullptr, part, c->st, it);
     }
     HIP3(c, hipGetLastError());
     return CCNS_OK;
@@ -923,7 +1066,7 @@ ccns_status ccns3_project(ccns3_ctx *c, ccns3_info *info) {
             if (c->timing) HIP3(c, hipEventRecord(c->ev[0][k][0], sm));
             k3_stencil<S_DIR><<<d.nblk, NT, 0, sm>>>(d, w[W_CX], w[W_CY], w[W_CZ], w[W_DINV], w[W_Z], pold, pnew,
                                                      w[W_Q], nullptr, c->st, it, mg ? pm : (it == 0 ? pr : pu),
-                                                     (it == 0 && !mg) ? d.nblk : d.nflat, c->n_active, pd);
+                                                     (it == 0 || mg) ? d.nblk : d.nflat, c->n_active, pd);
             if (c->timing) {
                 HIP3(c, hipEventRecord(c->ev[0][k][1], sm));
                 HIP3(c, hipEventRecord(c->ev[1][k][0], sm));
