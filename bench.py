@@ -78,6 +78,9 @@ WORKLOADS = {
 # update kernel reads 1/diag, p, (-L) p, x, r and writes x, r, z.
 DIR3_BYTES_PER_CELL = 7 * 8.0
 UPDATE3_BYTES_PER_ELEMENT = 8 * 8.0
+# With the multigrid preconditioner the update forms no z: p, q, x, r read,
+# x and r written.
+UPDATE3_MG_BYTES_PER_ELEMENT = 6 * 8.0
 # The finest level's up-sweep of the 3-D multigrid cycle: reads the iterate,
 # the right-hand side, 1/diag and c^x, c^y, c^z of its cell and the coarse
 # correction (one value per eight cells); writes the new iterate.
@@ -541,7 +544,8 @@ def run_projection3d(args):
         "div_rel_max": max(i.div_rel for i in infos),
         "kernels_us": {"k3_stencil<DIR>": dir_us, "k3_update": upd_us, "k3_mg_tile<T_POST1> (finest up-sweep)": sw_us,
                        "dir_GBps": DIR3_BYTES_PER_CELL * cells / (dir_us * 1e-6) / 1e9,
-                       "update_GBps": UPDATE3_BYTES_PER_ELEMENT * n_elem / (upd_us * 1e-6) / 1e9},
+                       "update_GBps": (UPDATE3_MG_BYTES_PER_ELEMENT if precond else UPDATE3_BYTES_PER_ELEMENT) *
+                       n_elem / (upd_us * 1e-6) / 1e9},
         "roofline": ({"bound": "hbm", "achieved": achieved, "peak": 8000.0, "unit": "GB/s",
                       "frac": achieved / 8000.0, "traffic": None,
                       "kernel": "k3_mg_tile<T_POST1> (the cycle's finest-level up-sweep)",

@@ -12,7 +12,9 @@
 //    one-cell halo, marching up a slab of 32 cells in z with the planes
 //    below and above each cell in registers and the current plane in LDS;
 //    q = (-L) p = sum over the six faces of c_f (p_c - p_nb); partial p.q;
-//  * k3_update: x += alpha p, r -= alpha q, z = r / diag; partials r.z, r.r.
+//  * k3_update: x += alpha p, r -= alpha q, and with the Jacobi preconditioner
+//    z = r / diag and the partials r.z, r.r (the multigrid cycle forms z and
+//    the partials after it).
 // Each launch reduces the previous launch's per-group partials itself, in a
 // fixed order, so alpha, beta and the stopping test are the same in every
 // group and the solve runs without host round trips inside a chunk of
@@ -227,6 +229,7 @@ __global__ __launch_bounds__(NT) void k3_stencil(Dims3 d, const double *__restri
 
 // x += alpha p, r -= alpha q, z = r / diag over every element (the masks
 // keep the entries off the unknowns at zero); partials (r.z, r.r).
+template <bool JAC>
 __global__ __launch_bounds__(NT) void k3_update(Dims3 d, const double *__restrict__ dinv, const double *__restrict__ p,
                                                 const double *__restrict__ q, double *__restrict__ x,
                                                 double *__restrict__ r, double *__restrict__ z, Cg3 *st, int it,
@@ -247,17 +250,19 @@ __global__ __launch_bounds__(NT) void k3_update(Dims3 d, const double *__restric
     double v[2] = {0.0, 0.0};
     const size_t stride = (size_t)gridDim.x * NT;
     for (size_t e = (size_t)blockIdx.x * NT + threadIdx.x; e < d.n; e += stride) {
-        const double dv = dinv[e], pe = p[e], qe = q[e];
+        const double pe = p[e], qe = q[e];
         const double xe = x[e], re = r[e];
         x[e] = fma(alpha, pe, xe);
         const double rn = fma(-alpha, qe, re);
-        const double zn = dv * rn;
         r[e] = rn;
-        z[e] = zn;
-        v[0] += rn * zn;
-        v[1] += rn * rn;
+        if constexpr (JAC) {
+            const double zn = dinv[e] * rn;
+            z[e] = zn;
+            v[0] += rn * zn;
+            v[1] += rn * rn;
+        }
     }
-    put_partials<2>(v, part, gridDim.x);
+    if constexpr (JAC) put_partials<2>(v, part, gridDim.x);
 }
 
 // b = -(rho/tau) cont(U*, 0) on the pressure unknowns (eq:divergence with
@@ -1071,8 +1076,8 @@ ccns_status ccns3_project(ccns3_ctx *c, ccns3_info *info) {
                 HIP3(c, hipEventRecord(c->ev[0][k][1], sm));
                 HIP3(c, hipEventRecord(c->ev[1][k][0], sm));
             }
-            k3_update<<<d.nflat, NT, 0, sm>>>(d, w[W_DINV], pnew, w[W_Q], w[W_X], w[W_R], w[W_Z], c->st, it, pd,
-                                              d.nblk, pu);
+            auto upd = mg ? k3_update<false> : k3_update<true>;
+            upd<<<d.nflat, NT, 0, sm>>>(d, w[W_DINV], pnew, w[W_Q], w[W_X], w[W_R], w[W_Z], c->st, it, pd, d.nblk, pu);
             if (c->timing) HIP3(c, hipEventRecord(c->ev[1][k][1], sm));
             c->tslot = c->timing ? k : -1;
             s = mg ? vcycle3(c, 2, pm, it) : CCNS_OK;
