@@ -101,7 +101,11 @@ size_t ccns3_caps_count(const ccns3_grid *grid);
  * finite, unknown kind). */
 ccns_status ccns3_capacities(const ccns3_grid *grid, const ccns3_body *bodies, int nbodies, double *out);
 
-/* Bytes of device workspace a context needs (0 for an invalid grid). */
+/* Bytes of device workspace a context needs: the solver's fields and, for
+ * the multigrid preconditioner, its coarse levels (about one field more) and
+ * the coarsest grid's dense pseudo-inverse.  0 for an invalid grid, or for
+ * one whose padded fields exceed 2^31 - 1 elements (the kernels index them
+ * in 32 bits; about 1,290^3 cells). */
 size_t ccns3_workspace_bytes(const ccns3_grid *grid);
 
 typedef struct ccns3_ctx ccns3_ctx;

@@ -925,6 +925,7 @@ extern "C" {
 size_t ccns3_workspace_bytes(const ccns3_grid *g) {
     if (!grid3_valid(g)) return 0;
     const Dims3 d = make_dims(*g);
+    if (d.n > (size_t)INT_MAX) return 0;  // the kernels index a field's elements in 32 bits
     return (size_t)W_COUNT * align256(d.n * sizeof(double)) + align256(PART_DOUBLES * sizeof(double)) +
            align256(sizeof(Cg3)) + mg3_bytes(*g);
 }
@@ -934,6 +935,7 @@ ccns_status ccns3_ctx_create(const ccns3_grid *grid, const ccns3_params *params,
     if (!out || !grid3_valid(grid) || !params_ok(params) || !caps_host || !workspace) return CCNS_EINVAL;
     *out = nullptr;
     if (((uintptr_t)workspace & 255) != 0) return CCNS_EINVAL;
+    if (ccns3_workspace_bytes(grid) == 0) return CCNS_EINVAL;
     if (workspace_bytes < ccns3_workspace_bytes(grid)) return CCNS_ENOMEM;
     ccns3_ctx *c = new (std::nothrow) ccns3_ctx;
     if (!c) return CCNS_ENOMEM;
