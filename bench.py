@@ -85,6 +85,9 @@ UPDATE3_MG_BYTES_PER_ELEMENT = 6 * 8.0
 # the right-hand side, 1/diag and c^x, c^y, c^z of its cell and the coarse
 # correction (one value per eight cells); writes the new iterate.
 SWEEP3_BYTES_PER_CELL = 7 * 8.0 + 1.0
+# The same with the cycle's fields in FP32: the iterate, 1/diag and the three
+# weights in FP32, the residual r in FP64, the coarse correction in FP32.
+SWEEP3_F32_BYTES_PER_CELL = 6 * 4.0 + 8.0 + 0.5
 
 
 # Device helpers whose text a kernel's counter readings also depend on.
@@ -471,7 +474,7 @@ def run_projection3d(args):
     g = case.grid
     t_setup = time.perf_counter()
     caps = ccns3d.capacities(g, case.bodies)
-    precond = 1 if args.precond3d == "multigrid" else 0
+    precond = {"jacobi": 0, "multigrid": 1, "multigrid-fp32": 2}[args.precond3d]
     ctx = ccns3d.Context3(g, ccns3d.make_params(case.rho, case.tau, tol=case.tol, mass_floor=case.mass_floor,
                                                 precond=precond), caps)
     U = [torch.from_numpy(u).cuda() for u in T.face_velocity(case)]
@@ -504,7 +507,8 @@ def run_projection3d(args):
     dir_us = dms * 1e3 / max(dn, 1)
     upd_us = ums * 1e3 / max(un, 1)
     sw_us = sms * 1e3 / max(sn, 1)
-    achieved = SWEEP3_BYTES_PER_CELL * cells / (sw_us * 1e-6) / 1e9
+    sweep_bytes = SWEEP3_F32_BYTES_PER_CELL if precond == 2 else SWEEP3_BYTES_PER_CELL
+    achieved = sweep_bytes * cells / (sw_us * 1e-6) / 1e9
     n_elem = (g.nx + 2 + 15) // 16 * 16 * (g.ny + 2) * (g.nz + 2)
     cpu = None
     if not args.no_cpu_baseline:
@@ -533,12 +537,12 @@ def run_projection3d(args):
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64+f32" if precond == 2 else "f64",
         "data": "synthetic",
         "config": {"workload": "sphere_projection_256", "cells": cells, "grid": [g.nx, g.ny, g.nz],
                    "bodies": "sphere r=0.3 in the unit box",
-                   "solver": ("multigrid-PCG (V-cycle, 2x2x2 agglomeration)" if precond else "Jacobi-PCG") +
-                             ", tol 1e-12",
+                   "solver": ("Jacobi-PCG", "multigrid-PCG (V-cycle, 2x2x2 agglomeration)",
+                              "multigrid-PCG, the cycle's fields in FP32 (FP64 CG)")[precond] + ", tol 1e-12",
                    "mass_floor": case.mass_floor},
         "cg_iterations": [i.iterations for i in infos],
         "div_rel_max": max(i.div_rel for i in infos),
@@ -549,7 +553,7 @@ def run_projection3d(args):
         "roofline": ({"bound": "hbm", "achieved": achieved, "peak": 8000.0, "unit": "GB/s",
                       "frac": achieved / 8000.0, "traffic": None,
                       "kernel": "k3_mg_tile<T_POST1> (the cycle's finest-level up-sweep)",
-                      "bytes_per_cell": SWEEP3_BYTES_PER_CELL, "mean_launch_us": sw_us, "timed_launches": sn}
+                      "bytes_per_cell": sweep_bytes, "mean_launch_us": sw_us, "timed_launches": sn}
                      if precond else
                      {"bound": "hbm", "achieved": DIR3_BYTES_PER_CELL * cells / (dir_us * 1e-6) / 1e9,
                       "peak": 8000.0, "unit": "GB/s",
@@ -595,8 +599,9 @@ def main():
     ap.add_argument("--coef-tables", default="auto", choices=["auto", "off"],
                     help="auto: the predictor CG reads its coefficients through the class table when it "
                          "fits (the library's default); off: from the coefficient arrays")
-    ap.add_argument("--precond3d", default="multigrid", choices=["multigrid", "jacobi"],
-                    help="sphere_projection_256: the Poisson CG's preconditioner")
+    ap.add_argument("--precond3d", default="multigrid", choices=["multigrid", "multigrid-fp32", "jacobi"],
+                    help="sphere_projection_256: the Poisson CG's preconditioner (multigrid-fp32: the cycle's "
+                         "fields in FP32, the CG in FP64)")
     args = ap.parse_args()
     if args.summarize_counters:
         summarize_counters(args.summarize_counters, "k_pred_cg", args.workload, args.coef_tables == "auto")

@@ -65,8 +65,10 @@ typedef struct {
  * (1 / diag), 1 a geometric multigrid V-cycle (2x2x2 agglomeration, half
  * the sum of the covered fine face weights on each coarse face, weighted
  * Jacobi two sweeps down and two up, the dense pseudo-inverse on a coarsest
- * grid of at most 256 cells).  The projection method leaves the solver open
- * (Sec. 4.6); both reach the same tolerance test. */
+ * grid of at most 256 cells), 2 the same cycle with its fields stored in
+ * FP32 (FP64 arithmetic; the CG itself stays FP64).  The projection method
+ * leaves the solver open (Sec. 4.6); all three reach the same FP64
+ * tolerance test. */
 typedef struct {
     double rho, tau, tol, mass_floor;
     int maxit;

@@ -108,7 +108,8 @@ def capacities(g, bodies) -> np.ndarray:
 
 
 def make_params(rho, tau, tol=1e-12, mass_floor=0.05, maxit=100000, precond=1) -> Params3:
-    """precond: 0 Jacobi, 1 the multigrid V-cycle (ccns3_params)."""
+    """precond: 0 Jacobi, 1 the multigrid V-cycle, 2 the cycle stored in
+    FP32 (ccns3_params)."""
     return Params3(rho, tau, tol, mass_floor, maxit, precond)
 
 

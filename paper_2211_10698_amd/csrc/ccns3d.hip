@@ -358,67 +358,71 @@ __global__ __launch_bounds__(NT) void k3_div_shift(Dims3 d, const double *__rest
 // (the first sweep from x = 0 is omega D^-1 b, formed where the second reads
 // it), the restriction of the residual, the first up-sweep with the
 // interpolated coarse correction added where it reads its input, and the
-// second up-sweep.  Every kernel loads all it needs of an interior element
-// before it looks at whether the element is an unknown (the loads of an
-// interior element stay inside the ghost layer), so no load waits on another.
+// second up-sweep.  The cycle's fields are stored in T (double, or float for
+// the FP32 cycle inside the FP64 CG); its arithmetic is FP64 either way.
 // ---------------------------------------------------------------------------
 
 constexpr double MG3_W = 0.8;   // Jacobi weight of the sweeps
 constexpr int MG3_MAXC = 256;   // cells of the coarsest grid at most
 
-// One level: dense (nz+2)(ny+2) rows of `pitch` doubles; b is the level's
+// One level: dense (nz+2)(ny+2) rows of `pitch` elements; b is the level's
 // right-hand side, x and xt its two iterates (the cycle's correction ends in
-// xt; on the finest level b is the CG's residual r and xt its z).  Every
+// xt).  On the finest level the right-hand side is the CG's residual r (FP64,
+// passed to its kernels apart) and the result goes to the CG's z.  Every
 // level has fewer than 2^31 elements.
-struct Lev3 {
+template <class T>
+struct LevT {
     int nx, ny, nz, pitch;
     size_t plane, n;
-    const double *cx, *cy, *cz, *dinv;
-    double *b, *x, *xt;
+    const T *cx, *cy, *cz, *dinv;
+    T *b, *x, *xt;
 };
 
 // (i, j, k) of element e of a level
-__device__ inline void ijk3(const Lev3 &v, unsigned e, int &i, int &j, int &k) {
+template <class T>
+__device__ inline void ijk3(const LevT<T> &v, unsigned e, int &i, int &j, int &k) {
     const unsigned row = e / (unsigned)v.pitch;
     i = (int)(e - row * (unsigned)v.pitch);
     k = (int)(row / (unsigned)(v.ny + 2));
     j = (int)(row - (unsigned)k * (unsigned)(v.ny + 2));
 }
-__device__ inline bool interior3(const Lev3 &v, int i, int j, int k) {
+template <class T>
+__device__ inline bool interior3(const LevT<T> &v, int i, int j, int k) {
     return i >= 1 && i <= v.nx && j >= 1 && j <= v.ny && k >= 1 && k <= v.nz;
 }
+// the parent of fine cell (i, j, k) on coarse level c
+template <class T>
+__device__ inline size_t parent3(const LevT<T> &c, int i, int j, int k) {
+    return (size_t)((k + 1) >> 1) * c.plane + (size_t)((j + 1) >> 1) * c.pitch + ((i + 1) >> 1);
+}
 
-// The value a sweep acts on at element e (cell (i, j, k)):
+// The value a coarse-level sweep acts on at element e (cell (i, j, k)):
 //  FROM_B: the first sweep's result omega D^-1 b;
 //  PRO:    u + the parent's coarse correction;
 //  else:   u.
-template <bool FROM_B, bool PRO>
-__device__ inline double sweep_in(const Lev3 &v, const double *__restrict__ u, const Lev3 &c,
-                                  const double *__restrict__ xc, size_t e, int i, int j, int k) {
-    if (FROM_B) return MG3_W * v.dinv[e] * v.b[e];
-    if (PRO)
-        return u[e] + xc[(size_t)((k + 1) >> 1) * c.plane + (size_t)((j + 1) >> 1) * c.pitch + ((i + 1) >> 1)];
-    return u[e];
+template <bool FROM_B, bool PRO, class T>
+__device__ inline double sweep_in(const LevT<T> &v, const T *__restrict__ u, const LevT<T> &c,
+                                  const T *__restrict__ xc, size_t e, int i, int j, int k) {
+    if (FROM_B) return MG3_W * (double)v.dinv[e] * (double)v.b[e];
+    if (PRO) return (double)u[e] + (double)xc[parent3(c, i, j, k)];
+    return (double)u[e];
 }
 
-// xout = y + omega D^-1 (b - (-L) y) on the unknowns, 0 elsewhere, with y
-// given by sweep_in.  NS = 2: partials (r.z, r.r) of the finest level (r = b,
-// z = xout); NS = 3: also b'.b' of the right-hand side `bp` (the first cycle
-// of a solve).
-template <int NS, bool FROM_B, bool PRO>
-__global__ __launch_bounds__(NT) void k3_mg_sweep(Lev3 v, const double *__restrict__ xin, double *__restrict__ xout,
-                                                  Lev3 c, const double *__restrict__ xc, const double *__restrict__ bp,
-                                                  double *part, const Cg3 *st, int it) {
+// Coarse levels: xout = y + omega D^-1 (b - (-L) y) on the unknowns, 0
+// elsewhere, with y given by sweep_in.  Every load of an interior element
+// is issued before the test of whether it is an unknown (its loads stay
+// inside the ghost layer).
+template <bool FROM_B, bool PRO, class T>
+__global__ __launch_bounds__(NT) void k3_mg_sweep(LevT<T> v, const T *__restrict__ xin, T *__restrict__ xout,
+                                                  LevT<T> c, const T *__restrict__ xc, const Cg3 *st, int it) {
     if (st->stop_it <= it) return;
-    double acc[NS > 0 ? NS : 1] = {};
     const size_t stride = (size_t)gridDim.x * NT, P = v.pitch, PL = v.plane;
     for (size_t e = (size_t)blockIdx.x * NT + threadIdx.x; e < v.n; e += stride) {
         int i, j, k;
         ijk3(v, (unsigned)e, i, j, k);
-        double o = 0.0, be = 0.0;
+        double o = 0.0;
         if (interior3(v, i, j, k)) {
-            be = v.b[e];
-            const double dv = v.dinv[e];
+            const double be = v.b[e], dv = v.dinv[e];
             const double y = sweep_in<FROM_B, PRO>(v, xin, c, xc, e, i, j, k);
             const double ye = sweep_in<FROM_B, PRO>(v, xin, c, xc, e + 1, i + 1, j, k);
             const double yw = sweep_in<FROM_B, PRO>(v, xin, c, xc, e - 1, i - 1, j, k);
@@ -426,28 +430,21 @@ __global__ __launch_bounds__(NT) void k3_mg_sweep(Lev3 v, const double *__restri
             const double ys = sweep_in<FROM_B, PRO>(v, xin, c, xc, e - P, i, j - 1, k);
             const double yt = sweep_in<FROM_B, PRO>(v, xin, c, xc, e + PL, i, j, k + 1);
             const double yb = sweep_in<FROM_B, PRO>(v, xin, c, xc, e - PL, i, j, k - 1);
-            const double ax = v.cx[e] * (y - ye) + v.cx[e - 1] * (y - yw) + v.cy[e] * (y - yn) +
-                              v.cy[e - P] * (y - ys) + v.cz[e] * (y - yt) + v.cz[e - PL] * (y - yb);
+            const double ax = (double)v.cx[e] * (y - ye) + (double)v.cx[e - 1] * (y - yw) +
+                              (double)v.cy[e] * (y - yn) + (double)v.cy[e - P] * (y - ys) +
+                              (double)v.cz[e] * (y - yt) + (double)v.cz[e - PL] * (y - yb);
             o = dv > 0.0 ? y + MG3_W * dv * (be - ax) : 0.0;
         }
-        xout[e] = o;
-        if constexpr (NS >= 2) {
-            acc[0] += be * o;
-            acc[1] += be * be;
-        }
-        if constexpr (NS >= 3) {
-            const double q = bp[e];
-            acc[2] += q * q;
-        }
+        xout[e] = (T)o;
     }
-    if constexpr (NS > 0) put_partials<NS>(acc, part, gridDim.x);
 }
 
 // coarse b = the sum over the (up to eight) children of the fine residual
 // b - (-L) xf on the fine unknowns; 0 on the coarse ghost layer.  A child
 // index beyond the fine grid is clamped to the grid (its load repeats its
 // sibling's) and contributes nothing.
-__global__ __launch_bounds__(NT) void k3_mg_restrict(Lev3 f, const double *__restrict__ xf, Lev3 c, const Cg3 *st,
+template <class T>
+__global__ __launch_bounds__(NT) void k3_mg_restrict(LevT<T> f, const T *__restrict__ xf, LevT<T> c, const Cg3 *st,
                                                      int it) {
     if (st->stop_it <= it) return;
     const size_t stride = (size_t)gridDim.x * NT, P = f.pitch, PL = f.plane;
@@ -463,39 +460,43 @@ __global__ __launch_bounds__(NT) void k3_mg_restrict(Lev3 f, const double *__res
                 const int i = min(i0, f.nx), j = min(j0, f.ny), k = min(k0, f.nz);
                 const size_t e = (size_t)k * PL + (size_t)j * P + i;
                 const double y = xf[e];
-                const double ax = f.cx[e] * (y - xf[e + 1]) + f.cx[e - 1] * (y - xf[e - 1]) +
-                                  f.cy[e] * (y - xf[e + P]) + f.cy[e - P] * (y - xf[e - P]) +
-                                  f.cz[e] * (y - xf[e + PL]) + f.cz[e - PL] * (y - xf[e - PL]);
-                const double r = f.b[e] - ax;
-                s += (in && f.dinv[e] > 0.0) ? r : 0.0;
+                const double ax = (double)f.cx[e] * (y - (double)xf[e + 1]) +
+                                  (double)f.cx[e - 1] * (y - (double)xf[e - 1]) +
+                                  (double)f.cy[e] * (y - (double)xf[e + P]) +
+                                  (double)f.cy[e - P] * (y - (double)xf[e - P]) +
+                                  (double)f.cz[e] * (y - (double)xf[e + PL]) +
+                                  (double)f.cz[e - PL] * (y - (double)xf[e - PL]);
+                const double r = (double)f.b[e] - ax;
+                s += (in && f.dinv[e] > (T)0) ? r : 0.0;
             }
         }
-        c.b[ec] = s;
+        c.b[ec] = (T)s;
     }
 }
 
 // The finest level's cycle kernels on the tiles of k3_stencil (64 x 4
 // columns marched up a slab of 32 cells in z, the current plane and its halo
-// in LDS), which read each value about once where the element-wise forms
-// re-read their plane and row neighbours from beyond L2:
-//  T_PRE:   both down-sweeps, xt from y = omega D^-1 b;
-//  T_RES:   the residual b - (-L) xt on the unknowns (for the restriction);
+// in LDS), which read each value about once where element-wise forms re-read
+// their plane and row neighbours from beyond L2:
+//  T_PRE:   both down-sweeps, xt from y = omega D^-1 r;
+//  T_RES:   the residual r - (-L) xt on the unknowns (for the restriction);
 //  T_POST1: the first up-sweep from y = xt + the parent's correction;
-//  T_POST2: the second up-sweep from y = x (NS: the partials of
-//           k3_mg_sweep).
+//  T_POST2: the second up-sweep from y = x, written (in TO) to the CG's z;
+//           NS = 2: partials (r.z, r.r); NS = 3: also b'.b' of `bp`.
+// v carries the finest level's coefficients (in T); r is the CG's residual.
 enum { T_PRE = 0, T_RES = 1, T_POST1 = 2, T_POST2 = 3 };
-template <int MODE>
-__device__ inline double tile_in(const Lev3 &v, const double *__restrict__ u, const Lev3 &c,
-                                 const double *__restrict__ xc, size_t e, int i, int j, int k) {
-    if (MODE == T_PRE) return MG3_W * v.dinv[e] * v.b[e];
-    if (MODE == T_POST1)
-        return u[e] + xc[(size_t)((k + 1) >> 1) * c.plane + (size_t)((j + 1) >> 1) * c.pitch + ((i + 1) >> 1)];
-    return u[e];
+template <int MODE, class T>
+__device__ inline double tile_in(const LevT<T> &v, const double *__restrict__ r, const T *__restrict__ u,
+                                 const LevT<T> &c, const T *__restrict__ xc, size_t e, int i, int j, int k) {
+    if (MODE == T_PRE) return MG3_W * (double)v.dinv[e] * r[e];
+    if (MODE == T_POST1) return (double)u[e] + (double)xc[parent3(c, i, j, k)];
+    return (double)u[e];
 }
-template <int MODE, int NS>
-__global__ __launch_bounds__(NT) void k3_mg_tile(Dims3 d, Lev3 v, const double *__restrict__ u, Lev3 c,
-                                                 const double *__restrict__ xc, double *__restrict__ out,
-                                                 const double *__restrict__ bp, double *part, const Cg3 *st, int it) {
+template <int MODE, int NS, class T, class TO>
+__global__ __launch_bounds__(NT) void k3_mg_tile(Dims3 d, LevT<T> v, const double *__restrict__ r,
+                                                 const T *__restrict__ u, LevT<T> c, const T *__restrict__ xc,
+                                                 TO *__restrict__ out, const double *__restrict__ bp, double *part,
+                                                 const Cg3 *st, int it) {
     if (st->stop_it <= it) return;
     __shared__ double s2[2][T3Y + 2][T3X + 2];
     const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
@@ -530,8 +531,8 @@ __global__ __launch_bounds__(NT) void k3_mg_tile(Dims3 d, Lev3 v, const double *
         const size_t col = (size_t)j * X + i;
         double prev = 0.0, cur = 0.0, czb = 0.0;
         if (own) {
-            prev = tile_in<MODE>(v, u, c, xc, (size_t)(k0 - 1) * PL + col, i, j, k0 - 1);
-            cur = tile_in<MODE>(v, u, c, xc, (size_t)k0 * PL + col, i, j, k0);
+            prev = tile_in<MODE>(v, r, u, c, xc, (size_t)(k0 - 1) * PL + col, i, j, k0 - 1);
+            cur = tile_in<MODE>(v, r, u, c, xc, (size_t)k0 * PL + col, i, j, k0);
             czb = v.cz[(size_t)(k0 - 1) * PL + col];
         }
         for (int k = k0; k < k1; ++k) {
@@ -540,16 +541,16 @@ __global__ __launch_bounds__(NT) void k3_mg_tile(Dims3 d, Lev3 v, const double *
             const size_t e = (size_t)k * PL + col;
             double nxt = 0.0, ce = 0.0, cw = 0.0, cn = 0.0, cs = 0.0, ct = 0.0, dv = 0.0, bv = 0.0, hv = 0.0;
             if (own) {
-                nxt = tile_in<MODE>(v, u, c, xc, e + PL, i, j, k + 1);
+                nxt = tile_in<MODE>(v, r, u, c, xc, e + PL, i, j, k + 1);
                 ce = v.cx[e];
                 cw = v.cx[e - 1];
                 cn = v.cy[e];
                 cs = v.cy[e - X];
                 ct = v.cz[e];
                 dv = v.dinv[e];
-                bv = v.b[e];
+                bv = r[e];
             }
-            if (hthr && hin) hv = tile_in<MODE>(v, u, c, xc, (size_t)k * PL + hoff, hi, hj, k);
+            if (hthr && hin) hv = tile_in<MODE>(v, r, u, c, xc, (size_t)k * PL + hoff, hi, hj, k);
             s[ty + 1][tx + 1] = cur;
             if (hthr) s[hy][hx] = hin ? hv : 0.0;
             __syncthreads();
@@ -562,7 +563,7 @@ __global__ __launch_bounds__(NT) void k3_mg_tile(Dims3 d, Lev3 v, const double *
                     o = dv > 0.0 ? bv - av : 0.0;
                 else
                     o = dv > 0.0 ? cur + MG3_W * dv * (bv - av) : 0.0;
-                out[e] = o;
+                out[e] = (TO)o;
                 if constexpr (NS >= 2) {
                     acc[0] += bv * o;
                     acc[1] += bv * bv;
@@ -583,7 +584,8 @@ __global__ __launch_bounds__(NT) void k3_mg_tile(Dims3 d, Lev3 v, const double *
 // coarse b = the sum of the fine residual rf over the (up to eight)
 // children; 0 on the coarse ghost layer.  rf is 0 off the fine unknowns; a
 // child index beyond the fine grid is clamped and contributes nothing.
-__global__ __launch_bounds__(NT) void k3_mg_sum8(Lev3 f, const double *__restrict__ rf, Lev3 c, const Cg3 *st,
+template <class T>
+__global__ __launch_bounds__(NT) void k3_mg_sum8(LevT<T> f, const T *__restrict__ rf, LevT<T> c, const Cg3 *st,
                                                  int it) {
     if (st->stop_it <= it) return;
     const size_t stride = (size_t)gridDim.x * NT;
@@ -597,19 +599,20 @@ __global__ __launch_bounds__(NT) void k3_mg_sum8(Lev3 f, const double *__restric
                 const int i0 = 2 * I - 1 + (q & 1), j0 = 2 * J - 1 + ((q >> 1) & 1), k0 = 2 * K - 1 + (q >> 2);
                 const bool in = i0 <= f.nx && j0 <= f.ny && k0 <= f.nz;
                 const size_t e = (size_t)min(k0, f.nz) * f.plane + (size_t)min(j0, f.ny) * f.pitch + min(i0, f.nx);
-                const double r = rf[e];
-                s += in ? r : 0.0;
+                const double rv = rf[e];
+                s += in ? rv : 0.0;
             }
         }
-        c.b[ec] = s;
+        c.b[ec] = (T)s;
     }
 }
 
 // coarsest grid: x = A^+ b on its n unknowns (element indices idx), one
 // work-group; n <= MG3_MAXC
+template <class T>
 __global__ __launch_bounds__(NT) void k3_mg_coarsest(int n, const int *__restrict__ idx, const double *__restrict__ pinv,
-                                                     const double *__restrict__ b, double *__restrict__ x,
-                                                     const Cg3 *st, int it) {
+                                                     const T *__restrict__ b, T *__restrict__ x, const Cg3 *st,
+                                                     int it) {
     if (st->stop_it <= it) return;
     __shared__ double sb[MG3_MAXC];
     for (int i = threadIdx.x; i < n; i += NT) sb[i] = b[idx[i]];
@@ -617,7 +620,7 @@ __global__ __launch_bounds__(NT) void k3_mg_coarsest(int n, const int *__restric
     for (int i = threadIdx.x; i < n; i += NT) {
         double acc = 0.0;
         for (int j = 0; j < n; ++j) acc += pinv[(size_t)i * n + j] * sb[j];
-        x[idx[i]] = acc;
+        x[idx[i]] = (T)acc;
     }
 }
 
@@ -677,6 +680,10 @@ size_t mg3_bytes(const ccns3_grid &g) {
     for (const auto &d : mg3_dims(g)) b += MG3_ARRS * align256(mg3_elems(d) * sizeof(double));
     return b + align256((size_t)MG3_MAXC * MG3_MAXC * sizeof(double)) + align256(MG3_MAXC * sizeof(int));
 }
+// The FP32 cycle's finest-level fields: c^x, c^y, c^z, 1/diag, x, xt and the
+// residual of the restriction, in the layout of the FP64 fields.
+constexpr int MG3_F32_FIELDS = 7;
+size_t mg3_f32_bytes(size_t n) { return MG3_F32_FIELDS * align256(n * sizeof(float)); }
 
 // Coarse Poisson weights of a 2x2x2 agglomeration (dense layouts, one ghost
 // layer): the weight of a coarse face is half the sum of the weights of the
@@ -746,7 +753,9 @@ struct ccns3_ctx {
     int n_active = 0;
     // the multigrid cycle (precond = 1): the finest level and the coarse
     // ones, the coarsest grid's unknowns and pseudo-inverse
-    std::vector<Lev3> lev;
+    std::vector<LevT<double>> lev;  // precond 1
+    std::vector<LevT<float>> lev32; // precond 2
+    float *r2_32 = nullptr;         // precond 2: the finest residual of the restriction
     int mg_n = 0;
     int *mg_idx = nullptr;
     double *mg_pinv = nullptr;
@@ -795,34 +804,69 @@ ccns_status download(ccns3_ctx *c, double *dst, const double *src, hipMemcpyKind
     return CCNS_OK;
 }
 
-// The cycle's levels: the finest on the context's fields (b = r, x = ZT,
-// xt = Z, so that the cycle's result is the CG's z), the coarse ones from
-// coarsen3 in the workspace at `mg`, and the coarsest grid's dense operator
-// on its unknowns with its pseudo-inverse (which also handles the null
-// space of the closed box).  Host rows stay in `keep` until the caller
-// synchronises the stream.
-ccns_status mg3_setup(ccns3_ctx *c, const HostCoef3 &hc, char *mg, std::vector<std::vector<double>> &keep) {
+// Stages host rows for an upload in flight (they stay in `keep` until the
+// caller synchronises the stream).
+template <class T>
+const T *stage(std::vector<std::vector<char>> &keep, const std::vector<double> &v) {
+    keep.emplace_back(v.size() * sizeof(T));
+    T *h = (T *)keep.back().data();
+    for (size_t k = 0; k < v.size(); ++k) h[k] = (T)v[k];
+    return h;
+}
+
+// The cycle's levels in storage type T.  The finest: in FP64 the context's
+// fields (x = ZT, xt = Z), in FP32 copies of the weights and 1/diag and
+// fields of its own in `f32`.  The coarse ones from coarsen3 in the
+// workspace at `mg`, and the coarsest grid's dense operator on its unknowns
+// with its pseudo-inverse (which also handles the null space of the closed
+// box).  Host rows stay in `keep` until the caller synchronises the stream.
+template <class T>
+ccns_status mg3_setup(ccns3_ctx *c, const HostCoef3 &hc, char *mg, char *f32, std::vector<LevT<T>> &lev,
+                      std::vector<std::vector<char>> &keep) {
     const Dims3 &d = c->d;
-    c->lev.clear();
-    c->lev.push_back(Lev3{c->g.nx, c->g.ny, c->g.nz, d.pitch, d.plane, d.n, c->w[W_CX], c->w[W_CY], c->w[W_CZ],
-                          c->w[W_DINV], c->w[W_R], c->w[W_ZT], c->w[W_Z]});
+    lev.clear();
+    LevT<T> l0{c->g.nx, c->g.ny, c->g.nz, d.pitch, d.plane, d.n, nullptr, nullptr, nullptr, nullptr, nullptr,
+               nullptr, nullptr};
+    if constexpr (sizeof(T) == sizeof(double)) {
+        l0.cx = (const T *)c->w[W_CX];
+        l0.cy = (const T *)c->w[W_CY];
+        l0.cz = (const T *)c->w[W_CZ];
+        l0.dinv = (const T *)c->w[W_DINV];
+        l0.x = (T *)c->w[W_ZT];
+        l0.xt = (T *)c->w[W_Z];
+    } else {
+        const size_t fb = align256(d.n * sizeof(float)), W = c->g.nx + 2;
+        T *f[MG3_F32_FIELDS];
+        for (int k = 0; k < MG3_F32_FIELDS; ++k) f[k] = (T *)(f32 + k * fb);
+        const std::vector<double> *src[4] = {&hc.c[0], &hc.c[1], &hc.c[2], &hc.dinv};
+        for (int k = 0; k < 4; ++k)
+            HIP3(c, hipMemcpy2DAsync(f[k], d.pitch * sizeof(T), stage<T>(keep, *src[k]), W * sizeof(T), W * sizeof(T),
+                                     (size_t)(c->g.ny + 2) * (c->g.nz + 2), hipMemcpyHostToDevice, c->stream));
+        l0.cx = f[0];
+        l0.cy = f[1];
+        l0.cz = f[2];
+        l0.dinv = f[3];
+        l0.x = f[4];
+        l0.xt = f[5];
+        c->r2_32 = (float *)f[6];
+    }
+    lev.push_back(l0);
     std::vector<double> cf[3] = {hc.c[0], hc.c[1], hc.c[2]}, dinv;
     int nx = c->g.nx, ny = c->g.ny, nz = c->g.nz;
     size_t off = 0;
     for (const auto &D : mg3_dims(c->g)) {
         std::vector<double> cc[3];
         coarsen3(nx, ny, nz, cf, D[0], D[1], D[2], cc, dinv);
+        // slots of FP64 size serve either storage type
         const size_t n = mg3_elems(D), ab = align256(n * sizeof(double));
-        double *a[MG3_ARRS];
-        for (int k = 0; k < MG3_ARRS; ++k) a[k] = (double *)(mg + off + k * ab);
+        T *a[MG3_ARRS];
+        for (int k = 0; k < MG3_ARRS; ++k) a[k] = (T *)(mg + off + k * ab);
         off += MG3_ARRS * ab;
         const std::vector<double> *src[4] = {&cc[0], &cc[1], &cc[2], &dinv};
-        for (int k = 0; k < 4; ++k) {
-            keep.push_back(*src[k]);
-            HIP3(c, hipMemcpyAsync(a[k], keep.back().data(), n * sizeof(double), hipMemcpyHostToDevice, c->stream));
-        }
+        for (int k = 0; k < 4; ++k)
+            HIP3(c, hipMemcpyAsync(a[k], stage<T>(keep, *src[k]), n * sizeof(T), hipMemcpyHostToDevice, c->stream));
         const int pitch = D[0] + 2;
-        c->lev.push_back(Lev3{D[0], D[1], D[2], pitch, (size_t)pitch * (D[1] + 2), n, a[0], a[1], a[2], a[3], a[4],
+        lev.push_back(LevT<T>{D[0], D[1], D[2], pitch, (size_t)pitch * (D[1] + 2), n, a[0], a[1], a[2], a[3], a[4],
                               a[5], a[6]});
         for (int k = 0; k < 3; ++k) cf[k].swap(cc[k]);
         nx = D[0];
@@ -848,74 +892,85 @@ ccns_status mg3_setup(ccns3_ctx *c, const HostCoef3 &hc, char *mg, std::vector<s
         for (int q = 0; q < 6; ++q)
             if (w[q] > 0.0 && pos[nb[q]] >= 0) A[(size_t)a * n + pos[nb[q]]] -= w[q];
     }
-    keep.push_back(n > 0 ? pseudo_inverse_spsd(A, n) : std::vector<double>(1, 0.0));
     c->mg_pinv = (double *)(mg + off);
     c->mg_idx = (int *)(mg + off + align256((size_t)MG3_MAXC * MG3_MAXC * sizeof(double)));
     c->mg_n = n;
     if (n > 0) {
-        HIP3(c, hipMemcpyAsync(c->mg_pinv, keep.back().data(), (size_t)n * n * sizeof(double), hipMemcpyHostToDevice,
-                               c->stream));
-        std::vector<double> idx_rows(((size_t)n * sizeof(int) + sizeof(double) - 1) / sizeof(double), 0.0);
-        std::memcpy(idx_rows.data(), idx.data(), (size_t)n * sizeof(int));
-        keep.push_back(std::move(idx_rows));
+        const double *pinv = stage<double>(keep, pseudo_inverse_spsd(A, n));
+        HIP3(c, hipMemcpyAsync(c->mg_pinv, pinv, (size_t)n * n * sizeof(double), hipMemcpyHostToDevice, c->stream));
+        keep.emplace_back((size_t)n * sizeof(int));
+        std::memcpy(keep.back().data(), idx.data(), (size_t)n * sizeof(int));
         HIP3(c, hipMemcpyAsync(c->mg_idx, keep.back().data(), (size_t)n * sizeof(int), hipMemcpyHostToDevice,
                                c->stream));
     }
     return CCNS_OK;
 }
 
-// One V-cycle, z = M^-1 r, on the context's stream (the finest level on
-// the tiles of k3_stencil, with d.nblk work-groups).  ns = 2: the finest
-// level's last sweep writes the partials (r.z, r.r) at `part`; ns = 3 also
-// b'.b'.  it: the CG iteration whose update this cycle follows (-1 before the
-// first); every kernel returns at once when the solve stopped at or before it.
-ccns_status vcycle3(ccns3_ctx *c, int ns, double *part, int it) {
+// One V-cycle, z = M^-1 r, on the context's stream, with the levels `lv`
+// stored in T and r2 the finest level's residual field (the finest level on
+// the tiles of k3_stencil, with d.nblk work-groups; z is written in FP64).
+// ns = 2: the finest level's last sweep writes the partials (r.z, r.r) at
+// `part`; ns = 3 also b'.b'.  it: the CG iteration whose update this cycle
+// follows (-1 before the first); every kernel returns at once when the
+// solve stopped at or before it.
+template <class T>
+ccns_status vcycle3(ccns3_ctx *c, const std::vector<LevT<T>> &lv, T *r2, int ns, double *part, int it) {
     hipStream_t sm = c->stream;
-    const std::vector<Lev3> &lv = c->lev;
     const int L = (int)lv.size() - 1;
     const Dims3 &d = c->d;
+    const double *r = c->w[W_R];
+    double *z = c->w[W_Z];
     for (int l = 0; l < L; ++l) {
-        const Lev3 &v = lv[l];
+        const LevT<T> &v = lv[l];
         // the two down-sweeps from x = 0 in one launch, then the restriction
-        // (on the finest level through its residual, in the free q field)
+        // (on the finest level through its stored residual)
         if (l == 0) {
-            k3_mg_tile<T_PRE, 0><<<d.nblk, NT, 0, sm>>>(d, v, nullptr, v, nullptr, v.xt, nullptr, nullptr, c->st, it);
-            k3_mg_tile<T_RES, 0><<<d.nblk, NT, 0, sm>>>(d, v, v.xt, v, nullptr, c->w[W_Q], nullptr, nullptr, c->st, it);
-            k3_mg_sum8<<<flat3(lv[1].n), NT, 0, sm>>>(v, c->w[W_Q], lv[1], c->st, it);
+            k3_mg_tile<T_PRE, 0, T, T><<<d.nblk, NT, 0, sm>>>(d, v, r, nullptr, v, nullptr, v.xt, nullptr, nullptr,
+                                                              c->st, it);
+            k3_mg_tile<T_RES, 0, T, T><<<d.nblk, NT, 0, sm>>>(d, v, r, v.xt, v, nullptr, r2, nullptr, nullptr, c->st,
+                                                              it);
+            k3_mg_sum8<T><<<flat3(lv[1].n), NT, 0, sm>>>(v, r2, lv[1], c->st, it);
             continue;
         }
-        k3_mg_sweep<0, true, false><<<flat3(v.n), NT, 0, sm>>>(v, nullptr, v.xt, v, nullptr, nullptr, nullptr, c->st,
-                                                               it);
-        k3_mg_restrict<<<flat3(lv[l + 1].n), NT, 0, sm>>>(v, v.xt, lv[l + 1], c->st, it);
+        k3_mg_sweep<true, false, T><<<flat3(v.n), NT, 0, sm>>>(v, nullptr, v.xt, v, nullptr, c->st, it);
+        k3_mg_restrict<T><<<flat3(lv[l + 1].n), NT, 0, sm>>>(v, v.xt, lv[l + 1], c->st, it);
     }
-    k3_mg_coarsest<<<1, NT, 0, sm>>>(c->mg_n, c->mg_idx, c->mg_pinv, lv[L].b, lv[L].x, c->st, it);
+    k3_mg_coarsest<T><<<1, NT, 0, sm>>>(c->mg_n, c->mg_idx, c->mg_pinv, lv[L].b, lv[L].x, c->st, it);
     for (int l = L - 1; l >= 0; --l) {
-        const Lev3 &v = lv[l];
+        const LevT<T> &v = lv[l];
         const int nb = flat3(v.n);
         // the first up-sweep on xt plus the interpolated coarse correction
-        const double *xc = l + 1 == L ? lv[L].x : lv[l + 1].xt;
+        const T *xc = l + 1 == L ? lv[L].x : lv[l + 1].xt;
         if (l > 0) {
-            k3_mg_sweep<0, false, true><<<nb, NT, 0, sm>>>(v, v.xt, v.x, lv[l + 1], xc, nullptr, nullptr, c->st, it);
-            k3_mg_sweep<0, false, false><<<nb, NT, 0, sm>>>(v, v.x, v.xt, v, nullptr, nullptr, nullptr, c->st, it);
+            k3_mg_sweep<false, true, T><<<nb, NT, 0, sm>>>(v, v.xt, v.x, lv[l + 1], xc, c->st, it);
+            k3_mg_sweep<false, false, T><<<nb, NT, 0, sm>>>(v, v.x, v.xt, v, nullptr, c->st, it);
             continue;
         }
         const bool timed = c->tslot >= 0;
         if (timed) HIP3(c, hipEventRecord(c->ev[2][c->tslot][0], sm));
-        k3_mg_tile<T_POST1, 0><<<d.nblk, NT, 0, sm>>>(d, v, v.xt, lv[1], xc, v.x, nullptr, nullptr, c->st, it);
+        k3_mg_tile<T_POST1, 0, T, T><<<d.nblk, NT, 0, sm>>>(d, v, r, v.xt, lv[1], xc, v.x, nullptr, nullptr, c->st,
+                                                            it);
         if (timed) HIP3(c, hipEventRecord(c->ev[2][c->tslot][1], sm));
         if (ns == 3)
-            k3_mg_tile<T_POST2, 3><<<d.nblk, NT, 0, sm>>>(d, v, v.x, v, nullptr, v.xt, c->w[W_B], part, c->st, it);
+            k3_mg_tile<T_POST2, 3, T, double><<<d.nblk, NT, 0, sm>>>(d, v, r, v.x, v, nullptr, z, c->w[W_B], part,
+                                                                     c->st, it);
         else
-            k3_mg_tile<T_POST2, 2><<<d.nblk, NT, 0, sm>>>(d, v, v.x, v, nullptr, v.xt, nullptr, part, c->st, it);
+            k3_mg_tile<T_POST2, 2, T, double><<<d.nblk, NT, 0, sm>>>(d, v, r, v.x, v, nullptr, z, nullptr, part,
+                                                                     c->st, it);
     }
     HIP3(c, hipGetLastError());
     return CCNS_OK;
 }
 
+ccns_status vcycle3(ccns3_ctx *c, int ns, double *part, int it) {
+    return c->p.precond == 2 ? vcycle3<float>(c, c->lev32, c->r2_32, ns, part, it)
+                             : vcycle3<double>(c, c->lev, c->w[W_Q], ns, part, it);
+}
+
 bool params_ok(const ccns3_params *p) {
     return p && p->rho > 0.0 && std::isfinite(p->rho) && p->tau > 0.0 && std::isfinite(p->tau) && p->tol >= 0.0 &&
            std::isfinite(p->tol) && p->maxit >= 0 && p->mass_floor >= 0.0 && p->mass_floor <= 1.0 &&
-           (p->precond == 0 || p->precond == 1);
+           p->precond >= 0 && p->precond <= 2;
 }
 
 }  // namespace
@@ -927,7 +982,7 @@ size_t ccns3_workspace_bytes(const ccns3_grid *g) {
     const Dims3 d = make_dims(*g);
     if (d.n > (size_t)INT_MAX) return 0;  // the kernels index a field's elements in 32 bits
     return (size_t)W_COUNT * align256(d.n * sizeof(double)) + align256(PART_DOUBLES * sizeof(double)) +
-           align256(sizeof(Cg3)) + mg3_bytes(*g);
+           align256(sizeof(Cg3)) + mg3_bytes(*g) + mg3_f32_bytes(d.n);
 }
 
 ccns_status ccns3_ctx_create(const ccns3_grid *grid, const ccns3_params *params, const double *caps_host,
@@ -972,10 +1027,14 @@ ccns_status ccns3_ctx_create(const ccns3_grid *grid, const ccns3_params *params,
             ccns3_ctx_destroy(c);
             return s;
         }
-    std::vector<std::vector<double>> keep;  // host rows of uploads in flight
-    if (c->p.precond == 1 && (s = mg3_setup(c, hc, base + (size_t)W_COUNT * fb + align256(PART_DOUBLES * sizeof(double)) +
-                                                      align256(sizeof(Cg3)),
-                                            keep)) != CCNS_OK) {
+    std::vector<std::vector<char>> keep;  // host rows of uploads in flight
+    char *mg = base + (size_t)W_COUNT * fb + align256(PART_DOUBLES * sizeof(double)) + align256(sizeof(Cg3));
+    char *f32 = mg + mg3_bytes(*grid);
+    if (c->p.precond == 1)
+        s = mg3_setup<double>(c, hc, mg, f32, c->lev, keep);
+    else if (c->p.precond == 2)
+        s = mg3_setup<float>(c, hc, mg, f32, c->lev32, keep);
+    if (s != CCNS_OK) {
         (void)hipStreamSynchronize(c->stream);
         ccns3_ctx_destroy(c);
         return s;
@@ -1046,7 +1105,7 @@ ccns_status ccns3_project(ccns3_ctx *c, ccns3_info *info) {
     hipStream_t sm = c->stream;
     double *pr = part_at(c, 0), *pd = part_at(c, 1), *pu = part_at(c, 2), *ps = part_at(c, 3), *pv = part_at(c, 4);
     double *pm = part_at(c, 5);
-    const bool mg = c->p.precond == 1;
+    const bool mg = c->p.precond >= 1;
     // solver state
     Cg3 h{};
     h.tol2 = c->p.tol * c->p.tol;

@@ -63,7 +63,7 @@ def test_poisson_operator_matches_the_oracle(name, make):
     ctx.close()
 
 
-@pytest.mark.parametrize("precond", [0, 1], ids=["jacobi", "multigrid"])
+@pytest.mark.parametrize("precond", [0, 1, 2], ids=["jacobi", "multigrid", "multigrid_fp32"])
 @pytest.mark.parametrize("name,make", _cases(), ids=[c[0] for c in _cases()])
 def test_projection_matches_the_oracle(name, make, precond):
     from paper_2211_10698_amd import ccns3d
@@ -96,7 +96,7 @@ def test_projection_matches_the_oracle(name, make, precond):
     ctx.close()
 
 
-@pytest.mark.parametrize("precond", [0, 1], ids=["jacobi", "multigrid"])
+@pytest.mark.parametrize("precond", [0, 1, 2], ids=["jacobi", "multigrid", "multigrid_fp32"])
 def test_projection_is_reproducible_bit_for_bit(precond):
     from paper_2211_10698_amd import ccns3d
     case = T.two_spheres(70, 20, 36)
@@ -116,15 +116,15 @@ def test_projection_is_reproducible_bit_for_bit(precond):
 
 
 def test_multigrid_and_jacobi_reach_the_same_solution():
-    """The two preconditioners solve the same system to the same
-    tolerance: the same Phi to the tolerance's reach, the multigrid in a
-    small fraction of the Jacobi iterations."""
+    """The preconditioners solve the same system to the same tolerance: the
+    same Phi to the tolerance's reach, the multigrid in a small fraction of
+    the Jacobi iterations, and with its fields in FP32 in about as many."""
     from paper_2211_10698_amd import ccns3d
     case = T.sphere_box(40)
     print("[3d] multigrid against Jacobi, sphere_40", flush=True)
     U = T.face_velocity(case)
     res = []
-    for precond in (0, 1):
+    for precond in (0, 1, 2):
         ctx = _context(case, precond=precond)
         for f, u in zip((ccns3d.F_UX, ccns3d.F_UY, ccns3d.F_UZ), U):
             ctx.set_field(f, u)
@@ -132,9 +132,11 @@ def test_multigrid_and_jacobi_reach_the_same_solution():
         assert info.status == ccns3d.OK and info.rel_residual <= 1e-12 and info.div_rel < 1e-10
         res.append((info.iterations, ctx.get_field(ccns3d.F_PHI).cpu().numpy()))
         ctx.close()
-    (it_j, phi_j), (it_m, phi_m) = res
+    (it_j, phi_j), (it_m, phi_m), (it_f, phi_f) = res
     assert np.abs(phi_m - phi_j).max() <= 1e-8 * np.abs(phi_j).max()
+    assert np.abs(phi_f - phi_j).max() <= 1e-8 * np.abs(phi_j).max()
     assert it_m * 5 < it_j, (it_m, it_j)
+    assert it_f <= it_m + 2, (it_f, it_m)
 
 
 def _local_faces(case, i, j, k):

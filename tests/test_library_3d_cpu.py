@@ -59,7 +59,7 @@ def test_argument_validation():
     bad_p = ccns3d.make_params(1.0, -0.01)
     assert L.ccns3_ctx_create(C.byref(g), C.byref(bad_p), caps.ctypes.data, C.c_void_p(4096), 1 << 30, None,
                               C.byref(h)) == -1
-    bad_pc = ccns3d.make_params(1.0, 0.01, precond=2)
+    bad_pc = ccns3d.make_params(1.0, 0.01, precond=3)
     assert L.ccns3_ctx_create(C.byref(g), C.byref(bad_pc), caps.ctypes.data, C.c_void_p(4096), 1 << 30, None,
                               C.byref(h)) == -1
     assert L.ccns3_ctx_create(C.byref(g), C.byref(p), caps.ctypes.data, C.c_void_p(4096), 16, None,
