@@ -6,8 +6,9 @@
 // = nx+2 rounded up to 16), element (i, j, k) at (k (ny+2) + j) pitch + i,
 // the same index meaning as the dense host layout.
 //
-// The Poisson solve is Jacobi-preconditioned CG with two kernels per
-// iteration, both HBM-bound:
+// The Poisson solve is preconditioned CG (Jacobi, or a geometric multigrid
+// V-cycle with its fields in FP64 or FP32) with two kernels per iteration
+// besides the preconditioner's, all HBM-bound:
 //  * k3_stencil<DIR>: p = z + beta p_old on a tile of 64 x 4 columns and its
 //    one-cell halo, marching up a slab of 32 cells in z with the planes
 //    below and above each cell in registers and the current plane in LDS;
