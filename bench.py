@@ -136,7 +136,40 @@ def stored_traffic(name, workload, classes):
     return t["bytes_per_launch"]
 
 
-def summarize_counters(root, kernel, workload, classes):
+def file_digest(*paths):
+    """SHA-1 of whole source files: the 3-D kernels' counter readings are
+    used only while their source and the shared device header are
+    unchanged."""
+    import hashlib
+
+    h = hashlib.sha1()
+    for p in paths:
+        h.update(open(p, "rb").read())
+    return h.hexdigest()
+
+
+SRC3 = os.path.join(ROOT, "paper_2211_10698_amd", "csrc", "ccns3d.hip")
+SWEEP3_KERNEL = {1: "k3_mg_tile<2, 0, double", 2: "k3_mg_tile<2, 0, float"}
+
+
+def traffic3_key(precond):
+    return f"k3_mg_tile<T_POST1>@sphere_projection_256/{'fp32' if precond == 2 else 'fp64'}"
+
+
+def stored_traffic3(precond):
+    """HBM bytes per launch of the 3-D cycle's finest up-sweep from the
+    committed counter summary, or None when there is none or the 3-D source
+    has changed."""
+    try:
+        t = json.load(open(TRAFFIC_FILE)).get(traffic3_key(precond))
+    except (OSError, ValueError):
+        return None
+    if not t or t.get("source_sha1") != file_digest(SRC3, KERNEL_HDR):
+        return None
+    return t["bytes_per_launch"]
+
+
+def summarize_counters(root, kernel, workload, classes, key=None, digest=None):
     """Turns four rocprofv3 --pmc runs into the stored traffic figure:
     root/fetch and root/write hold FETCH_SIZE and WRITE_SIZE of the bench
     run, root/cfetch and root/cwrite the same counters over the plain copies
@@ -163,7 +196,8 @@ def summarize_counters(root, kernel, workload, classes):
     fk, nf = med("fetch", kernel, "FETCH_SIZE")
     wk, nw = med("write", kernel, "WRITE_SIZE")
     sf, sw = copy_kib / cf, copy_kib / cw
-    rec = {"workload": workload, "coef_classes": classes, "kernel_sha1": kernel_digest(kernel),
+    rec = {"workload": workload, "coef_classes": classes,
+           **({"source_sha1": digest} if digest else {"kernel_sha1": kernel_digest(kernel)}),
            "fetch_kib": fk, "write_kib": wk,
            "launches": [nf, nw], "copy_fetch_kib": cf, "copy_write_kib": cw, "fetch_scale": sf,
            "write_scale": sw, "bytes_per_launch": (fk * sf + wk * sw) * 1024.0}
@@ -171,7 +205,7 @@ def summarize_counters(root, kernel, workload, classes):
         data = json.load(open(TRAFFIC_FILE))
     except (OSError, ValueError):
         data = {}
-    data[f"{kernel}@{workload}"] = rec
+    data[key or f"{kernel}@{workload}"] = rec
     with open(TRAFFIC_FILE, "w") as f:
         json.dump(data, f, indent=1)
         f.write("\n")
@@ -551,7 +585,7 @@ def run_projection3d(args):
                        "update_GBps": (UPDATE3_MG_BYTES_PER_ELEMENT if precond else UPDATE3_BYTES_PER_ELEMENT) *
                        n_elem / (upd_us * 1e-6) / 1e9},
         "roofline": ({"bound": "hbm", "achieved": achieved, "peak": 8000.0, "unit": "GB/s",
-                      "frac": achieved / 8000.0, "traffic": None,
+                      "frac": achieved / 8000.0, "traffic": stored_traffic3(precond),
                       "kernel": "k3_mg_tile<T_POST1> (the cycle's finest-level up-sweep)",
                       "bytes_per_cell": sweep_bytes, "mean_launch_us": sw_us, "timed_launches": sn}
                      if precond else
@@ -603,6 +637,13 @@ def main():
                     help="sphere_projection_256: the Poisson CG's preconditioner (multigrid-fp32: the cycle's "
                          "fields in FP32, the CG in FP64)")
     args = ap.parse_args()
+    if args.summarize_counters and args.workload == "sphere_projection_256":
+        pc = {"jacobi": 0, "multigrid": 1, "multigrid-fp32": 2}[args.precond3d]
+        if not pc:
+            raise SystemExit("the 3-D counter summary covers the multigrid cycle's up-sweep")
+        summarize_counters(args.summarize_counters, SWEEP3_KERNEL[pc], args.workload, False, key=traffic3_key(pc),
+                           digest=file_digest(SRC3, KERNEL_HDR))
+        return
     if args.summarize_counters:
         summarize_counters(args.summarize_counters, "k_pred_cg", args.workload, args.coef_tables == "auto")
         return

@@ -158,7 +158,8 @@ def _local_faces(case, i, j, k):
     return c["V"][2, 2, 2], faces
 
 
-def test_full_size_sphere_256_on_sampled_cells():
+@pytest.mark.parametrize("precond", [1, 2], ids=["multigrid", "multigrid_fp32"])
+def test_full_size_sphere_256_on_sampled_cells(precond):
     """256^3 cells: the Poisson operator at sampled cells and the corrected
     velocity at their faces, each computed by the oracle one cell at a time
     from its own capacities on a window around the cell; the whole
@@ -166,8 +167,8 @@ def test_full_size_sphere_256_on_sampled_cells():
     from paper_2211_10698_amd import ccns3d
     case = T.sphere_box_256()
     g = case.grid
-    print("[3d] full size 256^3: set-up", flush=True)
-    ctx = _context(case)
+    print(f"[3d] full size 256^3, precond {precond}: set-up", flush=True)
+    ctx = _context(case, precond=precond)
     x = T.random_cells(case, 43)
     ax = ctx.apply_poisson(x).cpu().numpy()
     U = T.face_velocity(case)
