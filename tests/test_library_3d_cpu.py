@@ -42,6 +42,11 @@ def test_argument_validation():
     bad = ccns3d.Grid3C(0, 4, 4, 0, 0, 0, 1, 1, 1)
     assert L.ccns3_caps_count(C.byref(bad)) == 0
     assert L.ccns3_workspace_bytes(C.byref(bad)) == 0
+    # fields beyond 32-bit element indices are refused (1,400^3 cells)
+    huge = ccns3d.Grid3C(1400, 1400, 1400, 0, 0, 0, 1.0 / 1400, 1.0 / 1400, 1.0 / 1400)
+    assert L.ccns3_workspace_bytes(C.byref(huge)) == 0
+    fits = ccns3d.Grid3C(1024, 1024, 1024, 0, 0, 0, 1.0 / 1024, 1.0 / 1024, 1.0 / 1024)
+    assert L.ccns3_workspace_bytes(C.byref(fits)) > 0
     g = ccns3d.Grid3C(4, 4, 4, 0, 0, 0, 0.25, 0.25, 0.25)
     out = np.zeros(L.ccns3_caps_count(C.byref(g)))
     for body in (ccns3d.Body3C(0, 0.5, 0.5, 0.5, -0.1), ccns3d.Body3C(7, 0.5, 0.5, 0.5, 0.1),
