@@ -160,8 +160,8 @@ def _local_faces(case, i, j, k):
 
 # On windows of 256^3-size cells the oracle's requested absolute quadrature
 # tolerance (1e-13 of a cell) lies below the rounding noise of its section
-# areas, and QUADPACK says so; the volumes are still good to about 1e-12 of a
-# cell, well inside the comparisons below.
+# areas, and QUADPACK says so; the error that leaves in the window's volumes
+# is of that noise's order, far inside the comparisons' tolerances below.
 @pytest.mark.filterwarnings("ignore::scipy.integrate.IntegrationWarning")
 @pytest.mark.parametrize("precond", [1, 2], ids=["multigrid", "multigrid_fp32"])
 def test_full_size_sphere_256_on_sampled_cells(precond):
