@@ -752,6 +752,7 @@ struct ccns3_ctx {
     Cg3 *h_st = nullptr;       // pinned
     double *h_part = nullptr;  // pinned, the divergence partials
     int n_active = 0;
+    int last_it = 0;  // iterations of the last solve: the first chunk of the next
     // the multigrid cycle (precond = 1): the finest level and the coarse
     // ones, the coarsest grid's unknowns and pseudo-inverse
     std::vector<LevT<double>> lev;  // precond 1
@@ -1125,7 +1126,9 @@ ccns_status ccns3_project(ccns3_ctx *c, ccns3_info *info) {
     // last sweep writes (r.z, r.r) (and b'.b' before the first iteration)
     ccns_status s = CCNS_OK;
     if (mg && (s = vcycle3(c, 3, pm, -1)) != CCNS_OK) return s;
-    int it = 0, chunk = 8;
+    // the first chunk covers the last solve's iterations (one look at the
+    // solver state when the count repeats), then chunks double
+    int it = 0, chunk = std::min(std::max(8, c->last_it + 1), 64);
     for (;;) {
         const int it0 = it;
         for (int k = 0; k < chunk; ++k, ++it) {
@@ -1182,6 +1185,7 @@ ccns_status ccns3_project(ccns3_ctx *c, ccns3_info *info) {
     }
     const Cg3 &r = *c->h_st;
     const ccns_status status = r.stop_it == INT_MAX ? CCNS_ENOTCONV : (ccns_status)r.status;
+    c->last_it = r.stop_it == INT_MAX ? it : r.stop_it;
     if (info) {
         info->iterations = r.stop_it == INT_MAX ? it : r.it_final;
         info->status = status;
